@@ -1,0 +1,194 @@
+"""Reaction networks and seeded synthetic workloads.
+
+This module only *describes* inputs: species, reactions, rate constants, bin
+grids, recycling targets and seeds.  It holds none of the simulation
+arithmetic, so both the HIP library and the CPU oracle can be fed from it.
+
+Models:
+  * birth-death: 0 -> X (k = 1.0), X -> 0 (gamma = 0.025 per copy); stationary
+    law Poisson(40).
+  * Schloegl (Sec. III.B, Eq. schlogl): A + 2X <-> 3X, B <-> X with
+    k1 = 3e-7, k2 = 1e-4, k3 = 1e-3, k4 = 3.5, A = 1e5, B = 2e5 held constant
+    and folded into the rate constants.
+  * futile cycle (Sec. III.A, Eq. futile): E1 + S1 <-> B1 -> E1 + S2,
+    E2 + S2 <-> B2 -> E2 + S1, k_f = 1.0, k_s = 0.1.
+  * a synthetic two-gene toggle (8 species, 16 mass-action reactions), and
+    synthetic large mass-action networks shaped like the 354-species /
+    3680-reaction model of Sec. III.D, both generated from a seed.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Dict, List, Optional, Sequence, Tuple
+
+import numpy as np
+
+
+@dataclasses.dataclass
+class Network:
+    """A mass-action reaction network in CSR form.
+
+    reactants of reaction j: reac_species[reac_ptr[j]:reac_ptr[j+1]] with
+    multiplicities reac_mult (1..3); net change of reaction j:
+    chg_species/chg_delta over chg_ptr; rate[j] is the stochastic rate
+    constant c_j, with constant reservoir species folded in.
+    """
+
+    S: int
+    R: int
+    reac_ptr: np.ndarray
+    reac_species: np.ndarray
+    reac_mult: np.ndarray
+    chg_ptr: np.ndarray
+    chg_species: np.ndarray
+    chg_delta: np.ndarray
+    rate: np.ndarray
+    names: List[str]
+
+    @staticmethod
+    def from_reactions(names: Sequence[str],
+                       reactions: Sequence[Tuple[Dict[str, int], Dict[str, int], float]]
+                       ) -> "Network":
+        """Build from (reactants, products, c_j) triples; reactants and
+        products map species name -> stoichiometric count."""
+        idx = {n: i for i, n in enumerate(names)}
+        rp, rs, rm, cp, cs, cd, rate = [0], [], [], [0], [], [], []
+        for reac, prod, c in reactions:
+            for sp in sorted(reac, key=lambda n: idx[n]):
+                rs.append(idx[sp])
+                rm.append(int(reac[sp]))
+            rp.append(len(rs))
+            delta: Dict[int, int] = {}
+            for sp, k in reac.items():
+                delta[idx[sp]] = delta.get(idx[sp], 0) - int(k)
+            for sp, k in prod.items():
+                delta[idx[sp]] = delta.get(idx[sp], 0) + int(k)
+            for s in sorted(delta):
+                if delta[s] != 0:
+                    cs.append(s)
+                    cd.append(delta[s])
+            cp.append(len(cs))
+            rate.append(float(c))
+        i32 = lambda a: np.ascontiguousarray(np.asarray(a, dtype=np.int32))
+        return Network(S=len(names), R=len(reactions),
+                       reac_ptr=i32(rp), reac_species=i32(rs), reac_mult=i32(rm),
+                       chg_ptr=i32(cp), chg_species=i32(cs), chg_delta=i32(cd),
+                       rate=np.ascontiguousarray(np.asarray(rate, dtype=np.float64)),
+                       names=list(names))
+
+    def order(self, j: int) -> int:
+        return int(self.reac_mult[self.reac_ptr[j]:self.reac_ptr[j + 1]].sum())
+
+
+@dataclasses.dataclass
+class WEConfig:
+    """Everything the WE procedure needs besides the network: the bin grid on
+    a linear progress coordinate, walkers per bin, the interval, the initial
+    state, the recycling target and the seeds of independent runs."""
+
+    name: str
+    net: Network
+    x0: np.ndarray                 # int32[S]
+    bin_coef: np.ndarray           # float64[S]
+    edges: np.ndarray              # float64[n_bins + 1]
+    m_targ: int
+    tau: float
+    n_iters: int
+    seeds: np.ndarray              # uint64[n_runs]
+    recycle: bool = False
+    tgt_coef: Optional[np.ndarray] = None
+    tgt_thr: float = 0.0
+    x_rec: Optional[np.ndarray] = None
+    hist_species: int = 0
+    hist_lo: int = 0
+    hist_hi: int = 0
+
+    @property
+    def n_bins(self) -> int:
+        return len(self.edges) - 1
+
+    @property
+    def cap(self) -> int:
+        return self.m_targ * self.n_bins
+
+    def with_seeds(self, seeds) -> "WEConfig":
+        return dataclasses.replace(self, seeds=np.asarray(seeds, dtype=np.uint64))
+
+
+def uniform_edges(lo: float, hi: float, n: int) -> np.ndarray:
+    """n equal bins on [lo, hi]: edges lo + i*(hi-lo)/n."""
+    return np.array([lo + i * (hi - lo) / n for i in range(n + 1)], dtype=np.float64)
+
+
+# --------------------------------------------------------------------------
+# 1-D birth-death.
+# --------------------------------------------------------------------------
+def birth_death(k: float = 1.0, gamma: float = 0.025) -> Network:
+    return Network.from_reactions(["X"], [({}, {"X": 1}, k), ({"X": 1}, {}, gamma)])
+
+
+def birth_death_config(n_runs: int = 1, seed0: int = 1, n_iters: int = 200) -> WEConfig:
+    net = birth_death()
+    return WEConfig(
+        name="birth_death", net=net, x0=np.array([40], np.int32),
+        bin_coef=np.array([1.0]), edges=uniform_edges(0.0, 120.0, 20),
+        m_targ=4, tau=1.0, n_iters=n_iters,
+        seeds=np.arange(seed0, seed0 + n_runs, dtype=np.uint64),
+        hist_species=0, hist_lo=0, hist_hi=140)
+
+
+# --------------------------------------------------------------------------
+# Schloegl model, Sec. III.B.
+# --------------------------------------------------------------------------
+SCHLOGL_K = dict(k1=3e-7, k2=1e-4, k3=1e-3, k4=3.5, A=1e5, B=2e5)
+
+
+def schlogl() -> Network:
+    p = SCHLOGL_K
+    return Network.from_reactions(["X"], [
+        ({"X": 2}, {"X": 3}, p["k1"] * p["A"]),      # A + 2X -> 3X
+        ({"X": 3}, {"X": 2}, p["k2"]),               # 3X -> A + 2X
+        ({}, {"X": 1}, p["k3"] * p["B"]),            # B -> X
+        ({"X": 1}, {}, p["k4"]),                     # X -> B
+    ])
+
+
+def schlogl_config(n_runs: int = 1, seed0: int = 1, n_iters: int = 2000,
+                   recycle: bool = True) -> WEConfig:
+    """60 bins of width 40/3 on [0, 800], 8 walkers per bin, tau = 0.05;
+    steady state with recycling X >= 563 -> X = 82 (the two wells of
+    Sec. III.B)."""
+    net = schlogl()
+    return WEConfig(
+        name="schlogl", net=net, x0=np.array([82], np.int32),
+        bin_coef=np.array([1.0]), edges=uniform_edges(0.0, 800.0, 60),
+        m_targ=8, tau=0.05, n_iters=n_iters,
+        seeds=np.arange(seed0, seed0 + n_runs, dtype=np.uint64),
+        recycle=recycle, tgt_coef=np.array([1.0]), tgt_thr=563.0,
+        x_rec=np.array([82], np.int32),
+        hist_species=0, hist_lo=0, hist_hi=800)
+
+
+# --------------------------------------------------------------------------
+# Enzymatic futile cycle, Sec. III.A.
+# --------------------------------------------------------------------------
+def futile_cycle(kf: float = 1.0, ks: float = 0.1) -> Network:
+    names = ["S1", "S2", "E1", "E2", "B1", "B2"]
+    return Network.from_reactions(names, [
+        ({"E1": 1, "S1": 1}, {"B1": 1}, kf),
+        ({"B1": 1}, {"E1": 1, "S1": 1}, kf),
+        ({"B1": 1}, {"E1": 1, "S2": 1}, ks),
+        ({"E2": 1, "S2": 1}, {"B2": 1}, kf),
+        ({"B2": 1}, {"E2": 1, "S2": 1}, kf),
+        ({"B2": 1}, {"E2": 1, "S1": 1}, ks),
+    ])
+
+
+# --------------------------------------------------------------------------
+# Small test networks.
+# --------------------------------------------------------------------------
+def isomerization(k_ab: float = 1.0, k_ba: float = 0.5) -> Network:
+    """A <-> B: with N molecules the stationary law of A is Binomial."""
+    return Network.from_reactions(["A", "B"], [({"A": 1}, {"B": 1}, k_ab),
+                                               ({"B": 1}, {"A": 1}, k_ba)])
