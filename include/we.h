@@ -1,0 +1,193 @@
+/*
+ * we.h -- C ABI of libwe.so, weighted-ensemble (WE) stochastic simulation of
+ * chemical kinetics on AMD Instinct MI355X (gfx950).
+ *
+ * Method: Donovan, Sedgewick, Faeder, Zuckerman, "Efficient stochastic
+ * simulation of chemical kinetics networks using a weighted ensemble of
+ * trajectories" (arXiv:1303.5986).  The calls below follow the paper's
+ * statement of the problem: a reaction network (Sec. II.A), a bin grid and
+ * a target number of walkers per bin, the interval tau and the initial state
+ * (the WE procedure of Sec. II.B), and a recycling target for steady-state
+ * mean first-passage times (Sec. II.B.2, Eq. mfpt).
+ *
+ * Conventions for every entry point:
+ *  - All pointer arguments are HOST pointers unless stated otherwise; every
+ *    input array is copied before the call returns, so the caller may free
+ *    it at once.  Output arrays are caller-allocated host memory.
+ *  - Handles (we_network, we_sim) are opaque and owned by the library until
+ *    passed to the matching destroy call.
+ *  - Functions return a we_status; a negative value is an error, and
+ *    we_last_error() then returns a thread-local message.  No C++ exception
+ *    crosses this interface.
+ *  - we_step_intervals is asynchronous on the sim's HIP stream.  Errors met
+ *    on the device (a count leaving [0, WE_COUNT_MAX], a selection guard
+ *    firing with no positive propensity) are latched in device memory and
+ *    returned by the next synchronous call (we_synchronize and every getter).
+ *  - Calls on one sim must not overlap (one host thread at a time).
+ */
+#ifndef WE_H
+#define WE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define WE_API __attribute__((visibility("default")))
+
+/* Largest copy number of any species: keeps each reactant factor
+ * prod_s C(x_s, nu_s) (reaction order <= 3) below 2^53, exact in FP64. */
+#define WE_COUNT_MAX 131071
+
+typedef struct we_network we_network;
+typedef struct we_sim we_sim;
+
+typedef enum {
+    WE_OK = 0,
+    WE_EINVAL = -1,     /* invalid argument or network                     */
+    WE_ENOMEM = -2,     /* device or host allocation failed                */
+    WE_EDEVICE = -3,    /* HIP runtime error                               */
+    WE_ECAPACITY = -4,  /* more iterations or walkers than were reserved   */
+    WE_EOVERFLOW = -5,  /* a copy number left [0, WE_COUNT_MAX]             */
+    WE_ESTATE = -6      /* call not valid in the sim's current state       */
+} we_status;
+
+typedef enum {
+    WE_KERNEL_AUTO = 0, /* lane-per-walker for small networks, else wave      */
+    WE_KERNEL_LANE = 1, /* one lane per walker, full propensity recompute     */
+    WE_KERNEL_WAVE = 2  /* one 64-wide wavefront per walker                   */
+} we_kernel;
+
+/* ---------------------------------------------------------------- network
+ * A mass-action reaction network (Sec. II.A), in CSR form:
+ *   reactants of reaction j: reac_species[reac_ptr[j] .. reac_ptr[j+1]) with
+ *     multiplicities reac_mult (1..3), each species at most once, total
+ *     order <= 3;
+ *   net change of reaction j: chg_species / chg_delta over chg_ptr
+ *     (non-zero deltas, each species at most once; a negative delta -d needs
+ *     the species among the reactants with multiplicity >= d);
+ *   rate_c[j]: stochastic rate constant c_j >= 0, with constant reservoir
+ *     species folded in.
+ * Propensity: a_j(x) = c_j * prod_s C(x_s, nu_js)  (the combinatorial
+ * mass-action convention under which the Schloegl model of Sec. III.B has
+ * its wells at 82 and 563).
+ * Errors: WE_EINVAL on any violation above; WE_ENOMEM / WE_EDEVICE. */
+WE_API we_status we_create_network(int32_t n_species, int32_t n_reactions,
+                                   const int32_t *reac_ptr, const int32_t *reac_species,
+                                   const int32_t *reac_mult,
+                                   const int32_t *chg_ptr, const int32_t *chg_species,
+                                   const int32_t *chg_delta,
+                                   const double *rate_c, we_network **out);
+WE_API void we_destroy_network(we_network *net);
+
+/* ---------------------------------------------------------------- bins
+ * Static grid on a linear progress coordinate q(x) = sum_s coef[s] * x_s
+ * (summed in species order in FP64).  Bin b is [edges[b], edges[b+1]);
+ * q below edges[0] goes to bin 0 and q at or above edges[n_bins] to bin
+ * n_bins-1 (the paper's grids are regular and the open-ended bin of
+ * Sec. III.C is the precedent).  edges must be strictly increasing. */
+typedef struct {
+    int32_t n_bins;
+    const double *coef;    /* [n_species] */
+    const double *edges;   /* [n_bins + 1] */
+} we_grid;
+
+/* ---------------------------------------------------------------- run setup
+ * One sim holds n_runs independent WE runs of the same network, bins and
+ * tau, each with its own seed (independent replicas, as the paper uses for
+ * error bars).  Each run reserves cap = m_targ * n_bins walker slots.
+ * Initial ensemble: m_targ walkers at x0, weight 1/m_targ each (weights sum
+ * to one, Sec. II.B), unless replaced by we_set_ensemble before the first
+ * step. */
+typedef struct {
+    double tau;                /* WE interval, > 0                                  */
+    int32_t m_targ;            /* walkers per occupied bin, >= 1                    */
+    int32_t n_runs;            /* independent runs, >= 1                            */
+    int32_t max_iters;         /* iterations reserved for flux / event series       */
+    int32_t kernel;            /* we_kernel                                         */
+    const uint64_t *seeds;     /* [n_runs] Philox keys                              */
+    const int32_t *x0;         /* [n_species] initial state, 0 <= x0 <= COUNT_MAX   */
+    int32_t recycle;           /* 1: steady state, walkers in B restart from A      */
+    const double *tgt_coef;    /* [n_species] B = { x : sum tgt_coef_s x_s >= thr } */
+    double tgt_thr;
+    const int32_t *x_rec;      /* [n_species] recycling state A (NULL: x0)          */
+    int32_t hist_species;      /* species whose P(x, t) is accumulated every        */
+    int32_t hist_lo, hist_hi;  /*   iteration over [lo, hi] (hi < lo: none)         */
+} we_params;
+
+/* Device bytes a sim needs (walker buffers, series, scratch). */
+WE_API we_status we_workspace_size(const we_network *net, const we_grid *grid,
+                                   const we_params *p, size_t *bytes);
+
+/* Create a sim.  hip_stream: a hipStream_t (NULL = default stream) on which
+ * every kernel of this sim is launched.  workspace: optional DEVICE pointer
+ * of at least we_workspace_size() bytes, 256-byte aligned, owned by the
+ * caller and kept alive until we_destroy (NULL: the library allocates).
+ * Errors: WE_EINVAL (bad sizes, edges not increasing, x0 out of range,
+ * tau <= 0, species out of range), WE_ENOMEM, WE_EDEVICE. */
+WE_API we_status we_init(const we_network *net, const we_grid *grid, const we_params *p,
+                         void *hip_stream, void *workspace, size_t workspace_bytes,
+                         we_sim **out);
+
+/* Replace run `run`'s ensemble before the first step: n walkers, states
+ * x[n*S] (walker-major), weights w[n].  Errors: WE_ESTATE after stepping,
+ * WE_ECAPACITY if n > cap, WE_EINVAL for counts out of range. */
+WE_API we_status we_set_ensemble(we_sim *s, int32_t run, int32_t n, const int32_t *x,
+                                 const double *w);
+
+/* Advance every run by n WE iterations (Sec. II.B): propagate each walker
+ * through tau with the Gillespie direct method, recycle walkers that reached
+ * B (if enabled), bin, split/merge per bin, record observables.
+ * Asynchronous.  Errors: WE_ECAPACITY past max_iters, WE_EDEVICE. */
+WE_API we_status we_step_intervals(we_sim *s, int32_t n);
+
+/* Wait for the sim's stream; return any latched device error. */
+WE_API we_status we_synchronize(we_sim *s);
+
+/* Copy run `run`'s current ensemble (canonical order: bins ascending,
+ * parents by ascending slot, copies consecutive) to host arrays of at least
+ * cap entries (x: cap*S).  Any output pointer may be NULL.  Synchronous. */
+WE_API we_status we_get_walkers(we_sim *s, int32_t run, int32_t *n, int32_t *x, double *w,
+                                int32_t *bin, int32_t *origin);
+
+/* P(x_species = k, t) for k = lo..hi from run `run`'s current ensemble
+ * (sum of walker weights, Sec. II.B.1); out has hi-lo+1 entries.
+ * Synchronous. */
+WE_API we_status we_histogram(we_sim *s, int32_t run, int32_t species, int32_t lo,
+                              int32_t hi, double *out);
+
+/* Sum over recorded iterations of P(x_hist_species = k, t) for
+ * k = hist_lo..hist_hi, per run (out: n_runs*(hi-lo+1)), and the number of
+ * iterations summed.  Synchronous. */
+WE_API we_status we_histogram_accum(we_sim *s, double *out, int32_t *n_iters);
+
+/* Weight recycled into B in iterations [first, first+count) of run `run`
+ * (out: count entries).  Synchronous. */
+WE_API we_status we_flux(we_sim *s, int32_t run, int32_t first, int32_t count, double *out);
+
+/* Steady-state MFPT = 1 / flux (Eq. mfpt): per run, flux = mean recycled
+ * weight per iteration after `discard` iterations divided by tau; the runs'
+ * fluxes are independent samples (Sec. III.C).  flux_sem is their standard
+ * error.  Synchronous. */
+WE_API we_status we_mfpt(we_sim *s, int32_t discard, double *mfpt, double *flux_mean,
+                         double *flux_sem);
+
+/* Totals over all runs and iterations so far: reactions fired and
+ * trajectory segments propagated (one segment = one walker over one tau).
+ * Synchronous. */
+WE_API we_status we_counters(we_sim *s, int64_t *events, int64_t *segments,
+                             int32_t *iterations);
+
+/* Per-iteration reactions fired, summed over runs, for iterations
+ * [first, first+count).  Synchronous. */
+WE_API we_status we_events_series(we_sim *s, int32_t first, int32_t count, int64_t *out);
+
+WE_API void we_destroy(we_sim *s);
+WE_API const char *we_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* WE_H */

@@ -1,0 +1,135 @@
+// we_common.h -- device-side building blocks and the argument block shared by
+// the WE kernels (gfx950).
+//
+// Random numbers: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten
+// rounds of two 32x32->64 multiplies with the round key, key bumped by the
+// Weyl constants between rounds.  Counter layout used throughout:
+//   SSA event e of the walker in slot k, iteration i:  (e, k, i, 0)
+//   merge number m in bin b, iteration i:              (m, b, i, 1)
+// keyed by the run's 64-bit seed.  Every result therefore depends only on
+// (seed, iteration, slot, event), never on scheduling.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define WE_COUNT_MAX_DEV 131071
+
+// Error bits latched in device memory.
+enum : int32_t {
+    WE_DERR_OVERFLOW = 1,   // a count left [0, WE_COUNT_MAX]
+    WE_DERR_SELECT = 2,     // no reaction with positive propensity at selection
+    WE_DERR_CAPACITY = 4,   // resampling would exceed the slot reservation
+};
+
+// One reaction's reactants and rate, packed for wave-uniform (scalar) loads.
+struct __align__(16) RxnDesc {
+    double c;        // stochastic rate constant c_j
+    uint16_t s1, s2; // reactant species (unused entries: 0)
+    uint8_t nu1, nu2;// multiplicities (0 = absent)
+    uint8_t nchg;    // number of species changed
+    uint8_t order;   // nu1 + nu2
+};
+
+// Species change of a reaction, packed as (species << 16) | (delta & 0xffff).
+__host__ __device__ inline int32_t pack_change(int32_t s, int32_t d) {
+    return (int32_t)(((uint32_t)s << 16) | ((uint32_t)d & 0xffffu));
+}
+__host__ __device__ inline int32_t change_species(int32_t p) { return (int32_t)((uint32_t)p >> 16); }
+__host__ __device__ inline int32_t change_delta(int32_t p) { return (int32_t)(int16_t)(p & 0xffff); }
+
+// Everything a WE kernel needs, passed by value.
+struct SimArgs {
+    // network
+    const RxnDesc *__restrict__ desc;    // [R]
+    const int32_t *__restrict__ chg_ptr; // [R+1]
+    const int32_t *__restrict__ chg;     // packed changes
+    const int32_t *__restrict__ dep_ptr; // [R+1] reactions whose propensity a reaction changes
+    const uint16_t *__restrict__ dep;    //       (sorted, unique)
+    int32_t S, R;
+    // runs
+    int32_t n_runs, cap, n_bins, m_targ, max_iters;
+    double tau;
+    const uint64_t *__restrict__ seeds;  // [n_runs]
+    // bins and target
+    const double *__restrict__ bin_coef; // [S]
+    const double *__restrict__ edges;    // [n_bins+1]
+    int32_t recycle;
+    double tgt_thr;
+    const double *__restrict__ tgt_coef; // [S]
+    const int32_t *__restrict__ x_rec;   // [S]
+    // ensemble (current and next buffers are passed per launch)
+    int32_t *n_walk;                     // [n_runs]
+    int32_t *bin;                        // [n_runs*cap] bin of each walker (after resample)
+    int32_t *origin;                     // [n_runs*cap] parent slot (after resample)
+    uint32_t *ev_walker;                 // [n_runs*cap] reactions fired this interval
+    // series
+    double *flux;                        // [n_runs*max_iters]
+    int64_t *ev_iter;                    // [n_runs*max_iters]
+    int32_t *seg_iter;                   // [n_runs*max_iters] walkers propagated
+    // resample scratch
+    int32_t *s_bin;                      // [n_runs*cap]
+    int32_t *s_rec;                      // [n_runs*cap]
+    int32_t *s_list;                     // [n_runs*cap]
+    double *s_w;                         // [n_runs*cap]
+    int32_t *s_cnt;                      // [n_runs*cap]
+    // observables
+    double *hist;                        // [n_runs*nh]
+    int32_t hist_species, hist_lo, nh;
+    int32_t *err;
+};
+
+// ---------------------------------------------------------------- Philox
+struct U4 { uint32_t x, y, z, w; };
+
+__device__ __forceinline__ U4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                             uint32_t k0, uint32_t k1) {
+    const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+    const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t lo0 = M0 * c0, hi0 = __umulhi(M0, c0);
+        const uint32_t lo1 = M1 * c2, hi1 = __umulhi(M1, c2);
+        const uint32_t n0 = hi1 ^ c1 ^ k0;
+        const uint32_t n2 = hi0 ^ c3 ^ k1;
+        c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+        k0 += W0; k1 += W1;
+    }
+    return U4{c0, c1, c2, c3};
+}
+
+// Uniform on [0,1) with 53 random bits: ((a >> 5) * 2^26 + (b >> 6)) * 2^-53.
+__device__ __forceinline__ double uniform53(uint32_t a, uint32_t b) {
+    const uint64_t m = ((uint64_t)(a >> 5) << 26) | (uint64_t)(b >> 6);
+    return (double)m * 0x1.0p-53;
+}
+
+// ---------------------------------------------------------------- propensity
+// C(x, nu) for nu in {0,1,2,3} as an exact 64-bit integer (x <= 2^17).
+__device__ __forceinline__ uint64_t binom_small(uint32_t x, uint32_t nu) {
+    if (nu == 0) return 1u;
+    if (x < nu) return 0u;
+    if (nu == 1) return x;
+    const uint64_t pair = ((uint64_t)x * (uint64_t)(x - 1u)) >> 1;   // C(x,2)
+    if (nu == 2) return pair;
+    return (pair * (uint64_t)(x - 2u)) / 3u;                          // C(x,3)
+}
+
+// a_j = c_j * h_j(x), h_j exact in int64 and converted once.
+__device__ __forceinline__ double propensity_from(const RxnDesc &d, uint32_t x1, uint32_t x2) {
+    const uint64_t h = binom_small(x1, d.nu1) * binom_small(x2, d.nu2);
+    return d.c * (double)h;
+}
+
+// ---------------------------------------------------------------- bins
+__device__ __forceinline__ int32_t bin_index(const double *__restrict__ edges, int32_t n_bins,
+                                             double q) {
+    // largest b in [0, n_bins-1] with edges[b] <= q (b = 0 if q < edges[1]);
+    // binary search over the strictly increasing inner edges edges[1..n_bins-1]
+    int32_t lo = 0, hi = n_bins - 1;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if (q >= edges[mid]) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}

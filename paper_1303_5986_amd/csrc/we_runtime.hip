@@ -1,0 +1,575 @@
+// we_runtime.hip -- host side of libwe.so: network compilation, device
+// layout, the iteration scheduler and the C ABI declared in include/we.h.
+//
+// Device layout of a sim (one workspace, 256-byte aligned pieces):
+//   x[2]      int32 [n_runs][cap][S]   walker states, walker-major, double-buffered
+//   w[2]      f64   [n_runs][cap]      weights
+//   bin, origin int32 [n_runs][cap]    after resampling
+//   ev_walker u32   [n_runs][cap]      reactions fired in the last interval
+//   flux      f64   [n_runs][max_iters] weight recycled per iteration
+//   ev_iter   i64   [n_runs][max_iters] reactions fired per iteration
+//   scratch for resampling, histogram accumulator, small parameter arrays.
+// cap = m_targ * n_bins is the most walkers a run can hold after resampling.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/we.h"
+#include "we_common.h"
+
+hipError_t launch_ssa_lane(const SimArgs &a, int32_t *xs, uint32_t iter, hipStream_t st);
+bool lane_kernel_fits(int32_t S, int32_t R);
+hipError_t launch_ssa_wave(const SimArgs &a, int32_t *xs, uint32_t iter, hipStream_t st);
+bool wave_kernel_fits(int32_t S, int32_t R);
+hipError_t launch_resample(const SimArgs &a, int32_t *x_cur, const double *w_cur, int32_t *x_nxt,
+                           double *w_nxt, uint32_t iter, int32_t rec_slot, hipStream_t st);
+hipError_t launch_observe(const SimArgs &a, const int32_t *xs, const double *ws, hipStream_t st);
+
+namespace {
+
+thread_local std::string g_err;
+
+we_status fail(we_status st, const std::string &msg) {
+    g_err = msg;
+    return st;
+}
+
+we_status hip_fail(hipError_t e, const char *what) {
+    return fail(WE_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr)                                       \
+    do {                                                    \
+        hipError_t _e = (expr);                             \
+        if (_e != hipSuccess) return hip_fail(_e, #expr);   \
+    } while (0)
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+}  // namespace
+
+struct we_network {
+    int32_t S = 0, R = 0;
+    int32_t max_order = 0;
+    std::vector<RxnDesc> desc;
+    std::vector<int32_t> chg_ptr, chg, dep_ptr;
+    std::vector<uint16_t> dep;
+    RxnDesc *d_desc = nullptr;
+    int32_t *d_chg_ptr = nullptr, *d_chg = nullptr, *d_dep_ptr = nullptr;
+    uint16_t *d_dep = nullptr;
+};
+
+struct we_sim {
+    const we_network *net = nullptr;
+    hipStream_t stream = nullptr;
+    SimArgs args{};
+    int32_t kernel = WE_KERNEL_LANE;
+    int32_t S = 0, NB = 0, M = 0, n_runs = 0, cap = 0, max_iters = 0;
+    double tau = 0.0;
+    int32_t iter = 0;
+    int32_t cur = 0;
+    int32_t hist_iters = 0;
+    bool owns_ws = false;
+    void *ws = nullptr;
+    int32_t *x[2] = {nullptr, nullptr};
+    double *w[2] = {nullptr, nullptr};
+    std::vector<int32_t> n_host; // walker counts known on the host (before first step)
+};
+
+// ------------------------------------------------------------------ network
+extern "C" we_status we_create_network(int32_t S, int32_t R, const int32_t *reac_ptr,
+                                       const int32_t *reac_species, const int32_t *reac_mult,
+                                       const int32_t *chg_ptr, const int32_t *chg_species,
+                                       const int32_t *chg_delta, const double *rate_c,
+                                       we_network **out) {
+    if (!out) return fail(WE_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (S <= 0 || R <= 0 || S > 65535 || R > 65535)
+        return fail(WE_EINVAL, "species and reactions must be in [1, 65535]");
+    if (!reac_ptr || !chg_ptr || !rate_c) return fail(WE_EINVAL, "NULL network array");
+    if (reac_ptr[0] != 0 || chg_ptr[0] != 0) return fail(WE_EINVAL, "CSR must start at 0");
+    we_network *net = new we_network();
+    net->S = S;
+    net->R = R;
+    net->desc.resize(R);
+    net->chg_ptr.assign(chg_ptr, chg_ptr + R + 1);
+    // species -> reactions having it as a reactant (to build the dependency lists)
+    std::vector<std::vector<int32_t>> users(S);
+    for (int32_t j = 0; j < R; ++j) {
+        RxnDesc d{};
+        d.c = rate_c[j];
+        if (!(rate_c[j] >= 0.0) || std::isinf(rate_c[j])) {
+            delete net;
+            return fail(WE_EINVAL, "rate constant must be finite and >= 0 (reaction " +
+                                       std::to_string(j) + ")");
+        }
+        const int32_t r0 = reac_ptr[j], r1 = reac_ptr[j + 1];
+        if (r1 < r0 || r1 - r0 > 2) {
+            delete net;
+            return fail(WE_EINVAL, "each reaction takes at most two distinct reactant species");
+        }
+        int32_t order = 0;
+        for (int32_t p = r0; p < r1; ++p) {
+            const int32_t s = reac_species[p], nu = reac_mult[p];
+            if (s < 0 || s >= S || nu < 1 || nu > 3) {
+                delete net;
+                return fail(WE_EINVAL, "reactant species or multiplicity out of range (reaction " +
+                                           std::to_string(j) + ")");
+            }
+            if (p == r0) { d.s1 = (uint16_t)s; d.nu1 = (uint8_t)nu; }
+            else {
+                if (s == d.s1) { delete net; return fail(WE_EINVAL, "repeated reactant species"); }
+                d.s2 = (uint16_t)s; d.nu2 = (uint8_t)nu;
+            }
+            order += nu;
+            users[s].push_back(j);
+        }
+        if (order > 3) { delete net; return fail(WE_EINVAL, "reaction order above 3"); }
+        d.order = (uint8_t)order;
+        const int32_t c0 = chg_ptr[j], c1 = chg_ptr[j + 1];
+        if (c1 < c0) { delete net; return fail(WE_EINVAL, "change CSR not monotone"); }
+        d.nchg = (uint8_t)std::min(c1 - c0, 255);
+        for (int32_t p = c0; p < c1; ++p) {
+            const int32_t s = chg_species[p], dl = chg_delta[p];
+            if (s < 0 || s >= S || dl == 0 || dl < -3 || dl > 32767) {
+                delete net;
+                return fail(WE_EINVAL, "change species or delta out of range (reaction " +
+                                           std::to_string(j) + ")");
+            }
+            for (int32_t q = c0; q < p; ++q)
+                if (chg_species[q] == s) { delete net; return fail(WE_EINVAL, "repeated change species"); }
+            if (dl < 0) {
+                int32_t nu = 0;
+                if (r1 > r0 && reac_species[r0] == s) nu = reac_mult[r0];
+                if (r1 > r0 + 1 && reac_species[r0 + 1] == s) nu = reac_mult[r0 + 1];
+                if (nu < -dl) {
+                    delete net;
+                    return fail(WE_EINVAL, "a reaction consumes a species it does not take as reactant");
+                }
+            }
+            net->chg.push_back(pack_change(s, dl));
+        }
+        net->max_order = std::max(net->max_order, order);
+        net->desc[j] = d;
+    }
+    // dependency lists: reactions whose propensity reaction j changes
+    net->dep_ptr.push_back(0);
+    std::vector<int32_t> mark(R, -1);
+    std::vector<int32_t> tmp;
+    for (int32_t j = 0; j < R; ++j) {
+        tmp.clear();
+        for (int32_t p = chg_ptr[j]; p < chg_ptr[j + 1]; ++p)
+            for (int32_t r : users[chg_species[p]])
+                if (mark[r] != j) { mark[r] = j; tmp.push_back(r); }
+        std::sort(tmp.begin(), tmp.end());
+        for (int32_t r : tmp) net->dep.push_back((uint16_t)r);
+        net->dep_ptr.push_back((int32_t)net->dep.size());
+    }
+    if (net->dep.empty()) net->dep.push_back(0);
+    if (net->chg.empty()) net->chg.push_back(0);
+    auto up = [&](void **dst, const void *src, size_t bytes) -> hipError_t {
+        hipError_t e = hipMalloc(dst, bytes);
+        if (e != hipSuccess) return e;
+        return hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
+    };
+    hipError_t e = up((void **)&net->d_desc, net->desc.data(), sizeof(RxnDesc) * R);
+    if (e == hipSuccess) e = up((void **)&net->d_chg_ptr, net->chg_ptr.data(), 4 * (R + 1));
+    if (e == hipSuccess) e = up((void **)&net->d_chg, net->chg.data(), 4 * net->chg.size());
+    if (e == hipSuccess) e = up((void **)&net->d_dep_ptr, net->dep_ptr.data(), 4 * (R + 1));
+    if (e == hipSuccess) e = up((void **)&net->d_dep, net->dep.data(), 2 * net->dep.size());
+    if (e != hipSuccess) {
+        we_destroy_network(net);
+        return hip_fail(e, "network upload");
+    }
+    *out = net;
+    return WE_OK;
+}
+
+extern "C" void we_destroy_network(we_network *net) {
+    if (!net) return;
+    (void)hipFree(net->d_desc);
+    (void)hipFree(net->d_chg_ptr);
+    (void)hipFree(net->d_chg);
+    (void)hipFree(net->d_dep_ptr);
+    (void)hipFree(net->d_dep);
+    delete net;
+}
+
+// ------------------------------------------------------------------ sim
+namespace {
+
+struct Layout {
+    size_t off[32];
+    size_t total = 0;
+    int n = 0;
+    size_t add(size_t bytes) {
+        off[n] = total;
+        total += align256(std::max<size_t>(bytes, 1));
+        return n++;
+    }
+};
+
+// Order of the pieces in the workspace; make_layout and we_init agree on it.
+enum Piece { P_X0, P_X1, P_W0, P_W1, P_BIN, P_ORIG, P_N, P_EVW, P_FLUX, P_EVI, P_SBIN, P_SREC,
+             P_SLIST, P_SW, P_SCNT, P_HIST, P_SEEDS, P_BCOEF, P_EDGES, P_TCOEF, P_XREC, P_ERR,
+             P_SEG, P_COUNT };
+
+Layout make_layout(int32_t S, int32_t NB, int32_t n_runs, int32_t cap, int32_t max_iters,
+                   int32_t nh) {
+    Layout L;
+    const size_t W = (size_t)n_runs * cap;
+    L.add(4 * W * S); L.add(4 * W * S);
+    L.add(8 * W); L.add(8 * W);
+    L.add(4 * W); L.add(4 * W);
+    L.add(4 * (size_t)n_runs);
+    L.add(4 * W);
+    L.add(8 * (size_t)n_runs * max_iters);
+    L.add(8 * (size_t)n_runs * max_iters);
+    L.add(4 * W); L.add(4 * W); L.add(4 * W); L.add(8 * W); L.add(4 * W);
+    L.add(8 * (size_t)n_runs * std::max(nh, 1));
+    L.add(8 * (size_t)n_runs);
+    L.add(8 * (size_t)S);
+    L.add(8 * (size_t)(NB + 1));
+    L.add(8 * (size_t)S);
+    L.add(4 * (size_t)S);
+    L.add(4);
+    L.add(4 * (size_t)n_runs * max_iters);
+    return L;
+}
+
+we_status check_params(const we_network *net, const we_grid *g, const we_params *p) {
+    if (!net || !g || !p) return fail(WE_EINVAL, "NULL argument");
+    if (g->n_bins < 1 || !g->coef || !g->edges) return fail(WE_EINVAL, "bad grid");
+    for (int32_t b = 0; b < g->n_bins; ++b)
+        if (!(g->edges[b] < g->edges[b + 1])) return fail(WE_EINVAL, "edges must increase strictly");
+    if (!(p->tau > 0.0) || std::isinf(p->tau)) return fail(WE_EINVAL, "tau must be > 0");
+    if (p->m_targ < 1 || p->n_runs < 1 || p->max_iters < 0)
+        return fail(WE_EINVAL, "m_targ, n_runs must be >= 1");
+    if (!p->seeds || !p->x0) return fail(WE_EINVAL, "seeds and x0 are required");
+    const int64_t cap = (int64_t)p->m_targ * g->n_bins;
+    if (cap > (1 << 24) || cap * p->n_runs > (int64_t)1 << 31)
+        return fail(WE_EINVAL, "too many walker slots");
+    for (int32_t s = 0; s < net->S; ++s)
+        if (p->x0[s] < 0 || p->x0[s] > WE_COUNT_MAX) return fail(WE_EINVAL, "x0 out of range");
+    if (p->recycle) {
+        if (!p->tgt_coef) return fail(WE_EINVAL, "recycling needs tgt_coef");
+        if (p->x_rec)
+            for (int32_t s = 0; s < net->S; ++s)
+                if (p->x_rec[s] < 0 || p->x_rec[s] > WE_COUNT_MAX)
+                    return fail(WE_EINVAL, "x_rec out of range");
+    }
+    if (p->hist_hi >= p->hist_lo && (p->hist_species < 0 || p->hist_species >= net->S))
+        return fail(WE_EINVAL, "hist_species out of range");
+    if (p->kernel < WE_KERNEL_AUTO || p->kernel > WE_KERNEL_WAVE)
+        return fail(WE_EINVAL, "unknown kernel");
+    return WE_OK;
+}
+
+}  // namespace
+
+extern "C" we_status we_workspace_size(const we_network *net, const we_grid *g, const we_params *p,
+                                       size_t *bytes) {
+    we_status st = check_params(net, g, p);
+    if (st != WE_OK) return st;
+    if (!bytes) return fail(WE_EINVAL, "bytes is NULL");
+    const int32_t nh = p->hist_hi >= p->hist_lo ? p->hist_hi - p->hist_lo + 1 : 0;
+    *bytes = make_layout(net->S, g->n_bins, p->n_runs, p->m_targ * g->n_bins,
+                         std::max(p->max_iters, 1), nh).total;
+    return WE_OK;
+}
+
+extern "C" we_status we_init(const we_network *net, const we_grid *g, const we_params *p,
+                             void *hip_stream, void *workspace, size_t workspace_bytes,
+                             we_sim **out) {
+    if (!out) return fail(WE_EINVAL, "out is NULL");
+    *out = nullptr;
+    we_status st = check_params(net, g, p);
+    if (st != WE_OK) return st;
+    const int32_t S = net->S, NB = g->n_bins, M = p->m_targ, n_runs = p->n_runs;
+    const int32_t cap = M * NB, max_iters = std::max(p->max_iters, 1);
+    const int32_t nh = p->hist_hi >= p->hist_lo ? p->hist_hi - p->hist_lo + 1 : 0;
+    int32_t kernel = p->kernel;
+    if (kernel == WE_KERNEL_AUTO)
+        kernel = lane_kernel_fits(S, net->R) && net->R <= 32 ? WE_KERNEL_LANE : WE_KERNEL_WAVE;
+    if (kernel == WE_KERNEL_LANE && !lane_kernel_fits(S, net->R))
+        return fail(WE_EINVAL, "network too large for the lane-per-walker kernel");
+    if (kernel == WE_KERNEL_WAVE && !wave_kernel_fits(S, net->R))
+        return fail(WE_EINVAL, "network too large for the wave-per-walker kernel");
+
+    Layout L = make_layout(S, NB, n_runs, cap, max_iters, nh);
+    we_sim *s = new we_sim();
+    s->net = net;
+    s->stream = (hipStream_t)hip_stream;
+    s->kernel = kernel;
+    s->S = S; s->NB = NB; s->M = M; s->n_runs = n_runs; s->cap = cap; s->max_iters = max_iters;
+    s->tau = p->tau;
+    if (workspace) {
+        if (workspace_bytes < L.total || ((uintptr_t)workspace & 255)) {
+            delete s;
+            return fail(WE_EINVAL, "workspace too small or not 256-byte aligned");
+        }
+        s->ws = workspace;
+    } else {
+        hipError_t e = hipMalloc(&s->ws, L.total);
+        if (e != hipSuccess) { delete s; return fail(WE_ENOMEM, "hipMalloc of the workspace failed"); }
+        s->owns_ws = true;
+    }
+    char *base = (char *)s->ws;
+    auto at = [&](int piece) { return (void *)(base + L.off[piece]); };
+    s->x[0] = (int32_t *)at(P_X0); s->x[1] = (int32_t *)at(P_X1);
+    s->w[0] = (double *)at(P_W0); s->w[1] = (double *)at(P_W1);
+    SimArgs &a = s->args;
+    a.desc = net->d_desc; a.chg_ptr = net->d_chg_ptr; a.chg = net->d_chg;
+    a.dep_ptr = net->d_dep_ptr; a.dep = net->d_dep;
+    a.S = S; a.R = net->R;
+    a.n_runs = n_runs; a.cap = cap; a.n_bins = NB; a.m_targ = M; a.max_iters = max_iters;
+    a.tau = p->tau;
+    a.seeds = (const uint64_t *)at(P_SEEDS);
+    a.bin_coef = (const double *)at(P_BCOEF);
+    a.edges = (const double *)at(P_EDGES);
+    a.recycle = p->recycle ? 1 : 0;
+    a.tgt_thr = p->tgt_thr;
+    a.tgt_coef = (const double *)at(P_TCOEF);
+    a.x_rec = (const int32_t *)at(P_XREC);
+    a.n_walk = (int32_t *)at(P_N);
+    a.bin = (int32_t *)at(P_BIN);
+    a.origin = (int32_t *)at(P_ORIG);
+    a.ev_walker = (uint32_t *)at(P_EVW);
+    a.flux = (double *)at(P_FLUX);
+    a.ev_iter = (int64_t *)at(P_EVI);
+    a.seg_iter = (int32_t *)at(P_SEG);
+    a.s_bin = (int32_t *)at(P_SBIN); a.s_rec = (int32_t *)at(P_SREC);
+    a.s_list = (int32_t *)at(P_SLIST); a.s_w = (double *)at(P_SW); a.s_cnt = (int32_t *)at(P_SCNT);
+    a.hist = (double *)at(P_HIST);
+    a.hist_species = nh > 0 ? p->hist_species : 0;
+    a.hist_lo = p->hist_lo;
+    a.nh = nh;
+    a.err = (int32_t *)at(P_ERR);
+
+    // initial ensemble: m_targ walkers at x0, weight 1/m_targ
+    const size_t W = (size_t)n_runs * cap;
+    std::vector<int32_t> hx(W * S, 0);
+    std::vector<double> hw(W, 0.0);
+    std::vector<int32_t> hn(n_runs, M), horig(W, -1), hbin(W, 0);
+    for (int32_t r = 0; r < n_runs; ++r)
+        for (int32_t k = 0; k < M; ++k) {
+            for (int32_t q = 0; q < S; ++q) hx[((size_t)r * cap + k) * S + q] = p->x0[q];
+            hw[(size_t)r * cap + k] = 1.0 / (double)M;
+        }
+    std::vector<double> zcoef(S, 0.0);
+    const hipStream_t st_ = s->stream;
+    auto put = [&](int piece, const void *src, size_t bytes) -> hipError_t {
+        return hipMemcpyAsync(at(piece), src, bytes, hipMemcpyHostToDevice, st_);
+    };
+    hipError_t e = hipMemsetAsync(s->ws, 0, L.total, st_);
+    if (e == hipSuccess) e = put(P_X0, hx.data(), 4 * W * S);
+    if (e == hipSuccess) e = put(P_W0, hw.data(), 8 * W);
+    if (e == hipSuccess) e = put(P_N, hn.data(), 4 * (size_t)n_runs);
+    if (e == hipSuccess) e = put(P_ORIG, horig.data(), 4 * W);
+    if (e == hipSuccess) e = put(P_SEEDS, p->seeds, 8 * (size_t)n_runs);
+    if (e == hipSuccess) e = put(P_BCOEF, g->coef, 8 * (size_t)S);
+    if (e == hipSuccess) e = put(P_EDGES, g->edges, 8 * (size_t)(NB + 1));
+    if (e == hipSuccess) e = put(P_TCOEF, p->tgt_coef ? p->tgt_coef : zcoef.data(), 8 * (size_t)S);
+    if (e == hipSuccess) e = put(P_XREC, p->x_rec ? p->x_rec : p->x0, 4 * (size_t)S);
+    if (e == hipSuccess) e = hipStreamSynchronize(st_);
+    if (e != hipSuccess) {
+        we_destroy(s);
+        return hip_fail(e, "sim upload");
+    }
+    s->n_host = hn;
+    *out = s;
+    return WE_OK;
+}
+
+extern "C" we_status we_set_ensemble(we_sim *s, int32_t run, int32_t n, const int32_t *x,
+                                     const double *w) {
+    if (!s) return fail(WE_EINVAL, "NULL sim");
+    if (s->iter != 0) return fail(WE_ESTATE, "ensemble can only be set before the first step");
+    if (run < 0 || run >= s->n_runs) return fail(WE_EINVAL, "run out of range");
+    if (n < 0 || n > s->cap) return fail(WE_ECAPACITY, "more walkers than slots");
+    if (n > 0 && (!x || !w)) return fail(WE_EINVAL, "NULL ensemble arrays");
+    for (int64_t i = 0; i < (int64_t)n * s->S; ++i)
+        if (x[i] < 0 || x[i] > WE_COUNT_MAX) return fail(WE_EINVAL, "count out of range");
+    for (int32_t i = 0; i < n; ++i)
+        if (!(w[i] >= 0.0) || std::isinf(w[i])) return fail(WE_EINVAL, "weights must be finite, >= 0");
+    const size_t base = (size_t)run * s->cap;
+    HIP_TRY(hipMemcpyAsync(s->x[s->cur] + base * s->S, x, 4 * (size_t)n * s->S,
+                           hipMemcpyHostToDevice, s->stream));
+    HIP_TRY(hipMemcpyAsync(s->w[s->cur] + base, w, 8 * (size_t)n, hipMemcpyHostToDevice, s->stream));
+    HIP_TRY(hipMemcpyAsync(s->args.n_walk + run, &n, 4, hipMemcpyHostToDevice, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    s->n_host[run] = n;
+    return WE_OK;
+}
+
+namespace {
+we_status read_err(we_sim *s) {
+    int32_t err = 0;
+    HIP_TRY(hipMemcpyAsync(&err, s->args.err, 4, hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    if (err & WE_DERR_OVERFLOW) return fail(WE_EOVERFLOW, "a copy number left [0, WE_COUNT_MAX]");
+    if (err & WE_DERR_CAPACITY) return fail(WE_ECAPACITY, "resampling exceeded the slot reservation");
+    if (err & WE_DERR_SELECT) return fail(WE_EDEVICE, "reaction selection found no positive propensity");
+    return WE_OK;
+}
+}  // namespace
+
+extern "C" we_status we_step_intervals(we_sim *s, int32_t n) {
+    if (!s) return fail(WE_EINVAL, "NULL sim");
+    if (n < 0) return fail(WE_EINVAL, "negative iteration count");
+    if ((int64_t)s->iter + n > s->max_iters) return fail(WE_ECAPACITY, "max_iters exceeded");
+    SimArgs &a = s->args;
+    for (int32_t i = 0; i < n; ++i) {
+        const uint32_t it = (uint32_t)s->iter;
+        const int32_t c = s->cur, nx = 1 - c;
+        hipError_t e = (s->kernel == WE_KERNEL_WAVE) ? launch_ssa_wave(a, s->x[c], it, s->stream)
+                                                     : launch_ssa_lane(a, s->x[c], it, s->stream);
+        if (e != hipSuccess) return hip_fail(e, "SSA launch");
+        e = launch_resample(a, s->x[c], s->w[c], s->x[nx], s->w[nx], it, (int32_t)it, s->stream);
+        if (e != hipSuccess) return hip_fail(e, "resample launch");
+        if (a.nh > 0) {
+            e = launch_observe(a, s->x[nx], s->w[nx], s->stream);
+            if (e != hipSuccess) return hip_fail(e, "observe launch");
+            s->hist_iters += 1;
+        }
+        s->cur = nx;
+        s->iter += 1;
+    }
+    return WE_OK;
+}
+
+extern "C" we_status we_synchronize(we_sim *s) {
+    if (!s) return fail(WE_EINVAL, "NULL sim");
+    return read_err(s);
+}
+
+extern "C" we_status we_get_walkers(we_sim *s, int32_t run, int32_t *n, int32_t *x, double *w,
+                                    int32_t *bin, int32_t *origin) {
+    if (!s) return fail(WE_EINVAL, "NULL sim");
+    if (run < 0 || run >= s->n_runs) return fail(WE_EINVAL, "run out of range");
+    we_status st = read_err(s);
+    if (st != WE_OK) return st;
+    int32_t nn = 0;
+    HIP_TRY(hipMemcpy(&nn, s->args.n_walk + run, 4, hipMemcpyDeviceToHost));
+    const size_t base = (size_t)run * s->cap;
+    if (n) *n = nn;
+    if (x) HIP_TRY(hipMemcpy(x, s->x[s->cur] + base * s->S, 4 * (size_t)nn * s->S, hipMemcpyDeviceToHost));
+    if (w) HIP_TRY(hipMemcpy(w, s->w[s->cur] + base, 8 * (size_t)nn, hipMemcpyDeviceToHost));
+    if (bin) HIP_TRY(hipMemcpy(bin, s->args.bin + base, 4 * (size_t)nn, hipMemcpyDeviceToHost));
+    if (origin) HIP_TRY(hipMemcpy(origin, s->args.origin + base, 4 * (size_t)nn, hipMemcpyDeviceToHost));
+    return WE_OK;
+}
+
+extern "C" we_status we_histogram(we_sim *s, int32_t run, int32_t species, int32_t lo, int32_t hi,
+                                  double *out) {
+    if (!s || !out) return fail(WE_EINVAL, "NULL argument");
+    if (species < 0 || species >= s->S || hi < lo) return fail(WE_EINVAL, "bad histogram range");
+    int32_t n = 0;
+    std::vector<int32_t> x((size_t)s->cap * s->S);
+    std::vector<double> w(s->cap);
+    we_status st = we_get_walkers(s, run, &n, x.data(), w.data(), nullptr, nullptr);
+    if (st != WE_OK) return st;
+    std::fill(out, out + (hi - lo + 1), 0.0);
+    for (int32_t k = 0; k < n; ++k) {
+        const int32_t v = x[(size_t)k * s->S + species];
+        if (v >= lo && v <= hi) out[v - lo] += w[k];
+    }
+    return WE_OK;
+}
+
+extern "C" we_status we_histogram_accum(we_sim *s, double *out, int32_t *n_iters) {
+    if (!s || !out) return fail(WE_EINVAL, "NULL argument");
+    if (s->args.nh <= 0) return fail(WE_ESTATE, "no histogram was requested at init");
+    we_status st = read_err(s);
+    if (st != WE_OK) return st;
+    HIP_TRY(hipMemcpy(out, s->args.hist, 8 * (size_t)s->n_runs * s->args.nh, hipMemcpyDeviceToHost));
+    if (n_iters) *n_iters = s->hist_iters;
+    return WE_OK;
+}
+
+extern "C" we_status we_flux(we_sim *s, int32_t run, int32_t first, int32_t count, double *out) {
+    if (!s || (!out && count > 0)) return fail(WE_EINVAL, "NULL argument");
+    if (run < 0 || run >= s->n_runs || first < 0 || count < 0 || first + count > s->iter)
+        return fail(WE_EINVAL, "flux range out of bounds");
+    we_status st = read_err(s);
+    if (st != WE_OK) return st;
+    if (count > 0)
+        HIP_TRY(hipMemcpy(out, s->args.flux + (size_t)run * s->max_iters + first, 8 * (size_t)count,
+                          hipMemcpyDeviceToHost));
+    return WE_OK;
+}
+
+extern "C" we_status we_mfpt(we_sim *s, int32_t discard, double *mfpt, double *flux_mean,
+                             double *flux_sem) {
+    if (!s) return fail(WE_EINVAL, "NULL sim");
+    if (discard < 0 || discard >= s->iter) return fail(WE_EINVAL, "discard must be < iterations run");
+    const int32_t cnt = s->iter - discard;
+    std::vector<double> f(cnt), per_run(s->n_runs);
+    for (int32_t r = 0; r < s->n_runs; ++r) {
+        we_status st = we_flux(s, r, discard, cnt, f.data());
+        if (st != WE_OK) return st;
+        double acc = 0.0;
+        for (double v : f) acc += v;
+        per_run[r] = acc / cnt / s->tau;
+    }
+    double mean = 0.0;
+    for (double v : per_run) mean += v;
+    mean /= s->n_runs;
+    double var = 0.0;
+    for (double v : per_run) var += (v - mean) * (v - mean);
+    const double sem = s->n_runs > 1 ? std::sqrt(var / (s->n_runs - 1) / s->n_runs) : NAN;
+    if (flux_mean) *flux_mean = mean;
+    if (flux_sem) *flux_sem = sem;
+    if (mfpt) *mfpt = mean > 0.0 ? 1.0 / mean : INFINITY;
+    return WE_OK;
+}
+
+extern "C" we_status we_events_series(we_sim *s, int32_t first, int32_t count, int64_t *out) {
+    if (!s || (!out && count > 0)) return fail(WE_EINVAL, "NULL argument");
+    if (first < 0 || count < 0 || first + count > s->iter) return fail(WE_EINVAL, "range out of bounds");
+    we_status st = read_err(s);
+    if (st != WE_OK) return st;
+    std::vector<int64_t> buf((size_t)s->n_runs * s->max_iters);
+    HIP_TRY(hipMemcpy(buf.data(), s->args.ev_iter, 8 * buf.size(), hipMemcpyDeviceToHost));
+    for (int32_t i = 0; i < count; ++i) {
+        int64_t acc = 0;
+        for (int32_t r = 0; r < s->n_runs; ++r) acc += buf[(size_t)r * s->max_iters + first + i];
+        out[i] = acc;
+    }
+    return WE_OK;
+}
+
+extern "C" we_status we_counters(we_sim *s, int64_t *events, int64_t *segments, int32_t *iterations) {
+    if (!s) return fail(WE_EINVAL, "NULL sim");
+    we_status st = read_err(s);
+    if (st != WE_OK) return st;
+    std::vector<int64_t> buf((size_t)s->n_runs * s->max_iters);
+    HIP_TRY(hipMemcpy(buf.data(), s->args.ev_iter, 8 * buf.size(), hipMemcpyDeviceToHost));
+    std::vector<int32_t> seg((size_t)s->n_runs * s->max_iters);
+    HIP_TRY(hipMemcpy(seg.data(), s->args.seg_iter, 4 * seg.size(), hipMemcpyDeviceToHost));
+    int64_t ev = 0, sg = 0;
+    for (int32_t r = 0; r < s->n_runs; ++r)
+        for (int32_t i = 0; i < s->iter; ++i) {
+            ev += buf[(size_t)r * s->max_iters + i];
+            sg += seg[(size_t)r * s->max_iters + i];
+        }
+    if (events) *events = ev;
+    if (segments) *segments = sg;
+    if (iterations) *iterations = s->iter;
+    return WE_OK;
+}
+
+extern "C" void we_destroy(we_sim *s) {
+    if (!s) return;
+    if (s->stream) (void)hipStreamSynchronize(s->stream);
+    else (void)hipDeviceSynchronize();
+    if (s->owns_ws) (void)hipFree(s->ws);
+    delete s;
+}
+
+extern "C" const char *we_last_error(void) { return g_err.c_str(); }

@@ -1,0 +1,263 @@
+"""Python binding of libwe.so (the C ABI in include/we.h).
+
+Argument marshalling only: every step of the WE iteration runs in the HIP
+kernels of libwe.so.  PyTorch supplies the device workspace and the stream.
+There is no CPU fallback: if libwe.so is missing or no HIP device is
+present, construction raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libwe.so")
+
+WE_OK, WE_EINVAL, WE_ENOMEM, WE_EDEVICE, WE_ECAPACITY, WE_EOVERFLOW, WE_ESTATE = 0, -1, -2, -3, -4, -5, -6
+WE_KERNEL_AUTO, WE_KERNEL_LANE, WE_KERNEL_WAVE = 0, 1, 2
+WE_COUNT_MAX = 131071
+
+_STATUS = {WE_EINVAL: "EINVAL", WE_ENOMEM: "ENOMEM", WE_EDEVICE: "EDEVICE",
+           WE_ECAPACITY: "ECAPACITY", WE_EOVERFLOW: "EOVERFLOW", WE_ESTATE: "ESTATE"}
+
+EXPORTED = [
+    "we_create_network", "we_destroy_network", "we_workspace_size", "we_init", "we_set_ensemble",
+    "we_step_intervals", "we_synchronize", "we_get_walkers", "we_histogram", "we_histogram_accum",
+    "we_flux", "we_mfpt", "we_counters", "we_events_series", "we_destroy", "we_last_error",
+]
+
+
+class WEError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class _Grid(C.Structure):
+    _fields_ = [("n_bins", C.c_int32), ("coef", C.c_void_p), ("edges", C.c_void_p)]
+
+
+class _Params(C.Structure):
+    _fields_ = [("tau", C.c_double), ("m_targ", C.c_int32), ("n_runs", C.c_int32),
+                ("max_iters", C.c_int32), ("kernel", C.c_int32), ("seeds", C.c_void_p),
+                ("x0", C.c_void_p), ("recycle", C.c_int32), ("tgt_coef", C.c_void_p),
+                ("tgt_thr", C.c_double), ("x_rec", C.c_void_p), ("hist_species", C.c_int32),
+                ("hist_lo", C.c_int32), ("hist_hi", C.c_int32)]
+
+
+_LIB = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libwe.so and declare its signatures.  Raises if it is missing."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(path):
+        raise RuntimeError(f"libwe.so not built ({path}); run __graft_entry__.build()")
+    L = C.CDLL(path)
+    P, vp, i32, i64, f64 = C.POINTER, C.c_void_p, C.c_int32, C.c_int64, C.c_double
+    L.we_create_network.argtypes = [i32, i32] + [vp] * 7 + [P(vp)]
+    L.we_destroy_network.argtypes = [vp]
+    L.we_destroy_network.restype = None
+    L.we_workspace_size.argtypes = [vp, vp, vp, P(C.c_size_t)]
+    L.we_init.argtypes = [vp, vp, vp, vp, vp, C.c_size_t, P(vp)]
+    L.we_set_ensemble.argtypes = [vp, i32, i32, vp, vp]
+    L.we_step_intervals.argtypes = [vp, i32]
+    L.we_synchronize.argtypes = [vp]
+    L.we_get_walkers.argtypes = [vp, i32, P(i32), vp, vp, vp, vp]
+    L.we_histogram.argtypes = [vp, i32, i32, i32, i32, vp]
+    L.we_histogram_accum.argtypes = [vp, vp, P(i32)]
+    L.we_flux.argtypes = [vp, i32, i32, i32, vp]
+    L.we_mfpt.argtypes = [vp, i32, P(f64), P(f64), P(f64)]
+    L.we_counters.argtypes = [vp, P(i64), P(i64), P(i32)]
+    L.we_events_series.argtypes = [vp, i32, i32, vp]
+    L.we_destroy.argtypes = [vp]
+    L.we_destroy.restype = None
+    L.we_last_error.restype = C.c_char_p
+    for name in EXPORTED:
+        fn = getattr(L, name)
+        if name not in ("we_destroy", "we_destroy_network", "we_last_error"):
+            fn.restype = C.c_int
+    _LIB = L
+    return L
+
+
+def _check(st: int):
+    if st != WE_OK:
+        raise WEError(st, load_library().we_last_error().decode())
+
+
+def _ptr(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data
+
+
+class Network:
+    """A compiled reaction network on the device (we_create_network)."""
+
+    def __init__(self, net):
+        L = load_library()
+        self.net = net
+        self.S, self.R = int(net.S), int(net.R)
+        arrs = [np.ascontiguousarray(getattr(net, k), dtype=np.int32) for k in
+                ("reac_ptr", "reac_species", "reac_mult", "chg_ptr", "chg_species", "chg_delta")]
+        rate = np.ascontiguousarray(net.rate, dtype=np.float64)
+        h = C.c_void_p()
+        _check(L.we_create_network(self.S, self.R, *[_ptr(a) for a in arrs], _ptr(rate),
+                                   C.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load_library().we_destroy_network(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Sim:
+    """n_runs independent WE runs of one network on the current HIP device.
+
+    The workspace is a torch uint8 tensor; kernels run on torch's current
+    stream of that device."""
+
+    def __init__(self, network: Network, bin_coef, edges, *, tau: float, m_targ: int,
+                 seeds: Sequence[int], x0, max_iters: int, kernel: int = WE_KERNEL_AUTO,
+                 recycle: bool = False, tgt_coef=None, tgt_thr: float = 0.0, x_rec=None,
+                 hist_species: int = 0, hist_lo: int = 0, hist_hi: int = -1, device=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device: libwe.so runs on MI355X only")
+        L = load_library()
+        self.network = network
+        S = network.S
+        self._keep = dict(
+            coef=np.ascontiguousarray(bin_coef, np.float64),
+            edges=np.ascontiguousarray(edges, np.float64),
+            seeds=np.ascontiguousarray(seeds, np.uint64),
+            x0=np.ascontiguousarray(x0, np.int32),
+            tgt=None if tgt_coef is None else np.ascontiguousarray(tgt_coef, np.float64),
+            xrec=None if x_rec is None else np.ascontiguousarray(x_rec, np.int32),
+        )
+        k = self._keep
+        if k["coef"].shape != (S,) or k["x0"].shape != (S,):
+            raise ValueError("bin_coef and x0 need one entry per species")
+        self.n_bins = len(k["edges"]) - 1
+        self.n_runs = len(k["seeds"])
+        self.m_targ = int(m_targ)
+        self.cap = self.m_targ * self.n_bins
+        self.S = S
+        self.tau = float(tau)
+        self.grid = _Grid(self.n_bins, k["coef"].ctypes.data, k["edges"].ctypes.data)
+        self.params = _Params(float(tau), int(m_targ), self.n_runs, int(max_iters), int(kernel),
+                              k["seeds"].ctypes.data, k["x0"].ctypes.data, int(bool(recycle)),
+                              _ptr(k["tgt"]), float(tgt_thr), _ptr(k["xrec"]),
+                              int(hist_species), int(hist_lo), int(hist_hi))
+        self.nh = hist_hi - hist_lo + 1 if hist_hi >= hist_lo else 0
+        nbytes = C.c_size_t(0)
+        _check(L.we_workspace_size(network.handle, C.byref(self.grid), C.byref(self.params),
+                                   C.byref(nbytes)))
+        dev = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        self.device = dev
+        with torch.cuda.device(dev):
+            self.workspace = torch.empty(int(nbytes.value) + 256, dtype=torch.uint8, device=dev)
+            self.stream = torch.cuda.current_stream(dev)
+        base = self.workspace.data_ptr()
+        aligned = (base + 255) & ~255
+        h = C.c_void_p()
+        _check(L.we_init(network.handle, C.byref(self.grid), C.byref(self.params),
+                         C.c_void_p(self.stream.cuda_stream), C.c_void_p(aligned),
+                         C.c_size_t(int(nbytes.value)), C.byref(h)))
+        self.handle = h
+
+    # ------------------------------------------------------------ stepping
+    def set_ensemble(self, run: int, x, w):
+        x = np.ascontiguousarray(x, np.int32).reshape(-1)
+        w = np.ascontiguousarray(w, np.float64)
+        _check(load_library().we_set_ensemble(self.handle, run, len(w), _ptr(x), _ptr(w)))
+
+    def step(self, n: int = 1):
+        _check(load_library().we_step_intervals(self.handle, int(n)))
+
+    def synchronize(self):
+        _check(load_library().we_synchronize(self.handle))
+
+    # ------------------------------------------------------------ outputs
+    def walkers(self, run: int):
+        n = C.c_int32(0)
+        x = np.zeros(self.cap * self.S, np.int32)
+        w = np.zeros(self.cap, np.float64)
+        b = np.zeros(self.cap, np.int32)
+        o = np.zeros(self.cap, np.int32)
+        _check(load_library().we_get_walkers(self.handle, run, C.byref(n), _ptr(x), _ptr(w),
+                                             _ptr(b), _ptr(o)))
+        m = n.value
+        return x[: m * self.S].reshape(m, self.S), w[:m], b[:m], o[:m]
+
+    def histogram(self, run: int, species: int, lo: int, hi: int) -> np.ndarray:
+        out = np.zeros(hi - lo + 1, np.float64)
+        _check(load_library().we_histogram(self.handle, run, species, lo, hi, _ptr(out)))
+        return out
+
+    def histogram_accum(self):
+        out = np.zeros(self.n_runs * self.nh, np.float64)
+        n = C.c_int32(0)
+        _check(load_library().we_histogram_accum(self.handle, _ptr(out), C.byref(n)))
+        return out.reshape(self.n_runs, self.nh), n.value
+
+    def flux(self, run: int, first: int = 0, count: Optional[int] = None) -> np.ndarray:
+        if count is None:
+            count = self.iterations - first
+        out = np.zeros(count, np.float64)
+        _check(load_library().we_flux(self.handle, run, first, count, _ptr(out)))
+        return out
+
+    def mfpt(self, discard: int):
+        m, f, e = C.c_double(), C.c_double(), C.c_double()
+        _check(load_library().we_mfpt(self.handle, discard, C.byref(m), C.byref(f), C.byref(e)))
+        return m.value, f.value, e.value
+
+    def counters(self):
+        ev, sg, it = C.c_int64(), C.c_int64(), C.c_int32()
+        _check(load_library().we_counters(self.handle, C.byref(ev), C.byref(sg), C.byref(it)))
+        return ev.value, sg.value, it.value
+
+    def events_series(self, first: int = 0, count: Optional[int] = None) -> np.ndarray:
+        if count is None:
+            count = self.iterations - first
+        out = np.zeros(count, np.int64)
+        _check(load_library().we_events_series(self.handle, first, count, _ptr(out)))
+        return out
+
+    @property
+    def iterations(self) -> int:
+        return self.counters()[2]
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load_library().we_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def sim_from_config(cfg, *, kernel: int = WE_KERNEL_AUTO, max_iters: Optional[int] = None,
+                    network: Optional[Network] = None) -> Sim:
+    """Build a Sim from a workloads.WEConfig."""
+    net = network if network is not None else Network(cfg.net)
+    return Sim(net, cfg.bin_coef, cfg.edges, tau=cfg.tau, m_targ=cfg.m_targ, seeds=cfg.seeds,
+               x0=cfg.x0, max_iters=max_iters if max_iters is not None else cfg.n_iters,
+               kernel=kernel, recycle=cfg.recycle, tgt_coef=cfg.tgt_coef, tgt_thr=cfg.tgt_thr,
+               x_rec=cfg.x_rec, hist_species=cfg.hist_species, hist_lo=cfg.hist_lo,
+               hist_hi=cfg.hist_hi)

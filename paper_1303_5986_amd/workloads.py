@@ -192,3 +192,139 @@ def isomerization(k_ab: float = 1.0, k_ba: float = 0.5) -> Network:
     """A <-> B: with N molecules the stationary law of A is Binomial."""
     return Network.from_reactions(["A", "B"], [({"A": 1}, {"B": 1}, k_ab),
                                                ({"B": 1}, {"A": 1}, k_ba)])
+
+
+# --------------------------------------------------------------------------
+# Seeded random mass-action networks shaped like the 354-species /
+# 3680-reaction model of Sec. III.D.
+# --------------------------------------------------------------------------
+def random_network(seed: int, S: int = 354, R: int = 3680, frac_zeroth: float = 0.1,
+                   frac_uni: float = 0.4, rate_lo: float = 1e-4, rate_hi: float = 1e1) -> Network:
+    """A random mass-action network from a seed.
+
+    * every species decays, X -> 0 (part of the unimolecular share), so every
+      species has an outflow;
+    * species carry masses m in {1,2,3}; every reaction with reactants keeps
+      sum(m products) <= sum(m reactants), so only the zeroth-order inflows
+      0 -> X add mass and copy numbers stay bounded;
+    * unimolecular X -> Y | Y + Z, bimolecular X + Y -> Z | Z + W (homodimers
+      X + X allowed), zeroth order 0 -> X | X + Y, no duplicate reactions;
+    * rate constants log-uniform on [rate_lo, rate_hi].
+    """
+    rng = np.random.default_rng(seed)
+    mass = rng.integers(1, 4, size=S)
+    names = [f"s{i}" for i in range(S)]
+    n0 = int(round(frac_zeroth * R))
+    n1 = int(round(frac_uni * R))
+    n2 = R - n0 - n1
+    if n1 < S:
+        raise ValueError("need at least one unimolecular reaction per species (decays)")
+    seen = set()
+    reactions = []
+
+    def rate():
+        return float(np.exp(rng.uniform(np.log(rate_lo), np.log(rate_hi))))
+
+    def add(reac: Dict[str, int], prod: Dict[str, int]) -> bool:
+        key = (tuple(sorted(reac.items())), tuple(sorted(prod.items())))
+        if key in seen or reac == prod:
+            return False
+        seen.add(key)
+        reactions.append((reac, prod, rate()))
+        return True
+
+    def products_within(budget: int) -> Dict[str, int]:
+        # zero, one or two product molecules whose total mass fits the budget
+        choice = rng.integers(0, 3)
+        prod: Dict[str, int] = {}
+        if choice == 0:
+            return prod
+        cand = np.flatnonzero(mass <= budget)
+        if len(cand) == 0:
+            return prod
+        a = int(rng.choice(cand))
+        prod[names[a]] = 1
+        if choice == 2:
+            cand2 = np.flatnonzero(mass <= budget - mass[a])
+            if len(cand2):
+                b = int(rng.choice(cand2))
+                prod[names[b]] = prod.get(names[b], 0) + 1
+        return prod
+
+    for s in range(S):
+        add({names[s]: 1}, {})
+    while len(reactions) < S + (n1 - S):
+        s = int(rng.integers(0, S))
+        prod = products_within(int(mass[s]))
+        if not prod:
+            continue
+        add({names[s]: 1}, prod)
+    while len(reactions) < n1 + n2:
+        a, b = (int(v) for v in rng.integers(0, S, size=2))
+        reac = {names[a]: 2} if a == b else {names[a]: 1, names[b]: 1}
+        add(reac, products_within(int(mass[a] + mass[b])))
+    while len(reactions) < R:
+        # inflow of one molecule, or of two once single inflows run out
+        a, b = (int(v) for v in rng.integers(0, S, size=2))
+        prod = {names[a]: 1} if rng.random() < 0.5 or len(reactions) - n1 - n2 >= S // 2 \
+            else ({names[a]: 2} if a == b else {names[a]: 1, names[b]: 1})
+        add({}, prod)
+    net = Network.from_reactions(names, reactions)
+    net.mass = mass
+    return net
+
+
+def log_uniform_counts(rng: np.random.Generator, S: int, hi: int = 1000) -> np.ndarray:
+    """floor(exp(U[0, ln(hi+1)])) - 1, i.e. counts on [0, hi], log-uniform."""
+    return (np.floor(np.exp(rng.uniform(0.0, np.log(hi + 1.0), size=S))) - 1).astype(np.int32)
+
+
+def producing_counts(net: Network) -> np.ndarray:
+    """Number of reactions that increase each species."""
+    c = np.zeros(net.S, np.int64)
+    for j in range(net.R):
+        for p in range(net.chg_ptr[j], net.chg_ptr[j + 1]):
+            if net.chg_delta[p] > 0:
+                c[net.chg_species[p]] += 1
+    return c
+
+
+def first_order_loss(net: Network) -> np.ndarray:
+    """kappa_s: summed rate constants of the unimolecular reactions that
+    consume species s (weighted by copies consumed)."""
+    k = np.zeros(net.S)
+    for j in range(net.R):
+        if net.order(j) != 1:
+            continue
+        for p in range(net.chg_ptr[j], net.chg_ptr[j + 1]):
+            if net.chg_delta[p] < 0:
+                k[net.chg_species[p]] += net.rate[j] * (-net.chg_delta[p])
+    return k
+
+
+def large_network_config(seed: int = 2024, n_walkers: int = 4096, n_bins: int = 50,
+                         n_iters: int = 50, tau: float = 0.1, S: int = 354,
+                         R: int = 3680) -> WEConfig:
+    """Synthetic stand-in for the 354/3680 model of Sec. III.D: seeded network,
+    log-uniform initial counts on [0, 1000], 50 bins of width 20 on [0, 1000),
+    floor(4096/50) = 81 walkers per bin, tau = 0.1.
+
+    The binned species is the one with the largest x0_s * exp(-kappa_s * 1 s)
+    (kappa_s its first-order loss constant): a structural rule that picks a
+    species present in hundreds of copies and slow to decay, so the 50 bins
+    are actually visited.  The joint histogram takes the next four by the
+    same score."""
+    net = random_network(seed, S, R)
+    rng = np.random.default_rng(seed + 1)
+    x0 = log_uniform_counts(rng, S)
+    score = x0 * np.exp(-first_order_loss(net))
+    order = sorted(range(S), key=lambda s: (-score[s], s))
+    bs = order[0]
+    coef = np.zeros(S)
+    coef[bs] = 1.0
+    cfg = WEConfig(name="large_network", net=net, x0=x0, bin_coef=coef,
+                   edges=uniform_edges(0.0, 1000.0, n_bins), m_targ=n_walkers // n_bins, tau=tau,
+                   n_iters=n_iters, seeds=np.array([seed], np.uint64),
+                   hist_species=bs, hist_lo=0, hist_hi=1000)
+    cfg.joint_species = order[:5]
+    return cfg
