@@ -58,6 +58,12 @@ def load_library(path: str = LIB_PATH):
         return _LIB
     if not os.path.exists(path):
         raise RuntimeError(f"libwe.so not built ({path}); run __graft_entry__.build()")
+    # torch ships its own libamdhip64 with the same soname as ROCm's: load and
+    # initialise it first so libwe.so binds to that one runtime, not a second.
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("no HIP device: libwe.so runs on MI355X only")
+    torch.cuda.init()
     L = C.CDLL(path)
     P, vp, i32, i64, f64 = C.POINTER, C.c_void_p, C.c_int32, C.c_int64, C.c_double
     L.we_create_network.argtypes = [i32, i32] + [vp] * 7 + [P(vp)]
