@@ -1,0 +1,202 @@
+#!/usr/bin/env python3
+"""Benchmark: weighted-ensemble SSA on one MI355X.
+
+One step = one full WE iteration over every run of the workload: propagate
+every walker through tau (Gillespie direct method), recycle walkers that
+reached the target, bin, split/merge per bin, accumulate the histogram.
+
+Default workload: the Schloegl model (Sec. III.B) in steady state with
+recycling X >= 563 -> 82, 60 bins of width 40/3 on [0, 800], 8 walkers per
+bin, tau = 0.05 -- 2048 independent replicas in one launch.  Inputs are
+synthetic (the model is fully specified by its rate constants); the ensemble
+is resident in HBM for the whole timed region.
+
+Prints one JSON line.  `value` is SSA events/s over the K timed steps.
+`roofline` covers the propagation kernel (the dominant one), timed with HIP
+events on the sim's stream; `cpu_baseline` is the sequential CPU oracle on a
+bounded sample of the same workload.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+METRIC = "SSA events/s; GPU-seconds to MFPT rel-err 5%, learned vs plain bins"
+
+# MI355X: 256 CUs, 64 lanes each, 2.4 GHz; one VALU operation per lane per clock
+# (FP64 FMA at this rate gives the published 78.6 TFLOP/s).
+PEAK_LANE_OPS = 256 * 64 * 2.4e9
+PEAK_HBM = 8.0e12
+
+
+def alg_ops_per_event(net) -> float:
+    """Arithmetic of one direct-method event with full propensity recompute,
+    counted per operation of the algorithm (each a single lane operation; a
+    log or a divide counts as one):
+      Philox4x32-10: 10 rounds x (2 mul-lo, 2 mul-hi, 4 xor, 2 key adds) = 100
+      two 53-bit uniforms: 2 x (2 shifts, 1 or, 1 convert, 1 scale)      = 10
+      waiting time: 1 - u1, log, divide by a0, t + dt, compare to tau     = 5
+      selection target u2*a0, time update                                 = 2
+      per reaction: reactant factor (C(x,2): 3, C(x,3): 6, two species: 1)
+        + convert + multiply by c + add to a0 + running sum + compare     = 5 + f_j
+      state update: one add per changed species + 2 bound checks.
+    """
+    per_rxn = 0.0
+    for j in range(net.R):
+        f = 0
+        lo, hi = net.reac_ptr[j], net.reac_ptr[j + 1]
+        for p in range(lo, hi):
+            nu = int(net.reac_mult[p])
+            f += {1: 0, 2: 3, 3: 6}[nu]
+        if hi - lo == 2:
+            f += 1
+        per_rxn += 5 + f
+    nchg = np.diff(net.chg_ptr).mean()
+    return 100 + 10 + 5 + 2 + per_rxn + nchg + 2
+
+
+def source_digest(paths):
+    h = hashlib.sha256()
+    for p in paths:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(kernel_tag: str, digest: str):
+    """HBM bytes per launch measured by rocprofv3 counters, if the committed
+    measurement was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", f"{kernel_tag}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("source_digest") != digest:
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(cfg, n_runs: int, n_iters: int):
+    from oracle import oracle as orc
+    ev = 0
+    t0 = time.perf_counter()
+    for r in range(n_runs):
+        o = orc.OracleWE(cfg, int(cfg.seeds[r]))
+        o.step(n_iters)
+        ev += sum(o.events)
+    dt = time.perf_counter() - t0
+    return ev / dt, dt, ev
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=300)
+    ap.add_argument("--warmup", type=int, default=150)
+    ap.add_argument("--runs", type=int, default=2048)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-runs", type=int, default=4)
+    ap.add_argument("--cpu-iters", type=int, default=400)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain device-to-device copy of MIB MiB five times "
+                         "(reference kernel for scaling the HBM byte counters)")
+    args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+        n = args.calibrate_copy * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": n * 4, "copies": 5}), flush=True)
+        return
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); "
+              "the weighted-ensemble runs shard by run with no communication, "
+              "so N GPUs would each run this same line on their own replicas.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1303_5986_amd import we, workloads as wl
+
+    K, W = args.steps, args.warmup
+    cfg = wl.schlogl_config(n_runs=args.runs, seed0=1, n_iters=W + K)
+    sim = we.sim_from_config(cfg, kernel=we.WE_KERNEL_LANE, max_iters=W + K)
+    sim.step(W)
+    sim.synchronize()
+    ev0, seg0, _ = sim.counters()
+    sim.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(K)
+    sim.synchronize()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_ssa, ms_res, ms_obs, n_prof = sim.profile_read()
+    ev1, seg1, _ = sim.counters()
+    elapsed = t1 - t0
+    events = ev1 - ev0
+    segments = seg1 - seg0
+    value = events / elapsed
+
+    ops_ev = alg_ops_per_event(cfg.net)
+    ssa_avg_s = ms_ssa / 1e3 / K
+    ev_per_launch = events / K
+    achieved = ops_ev * ev_per_launch / ssa_avg_s
+    digest = source_digest(["paper_1303_5986_amd/csrc/ssa_lane.hip",
+                            "paper_1303_5986_amd/csrc/we_common.h"])
+    traffic = traffic_from_profiles("ssa_lane_schlogl", digest)
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "events/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": elapsed * 1e3 / K,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "schlogl_steady_state_recycling", "runs": args.runs,
+                   "bins": cfg.n_bins, "walkers_per_bin": cfg.m_targ, "tau": cfg.tau,
+                   "target": "X>=563 -> X=82", "kernel": "ssa_lane",
+                   "walkers_per_step": segments / K},
+        "we_iters_per_s": K / elapsed,
+        "events_per_segment": events / max(segments, 1),
+        "kernel_ms_per_step": {"ssa_lane": ms_ssa / K, "resample": ms_res / K,
+                               "observe": ms_obs / K},
+        "roofline": {
+            "bound": "alu",
+            "achieved": achieved / 1e12,
+            "peak": PEAK_LANE_OPS / 1e12,
+            "unit": "Tops/s",
+            "frac": achieved / PEAK_LANE_OPS,
+            "traffic": traffic,
+            "ops_per_event": ops_ev,
+            "kernel": "ssa_lane_kernel<1,4>",
+            "avg_launch_ms": ms_ssa / K,
+            "events_per_launch": ev_per_launch,
+        },
+    }
+    if not args.no_cpu:
+        cpu_cfg = wl.schlogl_config(n_runs=args.cpu_runs, seed0=1, n_iters=args.cpu_iters)
+        rate, secs, cev = cpu_baseline(cpu_cfg, args.cpu_runs, args.cpu_iters)
+        out["cpu_baseline"] = {"value": rate, "unit": "events/s", "cores": 1, "kind": "oracle",
+                               "sample": f"{args.cpu_runs} runs x {args.cpu_iters} WE iterations "
+                                         f"of the same workload from its initial ensemble "
+                                         f"({cev} events, {secs:.1f} s, single thread)"}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

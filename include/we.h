@@ -184,6 +184,16 @@ WE_API we_status we_counters(we_sim *s, int64_t *events, int64_t *segments,
  * [first, first+count).  Synchronous. */
 WE_API we_status we_events_series(we_sim *s, int32_t first, int32_t count, int64_t *out);
 
+/* Per-kernel timing with HIP events recorded on the sim's stream around
+ * every launch.  we_profile(s, 1) clears and starts the accumulators,
+ * we_profile(s, 0) stops recording.  we_profile_read waits for the stream
+ * and returns the summed device time in milliseconds of the propagation
+ * (SSA) kernels, the recycle/bin/resample kernels and the observable
+ * kernels, and the number of iterations they cover.  Synchronous. */
+WE_API we_status we_profile(we_sim *s, int32_t enable);
+WE_API we_status we_profile_read(we_sim *s, double *ms_propagate, double *ms_resample,
+                                 double *ms_observe, int64_t *iterations);
+
 WE_API void we_destroy(we_sim *s);
 WE_API const char *we_last_error(void);
 

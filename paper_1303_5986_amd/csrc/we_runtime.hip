@@ -79,7 +79,42 @@ struct we_sim {
     int32_t *x[2] = {nullptr, nullptr};
     double *w[2] = {nullptr, nullptr};
     std::vector<int32_t> n_host; // walker counts known on the host (before first step)
+    // per-kernel timing: 4 events per profiled iteration
+    bool profiling = false;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+    double prof_ms[3] = {0.0, 0.0, 0.0};
+    int64_t prof_iters = 0;
 };
+
+namespace {
+hipError_t next_event(we_sim *s, hipEvent_t *out) {
+    if (s->ev_used == s->ev_pool.size()) {
+        hipEvent_t e;
+        hipError_t err = hipEventCreate(&e);
+        if (err != hipSuccess) return err;
+        s->ev_pool.push_back(e);
+    }
+    *out = s->ev_pool[s->ev_used++];
+    return hipSuccess;
+}
+
+hipError_t drain_profile(we_sim *s) {
+    hipError_t e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return e;
+    for (size_t i = 0; i + 3 < s->ev_used; i += 4) {
+        float t[3] = {0.f, 0.f, 0.f};
+        for (int k = 0; k < 3; ++k) {
+            e = hipEventElapsedTime(&t[k], s->ev_pool[i + k], s->ev_pool[i + k + 1]);
+            if (e != hipSuccess) return e;
+            s->prof_ms[k] += t[k];
+        }
+        s->prof_iters += 1;
+    }
+    s->ev_used = 0;
+    return hipSuccess;
+}
+}  // namespace
 
 // ------------------------------------------------------------------ network
 extern "C" we_status we_create_network(int32_t S, int32_t R, const int32_t *reac_ptr,
@@ -427,16 +462,25 @@ extern "C" we_status we_step_intervals(we_sim *s, int32_t n) {
     for (int32_t i = 0; i < n; ++i) {
         const uint32_t it = (uint32_t)s->iter;
         const int32_t c = s->cur, nx = 1 - c;
+        hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+        if (s->profiling) {
+            if (s->ev_used + 4 > 4096) HIP_TRY(drain_profile(s));
+            for (int k = 0; k < 4; ++k) HIP_TRY(next_event(s, &ev[k]));
+            HIP_TRY(hipEventRecord(ev[0], s->stream));
+        }
         hipError_t e = (s->kernel == WE_KERNEL_WAVE) ? launch_ssa_wave(a, s->x[c], it, s->stream)
                                                      : launch_ssa_lane(a, s->x[c], it, s->stream);
         if (e != hipSuccess) return hip_fail(e, "SSA launch");
+        if (s->profiling) HIP_TRY(hipEventRecord(ev[1], s->stream));
         e = launch_resample(a, s->x[c], s->w[c], s->x[nx], s->w[nx], it, (int32_t)it, s->stream);
         if (e != hipSuccess) return hip_fail(e, "resample launch");
+        if (s->profiling) HIP_TRY(hipEventRecord(ev[2], s->stream));
         if (a.nh > 0) {
             e = launch_observe(a, s->x[nx], s->w[nx], s->stream);
             if (e != hipSuccess) return hip_fail(e, "observe launch");
             s->hist_iters += 1;
         }
+        if (s->profiling) HIP_TRY(hipEventRecord(ev[3], s->stream));
         s->cur = nx;
         s->iter += 1;
     }
@@ -564,10 +608,32 @@ extern "C" we_status we_counters(we_sim *s, int64_t *events, int64_t *segments, 
     return WE_OK;
 }
 
+extern "C" we_status we_profile(we_sim *s, int32_t enable) {
+    if (!s) return fail(WE_EINVAL, "NULL sim");
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    s->ev_used = 0;
+    s->prof_ms[0] = s->prof_ms[1] = s->prof_ms[2] = 0.0;
+    s->prof_iters = 0;
+    s->profiling = enable != 0;
+    return WE_OK;
+}
+
+extern "C" we_status we_profile_read(we_sim *s, double *ms_propagate, double *ms_resample,
+                                     double *ms_observe, int64_t *iterations) {
+    if (!s) return fail(WE_EINVAL, "NULL sim");
+    HIP_TRY(drain_profile(s));
+    if (ms_propagate) *ms_propagate = s->prof_ms[0];
+    if (ms_resample) *ms_resample = s->prof_ms[1];
+    if (ms_observe) *ms_observe = s->prof_ms[2];
+    if (iterations) *iterations = s->prof_iters;
+    return WE_OK;
+}
+
 extern "C" void we_destroy(we_sim *s) {
     if (!s) return;
     if (s->stream) (void)hipStreamSynchronize(s->stream);
     else (void)hipDeviceSynchronize();
+    for (hipEvent_t e : s->ev_pool) (void)hipEventDestroy(e);
     if (s->owns_ws) (void)hipFree(s->ws);
     delete s;
 }

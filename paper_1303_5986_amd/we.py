@@ -26,7 +26,8 @@ _STATUS = {WE_EINVAL: "EINVAL", WE_ENOMEM: "ENOMEM", WE_EDEVICE: "EDEVICE",
 EXPORTED = [
     "we_create_network", "we_destroy_network", "we_workspace_size", "we_init", "we_set_ensemble",
     "we_step_intervals", "we_synchronize", "we_get_walkers", "we_histogram", "we_histogram_accum",
-    "we_flux", "we_mfpt", "we_counters", "we_events_series", "we_destroy", "we_last_error",
+    "we_flux", "we_mfpt", "we_counters", "we_events_series", "we_profile", "we_profile_read",
+    "we_destroy", "we_last_error",
 ]
 
 
@@ -81,6 +82,8 @@ def load_library(path: str = LIB_PATH):
     L.we_mfpt.argtypes = [vp, i32, P(f64), P(f64), P(f64)]
     L.we_counters.argtypes = [vp, P(i64), P(i64), P(i32)]
     L.we_events_series.argtypes = [vp, i32, i32, vp]
+    L.we_profile.argtypes = [vp, i32]
+    L.we_profile_read.argtypes = [vp, P(f64), P(f64), P(f64), P(i64)]
     L.we_destroy.argtypes = [vp]
     L.we_destroy.restype = None
     L.we_last_error.restype = C.c_char_p
@@ -241,6 +244,17 @@ class Sim:
         out = np.zeros(count, np.int64)
         _check(load_library().we_events_series(self.handle, first, count, _ptr(out)))
         return out
+
+    def profile(self, enable: bool = True):
+        _check(load_library().we_profile(self.handle, int(bool(enable))))
+
+    def profile_read(self):
+        """(ms in SSA kernels, ms in resample kernels, ms in observe kernels,
+        iterations covered), from HIP events on the sim's stream."""
+        a, b, c, n = C.c_double(), C.c_double(), C.c_double(), C.c_int64()
+        _check(load_library().we_profile_read(self.handle, C.byref(a), C.byref(b), C.byref(c),
+                                              C.byref(n)))
+        return a.value, b.value, c.value, n.value
 
     @property
     def iterations(self) -> int:
