@@ -101,8 +101,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=150)
     ap.add_argument("--runs", type=int, default=2048)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-runs", type=int, default=4)
-    ap.add_argument("--cpu-iters", type=int, default=400)
+    ap.add_argument("--cpu-runs", type=int, default=6)
+    ap.add_argument("--cpu-iters", type=int, default=800)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB five times "
                          "(reference kernel for scaling the HBM byte counters)")
