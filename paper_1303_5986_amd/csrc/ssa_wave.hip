@@ -1,8 +1,230 @@
-// ssa_wave.hip -- wavefront-per-walker direct-method SSA (placeholder until
-// the wave kernel lands: reports that no network fits).
+// ssa_wave.hip -- Gillespie direct-method SSA, one 64-wide wavefront per
+// walker (gfx950), for networks with up to 4096 reactions.
+//
+// The method per event is the same as the lane kernel (Sec. II.A): total
+// propensity a0, dt = -log(1 - u1)/a0 with the overshoot past tau
+// discarded, reaction j = first index whose running sum exceeds u2 * a0,
+// x += nu_j, with u1, u2 from Philox4x32-10 at (event, slot, iter, 0).
+// What changes is how the work is spread over the wave:
+//
+//  * reactions are grouped in chunks of 64 (reaction r is lane r % 64 of
+//    chunk r / 64); the wave keeps one FP64 partial sum per chunk, lane c
+//    holding chunk c's sum (so up to 64 chunks = 4096 reactions);
+//  * a0 and the chunk holding u2*a0 come from one inclusive prefix scan of
+//    the chunk sums across the wave plus a ballot; the reaction inside the
+//    chunk from a second scan over that chunk's 64 propensities,
+//    recomputed from the counts -- two wave-level prefix scans per event
+//    instead of an O(R) sequential pass;
+//  * after firing j, only the reactions whose propensity can change (the
+//    dependency list of j: every reaction taking a changed species as a
+//    reactant, sorted and without repeats) are re-evaluated, one per lane,
+//    and their propensity changes are added to the chunk sums by a
+//    segmented reduction in a fixed order, so results are reproducible;
+//  * the chunk sums are rebuilt from scratch at the start of every interval,
+//    which bounds the rounding drift of the incremental updates to one
+//    interval.
+//
+// Memory: walker counts (int32) and chunk sums live in LDS (about 2 KB per
+// walker at 354 species), so a CU holds many walkers at once; reaction
+// descriptors, stoichiometry and dependency lists are read from global
+// memory, where the whole network (~0.3 MB at 3680 reactions) stays
+// resident in the L2 caches.  No per-reaction propensity array is stored.
+//
+// Summation order differs from the sequential order of the oracle (chunked
+// scans), so a0 and the running sums can differ in the last bits; an event
+// changes only if u2*a0 or t+dt falls within a few ulps of a boundary.
 #include "we_common.h"
 
-hipError_t launch_ssa_wave(const SimArgs &, int32_t *, uint32_t, hipStream_t) {
-    return hipErrorNotSupported;
+#define WAVE_WALKERS_PER_BLOCK 4
+#define WAVE_DEP_ROUNDS 4
+
+namespace {
+
+__device__ __forceinline__ double prop_lds(const RxnDesc &d, const int32_t *lx) {
+    return propensity_from(d, (uint32_t)lx[d.s1], (uint32_t)lx[d.s2]);
 }
-bool wave_kernel_fits(int32_t, int32_t) { return false; }
+
+__device__ __forceinline__ double scan_incl(double v, int lane) {
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const double t = __shfl_up(v, off, 64);
+        if (lane >= off) v = v + t;
+    }
+    return v;
+}
+
+__device__ __forceinline__ int32_t last_set(unsigned long long m) {
+    return m ? 63 - __clzll((long long)m) : -1;
+}
+
+// Sum of all 64 propensities of chunk c, as the last lane of an inclusive scan.
+__device__ __forceinline__ double chunk_total(const SimArgs &a, const int32_t *lx, int c, int lane) {
+    const int r = c * 64 + lane;
+    double v = 0.0;
+    if (r < a.R) v = prop_lds(a.desc[r], lx);
+    v = scan_incl(v, lane);
+    return __shfl(v, 63, 64);
+}
+
+// Add, per chunk, the propensity changes held by the lanes (dependent
+// reaction rr, change dv; rr < 0 for idle lanes).  rr ascends across lanes.
+__device__ __forceinline__ void add_chunk_deltas(double *lchunk, int rr, double dv, int lane) {
+    const int ch = rr >= 0 ? (rr >> 6) : 64;
+    const double D = scan_incl(dv, lane);
+    const int ch_prev = __shfl_up(ch, 1, 64);
+    const int ch_next = __shfl_down(ch, 1, 64);
+    const bool start = (lane == 0) || (ch_prev != ch);
+    const bool end = (lane == 63) || (ch_next != ch);
+    const unsigned long long smask = __ballot(start);
+    const unsigned long long upto = (lane == 63) ? ~0ull : ((2ull << lane) - 1ull);
+    const int sl = last_set(smask & upto);
+    const double before = __shfl(D, sl > 0 ? sl - 1 : 0, 64);
+    const double seg = D - (sl > 0 ? before : 0.0);
+    if (end && ch < 64) lchunk[ch] = lchunk[ch] + seg;
+}
+
+}  // namespace
+
+__global__ __launch_bounds__(256) void ssa_wave_kernel(SimArgs a, int32_t *__restrict__ xs,
+                                                       uint32_t iter, int32_t s_pad) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    double *lchunk = reinterpret_cast<double *>(smem) + wv * 64;
+    int32_t *lx = reinterpret_cast<int32_t *>(smem + WAVE_WALKERS_PER_BLOCK * 64 * sizeof(double)) +
+                  wv * s_pad;
+
+    const int64_t gw = (int64_t)blockIdx.x * WAVE_WALKERS_PER_BLOCK + wv;
+    const int32_t run = (int32_t)(gw / a.cap);
+    const int32_t k = (int32_t)(gw - (int64_t)run * a.cap);
+    if (run >= a.n_runs) return;
+    if (k >= a.n_walk[run]) return;
+
+    const int32_t S = a.S, R = a.R;
+    const int32_t K = (R + 63) >> 6;
+    int32_t *xw = xs + ((size_t)run * a.cap + k) * S;
+    for (int s = lane; s < S; s += 64) lx[s] = xw[s];
+    __builtin_amdgcn_wave_barrier();
+
+    // chunk sums from scratch
+    double csum = 0.0;
+    for (int c = 0; c < K; ++c) {
+        const double tot = chunk_total(a, lx, c, lane);
+        if (lane == c) csum = tot;
+    }
+    lchunk[lane] = csum;
+
+    const uint64_t seed = a.seeds[run];
+    const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+    const double tau = a.tau;
+    double t = 0.0;
+    uint32_t e = 0, fired = 0;
+    bool bad = false;
+
+    for (;;) {
+        const double P = scan_incl(csum, lane);
+        const double a0 = __shfl(P, 63, 64);
+        if (!(a0 > 0.0)) break;
+        const U4 rnd = philox4x32_10(e, (uint32_t)k, iter, 0u, k0, k1);
+        e += 1;
+        const double u1 = uniform53(rnd.x, rnd.y);
+        const double u2 = uniform53(rnd.z, rnd.w);
+        const double dt = -log(1.0 - u1) / a0;
+        if (t + dt > tau) break;
+        t = t + dt;
+        const double target = u2 * a0;
+
+        // chunk holding the target
+        const unsigned long long m1 = __ballot(P > target);
+        int cs = m1 ? (__ffsll((long long)m1) - 1) : last_set(__ballot(csum > 0.0));
+        if (cs < 0) cs = 0;
+        const double base = __shfl(P - csum, cs, 64);
+        const double target2 = target - base;
+        // reaction inside the chunk
+        const int rsel = cs * 64 + lane;
+        double v = 0.0;
+        if (rsel < R) v = prop_lds(a.desc[rsel], lx);
+        const double Q = scan_incl(v, lane);
+        const unsigned long long m2 = __ballot(Q > target2);
+        const int ls = m2 ? (__ffsll((long long)m2) - 1) : last_set(__ballot(v > 0.0));
+        if (ls < 0) {              // chunk sum drifted above an all-zero chunk
+            if (lane == 0) atomicOr(a.err, WE_DERR_SELECT);
+            break;
+        }
+        const int j = cs * 64 + ls;
+
+        // propensities of the dependents before the change
+        const int32_t d0 = a.dep_ptr[j], d1 = a.dep_ptr[j + 1];
+        const int32_t nd = d1 - d0;
+        const int nround = (nd + 63) >> 6;
+        int rr[WAVE_DEP_ROUNDS];
+        double old[WAVE_DEP_ROUNDS];
+        if (nround <= WAVE_DEP_ROUNDS) {
+#pragma unroll
+            for (int q = 0; q < WAVE_DEP_ROUNDS; ++q) {
+                rr[q] = -1;
+                old[q] = 0.0;
+                if (q < nround) {
+                    const int idx = d0 + q * 64 + lane;
+                    if (idx < d1) {
+                        rr[q] = a.dep[idx];
+                        old[q] = prop_lds(a.desc[rr[q]], lx);
+                    }
+                }
+            }
+        }
+        // fire j
+        const int32_t c0 = a.chg_ptr[j], c1 = a.chg_ptr[j + 1];
+        __builtin_amdgcn_wave_barrier();
+        bool lbad = false;
+        if (lane < c1 - c0) {
+            const int32_t pc = a.chg[c0 + lane];
+            const int32_t s = change_species(pc);
+            const int32_t nv = lx[s] + change_delta(pc);
+            lx[s] = nv;
+            lbad = (nv < 0) || (nv > WE_COUNT_MAX_DEV);
+        }
+        __builtin_amdgcn_wave_barrier();
+        fired += 1;
+        if (__ballot(lbad)) { bad = true; break; }
+
+        // fold the dependents' changes into the chunk sums
+        if (nround <= WAVE_DEP_ROUNDS) {
+#pragma unroll
+            for (int q = 0; q < WAVE_DEP_ROUNDS; ++q) {
+                if (q < nround) {
+                    double dv = 0.0;
+                    if (rr[q] >= 0) dv = prop_lds(a.desc[rr[q]], lx) - old[q];
+                    add_chunk_deltas(lchunk, rr[q], dv, lane);
+                    __builtin_amdgcn_wave_barrier();
+                }
+            }
+            csum = lchunk[lane];
+        } else {
+            // very long dependency list: rebuild every chunk sum
+            csum = 0.0;
+            for (int c = 0; c < K; ++c) {
+                const double tot = chunk_total(a, lx, c, lane);
+                if (lane == c) csum = tot;
+            }
+            lchunk[lane] = csum;
+        }
+    }
+    if (bad && lane == 0) atomicOr(a.err, WE_DERR_OVERFLOW);
+    __builtin_amdgcn_wave_barrier();
+    for (int s = lane; s < S; s += 64) xw[s] = lx[s];
+    if (lane == 0) a.ev_walker[(size_t)run * a.cap + k] = fired;
+}
+
+bool wave_kernel_fits(int32_t S, int32_t R) { return R <= 4096 && S <= 8192; }
+
+hipError_t launch_ssa_wave(const SimArgs &a, int32_t *xs, uint32_t iter, hipStream_t st) {
+    if (!wave_kernel_fits(a.S, a.R)) return hipErrorInvalidValue;
+    const int32_t s_pad = (a.S + 3) & ~3;
+    const size_t shmem = WAVE_WALKERS_PER_BLOCK * (64 * sizeof(double) + sizeof(int32_t) * (size_t)s_pad);
+    const int64_t walkers = (int64_t)a.n_runs * a.cap;
+    const unsigned blocks = (unsigned)((walkers + WAVE_WALKERS_PER_BLOCK - 1) / WAVE_WALKERS_PER_BLOCK);
+    hipLaunchKernelGGL(ssa_wave_kernel, dim3(blocks), dim3(64 * WAVE_WALKERS_PER_BLOCK), shmem, st, a,
+                       xs, iter, s_pad);
+    return hipGetLastError();
+}

@@ -56,6 +56,7 @@ size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 struct we_network {
     int32_t S = 0, R = 0;
     int32_t max_order = 0;
+    int32_t max_chg = 0;
     std::vector<RxnDesc> desc;
     std::vector<int32_t> chg_ptr, chg, dep_ptr;
     std::vector<uint16_t> dep;
@@ -190,6 +191,7 @@ extern "C" we_status we_create_network(int32_t S, int32_t R, const int32_t *reac
             net->chg.push_back(pack_change(s, dl));
         }
         net->max_order = std::max(net->max_order, order);
+        net->max_chg = std::max(net->max_chg, c1 - c0);
         net->desc[j] = d;
     }
     // dependency lists: reactions whose propensity reaction j changes
@@ -333,7 +335,7 @@ extern "C" we_status we_init(const we_network *net, const we_grid *g, const we_p
         kernel = lane_kernel_fits(S, net->R) && net->R <= 32 ? WE_KERNEL_LANE : WE_KERNEL_WAVE;
     if (kernel == WE_KERNEL_LANE && !lane_kernel_fits(S, net->R))
         return fail(WE_EINVAL, "network too large for the lane-per-walker kernel");
-    if (kernel == WE_KERNEL_WAVE && !wave_kernel_fits(S, net->R))
+    if (kernel == WE_KERNEL_WAVE && (!wave_kernel_fits(S, net->R) || net->max_chg > 64))
         return fail(WE_EINVAL, "network too large for the wave-per-walker kernel");
 
     Layout L = make_layout(S, NB, n_runs, cap, max_iters, nh);
