@@ -115,6 +115,10 @@ typedef struct {
     const int32_t *x_rec;      /* [n_species] recycling state A (NULL: x0)          */
     int32_t hist_species;      /* species whose P(x, t) is accumulated every        */
     int32_t hist_lo, hist_hi;  /*   iteration over [lo, hi] (hi < lo: none)         */
+    int32_t n_joint;           /* 0..5 species in a joint histogram accumulated     */
+    const int32_t *joint_species; /* every iteration over joint_bins^n_joint cells, */
+    int32_t joint_bins;        /*   cell of species d = min(x / joint_width,        */
+    int32_t joint_width;       /*   joint_bins - 1), first species fastest          */
 } we_params;
 
 /* Device bytes a sim needs (walker buffers, series, scratch). */
@@ -143,6 +147,19 @@ WE_API we_status we_set_ensemble(we_sim *s, int32_t run, int32_t n, const int32_
  * Asynchronous.  Errors: WE_ECAPACITY past max_iters, WE_EDEVICE. */
 WE_API we_status we_step_intervals(we_sim *s, int32_t n);
 
+/* Record n iterations (n even, > 0) of the sim as one HIP graph, captured
+ * on a private stream; nothing is executed by the capture.  Every kernel
+ * reads the iteration number from device memory, so the graph can be
+ * replayed; n even brings the double-buffered ensemble back to the buffer it
+ * started from.  Replaces any earlier graph.  Errors: WE_EINVAL (n odd or
+ * <= 0), WE_EDEVICE. */
+WE_API we_status we_graph_capture(we_sim *s, int32_t n);
+
+/* Launch the captured graph `times` times on the sim's stream (n*times
+ * iterations, asynchronous).  Errors: WE_ESTATE (nothing captured),
+ * WE_ECAPACITY past max_iters. */
+WE_API we_status we_graph_replay(we_sim *s, int32_t times);
+
 /* Wait for the sim's stream; return any latched device error. */
 WE_API we_status we_synchronize(we_sim *s);
 
@@ -162,6 +179,10 @@ WE_API we_status we_histogram(we_sim *s, int32_t run, int32_t species, int32_t l
  * k = hist_lo..hist_hi, per run (out: n_runs*(hi-lo+1)), and the number of
  * iterations summed.  Synchronous. */
 WE_API we_status we_histogram_accum(we_sim *s, double *out, int32_t *n_iters);
+
+/* The joint histogram summed over recorded iterations, per run
+ * (out: n_runs * joint_bins^n_joint doubles).  Synchronous. */
+WE_API we_status we_joint_histogram(we_sim *s, double *out);
 
 /* Weight recycled into B in iterations [first, first+count) of run `run`
  * (out: count entries).  Synchronous. */

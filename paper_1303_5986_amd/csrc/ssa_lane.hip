@@ -20,8 +20,7 @@
 #include "we_common.h"
 
 template <int SMAX, int RMAX>
-__global__ __launch_bounds__(256) void ssa_lane_kernel(SimArgs a, int32_t *__restrict__ xs,
-                                                       uint32_t iter) {
+__global__ __launch_bounds__(256) void ssa_lane_kernel(SimArgs a, int32_t *__restrict__ xs) {
     const int32_t gid = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
     const int32_t run = gid / a.cap;
     const int32_t k = gid - run * a.cap;
@@ -35,6 +34,7 @@ __global__ __launch_bounds__(256) void ssa_lane_kernel(SimArgs a, int32_t *__res
 #pragma unroll
     for (int s = 0; s < SMAX; ++s) x[s] = (s < S) ? xw[s] : 0;
 
+    const uint32_t iter = *a.iter_dev;
     const uint64_t seed = a.seeds[run];
     const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
     const double tau = a.tau;
@@ -99,20 +99,20 @@ __global__ __launch_bounds__(256) void ssa_lane_kernel(SimArgs a, int32_t *__res
 }
 
 // Launch helper: picks the smallest register footprint that holds the network.
-hipError_t launch_ssa_lane(const SimArgs &a, int32_t *xs, uint32_t iter, hipStream_t st) {
+hipError_t launch_ssa_lane(const SimArgs &a, int32_t *xs, hipStream_t st) {
     const int64_t total = (int64_t)a.n_runs * a.cap;
     const dim3 block(256);
     const dim3 grid((unsigned)((total + 255) / 256));
     if (a.S <= 1 && a.R <= 4)
-        hipLaunchKernelGGL((ssa_lane_kernel<1, 4>), grid, block, 0, st, a, xs, iter);
+        hipLaunchKernelGGL((ssa_lane_kernel<1, 4>), grid, block, 0, st, a, xs);
     else if (a.S <= 2 && a.R <= 8)
-        hipLaunchKernelGGL((ssa_lane_kernel<2, 8>), grid, block, 0, st, a, xs, iter);
+        hipLaunchKernelGGL((ssa_lane_kernel<2, 8>), grid, block, 0, st, a, xs);
     else if (a.S <= 8 && a.R <= 16)
-        hipLaunchKernelGGL((ssa_lane_kernel<8, 16>), grid, block, 0, st, a, xs, iter);
+        hipLaunchKernelGGL((ssa_lane_kernel<8, 16>), grid, block, 0, st, a, xs);
     else if (a.S <= 16 && a.R <= 32)
-        hipLaunchKernelGGL((ssa_lane_kernel<16, 32>), grid, block, 0, st, a, xs, iter);
+        hipLaunchKernelGGL((ssa_lane_kernel<16, 32>), grid, block, 0, st, a, xs);
     else if (a.S <= 32 && a.R <= 64)
-        hipLaunchKernelGGL((ssa_lane_kernel<32, 64>), grid, block, 0, st, a, xs, iter);
+        hipLaunchKernelGGL((ssa_lane_kernel<32, 64>), grid, block, 0, st, a, xs);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();

@@ -86,7 +86,7 @@ __device__ __forceinline__ void add_chunk_deltas(double *lchunk, int rr, double 
 }  // namespace
 
 __global__ __launch_bounds__(256) void ssa_wave_kernel(SimArgs a, int32_t *__restrict__ xs,
-                                                       uint32_t iter, int32_t s_pad) {
+                                                       int32_t s_pad) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
@@ -114,6 +114,7 @@ __global__ __launch_bounds__(256) void ssa_wave_kernel(SimArgs a, int32_t *__res
     }
     lchunk[lane] = csum;
 
+    const uint32_t iter = *a.iter_dev;
     const uint64_t seed = a.seeds[run];
     const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
     const double tau = a.tau;
@@ -218,13 +219,13 @@ __global__ __launch_bounds__(256) void ssa_wave_kernel(SimArgs a, int32_t *__res
 
 bool wave_kernel_fits(int32_t S, int32_t R) { return R <= 4096 && S <= 8192; }
 
-hipError_t launch_ssa_wave(const SimArgs &a, int32_t *xs, uint32_t iter, hipStream_t st) {
+hipError_t launch_ssa_wave(const SimArgs &a, int32_t *xs, hipStream_t st) {
     if (!wave_kernel_fits(a.S, a.R)) return hipErrorInvalidValue;
     const int32_t s_pad = (a.S + 3) & ~3;
     const size_t shmem = WAVE_WALKERS_PER_BLOCK * (64 * sizeof(double) + sizeof(int32_t) * (size_t)s_pad);
     const int64_t walkers = (int64_t)a.n_runs * a.cap;
     const unsigned blocks = (unsigned)((walkers + WAVE_WALKERS_PER_BLOCK - 1) / WAVE_WALKERS_PER_BLOCK);
     hipLaunchKernelGGL(ssa_wave_kernel, dim3(blocks), dim3(64 * WAVE_WALKERS_PER_BLOCK), shmem, st, a,
-                       xs, iter, s_pad);
+                       xs, s_pad);
     return hipGetLastError();
 }

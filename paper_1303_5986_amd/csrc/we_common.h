@@ -76,7 +76,11 @@ struct SimArgs {
     // observables
     double *hist;                        // [n_runs*nh]
     int32_t hist_species, hist_lo, nh;
+    double *jhist;                       // [n_runs * jcells]
+    int32_t n_joint, joint_bins, joint_width, jcells;
+    int32_t joint_species[5];
     int32_t *err;
+    uint32_t *iter_dev;                  // current WE iteration (advanced on the device)
 };
 
 // ---------------------------------------------------------------- Philox

@@ -1,13 +1,17 @@
 // we_resample.hip -- the WE bookkeeping between two propagation steps:
-// recycling, binning, per-bin split/merge and the observables (gfx950).
+// recycling, binning, per-bin split/merge, the state gather and the
+// observables (gfx950).  Per iteration, after the SSA kernel:
 //
-// One workgroup per run (runs are independent, Sec. II.B).  Per iteration:
-//   A. recycling (Sec. II.B.2): a walker whose state is in
-//      B = { x : sum_s coef_s x_s >= thr } adds its weight to the run's flux
-//      and restarts from the state A, keeping its weight; checked once, at
-//      the end of the interval;
-//   B. bin of every walker on the progress coordinate;
-//   C. per-bin split/merge (Sec. II.B):
+//   recycle_bin (one lane per walker, whole grid)
+//      recycling (Sec. II.B.2): a walker whose state lies in
+//      B = { x : sum_s coef_s x_s >= thr } is flagged and restarts from the
+//      state A, keeping its weight; checked once, at the end of the interval
+//      (the paper checks walkers only every tau);
+//      bin of every walker on the progress coordinate (or, with learned
+//      bins, the bin is written afterwards by the committor kernel);
+//   resample (one workgroup per run)
+//      the run's recycled weight (summed in slot order) and reactions fired;
+//      per-bin split/merge (Sec. II.B):
 //        n == M: unchanged;
 //        n <  M: replicate to M copies; one more copy is given, repeatedly,
 //                to the parent with the largest per-copy weight w/c (ties:
@@ -16,13 +20,18 @@
 //        n >  M: merge the two lowest-weight walkers (ties: lowest slot): the
 //                first survives with probability w_i/(w_i+w_j), else the
 //                second, and the survivor carries w_i + w_j; repeat;
-//      output layout: bins ascending, parents by ascending slot, copies of a
-//      parent consecutive -- the "canonical" layout, which also keeps
-//      walkers of similar state in neighbouring lanes for the next SSA step;
-//   D. copy each new walker's state row from its parent.
-// All weight arithmetic is sequential per bin, so the resulting weights are
-// reproducible bit for bit.
+//      output order: bins ascending, parents by ascending slot, copies of a
+//      parent consecutive -- neighbouring lanes then hold walkers of similar
+//      state for the next SSA step;
+//      per-walker bin, weight and list arrays are staged in LDS;
+//   gather_rows (one lane per count, whole grid): new state rows copied
+//      from their parents;
+//   observe: P(x_s = k, t) accumulated per run with FP64 atomics.
+// All weight arithmetic is sequential per bin, so weights are reproducible
+// bit for bit.
 #include "we_common.h"
+
+#define RESAMPLE_LDS_CAP 8192
 
 __device__ __forceinline__ double coord_of(const double *__restrict__ coef,
                                            const int32_t *__restrict__ xr, int32_t S) {
@@ -31,67 +40,90 @@ __device__ __forceinline__ double coord_of(const double *__restrict__ coef,
     return q;
 }
 
-__global__ __launch_bounds__(256) void we_resample_kernel(SimArgs a, int32_t *__restrict__ x_cur,
-                                                          const double *__restrict__ w_cur,
-                                                          int32_t *__restrict__ x_nxt,
-                                                          double *__restrict__ w_nxt,
-                                                          uint32_t iter, int32_t rec_slot) {
-    extern __shared__ int32_t lds[];
+__global__ __launch_bounds__(256) void we_recycle_bin_kernel(SimArgs a, int32_t *__restrict__ x_cur,
+                                                             int32_t grid_bins) {
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int32_t run = (int32_t)(gid / a.cap);
+    const int32_t k = (int32_t)(gid - (int64_t)run * a.cap);
+    if (run >= a.n_runs) return;
+    if (k >= a.n_walk[run]) return;
+    const int32_t S = a.S;
+    const size_t idx = (size_t)run * a.cap + k;
+    int32_t *row = x_cur + idx * S;
+    int32_t rec = 0;
+    if (a.recycle && coord_of(a.tgt_coef, row, S) >= a.tgt_thr) {
+        rec = 1;
+        for (int32_t s = 0; s < S; ++s) row[s] = a.x_rec[s];
+    }
+    a.s_rec[idx] = rec;
+    if (grid_bins) a.s_bin[idx] = bin_index(a.edges, a.n_bins, coord_of(a.bin_coef, row, S));
+}
+
+// Per-walker working arrays of one run: LDS when the run fits, else global.
+struct RunWork {
+    uint16_t *bin, *list, *cnt;
+    double *w;
+};
+
+__global__ __launch_bounds__(256) void we_resample_kernel(SimArgs a, const double *__restrict__ w_cur,
+                                                          double *__restrict__ w_nxt, int32_t use_lds) {
+    extern __shared__ __align__(16) unsigned char lds[];
     const int32_t run = blockIdx.x;
     const int32_t tid = threadIdx.x, nthr = blockDim.x;
-    const int32_t S = a.S, NB = a.n_bins, M = a.m_targ, cap = a.cap;
-    int32_t *cnt = lds;                // [NB]
-    int32_t *start = cnt + NB;         // [NB+1]
-    int32_t *ostart = start + NB + 1;  // [NB+1]
+    const int32_t NB = a.n_bins, M = a.m_targ, cap = a.cap;
     __shared__ int64_t ev_part[256];
+    int32_t *cnt = reinterpret_cast<int32_t *>(lds);   // [NB]
+    int32_t *start = cnt + NB;                          // [NB+1]
+    int32_t *ostart = start + NB + 1;                   // [NB+1]
+    unsigned char *tail = lds + sizeof(int32_t) * (3 * (size_t)NB + 2);
+    tail += (16 - ((uintptr_t)tail & 15)) & 15;
 
+    const uint32_t iter = *a.iter_dev;
+    const int32_t rec_slot = (int32_t)iter;
     const int32_t n = a.n_walk[run];
     const size_t base = (size_t)run * cap;
-    int32_t *xr = x_cur + base * S;
     const double *wr = w_cur + base;
-    int32_t *sbin = a.s_bin + base;
-    int32_t *srec = a.s_rec + base;
-    int32_t *slist = a.s_list + base;
-    double *sw = a.s_w + base;
-    int32_t *scnt = a.s_cnt + base;
+    const int32_t *sbin = a.s_bin + base;
+    const int32_t *srec = a.s_rec + base;
+    RunWork wk;
+    if (use_lds) {
+        wk.w = reinterpret_cast<double *>(tail);
+        wk.bin = reinterpret_cast<uint16_t *>(wk.w + cap);
+        wk.list = wk.bin + cap;
+        wk.cnt = wk.list + cap;
+    } else {
+        wk.w = a.s_w + base;
+        wk.bin = reinterpret_cast<uint16_t *>(a.s_list + base);
+        wk.list = reinterpret_cast<uint16_t *>(a.s_cnt + base);
+        wk.cnt = wk.list + cap;
+    }
 
-    // A + B: recycling and bin of every walker
     int64_t my_ev = 0;
     for (int32_t k = tid; k < n; k += nthr) {
-        int32_t *row = xr + (size_t)k * S;
-        int32_t rec = 0;
-        if (a.recycle) {
-            if (coord_of(a.tgt_coef, row, S) >= a.tgt_thr) {
-                rec = 1;
-                for (int32_t s = 0; s < S; ++s) row[s] = a.x_rec[s];
-            }
-        }
-        srec[k] = rec;
-        sbin[k] = bin_index(a.edges, NB, coord_of(a.bin_coef, row, S));
+        wk.bin[k] = (uint16_t)sbin[k];
         my_ev += a.ev_walker[base + k];
     }
     ev_part[tid] = my_ev;
-    for (int32_t b = tid; b < NB; b += nthr) cnt[b] = 0;
     __syncthreads();
 
-    // flux (sequential in slot order) and events (integer, any order)
+    // recycled weight (slot order) and reactions fired (integer, any order)
     if (tid == 0) {
         double f = 0.0;
         for (int32_t k = 0; k < n; ++k)
             if (srec[k]) f = f + wr[k];
         int64_t ev = 0;
         for (int32_t t = 0; t < nthr; ++t) ev += ev_part[t];
-        if (rec_slot >= 0) {
+        if (rec_slot < a.max_iters) {
             a.flux[(size_t)run * a.max_iters + rec_slot] = f;
             a.ev_iter[(size_t)run * a.max_iters + rec_slot] = ev;
             a.seg_iter[(size_t)run * a.max_iters + rec_slot] = n;
         }
     }
 
-    // C1: members of each bin, in slot order
+    // members of each bin, in slot order
     for (int32_t b = tid; b < NB; b += nthr) {
         int32_t c = 0;
-        for (int32_t k = 0; k < n; ++k) c += (sbin[k] == b);
+        for (int32_t k = 0; k < n; ++k) c += (wk.bin[k] == b);
         cnt[b] = c;
     }
     __syncthreads();
@@ -105,21 +137,21 @@ __global__ __launch_bounds__(256) void we_resample_kernel(SimArgs a, int32_t *__
         }
         start[NB] = acc;
         ostart[NB] = oacc;
-        if (oacc > cap) atomicOr(a.err, WE_DERR_CAPACITY);
     }
     __syncthreads();
     for (int32_t b = tid; b < NB; b += nthr) {
+        if (cnt[b] == 0) continue;
         int32_t p = start[b];
         for (int32_t k = 0; k < n; ++k)
-            if (sbin[k] == b) {
-                slist[p] = k;
-                sw[p] = wr[k];
+            if (wk.bin[k] == b) {
+                wk.list[p] = (uint16_t)k;
+                wk.w[p] = wr[k];
                 ++p;
             }
     }
     __syncthreads();
 
-    // C2: split / merge, one thread per bin
+    // split / merge, one thread per bin
     const uint64_t seed = a.seeds[run];
     const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
     int32_t *orig = a.origin + base;
@@ -131,77 +163,83 @@ __global__ __launch_bounds__(256) void we_resample_kernel(SimArgs a, int32_t *__
         if (nb == 0) continue;
         if (nb == M) {
             for (int32_t q = 0; q < nb; ++q) {
-                orig[o] = slist[p0 + q];
-                wn[o] = sw[p0 + q];
+                orig[o] = wk.list[p0 + q];
+                wn[o] = wk.w[p0 + q];
                 obin[o] = b;
                 ++o;
             }
         } else if (nb < M) {
-            for (int32_t q = 0; q < nb; ++q) scnt[p0 + q] = 1;
+            for (int32_t q = 0; q < nb; ++q) wk.cnt[p0 + q] = 1;
             for (int32_t extra = nb; extra < M; ++extra) {
                 int32_t best = 0;
-                double best_share = sw[p0] / (double)scnt[p0];
+                double best_share = wk.w[p0] / (double)wk.cnt[p0];
                 for (int32_t q = 1; q < nb; ++q) {
-                    const double share = sw[p0 + q] / (double)scnt[p0 + q];
+                    const double share = wk.w[p0 + q] / (double)wk.cnt[p0 + q];
                     if (share > best_share) { best = q; best_share = share; }
                 }
-                scnt[p0 + best] += 1;
+                wk.cnt[p0 + best] += 1;
             }
             for (int32_t q = 0; q < nb; ++q) {
-                const int32_t c = scnt[p0 + q];
-                const double share = sw[p0 + q] / (double)c;
+                const int32_t c = wk.cnt[p0 + q];
+                const double share = wk.w[p0 + q] / (double)c;
                 for (int32_t r = 0; r < c; ++r) {
-                    orig[o] = slist[p0 + q];
+                    orig[o] = wk.list[p0 + q];
                     wn[o] = share;
                     obin[o] = b;
                     ++o;
                 }
             }
         } else {
-            for (int32_t q = 0; q < nb; ++q) scnt[p0 + q] = 1;   // alive flags
+            for (int32_t q = 0; q < nb; ++q) wk.cnt[p0 + q] = 1;   // alive flags
             int32_t alive = nb;
             uint32_t m = 0;
             while (alive > M) {
                 int32_t i = -1, j = -1;
+                double wi_min = 0.0, wj_min = 0.0;
                 for (int32_t q = 0; q < nb; ++q) {
-                    if (!scnt[p0 + q]) continue;
-                    const double v = sw[p0 + q];
-                    if (i < 0 || v < sw[p0 + i]) { j = i; i = q; }
-                    else if (j < 0 || v < sw[p0 + j]) { j = q; }
+                    if (!wk.cnt[p0 + q]) continue;
+                    const double v = wk.w[p0 + q];
+                    if (i < 0 || v < wi_min) { j = i; wj_min = wi_min; i = q; wi_min = v; }
+                    else if (j < 0 || v < wj_min) { j = q; wj_min = v; }
                 }
                 const U4 r = philox4x32_10(m, (uint32_t)b, iter, 1u, k0, k1);
                 m += 1;
                 const double u = uniform53(r.x, r.y);
-                const double wi = sw[p0 + i], wj = sw[p0 + j];
-                const double sum = wi + wj;
-                const double p_i = wi / sum;
+                const double sum = wi_min + wj_min;
+                const double p_i = wi_min / sum;
                 const int32_t keep = (u < p_i) ? i : j;
                 const int32_t drop = (keep == i) ? j : i;
-                sw[p0 + keep] = sum;
-                scnt[p0 + drop] = 0;
+                wk.w[p0 + keep] = sum;
+                wk.cnt[p0 + drop] = 0;
                 alive -= 1;
             }
             for (int32_t q = 0; q < nb; ++q) {
-                if (!scnt[p0 + q]) continue;
-                orig[o] = slist[p0 + q];
-                wn[o] = sw[p0 + q];
+                if (!wk.cnt[p0 + q]) continue;
+                orig[o] = wk.list[p0 + q];
+                wn[o] = wk.w[p0 + q];
                 obin[o] = b;
                 ++o;
             }
         }
     }
     __syncthreads();
+    if (tid == 0) a.n_walk[run] = ostart[NB];
+}
 
-    // D: state rows of the new ensemble
-    const int32_t n_out = ostart[NB];
-    int32_t *xn = x_nxt + base * S;
-    const int64_t total = (int64_t)n_out * S;
-    for (int64_t idx = tid; idx < total; idx += nthr) {
-        const int32_t dst = (int32_t)(idx / S);
-        const int32_t s = (int32_t)(idx - (int64_t)dst * S);
-        xn[idx] = xr[(size_t)orig[dst] * S + s];
-    }
-    if (tid == 0) a.n_walk[run] = n_out;
+// New state rows from their parents: one lane per copy number.
+__global__ __launch_bounds__(256) void we_gather_rows_kernel(SimArgs a, const int32_t *__restrict__ x_cur,
+                                                             int32_t *__restrict__ x_nxt) {
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t per_run = (int64_t)a.cap * a.S;
+    const int32_t run = (int32_t)(gid / per_run);
+    if (run >= a.n_runs) return;
+    const int64_t rem = gid - (int64_t)run * per_run;
+    const int32_t dst = (int32_t)(rem / a.S);
+    const int32_t s = (int32_t)(rem - (int64_t)dst * a.S);
+    if (dst >= a.n_walk[run]) return;
+    const size_t base = (size_t)run * a.cap;
+    const int32_t src = a.origin[base + dst];
+    x_nxt[(base + dst) * a.S + s] = x_cur[(base + src) * a.S + s];
 }
 
 // P(x_s = k, t) accumulated over iterations: one lane per walker, FP64 atomics.
@@ -213,15 +251,46 @@ __global__ __launch_bounds__(256) void we_observe_kernel(SimArgs a, const int32_
     if (run >= a.n_runs) return;
     if (k >= a.n_walk[run]) return;
     const size_t idx = (size_t)run * a.cap + k;
-    const int32_t v = xs[idx * a.S + a.hist_species] - a.hist_lo;
-    if (v >= 0 && v < a.nh) atomicAdd(&a.hist[(size_t)run * a.nh + v], ws[idx]);
+    const double wv = ws[idx];
+    if (a.nh > 0) {
+        const int32_t v = xs[idx * a.S + a.hist_species] - a.hist_lo;
+        if (v >= 0 && v < a.nh) atomicAdd(&a.hist[(size_t)run * a.nh + v], wv);
+    }
+    if (a.n_joint > 0) {
+        int32_t cell = 0, mul = 1;
+        for (int d = 0; d < a.n_joint; ++d) {
+            const int32_t c = min(xs[idx * a.S + a.joint_species[d]] / a.joint_width, a.joint_bins - 1);
+            cell += c * mul;
+            mul *= a.joint_bins;
+        }
+        atomicAdd(&a.jhist[(size_t)run * a.jcells + cell], wv);
+    }
+}
+
+hipError_t launch_recycle_bin(const SimArgs &a, int32_t *x_cur, bool grid_bins, hipStream_t st) {
+    const int64_t total = (int64_t)a.n_runs * a.cap;
+    hipLaunchKernelGGL(we_recycle_bin_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st,
+                       a, x_cur, grid_bins ? 1 : 0);
+    return hipGetLastError();
+}
+
+size_t resample_lds_bytes(const SimArgs &a, bool use_lds) {
+    size_t b = sizeof(int32_t) * (3 * (size_t)a.n_bins + 2) + 16;
+    if (use_lds) b += (size_t)a.cap * (sizeof(double) + 3 * sizeof(uint16_t));
+    return b;
 }
 
 hipError_t launch_resample(const SimArgs &a, int32_t *x_cur, const double *w_cur, int32_t *x_nxt,
-                           double *w_nxt, uint32_t iter, int32_t rec_slot, hipStream_t st) {
-    const size_t shmem = sizeof(int32_t) * (3 * (size_t)a.n_bins + 2);
-    hipLaunchKernelGGL(we_resample_kernel, dim3(a.n_runs), dim3(256), shmem, st, a, x_cur, w_cur,
-                       x_nxt, w_nxt, iter, rec_slot);
+                           double *w_nxt, hipStream_t st) {
+    const bool use_lds = a.cap <= RESAMPLE_LDS_CAP && resample_lds_bytes(a, true) <= 150 * 1024;
+    const size_t shmem = resample_lds_bytes(a, use_lds);
+    hipLaunchKernelGGL(we_resample_kernel, dim3(a.n_runs), dim3(256), shmem, st, a, w_cur, w_nxt,
+                       use_lds ? 1 : 0);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t total = (int64_t)a.n_runs * a.cap * a.S;
+    hipLaunchKernelGGL(we_gather_rows_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st,
+                       a, x_cur, x_nxt);
     return hipGetLastError();
 }
 
@@ -229,5 +298,15 @@ hipError_t launch_observe(const SimArgs &a, const int32_t *xs, const double *ws,
     const int64_t total = (int64_t)a.n_runs * a.cap;
     hipLaunchKernelGGL(we_observe_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st,
                        a, xs, ws);
+    return hipGetLastError();
+}
+
+// End of an iteration: advance the device-side iteration counter.
+__global__ void we_advance_kernel(SimArgs a) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *a.iter_dev += 1u;
+}
+
+hipError_t launch_advance(const SimArgs &a, hipStream_t st) {
+    hipLaunchKernelGGL(we_advance_kernel, dim3(1), dim3(64), 0, st, a);
     return hipGetLastError();
 }

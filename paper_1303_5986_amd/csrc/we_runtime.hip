@@ -22,12 +22,14 @@
 #include "../../include/we.h"
 #include "we_common.h"
 
-hipError_t launch_ssa_lane(const SimArgs &a, int32_t *xs, uint32_t iter, hipStream_t st);
+hipError_t launch_ssa_lane(const SimArgs &a, int32_t *xs, hipStream_t st);
 bool lane_kernel_fits(int32_t S, int32_t R);
-hipError_t launch_ssa_wave(const SimArgs &a, int32_t *xs, uint32_t iter, hipStream_t st);
+hipError_t launch_ssa_wave(const SimArgs &a, int32_t *xs, hipStream_t st);
 bool wave_kernel_fits(int32_t S, int32_t R);
+hipError_t launch_recycle_bin(const SimArgs &a, int32_t *x_cur, bool grid_bins, hipStream_t st);
 hipError_t launch_resample(const SimArgs &a, int32_t *x_cur, const double *w_cur, int32_t *x_nxt,
-                           double *w_nxt, uint32_t iter, int32_t rec_slot, hipStream_t st);
+                           double *w_nxt, hipStream_t st);
+hipError_t launch_advance(const SimArgs &a, hipStream_t st);
 hipError_t launch_observe(const SimArgs &a, const int32_t *xs, const double *ws, hipStream_t st);
 
 namespace {
@@ -86,6 +88,10 @@ struct we_sim {
     size_t ev_used = 0;
     double prof_ms[3] = {0.0, 0.0, 0.0};
     int64_t prof_iters = 0;
+    // captured iterations
+    hipGraphExec_t graph_exec = nullptr;
+    hipStream_t capture_stream = nullptr;
+    int32_t graph_iters = 0;
 };
 
 namespace {
@@ -254,10 +260,10 @@ struct Layout {
 // Order of the pieces in the workspace; make_layout and we_init agree on it.
 enum Piece { P_X0, P_X1, P_W0, P_W1, P_BIN, P_ORIG, P_N, P_EVW, P_FLUX, P_EVI, P_SBIN, P_SREC,
              P_SLIST, P_SW, P_SCNT, P_HIST, P_SEEDS, P_BCOEF, P_EDGES, P_TCOEF, P_XREC, P_ERR,
-             P_SEG, P_COUNT };
+             P_SEG, P_ITER, P_JHIST, P_COUNT };
 
 Layout make_layout(int32_t S, int32_t NB, int32_t n_runs, int32_t cap, int32_t max_iters,
-                   int32_t nh) {
+                   int32_t nh, int64_t jcells) {
     Layout L;
     const size_t W = (size_t)n_runs * cap;
     L.add(4 * W * S); L.add(4 * W * S);
@@ -276,6 +282,8 @@ Layout make_layout(int32_t S, int32_t NB, int32_t n_runs, int32_t cap, int32_t m
     L.add(4 * (size_t)S);
     L.add(4);
     L.add(4 * (size_t)n_runs * max_iters);
+    L.add(4);
+    L.add(8 * (size_t)n_runs * (size_t)jcells);
     return L;
 }
 
@@ -289,8 +297,8 @@ we_status check_params(const we_network *net, const we_grid *g, const we_params 
         return fail(WE_EINVAL, "m_targ, n_runs must be >= 1");
     if (!p->seeds || !p->x0) return fail(WE_EINVAL, "seeds and x0 are required");
     const int64_t cap = (int64_t)p->m_targ * g->n_bins;
-    if (cap > (1 << 24) || cap * p->n_runs > (int64_t)1 << 31)
-        return fail(WE_EINVAL, "too many walker slots");
+    if (cap > 65535 || cap * p->n_runs > (int64_t)1 << 30)
+        return fail(WE_EINVAL, "too many walker slots (m_targ * n_bins must be <= 65535)");
     for (int32_t s = 0; s < net->S; ++s)
         if (p->x0[s] < 0 || p->x0[s] > WE_COUNT_MAX) return fail(WE_EINVAL, "x0 out of range");
     if (p->recycle) {
@@ -304,7 +312,25 @@ we_status check_params(const we_network *net, const we_grid *g, const we_params 
         return fail(WE_EINVAL, "hist_species out of range");
     if (p->kernel < WE_KERNEL_AUTO || p->kernel > WE_KERNEL_WAVE)
         return fail(WE_EINVAL, "unknown kernel");
+    if (p->n_joint < 0 || p->n_joint > 5) return fail(WE_EINVAL, "n_joint must be in [0, 5]");
+    if (p->n_joint > 0) {
+        if (!p->joint_species || p->joint_bins < 1 || p->joint_width < 1)
+            return fail(WE_EINVAL, "joint histogram needs species, bins >= 1, width >= 1");
+        int64_t cells = 1;
+        for (int32_t d = 0; d < p->n_joint; ++d) {
+            if (p->joint_species[d] < 0 || p->joint_species[d] >= net->S)
+                return fail(WE_EINVAL, "joint species out of range");
+            cells *= p->joint_bins;
+        }
+        if (cells > (1 << 24)) return fail(WE_EINVAL, "joint histogram too large");
+    }
     return WE_OK;
+}
+
+int64_t joint_cells(const we_params *p) {
+    int64_t c = p->n_joint > 0 ? 1 : 0;
+    for (int32_t d = 0; d < p->n_joint; ++d) c *= p->joint_bins;
+    return c;
 }
 
 }  // namespace
@@ -316,7 +342,7 @@ extern "C" we_status we_workspace_size(const we_network *net, const we_grid *g, 
     if (!bytes) return fail(WE_EINVAL, "bytes is NULL");
     const int32_t nh = p->hist_hi >= p->hist_lo ? p->hist_hi - p->hist_lo + 1 : 0;
     *bytes = make_layout(net->S, g->n_bins, p->n_runs, p->m_targ * g->n_bins,
-                         std::max(p->max_iters, 1), nh).total;
+                         std::max(p->max_iters, 1), nh, joint_cells(p)).total;
     return WE_OK;
 }
 
@@ -338,7 +364,8 @@ extern "C" we_status we_init(const we_network *net, const we_grid *g, const we_p
     if (kernel == WE_KERNEL_WAVE && (!wave_kernel_fits(S, net->R) || net->max_chg > 64))
         return fail(WE_EINVAL, "network too large for the wave-per-walker kernel");
 
-    Layout L = make_layout(S, NB, n_runs, cap, max_iters, nh);
+    const int64_t jcells = joint_cells(p);
+    Layout L = make_layout(S, NB, n_runs, cap, max_iters, nh, jcells);
     we_sim *s = new we_sim();
     s->net = net;
     s->stream = (hipStream_t)hip_stream;
@@ -387,6 +414,13 @@ extern "C" we_status we_init(const we_network *net, const we_grid *g, const we_p
     a.hist_lo = p->hist_lo;
     a.nh = nh;
     a.err = (int32_t *)at(P_ERR);
+    a.iter_dev = (uint32_t *)at(P_ITER);
+    a.jhist = (double *)at(P_JHIST);
+    a.n_joint = p->n_joint;
+    a.joint_bins = p->n_joint > 0 ? p->joint_bins : 1;
+    a.joint_width = p->n_joint > 0 ? p->joint_width : 1;
+    a.jcells = (int32_t)jcells;
+    for (int32_t d = 0; d < 5; ++d) a.joint_species[d] = d < p->n_joint ? p->joint_species[d] : 0;
 
     // initial ensemble: m_targ walkers at x0, weight 1/m_targ
     const size_t W = (size_t)n_runs * cap;
@@ -456,35 +490,87 @@ we_status read_err(we_sim *s) {
 }
 }  // namespace
 
+namespace {
+// Launch one WE iteration on stream st.  Buffers alternate between
+// iterations; the iteration number is read by the kernels from device memory.
+we_status launch_iteration(we_sim *s, hipStream_t st, bool profile) {
+    SimArgs &a = s->args;
+    const int32_t c = s->cur, nx = 1 - c;
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    if (profile) {
+        if (s->ev_used + 4 > 4096) HIP_TRY(drain_profile(s));
+        for (int k = 0; k < 4; ++k) HIP_TRY(next_event(s, &ev[k]));
+        HIP_TRY(hipEventRecord(ev[0], st));
+    }
+    hipError_t e = (s->kernel == WE_KERNEL_WAVE) ? launch_ssa_wave(a, s->x[c], st)
+                                                 : launch_ssa_lane(a, s->x[c], st);
+    if (e != hipSuccess) return hip_fail(e, "SSA launch");
+    if (profile) HIP_TRY(hipEventRecord(ev[1], st));
+    e = launch_recycle_bin(a, s->x[c], true, st);
+    if (e != hipSuccess) return hip_fail(e, "recycle/bin launch");
+    e = launch_resample(a, s->x[c], s->w[c], s->x[nx], s->w[nx], st);
+    if (e != hipSuccess) return hip_fail(e, "resample launch");
+    if (profile) HIP_TRY(hipEventRecord(ev[2], st));
+    if (a.nh > 0 || a.n_joint > 0) {
+        e = launch_observe(a, s->x[nx], s->w[nx], st);
+        if (e != hipSuccess) return hip_fail(e, "observe launch");
+    }
+    e = launch_advance(a, st);
+    if (e != hipSuccess) return hip_fail(e, "advance launch");
+    if (profile) HIP_TRY(hipEventRecord(ev[3], st));
+    s->cur = nx;
+    return WE_OK;
+}
+}  // namespace
+
 extern "C" we_status we_step_intervals(we_sim *s, int32_t n) {
     if (!s) return fail(WE_EINVAL, "NULL sim");
     if (n < 0) return fail(WE_EINVAL, "negative iteration count");
     if ((int64_t)s->iter + n > s->max_iters) return fail(WE_ECAPACITY, "max_iters exceeded");
-    SimArgs &a = s->args;
     for (int32_t i = 0; i < n; ++i) {
-        const uint32_t it = (uint32_t)s->iter;
-        const int32_t c = s->cur, nx = 1 - c;
-        hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
-        if (s->profiling) {
-            if (s->ev_used + 4 > 4096) HIP_TRY(drain_profile(s));
-            for (int k = 0; k < 4; ++k) HIP_TRY(next_event(s, &ev[k]));
-            HIP_TRY(hipEventRecord(ev[0], s->stream));
-        }
-        hipError_t e = (s->kernel == WE_KERNEL_WAVE) ? launch_ssa_wave(a, s->x[c], it, s->stream)
-                                                     : launch_ssa_lane(a, s->x[c], it, s->stream);
-        if (e != hipSuccess) return hip_fail(e, "SSA launch");
-        if (s->profiling) HIP_TRY(hipEventRecord(ev[1], s->stream));
-        e = launch_resample(a, s->x[c], s->w[c], s->x[nx], s->w[nx], it, (int32_t)it, s->stream);
-        if (e != hipSuccess) return hip_fail(e, "resample launch");
-        if (s->profiling) HIP_TRY(hipEventRecord(ev[2], s->stream));
-        if (a.nh > 0) {
-            e = launch_observe(a, s->x[nx], s->w[nx], s->stream);
-            if (e != hipSuccess) return hip_fail(e, "observe launch");
-            s->hist_iters += 1;
-        }
-        if (s->profiling) HIP_TRY(hipEventRecord(ev[3], s->stream));
-        s->cur = nx;
+        we_status st = launch_iteration(s, s->stream, s->profiling);
+        if (st != WE_OK) return st;
+        if (s->args.nh > 0) s->hist_iters += 1;
         s->iter += 1;
+    }
+    return WE_OK;
+}
+
+extern "C" we_status we_graph_capture(we_sim *s, int32_t n) {
+    if (!s) return fail(WE_EINVAL, "NULL sim");
+    if (n <= 0 || (n & 1)) return fail(WE_EINVAL, "capture an even, positive number of iterations");
+    if (s->graph_exec) {
+        (void)hipGraphExecDestroy(s->graph_exec);
+        s->graph_exec = nullptr;
+    }
+    if (!s->capture_stream) HIP_TRY(hipStreamCreateWithFlags(&s->capture_stream, hipStreamNonBlocking));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    const int32_t cur0 = s->cur;
+    HIP_TRY(hipStreamBeginCapture(s->capture_stream, hipStreamCaptureModeThreadLocal));
+    we_status st = WE_OK;
+    for (int32_t i = 0; i < n && st == WE_OK; ++i) st = launch_iteration(s, s->capture_stream, false);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(s->capture_stream, &g);
+    s->cur = cur0;   // n is even: a replay leaves the buffers where they were
+    if (st != WE_OK) { if (g) (void)hipGraphDestroy(g); return st; }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    e = hipGraphInstantiate(&s->graph_exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+    s->graph_iters = n;
+    return WE_OK;
+}
+
+extern "C" we_status we_graph_replay(we_sim *s, int32_t times) {
+    if (!s) return fail(WE_EINVAL, "NULL sim");
+    if (!s->graph_exec) return fail(WE_ESTATE, "no captured graph");
+    if (times < 0) return fail(WE_EINVAL, "negative replay count");
+    if ((int64_t)s->iter + (int64_t)times * s->graph_iters > s->max_iters)
+        return fail(WE_ECAPACITY, "max_iters exceeded");
+    for (int32_t r = 0; r < times; ++r) {
+        HIP_TRY(hipGraphLaunch(s->graph_exec, s->stream));
+        s->iter += s->graph_iters;
+        if (s->args.nh > 0) s->hist_iters += s->graph_iters;
     }
     return WE_OK;
 }
@@ -535,6 +621,15 @@ extern "C" we_status we_histogram_accum(we_sim *s, double *out, int32_t *n_iters
     if (st != WE_OK) return st;
     HIP_TRY(hipMemcpy(out, s->args.hist, 8 * (size_t)s->n_runs * s->args.nh, hipMemcpyDeviceToHost));
     if (n_iters) *n_iters = s->hist_iters;
+    return WE_OK;
+}
+
+extern "C" we_status we_joint_histogram(we_sim *s, double *out) {
+    if (!s || !out) return fail(WE_EINVAL, "NULL argument");
+    if (s->args.n_joint <= 0) return fail(WE_ESTATE, "no joint histogram was requested at init");
+    we_status st = read_err(s);
+    if (st != WE_OK) return st;
+    HIP_TRY(hipMemcpy(out, s->args.jhist, 8 * (size_t)s->n_runs * s->args.jcells, hipMemcpyDeviceToHost));
     return WE_OK;
 }
 
@@ -636,6 +731,8 @@ extern "C" void we_destroy(we_sim *s) {
     if (s->stream) (void)hipStreamSynchronize(s->stream);
     else (void)hipDeviceSynchronize();
     for (hipEvent_t e : s->ev_pool) (void)hipEventDestroy(e);
+    if (s->graph_exec) (void)hipGraphExecDestroy(s->graph_exec);
+    if (s->capture_stream) (void)hipStreamDestroy(s->capture_stream);
     if (s->owns_ws) (void)hipFree(s->ws);
     delete s;
 }

@@ -25,8 +25,8 @@ _STATUS = {WE_EINVAL: "EINVAL", WE_ENOMEM: "ENOMEM", WE_EDEVICE: "EDEVICE",
 
 EXPORTED = [
     "we_create_network", "we_destroy_network", "we_workspace_size", "we_init", "we_set_ensemble",
-    "we_step_intervals", "we_synchronize", "we_get_walkers", "we_histogram", "we_histogram_accum",
-    "we_flux", "we_mfpt", "we_counters", "we_events_series", "we_profile", "we_profile_read",
+    "we_step_intervals", "we_graph_capture", "we_graph_replay", "we_synchronize", "we_get_walkers", "we_histogram", "we_histogram_accum",
+    "we_joint_histogram", "we_flux", "we_mfpt", "we_counters", "we_events_series", "we_profile", "we_profile_read",
     "we_destroy", "we_last_error",
 ]
 
@@ -46,7 +46,8 @@ class _Params(C.Structure):
                 ("max_iters", C.c_int32), ("kernel", C.c_int32), ("seeds", C.c_void_p),
                 ("x0", C.c_void_p), ("recycle", C.c_int32), ("tgt_coef", C.c_void_p),
                 ("tgt_thr", C.c_double), ("x_rec", C.c_void_p), ("hist_species", C.c_int32),
-                ("hist_lo", C.c_int32), ("hist_hi", C.c_int32)]
+                ("hist_lo", C.c_int32), ("hist_hi", C.c_int32), ("n_joint", C.c_int32),
+                ("joint_species", C.c_void_p), ("joint_bins", C.c_int32), ("joint_width", C.c_int32)]
 
 
 _LIB = None
@@ -74,10 +75,13 @@ def load_library(path: str = LIB_PATH):
     L.we_init.argtypes = [vp, vp, vp, vp, vp, C.c_size_t, P(vp)]
     L.we_set_ensemble.argtypes = [vp, i32, i32, vp, vp]
     L.we_step_intervals.argtypes = [vp, i32]
+    L.we_graph_capture.argtypes = [vp, i32]
+    L.we_graph_replay.argtypes = [vp, i32]
     L.we_synchronize.argtypes = [vp]
     L.we_get_walkers.argtypes = [vp, i32, P(i32), vp, vp, vp, vp]
     L.we_histogram.argtypes = [vp, i32, i32, i32, i32, vp]
     L.we_histogram_accum.argtypes = [vp, vp, P(i32)]
+    L.we_joint_histogram.argtypes = [vp, vp]
     L.we_flux.argtypes = [vp, i32, i32, i32, vp]
     L.we_mfpt.argtypes = [vp, i32, P(f64), P(f64), P(f64)]
     L.we_counters.argtypes = [vp, P(i64), P(i64), P(i32)]
@@ -140,7 +144,9 @@ class Sim:
     def __init__(self, network: Network, bin_coef, edges, *, tau: float, m_targ: int,
                  seeds: Sequence[int], x0, max_iters: int, kernel: int = WE_KERNEL_AUTO,
                  recycle: bool = False, tgt_coef=None, tgt_thr: float = 0.0, x_rec=None,
-                 hist_species: int = 0, hist_lo: int = 0, hist_hi: int = -1, device=None):
+                 hist_species: int = 0, hist_lo: int = 0, hist_hi: int = -1,
+                 joint_species: Sequence[int] = (), joint_bins: int = 16, joint_width: int = 64,
+                 device=None):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("no HIP device: libwe.so runs on MI355X only")
@@ -154,6 +160,7 @@ class Sim:
             x0=np.ascontiguousarray(x0, np.int32),
             tgt=None if tgt_coef is None else np.ascontiguousarray(tgt_coef, np.float64),
             xrec=None if x_rec is None else np.ascontiguousarray(x_rec, np.int32),
+            joint=np.ascontiguousarray(list(joint_species) or [0], np.int32),
         )
         k = self._keep
         if k["coef"].shape != (S,) or k["x0"].shape != (S,):
@@ -168,7 +175,11 @@ class Sim:
         self.params = _Params(float(tau), int(m_targ), self.n_runs, int(max_iters), int(kernel),
                               k["seeds"].ctypes.data, k["x0"].ctypes.data, int(bool(recycle)),
                               _ptr(k["tgt"]), float(tgt_thr), _ptr(k["xrec"]),
-                              int(hist_species), int(hist_lo), int(hist_hi))
+                              int(hist_species), int(hist_lo), int(hist_hi),
+                              len(joint_species), k["joint"].ctypes.data, int(joint_bins),
+                              int(joint_width))
+        self.n_joint = len(joint_species)
+        self.joint_cells = int(joint_bins) ** self.n_joint if self.n_joint else 0
         self.nh = hist_hi - hist_lo + 1 if hist_hi >= hist_lo else 0
         nbytes = C.c_size_t(0)
         _check(L.we_workspace_size(network.handle, C.byref(self.grid), C.byref(self.params),
@@ -195,6 +206,13 @@ class Sim:
     def step(self, n: int = 1):
         _check(load_library().we_step_intervals(self.handle, int(n)))
 
+    def graph_capture(self, n: int):
+        """Capture n (even) iterations as a HIP graph."""
+        _check(load_library().we_graph_capture(self.handle, int(n)))
+
+    def graph_replay(self, times: int = 1):
+        _check(load_library().we_graph_replay(self.handle, int(times)))
+
     def synchronize(self):
         _check(load_library().we_synchronize(self.handle))
 
@@ -220,6 +238,11 @@ class Sim:
         n = C.c_int32(0)
         _check(load_library().we_histogram_accum(self.handle, _ptr(out), C.byref(n)))
         return out.reshape(self.n_runs, self.nh), n.value
+
+    def joint_histogram(self) -> np.ndarray:
+        out = np.zeros(self.n_runs * self.joint_cells, np.float64)
+        _check(load_library().we_joint_histogram(self.handle, _ptr(out)))
+        return out.reshape(self.n_runs, self.joint_cells)
 
     def flux(self, run: int, first: int = 0, count: Optional[int] = None) -> np.ndarray:
         if count is None:
@@ -273,11 +296,12 @@ class Sim:
 
 
 def sim_from_config(cfg, *, kernel: int = WE_KERNEL_AUTO, max_iters: Optional[int] = None,
-                    network: Optional[Network] = None) -> Sim:
+                    network: Optional[Network] = None, joint: bool = False) -> Sim:
     """Build a Sim from a workloads.WEConfig."""
     net = network if network is not None else Network(cfg.net)
     return Sim(net, cfg.bin_coef, cfg.edges, tau=cfg.tau, m_targ=cfg.m_targ, seeds=cfg.seeds,
                x0=cfg.x0, max_iters=max_iters if max_iters is not None else cfg.n_iters,
                kernel=kernel, recycle=cfg.recycle, tgt_coef=cfg.tgt_coef, tgt_thr=cfg.tgt_thr,
                x_rec=cfg.x_rec, hist_species=cfg.hist_species, hist_lo=cfg.hist_lo,
-               hist_hi=cfg.hist_hi)
+               hist_hi=cfg.hist_hi,
+               joint_species=getattr(cfg, "joint_species", ()) if joint else ())

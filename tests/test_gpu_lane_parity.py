@@ -188,3 +188,56 @@ def test_invalid_arguments_rejected():
     sim.step(1)
     with pytest.raises(we.WEError):
         sim.step(1)                       # past max_iters
+
+
+def test_graph_replay_matches_eager_and_oracle():
+    """Four iterations captured as one HIP graph and replayed five times, with
+    host work and synchronisation between replays: every replay leaves the
+    ensemble identical to step-by-step launches and to the oracle."""
+    _say("case: hipGraph replay, Schloegl 2 runs, 4 iterations x 5 replays")
+    we = _we()
+    cfg = wl.schlogl_config(n_runs=2, seed0=61, n_iters=20)
+    g = we.sim_from_config(cfg, kernel=we.WE_KERNEL_LANE, max_iters=20)
+    e = we.sim_from_config(cfg, kernel=we.WE_KERNEL_LANE, max_iters=20)
+    ors = [orc.OracleWE(cfg, int(s)) for s in cfg.seeds]
+    g.graph_capture(4)
+    for rep in range(5):
+        g.graph_replay(1)
+        e.step(4)
+        g.synchronize()
+        for r in range(2):
+            ors[r].step(4)
+            gw = g.walkers(r)
+            _assert_same(4 * rep + 3, r, gw, e.walkers(r))
+            _assert_same(4 * rep + 3, r, gw, ors[r].walkers())
+    for r in range(2):
+        assert np.array_equal(g.flux(r), np.array(ors[r].flux))
+    assert g.iterations == 20
+    h1, n1 = g.histogram_accum()
+    h2, n2 = e.histogram_accum()
+    assert n1 == n2 == 20
+    np.testing.assert_allclose(h1, h2, rtol=1e-12, atol=1e-300)
+
+
+def test_joint_histogram_matches_ensembles():
+    """The 3-species joint histogram accumulated on the device equals the sum
+    over iterations of the oracle ensembles' weights per cell."""
+    _say("case: joint histogram, futile cycle")
+    we = _we()
+    net = wl.futile_cycle()
+    cfg = wl.WEConfig(name="futile", net=net, x0=np.array([50, 50, 1, 1, 0, 0], np.int32),
+                      bin_coef=np.array([1.0, 0, 0, 0, 0, 0]), edges=np.arange(0.0, 102.0, 4.0),
+                      m_targ=3, tau=1.0, n_iters=12, seeds=np.array([4], np.uint64))
+    sim = we.Sim(we.Network(net), cfg.bin_coef, cfg.edges, tau=cfg.tau, m_targ=cfg.m_targ,
+                 seeds=cfg.seeds, x0=cfg.x0, max_iters=12, kernel=we.WE_KERNEL_LANE,
+                 joint_species=[0, 1, 4], joint_bins=8, joint_width=16)
+    o = orc.OracleWE(cfg, 4)
+    acc = np.zeros(8 ** 3)
+    for it in range(12):
+        sim.step(1)
+        o.step(1)
+        x, w, _, _ = o.walkers()
+        for xi, wi in zip(x, w):
+            c = [min(int(xi[s]) // 16, 7) for s in (0, 1, 4)]
+            acc[c[0] + 8 * c[1] + 64 * c[2]] += wi
+    np.testing.assert_allclose(sim.joint_histogram()[0], acc, rtol=1e-12, atol=1e-300)
