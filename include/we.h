@@ -119,6 +119,8 @@ typedef struct {
     const int32_t *joint_species; /* every iteration over joint_bins^n_joint cells, */
     int32_t joint_bins;        /*   cell of species d = min(x / joint_width,        */
     int32_t joint_width;       /*   joint_bins - 1), first species fastest          */
+    int32_t record_iters;      /* keep the resampled ensemble of this many          */
+                               /*   iterations on the device (committor training)   */
 } we_params;
 
 /* Device bytes a sim needs (walker buffers, series, scratch). */
@@ -204,6 +206,67 @@ WE_API we_status we_counters(we_sim *s, int64_t *events, int64_t *segments,
 /* Per-iteration reactions fired, summed over runs, for iterations
  * [first, first+count).  Synchronous. */
 WE_API we_status we_events_series(we_sim *s, int32_t first, int32_t count, int64_t *out);
+
+/* ---------------------------------------------------------------- learned bins
+ * A committor q(x) ~ P(reach B before A | x), learned from the sim's own
+ * recorded trajectories, replaces the grid coordinate (the paper leaves the
+ * choice of bins open, Sec. IV.B; WE stays unbiased for any binning).
+ * Model: n_species -> 64 -> 64 -> 1 (tanh, tanh, sigmoid), FP32, inputs
+ * (log1p(x_s) - mean_s)/std_s; binary cross-entropy on soft labels; Adam.
+ * Parameters are one FP32 array: W1[64][S], b1[64], W2[64][64], b2[64],
+ * W3[64], b3[1].  The learned bins are the sim's n_bins equal-count
+ * quantiles of q over the training states. */
+typedef struct {
+    int32_t steps;             /* Adam steps                                        */
+    int32_t batch;             /* minibatch size, a positive multiple of 256        */
+    float lr;                  /* learning rate (beta1 0.9, beta2 0.999, eps 1e-8)  */
+    const double *a_coef;      /* [S] A = { x : sum a_coef_s x_s <= a_thr }          */
+    double a_thr;
+    uint64_t seed;             /* weight initialisation and minibatch draws         */
+} we_train_params;
+
+/* Label the recorded walkers by their descendants' first outcome (B: the
+ * walker's line was recycled; A: it re-entered A), train the model, and
+ * compute the quantile edges.  loss_out (may be NULL) gets the mean
+ * minibatch loss of every step; n_samples the training-set size.
+ * Synchronous.  Errors: WE_ESTATE without records or resolved walkers. */
+WE_API we_status we_train_committor(we_sim *s, const we_train_params *tp, float *loss_out,
+                                    int32_t *n_samples);
+
+/* Bin on the trained committor (enable = 1) or on the grid again (0). */
+WE_API we_status we_use_committor_bins(we_sim *s, int32_t enable);
+
+/* q(x) of n host states x[n*S] (out: q[n]).  Synchronous. */
+WE_API we_status we_committor_eval(we_sim *s, int32_t n, const int32_t *x, float *q);
+
+/* Copy the trained model: params[n_params], feat[2*S] (mean, 1/std),
+ * qedges[n_bins+1]; any pointer may be NULL.  Synchronous. */
+WE_API we_status we_committor_state(we_sim *s, float *params, float *feat, double *qedges,
+                                    int32_t *n_params);
+
+/* Outcome counts of every recorded walker: counts[2*(i*n_runs*cap + slot)]
+ * = (n_A, n_B).  Synchronous. */
+WE_API we_status we_record_labels(we_sim *s, const double *a_coef, double a_thr,
+                                  uint32_t *counts, int32_t *n_iters);
+
+/* Recorded iteration i: walker counts per run n[n_runs], states
+ * x[n_runs*cap*S], parent slots origin[n_runs*cap], recycled flags
+ * recycled[n_runs*cap].  Synchronous. */
+WE_API we_status we_get_record(we_sim *s, int32_t i, int32_t *n, int32_t *x, int32_t *origin,
+                               uint8_t *recycled);
+
+/* Stand-alone loss and gradient of the committor model on one host
+ * minibatch (the training kernels; for checking against other
+ * implementations): params[n_params(n_in)], feat[2*n_in], x[batch*n_in],
+ * y[batch]; out: loss (mean BCE), grad[n_params].  Synchronous, default
+ * stream. */
+WE_API we_status we_mlp_loss_grad(int32_t n_in, const float *params, const float *feat,
+                                  int32_t batch, const int32_t *x, const float *y, float *loss,
+                                  float *grad);
+
+/* One Adam update (step t >= 1) of n host parameters in place.  Synchronous. */
+WE_API we_status we_adam_step(int32_t n, float *params, float *m, float *v, const float *grad,
+                              float lr, int32_t t);
 
 /* Per-kernel timing with HIP events recorded on the sim's stream around
  * every launch.  we_profile(s, 1) clears and starts the accumulators,

@@ -48,7 +48,8 @@ def lib():
         L.or_bin_of.restype = C.c_int32
         L.or_we_iterate.argtypes = [C.c_void_p, C.c_void_p, C.c_uint32, P(C.c_int32),
                                     P(C.c_int32), P(C.c_double), P(C.c_int32),
-                                    P(C.c_int32), C.c_int32, P(C.c_double), P(C.c_int64)]
+                                    P(C.c_int32), C.c_int32, P(C.c_double), P(C.c_int64),
+                                    P(C.c_int32)]
         L.or_we_iterate.restype = C.c_int32
         L.or_resample_bin.argtypes = [C.c_int32, P(C.c_int32), P(C.c_double), C.c_int32,
                                       C.c_uint64, C.c_uint32, C.c_uint32,
@@ -182,6 +183,7 @@ class OracleWE:
         self.w = np.zeros(cap, np.float64)
         self.bin = np.zeros(cap, np.int32)
         self.origin = np.full(cap, -1, np.int32)
+        self.recycled = np.zeros(cap, np.int32)   # incoming slots recycled in the last step
         if init_x is None:
             n0 = cfg.m_targ
             self.x[: n0 * S] = np.tile(np.asarray(cfg.x0, np.int32), n0)
@@ -210,7 +212,8 @@ class OracleWE:
             st = L.or_we_iterate(self.onet.ptr, self.cptr, self.iter, C.byref(n),
                                  _p(self.x, C.c_int32), _p(self.w, C.c_double),
                                  _p(self.bin, C.c_int32), _p(self.origin, C.c_int32),
-                                 self.cfg.cap, C.byref(flux), C.byref(ev))
+                                 self.cfg.cap, C.byref(flux), C.byref(ev),
+                                 _p(self.recycled, C.c_int32))
             if st != 0:
                 raise RuntimeError(f"oracle WE iteration {self.iter} failed: status {st}")
             self.n = n.value
@@ -224,6 +227,11 @@ class OracleWE:
         n = self.n
         return (self.x[: n * S].reshape(n, S).copy(), self.w[:n].copy(),
                 self.bin[:n].copy(), self.origin[:n].copy())
+
+    def child_recycled(self) -> np.ndarray:
+        """For each walker of the current ensemble: 1 if its parent reached B
+        (and was recycled) in the last iteration."""
+        return self.recycled[self.origin[: self.n]].copy()
 
     def histogram(self, species: int, lo: int, hi: int) -> np.ndarray:
         """P(x_species = k) for k in [lo, hi] from the current ensemble (walker

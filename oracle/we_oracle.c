@@ -335,7 +335,7 @@ int32_t or_resample_bin(int32_t nb, const int32_t *slot, const double *w,
 int32_t or_we_iterate(const or_net *net, const or_we_cfg *cfg, uint32_t iter,
                       int32_t *n, int32_t *x, double *w, int32_t *bin,
                       int32_t *origin, int32_t cap,
-                      double *flux_out, int64_t *events_out)
+                      double *flux_out, int64_t *events_out, int32_t *recycled_out)
 {
     const int32_t S = net->S, N = *n, M = cfg->m_targ, NB = cfg->n_bins;
     if (N > cap || M * NB > cap) return OR_EINVAL;
@@ -352,9 +352,12 @@ int32_t or_we_iterate(const or_net *net, const or_we_cfg *cfg, uint32_t iter,
 
     /* 2. steady-state recycling B -> A, weight kept, flux recorded */
     double flux = 0.0;
+    if (recycled_out)
+        for (int32_t k = 0; k < N; ++k) recycled_out[k] = 0;
     if (cfg->recycle) {
         for (int32_t k = 0; k < N; ++k) {
             if (or_coord(S, cfg->tgt_coef, x + (size_t)k * S) >= cfg->tgt_thr) {
+                if (recycled_out) recycled_out[k] = 1;
                 flux = flux + w[k];
                 memcpy(x + (size_t)k * S, cfg->x_rec, sizeof(int32_t) * (size_t)S);
             }

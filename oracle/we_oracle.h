@@ -106,11 +106,13 @@ int32_t or_bin_of(int32_t n_bins, const double *edges, double q);
  * ascending; inside a bin, parents by ascending slot; copies of a parent
  * consecutive).  Arrays must hold cap = m_targ*n_bins walkers (and at least
  * the incoming *n).  flux_out gets the weight recycled this iteration;
- * events_out the reactions fired.  Returns a status. */
+ * events_out the reactions fired; recycled_out (may be NULL, size cap)
+ * gets 1 for every incoming slot whose walker reached B and was recycled.
+ * Returns a status. */
 int32_t or_we_iterate(const or_net *net, const or_we_cfg *cfg, uint32_t iter,
                       int32_t *n, int32_t *x, double *w, int32_t *bin,
                       int32_t *origin, int32_t cap,
-                      double *flux_out, int64_t *events_out);
+                      double *flux_out, int64_t *events_out, int32_t *recycled_out);
 
 /* The resampling step alone, for one bin: nb walkers (parent slots, weights)
  * in ascending slot order.  Writes the surviving/replicated walkers as

@@ -1,0 +1,692 @@
+// committor.hip -- a learned progress coordinate for binning (gfx950).
+//
+// The paper bins on hand-chosen coordinates and names optimal, automatic
+// binning an open problem (Sec. IV.B).  This module learns a committor
+// q(x) ~ P(reach B before A | x) from the WE trajectories themselves and bins
+// on it; WE stays unbiased for any binning (Sec. II.B), so a poor model only
+// costs efficiency.
+//
+//  1. records: after every iteration the resampled ensemble (states, parent
+//     slots, and whether the parent reached B in that interval) is copied to
+//     a record buffer in HBM;
+//  2. labels (reverse pass over the records, one launch per iteration):
+//     every walker adds to its parent the first outcome of each child --
+//     B if the child's parent was recycled in that interval, A if the child
+//     sits in the A region, otherwise the child's own counts.  Integer
+//     atomics, so the counts are exact and order-free.  Label
+//     y = n_B / (n_A + n_B) for walkers with a resolved descendant;
+//  3. dataset: resolved walkers compacted in record order (block counts,
+//     one scan, in-block ballot ranks);
+//  4. features: phi_s = (log1p(x_s) - mean_s) / std_s, statistics reduced in
+//     a fixed order per species;
+//  5. model: n_in -> 64 -> 64 -> 1, tanh, tanh, sigmoid, FP32; loss: binary
+//     cross-entropy with the soft label; Adam (beta 0.9/0.999, eps 1e-8).
+//     Forward/backward is one lane per sample; each parameter's gradient is
+//     summed over the minibatch by one lane in sample order, so a training
+//     run is reproducible;
+//  6. bins: n_bins equal-count quantile edges of q over the dataset (a
+//     65536-cell integer histogram of q); with the committor active, every
+//     walker's bin is bin_index(edges, q(x)) after recycling.
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "we_internal.h"
+
+#define CM_H 64
+#define Q_HIST 65536
+
+// ------------------------------------------------------------------ layout
+__host__ __device__ inline int32_t cm_n_params(int32_t n_in) {
+    return CM_H * n_in + CM_H + CM_H * CM_H + CM_H + CM_H + 1;
+}
+struct ParamView {
+    const float *W1, *b1, *W2, *b2, *W3, *b3;
+};
+__host__ __device__ inline ParamView cm_view(const float *p, int32_t n_in) {
+    ParamView v;
+    v.W1 = p;
+    v.b1 = v.W1 + CM_H * n_in;
+    v.W2 = v.b1 + CM_H;
+    v.b2 = v.W2 + CM_H * CM_H;
+    v.W3 = v.b2 + CM_H;
+    v.b3 = v.W3 + CM_H;
+    return v;
+}
+
+__device__ __forceinline__ float feature(int32_t x, const float *feat, int32_t k, int32_t n_in) {
+    return (log1pf((float)x) - feat[k]) * feat[n_in + k];
+}
+
+// q(x) for one state row; phi is recomputed on the fly.
+__device__ float mlp_q(const ParamView &P, const float *feat, const int32_t *xr, int32_t n_in) {
+    float h1[CM_H];
+#pragma unroll
+    for (int j = 0; j < CM_H; ++j) h1[j] = P.b1[j];
+    for (int k = 0; k < n_in; ++k) {
+        const float f = feature(xr[k], feat, k, n_in);
+#pragma unroll
+        for (int j = 0; j < CM_H; ++j) h1[j] = fmaf(P.W1[j * n_in + k], f, h1[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < CM_H; ++j) h1[j] = tanhf(h1[j]);
+    float z3 = P.b3[0];
+    for (int i = 0; i < CM_H; ++i) {
+        float z = P.b2[i];
+#pragma unroll
+        for (int j = 0; j < CM_H; ++j) z = fmaf(P.W2[i * CM_H + j], h1[j], z);
+        z3 = fmaf(P.W3[i], tanhf(z), z3);
+    }
+    return 1.0f / (1.0f + expf(-z3));
+}
+
+// ------------------------------------------------------------------ records
+__global__ __launch_bounds__(256) void cm_record_kernel(SimArgs a, const int32_t *__restrict__ x_nxt,
+                                                        int32_t *__restrict__ rx, int32_t *__restrict__ rorig,
+                                                        uint8_t *__restrict__ rrec, int32_t *__restrict__ rn) {
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int32_t run = (int32_t)(gid / a.cap);
+    const int32_t k = (int32_t)(gid - (int64_t)run * a.cap);
+    if (run >= a.n_runs) return;
+    const int32_t n = a.n_walk[run];
+    if (k == 0) rn[run] = n;
+    if (k >= n) return;
+    const size_t idx = (size_t)run * a.cap + k;
+    const int32_t o = a.origin[idx];
+    rorig[idx] = o;
+    rrec[idx] = (uint8_t)(a.s_rec[(size_t)run * a.cap + o] != 0);
+    for (int32_t s = 0; s < a.S; ++s) rx[idx * a.S + s] = x_nxt[idx * a.S + s];
+}
+
+hipError_t committor_record(we_sim *s, hipStream_t st) {
+    Records &R = s->rec;
+    if (R.cap_iters <= 0 || R.n_iters >= R.cap_iters) return hipSuccess;
+    const size_t W = (size_t)s->n_runs * s->cap;
+    const int32_t i = R.n_iters;
+    const int64_t total = (int64_t)W;
+    hipLaunchKernelGGL(cm_record_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st,
+                       s->args, s->x[s->cur], R.d_x + i * W * s->S, R.d_origin + i * W, R.d_rec + i * W,
+                       R.d_n + (size_t)i * s->n_runs);
+    R.n_iters += 1;
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ labels
+__global__ __launch_bounds__(256) void cm_label_kernel(int32_t n_runs, int32_t cap, int32_t S,
+                                                       const int32_t *__restrict__ x_child,
+                                                       const int32_t *__restrict__ orig_child,
+                                                       const uint8_t *__restrict__ rec_child,
+                                                       const int32_t *__restrict__ n_child,
+                                                       const uint32_t *__restrict__ cnt_child,
+                                                       uint32_t *__restrict__ cnt_parent,
+                                                       const double *__restrict__ a_coef, double a_thr) {
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int32_t run = (int32_t)(gid / cap);
+    const int32_t k = (int32_t)(gid - (int64_t)run * cap);
+    if (run >= n_runs) return;
+    if (k >= n_child[run]) return;
+    const size_t idx = (size_t)run * cap + k;
+    uint32_t nA, nB;
+    if (rec_child[idx]) {
+        nA = 0; nB = 1;
+    } else {
+        double q = 0.0;
+        for (int32_t s = 0; s < S; ++s) q = q + a_coef[s] * (double)x_child[idx * S + s];
+        if (q <= a_thr) { nA = 1; nB = 0; }
+        else { nA = cnt_child[2 * idx]; nB = cnt_child[2 * idx + 1]; }
+    }
+    const int32_t p = orig_child[idx];
+    if (p < 0 || p >= cap) return;
+    const size_t pidx = (size_t)run * cap + p;
+    if (nA) atomicAdd(&cnt_parent[2 * pidx], nA);
+    if (nB) atomicAdd(&cnt_parent[2 * pidx + 1], nB);
+}
+
+// ------------------------------------------------------------------ dataset
+__global__ __launch_bounds__(256) void cm_count_kernel(int64_t n_items, int32_t n_runs, int32_t cap,
+                                                       const int32_t *__restrict__ rn,
+                                                       const uint32_t *__restrict__ cnt,
+                                                       int32_t *__restrict__ blk) {
+    __shared__ int32_t part[256];
+    const int64_t f = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    int32_t v = 0;
+    if (f < n_items) {
+        const int64_t W = (int64_t)n_runs * cap;
+        const int64_t i = f / W;
+        const int32_t run = (int32_t)((f - i * W) / cap);
+        const int32_t k = (int32_t)(f - i * W - (int64_t)run * cap);
+        v = (k < rn[i * n_runs + run]) && (cnt[2 * f] + cnt[2 * f + 1] > 0);
+    }
+    part[threadIdx.x] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t c = 0;
+        for (int t = 0; t < 256; ++t) c += part[t];
+        blk[blockIdx.x] = c;
+    }
+}
+
+__global__ void cm_scan_kernel(int32_t n_blk, int32_t *__restrict__ blk, int32_t *__restrict__ total) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    int32_t acc = 0;
+    for (int32_t b = 0; b < n_blk; ++b) {
+        const int32_t c = blk[b];
+        blk[b] = acc;
+        acc += c;
+    }
+    *total = acc;
+}
+
+__global__ __launch_bounds__(256) void cm_compact_kernel(int64_t n_items, int32_t n_runs, int32_t cap,
+                                                         const int32_t *__restrict__ rn,
+                                                         const uint32_t *__restrict__ cnt,
+                                                         const int32_t *__restrict__ blk,
+                                                         int64_t *__restrict__ ds_idx,
+                                                         float *__restrict__ ds_y, int32_t ds_cap) {
+    __shared__ int32_t part[256];
+    const int64_t f = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    int32_t v = 0;
+    if (f < n_items) {
+        const int64_t W = (int64_t)n_runs * cap;
+        const int64_t i = f / W;
+        const int32_t run = (int32_t)((f - i * W) / cap);
+        const int32_t k = (int32_t)(f - i * W - (int64_t)run * cap);
+        v = (k < rn[i * n_runs + run]) && (cnt[2 * f] + cnt[2 * f + 1] > 0);
+    }
+    part[threadIdx.x] = v;
+    __syncthreads();
+    if (!v) return;
+    int32_t rank = 0;
+    for (int t = 0; t < (int)threadIdx.x; ++t) rank += part[t];
+    const int32_t pos = blk[blockIdx.x] + rank;
+    if (pos >= ds_cap) return;
+    ds_idx[pos] = f;
+    const float nA = (float)cnt[2 * f], nB = (float)cnt[2 * f + 1];
+    ds_y[pos] = nB / (nA + nB);
+}
+
+// per-species mean and 1/std of log1p(x) over the dataset (FP64, fixed order)
+__global__ __launch_bounds__(256) void cm_feat_kernel(int32_t n, int32_t S, const int64_t *__restrict__ ds_idx,
+                                                      const int32_t *__restrict__ rx, float *__restrict__ feat) {
+    __shared__ double s1[256], s2[256];
+    const int32_t sp = blockIdx.x;
+    double a = 0.0, b = 0.0;
+    for (int32_t i = threadIdx.x; i < n; i += 256) {
+        const double v = log1p((double)rx[ds_idx[i] * S + sp]);
+        a += v;
+        b += v * v;
+    }
+    s1[threadIdx.x] = a;
+    s2[threadIdx.x] = b;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) {
+            s1[threadIdx.x] += s1[threadIdx.x + off];
+            s2[threadIdx.x] += s2[threadIdx.x + off];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double mean = n > 0 ? s1[0] / n : 0.0;
+        const double var = n > 0 ? s2[0] / n - mean * mean : 0.0;
+        const double sd = var > 1e-12 ? sqrt(var) : 1.0;
+        feat[sp] = (float)mean;
+        feat[S + sp] = (float)(1.0 / sd);
+    }
+}
+
+// ------------------------------------------------------------------ training
+// Glorot-uniform weights from Philox (counter (index, 0, 0, 2)), zero biases.
+__global__ void cm_init_kernel(float *__restrict__ p, int32_t n_in, uint32_t k0, uint32_t k1) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int32_t np = cm_n_params(n_in);
+    if (i >= np) return;
+    const int32_t nW1 = CM_H * n_in, nW2 = CM_H * CM_H;
+    const int32_t b1 = nW1, w2 = b1 + CM_H, b2 = w2 + nW2, w3 = b2 + CM_H, b3 = w3 + CM_H;
+    float limit = 0.0f;
+    if (i < b1) limit = sqrtf(6.0f / (float)(n_in + CM_H));
+    else if (i >= w2 && i < b2) limit = sqrtf(6.0f / (float)(CM_H + CM_H));
+    else if (i >= w3 && i < b3) limit = sqrtf(6.0f / (float)(CM_H + 1));
+    const U4 r = philox4x32_10((uint32_t)i, 0u, 0u, 2u, k0, k1);
+    const float u = (float)uniform53(r.x, r.y);
+    p[i] = limit * (2.0f * u - 1.0f);
+}
+
+struct Scratch {
+    float *phi, *h1, *h2, *g1, *g2, *g3, *loss;   // [feature][B] layout
+};
+
+// Forward and backward of one sample per lane; the sample is either drawn
+// from the dataset with Philox (counter (b, step, 1, 2)) or given directly.
+__global__ __launch_bounds__(256) void cm_fwd_bwd_kernel(const float *__restrict__ params, const float *__restrict__ feat,
+                                                         int32_t n_in, int32_t B, int32_t step,
+                                                         uint32_t k0, uint32_t k1, int32_t n_ds,
+                                                         const int64_t *__restrict__ ds_idx,
+                                                         const float *__restrict__ ds_y,
+                                                         const int32_t *__restrict__ rx,
+                                                         const int32_t *__restrict__ direct_x,
+                                                         const float *__restrict__ direct_y, Scratch sc) {
+    const int32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    const ParamView P = cm_view(params, n_in);
+    const int32_t *xr;
+    float y;
+    if (direct_x) {
+        xr = direct_x + (size_t)b * n_in;
+        y = direct_y[b];
+    } else {
+        const U4 r = philox4x32_10((uint32_t)b, (uint32_t)step, 1u, 2u, k0, k1);
+        int32_t pick = (int32_t)(uniform53(r.x, r.y) * (double)n_ds);
+        if (pick >= n_ds) pick = n_ds - 1;
+        xr = rx + ds_idx[pick] * n_in;
+        y = ds_y[pick];
+    }
+    float h1[CM_H];
+#pragma unroll
+    for (int j = 0; j < CM_H; ++j) h1[j] = P.b1[j];
+    for (int k = 0; k < n_in; ++k) {
+        const float f = feature(xr[k], feat, k, n_in);
+        sc.phi[(size_t)k * B + b] = f;
+#pragma unroll
+        for (int j = 0; j < CM_H; ++j) h1[j] = fmaf(P.W1[j * n_in + k], f, h1[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < CM_H; ++j) {
+        h1[j] = tanhf(h1[j]);
+        sc.h1[(size_t)j * B + b] = h1[j];
+    }
+    float z3 = P.b3[0];
+    for (int i = 0; i < CM_H; ++i) {
+        float z = P.b2[i];
+#pragma unroll
+        for (int j = 0; j < CM_H; ++j) z = fmaf(P.W2[i * CM_H + j], h1[j], z);
+        const float h2 = tanhf(z);
+        sc.h2[(size_t)i * B + b] = h2;
+        z3 = fmaf(P.W3[i], h2, z3);
+    }
+    const float q = 1.0f / (1.0f + expf(-z3));
+    // binary cross-entropy with a soft label, in the stable form
+    sc.loss[b] = fmaxf(z3, 0.0f) - z3 * y + log1pf(expf(-fabsf(z3)));
+    const float g3 = (q - y) / (float)B;
+    sc.g3[b] = g3;
+    float acc[CM_H];
+#pragma unroll
+    for (int j = 0; j < CM_H; ++j) acc[j] = 0.0f;
+    for (int i = 0; i < CM_H; ++i) {
+        const float h2 = sc.h2[(size_t)i * B + b];
+        const float g2 = g3 * P.W3[i] * (1.0f - h2 * h2);
+        sc.g2[(size_t)i * B + b] = g2;
+#pragma unroll
+        for (int j = 0; j < CM_H; ++j) acc[j] = fmaf(P.W2[i * CM_H + j], g2, acc[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < CM_H; ++j) sc.g1[(size_t)j * B + b] = acc[j] * (1.0f - h1[j] * h1[j]);
+}
+
+// One lane per parameter: its gradient summed over the minibatch in sample order.
+__global__ __launch_bounds__(256) void cm_grad_kernel(int32_t n_in, int32_t B, Scratch sc, float *__restrict__ grad,
+                                                      float *__restrict__ loss_out) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int32_t np = cm_n_params(n_in);
+    if (i == np && loss_out) {
+        float l = 0.0f;
+        for (int32_t b = 0; b < B; ++b) l += sc.loss[b];
+        *loss_out = l / (float)B;
+        return;
+    }
+    if (i >= np) return;
+    const int32_t nW1 = CM_H * n_in, nW2 = CM_H * CM_H;
+    const int32_t b1 = nW1, w2 = b1 + CM_H, b2 = w2 + nW2, w3 = b2 + CM_H, b3 = w3 + CM_H;
+    const float *u, *v = nullptr;
+    if (i < b1) { u = sc.g1 + (size_t)(i / n_in) * B; v = sc.phi + (size_t)(i % n_in) * B; }
+    else if (i < w2) { u = sc.g1 + (size_t)(i - b1) * B; }
+    else if (i < b2) { const int32_t r = i - w2; u = sc.g2 + (size_t)(r / CM_H) * B; v = sc.h1 + (size_t)(r % CM_H) * B; }
+    else if (i < w3) { u = sc.g2 + (size_t)(i - b2) * B; }
+    else if (i < b3) { u = sc.g3; v = sc.h2 + (size_t)(i - w3) * B; }
+    else { u = sc.g3; }
+    float acc = 0.0f;
+    if (v) for (int32_t b = 0; b < B; ++b) acc = fmaf(u[b], v[b], acc);
+    else for (int32_t b = 0; b < B; ++b) acc += u[b];
+    grad[i] = acc;
+}
+
+__global__ void cm_adam_kernel(int32_t np, float *__restrict__ p, float *__restrict__ m, float *__restrict__ v,
+                               const float *__restrict__ g, float lr, int32_t t) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= np) return;
+    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float mh = mi / (1.0f - powf(b1, (float)t));
+    const float vh = vi / (1.0f - powf(b2, (float)t));
+    p[i] -= lr * mh / (sqrtf(vh) + eps);
+}
+
+// ------------------------------------------------------------------ inference
+__global__ __launch_bounds__(256) void cm_eval_kernel(const float *__restrict__ params, const float *__restrict__ feat,
+                                                      int32_t n_in, int32_t n, const int64_t *__restrict__ ds_idx,
+                                                      const int32_t *__restrict__ rx, float *__restrict__ q_out,
+                                                      uint32_t *__restrict__ qhist) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const ParamView P = cm_view(params, n_in);
+    const int32_t *xr = ds_idx ? rx + ds_idx[i] * n_in : rx + (size_t)i * n_in;
+    const float q = mlp_q(P, feat, xr, n_in);
+    if (q_out) q_out[i] = q;
+    if (qhist) {
+        int32_t c = (int32_t)(q * (float)Q_HIST);
+        c = c < 0 ? 0 : (c >= Q_HIST ? Q_HIST - 1 : c);
+        atomicAdd(&qhist[c], 1u);
+    }
+}
+
+__global__ void cm_edges_kernel(const uint32_t *__restrict__ qhist, int32_t n, int32_t nb, double *__restrict__ edges) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    edges[0] = 0.0;
+    int64_t cum = 0;
+    int32_t b = 1, c = 0;
+    for (; c < Q_HIST && b < nb; ++c) {
+        cum += qhist[c];
+        while (b < nb && cum * nb >= (int64_t)b * n) {
+            double e = (double)(c + 1) / (double)Q_HIST;
+            if (e <= edges[b - 1]) e = edges[b - 1] + 1.0 / (4.0 * Q_HIST);
+            edges[b] = e;
+            ++b;
+        }
+    }
+    for (; b < nb; ++b) edges[b] = edges[b - 1] + 1.0 / (4.0 * Q_HIST);
+    edges[nb] = edges[nb - 1] > 1.0 ? edges[nb - 1] + 1.0 : 1.0 + 1.0 / Q_HIST;
+}
+
+__global__ __launch_bounds__(256) void cm_bin_kernel(SimArgs a, const int32_t *__restrict__ x_cur,
+                                                     const float *__restrict__ params, const float *__restrict__ feat,
+                                                     const double *__restrict__ qedges) {
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int32_t run = (int32_t)(gid / a.cap);
+    const int32_t k = (int32_t)(gid - (int64_t)run * a.cap);
+    if (run >= a.n_runs) return;
+    if (k >= a.n_walk[run]) return;
+    const size_t idx = (size_t)run * a.cap + k;
+    const ParamView P = cm_view(params, a.S);
+    const float q = mlp_q(P, feat, x_cur + idx * a.S, a.S);
+    a.s_bin[idx] = bin_index(qedges, a.n_bins, (double)q);
+}
+
+hipError_t committor_bin(we_sim *s, int32_t *x_cur, hipStream_t st) {
+    const int64_t total = (int64_t)s->n_runs * s->cap;
+    hipLaunchKernelGGL(cm_bin_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, s->args, x_cur,
+                       s->cm.d_params, s->cm.d_feat, s->cm.d_qedges);
+    return hipGetLastError();
+}
+
+void committor_free(we_sim *s) {
+    Committor &c = s->cm;
+    (void)hipFree(c.d_params);
+    (void)hipFree(c.d_adam_m);
+    (void)hipFree(c.d_adam_v);
+    (void)hipFree(c.d_grad);
+    (void)hipFree(c.d_feat);
+    (void)hipFree(c.d_qedges);
+    c = Committor();
+}
+
+// ------------------------------------------------------------------ C ABI
+namespace {
+
+struct DevBuf {
+    void *p = nullptr;
+    ~DevBuf() { if (p) (void)hipFree(p); }
+    hipError_t alloc(size_t bytes) { return hipMalloc(&p, std::max<size_t>(bytes, 16)); }
+    template <class T> T *as() { return static_cast<T *>(p); }
+};
+
+struct ScratchBufs {
+    DevBuf phi, h1, h2, g1, g2, g3, loss;
+    hipError_t alloc(int32_t n_in, int32_t B) {
+        hipError_t e;
+        if ((e = phi.alloc(4ull * n_in * B)) != hipSuccess) return e;
+        if ((e = h1.alloc(4ull * CM_H * B)) != hipSuccess) return e;
+        if ((e = h2.alloc(4ull * CM_H * B)) != hipSuccess) return e;
+        if ((e = g1.alloc(4ull * CM_H * B)) != hipSuccess) return e;
+        if ((e = g2.alloc(4ull * CM_H * B)) != hipSuccess) return e;
+        if ((e = g3.alloc(4ull * B)) != hipSuccess) return e;
+        return loss.alloc(4ull * B);
+    }
+    Scratch view() {
+        return Scratch{phi.as<float>(), h1.as<float>(), h2.as<float>(), g1.as<float>(), g2.as<float>(),
+                       g3.as<float>(), loss.as<float>()};
+    }
+};
+
+// record-buffer counts of outcomes, [n_iters][n_runs*cap][2]
+we_status run_labels(we_sim *s, const double *a_coef_h, double a_thr, DevBuf &cnt) {
+    Records &R = s->rec;
+    const size_t W = (size_t)s->n_runs * s->cap;
+    HIP_TRY(cnt.alloc(8 * W * std::max(R.n_iters, 1)));
+    HIP_TRY(hipMemsetAsync(cnt.p, 0, 8 * W * std::max(R.n_iters, 1), s->stream));
+    DevBuf coef;
+    HIP_TRY(coef.alloc(8 * (size_t)s->S));
+    HIP_TRY(hipMemcpyAsync(coef.p, a_coef_h, 8 * (size_t)s->S, hipMemcpyHostToDevice, s->stream));
+    uint32_t *c = cnt.as<uint32_t>();
+    for (int32_t i = R.n_iters - 1; i >= 1; --i) {
+        hipLaunchKernelGGL(cm_label_kernel, dim3((unsigned)((W + 255) / 256)), dim3(256), 0, s->stream, s->n_runs,
+                           s->cap, s->S, R.d_x + i * W * s->S, R.d_origin + i * W, R.d_rec + i * W,
+                           R.d_n + (size_t)i * s->n_runs, c + 2 * i * W, c + 2 * (i - 1) * W, coef.as<double>(),
+                           a_thr);
+        HIP_TRY(hipGetLastError());
+    }
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    return WE_OK;
+}
+
+}  // namespace
+
+extern "C" we_status we_record_labels(we_sim *s, const double *a_coef, double a_thr, uint32_t *counts,
+                                      int32_t *n_iters) {
+    if (!s || !a_coef) return we_fail(WE_EINVAL, "NULL argument");
+    if (s->rec.cap_iters <= 0) return we_fail(WE_ESTATE, "no records were requested at init");
+    DevBuf cnt;
+    we_status st = run_labels(s, a_coef, a_thr, cnt);
+    if (st != WE_OK) return st;
+    const size_t W = (size_t)s->n_runs * s->cap;
+    if (counts) HIP_TRY(hipMemcpy(counts, cnt.p, 8 * W * s->rec.n_iters, hipMemcpyDeviceToHost));
+    if (n_iters) *n_iters = s->rec.n_iters;
+    return WE_OK;
+}
+
+extern "C" we_status we_get_record(we_sim *s, int32_t i, int32_t *n, int32_t *x, int32_t *origin,
+                                   uint8_t *recycled) {
+    if (!s) return we_fail(WE_EINVAL, "NULL sim");
+    if (i < 0 || i >= s->rec.n_iters) return we_fail(WE_EINVAL, "record index out of range");
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    const size_t W = (size_t)s->n_runs * s->cap;
+    if (n) HIP_TRY(hipMemcpy(n, s->rec.d_n + (size_t)i * s->n_runs, 4 * (size_t)s->n_runs, hipMemcpyDeviceToHost));
+    if (x) HIP_TRY(hipMemcpy(x, s->rec.d_x + i * W * s->S, 4 * W * s->S, hipMemcpyDeviceToHost));
+    if (origin) HIP_TRY(hipMemcpy(origin, s->rec.d_origin + i * W, 4 * W, hipMemcpyDeviceToHost));
+    if (recycled) HIP_TRY(hipMemcpy(recycled, s->rec.d_rec + i * W, W, hipMemcpyDeviceToHost));
+    return WE_OK;
+}
+
+extern "C" we_status we_train_committor(we_sim *s, const we_train_params *tp, float *loss_out,
+                                        int32_t *n_samples) {
+    if (!s || !tp || !tp->a_coef) return we_fail(WE_EINVAL, "NULL argument");
+    if (s->rec.cap_iters <= 0 || s->rec.n_iters < 2) return we_fail(WE_ESTATE, "need at least two recorded iterations");
+    if (tp->steps < 0 || tp->batch <= 0 || tp->batch % 256 || !(tp->lr > 0.0f))
+        return we_fail(WE_EINVAL, "steps >= 0, batch a positive multiple of 256, lr > 0");
+    const int32_t n_in = s->S;
+    if (n_in > 1024) return we_fail(WE_EINVAL, "committor supports up to 1024 species");
+    Records &R = s->rec;
+    const size_t W = (size_t)s->n_runs * s->cap;
+    DevBuf cnt;
+    we_status st = run_labels(s, tp->a_coef, tp->a_thr, cnt);
+    if (st != WE_OK) return st;
+
+    // dataset: resolved walkers, in record order
+    const int64_t n_items = (int64_t)R.n_iters * (int64_t)W;
+    const int32_t n_blk = (int32_t)((n_items + 255) / 256);
+    DevBuf blk, total, ds_idx, ds_y;
+    HIP_TRY(blk.alloc(4ull * n_blk));
+    HIP_TRY(total.alloc(4));
+    hipLaunchKernelGGL(cm_count_kernel, dim3(n_blk), dim3(256), 0, s->stream, n_items, s->n_runs, s->cap, R.d_n,
+                       cnt.as<uint32_t>(), blk.as<int32_t>());
+    HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(cm_scan_kernel, dim3(1), dim3(64), 0, s->stream, n_blk, blk.as<int32_t>(), total.as<int32_t>());
+    HIP_TRY(hipGetLastError());
+    int32_t n_ds = 0;
+    HIP_TRY(hipMemcpyAsync(&n_ds, total.p, 4, hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    if (n_ds < 1) return we_fail(WE_ESTATE, "no recorded walker has a resolved outcome yet");
+    HIP_TRY(ds_idx.alloc(8ull * n_ds));
+    HIP_TRY(ds_y.alloc(4ull * n_ds));
+    hipLaunchKernelGGL(cm_compact_kernel, dim3(n_blk), dim3(256), 0, s->stream, n_items, s->n_runs, s->cap, R.d_n,
+                       cnt.as<uint32_t>(), blk.as<int32_t>(), ds_idx.as<int64_t>(), ds_y.as<float>(), n_ds);
+    HIP_TRY(hipGetLastError());
+
+    // model buffers
+    Committor &C = s->cm;
+    committor_free(s);
+    C.n_in = n_in;
+    C.n_params = cm_n_params(n_in);
+    C.n_qbins = s->NB;
+    const size_t pb = 4ull * C.n_params;
+    HIP_TRY(hipMalloc(&C.d_params, pb));
+    HIP_TRY(hipMalloc(&C.d_adam_m, pb));
+    HIP_TRY(hipMalloc(&C.d_adam_v, pb));
+    HIP_TRY(hipMalloc(&C.d_grad, pb));
+    HIP_TRY(hipMalloc(&C.d_feat, 8ull * n_in));
+    HIP_TRY(hipMalloc(&C.d_qedges, 8ull * (C.n_qbins + 1)));
+    HIP_TRY(hipMemsetAsync(C.d_adam_m, 0, pb, s->stream));
+    HIP_TRY(hipMemsetAsync(C.d_adam_v, 0, pb, s->stream));
+    const uint32_t k0 = (uint32_t)tp->seed, k1 = (uint32_t)(tp->seed >> 32);
+    hipLaunchKernelGGL(cm_init_kernel, dim3((C.n_params + 255) / 256), dim3(256), 0, s->stream, C.d_params, n_in, k0, k1);
+    HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(cm_feat_kernel, dim3(n_in), dim3(256), 0, s->stream, n_ds, n_in, ds_idx.as<int64_t>(), R.d_x,
+                       C.d_feat);
+    HIP_TRY(hipGetLastError());
+
+    // Adam steps
+    const int32_t B = tp->batch;
+    ScratchBufs sb;
+    HIP_TRY(sb.alloc(n_in, B));
+    DevBuf dloss;
+    HIP_TRY(dloss.alloc(4ull * std::max(tp->steps, 1)));
+    for (int32_t step = 0; step < tp->steps; ++step) {
+        hipLaunchKernelGGL(cm_fwd_bwd_kernel, dim3(B / 256), dim3(256), 0, s->stream, C.d_params, C.d_feat, n_in, B,
+                           step, k0, k1, n_ds, ds_idx.as<int64_t>(), ds_y.as<float>(), R.d_x,
+                           (const int32_t *)nullptr, (const float *)nullptr, sb.view());
+        HIP_TRY(hipGetLastError());
+        hipLaunchKernelGGL(cm_grad_kernel, dim3((C.n_params + 1 + 255) / 256), dim3(256), 0, s->stream, n_in, B,
+                           sb.view(), C.d_grad, dloss.as<float>() + step);
+        HIP_TRY(hipGetLastError());
+        hipLaunchKernelGGL(cm_adam_kernel, dim3((C.n_params + 255) / 256), dim3(256), 0, s->stream, C.n_params,
+                           C.d_params, C.d_adam_m, C.d_adam_v, C.d_grad, tp->lr, step + 1);
+        HIP_TRY(hipGetLastError());
+    }
+
+    // equal-count quantile edges of q over the dataset
+    DevBuf qhist;
+    HIP_TRY(qhist.alloc(4ull * Q_HIST));
+    HIP_TRY(hipMemsetAsync(qhist.p, 0, 4ull * Q_HIST, s->stream));
+    hipLaunchKernelGGL(cm_eval_kernel, dim3((n_ds + 255) / 256), dim3(256), 0, s->stream, C.d_params, C.d_feat, n_in,
+                       n_ds, ds_idx.as<int64_t>(), R.d_x, (float *)nullptr, qhist.as<uint32_t>());
+    HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(cm_edges_kernel, dim3(1), dim3(64), 0, s->stream, qhist.as<uint32_t>(), n_ds, C.n_qbins,
+                       C.d_qedges);
+    HIP_TRY(hipGetLastError());
+    if (loss_out && tp->steps > 0)
+        HIP_TRY(hipMemcpyAsync(loss_out, dloss.p, 4ull * tp->steps, hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    C.trained = true;
+    if (n_samples) *n_samples = n_ds;
+    return WE_OK;
+}
+
+extern "C" we_status we_use_committor_bins(we_sim *s, int32_t enable) {
+    if (!s) return we_fail(WE_EINVAL, "NULL sim");
+    if (enable && !s->cm.trained) return we_fail(WE_ESTATE, "no trained committor");
+    if (s->graph_exec) return we_fail(WE_ESTATE, "recapture the graph after switching bins");
+    s->cm.active = enable != 0;
+    return WE_OK;
+}
+
+extern "C" we_status we_committor_eval(we_sim *s, int32_t n, const int32_t *x, float *q) {
+    if (!s || (n > 0 && (!x || !q))) return we_fail(WE_EINVAL, "NULL argument");
+    if (!s->cm.trained) return we_fail(WE_ESTATE, "no trained committor");
+    DevBuf dx, dq;
+    HIP_TRY(dx.alloc(4ull * n * s->S));
+    HIP_TRY(dq.alloc(4ull * n));
+    HIP_TRY(hipMemcpyAsync(dx.p, x, 4ull * n * s->S, hipMemcpyHostToDevice, s->stream));
+    hipLaunchKernelGGL(cm_eval_kernel, dim3((n + 255) / 256), dim3(256), 0, s->stream, s->cm.d_params, s->cm.d_feat,
+                       s->S, n, (const int64_t *)nullptr, dx.as<int32_t>(), dq.as<float>(), (uint32_t *)nullptr);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(q, dq.p, 4ull * n, hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    return WE_OK;
+}
+
+extern "C" we_status we_committor_state(we_sim *s, float *params, float *feat, double *qedges, int32_t *n_params) {
+    if (!s) return we_fail(WE_EINVAL, "NULL sim");
+    if (!s->cm.trained) return we_fail(WE_ESTATE, "no trained committor");
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    if (n_params) *n_params = s->cm.n_params;
+    if (params) HIP_TRY(hipMemcpy(params, s->cm.d_params, 4ull * s->cm.n_params, hipMemcpyDeviceToHost));
+    if (feat) HIP_TRY(hipMemcpy(feat, s->cm.d_feat, 8ull * s->cm.n_in, hipMemcpyDeviceToHost));
+    if (qedges) HIP_TRY(hipMemcpy(qedges, s->cm.d_qedges, 8ull * (s->cm.n_qbins + 1), hipMemcpyDeviceToHost));
+    return WE_OK;
+}
+
+extern "C" we_status we_mlp_loss_grad(int32_t n_in, const float *params, const float *feat, int32_t batch,
+                                      const int32_t *x, const float *y, float *loss, float *grad) {
+    if (n_in < 1 || n_in > 1024 || batch < 1 || !params || !feat || !x || !y)
+        return we_fail(WE_EINVAL, "bad arguments");
+    const int32_t np = cm_n_params(n_in);
+    DevBuf dp, df, dx, dy, dg, dl;
+    HIP_TRY(dp.alloc(4ull * np));
+    HIP_TRY(df.alloc(8ull * n_in));
+    HIP_TRY(dx.alloc(4ull * batch * n_in));
+    HIP_TRY(dy.alloc(4ull * batch));
+    HIP_TRY(dg.alloc(4ull * np));
+    HIP_TRY(dl.alloc(4));
+    HIP_TRY(hipMemcpy(dp.p, params, 4ull * np, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(df.p, feat, 8ull * n_in, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(dx.p, x, 4ull * batch * n_in, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(dy.p, y, 4ull * batch, hipMemcpyHostToDevice));
+    ScratchBufs sb;
+    HIP_TRY(sb.alloc(n_in, batch));
+    hipLaunchKernelGGL(cm_fwd_bwd_kernel, dim3((batch + 255) / 256), dim3(256), 0, nullptr, dp.as<float>(),
+                       df.as<float>(), n_in, batch, 0, 0u, 0u, 0, (const int64_t *)nullptr, (const float *)nullptr,
+                       (const int32_t *)nullptr, dx.as<int32_t>(), dy.as<float>(), sb.view());
+    HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(cm_grad_kernel, dim3((np + 1 + 255) / 256), dim3(256), 0, nullptr, n_in, batch, sb.view(),
+                       dg.as<float>(), dl.as<float>());
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipDeviceSynchronize());
+    if (grad) HIP_TRY(hipMemcpy(grad, dg.p, 4ull * np, hipMemcpyDeviceToHost));
+    if (loss) HIP_TRY(hipMemcpy(loss, dl.p, 4, hipMemcpyDeviceToHost));
+    return WE_OK;
+}
+
+extern "C" we_status we_adam_step(int32_t n, float *params, float *m, float *v, const float *grad, float lr,
+                                  int32_t t) {
+    if (n < 1 || !params || !m || !v || !grad || t < 1) return we_fail(WE_EINVAL, "bad arguments");
+    DevBuf dp, dm, dv, dg;
+    HIP_TRY(dp.alloc(4ull * n));
+    HIP_TRY(dm.alloc(4ull * n));
+    HIP_TRY(dv.alloc(4ull * n));
+    HIP_TRY(dg.alloc(4ull * n));
+    HIP_TRY(hipMemcpy(dp.p, params, 4ull * n, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(dm.p, m, 4ull * n, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(dv.p, v, 4ull * n, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(dg.p, grad, 4ull * n, hipMemcpyHostToDevice));
+    hipLaunchKernelGGL(cm_adam_kernel, dim3((n + 255) / 256), dim3(256), 0, nullptr, n, dp.as<float>(), dm.as<float>(),
+                       dv.as<float>(), dg.as<float>(), lr, t);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipDeviceSynchronize());
+    HIP_TRY(hipMemcpy(params, dp.p, 4ull * n, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(m, dm.p, 4ull * n, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(v, dv.p, 4ull * n, hipMemcpyDeviceToHost));
+    return WE_OK;
+}

@@ -1,0 +1,92 @@
+// we_internal.h -- host-side structures shared by the translation units of
+// libwe.so (not part of the public interface).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/we.h"
+#include "we_common.h"
+
+we_status we_fail(we_status st, const std::string &msg);
+we_status we_hip_fail(hipError_t e, const char *what);
+
+#define HIP_TRY(expr)                                          \
+    do {                                                       \
+        hipError_t _e = (expr);                                \
+        if (_e != hipSuccess) return we_hip_fail(_e, #expr);   \
+    } while (0)
+
+struct we_network {
+    int32_t S = 0, R = 0;
+    int32_t max_order = 0;
+    int32_t max_chg = 0;
+    std::vector<RxnDesc> desc;
+    std::vector<int32_t> chg_ptr, chg, dep_ptr;
+    std::vector<uint16_t> dep;
+    RxnDesc *d_desc = nullptr;
+    int32_t *d_chg_ptr = nullptr, *d_chg = nullptr, *d_dep_ptr = nullptr;
+    uint16_t *d_dep = nullptr;
+};
+
+// The learned committor attached to a sim (see committor.hip).
+struct Committor {
+    bool trained = false;
+    bool active = false;            // bins come from q(x) instead of the grid
+    int32_t n_in = 0;               // = number of species
+    int32_t n_params = 0;
+    float *d_params = nullptr;      // [n_params] FP32
+    float *d_adam_m = nullptr, *d_adam_v = nullptr, *d_grad = nullptr;
+    float *d_feat = nullptr;        // [2*n_in] mean, 1/std of log1p(x)
+    double *d_qedges = nullptr;     // [n_qbins+1]
+    int32_t n_qbins = 0;
+};
+
+// Per-iteration ensemble records kept for committor training.
+struct Records {
+    int32_t cap_iters = 0;          // iterations that fit
+    int32_t n_iters = 0;            // iterations recorded so far
+    int32_t *d_x = nullptr;         // [cap_iters][n_runs*cap][S]
+    int32_t *d_origin = nullptr;    // [cap_iters][n_runs*cap]
+    uint8_t *d_rec = nullptr;       // [cap_iters][n_runs*cap] parent reached B this iteration
+    int32_t *d_n = nullptr;         // [cap_iters][n_runs]
+};
+
+struct we_sim {
+    const we_network *net = nullptr;
+    hipStream_t stream = nullptr;
+    SimArgs args{};
+    int32_t kernel = WE_KERNEL_LANE;
+    int32_t S = 0, NB = 0, M = 0, n_runs = 0, cap = 0, max_iters = 0;
+    double tau = 0.0;
+    int32_t iter = 0;
+    int32_t cur = 0;
+    int32_t hist_iters = 0;
+    bool owns_ws = false;
+    void *ws = nullptr;
+    int32_t *x[2] = {nullptr, nullptr};
+    double *w[2] = {nullptr, nullptr};
+    std::vector<int32_t> n_host;
+    // per-kernel timing: 4 events per profiled iteration
+    bool profiling = false;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+    double prof_ms[3] = {0.0, 0.0, 0.0};
+    int64_t prof_iters = 0;
+    // captured iterations
+    hipGraphExec_t graph_exec = nullptr;
+    hipStream_t capture_stream = nullptr;
+    int32_t graph_iters = 0;
+    bool capturing = false;
+    // committor
+    Records rec;
+    Committor cm;
+    double *d_bin_edges_grid = nullptr;
+};
+
+// committor.hip
+hipError_t committor_record(we_sim *s, hipStream_t st);
+hipError_t committor_bin(we_sim *s, int32_t *x_cur, hipStream_t st);
+void committor_free(we_sim *s);

@@ -19,8 +19,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/we.h"
-#include "we_common.h"
+#include "we_internal.h"
 
 hipError_t launch_ssa_lane(const SimArgs &a, int32_t *xs, hipStream_t st);
 bool lane_kernel_fits(int32_t S, int32_t R);
@@ -33,66 +32,19 @@ hipError_t launch_advance(const SimArgs &a, hipStream_t st);
 hipError_t launch_observe(const SimArgs &a, const int32_t *xs, const double *ws, hipStream_t st);
 
 namespace {
-
 thread_local std::string g_err;
-
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 we_status fail(we_status st, const std::string &msg) {
     g_err = msg;
     return st;
 }
-
 we_status hip_fail(hipError_t e, const char *what) {
     return fail(WE_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
 }
-
-#define HIP_TRY(expr)                                       \
-    do {                                                    \
-        hipError_t _e = (expr);                             \
-        if (_e != hipSuccess) return hip_fail(_e, #expr);   \
-    } while (0)
-
-size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
-
 }  // namespace
 
-struct we_network {
-    int32_t S = 0, R = 0;
-    int32_t max_order = 0;
-    int32_t max_chg = 0;
-    std::vector<RxnDesc> desc;
-    std::vector<int32_t> chg_ptr, chg, dep_ptr;
-    std::vector<uint16_t> dep;
-    RxnDesc *d_desc = nullptr;
-    int32_t *d_chg_ptr = nullptr, *d_chg = nullptr, *d_dep_ptr = nullptr;
-    uint16_t *d_dep = nullptr;
-};
-
-struct we_sim {
-    const we_network *net = nullptr;
-    hipStream_t stream = nullptr;
-    SimArgs args{};
-    int32_t kernel = WE_KERNEL_LANE;
-    int32_t S = 0, NB = 0, M = 0, n_runs = 0, cap = 0, max_iters = 0;
-    double tau = 0.0;
-    int32_t iter = 0;
-    int32_t cur = 0;
-    int32_t hist_iters = 0;
-    bool owns_ws = false;
-    void *ws = nullptr;
-    int32_t *x[2] = {nullptr, nullptr};
-    double *w[2] = {nullptr, nullptr};
-    std::vector<int32_t> n_host; // walker counts known on the host (before first step)
-    // per-kernel timing: 4 events per profiled iteration
-    bool profiling = false;
-    std::vector<hipEvent_t> ev_pool;
-    size_t ev_used = 0;
-    double prof_ms[3] = {0.0, 0.0, 0.0};
-    int64_t prof_iters = 0;
-    // captured iterations
-    hipGraphExec_t graph_exec = nullptr;
-    hipStream_t capture_stream = nullptr;
-    int32_t graph_iters = 0;
-};
+we_status we_fail(we_status st, const std::string &msg) { return fail(st, msg); }
+we_status we_hip_fail(hipError_t e, const char *what) { return hip_fail(e, what); }
 
 namespace {
 hipError_t next_event(we_sim *s, hipEvent_t *out) {
@@ -313,6 +265,7 @@ we_status check_params(const we_network *net, const we_grid *g, const we_params 
     if (p->kernel < WE_KERNEL_AUTO || p->kernel > WE_KERNEL_WAVE)
         return fail(WE_EINVAL, "unknown kernel");
     if (p->n_joint < 0 || p->n_joint > 5) return fail(WE_EINVAL, "n_joint must be in [0, 5]");
+    if (p->record_iters < 0) return fail(WE_EINVAL, "record_iters must be >= 0");
     if (p->n_joint > 0) {
         if (!p->joint_species || p->joint_bins < 1 || p->joint_width < 1)
             return fail(WE_EINVAL, "joint histogram needs species, bins >= 1, width >= 1");
@@ -453,6 +406,19 @@ extern "C" we_status we_init(const we_network *net, const we_grid *g, const we_p
         return hip_fail(e, "sim upload");
     }
     s->n_host = hn;
+    if (p->record_iters > 0) {
+        Records &R = s->rec;
+        R.cap_iters = p->record_iters;
+        const size_t W = (size_t)n_runs * cap;
+        hipError_t er = hipMalloc(&R.d_x, 4 * W * S * R.cap_iters);
+        if (er == hipSuccess) er = hipMalloc(&R.d_origin, 4 * W * R.cap_iters);
+        if (er == hipSuccess) er = hipMalloc(&R.d_rec, W * R.cap_iters);
+        if (er == hipSuccess) er = hipMalloc(&R.d_n, 4 * (size_t)n_runs * R.cap_iters);
+        if (er != hipSuccess) {
+            we_destroy(s);
+            return fail(WE_ENOMEM, "record buffer allocation failed");
+        }
+    }
     *out = s;
     return WE_OK;
 }
@@ -506,8 +472,12 @@ we_status launch_iteration(we_sim *s, hipStream_t st, bool profile) {
                                                  : launch_ssa_lane(a, s->x[c], st);
     if (e != hipSuccess) return hip_fail(e, "SSA launch");
     if (profile) HIP_TRY(hipEventRecord(ev[1], st));
-    e = launch_recycle_bin(a, s->x[c], true, st);
+    e = launch_recycle_bin(a, s->x[c], !s->cm.active, st);
     if (e != hipSuccess) return hip_fail(e, "recycle/bin launch");
+    if (s->cm.active) {
+        e = committor_bin(s, s->x[c], st);
+        if (e != hipSuccess) return hip_fail(e, "committor bin launch");
+    }
     e = launch_resample(a, s->x[c], s->w[c], s->x[nx], s->w[nx], st);
     if (e != hipSuccess) return hip_fail(e, "resample launch");
     if (profile) HIP_TRY(hipEventRecord(ev[2], st));
@@ -519,6 +489,10 @@ we_status launch_iteration(we_sim *s, hipStream_t st, bool profile) {
     if (e != hipSuccess) return hip_fail(e, "advance launch");
     if (profile) HIP_TRY(hipEventRecord(ev[3], st));
     s->cur = nx;
+    if (!s->capturing) {
+        e = committor_record(s, st);
+        if (e != hipSuccess) return hip_fail(e, "record launch");
+    }
     return WE_OK;
 }
 }  // namespace
@@ -545,10 +519,14 @@ extern "C" we_status we_graph_capture(we_sim *s, int32_t n) {
     }
     if (!s->capture_stream) HIP_TRY(hipStreamCreateWithFlags(&s->capture_stream, hipStreamNonBlocking));
     HIP_TRY(hipStreamSynchronize(s->stream));
+    if (s->rec.cap_iters > 0 && s->rec.n_iters < s->rec.cap_iters)
+        return fail(WE_ESTATE, "recording is active: step eagerly until the record buffer is full");
     const int32_t cur0 = s->cur;
     HIP_TRY(hipStreamBeginCapture(s->capture_stream, hipStreamCaptureModeThreadLocal));
     we_status st = WE_OK;
+    s->capturing = true;
     for (int32_t i = 0; i < n && st == WE_OK; ++i) st = launch_iteration(s, s->capture_stream, false);
+    s->capturing = false;
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(s->capture_stream, &g);
     s->cur = cur0;   // n is even: a replay leaves the buffers where they were
@@ -732,6 +710,11 @@ extern "C" void we_destroy(we_sim *s) {
     else (void)hipDeviceSynchronize();
     for (hipEvent_t e : s->ev_pool) (void)hipEventDestroy(e);
     if (s->graph_exec) (void)hipGraphExecDestroy(s->graph_exec);
+    committor_free(s);
+    (void)hipFree(s->rec.d_x);
+    (void)hipFree(s->rec.d_origin);
+    (void)hipFree(s->rec.d_rec);
+    (void)hipFree(s->rec.d_n);
     if (s->capture_stream) (void)hipStreamDestroy(s->capture_stream);
     if (s->owns_ws) (void)hipFree(s->ws);
     delete s;

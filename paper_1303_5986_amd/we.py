@@ -25,10 +25,20 @@ _STATUS = {WE_EINVAL: "EINVAL", WE_ENOMEM: "ENOMEM", WE_EDEVICE: "EDEVICE",
 
 EXPORTED = [
     "we_create_network", "we_destroy_network", "we_workspace_size", "we_init", "we_set_ensemble",
-    "we_step_intervals", "we_graph_capture", "we_graph_replay", "we_synchronize", "we_get_walkers", "we_histogram", "we_histogram_accum",
-    "we_joint_histogram", "we_flux", "we_mfpt", "we_counters", "we_events_series", "we_profile", "we_profile_read",
+    "we_step_intervals", "we_graph_capture", "we_graph_replay", "we_synchronize", "we_get_walkers",
+    "we_histogram", "we_histogram_accum", "we_joint_histogram", "we_flux", "we_mfpt",
+    "we_counters", "we_events_series", "we_profile", "we_profile_read",
+    "we_train_committor", "we_use_committor_bins", "we_committor_eval", "we_committor_state",
+    "we_record_labels", "we_get_record", "we_mlp_loss_grad", "we_adam_step",
     "we_destroy", "we_last_error",
 ]
+
+N_HIDDEN = 64
+
+
+def n_params(n_in: int) -> int:
+    """Parameters of the committor model n_in -> 64 -> 64 -> 1."""
+    return N_HIDDEN * n_in + N_HIDDEN + N_HIDDEN * N_HIDDEN + N_HIDDEN + N_HIDDEN + 1
 
 
 class WEError(RuntimeError):
@@ -47,7 +57,13 @@ class _Params(C.Structure):
                 ("x0", C.c_void_p), ("recycle", C.c_int32), ("tgt_coef", C.c_void_p),
                 ("tgt_thr", C.c_double), ("x_rec", C.c_void_p), ("hist_species", C.c_int32),
                 ("hist_lo", C.c_int32), ("hist_hi", C.c_int32), ("n_joint", C.c_int32),
-                ("joint_species", C.c_void_p), ("joint_bins", C.c_int32), ("joint_width", C.c_int32)]
+                ("joint_species", C.c_void_p), ("joint_bins", C.c_int32), ("joint_width", C.c_int32),
+                ("record_iters", C.c_int32)]
+
+
+class _TrainParams(C.Structure):
+    _fields_ = [("steps", C.c_int32), ("batch", C.c_int32), ("lr", C.c_float),
+                ("a_coef", C.c_void_p), ("a_thr", C.c_double), ("seed", C.c_uint64)]
 
 
 _LIB = None
@@ -88,6 +104,14 @@ def load_library(path: str = LIB_PATH):
     L.we_events_series.argtypes = [vp, i32, i32, vp]
     L.we_profile.argtypes = [vp, i32]
     L.we_profile_read.argtypes = [vp, P(f64), P(f64), P(f64), P(i64)]
+    L.we_train_committor.argtypes = [vp, vp, vp, P(i32)]
+    L.we_use_committor_bins.argtypes = [vp, i32]
+    L.we_committor_eval.argtypes = [vp, i32, vp, vp]
+    L.we_committor_state.argtypes = [vp, vp, vp, vp, P(i32)]
+    L.we_record_labels.argtypes = [vp, vp, f64, vp, P(i32)]
+    L.we_get_record.argtypes = [vp, i32, vp, vp, vp, vp]
+    L.we_mlp_loss_grad.argtypes = [i32, vp, vp, i32, vp, vp, vp, vp]
+    L.we_adam_step.argtypes = [i32, vp, vp, vp, vp, C.c_float, i32]
     L.we_destroy.argtypes = [vp]
     L.we_destroy.restype = None
     L.we_last_error.restype = C.c_char_p
@@ -146,7 +170,7 @@ class Sim:
                  recycle: bool = False, tgt_coef=None, tgt_thr: float = 0.0, x_rec=None,
                  hist_species: int = 0, hist_lo: int = 0, hist_hi: int = -1,
                  joint_species: Sequence[int] = (), joint_bins: int = 16, joint_width: int = 64,
-                 device=None):
+                 record_iters: int = 0, device=None):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("no HIP device: libwe.so runs on MI355X only")
@@ -177,7 +201,7 @@ class Sim:
                               _ptr(k["tgt"]), float(tgt_thr), _ptr(k["xrec"]),
                               int(hist_species), int(hist_lo), int(hist_hi),
                               len(joint_species), k["joint"].ctypes.data, int(joint_bins),
-                              int(joint_width))
+                              int(joint_width), int(record_iters))
         self.n_joint = len(joint_species)
         self.joint_cells = int(joint_bins) ** self.n_joint if self.n_joint else 0
         self.nh = hist_hi - hist_lo + 1 if hist_hi >= hist_lo else 0
@@ -268,6 +292,54 @@ class Sim:
         _check(load_library().we_events_series(self.handle, first, count, _ptr(out)))
         return out
 
+    # ------------------------------------------------------------ learned bins
+    def train_committor(self, a_coef, a_thr: float, steps: int = 2000, batch: int = 1024,
+                        lr: float = 1e-3, seed: int = 1):
+        """Train the committor on the recorded iterations; returns
+        (per-step loss, number of training states)."""
+        a = np.ascontiguousarray(a_coef, np.float64)
+        tp = _TrainParams(int(steps), int(batch), float(lr), a.ctypes.data, float(a_thr), int(seed))
+        loss = np.zeros(max(int(steps), 1), np.float32)
+        n = C.c_int32(0)
+        _check(load_library().we_train_committor(self.handle, C.byref(tp), _ptr(loss), C.byref(n)))
+        return loss[:steps], n.value
+
+    def use_committor_bins(self, enable: bool = True):
+        _check(load_library().we_use_committor_bins(self.handle, int(bool(enable))))
+
+    def committor(self, x) -> np.ndarray:
+        x = np.ascontiguousarray(x, np.int32).reshape(-1, self.S)
+        q = np.zeros(len(x), np.float32)
+        _check(load_library().we_committor_eval(self.handle, len(x), _ptr(x), _ptr(q)))
+        return q
+
+    def committor_state(self):
+        npar = n_params(self.S)
+        p = np.zeros(npar, np.float32)
+        f = np.zeros(2 * self.S, np.float32)
+        e = np.zeros(self.n_bins + 1, np.float64)
+        n = C.c_int32(0)
+        _check(load_library().we_committor_state(self.handle, _ptr(p), _ptr(f), _ptr(e), C.byref(n)))
+        return p, f, e
+
+    def record_labels(self, a_coef, a_thr: float, n_rec: int):
+        a = np.ascontiguousarray(a_coef, np.float64)
+        out = np.zeros(2 * n_rec * self.n_runs * self.cap, np.uint32)
+        n = C.c_int32(0)
+        _check(load_library().we_record_labels(self.handle, _ptr(a), float(a_thr), _ptr(out),
+                                               C.byref(n)))
+        return out.reshape(n_rec, self.n_runs, self.cap, 2)[: n.value]
+
+    def record(self, i: int):
+        W = self.n_runs * self.cap
+        n = np.zeros(self.n_runs, np.int32)
+        x = np.zeros(W * self.S, np.int32)
+        o = np.zeros(W, np.int32)
+        r = np.zeros(W, np.uint8)
+        _check(load_library().we_get_record(self.handle, i, _ptr(n), _ptr(x), _ptr(o), _ptr(r)))
+        return n, x.reshape(self.n_runs, self.cap, self.S), o.reshape(self.n_runs, self.cap), \
+            r.reshape(self.n_runs, self.cap)
+
     def profile(self, enable: bool = True):
         _check(load_library().we_profile(self.handle, int(bool(enable))))
 
@@ -296,7 +368,8 @@ class Sim:
 
 
 def sim_from_config(cfg, *, kernel: int = WE_KERNEL_AUTO, max_iters: Optional[int] = None,
-                    network: Optional[Network] = None, joint: bool = False) -> Sim:
+                    network: Optional[Network] = None, joint: bool = False,
+                    record_iters: int = 0) -> Sim:
     """Build a Sim from a workloads.WEConfig."""
     net = network if network is not None else Network(cfg.net)
     return Sim(net, cfg.bin_coef, cfg.edges, tau=cfg.tau, m_targ=cfg.m_targ, seeds=cfg.seeds,
@@ -304,4 +377,29 @@ def sim_from_config(cfg, *, kernel: int = WE_KERNEL_AUTO, max_iters: Optional[in
                kernel=kernel, recycle=cfg.recycle, tgt_coef=cfg.tgt_coef, tgt_thr=cfg.tgt_thr,
                x_rec=cfg.x_rec, hist_species=cfg.hist_species, hist_lo=cfg.hist_lo,
                hist_hi=cfg.hist_hi,
-               joint_species=getattr(cfg, "joint_species", ()) if joint else ())
+               joint_species=getattr(cfg, "joint_species", ()) if joint else (),
+               record_iters=record_iters)
+
+
+def mlp_loss_grad(n_in: int, params, feat, x, y):
+    """Loss and gradient of the committor model on one minibatch, computed by
+    the library's training kernels (default stream)."""
+    p = np.ascontiguousarray(params, np.float32)
+    f = np.ascontiguousarray(feat, np.float32)
+    xx = np.ascontiguousarray(x, np.int32).reshape(-1)
+    yy = np.ascontiguousarray(y, np.float32)
+    g = np.zeros(n_params(n_in), np.float32)
+    loss = np.zeros(1, np.float32)
+    _check(load_library().we_mlp_loss_grad(n_in, _ptr(p), _ptr(f), len(yy), _ptr(xx), _ptr(yy),
+                                           _ptr(loss), _ptr(g)))
+    return float(loss[0]), g
+
+
+def adam_step(params, m, v, grad, lr: float, t: int):
+    p = np.array(params, np.float32)
+    mm = np.array(m, np.float32)
+    vv = np.array(v, np.float32)
+    g = np.ascontiguousarray(grad, np.float32)
+    _check(load_library().we_adam_step(len(p), _ptr(p), _ptr(mm), _ptr(vv), _ptr(g), float(lr),
+                                       int(t)))
+    return p, mm, vv

@@ -328,3 +328,95 @@ def large_network_config(seed: int = 2024, n_walkers: int = 4096, n_bins: int = 
                    hist_species=bs, hist_lo=0, hist_hi=1000)
     cfg.joint_species = order[:5]
     return cfg
+
+
+# --------------------------------------------------------------------------
+# Synthetic two-gene mutual-repression toggle (8 species, 16 reactions).
+# --------------------------------------------------------------------------
+TOGGLE_SPECIES = ["G1", "G1r", "G2", "G2r", "P1", "P2", "D1", "D2"]
+
+
+def toggle_rates(seed: int) -> Dict[str, float]:
+    """Eight rate constants log-uniform on [1e-3, 10], shared by the two
+    mirror-image genes; the leak is the smaller of the two expression draws."""
+    rng = np.random.default_rng(seed)
+    r = np.exp(rng.uniform(np.log(1e-3), np.log(1e1), 8))
+    ke, kl, kp, kd, ku, kb, kub, kdd = (float(v) for v in r)
+    if kl > ke:
+        ke, kl = kl, ke
+    return dict(ke=ke, kl=kl, kp=kp, kd=kd, ku=ku, kb=kb, kub=kub, kdd=kdd)
+
+
+def toggle(p: Dict[str, float]) -> Network:
+    """Expression G -> G + P, leak Gr -> Gr + P, P -> 0, 2P -> D, D -> 2P,
+    promoter binding G1 + D2 -> G1r (and mirror), unbinding, D -> 0."""
+    R = [({"G1": 1}, {"G1": 1, "P1": 1}, p["ke"]), ({"G2": 1}, {"G2": 1, "P2": 1}, p["ke"]),
+         ({"G1r": 1}, {"G1r": 1, "P1": 1}, p["kl"]), ({"G2r": 1}, {"G2r": 1, "P2": 1}, p["kl"]),
+         ({"P1": 1}, {}, p["kp"]), ({"P2": 1}, {}, p["kp"]),
+         ({"P1": 2}, {"D1": 1}, p["kd"]), ({"P2": 2}, {"D2": 1}, p["kd"]),
+         ({"D1": 1}, {"P1": 2}, p["ku"]), ({"D2": 1}, {"P2": 2}, p["ku"]),
+         ({"G1": 1, "D2": 1}, {"G1r": 1}, p["kb"]), ({"G2": 1, "D1": 1}, {"G2r": 1}, p["kb"]),
+         ({"G1r": 1}, {"G1": 1, "D2": 1}, p["kub"]), ({"G2r": 1}, {"G2": 1, "D1": 1}, p["kub"]),
+         ({"D1": 1}, {}, p["kdd"]), ({"D2": 1}, {}, p["kdd"])]
+    return Network.from_reactions(TOGGLE_SPECIES, R)
+
+
+def _toggle_rre_states(p: Dict[str, float]):
+    """Steady states of the reaction-rate equations reached from gene-1-on and
+    gene-2-on starts (gene occupancies as fractions)."""
+    from scipy.integrate import solve_ivp
+
+    def rhs(t, y):
+        G1r, G2r, P1, P2, D1, D2 = y
+        G1, G2 = 1 - G1r, 1 - G2r
+        return [p["kb"] * G1 * D2 - p["kub"] * G1r,
+                p["kb"] * G2 * D1 - p["kub"] * G2r,
+                p["ke"] * G1 + p["kl"] * G1r - p["kp"] * P1 - p["kd"] * P1 * P1 + 2 * p["ku"] * D1,
+                p["ke"] * G2 + p["kl"] * G2r - p["kp"] * P2 - p["kd"] * P2 * P2 + 2 * p["ku"] * D2,
+                p["kd"] * P1 * P1 / 2 - (p["ku"] + p["kdd"]) * D1 - p["kb"] * G2 * D1 + p["kub"] * G2r,
+                p["kd"] * P2 * P2 / 2 - (p["ku"] + p["kdd"]) * D2 - p["kb"] * G1 * D2 + p["kub"] * G1r]
+
+    out = []
+    for y0 in ([0, 1, 50, 0, 50, 0], [1, 0, 0, 50, 0, 50]):
+        s = solve_ivp(rhs, (0, 2e4), y0, method="LSODA", rtol=1e-8, atol=1e-10)
+        out.append(s.y[:, -1])
+    return out   # [gene-1-on state, gene-2-on state]
+
+
+def toggle_accepts(p: Dict[str, float]) -> bool:
+    """Two distinct stable states (mirror images, |Delta| > 20 where
+    Delta = (P1 + 2 D1) - (P2 + 2 D2)) with every count at most 500."""
+    b, a = _toggle_rre_states(p)
+    da = (a[2] + 2 * a[4]) - (a[3] + 2 * a[5])
+    db = (b[2] + 2 * b[4]) - (b[3] + 2 * b[5])
+    return da < -20 and db > 20 and max(a[2:].max(), b[2:].max()) <= 500
+
+
+def toggle_config(seed0: int = 100, n_runs: int = 16, n_bins: int = 64, m_targ: int = 16,
+                  n_iters: int = 500, tau: float = 0.7) -> WEConfig:
+    """The first seed >= seed0 whose rates pass toggle_accepts (seed 101 for
+    seed0 = 100).  A = the rounded gene-2-on steady state (walkers restart
+    there), B = {Delta >= 0.8 Delta_B*} with Delta_B* the gene-1-on value;
+    64 plain bins on Delta over [Delta_A - 8, threshold); tau = 0.7, about
+    10 / a0 at A (a0(A) = 14.85 for seed 101: ten reactions per walker and
+    interval)."""
+    seed = seed0
+    while not toggle_accepts(toggle_rates(seed)):
+        seed += 1
+    p = toggle_rates(seed)
+    b, a = _toggle_rre_states(p)
+    xA = np.array([round(1 - a[0]), round(a[0]), round(1 - a[1]), round(a[1]),
+                   round(a[2]), round(a[3]), round(a[4]), round(a[5])], np.int32)
+    dB = (b[2] + 2 * b[4]) - (b[3] + 2 * b[5])
+    thr = float(np.floor(0.8 * dB))
+    coef = np.array([0, 0, 0, 0, 1, -1, 2, -2], np.float64)
+    dA = float(coef @ xA)
+    net = toggle(p)
+    cfg = WEConfig(name="toggle", net=net, x0=xA, bin_coef=coef,
+                   edges=uniform_edges(dA - 8.0, thr, n_bins), m_targ=m_targ, tau=tau,
+                   n_iters=n_iters, seeds=np.arange(1, n_runs + 1, dtype=np.uint64),
+                   recycle=True, tgt_coef=coef.copy(), tgt_thr=thr, x_rec=xA.copy(),
+                   hist_species=4, hist_lo=0, hist_hi=200)
+    cfg.toggle_seed = seed
+    cfg.a_thr = -thr          # A region for committor labels: Delta <= -thr
+    return cfg

@@ -1,0 +1,140 @@
+"""GPU parity of the learned-committor pieces: FP32 gradient and Adam kernels
+against the FP64 reference, lineage labels against the oracle's, training and
+binning on the toggle model."""
+import numpy as np
+import pytest
+from scipy import stats
+
+from oracle import lineage, mlp
+from oracle import oracle as orc
+from paper_1303_5986_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def _we():
+    from paper_1303_5986_amd import we
+    return we
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+@pytest.mark.parametrize("n_in,B", [(8, 1024), (354, 256)])
+def test_gradient_matches_fp64_reference(n_in, B):
+    """One minibatch through the training kernels (FP32) against the FP64
+    chain rule: loss to 1e-5 relative, gradient to 1e-4 of its norm."""
+    _say(f"case: MLP loss/grad n_in={n_in} B={B}")
+    we = _we()
+    rng = np.random.default_rng(n_in)
+    npar = we.n_params(n_in)
+    p = rng.normal(0, 0.15, npar).astype(np.float32)
+    feat = np.concatenate([rng.uniform(0.5, 3.0, n_in), rng.uniform(0.3, 1.5, n_in)]).astype(np.float32)
+    x = rng.integers(0, 80, size=(B, n_in)).astype(np.int32)
+    y = rng.uniform(0, 1, B).astype(np.float32)
+    L, g = we.mlp_loss_grad(n_in, p, feat, x, y)
+    Lr, gr = mlp.loss_grad(p.astype(np.float64), feat.astype(np.float64), x, y.astype(np.float64), n_in)
+    assert abs(L - Lr) <= 1e-5 * abs(Lr)
+    err = np.linalg.norm(g - gr) / np.linalg.norm(gr)
+    _say(f"   loss {L:.6f} vs {Lr:.6f}; gradient relative error {err:.2e}")
+    assert err <= 1e-4
+    assert np.all(np.abs(g - gr) <= 1e-4 * np.abs(gr).max() + 1e-3 * np.abs(gr))
+
+
+def test_adam_matches_fp64_reference():
+    we = _we()
+    rng = np.random.default_rng(9)
+    n = 5000
+    p = rng.normal(size=n).astype(np.float32)
+    m = (rng.normal(size=n) * 1e-2).astype(np.float32)
+    v = (rng.uniform(size=n) * 1e-4).astype(np.float32)
+    g = (rng.normal(size=n) * 1e-2).astype(np.float32)
+    q, mq, vq = we.adam_step(p, m, v, g, 1e-3, 5)
+    qr, mr, vr = mlp.adam(p.astype(np.float64), m.astype(np.float64), v.astype(np.float64),
+                          g.astype(np.float64), 1e-3, 5)
+    assert np.allclose(mq, mr, rtol=1e-5, atol=1e-9)
+    assert np.allclose(vq, vr, rtol=1e-5, atol=1e-12)
+    assert np.allclose(q, qr, rtol=1e-5, atol=1e-6)
+
+
+def _toggle_small(n_runs=2, n_bins=16, m_targ=4, n_iters=40):
+    cfg = wl.toggle_config(n_runs=n_runs, n_bins=n_bins, m_targ=m_targ, n_iters=n_iters)
+    return cfg
+
+
+def test_lineage_labels_match_oracle():
+    """Records of a lane-path run equal the oracle's ensembles, and the
+    device's reverse-pass outcome counts equal the oracle lineage labels
+    computed from the oracle's own ensembles."""
+    _say("case: lineage labels, toggle 2 runs x 40 iterations")
+    we = _we()
+    cfg = _toggle_small()
+    T = 40
+    sim = we.sim_from_config(cfg, kernel=we.WE_KERNEL_LANE, max_iters=T, record_iters=T)
+    ors = [orc.OracleWE(cfg, int(s)) for s in cfg.seeds]
+    recs = []
+    S, cap, R = cfg.net.S, cfg.cap, len(cfg.seeds)
+    for it in range(T):
+        sim.step(1)
+        n = np.zeros(R, np.int32)
+        x = np.zeros((R, cap, S), np.int32)
+        o = np.zeros((R, cap), np.int32)
+        rc = np.zeros((R, cap), np.uint8)
+        for r, orr in enumerate(ors):
+            orr.step(1)
+            ox, ow, ob, oo = orr.walkers()
+            n[r] = len(ow)
+            x[r, :n[r]] = ox
+            o[r, :n[r]] = oo
+            rc[r, :n[r]] = orr.child_recycled()
+        recs.append((n, x, o, rc))
+        gn, gx, go, grc = sim.record(it)
+        assert np.array_equal(gn, n)
+        for r in range(R):
+            k = n[r]
+            assert np.array_equal(gx[r, :k], x[r, :k])
+            assert np.array_equal(go[r, :k], o[r, :k])
+            assert np.array_equal(grc[r, :k], rc[r, :k])
+    ref = lineage.label_counts(recs, cfg.bin_coef, cfg.a_thr)
+    got = sim.record_labels(cfg.bin_coef, cfg.a_thr, T)
+    for i in range(T):
+        for r in range(R):
+            k = recs[i][0][r]
+            assert np.array_equal(got[i, r, :k], ref[i, r, :k]), (i, r)
+    assert ref.sum() > 0
+
+
+def test_training_learns_a_committor_and_bins_on_it():
+    """Train on 120 recorded iterations of the toggle (4 runs x 64 bins x 16):
+    the loss falls, q rises with the hand-chosen coordinate Delta (Spearman >
+    0.6), the quantile edges increase, and WE keeps running on learned bins
+    with the total weight of every run equal to one."""
+    _say("case: committor training on the toggle")
+    we = _we()
+    cfg = wl.toggle_config(n_runs=4, n_iters=200)
+    sim = we.sim_from_config(cfg, kernel=we.WE_KERNEL_LANE, max_iters=200, record_iters=120)
+    sim.step(120)
+    loss, n = sim.train_committor(cfg.bin_coef, cfg.a_thr, steps=600, batch=1024, lr=2e-3, seed=5)
+    _say(f"   {n} training states; loss {loss[:10].mean():.4f} -> {loss[-50:].mean():.4f}")
+    assert n > 1000
+    assert loss[-50:].mean() < 0.9 * loss[:10].mean()
+    p, feat, edges = sim.committor_state()
+    assert np.all(np.diff(edges) > 0)
+    rng = np.random.default_rng(0)
+    xs = []
+    for r in range(4):
+        x, w, b, o = sim.walkers(r)
+        xs.append(x)
+    X = np.concatenate(xs)
+    q = sim.committor(X)
+    delta = X @ cfg.bin_coef
+    rho = stats.spearmanr(q, delta).correlation
+    _say(f"   Spearman(q, Delta) = {rho:.3f}")
+    assert rho > 0.6
+    sim.use_committor_bins(True)
+    sim.step(40)
+    for r in range(4):
+        x, w, b, o = sim.walkers(r)
+        assert abs(w.sum() - 1.0) < 1e-12
+        assert b.min() >= 0 and b.max() < cfg.n_bins
