@@ -94,6 +94,113 @@ def cpu_baseline(cfg, n_runs: int, n_iters: int):
     return ev / dt, dt, ev
 
 
+def _rel_err_curve(flux, tau, burn, ref):
+    """Running MFPT of every run (tau / mean recycled weight over iterations
+    [burn, t]) and the RMS relative error against ref, for every t > burn."""
+    f = np.asarray(flux, np.float64)[:, burn:]
+    csum = np.cumsum(f, axis=1)
+    n = np.arange(1, f.shape[1] + 1)
+    mean = csum / n
+    with np.errstate(divide="ignore"):
+        mfpt = np.where(mean > 0, tau / mean, np.inf)
+    err = np.sqrt(np.mean((mfpt / ref - 1.0) ** 2, axis=0))
+    return err
+
+
+def _time_to(err, times, thr):
+    """First time after which the error stays at or below thr."""
+    ok = err <= thr
+    if not ok[-1]:
+        return None
+    bad = np.flatnonzero(~ok)
+    first = 0 if bad.size == 0 else bad[-1] + 1
+    return float(times[first])
+
+
+def experiment_toggle_mfpt(args):
+    """GPU-seconds until 16 replicas' MFPT estimates stay within a relative
+    error of the reference, plain Delta bins vs learned committor bins, on
+    the synthetic toggle.  The learned time includes its plain-bin record
+    phase and the training."""
+    import torch
+    from paper_1303_5986_amd import we, workloads as wl
+
+    chunk = 10
+    total = args.exp_iters
+    burn = 100
+    base = wl.toggle_config(n_runs=16, n_iters=total)
+    tau = base.tau
+
+    # reference: brute force = one bin, 1024 walkers per run x 64 runs, recycling
+    ref_iters = args.ref_iters
+    bf = wl.WEConfig(**{**base.__dict__, "edges": np.array([-1e9, 1e9]), "m_targ": 1024,
+                        "seeds": np.arange(1001, 1065, dtype=np.uint64)})
+    simb = we.sim_from_config(bf, kernel=we.WE_KERNEL_LANE, max_iters=ref_iters)
+    simb.graph_capture(20)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    simb.graph_replay(ref_iters // 20)
+    simb.synchronize()
+    t_ref = time.perf_counter() - t0
+    ref_mfpt, ref_flux, ref_sem = simb.mfpt(200)
+    ev_ref = simb.counters()[0]
+
+    def run(learned: bool):
+        sim = we.sim_from_config(base, kernel=we.WE_KERNEL_LANE, max_iters=total,
+                                 record_iters=args.record_iters if learned else 0)
+        times, iters = [], []
+        gpu = 0.0
+        done = 0
+        train_s = 0.0
+        if learned:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sim.step(args.record_iters)
+            sim.synchronize()
+            gpu += time.perf_counter() - t0
+            done = args.record_iters
+            times.append(gpu)
+            iters.append(done)
+            t0 = time.perf_counter()
+            loss, n = sim.train_committor(base.bin_coef, base.a_thr, steps=args.train_steps,
+                                          batch=1024, lr=2e-3, seed=7)
+            sim.use_committor_bins(True)
+            train_s = time.perf_counter() - t0
+            gpu += train_s
+        sim.graph_capture(chunk)
+        while done + chunk <= total:
+            t0 = time.perf_counter()
+            sim.graph_replay(1)
+            sim.synchronize()
+            gpu += time.perf_counter() - t0
+            done += chunk
+            times.append(gpu)
+            iters.append(done)
+        flux = np.stack([sim.flux(r, 0, done) for r in range(base.seeds.size)])
+        err = _rel_err_curve(flux, tau, burn, ref_mfpt)
+        at = np.array(iters) - burn - 1
+        keep = at >= 0
+        err_at = err[at[keep]]
+        tt = np.array(times)[keep]
+        res = {"gpu_s_total": gpu, "iterations": done, "train_s": train_s,
+               "final_rel_err": float(err_at[-1]),
+               "mfpt_mean": float(np.mean(tau / flux[:, burn:].mean(axis=1)))}
+        for thr in (0.05, 0.1, 0.2):
+            res[f"gpu_s_to_{int(thr * 100)}pct"] = _time_to(err_at, tt, thr)
+        return res
+
+    plain = run(False)
+    learned = run(True)
+    out = {"metric": "GPU-seconds to MFPT rel-err 5%, learned vs plain bins",
+           "workload": "toggle (seed 101), 16 replicas x 64 bins x 16 walkers, tau 0.7",
+           "reference": {"mfpt": ref_mfpt, "sem_rel": ref_sem / ref_flux, "kind":
+                         "GPU brute force: 64 runs x 1024 walkers in one bin, recycling",
+                         "iterations": ref_iters, "gpu_s": t_ref, "events": ev_ref},
+           "burn_in_iterations": burn, "plain": plain, "learned": learned,
+           "record_iters": args.record_iters, "train_steps": args.train_steps}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -106,7 +213,15 @@ def main():
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB five times "
                          "(reference kernel for scaling the HBM byte counters)")
+    ap.add_argument("--experiment", default="", choices=["", "toggle_mfpt"])
+    ap.add_argument("--exp-iters", type=int, default=4000)
+    ap.add_argument("--ref-iters", type=int, default=4000)
+    ap.add_argument("--record-iters", type=int, default=150)
+    ap.add_argument("--train-steps", type=int, default=600)
     args = ap.parse_args()
+    if args.experiment == "toggle_mfpt":
+        experiment_toggle_mfpt(args)
+        return
     if args.calibrate_copy:
         import torch
         n = args.calibrate_copy * (1 << 20) // 4

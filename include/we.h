@@ -215,7 +215,8 @@ WE_API we_status we_events_series(we_sim *s, int32_t first, int32_t count, int64
  * (log1p(x_s) - mean_s)/std_s; binary cross-entropy on soft labels; Adam.
  * Parameters are one FP32 array: W1[64][S], b1[64], W2[64][64], b2[64],
  * W3[64], b3[1].  The learned bins are the sim's n_bins equal-count
- * quantiles of q over the training states. */
+ * quantiles of q over the training states, stored as edges on the logit
+ * z = log(q / (1 - q)) (the same partition; the logit resolves q near 0). */
 typedef struct {
     int32_t steps;             /* Adam steps                                        */
     int32_t batch;             /* minibatch size, a positive multiple of 256        */
@@ -240,7 +241,7 @@ WE_API we_status we_use_committor_bins(we_sim *s, int32_t enable);
 WE_API we_status we_committor_eval(we_sim *s, int32_t n, const int32_t *x, float *q);
 
 /* Copy the trained model: params[n_params], feat[2*S] (mean, 1/std),
- * qedges[n_bins+1]; any pointer may be NULL.  Synchronous. */
+ * qedges[n_bins+1] (logit edges); any pointer may be NULL.  Synchronous. */
 WE_API we_status we_committor_state(we_sim *s, float *params, float *feat, double *qedges,
                                     int32_t *n_params);
 

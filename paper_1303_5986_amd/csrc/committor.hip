@@ -24,9 +24,12 @@
 //     Forward/backward is one lane per sample; each parameter's gradient is
 //     summed over the minibatch by one lane in sample order, so a training
 //     run is reproducible;
-//  6. bins: n_bins equal-count quantile edges of q over the dataset (a
-//     65536-cell integer histogram of q); with the committor active, every
-//     walker's bin is bin_index(edges, q(x)) after recycling.
+//  6. bins: n_bins equal-count quantile edges over the dataset, taken on
+//     the logit z = log(q/(1-q)) (quantiles do not change under a monotone
+//     map, and the logit resolves the q ~ 1e-10 values near A that FP32 q
+//     cannot); a 65536-cell integer histogram over z in [-40, 40]; with the
+//     committor active every walker's bin is bin_index(edges, z(x)) after
+//     recycling.
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -58,8 +61,8 @@ __device__ __forceinline__ float feature(int32_t x, const float *feat, int32_t k
     return (log1pf((float)x) - feat[k]) * feat[n_in + k];
 }
 
-// q(x) for one state row; phi is recomputed on the fly.
-__device__ float mlp_q(const ParamView &P, const float *feat, const int32_t *xr, int32_t n_in) {
+// logit z(x) of the committor, q = 1 / (1 + e^-z); phi recomputed on the fly.
+__device__ float mlp_z(const ParamView &P, const float *feat, const int32_t *xr, int32_t n_in) {
     float h1[CM_H];
 #pragma unroll
     for (int j = 0; j < CM_H; ++j) h1[j] = P.b1[j];
@@ -77,7 +80,14 @@ __device__ float mlp_q(const ParamView &P, const float *feat, const int32_t *xr,
         for (int j = 0; j < CM_H; ++j) z = fmaf(P.W2[i * CM_H + j], h1[j], z);
         z3 = fmaf(P.W3[i], tanhf(z), z3);
     }
-    return 1.0f / (1.0f + expf(-z3));
+    return z3;
+}
+
+// Quantile histogram cell of a logit: 65536 cells over [-Z_SPAN, Z_SPAN].
+#define Z_SPAN 40.0f
+__device__ __forceinline__ int32_t z_cell(float z) {
+    int32_t c = (int32_t)((z + Z_SPAN) * ((float)Q_HIST / (2.0f * Z_SPAN)));
+    return c < 0 ? 0 : (c >= Q_HIST ? Q_HIST - 1 : c);
 }
 
 // ------------------------------------------------------------------ records
@@ -374,31 +384,31 @@ __global__ __launch_bounds__(256) void cm_eval_kernel(const float *__restrict__ 
     if (i >= n) return;
     const ParamView P = cm_view(params, n_in);
     const int32_t *xr = ds_idx ? rx + ds_idx[i] * n_in : rx + (size_t)i * n_in;
-    const float q = mlp_q(P, feat, xr, n_in);
-    if (q_out) q_out[i] = q;
-    if (qhist) {
-        int32_t c = (int32_t)(q * (float)Q_HIST);
-        c = c < 0 ? 0 : (c >= Q_HIST ? Q_HIST - 1 : c);
-        atomicAdd(&qhist[c], 1u);
-    }
+    const float z = mlp_z(P, feat, xr, n_in);
+    if (q_out) q_out[i] = 1.0f / (1.0f + expf(-z));
+    if (qhist) atomicAdd(&qhist[z_cell(z)], 1u);
 }
 
+// Equal-count edges in logit space: edge b is the upper end of the cell where
+// the cumulative count first reaches b*n/nb; edges stay strictly increasing.
 __global__ void cm_edges_kernel(const uint32_t *__restrict__ qhist, int32_t n, int32_t nb, double *__restrict__ edges) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    edges[0] = 0.0;
+    const double cell = 2.0 * (double)Z_SPAN / (double)Q_HIST;
+    const double nudge = cell / 64.0;
+    edges[0] = -(double)Z_SPAN;
     int64_t cum = 0;
-    int32_t b = 1, c = 0;
-    for (; c < Q_HIST && b < nb; ++c) {
+    int32_t b = 1;
+    for (int32_t c = 0; c < Q_HIST && b < nb; ++c) {
         cum += qhist[c];
         while (b < nb && cum * nb >= (int64_t)b * n) {
-            double e = (double)(c + 1) / (double)Q_HIST;
-            if (e <= edges[b - 1]) e = edges[b - 1] + 1.0 / (4.0 * Q_HIST);
+            double e = -(double)Z_SPAN + (double)(c + 1) * cell;
+            if (e <= edges[b - 1]) e = edges[b - 1] + nudge;
             edges[b] = e;
             ++b;
         }
     }
-    for (; b < nb; ++b) edges[b] = edges[b - 1] + 1.0 / (4.0 * Q_HIST);
-    edges[nb] = edges[nb - 1] > 1.0 ? edges[nb - 1] + 1.0 : 1.0 + 1.0 / Q_HIST;
+    for (; b < nb; ++b) edges[b] = edges[b - 1] + nudge;
+    edges[nb] = edges[nb - 1] + (double)Z_SPAN;
 }
 
 __global__ __launch_bounds__(256) void cm_bin_kernel(SimArgs a, const int32_t *__restrict__ x_cur,
@@ -411,8 +421,8 @@ __global__ __launch_bounds__(256) void cm_bin_kernel(SimArgs a, const int32_t *_
     if (k >= a.n_walk[run]) return;
     const size_t idx = (size_t)run * a.cap + k;
     const ParamView P = cm_view(params, a.S);
-    const float q = mlp_q(P, feat, x_cur + idx * a.S, a.S);
-    a.s_bin[idx] = bin_index(qedges, a.n_bins, (double)q);
+    const float z = mlp_z(P, feat, x_cur + idx * a.S, a.S);
+    a.s_bin[idx] = bin_index(qedges, a.n_bins, (double)z);
 }
 
 hipError_t committor_bin(we_sim *s, int32_t *x_cur, hipStream_t st) {
