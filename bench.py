@@ -122,6 +122,8 @@ def experiment_toggle_mfpt(args):
     error of the reference, plain Delta bins vs learned committor bins, on
     the synthetic toggle.  The learned time includes its plain-bin record
     phase and the training."""
+    import dataclasses
+
     import torch
     from paper_1303_5986_amd import we, workloads as wl
 
@@ -129,12 +131,18 @@ def experiment_toggle_mfpt(args):
     total = args.exp_iters
     burn = 100
     base = wl.toggle_config(n_runs=16, n_iters=total)
+    if args.plain_coord == "total1":
+        # a single product coordinate: all protein of gene 1, P1 + 2 D1
+        coef = np.array([0, 0, 0, 0, 1, 0, 2, 0], np.float64)
+        base = dataclasses.replace(base, bin_coef=coef,
+                                   edges=wl.uniform_edges(-0.5, 48.0, base.n_bins))
+        base.a_thr = -base.tgt_thr
     tau = base.tau
 
     # reference: brute force = one bin, 1024 walkers per run x 64 runs, recycling
     ref_iters = args.ref_iters
-    bf = wl.WEConfig(**{**base.__dict__, "edges": np.array([-1e9, 1e9]), "m_targ": 1024,
-                        "seeds": np.arange(1001, 1065, dtype=np.uint64)})
+    bf = dataclasses.replace(base, edges=np.array([-1e9, 1e9]), m_targ=1024,
+                             seeds=np.arange(1001, 1065, dtype=np.uint64))
     simb = we.sim_from_config(bf, kernel=we.WE_KERNEL_LANE, max_iters=ref_iters)
     simb.graph_capture(20)
     torch.cuda.synchronize()
@@ -145,9 +153,9 @@ def experiment_toggle_mfpt(args):
     ref_mfpt, ref_flux, ref_sem = simb.mfpt(200)
     ev_ref = simb.counters()[0]
 
-    def run(learned: bool):
+    def run(learned: bool, edge_mode: int = 0, record_iters: int = 150, train_steps: int = 600):
         sim = we.sim_from_config(base, kernel=we.WE_KERNEL_LANE, max_iters=total,
-                                 record_iters=args.record_iters if learned else 0)
+                                 record_iters=record_iters if learned else 0)
         times, iters = [], []
         gpu = 0.0
         done = 0
@@ -155,18 +163,20 @@ def experiment_toggle_mfpt(args):
         if learned:
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            sim.step(args.record_iters)
+            sim.step(record_iters)
             sim.synchronize()
             gpu += time.perf_counter() - t0
-            done = args.record_iters
+            done = record_iters
             times.append(gpu)
             iters.append(done)
             t0 = time.perf_counter()
-            loss, n = sim.train_committor(base.bin_coef, base.a_thr, steps=args.train_steps,
-                                          batch=1024, lr=2e-3, seed=7)
+            loss, n = sim.train_committor(np.array([0, 0, 0, 0, 1, -1, 2, -2.0]), -base.tgt_thr,
+                                          steps=train_steps,
+                                          batch=1024, lr=2e-3, seed=7, edge_mode=edge_mode)
             sim.use_committor_bins(True)
             train_s = time.perf_counter() - t0
             gpu += train_s
+            _, _, edges = sim.committor_state()
         sim.graph_capture(chunk)
         while done + chunk <= total:
             t0 = time.perf_counter()
@@ -184,20 +194,37 @@ def experiment_toggle_mfpt(args):
         tt = np.array(times)[keep]
         res = {"gpu_s_total": gpu, "iterations": done, "train_s": train_s,
                "final_rel_err": float(err_at[-1]),
-               "mfpt_mean": float(np.mean(tau / flux[:, burn:].mean(axis=1)))}
+               "mfpt_mean": float(np.mean(tau / flux[:, burn:].mean(axis=1))),
+               "mfpt_runs_rel": [round(float(v), 3) for v in
+                                 (tau / flux[:, burn:].mean(axis=1)) / ref_mfpt]}
+        if learned:
+            res.update(edge_mode=edge_mode, record_iters=record_iters, train_steps=train_steps,
+                       train_states=n, loss_first=float(loss[:10].mean()),
+                       loss_last=float(loss[-50:].mean()),
+                       edges=[round(float(v), 2) for v in edges[1:-1:8]])
+            occ = []
+            for r in range(2):
+                _, _, b, _ = sim.walkers(r)
+                occ.append(int(len(set(b.tolist()))))
+            res["occupied_bins"] = occ
         for thr in (0.05, 0.1, 0.2):
             res[f"gpu_s_to_{int(thr * 100)}pct"] = _time_to(err_at, tt, thr)
         return res
 
     plain = run(False)
-    learned = run(True)
+    variants = []
+    for spec in args.variants.split(","):
+        em, ri, ts = (int(v) for v in spec.split(":"))
+        variants.append(run(True, em, ri, ts))
+    learned = variants[0]
     out = {"metric": "GPU-seconds to MFPT rel-err 5%, learned vs plain bins",
            "workload": "toggle (seed 101), 16 replicas x 64 bins x 16 walkers, tau 0.7",
+           "plain_coordinate": args.plain_coord,
            "reference": {"mfpt": ref_mfpt, "sem_rel": ref_sem / ref_flux, "kind":
                          "GPU brute force: 64 runs x 1024 walkers in one bin, recycling",
                          "iterations": ref_iters, "gpu_s": t_ref, "events": ev_ref},
            "burn_in_iterations": burn, "plain": plain, "learned": learned,
-           "record_iters": args.record_iters, "train_steps": args.train_steps}
+           "learned_variants": variants[1:]}
     print(json.dumps(out), flush=True)
 
 
@@ -216,8 +243,11 @@ def main():
     ap.add_argument("--experiment", default="", choices=["", "toggle_mfpt"])
     ap.add_argument("--exp-iters", type=int, default=4000)
     ap.add_argument("--ref-iters", type=int, default=4000)
-    ap.add_argument("--record-iters", type=int, default=150)
-    ap.add_argument("--train-steps", type=int, default=600)
+    ap.add_argument("--plain-coord", default="delta", choices=["delta", "total1"],
+                    help="hand-chosen bin coordinate: Delta = (P1+2D1)-(P2+2D2), or P1+2D1")
+    ap.add_argument("--variants", default="1:150:600",
+                    help="learned-bin runs as edge_mode:record_iters:train_steps, comma separated; "
+                         "the first is the reported one")
     args = ap.parse_args()
     if args.experiment == "toggle_mfpt":
         experiment_toggle_mfpt(args)

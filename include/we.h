@@ -214,9 +214,9 @@ WE_API we_status we_events_series(we_sim *s, int32_t first, int32_t count, int64
  * Model: n_species -> 64 -> 64 -> 1 (tanh, tanh, sigmoid), FP32, inputs
  * (log1p(x_s) - mean_s)/std_s; binary cross-entropy on soft labels; Adam.
  * Parameters are one FP32 array: W1[64][S], b1[64], W2[64][64], b2[64],
- * W3[64], b3[1].  The learned bins are the sim's n_bins equal-count
- * quantiles of q over the training states, stored as edges on the logit
- * z = log(q / (1 - q)) (the same partition; the logit resolves q near 0). */
+ * W3[64], b3[1].  The learned bins partition the logit
+ * z = log(q / (1 - q)) (which resolves q near 0): equal-count quantiles of
+ * the training states, or equal widths (edge_mode below). */
 typedef struct {
     int32_t steps;             /* Adam steps                                        */
     int32_t batch;             /* minibatch size, a positive multiple of 256        */
@@ -224,6 +224,9 @@ typedef struct {
     const double *a_coef;      /* [S] A = { x : sum a_coef_s x_s <= a_thr }          */
     double a_thr;
     uint64_t seed;             /* weight initialisation and minibatch draws         */
+    int32_t edge_mode;         /* 0: n_bins equal-count quantiles of q over the     */
+                               /*    training states; 1: n_bins equal widths in     */
+                               /*    the logit between its 0.5% and 99.5% quantiles  */
 } we_train_params;
 
 /* Label the recorded walkers by their descendants' first outcome (B: the

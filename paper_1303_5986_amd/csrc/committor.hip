@@ -391,11 +391,27 @@ __global__ __launch_bounds__(256) void cm_eval_kernel(const float *__restrict__ 
 
 // Equal-count edges in logit space: edge b is the upper end of the cell where
 // the cumulative count first reaches b*n/nb; edges stay strictly increasing.
-__global__ void cm_edges_kernel(const uint32_t *__restrict__ qhist, int32_t n, int32_t nb, double *__restrict__ edges) {
+__global__ void cm_edges_kernel(const uint32_t *__restrict__ qhist, int32_t n, int32_t nb, double *__restrict__ edges,
+                                int32_t mode) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     const double cell = 2.0 * (double)Z_SPAN / (double)Q_HIST;
     const double nudge = cell / 64.0;
     edges[0] = -(double)Z_SPAN;
+    if (mode == 1) {
+        // uniform in the logit between the 0.5% and 99.5% quantiles of the data
+        int64_t cum = 0;
+        double zlo = -(double)Z_SPAN, zhi = (double)Z_SPAN;
+        bool have_lo = false;
+        for (int32_t c = 0; c < Q_HIST; ++c) {
+            cum += qhist[c];
+            if (!have_lo && cum * 200 >= (int64_t)n) { zlo = -(double)Z_SPAN + c * cell; have_lo = true; }
+            if (cum * 200 >= (int64_t)n * 199) { zhi = -(double)Z_SPAN + (c + 1) * cell; break; }
+        }
+        if (!(zhi > zlo)) zhi = zlo + cell;
+        for (int32_t b = 1; b < nb; ++b) edges[b] = zlo + (zhi - zlo) * (double)b / (double)nb;
+        edges[nb] = edges[nb - 1] + (double)Z_SPAN;
+        return;
+    }
     int64_t cum = 0;
     int32_t b = 1;
     for (int32_t c = 0; c < Q_HIST && b < nb; ++c) {
@@ -526,6 +542,7 @@ extern "C" we_status we_train_committor(we_sim *s, const we_train_params *tp, fl
     if (s->rec.cap_iters <= 0 || s->rec.n_iters < 2) return we_fail(WE_ESTATE, "need at least two recorded iterations");
     if (tp->steps < 0 || tp->batch <= 0 || tp->batch % 256 || !(tp->lr > 0.0f))
         return we_fail(WE_EINVAL, "steps >= 0, batch a positive multiple of 256, lr > 0");
+    if (tp->edge_mode < 0 || tp->edge_mode > 1) return we_fail(WE_EINVAL, "edge_mode must be 0 or 1");
     const int32_t n_in = s->S;
     if (n_in > 1024) return we_fail(WE_EINVAL, "committor supports up to 1024 species");
     Records &R = s->rec;
@@ -604,7 +621,7 @@ extern "C" we_status we_train_committor(we_sim *s, const we_train_params *tp, fl
                        n_ds, ds_idx.as<int64_t>(), R.d_x, (float *)nullptr, qhist.as<uint32_t>());
     HIP_TRY(hipGetLastError());
     hipLaunchKernelGGL(cm_edges_kernel, dim3(1), dim3(64), 0, s->stream, qhist.as<uint32_t>(), n_ds, C.n_qbins,
-                       C.d_qedges);
+                       C.d_qedges, tp->edge_mode);
     HIP_TRY(hipGetLastError());
     if (loss_out && tp->steps > 0)
         HIP_TRY(hipMemcpyAsync(loss_out, dloss.p, 4ull * tp->steps, hipMemcpyDeviceToHost, s->stream));

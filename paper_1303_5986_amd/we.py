@@ -63,7 +63,8 @@ class _Params(C.Structure):
 
 class _TrainParams(C.Structure):
     _fields_ = [("steps", C.c_int32), ("batch", C.c_int32), ("lr", C.c_float),
-                ("a_coef", C.c_void_p), ("a_thr", C.c_double), ("seed", C.c_uint64)]
+                ("a_coef", C.c_void_p), ("a_thr", C.c_double), ("seed", C.c_uint64),
+                ("edge_mode", C.c_int32)]
 
 
 _LIB = None
@@ -294,11 +295,12 @@ class Sim:
 
     # ------------------------------------------------------------ learned bins
     def train_committor(self, a_coef, a_thr: float, steps: int = 2000, batch: int = 1024,
-                        lr: float = 1e-3, seed: int = 1):
+                        lr: float = 1e-3, seed: int = 1, edge_mode: int = 0):
         """Train the committor on the recorded iterations; returns
         (per-step loss, number of training states)."""
         a = np.ascontiguousarray(a_coef, np.float64)
-        tp = _TrainParams(int(steps), int(batch), float(lr), a.ctypes.data, float(a_thr), int(seed))
+        tp = _TrainParams(int(steps), int(batch), float(lr), a.ctypes.data, float(a_thr), int(seed),
+                          int(edge_mode))
         loss = np.zeros(max(int(steps), 1), np.float32)
         n = C.c_int32(0)
         _check(load_library().we_train_committor(self.handle, C.byref(tp), _ptr(loss), C.byref(n)))

@@ -138,3 +138,44 @@ def test_training_learns_a_committor_and_bins_on_it():
         x, w, b, o = sim.walkers(r)
         assert abs(w.sum() - 1.0) < 1e-12
         assert b.min() >= 0 and b.max() < cfg.n_bins
+
+
+def test_learned_bins_gain_over_a_product_count_coordinate():
+    """What the trained network gains: with bins on a single product count
+    (P1 + 2 D1) the 16 replicas' MFPT estimates of the toggle stay far from
+    the brute-force reference after 2000 iterations; binning the same runs on
+    the committor learned from their own first 400 iterations brings the RMS
+    relative error down by at least a factor of 1.5."""
+    _say("case: learned vs plain (product-count) bins, toggle MFPT")
+    import dataclasses
+    we = _we()
+    T, burn = 2000, 100
+    base = wl.toggle_config(n_runs=16, n_iters=T)
+    delta = np.array([0, 0, 0, 0, 1, -1, 2, -2.0])
+    weak = dataclasses.replace(base, bin_coef=np.array([0, 0, 0, 0, 1, 0, 2, 0.0]),
+                               edges=wl.uniform_edges(-0.5, 48.0, base.n_bins))
+    bf = dataclasses.replace(base, edges=np.array([-1e9, 1e9]), m_targ=1024,
+                             seeds=np.arange(1001, 1065, dtype=np.uint64))
+    sb = we.sim_from_config(bf, kernel=we.WE_KERNEL_LANE, max_iters=T)
+    sb.graph_capture(20)
+    sb.graph_replay(T // 20)
+    ref, _, _ = sb.mfpt(200)
+
+    def rel_err(sim):
+        f = np.stack([sim.flux(r, burn, T - burn) for r in range(16)])
+        m = base.tau / f.mean(axis=1)
+        return float(np.sqrt(np.mean((m / ref - 1.0) ** 2)))
+
+    plain = we.sim_from_config(weak, kernel=we.WE_KERNEL_LANE, max_iters=T)
+    plain.graph_capture(20)
+    plain.graph_replay(T // 20)
+    learned = we.sim_from_config(weak, kernel=we.WE_KERNEL_LANE, max_iters=T, record_iters=400)
+    learned.step(400)
+    learned.train_committor(delta, -base.tgt_thr, steps=1500, batch=1024, lr=2e-3, seed=7,
+                            edge_mode=1)
+    learned.use_committor_bins(True)
+    learned.graph_capture(20)
+    learned.graph_replay((T - 400) // 20)
+    ep, el = rel_err(plain), rel_err(learned)
+    _say(f"   reference MFPT {ref:.0f}; RMS relative error plain {ep:.3f}, learned {el:.3f}")
+    assert el * 1.5 < ep
