@@ -61,8 +61,10 @@ __global__ __launch_bounds__(256) void we_recycle_bin_kernel(SimArgs a, int32_t 
 
 // Per-walker working arrays of one run: LDS when the run fits, else global.
 struct RunWork {
-    uint16_t *bin, *list, *cnt;
-    double *w;
+    double *w;          // weights in bin-major order
+    int32_t *list;      // slots in bin-major order
+    uint16_t *bin;      // bin of every slot
+    uint16_t *cnt;      // copies / alive flags in bin-major order
 };
 
 __global__ __launch_bounds__(256) void we_resample_kernel(SimArgs a, const double *__restrict__ w_cur,
@@ -75,7 +77,8 @@ __global__ __launch_bounds__(256) void we_resample_kernel(SimArgs a, const doubl
     int32_t *cnt = reinterpret_cast<int32_t *>(lds);   // [NB]
     int32_t *start = cnt + NB;                          // [NB+1]
     int32_t *ostart = start + NB + 1;                   // [NB+1]
-    unsigned char *tail = lds + sizeof(int32_t) * (3 * (size_t)NB + 2);
+    int32_t *cursor = ostart + NB + 1;                  // [NB]
+    unsigned char *tail = reinterpret_cast<unsigned char *>(cursor + NB);
     tail += (16 - ((uintptr_t)tail & 15)) & 15;
 
     const uint32_t iter = *a.iter_dev;
@@ -88,25 +91,29 @@ __global__ __launch_bounds__(256) void we_resample_kernel(SimArgs a, const doubl
     RunWork wk;
     if (use_lds) {
         wk.w = reinterpret_cast<double *>(tail);
-        wk.bin = reinterpret_cast<uint16_t *>(wk.w + cap);
-        wk.list = wk.bin + cap;
-        wk.cnt = wk.list + cap;
+        wk.list = reinterpret_cast<int32_t *>(wk.w + cap);
+        wk.bin = reinterpret_cast<uint16_t *>(wk.list + cap);
+        wk.cnt = wk.bin + cap;
     } else {
         wk.w = a.s_w + base;
-        wk.bin = reinterpret_cast<uint16_t *>(a.s_list + base);
-        wk.list = reinterpret_cast<uint16_t *>(a.s_cnt + base);
-        wk.cnt = wk.list + cap;
+        wk.list = a.s_list + base;
+        wk.bin = reinterpret_cast<uint16_t *>(a.s_cnt + base);
+        wk.cnt = wk.bin + cap;
     }
 
+    for (int32_t b = tid; b < NB; b += nthr) cnt[b] = 0;
+    __syncthreads();
     int64_t my_ev = 0;
     for (int32_t k = tid; k < n; k += nthr) {
-        wk.bin[k] = (uint16_t)sbin[k];
+        const int32_t b = sbin[k];
+        wk.bin[k] = (uint16_t)b;
+        atomicAdd(&cnt[b], 1);
         my_ev += a.ev_walker[base + k];
     }
     ev_part[tid] = my_ev;
     __syncthreads();
 
-    // recycled weight (slot order) and reactions fired (integer, any order)
+    // recycled weight (slot order), reactions fired, bin offsets
     if (tid == 0) {
         double f = 0.0;
         for (int32_t k = 0; k < n; ++k)
@@ -118,19 +125,10 @@ __global__ __launch_bounds__(256) void we_resample_kernel(SimArgs a, const doubl
             a.ev_iter[(size_t)run * a.max_iters + rec_slot] = ev;
             a.seg_iter[(size_t)run * a.max_iters + rec_slot] = n;
         }
-    }
-
-    // members of each bin, in slot order
-    for (int32_t b = tid; b < NB; b += nthr) {
-        int32_t c = 0;
-        for (int32_t k = 0; k < n; ++k) c += (wk.bin[k] == b);
-        cnt[b] = c;
-    }
-    __syncthreads();
-    if (tid == 0) {
         int32_t acc = 0, oacc = 0;
         for (int32_t b = 0; b < NB; ++b) {
             start[b] = acc;
+            cursor[b] = acc;
             ostart[b] = oacc;
             acc += cnt[b];
             oacc += (cnt[b] > 0) ? M : 0;
@@ -139,15 +137,33 @@ __global__ __launch_bounds__(256) void we_resample_kernel(SimArgs a, const doubl
         ostart[NB] = oacc;
     }
     __syncthreads();
-    for (int32_t b = tid; b < NB; b += nthr) {
-        if (cnt[b] == 0) continue;
-        int32_t p = start[b];
-        for (int32_t k = 0; k < n; ++k)
-            if (wk.bin[k] == b) {
-                wk.list[p] = (uint16_t)k;
-                wk.w[p] = wr[k];
-                ++p;
+
+    // stable placement of every walker into its bin's segment (slot order
+    // kept): one wave walks the slots 64 at a time; lanes with the same bin
+    // are ranked by a ballot, and the bin's cursor advances by the group size
+    if (tid < 64) {
+        const int lane = tid;
+        for (int32_t c0 = 0; c0 < n; c0 += 64) {
+            const int32_t k = c0 + lane;
+            const bool valid = k < n;
+            const int32_t b = valid ? (int32_t)wk.bin[k] : -1;
+            unsigned long long todo = __ballot(valid);
+            while (todo) {
+                const int leader = __ffsll((long long)todo) - 1;
+                const int32_t lb = __shfl(b, leader, 64);
+                const unsigned long long grp = __ballot(valid && b == lb);
+                if (valid && b == lb) {
+                    const unsigned long long below = lane ? (grp & ((1ull << lane) - 1ull)) : 0ull;
+                    const int32_t p = cursor[lb] + __popcll(below);
+                    wk.list[p] = k;
+                    wk.w[p] = wr[k];
+                }
+                __builtin_amdgcn_wave_barrier();
+                if (lane == leader) cursor[lb] += __popcll(grp);
+                __builtin_amdgcn_wave_barrier();
+                todo &= ~grp;
             }
+        }
     }
     __syncthreads();
 
@@ -275,8 +291,8 @@ hipError_t launch_recycle_bin(const SimArgs &a, int32_t *x_cur, bool grid_bins, 
 }
 
 size_t resample_lds_bytes(const SimArgs &a, bool use_lds) {
-    size_t b = sizeof(int32_t) * (3 * (size_t)a.n_bins + 2) + 16;
-    if (use_lds) b += (size_t)a.cap * (sizeof(double) + 3 * sizeof(uint16_t));
+    size_t b = sizeof(int32_t) * (4 * (size_t)a.n_bins + 2) + 16;
+    if (use_lds) b += (size_t)a.cap * (sizeof(double) + sizeof(int32_t) + 2 * sizeof(uint16_t));
     return b;
 }
 

@@ -249,8 +249,9 @@ we_status check_params(const we_network *net, const we_grid *g, const we_params 
         return fail(WE_EINVAL, "m_targ, n_runs must be >= 1");
     if (!p->seeds || !p->x0) return fail(WE_EINVAL, "seeds and x0 are required");
     const int64_t cap = (int64_t)p->m_targ * g->n_bins;
-    if (cap > 65535 || cap * p->n_runs > (int64_t)1 << 30)
-        return fail(WE_EINVAL, "too many walker slots (m_targ * n_bins must be <= 65535)");
+    if (g->n_bins > 8192) return fail(WE_EINVAL, "at most 8192 bins");
+    if (cap > (1 << 22) || cap * p->n_runs > (int64_t)1 << 30)
+        return fail(WE_EINVAL, "too many walker slots");
     for (int32_t s = 0; s < net->S; ++s)
         if (p->x0[s] < 0 || p->x0[s] > WE_COUNT_MAX) return fail(WE_EINVAL, "x0 out of range");
     if (p->recycle) {

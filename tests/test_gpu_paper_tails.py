@@ -1,0 +1,76 @@
+"""The paper's rare-state experiments at the paper's own scale, on the GPU
+(lane path), against the exact chemical-master-equation values the paper
+prints and that the closed-form references reproduce.
+
+* Schloegl (Sec. III.B): P(X >= 700, t = 5 s | X(0) = 82), 802 unit bins,
+  100 walkers per bin, tau = 0.05, 100 intervals, ten replicas.
+  Paper: WE 1.143e-9 +- 4.7e-11, CME 1.148e-9.
+* Futile cycle (Sec. III.A): P(S1 > 90, t = 100 s) from S1 = S2 = 50,
+  101 unit bins on S1, 100 walkers per bin, tau = 1, 100 intervals, ten
+  replicas.  Paper: WE 2.47e-18 +- 3.4e-19, CME 2.72e-18.
+
+The check: the replicas' mean lies within 3 standard errors (over replicas)
+of the exact value, and within 25% of it.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import closed_form as cf
+from paper_1303_5986_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
+PAPER = json.load(open(os.path.join(HERE, "golden", "paper_values.json")))
+
+
+def _we():
+    from paper_1303_5986_amd import we
+    return we
+
+
+def _tail_estimates(cfg, species, lo, n_iters):
+    we = _we()
+    sim = we.sim_from_config(cfg, kernel=we.WE_KERNEL_LANE, max_iters=n_iters)
+    sim.step(n_iters)
+    sim.synchronize()
+    est = []
+    for r in range(len(cfg.seeds)):
+        x, w, _, _ = sim.walkers(r)
+        est.append(float(w[x[:, species] >= lo].sum()))
+        assert abs(w.sum() - 1.0) < 1e-12
+    return np.array(est)
+
+
+def test_schlogl_transient_tail_at_paper_scale():
+    print("case: Schloegl P(X>=700, t=5), 802 bins x 100 walkers x 10 replicas", flush=True)
+    cfg = wl.WEConfig(name="schlogl_t5", net=wl.schlogl(), x0=np.array([82], np.int32),
+                      bin_coef=np.array([1.0]), edges=np.arange(0.0, 803.0), m_targ=100,
+                      tau=0.05, n_iters=100, seeds=np.arange(501, 511, dtype=np.uint64))
+    est = _tail_estimates(cfg, 0, 700, 100)
+    lam, mu = cf.schlogl_rates(1000)
+    exact = cf.chain_transient(lam, mu, 82, 5.0)[700:].sum()
+    mean, sem = est.mean(), est.std(ddof=1) / np.sqrt(len(est))
+    print(f"   WE {mean:.4e} +- {sem:.1e} (10 replicas); exact {exact:.4e}; "
+          f"paper WE {PAPER['schlogl_tail_t5_we']['value']:.3e}", flush=True)
+    assert abs(mean - exact) < 3 * sem + 1e-30
+    assert abs(mean / exact - 1) < 0.25
+
+
+def test_futile_cycle_tail_at_paper_scale():
+    print("case: futile cycle P(S1>90, t=100), 101 bins x 100 walkers x 10 replicas", flush=True)
+    x0 = np.array([50, 50, 1, 1, 0, 0], np.int32)      # S1 S2 E1 E2 B1 B2
+    cfg = wl.WEConfig(name="futile_t100", net=wl.futile_cycle(), x0=x0,
+                      bin_coef=np.array([1.0, 0, 0, 0, 0, 0]), edges=np.arange(0.0, 102.0),
+                      m_targ=100, tau=1.0, n_iters=100,
+                      seeds=np.arange(601, 611, dtype=np.uint64))
+    est = _tail_estimates(cfg, 0, 91, 100)
+    states, p = cf.futile_transient(100.0)
+    exact = sum(pk for s, pk in zip(states, p) if s[0] > 90)
+    mean, sem = est.mean(), est.std(ddof=1) / np.sqrt(len(est))
+    print(f"   WE {mean:.4e} +- {sem:.1e} (10 replicas); exact {exact:.4e}; "
+          f"paper WE {PAPER['futile_tail_t100']['value']:.3e} (CME)", flush=True)
+    assert abs(mean - exact) < 3 * sem
+    assert abs(mean / exact - 1) < 0.25
