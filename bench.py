@@ -228,6 +228,59 @@ def experiment_toggle_mfpt(args):
     print(json.dumps(out), flush=True)
 
 
+def experiment_batch(args):
+    """64 independent WE runs on seeded networks of 8..3680 reactions and
+    256..8192 walker slots: one batch (persistent propagation launches,
+    autotuned lane/wave choice, HIP graph) against the same runs stepped as
+    plain sequential launches, one run after another."""
+    import torch
+    from paper_1303_5986_amd import we, workloads as wl
+
+    W, K = args.warmup, args.steps
+    cfgs = wl.batch_configs(n_runs=args.batch_runs, n_iters=W + 2 * K)
+    cache = os.path.join(ROOT, "profiles", "batch_autotune.json") if args.tune_cache else None
+    t0 = time.perf_counter()
+    b = we.Batch(cfgs, max_iters=W + 2 * K, autotune_iters=args.autotune_iters, cache_path=cache)
+    tune_s = time.perf_counter() - t0
+    b.step(W)
+    b.synchronize()
+    ev0 = sum(m.counters()[0] for m in b.members)
+    b.graph_capture(2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.graph_replay(K // 2)
+    b.synchronize()
+    tb = time.perf_counter() - t0
+    evb = sum(m.counters()[0] for m in b.members) - ev0
+    kernels = b.kernels().tolist()
+
+    # the same runs as independent sims, each launched on its own, in turn
+    sims = [we.sim_from_config(c, kernel=int(k), max_iters=W + 2 * K) for c, k in zip(cfgs, kernels)]
+    for s in sims:
+        s.step(W)
+    for s in sims:
+        s.synchronize()
+    ev0 = sum(s.counters()[0] for s in sims)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(K):
+        for s in sims:
+            s.step(1)
+    for s in sims:
+        s.synchronize()
+    ts = time.perf_counter() - t0
+    evs = sum(s.counters()[0] for s in sims) - ev0
+    out = {"metric": "SSA events/s, batched vs sequential launches", "runs": len(cfgs),
+           "reactions": [cfgs[0].net.R, cfgs[-1].net.R],
+           "walker_slots_total": int(sum(c.cap for c in cfgs)), "steps": K, "warmup": W,
+           "batched": {"events_per_s": evb / tb, "we_iters_per_s": K / tb, "ms_per_step": tb * 1e3 / K},
+           "sequential": {"events_per_s": evs / ts, "we_iters_per_s": K / ts, "ms_per_step": ts * 1e3 / K},
+           "speedup": ts / tb, "events_equal": bool(evb == evs),
+           "kernels": {"lane": kernels.count(1), "wave": kernels.count(2)},
+           "autotune_s": tune_s}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -240,7 +293,10 @@ def main():
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB five times "
                          "(reference kernel for scaling the HBM byte counters)")
-    ap.add_argument("--experiment", default="", choices=["", "toggle_mfpt"])
+    ap.add_argument("--experiment", default="", choices=["", "toggle_mfpt", "batch"])
+    ap.add_argument("--batch-runs", type=int, default=64)
+    ap.add_argument("--autotune-iters", type=int, default=3)
+    ap.add_argument("--tune-cache", action="store_true")
     ap.add_argument("--exp-iters", type=int, default=4000)
     ap.add_argument("--ref-iters", type=int, default=4000)
     ap.add_argument("--plain-coord", default="delta", choices=["delta", "total1"],
@@ -251,6 +307,9 @@ def main():
     args = ap.parse_args()
     if args.experiment == "toggle_mfpt":
         experiment_toggle_mfpt(args)
+        return
+    if args.experiment == "batch":
+        experiment_batch(args)
         return
     if args.calibrate_copy:
         import torch

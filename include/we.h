@@ -272,6 +272,33 @@ WE_API we_status we_mlp_loss_grad(int32_t n_in, const float *params, const float
 WE_API we_status we_adam_step(int32_t n, float *params, float *m, float *v, const float *grad,
                               float lr, int32_t t);
 
+/* ---------------------------------------------------------------- batches
+ * Many independent WE runs of DIFFERENT networks stepped together on one
+ * stream (the paper runs independent replicas, Sec. IV).  Member i is an
+ * ordinary sim built from nets[i], grids[i], params[i] (library-allocated
+ * workspace, records not supported); the propagation of all members is one
+ * persistent launch per kernel variant whose waves pull (run, walker-tile)
+ * work items from a device counter, so uneven runs balance across the chip.
+ * autotune_iters > 0: a network that fits both kernels (params.kernel
+ * AUTO) is timed for that many iterations with each and the faster is kept;
+ * choices are cached in the JSON file cache_path (NULL: no cache).
+ * Members are owned by the batch: read them with the sim getters via
+ * we_batch_sim, never step or destroy them directly. */
+typedef struct we_batch we_batch;
+WE_API we_status we_batch_create(int32_t n, const we_network *const *nets, const we_grid *grids,
+                                 const we_params *params, void *hip_stream,
+                                 int32_t autotune_iters, const char *cache_path, we_batch **out);
+/* n iterations of every member (asynchronous).  Errors: WE_ECAPACITY past
+ * the smallest member max_iters. */
+WE_API we_status we_batch_step(we_batch *b, int32_t n);
+/* Capture n (even) batched iterations as one HIP graph / replay it. */
+WE_API we_status we_batch_graph_capture(we_batch *b, int32_t n);
+WE_API we_status we_batch_graph_replay(we_batch *b, int32_t times);
+/* Member i (NULL if out of range); kernels[i] gets each member's kernel. */
+WE_API we_sim *we_batch_sim(we_batch *b, int32_t i);
+WE_API we_status we_batch_info(we_batch *b, int32_t *n_sims, int32_t *kernels);
+WE_API void we_batch_destroy(we_batch *b);
+
 /* Per-kernel timing with HIP events recorded on the sim's stream around
  * every launch.  we_profile(s, 1) clears and starts the accumulators,
  * we_profile(s, 0) stops recording.  we_profile_read waits for the stream

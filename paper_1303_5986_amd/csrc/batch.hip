@@ -1,0 +1,390 @@
+// batch.hip -- many independent WE runs of different networks stepped
+// together (gfx950).
+//
+// Runs are independent (the paper runs independent replicas for its error
+// bars, Sec. IV), so a batch is a set of ordinary sims sharing one stream.
+// What is batched is the propagation: instead of one SSA launch per run --
+// each too small to fill 256 CUs when a run holds a few hundred walkers --
+// every kernel variant gets ONE persistent launch whose waves pull work
+// items (run, tile) from a device counter until the list is exhausted:
+//   lane variants: a tile is 64 consecutive walker slots, one per lane;
+//   wave variant:  a tile is one walker slot, one wave.
+// Items of cheap and expensive runs mix freely, so uneven runs balance
+// across the chip.  Resampling and the observables stay per run (they are
+// microseconds each), all on the same stream; the whole iteration can be
+// captured as a HIP graph (the work counters are cleared by a kernel, not a
+// memset, so replays are safe).
+//
+// Autotuning: for a network that fits both kernels, a short pilot of each
+// (timed with HIP events) picks the faster; the choice is cached in a JSON
+// file keyed by (species, reactions, walker slots, runs).
+#include <algorithm>
+#include <cstdio>
+#include <fstream>
+#include <map>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "ssa_lane_body.h"
+#include "ssa_wave_body.h"
+#include "we_internal.h"
+
+namespace {
+
+enum Variant { V_LANE_1_4 = 0, V_LANE_2_8, V_LANE_8_16, V_LANE_16_32, V_WAVE, V_COUNT };
+
+struct Item {
+    int32_t sim, run, slot;
+};
+
+Variant variant_of(const we_sim *s) {
+    const int32_t S = s->S, R = s->net->R;
+    if (s->kernel == WE_KERNEL_WAVE) return V_WAVE;
+    if (S <= 1 && R <= 4) return V_LANE_1_4;
+    if (S <= 2 && R <= 8) return V_LANE_2_8;
+    if (S <= 8 && R <= 16) return V_LANE_8_16;
+    if (S <= 16 && R <= 32) return V_LANE_16_32;
+    return V_WAVE;
+}
+
+}  // namespace
+
+template <int SMAX, int RMAX>
+__global__ __launch_bounds__(256) void batch_lane_kernel(const SimArgs *__restrict__ args,
+                                                         int32_t *const *__restrict__ xptr,
+                                                         const Item *__restrict__ items, int32_t n_items,
+                                                         uint32_t *__restrict__ counter) {
+    const int lane = threadIdx.x & 63;
+    for (;;) {
+        uint32_t idx = 0;
+        if (lane == 0) idx = atomicAdd(counter, 1u);
+        idx = __shfl(idx, 0, 64);
+        if (idx >= (uint32_t)n_items) break;
+        const Item it = items[idx];
+        const SimArgs &a = args[it.sim];
+        const int32_t k = it.slot + lane;
+        if (k < a.n_walk[it.run]) lane_walker<SMAX, RMAX>(a, xptr[it.sim], it.run, k, *a.iter_dev);
+    }
+}
+
+__global__ __launch_bounds__(256) void batch_wave_kernel(const SimArgs *__restrict__ args,
+                                                         int32_t *const *__restrict__ xptr,
+                                                         const Item *__restrict__ items, int32_t n_items,
+                                                         uint32_t *__restrict__ counter, int32_t s_pad) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    double *lchunk = reinterpret_cast<double *>(smem) + wv * 64;
+    int32_t *lx = reinterpret_cast<int32_t *>(smem + WAVE_WALKERS_PER_BLOCK * 64 * sizeof(double)) + wv * s_pad;
+    for (;;) {
+        uint32_t idx = 0;
+        if (lane == 0) idx = atomicAdd(counter, 1u);
+        idx = __shfl(idx, 0, 64);
+        if (idx >= (uint32_t)n_items) break;
+        const Item it = items[idx];
+        const SimArgs &a = args[it.sim];
+        if (it.slot < a.n_walk[it.run]) wave_walker(a, xptr[it.sim], it.run, it.slot, *a.iter_dev, lchunk, lx);
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+__global__ void batch_reset_kernel(uint32_t *counters, int32_t n) {
+    const int32_t i = threadIdx.x;
+    if (i < n) counters[i] = 0u;
+}
+
+struct we_batch {
+    hipStream_t stream = nullptr;
+    std::vector<we_sim *> sims;
+    std::vector<Variant> var;
+    std::vector<Item> items[V_COUNT];
+    Item *d_items[V_COUNT] = {};
+    uint32_t *d_counters = nullptr;
+    SimArgs *d_args = nullptr;
+    int32_t **d_xptr[2] = {nullptr, nullptr};
+    int32_t s_pad = 4;
+    int32_t iter = 0, max_iters = 0;
+    hipGraphExec_t graph_exec = nullptr;
+    hipStream_t capture_stream = nullptr;
+    int32_t graph_iters = 0;
+    bool capturing = false;
+};
+
+namespace {
+
+// Pilot timing of one kernel choice: a throw-away sim, `iters` iterations.
+we_status pilot_ms(const we_network *net, const we_grid *g, const we_params *p, int32_t kernel, int32_t iters,
+                   hipStream_t st, double *ms) {
+    we_params q = *p;
+    q.kernel = kernel;
+    q.max_iters = iters;
+    q.record_iters = 0;
+    q.n_joint = 0;
+    q.hist_hi = q.hist_lo - 1;
+    we_sim *s = nullptr;
+    we_status r = we_init(net, g, &q, st, nullptr, 0, &s);
+    if (r != WE_OK) return r;
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    HIP_TRY(hipEventRecord(e0, st));
+    r = we_step_intervals(s, iters);
+    HIP_TRY(hipEventRecord(e1, st));
+    HIP_TRY(hipEventSynchronize(e1));
+    float t = 0.f;
+    HIP_TRY(hipEventElapsedTime(&t, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (r == WE_OK) r = we_synchronize(s);
+    we_destroy(s);
+    *ms = t;
+    return r;
+}
+
+std::map<std::string, int> read_cache(const char *path) {
+    std::map<std::string, int> m;
+    if (!path || !*path) return m;
+    std::ifstream f(path);
+    if (!f) return m;
+    std::stringstream ss;
+    ss << f.rdbuf();
+    const std::string t = ss.str();
+    // flat object of "key": value pairs
+    size_t pos = 0;
+    while ((pos = t.find('"', pos)) != std::string::npos) {
+        const size_t end = t.find('"', pos + 1);
+        if (end == std::string::npos) break;
+        const std::string key = t.substr(pos + 1, end - pos - 1);
+        const size_t colon = t.find(':', end);
+        if (colon == std::string::npos) break;
+        m[key] = std::atoi(t.c_str() + colon + 1);
+        pos = t.find_first_of(",}", colon);
+        if (pos == std::string::npos) break;
+    }
+    return m;
+}
+
+void write_cache(const char *path, const std::map<std::string, int> &m) {
+    if (!path || !*path) return;
+    std::ofstream f(path);
+    f << "{";
+    bool first = true;
+    for (const auto &kv : m) {
+        f << (first ? "" : ",") << "\n  \"" << kv.first << "\": " << kv.second;
+        first = false;
+    }
+    f << "\n}\n";
+}
+
+we_status build_items(we_batch *b) {
+    for (int v = 0; v < V_COUNT; ++v) b->items[v].clear();
+    for (size_t i = 0; i < b->sims.size(); ++i) {
+        we_sim *s = b->sims[i];
+        const Variant v = b->var[i];
+        const int32_t step = (v == V_WAVE) ? 1 : 64;
+        for (int32_t r = 0; r < s->n_runs; ++r)
+            for (int32_t k = 0; k < s->cap; k += step) b->items[v].push_back(Item{(int32_t)i, r, k});
+    }
+    for (int v = 0; v < V_COUNT; ++v) {
+        if (b->d_items[v]) { (void)hipFree(b->d_items[v]); b->d_items[v] = nullptr; }
+        if (b->items[v].empty()) continue;
+        HIP_TRY(hipMalloc(&b->d_items[v], sizeof(Item) * b->items[v].size()));
+        HIP_TRY(hipMemcpy(b->d_items[v], b->items[v].data(), sizeof(Item) * b->items[v].size(),
+                          hipMemcpyHostToDevice));
+    }
+    return WE_OK;
+}
+
+we_status launch_batch_iteration(we_batch *b, hipStream_t st) {
+    const int32_t parity = b->sims[0]->cur;
+    hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(64), 0, st, b->d_counters, (int32_t)V_COUNT);
+    HIP_TRY(hipGetLastError());
+    int32_t *const *xp = b->d_xptr[parity];
+    for (int v = 0; v < V_COUNT; ++v) {
+        const int32_t n = (int32_t)b->items[v].size();
+        if (n == 0) continue;
+        const unsigned blocks = (unsigned)std::min<int64_t>((n + 3) / 4, 2048);
+        uint32_t *cnt = b->d_counters + v;
+        switch (v) {
+        case V_LANE_1_4:
+            hipLaunchKernelGGL((batch_lane_kernel<1, 4>), dim3(blocks), dim3(256), 0, st, b->d_args, xp, b->d_items[v], n, cnt);
+            break;
+        case V_LANE_2_8:
+            hipLaunchKernelGGL((batch_lane_kernel<2, 8>), dim3(blocks), dim3(256), 0, st, b->d_args, xp, b->d_items[v], n, cnt);
+            break;
+        case V_LANE_8_16:
+            hipLaunchKernelGGL((batch_lane_kernel<8, 16>), dim3(blocks), dim3(256), 0, st, b->d_args, xp, b->d_items[v], n, cnt);
+            break;
+        case V_LANE_16_32:
+            hipLaunchKernelGGL((batch_lane_kernel<16, 32>), dim3(blocks), dim3(256), 0, st, b->d_args, xp, b->d_items[v], n, cnt);
+            break;
+        default: {
+            const size_t shmem = WAVE_WALKERS_PER_BLOCK * (64 * sizeof(double) + sizeof(int32_t) * (size_t)b->s_pad);
+            hipLaunchKernelGGL(batch_wave_kernel, dim3(blocks), dim3(256), shmem, st, b->d_args, xp, b->d_items[v],
+                               n, cnt, b->s_pad);
+        }
+        }
+        HIP_TRY(hipGetLastError());
+    }
+    for (we_sim *s : b->sims) {
+        we_status r = we_sim_bookkeeping(s, st, nullptr);
+        if (r != WE_OK) return r;
+    }
+    return WE_OK;
+}
+
+}  // namespace
+
+extern "C" we_status we_batch_create(int32_t n, const we_network *const *nets, const we_grid *grids,
+                                     const we_params *params, void *hip_stream, int32_t autotune_iters,
+                                     const char *cache_path, we_batch **out) {
+    if (!out || n <= 0 || !nets || !grids || !params) return we_fail(WE_EINVAL, "bad arguments");
+    *out = nullptr;
+    we_batch *b = new we_batch();
+    b->stream = (hipStream_t)hip_stream;
+    std::map<std::string, int> cache = read_cache(cache_path);
+    bool cache_dirty = false;
+    for (int32_t i = 0; i < n; ++i) {
+        we_params p = params[i];
+        if (p.record_iters > 0) {
+            we_batch_destroy(b);
+            return we_fail(WE_EINVAL, "records are not supported inside a batch");
+        }
+        const int32_t S = nets[i]->S, R = nets[i]->R;
+        if (p.kernel == WE_KERNEL_AUTO) {
+            if (!(lane_kernel_fits(S, R) && R <= 32)) {
+                p.kernel = WE_KERNEL_WAVE;
+            } else if (autotune_iters > 0) {
+                char key[128];
+                std::snprintf(key, sizeof key, "S%d_R%d_cap%d_runs%d_tau%g", S, R, p.m_targ * grids[i].n_bins,
+                              p.n_runs, p.tau);
+                auto it = cache.find(key);
+                if (it != cache.end()) {
+                    p.kernel = it->second;
+                } else {
+                    double t_lane = 0.0, t_wave = 0.0;
+                    we_status r = pilot_ms(nets[i], &grids[i], &p, WE_KERNEL_LANE, autotune_iters, b->stream, &t_lane);
+                    if (r == WE_OK) r = pilot_ms(nets[i], &grids[i], &p, WE_KERNEL_WAVE, autotune_iters, b->stream, &t_wave);
+                    if (r != WE_OK) { we_batch_destroy(b); return r; }
+                    p.kernel = (t_wave < t_lane) ? WE_KERNEL_WAVE : WE_KERNEL_LANE;
+                    cache[key] = p.kernel;
+                    cache_dirty = true;
+                }
+            } else {
+                p.kernel = WE_KERNEL_LANE;
+            }
+        }
+        we_sim *s = nullptr;
+        we_status r = we_init(nets[i], &grids[i], &p, b->stream, nullptr, 0, &s);
+        if (r != WE_OK) { we_batch_destroy(b); return r; }
+        b->sims.push_back(s);
+        b->var.push_back(variant_of(s));
+        b->s_pad = std::max(b->s_pad, (S + 3) & ~3);
+        b->max_iters = (i == 0) ? s->max_iters : std::min(b->max_iters, s->max_iters);
+    }
+    if (cache_dirty) write_cache(cache_path, cache);
+    if ((size_t)WAVE_WALKERS_PER_BLOCK * (64 * sizeof(double) + 4 * (size_t)b->s_pad) > 64 * 1024) {
+        we_batch_destroy(b);
+        return we_fail(WE_EINVAL, "species count too large for the batched wave kernel");
+    }
+    std::vector<SimArgs> args;
+    std::vector<int32_t *> xp0, xp1;
+    for (we_sim *s : b->sims) {
+        args.push_back(s->args);
+        xp0.push_back(s->x[0]);
+        xp1.push_back(s->x[1]);
+    }
+    HIP_TRY(hipMalloc(&b->d_args, sizeof(SimArgs) * n));
+    HIP_TRY(hipMemcpy(b->d_args, args.data(), sizeof(SimArgs) * n, hipMemcpyHostToDevice));
+    HIP_TRY(hipMalloc(&b->d_xptr[0], sizeof(int32_t *) * n));
+    HIP_TRY(hipMalloc(&b->d_xptr[1], sizeof(int32_t *) * n));
+    HIP_TRY(hipMemcpy(b->d_xptr[0], xp0.data(), sizeof(int32_t *) * n, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(b->d_xptr[1], xp1.data(), sizeof(int32_t *) * n, hipMemcpyHostToDevice));
+    HIP_TRY(hipMalloc(&b->d_counters, sizeof(uint32_t) * V_COUNT));
+    we_status r = build_items(b);
+    if (r != WE_OK) { we_batch_destroy(b); return r; }
+    *out = b;
+    return WE_OK;
+}
+
+extern "C" we_status we_batch_step(we_batch *b, int32_t n) {
+    if (!b) return we_fail(WE_EINVAL, "NULL batch");
+    if (n < 0 || (int64_t)b->iter + n > b->max_iters) return we_fail(WE_ECAPACITY, "max_iters exceeded");
+    for (int32_t i = 0; i < n; ++i) {
+        we_status r = launch_batch_iteration(b, b->stream);
+        if (r != WE_OK) return r;
+        b->iter += 1;
+        for (we_sim *s : b->sims) {
+            s->iter += 1;
+            if (s->args.nh > 0) s->hist_iters += 1;
+        }
+    }
+    return WE_OK;
+}
+
+extern "C" we_status we_batch_graph_capture(we_batch *b, int32_t n) {
+    if (!b) return we_fail(WE_EINVAL, "NULL batch");
+    if (n <= 0 || (n & 1)) return we_fail(WE_EINVAL, "capture an even, positive number of iterations");
+    if (b->graph_exec) { (void)hipGraphExecDestroy(b->graph_exec); b->graph_exec = nullptr; }
+    if (!b->capture_stream) HIP_TRY(hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking));
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    std::vector<int32_t> cur0;
+    for (we_sim *s : b->sims) { cur0.push_back(s->cur); s->capturing = true; }
+    HIP_TRY(hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal));
+    we_status r = WE_OK;
+    for (int32_t i = 0; i < n && r == WE_OK; ++i) r = launch_batch_iteration(b, b->capture_stream);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(b->capture_stream, &g);
+    for (size_t i = 0; i < b->sims.size(); ++i) { b->sims[i]->cur = cur0[i]; b->sims[i]->capturing = false; }
+    if (r != WE_OK) { if (g) (void)hipGraphDestroy(g); return r; }
+    if (e != hipSuccess) return we_hip_fail(e, "hipStreamEndCapture");
+    e = hipGraphInstantiate(&b->graph_exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return we_hip_fail(e, "hipGraphInstantiate");
+    b->graph_iters = n;
+    return WE_OK;
+}
+
+extern "C" we_status we_batch_graph_replay(we_batch *b, int32_t times) {
+    if (!b) return we_fail(WE_EINVAL, "NULL batch");
+    if (!b->graph_exec) return we_fail(WE_ESTATE, "no captured graph");
+    if (times < 0 || (int64_t)b->iter + (int64_t)times * b->graph_iters > b->max_iters)
+        return we_fail(WE_ECAPACITY, "max_iters exceeded");
+    for (int32_t t = 0; t < times; ++t) {
+        HIP_TRY(hipGraphLaunch(b->graph_exec, b->stream));
+        b->iter += b->graph_iters;
+        for (we_sim *s : b->sims) {
+            s->iter += b->graph_iters;
+            if (s->args.nh > 0) s->hist_iters += b->graph_iters;
+        }
+    }
+    return WE_OK;
+}
+
+extern "C" we_sim *we_batch_sim(we_batch *b, int32_t i) {
+    if (!b || i < 0 || i >= (int32_t)b->sims.size()) return nullptr;
+    return b->sims[i];
+}
+
+extern "C" we_status we_batch_info(we_batch *b, int32_t *n_sims, int32_t *kernels) {
+    if (!b) return we_fail(WE_EINVAL, "NULL batch");
+    if (n_sims) *n_sims = (int32_t)b->sims.size();
+    if (kernels)
+        for (size_t i = 0; i < b->sims.size(); ++i) kernels[i] = b->sims[i]->kernel;
+    return WE_OK;
+}
+
+extern "C" void we_batch_destroy(we_batch *b) {
+    if (!b) return;
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    for (we_sim *s : b->sims) we_destroy(s);
+    for (int v = 0; v < V_COUNT; ++v) (void)hipFree(b->d_items[v]);
+    (void)hipFree(b->d_counters);
+    (void)hipFree(b->d_args);
+    (void)hipFree(b->d_xptr[0]);
+    (void)hipFree(b->d_xptr[1]);
+    if (b->graph_exec) (void)hipGraphExecDestroy(b->graph_exec);
+    if (b->capture_stream) (void)hipStreamDestroy(b->capture_stream);
+    delete b;
+}

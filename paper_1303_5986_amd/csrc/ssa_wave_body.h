@@ -1,0 +1,176 @@
+// ssa_wave_body.h -- the wave-per-walker event loop, shared by the per-sim
+// kernel and the batched persistent kernel.
+#pragma once
+#include "we_common.h"
+
+#define WAVE_WALKERS_PER_BLOCK 4
+#define WAVE_DEP_ROUNDS 4
+
+namespace {
+
+__device__ __forceinline__ double prop_lds(const RxnDesc &d, const int32_t *lx) {
+    return propensity_from(d, (uint32_t)lx[d.s1], (uint32_t)lx[d.s2]);
+}
+
+__device__ __forceinline__ double scan_incl(double v, int lane) {
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const double t = __shfl_up(v, off, 64);
+        if (lane >= off) v = v + t;
+    }
+    return v;
+}
+
+__device__ __forceinline__ int32_t last_set(unsigned long long m) {
+    return m ? 63 - __clzll((long long)m) : -1;
+}
+
+// Sum of all 64 propensities of chunk c, as the last lane of an inclusive scan.
+__device__ __forceinline__ double chunk_total(const SimArgs &a, const int32_t *lx, int c, int lane) {
+    const int r = c * 64 + lane;
+    double v = 0.0;
+    if (r < a.R) v = prop_lds(a.desc[r], lx);
+    v = scan_incl(v, lane);
+    return __shfl(v, 63, 64);
+}
+
+// Add, per chunk, the propensity changes held by the lanes (dependent
+// reaction rr, change dv; rr < 0 for idle lanes).  rr ascends across lanes.
+__device__ __forceinline__ void add_chunk_deltas(double *lchunk, int rr, double dv, int lane) {
+    const int ch = rr >= 0 ? (rr >> 6) : 64;
+    const double D = scan_incl(dv, lane);
+    const int ch_prev = __shfl_up(ch, 1, 64);
+    const int ch_next = __shfl_down(ch, 1, 64);
+    const bool start = (lane == 0) || (ch_prev != ch);
+    const bool end = (lane == 63) || (ch_next != ch);
+    const unsigned long long smask = __ballot(start);
+    const unsigned long long upto = (lane == 63) ? ~0ull : ((2ull << lane) - 1ull);
+    const int sl = last_set(smask & upto);
+    const double before = __shfl(D, sl > 0 ? sl - 1 : 0, 64);
+    const double seg = D - (sl > 0 ? before : 0.0);
+    if (end && ch < 64) lchunk[ch] = lchunk[ch] + seg;
+}
+
+}  // namespace
+
+// One walker through one interval on the calling wave; lchunk (64 doubles)
+// and lx (S ints) are this wave's LDS slices.
+__device__ void wave_walker(const SimArgs &a, int32_t *__restrict__ xs, int32_t run, int32_t k,
+                            uint32_t iter, double *lchunk, int32_t *lx) {
+    const int lane = threadIdx.x & 63;
+    const int32_t S = a.S, R = a.R;
+    const int32_t K = (R + 63) >> 6;
+    int32_t *xw = xs + ((size_t)run * a.cap + k) * S;
+    for (int s = lane; s < S; s += 64) lx[s] = xw[s];
+    __builtin_amdgcn_wave_barrier();
+
+    // chunk sums from scratch
+    double csum = 0.0;
+    for (int c = 0; c < K; ++c) {
+        const double tot = chunk_total(a, lx, c, lane);
+        if (lane == c) csum = tot;
+    }
+    lchunk[lane] = csum;
+
+    const uint64_t seed = a.seeds[run];
+    const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+    const double tau = a.tau;
+    double t = 0.0;
+    uint32_t e = 0, fired = 0;
+    bool bad = false;
+
+    for (;;) {
+        const double P = scan_incl(csum, lane);
+        const double a0 = __shfl(P, 63, 64);
+        if (!(a0 > 0.0)) break;
+        const U4 rnd = philox4x32_10(e, (uint32_t)k, iter, 0u, k0, k1);
+        e += 1;
+        const double u1 = uniform53(rnd.x, rnd.y);
+        const double u2 = uniform53(rnd.z, rnd.w);
+        const double dt = -log(1.0 - u1) / a0;
+        if (t + dt > tau) break;
+        t = t + dt;
+        const double target = u2 * a0;
+
+        // chunk holding the target
+        const unsigned long long m1 = __ballot(P > target);
+        int cs = m1 ? (__ffsll((long long)m1) - 1) : last_set(__ballot(csum > 0.0));
+        if (cs < 0) cs = 0;
+        const double base = __shfl(P - csum, cs, 64);
+        const double target2 = target - base;
+        // reaction inside the chunk
+        const int rsel = cs * 64 + lane;
+        double v = 0.0;
+        if (rsel < R) v = prop_lds(a.desc[rsel], lx);
+        const double Q = scan_incl(v, lane);
+        const unsigned long long m2 = __ballot(Q > target2);
+        const int ls = m2 ? (__ffsll((long long)m2) - 1) : last_set(__ballot(v > 0.0));
+        if (ls < 0) {              // chunk sum drifted above an all-zero chunk
+            if (lane == 0) atomicOr(a.err, WE_DERR_SELECT);
+            break;
+        }
+        const int j = cs * 64 + ls;
+
+        // propensities of the dependents before the change
+        const int32_t d0 = a.dep_ptr[j], d1 = a.dep_ptr[j + 1];
+        const int32_t nd = d1 - d0;
+        const int nround = (nd + 63) >> 6;
+        int rr[WAVE_DEP_ROUNDS];
+        double old[WAVE_DEP_ROUNDS];
+        if (nround <= WAVE_DEP_ROUNDS) {
+#pragma unroll
+            for (int q = 0; q < WAVE_DEP_ROUNDS; ++q) {
+                rr[q] = -1;
+                old[q] = 0.0;
+                if (q < nround) {
+                    const int idx = d0 + q * 64 + lane;
+                    if (idx < d1) {
+                        rr[q] = a.dep[idx];
+                        old[q] = prop_lds(a.desc[rr[q]], lx);
+                    }
+                }
+            }
+        }
+        // fire j
+        const int32_t c0 = a.chg_ptr[j], c1 = a.chg_ptr[j + 1];
+        __builtin_amdgcn_wave_barrier();
+        bool lbad = false;
+        if (lane < c1 - c0) {
+            const int32_t pc = a.chg[c0 + lane];
+            const int32_t s = change_species(pc);
+            const int32_t nv = lx[s] + change_delta(pc);
+            lx[s] = nv;
+            lbad = (nv < 0) || (nv > WE_COUNT_MAX_DEV);
+        }
+        __builtin_amdgcn_wave_barrier();
+        fired += 1;
+        if (__ballot(lbad)) { bad = true; break; }
+
+        // fold the dependents' changes into the chunk sums
+        if (nround <= WAVE_DEP_ROUNDS) {
+#pragma unroll
+            for (int q = 0; q < WAVE_DEP_ROUNDS; ++q) {
+                if (q < nround) {
+                    double dv = 0.0;
+                    if (rr[q] >= 0) dv = prop_lds(a.desc[rr[q]], lx) - old[q];
+                    add_chunk_deltas(lchunk, rr[q], dv, lane);
+                    __builtin_amdgcn_wave_barrier();
+                }
+            }
+            csum = lchunk[lane];
+        } else {
+            // very long dependency list: rebuild every chunk sum
+            csum = 0.0;
+            for (int c = 0; c < K; ++c) {
+                const double tot = chunk_total(a, lx, c, lane);
+                if (lane == c) csum = tot;
+            }
+            lchunk[lane] = csum;
+        }
+    }
+    if (bad && lane == 0) atomicOr(a.err, WE_DERR_OVERFLOW);
+    __builtin_amdgcn_wave_barrier();
+    for (int s = lane; s < S; s += 64) xw[s] = lx[s];
+    if (lane == 0) a.ev_walker[(size_t)run * a.cap + k] = fired;
+}
+

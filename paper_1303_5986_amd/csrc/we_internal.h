@@ -86,6 +86,14 @@ struct we_sim {
     double *d_bin_edges_grid = nullptr;
 };
 
+// we_runtime.hip
+extern "C" void we_batch_destroy(we_batch *b);
+we_status we_sim_bookkeeping(we_sim *s, hipStream_t st, hipEvent_t *ev);
+hipError_t launch_ssa_lane(const SimArgs &a, int32_t *xs, hipStream_t st);
+hipError_t launch_ssa_wave(const SimArgs &a, int32_t *xs, hipStream_t st);
+bool lane_kernel_fits(int32_t S, int32_t R);
+bool wave_kernel_fits(int32_t S, int32_t R);
+
 // committor.hip
 hipError_t committor_record(we_sim *s, hipStream_t st);
 hipError_t committor_bin(we_sim *s, int32_t *x_cur, hipStream_t st);

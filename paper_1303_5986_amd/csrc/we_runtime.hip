@@ -457,12 +457,43 @@ we_status read_err(we_sim *s) {
 }
 }  // namespace
 
+// Everything after propagation: recycle and bin, resample and gather,
+// observables, the device iteration counter, records; flips the buffers.
+// ev (optional) points at three events: ev[0] already recorded after the
+// SSA step; ev[1] and ev[2] are recorded here.
+we_status we_sim_bookkeeping(we_sim *s, hipStream_t st, hipEvent_t *ev) {
+    SimArgs &a = s->args;
+    const int32_t c = s->cur, nx = 1 - c;
+    hipError_t e = launch_recycle_bin(a, s->x[c], !s->cm.active, st);
+    if (e != hipSuccess) return hip_fail(e, "recycle/bin launch");
+    if (s->cm.active) {
+        e = committor_bin(s, s->x[c], st);
+        if (e != hipSuccess) return hip_fail(e, "committor bin launch");
+    }
+    e = launch_resample(a, s->x[c], s->w[c], s->x[nx], s->w[nx], st);
+    if (e != hipSuccess) return hip_fail(e, "resample launch");
+    if (ev) HIP_TRY(hipEventRecord(ev[1], st));
+    if (a.nh > 0 || a.n_joint > 0) {
+        e = launch_observe(a, s->x[nx], s->w[nx], st);
+        if (e != hipSuccess) return hip_fail(e, "observe launch");
+    }
+    e = launch_advance(a, st);
+    if (e != hipSuccess) return hip_fail(e, "advance launch");
+    if (ev) HIP_TRY(hipEventRecord(ev[2], st));
+    s->cur = nx;
+    if (!s->capturing) {
+        e = committor_record(s, st);
+        if (e != hipSuccess) return hip_fail(e, "record launch");
+    }
+    return WE_OK;
+}
+
 namespace {
 // Launch one WE iteration on stream st.  Buffers alternate between
 // iterations; the iteration number is read by the kernels from device memory.
 we_status launch_iteration(we_sim *s, hipStream_t st, bool profile) {
     SimArgs &a = s->args;
-    const int32_t c = s->cur, nx = 1 - c;
+    const int32_t c = s->cur;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     if (profile) {
         if (s->ev_used + 4 > 4096) HIP_TRY(drain_profile(s));
@@ -473,28 +504,7 @@ we_status launch_iteration(we_sim *s, hipStream_t st, bool profile) {
                                                  : launch_ssa_lane(a, s->x[c], st);
     if (e != hipSuccess) return hip_fail(e, "SSA launch");
     if (profile) HIP_TRY(hipEventRecord(ev[1], st));
-    e = launch_recycle_bin(a, s->x[c], !s->cm.active, st);
-    if (e != hipSuccess) return hip_fail(e, "recycle/bin launch");
-    if (s->cm.active) {
-        e = committor_bin(s, s->x[c], st);
-        if (e != hipSuccess) return hip_fail(e, "committor bin launch");
-    }
-    e = launch_resample(a, s->x[c], s->w[c], s->x[nx], s->w[nx], st);
-    if (e != hipSuccess) return hip_fail(e, "resample launch");
-    if (profile) HIP_TRY(hipEventRecord(ev[2], st));
-    if (a.nh > 0 || a.n_joint > 0) {
-        e = launch_observe(a, s->x[nx], s->w[nx], st);
-        if (e != hipSuccess) return hip_fail(e, "observe launch");
-    }
-    e = launch_advance(a, st);
-    if (e != hipSuccess) return hip_fail(e, "advance launch");
-    if (profile) HIP_TRY(hipEventRecord(ev[3], st));
-    s->cur = nx;
-    if (!s->capturing) {
-        e = committor_record(s, st);
-        if (e != hipSuccess) return hip_fail(e, "record launch");
-    }
-    return WE_OK;
+    return we_sim_bookkeeping(s, st, profile ? ev + 1 : nullptr);
 }
 }  // namespace
 

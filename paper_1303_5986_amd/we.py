@@ -30,6 +30,8 @@ EXPORTED = [
     "we_counters", "we_events_series", "we_profile", "we_profile_read",
     "we_train_committor", "we_use_committor_bins", "we_committor_eval", "we_committor_state",
     "we_record_labels", "we_get_record", "we_mlp_loss_grad", "we_adam_step",
+    "we_batch_create", "we_batch_step", "we_batch_graph_capture", "we_batch_graph_replay",
+    "we_batch_sim", "we_batch_info", "we_batch_destroy",
     "we_destroy", "we_last_error",
 ]
 
@@ -113,12 +115,22 @@ def load_library(path: str = LIB_PATH):
     L.we_get_record.argtypes = [vp, i32, vp, vp, vp, vp]
     L.we_mlp_loss_grad.argtypes = [i32, vp, vp, i32, vp, vp, vp, vp]
     L.we_adam_step.argtypes = [i32, vp, vp, vp, vp, C.c_float, i32]
+    L.we_batch_create.argtypes = [i32, vp, vp, vp, vp, i32, C.c_char_p, P(vp)]
+    L.we_batch_step.argtypes = [vp, i32]
+    L.we_batch_graph_capture.argtypes = [vp, i32]
+    L.we_batch_graph_replay.argtypes = [vp, i32]
+    L.we_batch_sim.argtypes = [vp, i32]
+    L.we_batch_sim.restype = vp
+    L.we_batch_info.argtypes = [vp, P(i32), vp]
+    L.we_batch_destroy.argtypes = [vp]
+    L.we_batch_destroy.restype = None
     L.we_destroy.argtypes = [vp]
     L.we_destroy.restype = None
     L.we_last_error.restype = C.c_char_p
     for name in EXPORTED:
         fn = getattr(L, name)
-        if name not in ("we_destroy", "we_destroy_network", "we_last_error"):
+        if name not in ("we_destroy", "we_destroy_network", "we_last_error", "we_batch_sim",
+                        "we_batch_destroy"):
             fn.restype = C.c_int
     _LIB = L
     return L
@@ -405,3 +417,96 @@ def adam_step(params, m, v, grad, lr: float, t: int):
     _check(load_library().we_adam_step(len(p), _ptr(p), _ptr(mm), _ptr(vv), _ptr(g), float(lr),
                                        int(t)))
     return p, mm, vv
+
+
+class _MemberSim(Sim):
+    """A member of a Batch: the getters of Sim on a handle the batch owns."""
+
+    def __init__(self, batch, i, cfg):
+        self.handle = C.c_void_p(load_library().we_batch_sim(batch.handle, i))
+        self.network = batch.networks[i]
+        self.S = cfg.net.S
+        self.n_bins = cfg.n_bins
+        self.n_runs = len(cfg.seeds)
+        self.m_targ = cfg.m_targ
+        self.cap = cfg.m_targ * cfg.n_bins
+        self.tau = cfg.tau
+        self.nh = cfg.hist_hi - cfg.hist_lo + 1 if cfg.hist_hi >= cfg.hist_lo else 0
+        self.n_joint = 0
+        self.joint_cells = 0
+        self._owner = batch
+
+    def close(self):
+        self.handle = None
+
+
+class Batch:
+    """Independent WE runs of different networks stepped together: one
+    persistent propagation launch per kernel variant (we_batch_create)."""
+
+    def __init__(self, cfgs, *, max_iters: int, autotune_iters: int = 0,
+                 cache_path: Optional[str] = None, kernels=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device: libwe.so runs on MI355X only")
+        L = load_library()
+        n = len(cfgs)
+        self.cfgs = cfgs
+        self.networks = [Network(c.net) for c in cfgs]
+        self._keep = []
+        grids = (_Grid * n)()
+        params = (_Params * n)()
+        for i, c in enumerate(cfgs):
+            k = dict(coef=np.ascontiguousarray(c.bin_coef, np.float64),
+                     edges=np.ascontiguousarray(c.edges, np.float64),
+                     seeds=np.ascontiguousarray(c.seeds, np.uint64),
+                     x0=np.ascontiguousarray(c.x0, np.int32),
+                     tgt=None if c.tgt_coef is None else np.ascontiguousarray(c.tgt_coef, np.float64),
+                     xrec=None if c.x_rec is None else np.ascontiguousarray(c.x_rec, np.int32),
+                     joint=np.zeros(1, np.int32))
+            self._keep.append(k)
+            grids[i] = _Grid(len(k["edges"]) - 1, k["coef"].ctypes.data, k["edges"].ctypes.data)
+            kern = WE_KERNEL_AUTO if kernels is None else int(kernels[i])
+            params[i] = _Params(float(c.tau), int(c.m_targ), len(k["seeds"]), int(max_iters), kern,
+                                k["seeds"].ctypes.data, k["x0"].ctypes.data, int(bool(c.recycle)),
+                                _ptr(k["tgt"]), float(c.tgt_thr), _ptr(k["xrec"]),
+                                int(c.hist_species), int(c.hist_lo), int(c.hist_hi),
+                                0, k["joint"].ctypes.data, 1, 1, 0)
+        nets = (C.c_void_p * n)(*[net.handle.value for net in self.networks])
+        self.stream = torch.cuda.current_stream()
+        h = C.c_void_p()
+        _check(L.we_batch_create(n, nets, grids, params, C.c_void_p(self.stream.cuda_stream),
+                                 int(autotune_iters),
+                                 None if cache_path is None else cache_path.encode(), C.byref(h)))
+        self.handle = h
+        self.members = [_MemberSim(self, i, c) for i, c in enumerate(cfgs)]
+
+    def step(self, n: int = 1):
+        _check(load_library().we_batch_step(self.handle, int(n)))
+
+    def graph_capture(self, n: int):
+        _check(load_library().we_batch_graph_capture(self.handle, int(n)))
+
+    def graph_replay(self, times: int = 1):
+        _check(load_library().we_batch_graph_replay(self.handle, int(times)))
+
+    def kernels(self):
+        k = np.zeros(len(self.cfgs), np.int32)
+        n = C.c_int32()
+        _check(load_library().we_batch_info(self.handle, C.byref(n), _ptr(k)))
+        return k
+
+    def synchronize(self):
+        for m in self.members:
+            m.synchronize()
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load_library().we_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -215,9 +215,9 @@ def random_network(seed: int, S: int = 354, R: int = 3680, frac_zeroth: float = 
     mass = rng.integers(1, 4, size=S)
     names = [f"s{i}" for i in range(S)]
     n0 = int(round(frac_zeroth * R))
-    n1 = int(round(frac_uni * R))
+    n1 = max(int(round(frac_uni * R)), S)      # at least one decay per species
     n2 = R - n0 - n1
-    if n1 < S:
+    if n2 < 0:
         raise ValueError("need at least one unimolecular reaction per species (decays)")
     seen = set()
     reactions = []
@@ -251,19 +251,28 @@ def random_network(seed: int, S: int = 354, R: int = 3680, frac_zeroth: float = 
                 prod[names[b]] = prod.get(names[b], 0) + 1
         return prod
 
+    def give_up(tries):
+        if tries > 200000:
+            raise ValueError(f"cannot draw {R} distinct reactions over {S} species")
+        return tries + 1
+
     for s in range(S):
         add({names[s]: 1}, {})
-    while len(reactions) < S + (n1 - S):
+    tries = 0
+    while len(reactions) < n1:
+        tries = give_up(tries)
         s = int(rng.integers(0, S))
         prod = products_within(int(mass[s]))
         if not prod:
             continue
         add({names[s]: 1}, prod)
     while len(reactions) < n1 + n2:
+        tries = give_up(tries)
         a, b = (int(v) for v in rng.integers(0, S, size=2))
         reac = {names[a]: 2} if a == b else {names[a]: 1, names[b]: 1}
         add(reac, products_within(int(mass[a] + mass[b])))
     while len(reactions) < R:
+        tries = give_up(tries)
         # inflow of one molecule, or of two once single inflows run out
         a, b = (int(v) for v in rng.integers(0, S, size=2))
         prod = {names[a]: 1} if rng.random() < 0.5 or len(reactions) - n1 - n2 >= S // 2 \
@@ -420,3 +429,39 @@ def toggle_config(seed0: int = 100, n_runs: int = 16, n_bins: int = 64, m_targ: 
     cfg.toggle_seed = seed
     cfg.a_thr = -thr          # A region for committor labels: Delta <= -thr
     return cfg
+
+
+# --------------------------------------------------------------------------
+# A batch of independent runs on networks of uneven size.
+# --------------------------------------------------------------------------
+def batch_configs(n_runs: int = 64, seed: int = 7, r_max: int = 3680, w_min: int = 256,
+                  w_max: int = 8192, n_bins: int = 16, tau: float = 0.01,
+                  n_iters: int = 200) -> List[WEConfig]:
+    """Run k of n: R_k = round(8 * (r_max/8)^(k/(n-1))) reactions,
+    S_k = max(round(R_k * 354/3680), min(8, R_k // 3)) species (the floor
+    leaves the smallest networks enough species to draw distinct reactions
+    under the mass rule), walker slots
+    W_k = w_min * (w_max/w_min)^(pi(k)/(n-1)) with pi a seeded permutation
+    (so network size and walker count are not correlated), 16 bins on the
+    species chosen by the same structural rule as the large network, initial
+    counts log-uniform on [0, 20], no recycling."""
+    rng = np.random.default_rng(seed)
+    perm = rng.permutation(n_runs)
+    out = []
+    for k in range(n_runs):
+        f = k / max(n_runs - 1, 1)
+        R = int(round(8 * (r_max / 8) ** f))
+        S = max(int(round(R * 354 / 3680)), min(8, R // 3))
+        W = int(round(w_min * (w_max / w_min) ** (perm[k] / max(n_runs - 1, 1))))
+        m = max(1, W // n_bins)
+        net = random_network(seed * 1000 + k, S, R)
+        x0 = log_uniform_counts(np.random.default_rng(seed * 1000 + k + 1), S, hi=20)
+        score = x0 * np.exp(-first_order_loss(net))
+        bs = int(sorted(range(S), key=lambda s: (-score[s], s))[0])
+        coef = np.zeros(S)
+        coef[bs] = 1.0
+        out.append(WEConfig(name=f"batch{k}", net=net, x0=x0, bin_coef=coef,
+                            edges=uniform_edges(0.0, 2.0 * n_bins, n_bins), m_targ=m, tau=tau,
+                            n_iters=n_iters, seeds=np.array([seed * 1000 + k], np.uint64),
+                            hist_species=bs, hist_lo=0, hist_hi=-1))
+    return out
