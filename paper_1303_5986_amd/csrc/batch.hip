@@ -10,10 +10,13 @@
 //   lane variants: a tile is 64 consecutive walker slots, one per lane;
 //   wave variant:  a tile is one walker slot, one wave.
 // Items of cheap and expensive runs mix freely, so uneven runs balance
-// across the chip.  Resampling and the observables stay per run (they are
-// microseconds each), all on the same stream; the whole iteration can be
-// captured as a HIP graph (the work counters are cleared by a kernel, not a
-// memset, so replays are safe).
+// across the chip.  The bookkeeping is batched the same way: recycle/bin,
+// resample (one workgroup per run of every member), gather, observe and the
+// iteration counters are one launch each, with the member index on grid y;
+// a member's arguments and buffers are read from device tables.  The whole
+// iteration can be captured as a HIP graph (the work counters are cleared
+// by a kernel, not a memset, so replays are safe).  A batch bins on grids
+// only (no learned bins, no records).
 //
 // Autotuning: for a network that fits both kernels, a short pilot of each
 // (timed with HIP events) picks the faster; the choice is cached in a JSON
@@ -94,6 +97,20 @@ __global__ void batch_reset_kernel(uint32_t *counters, int32_t n) {
     if (i < n) counters[i] = 0u;
 }
 
+struct BatchPtrs {
+    const SimArgs *args;
+    int32_t *const *x_cur;
+    int32_t *const *x_nxt;
+    const double *const *w_cur;
+    double *const *w_nxt;
+    const int32_t *use_lds;
+    const int32_t *grid_bins;
+};
+hipError_t launch_batch_bookkeeping(const BatchPtrs &b, int32_t n_sims, int64_t max_slots, int32_t max_runs,
+                                    int64_t max_cells, size_t shmem, bool observe, hipStream_t st);
+bool resample_uses_lds(const SimArgs &a);
+size_t resample_lds_bytes(const SimArgs &a, bool use_lds);
+
 struct we_batch {
     hipStream_t stream = nullptr;
     std::vector<we_sim *> sims;
@@ -103,6 +120,12 @@ struct we_batch {
     uint32_t *d_counters = nullptr;
     SimArgs *d_args = nullptr;
     int32_t **d_xptr[2] = {nullptr, nullptr};
+    double **d_wptr[2] = {nullptr, nullptr};
+    int32_t *d_use_lds = nullptr, *d_grid_bins = nullptr;
+    int64_t max_slots = 0, max_cells = 0;
+    int32_t max_runs = 0;
+    size_t resample_shmem = 0;
+    bool observe = false;
     int32_t s_pad = 4;
     int32_t iter = 0, max_iters = 0;
     hipGraphExec_t graph_exec = nullptr;
@@ -197,6 +220,8 @@ we_status build_items(we_batch *b) {
 }
 
 we_status launch_batch_iteration(we_batch *b, hipStream_t st) {
+    for (we_sim *s : b->sims)
+        if (s->cm.active) return we_fail(WE_ESTATE, "learned bins are not supported inside a batch");
     const int32_t parity = b->sims[0]->cur;
     hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(64), 0, st, b->d_counters, (int32_t)V_COUNT);
     HIP_TRY(hipGetLastError());
@@ -227,10 +252,14 @@ we_status launch_batch_iteration(we_batch *b, hipStream_t st) {
         }
         HIP_TRY(hipGetLastError());
     }
-    for (we_sim *s : b->sims) {
-        we_status r = we_sim_bookkeeping(s, st, nullptr);
-        if (r != WE_OK) return r;
-    }
+    // recycle/bin, committor bins where active, resample, gather, observe,
+    // advance: one launch per step for all members
+    BatchPtrs bp{b->d_args, b->d_xptr[parity], b->d_xptr[1 - parity],
+                 (const double *const *)b->d_wptr[parity], b->d_wptr[1 - parity], b->d_use_lds,
+                 b->d_grid_bins};
+    HIP_TRY(launch_batch_bookkeeping(bp, (int32_t)b->sims.size(), b->max_slots, b->max_runs, b->max_cells,
+                                     b->resample_shmem, b->observe, st));
+    for (we_sim *s : b->sims) s->cur = 1 - s->cur;
     return WE_OK;
 }
 
@@ -290,11 +319,31 @@ extern "C" we_status we_batch_create(int32_t n, const we_network *const *nets, c
     }
     std::vector<SimArgs> args;
     std::vector<int32_t *> xp0, xp1;
+    std::vector<double *> wp0, wp1;
+    std::vector<int32_t> use_lds, grid_bins;
     for (we_sim *s : b->sims) {
         args.push_back(s->args);
         xp0.push_back(s->x[0]);
         xp1.push_back(s->x[1]);
+        wp0.push_back(s->w[0]);
+        wp1.push_back(s->w[1]);
+        const bool ul = resample_uses_lds(s->args);
+        use_lds.push_back(ul ? 1 : 0);
+        grid_bins.push_back(1);
+        b->resample_shmem = std::max(b->resample_shmem, resample_lds_bytes(s->args, ul));
+        b->max_slots = std::max<int64_t>(b->max_slots, (int64_t)s->n_runs * s->cap);
+        b->max_cells = std::max<int64_t>(b->max_cells, (int64_t)s->n_runs * s->cap * s->S);
+        b->max_runs = std::max(b->max_runs, s->n_runs);
+        b->observe = b->observe || s->args.nh > 0 || s->args.n_joint > 0;
     }
+    HIP_TRY(hipMalloc(&b->d_wptr[0], sizeof(double *) * n));
+    HIP_TRY(hipMalloc(&b->d_wptr[1], sizeof(double *) * n));
+    HIP_TRY(hipMemcpy(b->d_wptr[0], wp0.data(), sizeof(double *) * n, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(b->d_wptr[1], wp1.data(), sizeof(double *) * n, hipMemcpyHostToDevice));
+    HIP_TRY(hipMalloc(&b->d_use_lds, sizeof(int32_t) * n));
+    HIP_TRY(hipMalloc(&b->d_grid_bins, sizeof(int32_t) * n));
+    HIP_TRY(hipMemcpy(b->d_use_lds, use_lds.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(b->d_grid_bins, grid_bins.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice));
     HIP_TRY(hipMalloc(&b->d_args, sizeof(SimArgs) * n));
     HIP_TRY(hipMemcpy(b->d_args, args.data(), sizeof(SimArgs) * n, hipMemcpyHostToDevice));
     HIP_TRY(hipMalloc(&b->d_xptr[0], sizeof(int32_t *) * n));
@@ -384,6 +433,10 @@ extern "C" void we_batch_destroy(we_batch *b) {
     (void)hipFree(b->d_args);
     (void)hipFree(b->d_xptr[0]);
     (void)hipFree(b->d_xptr[1]);
+    (void)hipFree(b->d_wptr[0]);
+    (void)hipFree(b->d_wptr[1]);
+    (void)hipFree(b->d_use_lds);
+    (void)hipFree(b->d_grid_bins);
     if (b->graph_exec) (void)hipGraphExecDestroy(b->graph_exec);
     if (b->capture_stream) (void)hipStreamDestroy(b->capture_stream);
     delete b;

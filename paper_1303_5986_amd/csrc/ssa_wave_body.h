@@ -1,46 +1,82 @@
 // ssa_wave_body.h -- the wave-per-walker event loop, shared by the per-sim
 // kernel and the batched persistent kernel.
+//
+// Cross-lane work uses the CDNA data-parallel primitives directly:
+//  * inclusive prefix sums of FP64 values: four DPP row shifts (1, 2, 4, 8)
+//    build scans inside each 16-lane row, then the row_bcast:15 and
+//    row_bcast:31 broadcasts carry row totals across the wave -- six steps
+//    of two 32-bit DPP moves and one add, no LDS round trip;
+//  * broadcasts of one lane: v_readlane;
+//  * neighbour exchange: wave_shr / wave_shl DPP.
+// Per event the dependent loads from global memory are: the descriptors of
+// the chosen chunk (64 lanes, one 16-byte load each), then one packed
+// header of the chosen reaction, then its dependency entries (each carrying
+// the descriptor of the reaction it names) together with its changes.
 #pragma once
 #include "we_common.h"
 
 #define WAVE_WALKERS_PER_BLOCK 4
-#define WAVE_DEP_ROUNDS 4
+#define WAVE_DEP_ROUNDS 2
 
 namespace {
 
-__device__ __forceinline__ double prop_lds(const RxnDesc &d, const int32_t *lx) {
+template <class D>
+__device__ __forceinline__ double prop_lds(const D &d, const int32_t *lx) {
     return propensity_from(d, (uint32_t)lx[d.s1], (uint32_t)lx[d.s2]);
 }
 
-__device__ __forceinline__ double scan_incl(double v, int lane) {
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const double t = __shfl_up(v, off, 64);
-        if (lane >= off) v = v + t;
-    }
+union F64Bits {
+    double d;
+    int32_t w[2];
+};
+
+template <int CTRL, int ROW_MASK, bool BOUND>
+__device__ __forceinline__ double dpp_f64(double v) {
+    F64Bits in, out;
+    in.d = v;
+    out.w[0] = __builtin_amdgcn_update_dpp(0, in.w[0], CTRL, ROW_MASK, 0xF, BOUND);
+    out.w[1] = __builtin_amdgcn_update_dpp(0, in.w[1], CTRL, ROW_MASK, 0xF, BOUND);
+    return out.d;
+}
+
+// Inclusive prefix sum over the 64 lanes (fixed order, reproducible).
+__device__ __forceinline__ double scan_incl(double v) {
+    v = v + dpp_f64<0x111, 0xF, true>(v);    // row_shr:1
+    v = v + dpp_f64<0x112, 0xF, true>(v);    // row_shr:2
+    v = v + dpp_f64<0x114, 0xF, true>(v);    // row_shr:4
+    v = v + dpp_f64<0x118, 0xF, true>(v);    // row_shr:8
+    v = v + dpp_f64<0x142, 0xA, false>(v);   // row_bcast:15 into rows 1 and 3
+    v = v + dpp_f64<0x143, 0xC, false>(v);   // row_bcast:31 into rows 2 and 3
     return v;
+}
+
+__device__ __forceinline__ double lane_value(double v, int lane) {
+    F64Bits in, out;
+    in.d = v;
+    out.w[0] = __builtin_amdgcn_readlane(in.w[0], lane);
+    out.w[1] = __builtin_amdgcn_readlane(in.w[1], lane);
+    return out.d;
 }
 
 __device__ __forceinline__ int32_t last_set(unsigned long long m) {
     return m ? 63 - __clzll((long long)m) : -1;
 }
 
-// Sum of all 64 propensities of chunk c, as the last lane of an inclusive scan.
+// Sum of all 64 propensities of chunk c (last lane of the scan).
 __device__ __forceinline__ double chunk_total(const SimArgs &a, const int32_t *lx, int c, int lane) {
     const int r = c * 64 + lane;
     double v = 0.0;
     if (r < a.R) v = prop_lds(a.desc[r], lx);
-    v = scan_incl(v, lane);
-    return __shfl(v, 63, 64);
+    return lane_value(scan_incl(v), 63);
 }
 
 // Add, per chunk, the propensity changes held by the lanes (dependent
 // reaction rr, change dv; rr < 0 for idle lanes).  rr ascends across lanes.
 __device__ __forceinline__ void add_chunk_deltas(double *lchunk, int rr, double dv, int lane) {
     const int ch = rr >= 0 ? (rr >> 6) : 64;
-    const double D = scan_incl(dv, lane);
-    const int ch_prev = __shfl_up(ch, 1, 64);
-    const int ch_next = __shfl_down(ch, 1, 64);
+    const double D = scan_incl(dv);
+    const int ch_prev = __builtin_amdgcn_update_dpp(-1, ch, 0x138, 0xF, 0xF, false);   // wave_shr:1
+    const int ch_next = __builtin_amdgcn_update_dpp(-1, ch, 0x130, 0xF, 0xF, false);   // wave_shl:1
     const bool start = (lane == 0) || (ch_prev != ch);
     const bool end = (lane == 63) || (ch_next != ch);
     const unsigned long long smask = __ballot(start);
@@ -55,8 +91,8 @@ __device__ __forceinline__ void add_chunk_deltas(double *lchunk, int rr, double 
 
 // One walker through one interval on the calling wave; lchunk (64 doubles)
 // and lx (S ints) are this wave's LDS slices.
-__device__ void wave_walker(const SimArgs &a, int32_t *__restrict__ xs, int32_t run, int32_t k,
-                            uint32_t iter, double *lchunk, int32_t *lx) {
+__device__ inline void wave_walker(const SimArgs &a, int32_t *__restrict__ xs, int32_t run, int32_t k,
+                                   uint32_t iter, double *lchunk, int32_t *lx) {
     const int lane = threadIdx.x & 63;
     const int32_t S = a.S, R = a.R;
     const int32_t K = (R + 63) >> 6;
@@ -80,8 +116,8 @@ __device__ void wave_walker(const SimArgs &a, int32_t *__restrict__ xs, int32_t 
     bool bad = false;
 
     for (;;) {
-        const double P = scan_incl(csum, lane);
-        const double a0 = __shfl(P, 63, 64);
+        const double P = scan_incl(csum);
+        const double a0 = lane_value(P, 63);
         if (!(a0 > 0.0)) break;
         const U4 rnd = philox4x32_10(e, (uint32_t)k, iter, 0u, k0, k1);
         e += 1;
@@ -96,47 +132,50 @@ __device__ void wave_walker(const SimArgs &a, int32_t *__restrict__ xs, int32_t 
         const unsigned long long m1 = __ballot(P > target);
         int cs = m1 ? (__ffsll((long long)m1) - 1) : last_set(__ballot(csum > 0.0));
         if (cs < 0) cs = 0;
-        const double base = __shfl(P - csum, cs, 64);
+        cs = __builtin_amdgcn_readfirstlane(cs);
+        const double base = lane_value(P - csum, cs);
         const double target2 = target - base;
         // reaction inside the chunk
         const int rsel = cs * 64 + lane;
         double v = 0.0;
         if (rsel < R) v = prop_lds(a.desc[rsel], lx);
-        const double Q = scan_incl(v, lane);
+        const double Q = scan_incl(v);
         const unsigned long long m2 = __ballot(Q > target2);
         const int ls = m2 ? (__ffsll((long long)m2) - 1) : last_set(__ballot(v > 0.0));
         if (ls < 0) {              // chunk sum drifted above an all-zero chunk
             if (lane == 0) atomicOr(a.err, WE_DERR_SELECT);
             break;
         }
-        const int j = cs * 64 + ls;
+        const int j = __builtin_amdgcn_readfirstlane(cs * 64 + ls);
 
-        // propensities of the dependents before the change
-        const int32_t d0 = a.dep_ptr[j], d1 = a.dep_ptr[j + 1];
-        const int32_t nd = d1 - d0;
+        // header of j; its dependents (with descriptors) and changes
+        const RxnInfo info = a.rinfo[j];
+        const int32_t nd = info.dep_count;
         const int nround = (nd + 63) >> 6;
+        int32_t pc = 0;
+        if (lane < info.chg_count) pc = a.chg[info.chg_begin + lane];
         int rr[WAVE_DEP_ROUNDS];
         double old[WAVE_DEP_ROUNDS];
+        DepEntry de[WAVE_DEP_ROUNDS];
         if (nround <= WAVE_DEP_ROUNDS) {
 #pragma unroll
             for (int q = 0; q < WAVE_DEP_ROUNDS; ++q) {
                 rr[q] = -1;
                 old[q] = 0.0;
                 if (q < nround) {
-                    const int idx = d0 + q * 64 + lane;
-                    if (idx < d1) {
-                        rr[q] = a.dep[idx];
-                        old[q] = prop_lds(a.desc[rr[q]], lx);
+                    const int idx = q * 64 + lane;
+                    if (idx < nd) {
+                        de[q] = a.deps[info.dep_begin + idx];
+                        rr[q] = de[q].r;
+                        old[q] = prop_lds(de[q], lx);
                     }
                 }
             }
         }
         // fire j
-        const int32_t c0 = a.chg_ptr[j], c1 = a.chg_ptr[j + 1];
         __builtin_amdgcn_wave_barrier();
         bool lbad = false;
-        if (lane < c1 - c0) {
-            const int32_t pc = a.chg[c0 + lane];
+        if (lane < info.chg_count) {
             const int32_t s = change_species(pc);
             const int32_t nv = lx[s] + change_delta(pc);
             lx[s] = nv;
@@ -152,7 +191,7 @@ __device__ void wave_walker(const SimArgs &a, int32_t *__restrict__ xs, int32_t 
             for (int q = 0; q < WAVE_DEP_ROUNDS; ++q) {
                 if (q < nround) {
                     double dv = 0.0;
-                    if (rr[q] >= 0) dv = prop_lds(a.desc[rr[q]], lx) - old[q];
+                    if (rr[q] >= 0) dv = prop_lds(de[q], lx) - old[q];
                     add_chunk_deltas(lchunk, rr[q], dv, lane);
                     __builtin_amdgcn_wave_barrier();
                 }
@@ -173,4 +212,3 @@ __device__ void wave_walker(const SimArgs &a, int32_t *__restrict__ xs, int32_t 
     for (int s = lane; s < S; s += 64) xw[s] = lx[s];
     if (lane == 0) a.ev_walker[(size_t)run * a.cap + k] = fired;
 }
-

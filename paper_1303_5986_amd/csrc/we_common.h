@@ -31,6 +31,20 @@ struct __align__(16) RxnDesc {
     uint8_t order;   // nu1 + nu2
 };
 
+// Where a reaction's dependency entries and changes start, in one load.
+struct __align__(16) RxnInfo {
+    int32_t dep_begin, dep_count, chg_begin, chg_count;
+};
+
+// One reaction whose propensity changes when a given reaction fires, with
+// its own descriptor inline (so no second lookup is needed).
+struct __align__(16) DepEntry {
+    double c;
+    uint16_t s1, s2;
+    uint8_t nu1, nu2;
+    uint16_t r;
+};
+
 // Species change of a reaction, packed as (species << 16) | (delta & 0xffff).
 __host__ __device__ inline int32_t pack_change(int32_t s, int32_t d) {
     return (int32_t)(((uint32_t)s << 16) | ((uint32_t)d & 0xffffu));
@@ -46,6 +60,8 @@ struct SimArgs {
     const int32_t *__restrict__ chg;     // packed changes
     const int32_t *__restrict__ dep_ptr; // [R+1] reactions whose propensity a reaction changes
     const uint16_t *__restrict__ dep;    //       (sorted, unique)
+    const RxnInfo *__restrict__ rinfo;   // [R]
+    const DepEntry *__restrict__ deps;   // dependency entries with descriptors
     int32_t S, R;
     // runs
     int32_t n_runs, cap, n_bins, m_targ, max_iters;
@@ -120,7 +136,8 @@ __device__ __forceinline__ uint64_t binom_small(uint32_t x, uint32_t nu) {
 }
 
 // a_j = c_j * h_j(x), h_j exact in int64 and converted once.
-__device__ __forceinline__ double propensity_from(const RxnDesc &d, uint32_t x1, uint32_t x2) {
+template <class D>
+__device__ __forceinline__ double propensity_from(const D &d, uint32_t x1, uint32_t x2) {
     const uint64_t h = binom_small(x1, d.nu1) * binom_small(x2, d.nu2);
     return d.c * (double)h;
 }

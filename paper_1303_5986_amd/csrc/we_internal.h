@@ -29,6 +29,8 @@ struct we_network {
     RxnDesc *d_desc = nullptr;
     int32_t *d_chg_ptr = nullptr, *d_chg = nullptr, *d_dep_ptr = nullptr;
     uint16_t *d_dep = nullptr;
+    RxnInfo *d_rinfo = nullptr;
+    DepEntry *d_deps = nullptr;
 };
 
 // The learned committor attached to a sim (see committor.hip).

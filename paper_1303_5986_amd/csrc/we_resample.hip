@@ -40,9 +40,8 @@ __device__ __forceinline__ double coord_of(const double *__restrict__ coef,
     return q;
 }
 
-__global__ __launch_bounds__(256) void we_recycle_bin_kernel(SimArgs a, int32_t *__restrict__ x_cur,
-                                                             int32_t grid_bins) {
-    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void recycle_bin_one(const SimArgs &a, int32_t *__restrict__ x_cur, int32_t grid_bins,
+                                                int64_t gid) {
     const int32_t run = (int32_t)(gid / a.cap);
     const int32_t k = (int32_t)(gid - (int64_t)run * a.cap);
     if (run >= a.n_runs) return;
@@ -59,6 +58,11 @@ __global__ __launch_bounds__(256) void we_recycle_bin_kernel(SimArgs a, int32_t 
     if (grid_bins) a.s_bin[idx] = bin_index(a.edges, a.n_bins, coord_of(a.bin_coef, row, S));
 }
 
+__global__ __launch_bounds__(256) void we_recycle_bin_kernel(SimArgs a, int32_t *__restrict__ x_cur,
+                                                             int32_t grid_bins) {
+    recycle_bin_one(a, x_cur, grid_bins, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
 // Per-walker working arrays of one run: LDS when the run fits, else global.
 struct RunWork {
     double *w;          // weights in bin-major order
@@ -67,10 +71,9 @@ struct RunWork {
     uint16_t *cnt;      // copies / alive flags in bin-major order
 };
 
-__global__ __launch_bounds__(256) void we_resample_kernel(SimArgs a, const double *__restrict__ w_cur,
-                                                          double *__restrict__ w_nxt, int32_t use_lds) {
-    extern __shared__ __align__(16) unsigned char lds[];
-    const int32_t run = blockIdx.x;
+__device__ __forceinline__ void resample_run(const SimArgs &a, const double *__restrict__ w_cur,
+                                             double *__restrict__ w_nxt, int32_t use_lds, int32_t run,
+                                             unsigned char *lds) {
     const int32_t tid = threadIdx.x, nthr = blockDim.x;
     const int32_t NB = a.n_bins, M = a.m_targ, cap = a.cap;
     __shared__ int64_t ev_part[256];
@@ -242,10 +245,15 @@ __global__ __launch_bounds__(256) void we_resample_kernel(SimArgs a, const doubl
     if (tid == 0) a.n_walk[run] = ostart[NB];
 }
 
+__global__ __launch_bounds__(256) void we_resample_kernel(SimArgs a, const double *__restrict__ w_cur,
+                                                          double *__restrict__ w_nxt, int32_t use_lds) {
+    extern __shared__ __align__(16) unsigned char lds[];
+    resample_run(a, w_cur, w_nxt, use_lds, blockIdx.x, lds);
+}
+
 // New state rows from their parents: one lane per copy number.
-__global__ __launch_bounds__(256) void we_gather_rows_kernel(SimArgs a, const int32_t *__restrict__ x_cur,
-                                                             int32_t *__restrict__ x_nxt) {
-    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void gather_one(const SimArgs &a, const int32_t *__restrict__ x_cur,
+                                           int32_t *__restrict__ x_nxt, int64_t gid) {
     const int64_t per_run = (int64_t)a.cap * a.S;
     const int32_t run = (int32_t)(gid / per_run);
     if (run >= a.n_runs) return;
@@ -258,10 +266,15 @@ __global__ __launch_bounds__(256) void we_gather_rows_kernel(SimArgs a, const in
     x_nxt[(base + dst) * a.S + s] = x_cur[(base + src) * a.S + s];
 }
 
+__global__ __launch_bounds__(256) void we_gather_rows_kernel(SimArgs a, const int32_t *__restrict__ x_cur,
+                                                             int32_t *__restrict__ x_nxt) {
+    gather_one(a, x_cur, x_nxt, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
 // P(x_s = k, t) accumulated over iterations: one lane per walker, FP64 atomics.
-__global__ __launch_bounds__(256) void we_observe_kernel(SimArgs a, const int32_t *__restrict__ xs,
-                                                         const double *__restrict__ ws) {
-    const int32_t gid = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
+__device__ __forceinline__ void observe_one(const SimArgs &a, const int32_t *__restrict__ xs,
+                                            const double *__restrict__ ws, int64_t gid64) {
+    const int32_t gid = (int32_t)gid64;
     const int32_t run = gid / a.cap;
     const int32_t k = gid - run * a.cap;
     if (run >= a.n_runs) return;
@@ -283,6 +296,65 @@ __global__ __launch_bounds__(256) void we_observe_kernel(SimArgs a, const int32_
     }
 }
 
+__global__ __launch_bounds__(256) void we_observe_kernel(SimArgs a, const int32_t *__restrict__ xs,
+                                                         const double *__restrict__ ws) {
+    observe_one(a, xs, ws, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// ---------------------------------------------------------------- batched
+// The same steps for many sims in one launch each: grid y = sim, per-sim
+// arguments and buffer pointers read from device memory.
+struct BatchPtrs {
+    const SimArgs *args;
+    int32_t *const *x_cur;
+    int32_t *const *x_nxt;
+    const double *const *w_cur;
+    double *const *w_nxt;
+    const int32_t *use_lds;
+    const int32_t *grid_bins;
+};
+
+__global__ __launch_bounds__(256) void we_batch_recycle_bin_kernel(BatchPtrs b) {
+    const int32_t i = blockIdx.y;
+    recycle_bin_one(b.args[i], b.x_cur[i], b.grid_bins[i], (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+__global__ __launch_bounds__(256) void we_batch_resample_kernel(BatchPtrs b) {
+    extern __shared__ __align__(16) unsigned char lds[];
+    const int32_t i = blockIdx.y;
+    const SimArgs &a = b.args[i];
+    if ((int32_t)blockIdx.x >= a.n_runs) return;
+    resample_run(a, b.w_cur[i], b.w_nxt[i], b.use_lds[i], blockIdx.x, lds);
+}
+
+__global__ __launch_bounds__(256) void we_batch_gather_kernel(BatchPtrs b) {
+    const int32_t i = blockIdx.y;
+    gather_one(b.args[i], b.x_cur[i], b.x_nxt[i], (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+__global__ __launch_bounds__(256) void we_batch_observe_kernel(BatchPtrs b) {
+    const int32_t i = blockIdx.y;
+    const SimArgs &a = b.args[i];
+    if (a.nh <= 0 && a.n_joint <= 0) return;
+    observe_one(a, b.x_nxt[i], b.w_nxt[i], (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+__global__ void we_batch_advance_kernel(BatchPtrs b, int32_t n) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) *b.args[i].iter_dev += 1u;
+}
+
+hipError_t launch_batch_bookkeeping(const BatchPtrs &b, int32_t n_sims, int64_t max_slots, int32_t max_runs,
+                                    int64_t max_cells, size_t shmem, bool observe, hipStream_t st) {
+    const unsigned gs = (unsigned)((max_slots + 255) / 256);
+    hipLaunchKernelGGL(we_batch_recycle_bin_kernel, dim3(gs, n_sims), dim3(256), 0, st, b);
+    hipLaunchKernelGGL(we_batch_resample_kernel, dim3(max_runs, n_sims), dim3(256), shmem, st, b);
+    hipLaunchKernelGGL(we_batch_gather_kernel, dim3((unsigned)((max_cells + 255) / 256), n_sims), dim3(256), 0, st, b);
+    if (observe) hipLaunchKernelGGL(we_batch_observe_kernel, dim3(gs, n_sims), dim3(256), 0, st, b);
+    hipLaunchKernelGGL(we_batch_advance_kernel, dim3((n_sims + 63) / 64), dim3(64), 0, st, b, n_sims);
+    return hipGetLastError();
+}
+
 hipError_t launch_recycle_bin(const SimArgs &a, int32_t *x_cur, bool grid_bins, hipStream_t st) {
     const int64_t total = (int64_t)a.n_runs * a.cap;
     hipLaunchKernelGGL(we_recycle_bin_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st,
@@ -290,15 +362,20 @@ hipError_t launch_recycle_bin(const SimArgs &a, int32_t *x_cur, bool grid_bins, 
     return hipGetLastError();
 }
 
+bool resample_uses_lds(const SimArgs &a);
 size_t resample_lds_bytes(const SimArgs &a, bool use_lds) {
     size_t b = sizeof(int32_t) * (4 * (size_t)a.n_bins + 2) + 16;
     if (use_lds) b += (size_t)a.cap * (sizeof(double) + sizeof(int32_t) + 2 * sizeof(uint16_t));
     return b;
 }
 
+bool resample_uses_lds(const SimArgs &a) {
+    return a.cap <= RESAMPLE_LDS_CAP && resample_lds_bytes(a, true) <= 150 * 1024;
+}
+
 hipError_t launch_resample(const SimArgs &a, int32_t *x_cur, const double *w_cur, int32_t *x_nxt,
                            double *w_nxt, hipStream_t st) {
-    const bool use_lds = a.cap <= RESAMPLE_LDS_CAP && resample_lds_bytes(a, true) <= 150 * 1024;
+    const bool use_lds = resample_uses_lds(a);
     const size_t shmem = resample_lds_bytes(a, use_lds);
     hipLaunchKernelGGL(we_resample_kernel, dim3(a.n_runs), dim3(256), shmem, st, a, w_cur, w_nxt,
                        use_lds ? 1 : 0);

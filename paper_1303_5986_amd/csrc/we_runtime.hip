@@ -165,6 +165,17 @@ extern "C" we_status we_create_network(int32_t S, int32_t R, const int32_t *reac
         for (int32_t r : tmp) net->dep.push_back((uint16_t)r);
         net->dep_ptr.push_back((int32_t)net->dep.size());
     }
+    std::vector<RxnInfo> rinfo(R);
+    std::vector<DepEntry> deps;
+    for (int32_t j = 0; j < R; ++j) {
+        rinfo[j] = RxnInfo{net->dep_ptr[j], net->dep_ptr[j + 1] - net->dep_ptr[j], chg_ptr[j],
+                           chg_ptr[j + 1] - chg_ptr[j]};
+        for (int32_t p = net->dep_ptr[j]; p < net->dep_ptr[j + 1]; ++p) {
+            const RxnDesc &d = net->desc[net->dep[p]];
+            deps.push_back(DepEntry{d.c, d.s1, d.s2, d.nu1, d.nu2, net->dep[p]});
+        }
+    }
+    if (deps.empty()) deps.push_back(DepEntry{});
     if (net->dep.empty()) net->dep.push_back(0);
     if (net->chg.empty()) net->chg.push_back(0);
     auto up = [&](void **dst, const void *src, size_t bytes) -> hipError_t {
@@ -177,6 +188,8 @@ extern "C" we_status we_create_network(int32_t S, int32_t R, const int32_t *reac
     if (e == hipSuccess) e = up((void **)&net->d_chg, net->chg.data(), 4 * net->chg.size());
     if (e == hipSuccess) e = up((void **)&net->d_dep_ptr, net->dep_ptr.data(), 4 * (R + 1));
     if (e == hipSuccess) e = up((void **)&net->d_dep, net->dep.data(), 2 * net->dep.size());
+    if (e == hipSuccess) e = up((void **)&net->d_rinfo, rinfo.data(), sizeof(RxnInfo) * R);
+    if (e == hipSuccess) e = up((void **)&net->d_deps, deps.data(), sizeof(DepEntry) * deps.size());
     if (e != hipSuccess) {
         we_destroy_network(net);
         return hip_fail(e, "network upload");
@@ -192,6 +205,8 @@ extern "C" void we_destroy_network(we_network *net) {
     (void)hipFree(net->d_chg);
     (void)hipFree(net->d_dep_ptr);
     (void)hipFree(net->d_dep);
+    (void)hipFree(net->d_rinfo);
+    (void)hipFree(net->d_deps);
     delete net;
 }
 
@@ -344,6 +359,7 @@ extern "C" we_status we_init(const we_network *net, const we_grid *g, const we_p
     SimArgs &a = s->args;
     a.desc = net->d_desc; a.chg_ptr = net->d_chg_ptr; a.chg = net->d_chg;
     a.dep_ptr = net->d_dep_ptr; a.dep = net->d_dep;
+    a.rinfo = net->d_rinfo; a.deps = net->d_deps;
     a.S = S; a.R = net->R;
     a.n_runs = n_runs; a.cap = cap; a.n_bins = NB; a.m_targ = M; a.max_iters = max_iters;
     a.tau = p->tau;

@@ -80,7 +80,7 @@ def test_wave_random_networks_match_oracle(S, R, seed):
 
 def test_wave_long_dependency_lists():
     """A hub species used by 300 reactions: firing its inflow changes more
-    propensities than the incremental path holds (4 x 64), which takes the
+    propensities than the incremental path holds (2 x 64), which takes the
     rebuild-all-chunks path."""
     _say("case: wave kernel, hub network (dependency list of 300)")
     names = ["hub"] + [f"s{i}" for i in range(1, 301)]
