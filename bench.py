@@ -62,6 +62,38 @@ def alg_ops_per_event(net) -> float:
     return 100 + 10 + 5 + 2 + per_rxn + nchg + 2
 
 
+def alg_ops_per_event_wave(net) -> float:
+    """Arithmetic of one event of the chunked direct method on one wave, per
+    the same operation model as alg_ops_per_event:
+      random numbers, waiting time, target, time update     = 117
+      chunk-sum scan over K = ceil(R/64) chunks             = K adds + ballot (1)
+      the chosen chunk: 64 propensity evaluations (5 + f each, the mean f
+        over reactions) and a 64-lane scan (63 adds) + ballot (1)
+      dependents of the fired reaction (mean list length d): propensity
+        before and after (2 x (4 + f)), their difference, and the segmented
+        fold into the chunk sums (one add)                  = d x (2 (4 + f) + 2)
+      state update: changed species + 2 bound checks."""
+    fs = []
+    users = [[] for _ in range(net.S)]
+    for j in range(net.R):
+        lo, hi = net.reac_ptr[j], net.reac_ptr[j + 1]
+        f = sum({1: 0, 2: 3, 3: 6}[int(net.reac_mult[p])] for p in range(lo, hi)) + (1 if hi - lo == 2 else 0)
+        fs.append(f)
+        for p in range(lo, hi):
+            users[int(net.reac_species[p])].append(j)
+    fbar = float(np.mean(fs))
+    deps = []
+    for j in range(net.R):
+        d = set()
+        for p in range(net.chg_ptr[j], net.chg_ptr[j + 1]):
+            d.update(users[int(net.chg_species[p])])
+        deps.append(len(d))
+    dbar = float(np.mean(deps))
+    K = (net.R + 63) // 64
+    nchg = float(np.diff(net.chg_ptr).mean())
+    return 117 + K + 1 + 64 * (5 + fbar) + 63 + 1 + dbar * (2 * (4 + fbar) + 2) + nchg + 2
+
+
 def source_digest(paths):
     h = hashlib.sha256()
     for p in paths:
@@ -294,6 +326,9 @@ def main():
                     help="only run a plain device-to-device copy of MIB MiB five times "
                          "(reference kernel for scaling the HBM byte counters)")
     ap.add_argument("--experiment", default="", choices=["", "toggle_mfpt", "batch"])
+    ap.add_argument("--workload", default="schlogl", choices=["schlogl", "large"],
+                    help="schlogl: 2048 Schloegl replicas, lane kernel (default); large: the "
+                         "354-species / 3680-reaction network, 4096 walkers, wave kernel")
     ap.add_argument("--batch-runs", type=int, default=64)
     ap.add_argument("--autotune-iters", type=int, default=3)
     ap.add_argument("--tune-cache", action="store_true")
@@ -331,8 +366,27 @@ def main():
     from paper_1303_5986_amd import we, workloads as wl
 
     K, W = args.steps, args.warmup
-    cfg = wl.schlogl_config(n_runs=args.runs, seed0=1, n_iters=W + K)
-    sim = we.sim_from_config(cfg, kernel=we.WE_KERNEL_LANE, max_iters=W + K)
+    if args.workload == "large":
+        cfg = wl.large_network_config(n_iters=W + K)
+        kernel, kname = we.WE_KERNEL_WAVE, "ssa_wave_kernel"
+        ops_ev = alg_ops_per_event_wave(cfg.net)
+        cfg_desc = {"workload": "large_network_354x3680", "runs": 1, "species": cfg.net.S,
+                    "reactions": cfg.net.R, "bins": cfg.n_bins, "walkers_per_bin": cfg.m_targ,
+                    "tau": cfg.tau, "kernel": "ssa_wave"}
+        digest_src = ["paper_1303_5986_amd/csrc/ssa_wave.hip", "paper_1303_5986_amd/csrc/ssa_wave_body.h",
+                      "paper_1303_5986_amd/csrc/we_common.h"]
+        tag = "ssa_wave_large"
+    else:
+        cfg = wl.schlogl_config(n_runs=args.runs, seed0=1, n_iters=W + K)
+        kernel, kname = we.WE_KERNEL_LANE, "ssa_lane_kernel<1,4>"
+        ops_ev = alg_ops_per_event(cfg.net)
+        cfg_desc = {"workload": "schlogl_steady_state_recycling", "runs": args.runs,
+                    "bins": cfg.n_bins, "walkers_per_bin": cfg.m_targ, "tau": cfg.tau,
+                    "target": "X>=563 -> X=82", "kernel": "ssa_lane"}
+        digest_src = ["paper_1303_5986_amd/csrc/ssa_lane.hip", "paper_1303_5986_amd/csrc/ssa_lane_body.h",
+                      "paper_1303_5986_amd/csrc/we_common.h"]
+        tag = "ssa_lane_schlogl"
+    sim = we.sim_from_config(cfg, kernel=kernel, max_iters=W + K)
     sim.step(W)
     sim.synchronize()
     ev0, seg0, _ = sim.counters()
@@ -350,13 +404,11 @@ def main():
     segments = seg1 - seg0
     value = events / elapsed
 
-    ops_ev = alg_ops_per_event(cfg.net)
     ssa_avg_s = ms_ssa / 1e3 / K
     ev_per_launch = events / K
     achieved = ops_ev * ev_per_launch / ssa_avg_s
-    digest = source_digest(["paper_1303_5986_amd/csrc/ssa_lane.hip",
-                            "paper_1303_5986_amd/csrc/we_common.h"])
-    traffic = traffic_from_profiles("ssa_lane_schlogl", digest)
+    traffic = traffic_from_profiles(tag, source_digest(digest_src))
+    cfg_desc["walkers_per_step"] = segments / K
 
     out = {
         "metric": METRIC,
@@ -371,14 +423,10 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "schlogl_steady_state_recycling", "runs": args.runs,
-                   "bins": cfg.n_bins, "walkers_per_bin": cfg.m_targ, "tau": cfg.tau,
-                   "target": "X>=563 -> X=82", "kernel": "ssa_lane",
-                   "walkers_per_step": segments / K},
+        "config": cfg_desc,
         "we_iters_per_s": K / elapsed,
         "events_per_segment": events / max(segments, 1),
-        "kernel_ms_per_step": {"ssa_lane": ms_ssa / K, "resample": ms_res / K,
-                               "observe": ms_obs / K},
+        "kernel_ms_per_step": {"ssa": ms_ssa / K, "resample": ms_res / K, "observe": ms_obs / K},
         "roofline": {
             "bound": "alu",
             "achieved": achieved / 1e12,
@@ -387,14 +435,21 @@ def main():
             "frac": achieved / PEAK_LANE_OPS,
             "traffic": traffic,
             "ops_per_event": ops_ev,
-            "kernel": "ssa_lane_kernel<1,4>",
+            "kernel": kname,
             "avg_launch_ms": ms_ssa / K,
             "events_per_launch": ev_per_launch,
         },
     }
     if not args.no_cpu:
-        cpu_cfg = wl.schlogl_config(n_runs=args.cpu_runs, seed0=1, n_iters=args.cpu_iters)
-        rate, secs, cev = cpu_baseline(cpu_cfg, args.cpu_runs, args.cpu_iters)
+        if args.workload == "large":
+            import dataclasses
+            cpu_cfg = dataclasses.replace(wl.large_network_config(n_iters=args.cpu_iters),
+                                          m_targ=2)
+            rate, secs, cev = cpu_baseline(cpu_cfg, 1, 4)
+            args.cpu_runs, args.cpu_iters = 1, 4
+        else:
+            cpu_cfg = wl.schlogl_config(n_runs=args.cpu_runs, seed0=1, n_iters=args.cpu_iters)
+            rate, secs, cev = cpu_baseline(cpu_cfg, args.cpu_runs, args.cpu_iters)
         out["cpu_baseline"] = {"value": rate, "unit": "events/s", "cores": 1, "kind": "oracle",
                                "sample": f"{args.cpu_runs} runs x {args.cpu_iters} WE iterations "
                                          f"of the same workload from its initial ensemble "
