@@ -11,15 +11,21 @@
 //      bins, the bin is written afterwards by the committor kernel);
 //   resample (one workgroup per run)
 //      the run's recycled weight (summed in slot order) and reactions fired;
-//      per-bin split/merge (Sec. II.B):
+//      per-bin split/merge (Sec. II.B), one wave per bin:
 //        n == M: unchanged;
 //        n <  M: replicate to M copies; one more copy is given, repeatedly,
 //                to the parent with the largest per-copy weight w/c (ties:
 //                lowest slot); each copy carries w/c, so the bin's weight is
-//                conserved (a lone walker gets the paper's w/M exactly);
+//                conserved (a lone walker gets the paper's w/M exactly); the
+//                wave finds the largest share with DPP max steps;
 //        n >  M: merge the two lowest-weight walkers (ties: lowest slot): the
 //                first survives with probability w_i/(w_i+w_j), else the
-//                second, and the survivor carries w_i + w_j; repeat;
+//                second, and the survivor carries w_i + w_j; repeat.  The
+//                bin is sorted once by (weight, slot); merged walkers queue up
+//                in the order they are made, which is also non-decreasing in
+//                weight, so each merge only compares the heads of the two
+//                queues (ties of equal sums ordered by a small heap): the same
+//                pairs as a full search, in O(n log n) instead of O(n^2);
 //      output order: bins ascending, parents by ascending slot, copies of a
 //      parent consecutive -- neighbouring lanes then hold walkers of similar
 //      state for the next SSA step;
@@ -63,18 +69,313 @@ __global__ __launch_bounds__(256) void we_recycle_bin_kernel(SimArgs a, int32_t 
     recycle_bin_one(a, x_cur, grid_bins, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
-// Per-walker working arrays of one run: LDS when the run fits, else global.
+// Per-walker working arrays of one run (LDS when the run fits, else global);
+// Idx is the type of an index inside one bin (uint16 in LDS, int32 in global).
+template <class Idx>
 struct RunWork {
-    double *w;          // weights in bin-major order
+    double *w;          // weights in bin-major order (-1 marks a merged-away walker)
     int32_t *list;      // slots in bin-major order
-    uint16_t *bin;      // bin of every slot
-    uint16_t *cnt;      // copies / alive flags in bin-major order
+    uint16_t *tag;      // per slot: bin | 0x8000 if recycled (until placement)
+    Idx *aux;           // per position: split copy counts, or the merge sort order
+    Idx *qa;            // per position: queue of merged walkers (aliases tag)
 };
 
-__device__ __forceinline__ void resample_run(const SimArgs &a, const double *__restrict__ w_cur,
-                                             double *__restrict__ w_nxt, int32_t use_lds, int32_t run,
-                                             unsigned char *lds) {
+namespace {
+
+union RsBits {
+    double d;
+    int32_t w[2];
+};
+
+template <int CTRL>
+__device__ __forceinline__ double rs_dpp(double v) {
+    RsBits in, out;
+    in.d = v;
+    out.w[0] = __builtin_amdgcn_update_dpp(0, in.w[0], CTRL, 0xF, 0xF, false);
+    out.w[1] = __builtin_amdgcn_update_dpp(0, in.w[1], CTRL, 0xF, 0xF, false);
+    return out.d;
+}
+
+__device__ __forceinline__ double rs_readlane(double v, int l) {
+    RsBits in, out;
+    in.d = v;
+    out.w[0] = __builtin_amdgcn_readlane(in.w[0], l);
+    out.w[1] = __builtin_amdgcn_readlane(in.w[1], l);
+    return out.d;
+}
+
+// Largest value over the 64 lanes (every lane gets it): quad swaps, half-row
+// and row mirrors give each 16-lane row its maximum; four readlanes finish.
+__device__ __forceinline__ double wave_max(double v) {
+    v = fmax(v, rs_dpp<0xB1>(v));    // quad_perm [1,0,3,2]
+    v = fmax(v, rs_dpp<0x4E>(v));    // quad_perm [2,3,0,1]
+    v = fmax(v, rs_dpp<0x141>(v));   // row_half_mirror
+    v = fmax(v, rs_dpp<0x140>(v));   // row_mirror
+    return fmax(fmax(rs_readlane(v, 0), rs_readlane(v, 16)), fmax(rs_readlane(v, 32), rs_readlane(v, 48)));
+}
+
+__device__ __forceinline__ int32_t wave_excl_scan(int32_t v, int lane, int32_t *total) {
+    int32_t x = v;
+    for (int d = 1; d < 64; d <<= 1) {
+        const int32_t y = __shfl_up(x, d, 64);
+        if (lane >= d) x += y;
+    }
+    *total = __shfl(x, 63, 64);
+    return x - v;
+}
+
+// Orders the LDS/global accesses of the lanes of one wave.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ int32_t uni(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
+struct BinOut {
+    int32_t *orig;
+    double *wn;
+    int32_t *obin;
+};
+
+// n < M: M - n extra copies handed out one at a time to the parent with the
+// largest per-copy weight w/c, ties to the lowest slot.  Lane L owns the
+// contiguous parents [L*kq, (L+1)*kq), so the lowest lane holding the wave's
+// largest share holds the lowest tied slot.
+template <class Idx>
+__device__ void split_bin(const RunWork<Idx> &wk, int32_t p0, int32_t nb, int32_t M, int32_t b, int32_t o0,
+                          const BinOut &out, int lane) {
+    const int32_t kq = (nb + 63) >> 6;
+    const int32_t q_lo = min(lane * kq, nb), q_hi = min(q_lo + kq, nb);
+    const double *w = wk.w + p0;
+    Idx *c = wk.aux + p0;
+    double bs = -1.0;
+    int32_t bq = -1;
+    for (int32_t q = q_lo; q < q_hi; ++q) {
+        c[q] = 1;
+        const double s = w[q] / 1.0;
+        if (s > bs) { bs = s; bq = q; }
+    }
+    for (int32_t e = nb; e < M; ++e) {
+        const double mx = wave_max(bs);
+        const unsigned long long win = __ballot(bs == mx);
+        const int wl = __ffsll((long long)win) - 1;
+        if (lane == wl) {
+            c[bq] = (Idx)(c[bq] + 1);
+            bs = -1.0;
+            bq = -1;
+            for (int32_t q = q_lo; q < q_hi; ++q) {
+                const double s = w[q] / (double)c[q];
+                if (s > bs) { bs = s; bq = q; }
+            }
+        }
+    }
+    int32_t cl = 0;
+    for (int32_t q = q_lo; q < q_hi; ++q) cl += (int32_t)c[q];
+    int32_t tot;
+    int32_t o = o0 + wave_excl_scan(cl, lane, &tot);
+    for (int32_t q = q_lo; q < q_hi; ++q) {
+        const int32_t cc = (int32_t)c[q];
+        const double share = w[q] / (double)cc;
+        const int32_t k = wk.list[p0 + q];
+        for (int32_t r = 0; r < cc; ++r) {
+            out.orig[o] = k;
+            out.wn[o] = share;
+            out.obin[o] = b;
+            ++o;
+        }
+    }
+}
+
+// The merge queues of one bin.  Q1: the bin's walkers sorted by (weight,
+// slot).  Q2: merged walkers in the order they were made; their weights never
+// decrease (each merge takes the two lightest, so every later pair sums to at
+// least as much), so only equal-weight runs of Q2 need ordering by slot: the
+// run at the front of Q2 is kept as a min-heap on the slot in A[hs, he);
+// A[he, re) are spent entries and A[re, t) is the rest of Q2 in order.
+// Every lane runs the same steps; lane 0 does the stores.
+template <class Idx>
+struct MergeQueues {
+    const Idx *perm;
+    Idx *A;
+    double *W;
+    int32_t nb, h1, q1;
+    double w1;
+    int32_t hs, he, re, t;
+    double hw;
+    int lane;
+
+    __device__ void put(int32_t i, int32_t v) {
+        if (lane == 0) A[i] = (Idx)v;
+        wave_sync();
+    }
+
+    __device__ void sift_down(int32_t pos, int32_t size, int32_t x) {
+        for (;;) {
+            int32_t ch = 2 * pos + 1;
+            if (ch >= size) break;
+            int32_t cv = uni((int32_t)A[hs + ch]);
+            if (ch + 1 < size) {
+                const int32_t cv2 = uni((int32_t)A[hs + ch + 1]);
+                if (cv2 < cv) { ch += 1; cv = cv2; }
+            }
+            if (cv >= x) break;
+            put(hs + pos, cv);
+            pos = ch;
+        }
+        put(hs + pos, x);
+    }
+
+    __device__ void refill() {
+        hs = re;
+        hw = W[uni((int32_t)A[re])];
+        int32_t e = re + 1;
+        while (e < t && W[uni((int32_t)A[e])] == hw) ++e;
+        he = e;
+        re = e;
+        for (int32_t i = (e - hs) / 2 - 1; i >= 0; --i) sift_down(i, e - hs, uni((int32_t)A[hs + i]));
+    }
+
+    // remove and return the lightest walker (ties: lowest slot)
+    __device__ void pop(double *wo, int32_t *qo) {
+        if (he == hs && re < t) refill();
+        const bool has1 = h1 < nb, has2 = he > hs;
+        int32_t q2 = has2 ? uni((int32_t)A[hs]) : 0;
+        const bool take1 = has1 && (!has2 || w1 < hw || (w1 == hw && q1 < q2));
+        if (take1) {
+            *wo = w1;
+            *qo = q1;
+            ++h1;
+            if (h1 < nb) {
+                q1 = uni((int32_t)perm[h1]);
+                w1 = W[q1];
+            }
+        } else {
+            *wo = hw;
+            *qo = q2;
+            --he;
+            if (he > hs) sift_down(0, he - hs, uni((int32_t)A[he]));
+        }
+    }
+
+    __device__ void push(double s, int32_t q) {
+        if (he > hs && re == t && s == hw) {
+            int32_t pos = he - hs;
+            if (he == t) { ++t; ++re; }
+            ++he;
+            while (pos > 0) {
+                const int32_t par = (pos - 1) >> 1;
+                const int32_t pv = uni((int32_t)A[hs + par]);
+                if (pv <= q) break;
+                put(hs + pos, pv);
+                pos = par;
+            }
+            put(hs + pos, q);
+        } else {
+            put(t, q);
+            ++t;
+        }
+    }
+};
+
+// n > M: merge the two lightest walkers (ties: lowest slot) until M remain.
+template <class Idx>
+__device__ void merge_bin(const RunWork<Idx> &wk, int32_t p0, int32_t nb, int32_t M, int32_t b, int32_t o0,
+                          const BinOut &out, uint32_t iter, uint32_t k0, uint32_t k1, int lane) {
+    double *W = wk.w + p0;
+    Idx *perm = wk.aux + p0;
+    // sort order of the bin by (weight, slot): bitonic network whose first
+    // step of every merge compares mirrored pairs, so positions past nb act as
+    // +inf and never move
+    for (int32_t q = lane; q < nb; q += 64) perm[q] = (Idx)q;
+    wave_sync();
+    int32_t P = 1;
+    while (P < nb) P <<= 1;
+    for (int32_t size = 2; size <= P; size <<= 1) {
+        for (int32_t d = size >> 1; d > 0; d >>= 1) {
+            const bool mirror = d == (size >> 1);
+            for (int32_t cidx = lane; cidx < (P >> 1); cidx += 64) {
+                const int32_t blk = cidx / d, r = cidx - blk * d;
+                int32_t i, j;
+                if (mirror) {
+                    i = blk * size + r;
+                    j = blk * size + size - 1 - r;
+                } else {
+                    i = blk * 2 * d + r;
+                    j = i + d;
+                }
+                if (j < nb) {
+                    const int32_t qi = (int32_t)perm[i], qj = (int32_t)perm[j];
+                    const double wi = W[qi], wj = W[qj];
+                    if (wj < wi || (wj == wi && qj < qi)) {
+                        perm[i] = (Idx)qj;
+                        perm[j] = (Idx)qi;
+                    }
+                }
+            }
+            wave_sync();
+        }
+    }
+
+    MergeQueues<Idx> Q;
+    Q.perm = perm;
+    Q.A = wk.qa + p0;
+    Q.W = W;
+    Q.nb = nb;
+    Q.h1 = 0;
+    Q.q1 = uni((int32_t)perm[0]);
+    Q.w1 = W[Q.q1];
+    Q.hs = Q.he = Q.re = Q.t = 0;
+    Q.hw = 0.0;
+    Q.lane = lane;
+    double ul = 0.0;
+    for (int32_t m = 0; m < nb - M; ++m) {
+        double wi, wj;
+        int32_t qi, qj;
+        Q.pop(&wi, &qi);
+        Q.pop(&wj, &qj);
+        if ((m & 63) == 0) {   // the next 64 merge draws, one per lane
+            const U4 rr = philox4x32_10((uint32_t)(m + lane), (uint32_t)b, iter, 1u, k0, k1);
+            ul = uniform53(rr.x, rr.y);
+        }
+        const double u = rs_readlane(ul, m & 63);
+        const double sum = wi + wj;
+        const double p_i = wi / sum;
+        const int32_t keep = (u < p_i) ? qi : qj;
+        const int32_t drop = (keep == qi) ? qj : qi;
+        if (lane == 0) {
+            W[keep] = sum;
+            W[drop] = -1.0;
+        }
+        wave_sync();
+        Q.push(sum, keep);
+    }
+    wave_sync();
+
+    const int32_t kq = (nb + 63) >> 6;
+    const int32_t q_lo = min(lane * kq, nb), q_hi = min(q_lo + kq, nb);
+    int32_t cl = 0;
+    for (int32_t q = q_lo; q < q_hi; ++q) cl += (W[q] >= 0.0) ? 1 : 0;
+    int32_t tot;
+    int32_t o = o0 + wave_excl_scan(cl, lane, &tot);
+    for (int32_t q = q_lo; q < q_hi; ++q) {
+        const double wq = W[q];
+        if (!(wq >= 0.0)) continue;
+        out.orig[o] = wk.list[p0 + q];
+        out.wn[o] = wq;
+        out.obin[o] = b;
+        ++o;
+    }
+}
+
+}  // namespace
+
+template <class Idx>
+__device__ void resample_run_t(const SimArgs &a, const double *__restrict__ w_cur, double *__restrict__ w_nxt,
+                               int32_t use_lds, int32_t run, unsigned char *lds) {
     const int32_t tid = threadIdx.x, nthr = blockDim.x;
+    const int lane = tid & 63, wave = tid >> 6, n_waves = nthr >> 6;
     const int32_t NB = a.n_bins, M = a.m_targ, cap = a.cap;
     __shared__ int64_t ev_part[256];
     int32_t *cnt = reinterpret_cast<int32_t *>(lds);   // [NB]
@@ -91,17 +392,22 @@ __device__ __forceinline__ void resample_run(const SimArgs &a, const double *__r
     const double *wr = w_cur + base;
     const int32_t *sbin = a.s_bin + base;
     const int32_t *srec = a.s_rec + base;
-    RunWork wk;
+    RunWork<Idx> wk;
     if (use_lds) {
         wk.w = reinterpret_cast<double *>(tail);
         wk.list = reinterpret_cast<int32_t *>(wk.w + cap);
-        wk.bin = reinterpret_cast<uint16_t *>(wk.list + cap);
-        wk.cnt = wk.bin + cap;
+        wk.tag = reinterpret_cast<uint16_t *>(wk.list + cap);
+        wk.qa = reinterpret_cast<Idx *>(wk.tag);
+        wk.aux = reinterpret_cast<Idx *>(wk.tag + cap);
     } else {
+        // global: the tag array in the first half of the s_cnt rows, the
+        // queue over s_bin (read only before the first barrier), the aux
+        // array over s_cnt once placement is done
         wk.w = a.s_w + base;
         wk.list = a.s_list + base;
-        wk.bin = reinterpret_cast<uint16_t *>(a.s_cnt + base);
-        wk.cnt = wk.bin + cap;
+        wk.tag = reinterpret_cast<uint16_t *>(a.s_cnt + base);
+        wk.qa = reinterpret_cast<Idx *>(a.s_bin + base);
+        wk.aux = reinterpret_cast<Idx *>(a.s_cnt + base);
     }
 
     for (int32_t b = tid; b < NB; b += nthr) cnt[b] = 0;
@@ -109,47 +415,60 @@ __device__ __forceinline__ void resample_run(const SimArgs &a, const double *__r
     int64_t my_ev = 0;
     for (int32_t k = tid; k < n; k += nthr) {
         const int32_t b = sbin[k];
-        wk.bin[k] = (uint16_t)b;
+        wk.tag[k] = (uint16_t)(b | (srec[k] ? 0x8000 : 0));
         atomicAdd(&cnt[b], 1);
         my_ev += a.ev_walker[base + k];
     }
     ev_part[tid] = my_ev;
     __syncthreads();
 
-    // recycled weight (slot order), reactions fired, bin offsets
-    if (tid == 0) {
-        double f = 0.0;
-        for (int32_t k = 0; k < n; ++k)
-            if (srec[k]) f = f + wr[k];
+    // wave 0: reactions fired, bin offsets, stable placement and the
+    // recycled weight in slot order
+    if (wave == 0) {
         int64_t ev = 0;
-        for (int32_t t = 0; t < nthr; ++t) ev += ev_part[t];
-        if (rec_slot < a.max_iters) {
-            a.flux[(size_t)run * a.max_iters + rec_slot] = f;
-            a.ev_iter[(size_t)run * a.max_iters + rec_slot] = ev;
-            a.seg_iter[(size_t)run * a.max_iters + rec_slot] = n;
-        }
+        for (int32_t t = lane; t < nthr; t += 64) ev += ev_part[t];
+        for (int d = 32; d > 0; d >>= 1) ev += __shfl_xor(ev, d, 64);
+
+        const int32_t kb = (NB + 63) >> 6;
+        const int32_t b_lo = min(lane * kb, NB), b_hi = min(b_lo + kb, NB);
         int32_t acc = 0, oacc = 0;
-        for (int32_t b = 0; b < NB; ++b) {
+        for (int32_t b = b_lo; b < b_hi; ++b) {
+            acc += cnt[b];
+            oacc += cnt[b] > 0 ? M : 0;
+        }
+        int32_t tot, otot;
+        acc = wave_excl_scan(acc, lane, &tot);
+        oacc = wave_excl_scan(oacc, lane, &otot);
+        for (int32_t b = b_lo; b < b_hi; ++b) {
             start[b] = acc;
             cursor[b] = acc;
             ostart[b] = oacc;
             acc += cnt[b];
-            oacc += (cnt[b] > 0) ? M : 0;
+            oacc += cnt[b] > 0 ? M : 0;
         }
-        start[NB] = acc;
-        ostart[NB] = oacc;
-    }
-    __syncthreads();
+        if (lane == 63) {
+            start[NB] = tot;
+            ostart[NB] = otot;
+        }
+        wave_sync();
 
-    // stable placement of every walker into its bin's segment (slot order
-    // kept): one wave walks the slots 64 at a time; lanes with the same bin
-    // are ranked by a ballot, and the bin's cursor advances by the group size
-    if (tid < 64) {
-        const int lane = tid;
+        // lanes with the same bin are ranked by a ballot; the bin's cursor
+        // advances by the group size
+        double f = 0.0;
         for (int32_t c0 = 0; c0 < n; c0 += 64) {
             const int32_t k = c0 + lane;
             const bool valid = k < n;
-            const int32_t b = valid ? (int32_t)wk.bin[k] : -1;
+            const int32_t tg = valid ? (int32_t)wk.tag[k] : 0;
+            const int32_t b = valid ? (tg & 0x7FFF) : -1;
+            unsigned long long rm = __ballot(valid && (tg & 0x8000));
+            if (rm) {
+                const double wv = (valid && (tg & 0x8000)) ? wr[k] : 0.0;
+                while (rm) {
+                    const int l = __ffsll((long long)rm) - 1;
+                    f = f + rs_readlane(wv, l);
+                    rm &= rm - 1ull;
+                }
+            }
             unsigned long long todo = __ballot(valid);
             while (todo) {
                 const int leader = __ffsll((long long)todo) - 1;
@@ -157,92 +476,56 @@ __device__ __forceinline__ void resample_run(const SimArgs &a, const double *__r
                 const unsigned long long grp = __ballot(valid && b == lb);
                 if (valid && b == lb) {
                     const unsigned long long below = lane ? (grp & ((1ull << lane) - 1ull)) : 0ull;
-                    const int32_t p = cursor[lb] + __popcll(below);
-                    wk.list[p] = k;
-                    wk.w[p] = wr[k];
+                    wk.list[cursor[lb] + __popcll(below)] = k;
                 }
-                __builtin_amdgcn_wave_barrier();
+                wave_sync();
                 if (lane == leader) cursor[lb] += __popcll(grp);
-                __builtin_amdgcn_wave_barrier();
+                wave_sync();
                 todo &= ~grp;
             }
         }
+        if (lane == 0 && rec_slot < a.max_iters) {
+            a.flux[(size_t)run * a.max_iters + rec_slot] = f;
+            a.ev_iter[(size_t)run * a.max_iters + rec_slot] = ev;
+            a.seg_iter[(size_t)run * a.max_iters + rec_slot] = n;
+        }
     }
     __syncthreads();
+    for (int32_t p = tid; p < n; p += nthr) wk.w[p] = wr[wk.list[p]];
+    __syncthreads();
 
-    // split / merge, one thread per bin
+    // split / merge: one wave per bin
     const uint64_t seed = a.seeds[run];
     const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
-    int32_t *orig = a.origin + base;
-    int32_t *obin = a.bin + base;
-    double *wn = w_nxt + base;
-    for (int32_t b = tid; b < NB; b += nthr) {
-        const int32_t nb = cnt[b], p0 = start[b];
-        int32_t o = ostart[b];
+    BinOut out;
+    out.orig = a.origin + base;
+    out.obin = a.bin + base;
+    out.wn = w_nxt + base;
+    for (int32_t b = wave; b < NB; b += n_waves) {
+        const int32_t nb = uni(cnt[b]);
         if (nb == 0) continue;
+        const int32_t p0 = uni(start[b]), o0 = uni(ostart[b]);
         if (nb == M) {
-            for (int32_t q = 0; q < nb; ++q) {
-                orig[o] = wk.list[p0 + q];
-                wn[o] = wk.w[p0 + q];
-                obin[o] = b;
-                ++o;
+            for (int32_t q = lane; q < nb; q += 64) {
+                out.orig[o0 + q] = wk.list[p0 + q];
+                out.wn[o0 + q] = wk.w[p0 + q];
+                out.obin[o0 + q] = b;
             }
         } else if (nb < M) {
-            for (int32_t q = 0; q < nb; ++q) wk.cnt[p0 + q] = 1;
-            for (int32_t extra = nb; extra < M; ++extra) {
-                int32_t best = 0;
-                double best_share = wk.w[p0] / (double)wk.cnt[p0];
-                for (int32_t q = 1; q < nb; ++q) {
-                    const double share = wk.w[p0 + q] / (double)wk.cnt[p0 + q];
-                    if (share > best_share) { best = q; best_share = share; }
-                }
-                wk.cnt[p0 + best] += 1;
-            }
-            for (int32_t q = 0; q < nb; ++q) {
-                const int32_t c = wk.cnt[p0 + q];
-                const double share = wk.w[p0 + q] / (double)c;
-                for (int32_t r = 0; r < c; ++r) {
-                    orig[o] = wk.list[p0 + q];
-                    wn[o] = share;
-                    obin[o] = b;
-                    ++o;
-                }
-            }
+            split_bin(wk, p0, nb, M, b, o0, out, lane);
         } else {
-            for (int32_t q = 0; q < nb; ++q) wk.cnt[p0 + q] = 1;   // alive flags
-            int32_t alive = nb;
-            uint32_t m = 0;
-            while (alive > M) {
-                int32_t i = -1, j = -1;
-                double wi_min = 0.0, wj_min = 0.0;
-                for (int32_t q = 0; q < nb; ++q) {
-                    if (!wk.cnt[p0 + q]) continue;
-                    const double v = wk.w[p0 + q];
-                    if (i < 0 || v < wi_min) { j = i; wj_min = wi_min; i = q; wi_min = v; }
-                    else if (j < 0 || v < wj_min) { j = q; wj_min = v; }
-                }
-                const U4 r = philox4x32_10(m, (uint32_t)b, iter, 1u, k0, k1);
-                m += 1;
-                const double u = uniform53(r.x, r.y);
-                const double sum = wi_min + wj_min;
-                const double p_i = wi_min / sum;
-                const int32_t keep = (u < p_i) ? i : j;
-                const int32_t drop = (keep == i) ? j : i;
-                wk.w[p0 + keep] = sum;
-                wk.cnt[p0 + drop] = 0;
-                alive -= 1;
-            }
-            for (int32_t q = 0; q < nb; ++q) {
-                if (!wk.cnt[p0 + q]) continue;
-                orig[o] = wk.list[p0 + q];
-                wn[o] = wk.w[p0 + q];
-                obin[o] = b;
-                ++o;
-            }
+            merge_bin(wk, p0, nb, M, b, o0, out, iter, k0, k1, lane);
         }
     }
     __syncthreads();
     if (tid == 0) a.n_walk[run] = ostart[NB];
+}
+
+__device__ __forceinline__ void resample_run(const SimArgs &a, const double *__restrict__ w_cur,
+                                             double *__restrict__ w_nxt, int32_t use_lds, int32_t run,
+                                             unsigned char *lds) {
+    if (use_lds) resample_run_t<uint16_t>(a, w_cur, w_nxt, 1, run, lds);
+    else resample_run_t<int32_t>(a, w_cur, w_nxt, 0, run, lds);
 }
 
 __global__ __launch_bounds__(256) void we_resample_kernel(SimArgs a, const double *__restrict__ w_cur,
