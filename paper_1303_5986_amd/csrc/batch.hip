@@ -58,6 +58,10 @@ __global__ __launch_bounds__(256) void batch_lane_kernel(const SimArgs *__restri
                                                          int32_t *const *__restrict__ xptr,
                                                          const Item *__restrict__ items, int32_t n_items,
                                                          uint32_t *__restrict__ counter) {
+    constexpr bool REG = RMAX <= LANE_REG_RMAX;
+    constexpr int ROWS = REG ? 1 : RMAX * LaneRow<SMAX>::W;
+    __shared__ int32_t rows[4 * ROWS];
+    int32_t *wrows = rows + (threadIdx.x >> 6) * ROWS;
     const int lane = threadIdx.x & 63;
     for (;;) {
         uint32_t idx = 0;
@@ -66,8 +70,9 @@ __global__ __launch_bounds__(256) void batch_lane_kernel(const SimArgs *__restri
         if (idx >= (uint32_t)n_items) break;
         const Item it = items[idx];
         const SimArgs &a = args[it.sim];
+        if constexpr (!REG) lane_stage_rows<SMAX>(a, wrows);
         const int32_t k = it.slot + lane;
-        if (k < a.n_walk[it.run]) lane_walker<SMAX, RMAX>(a, xptr[it.sim], it.run, k, *a.iter_dev);
+        if (k < a.n_walk[it.run]) lane_walker<SMAX, RMAX>(a, xptr[it.sim], it.run, k, *a.iter_dev, wrows);
     }
 }
 
@@ -282,7 +287,7 @@ extern "C" we_status we_batch_create(int32_t n, const we_network *const *nets, c
         }
         const int32_t S = nets[i]->S, R = nets[i]->R;
         if (p.kernel == WE_KERNEL_AUTO) {
-            if (!(lane_kernel_fits(S, R) && R <= 32)) {
+            if (!(lane_kernel_fits(S, R, nets[i]->max_delta) && R <= 32)) {
                 p.kernel = WE_KERNEL_WAVE;
             } else if (autotune_iters > 0) {
                 char key[128];

@@ -11,22 +11,27 @@
 // u1, u2 come from one Philox4x32-10 block at counter (event, slot, iter, 0).
 //
 // Design for CDNA4: walker state and propensities live in VGPRs, the
-// reaction table is wave-uniform and read through scalar loads, and the
-// stoichiometric update is a uniform loop over reactions with per-lane
-// predication, so no per-lane gather ever touches memory inside the event
-// loop.  HBM traffic is one read and one write of the state per interval.
-// Walkers are laid out bin-major, so neighbouring lanes have similar total
-// propensity and the wave diverges little.
+// reaction table is wave-uniform (scalar loads), and the state change of the
+// chosen reaction is an int8 delta row picked by register selects (up to 8
+// reactions) or read from the wave's LDS copy of the rows, so nothing in the
+// event loop waits on global memory.  HBM traffic is one read and one write
+// of the state per interval.  Walkers are laid out bin-major, so neighbouring
+// lanes have similar total propensity and the wave diverges little.
 #include "ssa_lane_body.h"
 
 template <int SMAX, int RMAX>
 __global__ __launch_bounds__(256) void ssa_lane_kernel(SimArgs a, int32_t *__restrict__ xs) {
+    constexpr bool REG = RMAX <= LANE_REG_RMAX;
+    constexpr int ROWS = REG ? 1 : RMAX * LaneRow<SMAX>::W;
+    __shared__ int32_t rows[4 * ROWS];
+    int32_t *wrows = rows + (threadIdx.x >> 6) * ROWS;
+    if constexpr (!REG) lane_stage_rows<SMAX>(a, wrows);
     const int32_t gid = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
     const int32_t run = gid / a.cap;
     const int32_t k = gid - run * a.cap;
     if (run >= a.n_runs) return;
     if (k >= a.n_walk[run]) return;
-    lane_walker<SMAX, RMAX>(a, xs, run, k, *a.iter_dev);
+    lane_walker<SMAX, RMAX>(a, xs, run, k, *a.iter_dev, wrows);
 }
 
 // Launch helper: picks the smallest register footprint that holds the network.
@@ -49,4 +54,7 @@ hipError_t launch_ssa_lane(const SimArgs &a, int32_t *xs, hipStream_t st) {
     return hipGetLastError();
 }
 
-bool lane_kernel_fits(int32_t S, int32_t R) { return S <= 32 && R <= 64; }
+// Deltas travel as int8, so every change must lie in [-128, 127].
+bool lane_kernel_fits(int32_t S, int32_t R, int32_t max_delta) {
+    return S <= 32 && R <= 64 && max_delta <= 127;
+}

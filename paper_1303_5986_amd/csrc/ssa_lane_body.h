@@ -1,35 +1,119 @@
 // ssa_lane_body.h -- the lane-per-walker event loop (one walker through one
 // interval), shared by the per-sim kernel and the batched persistent kernel.
+//
+// Nothing inside the event loop waits on global memory:
+//  * the reaction descriptors are read as whole 16-byte words at uniform
+//    addresses (scalar loads, kept in SGPRs where they fit);
+//  * h_j(x) = prod_s C(x_s, nu_js) is formed in FP64: every factor and the
+//    product are integers below 2^53 (counts <= 2^17, order <= 3), so each
+//    is exact -- C(x,3) is x(x-1)(x-2)/2 times the double nearest 1/3,
+//    rounded to the nearest integer, which is exact because the error is
+//    below 2^-3 -- and no 64-bit integer division is needed;
+//  * the state change of the chosen reaction comes from a table of int8
+//    deltas per reaction and species: small networks pick their row with
+//    register selects while the reaction is chosen, larger ones read it from
+//    a per-wave copy in LDS.
 #pragma once
 #include "we_common.h"
 
+// Networks of up to LANE_REG_RMAX reactions keep their delta rows in registers.
+#define LANE_REG_RMAX 8
+
+namespace {
+
+struct LaneRxn {
+    double c;
+    uint32_t s1, s2, nu1, nu2;
+};
+
+__device__ __forceinline__ LaneRxn lane_rxn(const RxnDesc *__restrict__ desc, int j) {
+    const uint4 r = reinterpret_cast<const uint4 *>(desc)[j];
+    LaneRxn o;
+    o.c = __hiloint2double((int)r.y, (int)r.x);
+    o.s1 = r.z & 0xFFFFu;
+    o.s2 = r.z >> 16;
+    o.nu1 = r.w & 0xFFu;
+    o.nu2 = (r.w >> 8) & 0xFFu;
+    return o;
+}
+
+// C(x, nu) for nu in {0,1,2,3}, exactly, as a double.
+__device__ __forceinline__ double binom_f64(double xd, uint32_t nu) {
+    const double p2 = xd * fmax(xd - 1.0, 0.0);                          // x(x-1)
+    const double c3 = rint(((p2 * fmax(xd - 2.0, 0.0)) * 0.5) * (1.0 / 3.0));
+    const double c2 = p2 * 0.5;
+    return nu == 0 ? 1.0 : nu == 1 ? xd : nu == 2 ? c2 : c3;
+}
+
+template <int SMAX>
+__device__ __forceinline__ double lane_propensity(const LaneRxn &d, const int32_t (&x)[SMAX]) {
+    const double h1 = binom_f64((double)x[SMAX == 1 ? 0 : d.s1], d.nu1);
+    const double h2 = binom_f64((double)x[SMAX == 1 ? 0 : d.s2], d.nu2);
+    return d.c * (h1 * h2);
+}
+
+}  // namespace
+
+// Words of the delta row a variant reads (4 species per word).
+template <int SMAX>
+struct LaneRow {
+    static constexpr int W = (SMAX + 3) / 4;
+};
+
+// Copies the network's delta rows (R rows of LaneRow<SMAX>::W words) into
+// the calling wave's LDS slice; all 64 lanes take part.
+template <int SMAX>
+__device__ __forceinline__ void lane_stage_rows(const SimArgs &a, int32_t *rows) {
+    constexpr int W = LaneRow<SMAX>::W;
+    const int lane = threadIdx.x & 63;
+    for (int i = lane; i < a.R * W; i += 64) rows[i] = a.dpack[(i / W) * WE_DPACK_WORDS + (i % W)];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// rows: this wave's staged delta rows (unused when RMAX <= LANE_REG_RMAX).
 template <int SMAX, int RMAX>
 __device__ __forceinline__ void lane_walker(const SimArgs &a, int32_t *__restrict__ xs, int32_t run,
-                                            int32_t k, uint32_t iter) {
+                                            int32_t k, uint32_t iter, const int32_t *rows) {
+    constexpr int W = LaneRow<SMAX>::W;
+    constexpr bool REG = RMAX <= LANE_REG_RMAX;
     const int32_t S = a.S, R = a.R;
     int32_t *xw = xs + ((size_t)run * a.cap + k) * S;
     int32_t x[SMAX];
 #pragma unroll
     for (int s = 0; s < SMAX; ++s) x[s] = (s < S) ? xw[s] : 0;
 
+    // uniform tables (padded with zero-rate rows to 64 reactions, so every
+    // load is in bounds); small networks keep them for the whole interval
+    uint32_t drow[REG ? RMAX : 1][W];
+    LaneRxn rx[REG ? RMAX : 1];
+    if constexpr (REG) {
+#pragma unroll
+        for (int j = 0; j < RMAX; ++j) {
+            rx[j] = lane_rxn(a.desc, j);
+#pragma unroll
+            for (int w = 0; w < W; ++w) drow[j][w] = (uint32_t)a.dpack[j * WE_DPACK_WORDS + w];
+        }
+    }
+
     const uint64_t seed = a.seeds[run];
     const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
     const double tau = a.tau;
     double t = 0.0;
     uint32_t e = 0, fired = 0;
-    int32_t bad = 0;
+    bool bad = false;
     double prop[RMAX];
 
     for (;;) {
         double a0 = 0.0;
 #pragma unroll
         for (int j = 0; j < RMAX; ++j) {
+            const LaneRxn d = REG ? rx[REG ? j : 0] : lane_rxn(a.desc, j);
+            prop[j] = 0.0;
             if (j < R) {
-                const RxnDesc d = a.desc[j];
-                prop[j] = propensity_from(d, (uint32_t)x[d.s1], (uint32_t)x[d.s2]);
+                prop[j] = lane_propensity<SMAX>(d, x);
                 a0 = a0 + prop[j];
-            } else {
-                prop[j] = 0.0;
             }
         }
         if (!(a0 > 0.0)) break;
@@ -43,30 +127,42 @@ __device__ __forceinline__ void lane_walker(const SimArgs &a, int32_t *__restric
         const double target = u2 * a0;
         double cum = 0.0;
         int32_t jsel = -1, last_pos = -1;
+        uint32_t dsel[W];
+#pragma unroll
+        for (int w = 0; w < W; ++w) dsel[w] = 0u;
 #pragma unroll
         for (int j = 0; j < RMAX; ++j) {
             if (j < R) {
                 cum = cum + prop[j];
                 if (prop[j] > 0.0) last_pos = j;
-                if (jsel < 0 && cum > target) jsel = j;
-            }
-        }
-        if (jsel < 0) jsel = last_pos;
-        fired += 1;
-        // apply nu_jsel: uniform loop over reactions, lane-predicated
-        for (int j = 0; j < R; ++j) {
-            if (j == jsel) {
-                const int32_t p0 = a.chg_ptr[j], p1 = a.chg_ptr[j + 1];
-                for (int32_t p = p0; p < p1; ++p) {
-                    const int32_t c = a.chg[p];
-                    const int32_t s = change_species(c);
-                    const int32_t v = x[s] + change_delta(c);
-                    x[s] = v;
-                    bad |= (v < 0) | (v > WE_COUNT_MAX_DEV);
+                const bool hit = (jsel < 0) && (cum > target);
+                if (hit) jsel = j;
+                if constexpr (REG) {
+#pragma unroll
+                    for (int w = 0; w < W; ++w) dsel[w] = hit ? drow[j][w] : dsel[w];
                 }
             }
         }
-        if (bad) break;
+        if (jsel < 0) {   // rounding left the target above the running sum
+            jsel = last_pos;
+            if constexpr (REG) {
+#pragma unroll
+                for (int w = 0; w < W; ++w) dsel[w] = (uint32_t)a.dpack[jsel * WE_DPACK_WORDS + w];
+            }
+        }
+        if constexpr (!REG) {
+#pragma unroll
+            for (int w = 0; w < W; ++w) dsel[w] = (uint32_t)rows[jsel * W + w];
+        }
+        fired += 1;
+        int32_t any = 0;
+#pragma unroll
+        for (int s = 0; s < SMAX; ++s) {
+            x[s] += (int32_t)(dsel[s >> 2] << (24 - 8 * (s & 3))) >> 24;
+            any |= x[s];
+        }
+        // a count left [0, 2^17 - 1] iff a bit outside the low 17 is set
+        if (any & ~WE_COUNT_MAX_DEV) { bad = true; break; }
     }
     if (bad) atomicOr(a.err, WE_DERR_OVERFLOW);
 #pragma unroll
@@ -74,4 +170,3 @@ __device__ __forceinline__ void lane_walker(const SimArgs &a, int32_t *__restric
         if (s < S) xw[s] = x[s];
     a.ev_walker[(size_t)run * a.cap + k] = fired;
 }
-

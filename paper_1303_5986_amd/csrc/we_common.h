@@ -14,6 +14,7 @@
 #include <stdint.h>
 
 #define WE_COUNT_MAX_DEV 131071
+#define WE_DPACK_WORDS 8
 
 // Error bits latched in device memory.
 enum : int32_t {
@@ -58,6 +59,8 @@ struct SimArgs {
     const RxnDesc *__restrict__ desc;    // [R]
     const int32_t *__restrict__ chg_ptr; // [R+1]
     const int32_t *__restrict__ chg;     // packed changes
+    const int32_t *__restrict__ dpack;   // [R][WE_DPACK_WORDS]: the change of species s (< 32) in
+                                         //   byte s%4 of word s/4, as int8 (lane kernel)
     const int32_t *__restrict__ dep_ptr; // [R+1] reactions whose propensity a reaction changes
     const uint16_t *__restrict__ dep;    //       (sorted, unique)
     const RxnInfo *__restrict__ rinfo;   // [R]
@@ -108,8 +111,9 @@ __device__ __forceinline__ U4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c
     const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint32_t lo0 = M0 * c0, hi0 = __umulhi(M0, c0);
-        const uint32_t lo1 = M1 * c2, hi1 = __umulhi(M1, c2);
+        const uint64_t p0 = (uint64_t)M0 * c0, p1 = (uint64_t)M1 * c2;   // one 32x32->64 multiply each
+        const uint32_t lo0 = (uint32_t)p0, hi0 = (uint32_t)(p0 >> 32);
+        const uint32_t lo1 = (uint32_t)p1, hi1 = (uint32_t)(p1 >> 32);
         const uint32_t n0 = hi1 ^ c1 ^ k0;
         const uint32_t n2 = hi0 ^ c3 ^ k1;
         c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;

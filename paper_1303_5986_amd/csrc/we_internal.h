@@ -23,6 +23,7 @@ struct we_network {
     int32_t S = 0, R = 0;
     int32_t max_order = 0;
     int32_t max_chg = 0;
+    int32_t max_delta = 0;          // largest |change| of any species
     std::vector<RxnDesc> desc;
     std::vector<int32_t> chg_ptr, chg, dep_ptr;
     std::vector<uint16_t> dep;
@@ -31,6 +32,7 @@ struct we_network {
     uint16_t *d_dep = nullptr;
     RxnInfo *d_rinfo = nullptr;
     DepEntry *d_deps = nullptr;
+    int32_t *d_dpack = nullptr;     // [R][WE_DPACK_WORDS] int8 deltas (species < 32)
 };
 
 // The learned committor attached to a sim (see committor.hip).
@@ -93,7 +95,7 @@ extern "C" void we_batch_destroy(we_batch *b);
 we_status we_sim_bookkeeping(we_sim *s, hipStream_t st, hipEvent_t *ev);
 hipError_t launch_ssa_lane(const SimArgs &a, int32_t *xs, hipStream_t st);
 hipError_t launch_ssa_wave(const SimArgs &a, int32_t *xs, hipStream_t st);
-bool lane_kernel_fits(int32_t S, int32_t R);
+bool lane_kernel_fits(int32_t S, int32_t R, int32_t max_delta);
 bool wave_kernel_fits(int32_t S, int32_t R);
 
 // committor.hip

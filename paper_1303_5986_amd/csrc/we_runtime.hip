@@ -15,6 +15,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -22,7 +23,7 @@
 #include "we_internal.h"
 
 hipError_t launch_ssa_lane(const SimArgs &a, int32_t *xs, hipStream_t st);
-bool lane_kernel_fits(int32_t S, int32_t R);
+bool lane_kernel_fits(int32_t S, int32_t R, int32_t max_delta);
 hipError_t launch_ssa_wave(const SimArgs &a, int32_t *xs, hipStream_t st);
 bool wave_kernel_fits(int32_t S, int32_t R);
 hipError_t launch_recycle_bin(const SimArgs &a, int32_t *x_cur, bool grid_bins, hipStream_t st);
@@ -147,6 +148,7 @@ extern "C" we_status we_create_network(int32_t S, int32_t R, const int32_t *reac
                 }
             }
             net->chg.push_back(pack_change(s, dl));
+            net->max_delta = std::max(net->max_delta, std::abs(dl));
         }
         net->max_order = std::max(net->max_order, order);
         net->max_chg = std::max(net->max_chg, c1 - c0);
@@ -175,6 +177,17 @@ extern "C" we_status we_create_network(int32_t S, int32_t R, const int32_t *reac
             deps.push_back(DepEntry{d.c, d.s1, d.s2, d.nu1, d.nu2, net->dep[p]});
         }
     }
+    // int8 delta rows for the lane kernel (species 0..31; bytes stay zero
+    // for other species, and the lane kernel is not used when S > 32)
+    std::vector<int32_t> dpack((size_t)R * WE_DPACK_WORDS, 0);
+    for (int32_t j = 0; j < R; ++j)
+        for (int32_t p = chg_ptr[j]; p < chg_ptr[j + 1]; ++p) {
+            const int32_t sp = chg_species[p], dl = chg_delta[p];
+            if (sp < 4 * WE_DPACK_WORDS && dl >= -128 && dl <= 127) {
+                uint32_t &wd = reinterpret_cast<uint32_t &>(dpack[(size_t)j * WE_DPACK_WORDS + sp / 4]);
+                wd |= ((uint32_t)dl & 0xFFu) << (8 * (sp % 4));
+            }
+        }
     if (deps.empty()) deps.push_back(DepEntry{});
     if (net->dep.empty()) net->dep.push_back(0);
     if (net->chg.empty()) net->chg.push_back(0);
@@ -183,13 +196,20 @@ extern "C" we_status we_create_network(int32_t S, int32_t R, const int32_t *reac
         if (e != hipSuccess) return e;
         return hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
     };
-    hipError_t e = up((void **)&net->d_desc, net->desc.data(), sizeof(RxnDesc) * R);
+    // descriptor and delta tables padded with zero-rate rows to a multiple of
+    // 64, so the lane kernel can load a whole variant's rows unconditionally
+    const int32_t R_pad = (R + 63) / 64 * 64;
+    std::vector<RxnDesc> desc_pad(net->desc);
+    desc_pad.resize(R_pad, RxnDesc{});
+    dpack.resize((size_t)R_pad * WE_DPACK_WORDS, 0);
+    hipError_t e = up((void **)&net->d_desc, desc_pad.data(), sizeof(RxnDesc) * R_pad);
     if (e == hipSuccess) e = up((void **)&net->d_chg_ptr, net->chg_ptr.data(), 4 * (R + 1));
     if (e == hipSuccess) e = up((void **)&net->d_chg, net->chg.data(), 4 * net->chg.size());
     if (e == hipSuccess) e = up((void **)&net->d_dep_ptr, net->dep_ptr.data(), 4 * (R + 1));
     if (e == hipSuccess) e = up((void **)&net->d_dep, net->dep.data(), 2 * net->dep.size());
     if (e == hipSuccess) e = up((void **)&net->d_rinfo, rinfo.data(), sizeof(RxnInfo) * R);
     if (e == hipSuccess) e = up((void **)&net->d_deps, deps.data(), sizeof(DepEntry) * deps.size());
+    if (e == hipSuccess) e = up((void **)&net->d_dpack, dpack.data(), 4 * dpack.size());
     if (e != hipSuccess) {
         we_destroy_network(net);
         return hip_fail(e, "network upload");
@@ -207,6 +227,7 @@ extern "C" void we_destroy_network(we_network *net) {
     (void)hipFree(net->d_dep);
     (void)hipFree(net->d_rinfo);
     (void)hipFree(net->d_deps);
+    (void)hipFree(net->d_dpack);
     delete net;
 }
 
@@ -327,9 +348,9 @@ extern "C" we_status we_init(const we_network *net, const we_grid *g, const we_p
     const int32_t nh = p->hist_hi >= p->hist_lo ? p->hist_hi - p->hist_lo + 1 : 0;
     int32_t kernel = p->kernel;
     if (kernel == WE_KERNEL_AUTO)
-        kernel = lane_kernel_fits(S, net->R) && net->R <= 32 ? WE_KERNEL_LANE : WE_KERNEL_WAVE;
-    if (kernel == WE_KERNEL_LANE && !lane_kernel_fits(S, net->R))
-        return fail(WE_EINVAL, "network too large for the lane-per-walker kernel");
+        kernel = lane_kernel_fits(S, net->R, net->max_delta) && net->R <= 32 ? WE_KERNEL_LANE : WE_KERNEL_WAVE;
+    if (kernel == WE_KERNEL_LANE && !lane_kernel_fits(S, net->R, net->max_delta))
+        return fail(WE_EINVAL, "network does not fit the lane-per-walker kernel (S <= 32, R <= 64, |change| <= 127)");
     if (kernel == WE_KERNEL_WAVE && (!wave_kernel_fits(S, net->R) || net->max_chg > 64))
         return fail(WE_EINVAL, "network too large for the wave-per-walker kernel");
 
@@ -357,7 +378,7 @@ extern "C" we_status we_init(const we_network *net, const we_grid *g, const we_p
     s->x[0] = (int32_t *)at(P_X0); s->x[1] = (int32_t *)at(P_X1);
     s->w[0] = (double *)at(P_W0); s->w[1] = (double *)at(P_W1);
     SimArgs &a = s->args;
-    a.desc = net->d_desc; a.chg_ptr = net->d_chg_ptr; a.chg = net->d_chg;
+    a.desc = net->d_desc; a.chg_ptr = net->d_chg_ptr; a.chg = net->d_chg; a.dpack = net->d_dpack;
     a.dep_ptr = net->d_dep_ptr; a.dep = net->d_dep;
     a.rinfo = net->d_rinfo; a.deps = net->d_deps;
     a.S = S; a.R = net->R;
