@@ -328,6 +328,7 @@ extern "C" we_status we_batch_create(int32_t n, const we_network *const *nets, c
     std::vector<int32_t> use_lds, grid_bins;
     for (we_sim *s : b->sims) {
         args.push_back(s->args);
+        args.back().lane_pool = 0;   // the batched kernels keep their own work queue
         xp0.push_back(s->x[0]);
         xp1.push_back(s->x[1]);
         wp0.push_back(s->w[0]);

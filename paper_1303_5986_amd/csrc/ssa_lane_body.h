@@ -72,101 +72,153 @@ __device__ __forceinline__ void lane_stage_rows(const SimArgs &a, int32_t *rows)
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// rows: this wave's staged delta rows (unused when RMAX <= LANE_REG_RMAX).
+// The network's uniform tables as one lane kernel sees them.
+template <int SMAX, int RMAX>
+struct LaneNet {
+    static constexpr int W = LaneRow<SMAX>::W;
+    static constexpr bool REG = RMAX <= LANE_REG_RMAX;
+    LaneRxn rx[REG ? RMAX : 1];
+    uint32_t drow[REG ? RMAX : 1][W];
+    const RxnDesc *desc;
+    const int32_t *dpack;
+    const int32_t *rows;   // this wave's staged delta rows (unused when REG)
+    int32_t R;
+
+    // tables padded with zero-rate rows to 64 reactions, so every load is
+    // in bounds; small networks keep them in registers for the whole launch
+    __device__ __forceinline__ void load(const SimArgs &a, const int32_t *rows_) {
+        desc = a.desc;
+        dpack = a.dpack;
+        rows = rows_;
+        R = a.R;
+        if constexpr (REG) {
+#pragma unroll
+            for (int j = 0; j < RMAX; ++j) {
+                rx[j] = lane_rxn(a.desc, j);
+#pragma unroll
+                for (int w = 0; w < W; ++w) drow[j][w] = (uint32_t)a.dpack[j * WE_DPACK_WORDS + w];
+            }
+        }
+    }
+};
+
+// One walker's progress through the current interval (its counts live in a
+// separate register array, which keeps this struct out of LDS).
+struct LaneWalker {
+    double t;
+    uint32_t e, fired;
+    uint32_t slot, k0, k1;
+    bool bad;
+
+    template <int SMAX>
+    __device__ __forceinline__ void begin(int32_t (&x)[SMAX], const int32_t *__restrict__ xr, int32_t S, uint32_t k,
+                                          uint64_t seed) {
+#pragma unroll
+        for (int s = 0; s < SMAX; ++s) x[s] = (s < S) ? xr[s] : 0;
+        t = 0.0;
+        e = 0;
+        fired = 0;
+        slot = k;
+        k0 = (uint32_t)seed;
+        k1 = (uint32_t)(seed >> 32);
+        bad = false;
+    }
+};
+
+// One event of the direct method (Sec. II.A); false once the walker's
+// interval is over (next event beyond tau, no reaction possible, or a count
+// out of range -- then w.bad is set).
+template <int SMAX, int RMAX>
+__device__ __forceinline__ bool lane_event(const LaneNet<SMAX, RMAX> &net, LaneWalker &w, int32_t (&x)[SMAX],
+                                           uint32_t iter, double tau) {
+    constexpr int W = LaneRow<SMAX>::W;
+    constexpr bool REG = LaneNet<SMAX, RMAX>::REG;
+    double prop[RMAX];
+    double a0 = 0.0;
+#pragma unroll
+    for (int j = 0; j < RMAX; ++j) {
+        const LaneRxn d = REG ? net.rx[REG ? j : 0] : lane_rxn(net.desc, j);
+        prop[j] = 0.0;
+        if (j < net.R) {
+            prop[j] = lane_propensity<SMAX>(d, x);
+            a0 = a0 + prop[j];
+        }
+    }
+    if (!(a0 > 0.0)) return false;
+    const U4 r = philox4x32_10(w.e, w.slot, iter, 0u, w.k0, w.k1);
+    w.e += 1;
+    const double u1 = uniform53(r.x, r.y);
+    const double u2 = uniform53(r.z, r.w);
+    const double dt = -log(1.0 - u1) / a0;
+    if (w.t + dt > tau) return false;
+    w.t = w.t + dt;
+    const double target = u2 * a0;
+    double cum = 0.0;
+    int32_t jsel = -1, last_pos = -1;
+    uint32_t dsel[W];
+#pragma unroll
+    for (int q = 0; q < W; ++q) dsel[q] = 0u;
+#pragma unroll
+    for (int j = 0; j < RMAX; ++j) {
+        if (j < net.R) {
+            cum = cum + prop[j];
+            if (prop[j] > 0.0) last_pos = j;
+            const bool hit = (jsel < 0) && (cum > target);
+            if (hit) jsel = j;
+            if constexpr (REG) {
+#pragma unroll
+                for (int q = 0; q < W; ++q) dsel[q] = hit ? net.drow[REG ? j : 0][q] : dsel[q];
+            }
+        }
+    }
+    if (jsel < 0) {   // rounding left the target above the running sum
+        jsel = last_pos;
+        if constexpr (REG) {
+#pragma unroll
+            for (int q = 0; q < W; ++q) dsel[q] = (uint32_t)net.dpack[jsel * WE_DPACK_WORDS + q];
+        }
+    }
+    if constexpr (!REG) {
+#pragma unroll
+        for (int q = 0; q < W; ++q) dsel[q] = (uint32_t)net.rows[jsel * W + q];
+    }
+    w.fired += 1;
+    int32_t any = 0;
+#pragma unroll
+    for (int s = 0; s < SMAX; ++s) {
+        x[s] += (int32_t)(dsel[s >> 2] << (24 - 8 * (s & 3))) >> 24;
+        any |= x[s];
+    }
+    // a count left [0, 2^17 - 1] iff a bit outside the low 17 is set
+    if (any & ~WE_COUNT_MAX_DEV) {
+        w.bad = true;
+        return false;
+    }
+    return true;
+}
+
+template <int SMAX>
+__device__ __forceinline__ void lane_finish(const SimArgs &a, const LaneWalker &w, const int32_t (&x)[SMAX],
+                                            int32_t *__restrict__ xr, size_t gslot) {
+    if (w.bad) atomicOr(a.err, WE_DERR_OVERFLOW);
+#pragma unroll
+    for (int s = 0; s < SMAX; ++s)
+        if (s < a.S) xr[s] = x[s];
+    a.ev_walker[gslot] = w.fired;
+}
+
+// One walker through one interval (one lane per walker, fixed assignment).
 template <int SMAX, int RMAX>
 __device__ __forceinline__ void lane_walker(const SimArgs &a, int32_t *__restrict__ xs, int32_t run,
                                             int32_t k, uint32_t iter, const int32_t *rows) {
-    constexpr int W = LaneRow<SMAX>::W;
-    constexpr bool REG = RMAX <= LANE_REG_RMAX;
-    const int32_t S = a.S, R = a.R;
-    int32_t *xw = xs + ((size_t)run * a.cap + k) * S;
+    LaneNet<SMAX, RMAX> net;
+    net.load(a, rows);
+    const size_t gslot = (size_t)run * a.cap + k;
+    int32_t *xr = xs + gslot * a.S;
+    LaneWalker w;
     int32_t x[SMAX];
-#pragma unroll
-    for (int s = 0; s < SMAX; ++s) x[s] = (s < S) ? xw[s] : 0;
-
-    // uniform tables (padded with zero-rate rows to 64 reactions, so every
-    // load is in bounds); small networks keep them for the whole interval
-    uint32_t drow[REG ? RMAX : 1][W];
-    LaneRxn rx[REG ? RMAX : 1];
-    if constexpr (REG) {
-#pragma unroll
-        for (int j = 0; j < RMAX; ++j) {
-            rx[j] = lane_rxn(a.desc, j);
-#pragma unroll
-            for (int w = 0; w < W; ++w) drow[j][w] = (uint32_t)a.dpack[j * WE_DPACK_WORDS + w];
-        }
+    w.begin(x, xr, a.S, (uint32_t)k, a.seeds[run]);
+    while (lane_event(net, w, x, iter, a.tau)) {
     }
-
-    const uint64_t seed = a.seeds[run];
-    const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
-    const double tau = a.tau;
-    double t = 0.0;
-    uint32_t e = 0, fired = 0;
-    bool bad = false;
-    double prop[RMAX];
-
-    for (;;) {
-        double a0 = 0.0;
-#pragma unroll
-        for (int j = 0; j < RMAX; ++j) {
-            const LaneRxn d = REG ? rx[REG ? j : 0] : lane_rxn(a.desc, j);
-            prop[j] = 0.0;
-            if (j < R) {
-                prop[j] = lane_propensity<SMAX>(d, x);
-                a0 = a0 + prop[j];
-            }
-        }
-        if (!(a0 > 0.0)) break;
-        const U4 r = philox4x32_10(e, (uint32_t)k, iter, 0u, k0, k1);
-        e += 1;
-        const double u1 = uniform53(r.x, r.y);
-        const double u2 = uniform53(r.z, r.w);
-        const double dt = -log(1.0 - u1) / a0;
-        if (t + dt > tau) break;
-        t = t + dt;
-        const double target = u2 * a0;
-        double cum = 0.0;
-        int32_t jsel = -1, last_pos = -1;
-        uint32_t dsel[W];
-#pragma unroll
-        for (int w = 0; w < W; ++w) dsel[w] = 0u;
-#pragma unroll
-        for (int j = 0; j < RMAX; ++j) {
-            if (j < R) {
-                cum = cum + prop[j];
-                if (prop[j] > 0.0) last_pos = j;
-                const bool hit = (jsel < 0) && (cum > target);
-                if (hit) jsel = j;
-                if constexpr (REG) {
-#pragma unroll
-                    for (int w = 0; w < W; ++w) dsel[w] = hit ? drow[j][w] : dsel[w];
-                }
-            }
-        }
-        if (jsel < 0) {   // rounding left the target above the running sum
-            jsel = last_pos;
-            if constexpr (REG) {
-#pragma unroll
-                for (int w = 0; w < W; ++w) dsel[w] = (uint32_t)a.dpack[jsel * WE_DPACK_WORDS + w];
-            }
-        }
-        if constexpr (!REG) {
-#pragma unroll
-            for (int w = 0; w < W; ++w) dsel[w] = (uint32_t)rows[jsel * W + w];
-        }
-        fired += 1;
-        int32_t any = 0;
-#pragma unroll
-        for (int s = 0; s < SMAX; ++s) {
-            x[s] += (int32_t)(dsel[s >> 2] << (24 - 8 * (s & 3))) >> 24;
-            any |= x[s];
-        }
-        // a count left [0, 2^17 - 1] iff a bit outside the low 17 is set
-        if (any & ~WE_COUNT_MAX_DEV) { bad = true; break; }
-    }
-    if (bad) atomicOr(a.err, WE_DERR_OVERFLOW);
-#pragma unroll
-    for (int s = 0; s < SMAX; ++s)
-        if (s < S) xw[s] = x[s];
-    a.ev_walker[(size_t)run * a.cap + k] = fired;
+    lane_finish(a, w, x, xr, gslot);
 }

@@ -100,6 +100,16 @@ struct SimArgs {
     int32_t joint_species[5];
     int32_t *err;
     uint32_t *iter_dev;                  // current WE iteration (advanced on the device)
+    // work queue of the lane kernel: segments of up to m_targ consecutive
+    // walkers, ordered by the mean events per walker of their bin
+    int32_t lane_pool;                   // 1: resampling gathers the per-bin event statistics
+    float *ev_bin;                       // [n_bins] events of the walkers that ended in each bin
+    int32_t *n_bin;                      // [n_bins] walkers that ended in each bin
+    int32_t *occ_bin;                    // [n_bins] queue segments per bin
+    int32_t *seg_off;                    // [n_bins] first queue segment of each bin
+    int32_t *seg_cur;                    // [n_bins]
+    int2 *seg;                           // [n_runs * n_bins] (first slot run*cap + j*m_targ, walkers)
+    uint32_t *queue;                     // [2] next walker index, number of segments
 };
 
 // ---------------------------------------------------------------- Philox

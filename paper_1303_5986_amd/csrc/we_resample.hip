@@ -382,7 +382,8 @@ __device__ void resample_run_t(const SimArgs &a, const double *__restrict__ w_cu
     int32_t *start = cnt + NB;                          // [NB+1]
     int32_t *ostart = start + NB + 1;                   // [NB+1]
     int32_t *cursor = ostart + NB + 1;                  // [NB]
-    unsigned char *tail = reinterpret_cast<unsigned char *>(cursor + NB);
+    float *evb = reinterpret_cast<float *>(cursor + NB); // [NB] events of the walkers in each bin
+    unsigned char *tail = reinterpret_cast<unsigned char *>(evb + NB);
     tail += (16 - ((uintptr_t)tail & 15)) & 15;
 
     const uint32_t iter = *a.iter_dev;
@@ -410,17 +411,30 @@ __device__ void resample_run_t(const SimArgs &a, const double *__restrict__ w_cu
         wk.aux = reinterpret_cast<Idx *>(a.s_cnt + base);
     }
 
-    for (int32_t b = tid; b < NB; b += nthr) cnt[b] = 0;
+    for (int32_t b = tid; b < NB; b += nthr) {
+        cnt[b] = 0;
+        evb[b] = 0.0f;
+    }
     __syncthreads();
     int64_t my_ev = 0;
     for (int32_t k = tid; k < n; k += nthr) {
         const int32_t b = sbin[k];
+        const uint32_t ev = a.ev_walker[base + k];
         wk.tag[k] = (uint16_t)(b | (srec[k] ? 0x8000 : 0));
         atomicAdd(&cnt[b], 1);
-        my_ev += a.ev_walker[base + k];
+        if (a.lane_pool) atomicAdd(&evb[b], (float)ev);
+        my_ev += ev;
     }
     ev_part[tid] = my_ev;
     __syncthreads();
+    // per-bin event statistics for the lane kernel's work queue (a
+    // scheduling hint only: no result depends on it)
+    if (a.lane_pool)
+        for (int32_t b = tid; b < NB; b += nthr)
+            if (cnt[b] > 0) {
+                atomicAdd(&a.ev_bin[b], evb[b]);
+                atomicAdd(&a.n_bin[b], cnt[b]);
+            }
 
     // wave 0: reactions fired, bin offsets, stable placement and the
     // recycled weight in slot order
@@ -647,7 +661,7 @@ hipError_t launch_recycle_bin(const SimArgs &a, int32_t *x_cur, bool grid_bins, 
 
 bool resample_uses_lds(const SimArgs &a);
 size_t resample_lds_bytes(const SimArgs &a, bool use_lds) {
-    size_t b = sizeof(int32_t) * (4 * (size_t)a.n_bins + 2) + 16;
+    size_t b = sizeof(int32_t) * (5 * (size_t)a.n_bins + 2) + 16;
     if (use_lds) b += (size_t)a.cap * (sizeof(double) + sizeof(int32_t) + 2 * sizeof(uint16_t));
     return b;
 }

@@ -23,6 +23,7 @@
 #include "we_internal.h"
 
 hipError_t launch_ssa_lane(const SimArgs &a, int32_t *xs, hipStream_t st);
+hipError_t launch_lane_schedule(const SimArgs &a, hipStream_t st);
 bool lane_kernel_fits(int32_t S, int32_t R, int32_t max_delta);
 hipError_t launch_ssa_wave(const SimArgs &a, int32_t *xs, hipStream_t st);
 bool wave_kernel_fits(int32_t S, int32_t R);
@@ -248,7 +249,7 @@ struct Layout {
 // Order of the pieces in the workspace; make_layout and we_init agree on it.
 enum Piece { P_X0, P_X1, P_W0, P_W1, P_BIN, P_ORIG, P_N, P_EVW, P_FLUX, P_EVI, P_SBIN, P_SREC,
              P_SLIST, P_SW, P_SCNT, P_HIST, P_SEEDS, P_BCOEF, P_EDGES, P_TCOEF, P_XREC, P_ERR,
-             P_SEG, P_ITER, P_JHIST, P_COUNT };
+             P_SEG, P_ITER, P_JHIST, P_SCHED, P_SEGLIST, P_QUEUE, P_COUNT };
 
 Layout make_layout(int32_t S, int32_t NB, int32_t n_runs, int32_t cap, int32_t max_iters,
                    int32_t nh, int64_t jcells) {
@@ -272,6 +273,9 @@ Layout make_layout(int32_t S, int32_t NB, int32_t n_runs, int32_t cap, int32_t m
     L.add(4 * (size_t)n_runs * max_iters);
     L.add(4);
     L.add(8 * (size_t)n_runs * (size_t)jcells);
+    L.add(4 * 5 * (size_t)NB);
+    L.add(8 * (size_t)n_runs * NB);
+    L.add(8);
     return L;
 }
 
@@ -407,6 +411,14 @@ extern "C" we_status we_init(const we_network *net, const we_grid *g, const we_p
     a.err = (int32_t *)at(P_ERR);
     a.iter_dev = (uint32_t *)at(P_ITER);
     a.jhist = (double *)at(P_JHIST);
+    a.lane_pool = kernel == WE_KERNEL_LANE ? 1 : 0;
+    a.ev_bin = (float *)at(P_SCHED);
+    a.n_bin = (int32_t *)at(P_SCHED) + NB;
+    a.occ_bin = (int32_t *)at(P_SCHED) + 2 * NB;
+    a.seg_off = (int32_t *)at(P_SCHED) + 3 * NB;
+    a.seg_cur = (int32_t *)at(P_SCHED) + 4 * NB;
+    a.seg = (int2 *)at(P_SEGLIST);
+    a.queue = (uint32_t *)at(P_QUEUE);
     a.n_joint = p->n_joint;
     a.joint_bins = p->n_joint > 0 ? p->joint_bins : 1;
     a.joint_width = p->n_joint > 0 ? p->joint_width : 1;
@@ -532,6 +544,10 @@ we_status launch_iteration(we_sim *s, hipStream_t st, bool profile) {
     SimArgs &a = s->args;
     const int32_t c = s->cur;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    if (s->kernel != WE_KERNEL_WAVE) {
+        const hipError_t e = launch_lane_schedule(a, st);
+        if (e != hipSuccess) return hip_fail(e, "lane work-queue launch");
+    }
     if (profile) {
         if (s->ev_used + 4 > 4096) HIP_TRY(drain_profile(s));
         for (int k = 0; k < 4; ++k) HIP_TRY(next_event(s, &ev[k]));
