@@ -378,7 +378,7 @@ def main():
         tag = "ssa_wave_large"
     else:
         cfg = wl.schlogl_config(n_runs=args.runs, seed0=1, n_iters=W + K)
-        kernel, kname = we.WE_KERNEL_LANE, "ssa_lane_kernel<1,4>"
+        kernel, kname = we.WE_KERNEL_LANE, "ssa_lane_pool_kernel<1,4>"
         ops_ev = alg_ops_per_event(cfg.net)
         cfg_desc = {"workload": "schlogl_steady_state_recycling", "runs": args.runs,
                     "bins": cfg.n_bins, "walkers_per_bin": cfg.m_targ, "tau": cfg.tau,

@@ -40,7 +40,7 @@ __global__ __launch_bounds__(256) void lane_seg_count_kernel(SimArgs a) {
     const int64_t first = (int64_t)j * a.m_targ;
     if (first >= a.n_walk[run]) return;
     const int32_t b = min(max(a.bin[(size_t)run * a.cap + first], 0), a.n_bins - 1);
-    atomicAdd(&a.occ_bin[b], 1);
+    atomicAdd(&a.occ_bin[b * a.seg_rep + run % a.seg_rep], 1);
 }
 
 // Bin order and queue offsets: one block.  Sorts the bins by mean events
@@ -82,11 +82,14 @@ __global__ __launch_bounds__(1024) void lane_seg_order_kernel(SimArgs a) {
             }
             __syncthreads();
         }
-    // exclusive prefix of segment counts in sorted order: per-thread chunks
-    const int32_t per = (NB + nthr - 1) / nthr;
-    const int32_t lo = min(tid * per, NB), hi = min(lo + per, NB);
+    // exclusive prefix of the segment counters in sorted bin order (the
+    // replicas of a bin consecutive): per-thread chunks of that sequence
+    const int32_t rep = a.seg_rep, NC = NB * rep;
+    const int32_t per = (NC + nthr - 1) / nthr;
+    const int32_t lo = min(tid * per, NC), hi = min(lo + per, NC);
+    auto counter = [&](int32_t i) { return (int32_t)idx[i / rep] * rep + i % rep; };
     int32_t acc = 0;
-    for (int32_t i = lo; i < hi; ++i) acc += a.occ_bin[idx[i]];
+    for (int32_t i = lo; i < hi; ++i) acc += a.occ_bin[counter(i)];
     // block-wide exclusive scan of the chunk sums: within waves, then over
     // the wave totals
     const int lane = tid & 63, wv = tid >> 6;
@@ -110,14 +113,16 @@ __global__ __launch_bounds__(1024) void lane_seg_order_kernel(SimArgs a) {
     __syncthreads();
     acc = part[wv] + incl - acc;
     for (int32_t i = lo; i < hi; ++i) {
-        const int32_t b = idx[i];
-        a.seg_off[b] = acc;
-        acc += a.occ_bin[b];
+        const int32_t c = counter(i);
+        a.seg_off[c] = acc;
+        acc += a.occ_bin[c];
     }
     __syncthreads();
+    for (int32_t c = tid; c < NC; c += nthr) {
+        a.occ_bin[c] = 0;
+        a.seg_cur[c] = 0;
+    }
     for (int32_t b = tid; b < NB; b += nthr) {
-        a.occ_bin[b] = 0;
-        a.seg_cur[b] = 0;
         a.ev_bin[b] = 0.0f;
         a.n_bin[b] = 0;
     }
@@ -133,12 +138,15 @@ __global__ __launch_bounds__(256) void lane_seg_fill_kernel(SimArgs a) {
     if (first >= n) return;
     const size_t g = (size_t)run * a.cap + first;
     const int32_t b = min(max(a.bin[g], 0), a.n_bins - 1);
-    const int32_t pos = a.seg_off[b] + atomicAdd(&a.seg_cur[b], 1);
+    const int32_t c = b * a.seg_rep + run % a.seg_rep;
+    const int32_t pos = a.seg_off[c] + atomicAdd(&a.seg_cur[c], 1);
     a.seg[pos] = make_int2((int32_t)g, (int32_t)min((int64_t)a.m_targ, n - first));
 }
 
 // Idle lanes refill once at least this many of the wave's lanes are idle.
-#define LANE_REFILL_MIN 8
+#ifndef LANE_REFILL_MIN
+#define LANE_REFILL_MIN 4
+#endif
 
 // Persistent lane kernel: every lane runs walkers from the queue until it is
 // empty; the wave takes as many queue entries as it has idle lanes with one

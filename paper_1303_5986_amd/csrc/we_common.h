@@ -105,9 +105,11 @@ struct SimArgs {
     int32_t lane_pool;                   // 1: resampling gathers the per-bin event statistics
     float *ev_bin;                       // [n_bins] events of the walkers that ended in each bin
     int32_t *n_bin;                      // [n_bins] walkers that ended in each bin
-    int32_t *occ_bin;                    // [n_bins] queue segments per bin
-    int32_t *seg_off;                    // [n_bins] first queue segment of each bin
-    int32_t *seg_cur;                    // [n_bins]
+    int32_t seg_rep;                     // counters per bin (spread over replicas, picked by run,
+                                         //   against atomic contention): min(32, max(1, 4096/n_bins))
+    int32_t *occ_bin;                    // [n_bins][seg_rep] queue segments per counter
+    int32_t *seg_off;                    // [n_bins][seg_rep] first queue segment of each counter
+    int32_t *seg_cur;                    // [n_bins][seg_rep]
     int2 *seg;                           // [n_runs * n_bins] (first slot run*cap + j*m_targ, walkers)
     uint32_t *queue;                     // [2] next walker index, number of segments
 };

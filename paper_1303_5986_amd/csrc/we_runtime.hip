@@ -251,6 +251,8 @@ enum Piece { P_X0, P_X1, P_W0, P_W1, P_BIN, P_ORIG, P_N, P_EVW, P_FLUX, P_EVI, P
              P_SLIST, P_SW, P_SCNT, P_HIST, P_SEEDS, P_BCOEF, P_EDGES, P_TCOEF, P_XREC, P_ERR,
              P_SEG, P_ITER, P_JHIST, P_SCHED, P_SEGLIST, P_QUEUE, P_COUNT };
 
+int32_t seg_rep_for(int32_t NB) { return std::min(32, std::max(1, 4096 / NB)); }
+
 Layout make_layout(int32_t S, int32_t NB, int32_t n_runs, int32_t cap, int32_t max_iters,
                    int32_t nh, int64_t jcells) {
     Layout L;
@@ -273,7 +275,7 @@ Layout make_layout(int32_t S, int32_t NB, int32_t n_runs, int32_t cap, int32_t m
     L.add(4 * (size_t)n_runs * max_iters);
     L.add(4);
     L.add(8 * (size_t)n_runs * (size_t)jcells);
-    L.add(4 * 5 * (size_t)NB);
+    L.add(4 * (2 + 3 * (size_t)seg_rep_for(NB)) * (size_t)NB);
     L.add(8 * (size_t)n_runs * NB);
     L.add(8);
     return L;
@@ -414,9 +416,10 @@ extern "C" we_status we_init(const we_network *net, const we_grid *g, const we_p
     a.lane_pool = kernel == WE_KERNEL_LANE ? 1 : 0;
     a.ev_bin = (float *)at(P_SCHED);
     a.n_bin = (int32_t *)at(P_SCHED) + NB;
+    a.seg_rep = seg_rep_for(NB);
     a.occ_bin = (int32_t *)at(P_SCHED) + 2 * NB;
-    a.seg_off = (int32_t *)at(P_SCHED) + 3 * NB;
-    a.seg_cur = (int32_t *)at(P_SCHED) + 4 * NB;
+    a.seg_off = a.occ_bin + a.seg_rep * NB;
+    a.seg_cur = a.seg_off + a.seg_rep * NB;
     a.seg = (int2 *)at(P_SEGLIST);
     a.queue = (uint32_t *)at(P_QUEUE);
     a.n_joint = p->n_joint;
