@@ -368,7 +368,7 @@ def main():
     K, W = args.steps, args.warmup
     if args.workload == "large":
         cfg = wl.large_network_config(n_iters=W + K)
-        kernel, kname = we.WE_KERNEL_WAVE, "ssa_wave_kernel"
+        kernel, kname = we.WE_KERNEL_WAVE, "ssa_wave_lds_kernel"
         ops_ev = alg_ops_per_event_wave(cfg.net)
         cfg_desc = {"workload": "large_network_354x3680", "runs": 1, "species": cfg.net.S,
                     "reactions": cfg.net.R, "bins": cfg.n_bins, "walkers_per_bin": cfg.m_targ,

@@ -19,8 +19,8 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libwe.so")
 
-SOURCES = ["we_runtime.hip", "ssa_lane.hip", "ssa_wave.hip", "we_resample.hip", "committor.hip",
-           "batch.hip"]
+SOURCES = ["we_runtime.hip", "work_queue.hip", "ssa_lane.hip", "ssa_wave.hip", "we_resample.hip",
+           "committor.hip", "batch.hip"]
 
 
 def hipcc() -> str:

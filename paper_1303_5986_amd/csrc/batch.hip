@@ -64,9 +64,10 @@ __global__ __launch_bounds__(256) void batch_lane_kernel(const SimArgs *__restri
     int32_t *wrows = rows + (threadIdx.x >> 6) * ROWS;
     const int lane = threadIdx.x & 63;
     for (;;) {
-        uint32_t idx = 0;
-        if (lane == 0) idx = atomicAdd(counter, 1u);
-        idx = __shfl(idx, 0, 64);
+        // every lane executes the atomic (lane 0 adds one): no lane takes a
+        // path of its own around the wave-wide steps of the walker
+        const uint32_t got = atomicAdd(counter, lane == 0 ? 1u : 0u);
+        const uint32_t idx = (uint32_t)__shfl((int)got, 0, 64);
         if (idx >= (uint32_t)n_items) break;
         const Item it = items[idx];
         const SimArgs &a = args[it.sim];
@@ -86,9 +87,10 @@ __global__ __launch_bounds__(256) void batch_wave_kernel(const SimArgs *__restri
     double *lchunk = reinterpret_cast<double *>(smem) + wv * 64;
     int32_t *lx = reinterpret_cast<int32_t *>(smem + WAVE_WALKERS_PER_BLOCK * 64 * sizeof(double)) + wv * s_pad;
     for (;;) {
-        uint32_t idx = 0;
-        if (lane == 0) idx = atomicAdd(counter, 1u);
-        idx = __shfl(idx, 0, 64);
+        // every lane executes the atomic (lane 0 adds one): no lane takes a
+        // path of its own around the wave-wide steps of the walker
+        const uint32_t got = atomicAdd(counter, lane == 0 ? 1u : 0u);
+        const uint32_t idx = (uint32_t)__shfl((int)got, 0, 64);
         if (idx >= (uint32_t)n_items) break;
         const Item it = items[idx];
         const SimArgs &a = args[it.sim];
@@ -328,7 +330,7 @@ extern "C" we_status we_batch_create(int32_t n, const we_network *const *nets, c
     std::vector<int32_t> use_lds, grid_bins;
     for (we_sim *s : b->sims) {
         args.push_back(s->args);
-        args.back().lane_pool = 0;   // the batched kernels keep their own work queue
+        args.back().queue_stats = 0;   // the batched kernels keep their own work queue
         xp0.push_back(s->x[0]);
         xp1.push_back(s->x[1]);
         wp0.push_back(s->w[0]);

@@ -37,14 +37,6 @@ __device__ __forceinline__ LaneRxn lane_rxn(const RxnDesc *__restrict__ desc, in
     return o;
 }
 
-// C(x, nu) for nu in {0,1,2,3}, exactly, as a double.
-__device__ __forceinline__ double binom_f64(double xd, uint32_t nu) {
-    const double p2 = xd * fmax(xd - 1.0, 0.0);                          // x(x-1)
-    const double c3 = rint(((p2 * fmax(xd - 2.0, 0.0)) * 0.5) * (1.0 / 3.0));
-    const double c2 = p2 * 0.5;
-    return nu == 0 ? 1.0 : nu == 1 ? xd : nu == 2 ? c2 : c3;
-}
-
 template <int SMAX>
 __device__ __forceinline__ double lane_propensity(const LaneRxn &d, const int32_t (&x)[SMAX]) {
     const double h1 = binom_f64((double)x[SMAX == 1 ? 0 : d.s1], d.nu1);

@@ -25,15 +25,17 @@
 //    interval.
 //
 // Memory: walker counts (int32) and chunk sums live in LDS (about 2 KB per
-// walker at 354 species), so a CU holds many walkers at once; reaction
-// descriptors, stoichiometry and dependency lists are read from global
-// memory, where the whole network (~0.3 MB at 3680 reactions) stays
-// resident in the L2 caches.  No per-reaction propensity array is stored.
+// walker at 354 species).  When they fit, the block also keeps the reaction
+// descriptors and headers in LDS (ssa_wave_lds_kernel); dependency lists and
+// stoichiometry are read from global memory, where they stay resident in
+// the L2 caches.  No per-reaction propensity array is stored.
 //
 // Summation order differs from the sequential order of the oracle (chunked
 // scans), so a0 and the running sums can differ in the last bits; an event
 // changes only if u2*a0 or t+dt falls within a few ulps of a boundary.
 #include "ssa_wave_body.h"
+
+#include <algorithm>
 
 __global__ __launch_bounds__(256) void ssa_wave_kernel(SimArgs a, int32_t *__restrict__ xs,
                                                        int32_t s_pad) {
@@ -50,13 +52,109 @@ __global__ __launch_bounds__(256) void ssa_wave_kernel(SimArgs a, int32_t *__res
     wave_walker(a, xs, run, k, *a.iter_dev, lchunk, lx);
 }
 
+// LDS-table variant: the block copies the descriptor and header tables (32
+// bytes per reaction, 118 KB at 3680 reactions) into LDS once, and its waves
+// then take walkers from the work queue until it is empty.  Per event the
+// only global-memory round trip left is the fired reaction's dependency
+// ids and changes (16-bit ids: 0.3 MB for the whole 3680-reaction network,
+// which stays in L2).
+#define WAVE_LDS_MAX_WAVES 8
+#define WAVE_LDS_BYTES (160 * 1024)
+
+__global__ __launch_bounds__(64 * WAVE_LDS_MAX_WAVES) void ssa_wave_lds_kernel(SimArgs a, int32_t *__restrict__ xs,
+                                                                              int32_t s_pad) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int32_t R = a.R;
+    RxnDesc *ldesc = reinterpret_cast<RxnDesc *>(smem);
+    RxnInfo *linfo = reinterpret_cast<RxnInfo *>(smem + 16 * (size_t)R);
+    unsigned char *wbase = smem + 32 * (size_t)R;
+    const int nw = blockDim.x >> 6, wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    double *lchunk = reinterpret_cast<double *>(wbase) + wv * 64;
+    int32_t *lx = reinterpret_cast<int32_t *>(wbase + (size_t)nw * 64 * sizeof(double)) + wv * s_pad;
+    const uint4 *gd = reinterpret_cast<const uint4 *>(a.desc);
+    const uint4 *gh = reinterpret_cast<const uint4 *>(a.rinfo);
+    uint4 *sd = reinterpret_cast<uint4 *>(ldesc);
+    uint4 *sh = reinterpret_cast<uint4 *>(linfo);
+    for (int32_t i = threadIdx.x; i < R; i += blockDim.x) {
+        sd[i] = gd[i];
+        sh[i] = gh[i];
+    }
+    __syncthreads();
+    LdsTables tab;
+    tab.d = ldesc;
+    tab.h = linfo;
+    tab.ids = a.dep;
+    const uint32_t iter = *a.iter_dev;
+    const uint32_t M = (uint32_t)a.m_targ, cap = (uint32_t)a.cap;
+    const uint32_t total = a.queue[1] * M;
+    // Every lane executes the atomic (lane 0 adds one, the others zero) and
+    // lane 0's result is broadcast.  With the atomic inside `if (lane == 0)`
+    // the compiler routed lanes 1-63 around it (their result is always
+    // zero) into an inner loop of their own, so they ran the next walker
+    // without lane 0 -- and wave_walker_t needs the whole wave.
+    for (;;) {
+        const uint32_t got = atomicAdd(&a.queue[0], lane == 0 ? 1u : 0u);
+        const uint32_t q = (uint32_t)__shfl((int)got, 0, 64);
+        if (q >= total) break;
+        const uint32_t sg = q / M, o = q - sg * M;
+        const int2 seg = a.seg[sg];
+        if ((int32_t)o < seg.y) {
+            const uint32_t g = (uint32_t)seg.x + o;
+            const uint32_t run = g / cap;
+            wave_walker_t(a, tab, xs, (int32_t)run, (int32_t)(g - run * cap), iter, lchunk, lx);
+        }
+    }
+}
+
 bool wave_kernel_fits(int32_t S, int32_t R) { return R <= 4096 && S <= 8192; }
 
+namespace {
+// Blocks of the LDS variant that stay resident per CU, for a given LDS size.
+int lds_blocks_per_cu(int waves, size_t shmem) {
+    static size_t last_shmem = 0;
+    static int last_waves = 0, last = 1;
+    if (shmem != last_shmem || waves != last_waves) {
+        int nb = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, ssa_wave_lds_kernel, 64 * waves, shmem) !=
+                hipSuccess || nb < 1)
+            nb = 1;
+        last = nb;
+        last_shmem = shmem;
+        last_waves = waves;
+    }
+    return last;
+}
+
+int device_cus() {
+    static int n = 0;
+    if (n == 0) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n < 1)
+            n = 1;
+    }
+    return n;
+}
+}  // namespace
+
+// The LDS variant when its tables and at least two walkers fit in one CU's
+// LDS (it then needs the work queue built by launch_work_queue), else
+// one wave per slot with tables in global memory.
 hipError_t launch_ssa_wave(const SimArgs &a, int32_t *xs, hipStream_t st) {
     if (!wave_kernel_fits(a.S, a.R)) return hipErrorInvalidValue;
     const int32_t s_pad = (a.S + 3) & ~3;
-    const size_t shmem = WAVE_WALKERS_PER_BLOCK * (64 * sizeof(double) + sizeof(int32_t) * (size_t)s_pad);
+    const size_t per_wave = 64 * sizeof(double) + sizeof(int32_t) * (size_t)s_pad;
+    const size_t tables = 32 * (size_t)a.R;
     const int64_t walkers = (int64_t)a.n_runs * a.cap;
+    if (tables + 2 * per_wave <= WAVE_LDS_BYTES) {
+        const int nw = (int)std::min<size_t>(WAVE_LDS_MAX_WAVES, (WAVE_LDS_BYTES - tables) / per_wave);
+        const size_t shmem = tables + nw * per_wave;
+        const int64_t resident = (int64_t)lds_blocks_per_cu(nw, shmem) * device_cus();
+        const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>(resident, (walkers + nw - 1) / nw));
+        hipLaunchKernelGGL(ssa_wave_lds_kernel, dim3(blocks), dim3(64 * nw), shmem, st, a, xs, s_pad);
+        return hipGetLastError();
+    }
+    const size_t shmem = WAVE_WALKERS_PER_BLOCK * per_wave;
     const unsigned blocks = (unsigned)((walkers + WAVE_WALKERS_PER_BLOCK - 1) / WAVE_WALKERS_PER_BLOCK);
     hipLaunchKernelGGL(ssa_wave_kernel, dim3(blocks), dim3(64 * WAVE_WALKERS_PER_BLOCK), shmem, st, a,
                        xs, s_pad);

@@ -63,10 +63,11 @@ __device__ __forceinline__ int32_t last_set(unsigned long long m) {
 }
 
 // Sum of all 64 propensities of chunk c (last lane of the scan).
-__device__ __forceinline__ double chunk_total(const SimArgs &a, const int32_t *lx, int c, int lane) {
+template <class T>
+__device__ __forceinline__ double chunk_total(const T &tab, int32_t R, const int32_t *lx, int c, int lane) {
     const int r = c * 64 + lane;
     double v = 0.0;
-    if (r < a.R) v = prop_lds(a.desc[r], lx);
+    if (r < R) v = prop_lds(tab.desc(r), lx);
     return lane_value(scan_incl(v), 63);
 }
 
@@ -89,10 +90,46 @@ __device__ __forceinline__ void add_chunk_deltas(double *lchunk, int rr, double 
 
 }  // namespace
 
+// Where the wave reads the network from.
+//  GlobalTables: descriptors, reaction headers and dependency entries (each
+//    with its reaction's descriptor inline) from global memory;
+//  LdsTables: descriptors and headers from the block's LDS copy; the
+//    dependency lists as 16-bit reaction ids from global memory, their
+//    descriptors from LDS.
+struct GlobalTables {
+    const RxnDesc *__restrict__ d;
+    const RxnInfo *__restrict__ h;
+    const DepEntry *__restrict__ e;
+    __device__ __forceinline__ RxnDesc desc(int r) const { return d[r]; }
+    __device__ __forceinline__ RxnInfo info(int j) const { return h[j]; }
+    __device__ __forceinline__ DepEntry dep(int i) const { return e[i]; }
+};
+
+struct LdsTables {
+    const RxnDesc *d;                  // LDS
+    const RxnInfo *h;                  // LDS
+    const uint16_t *__restrict__ ids;  // global
+    __device__ __forceinline__ RxnDesc desc(int r) const { return d[r]; }
+    __device__ __forceinline__ RxnInfo info(int j) const { return h[j]; }
+    __device__ __forceinline__ DepEntry dep(int i) const {
+        const int r = ids[i];
+        const RxnDesc q = d[r];
+        DepEntry o;
+        o.c = q.c;
+        o.s1 = q.s1;
+        o.s2 = q.s2;
+        o.nu1 = q.nu1;
+        o.nu2 = q.nu2;
+        o.r = (uint16_t)r;
+        return o;
+    }
+};
+
 // One walker through one interval on the calling wave; lchunk (64 doubles)
 // and lx (S ints) are this wave's LDS slices.
-__device__ inline void wave_walker(const SimArgs &a, int32_t *__restrict__ xs, int32_t run, int32_t k,
-                                   uint32_t iter, double *lchunk, int32_t *lx) {
+template <class T>
+__device__ inline void wave_walker_t(const SimArgs &a, const T &tab, int32_t *__restrict__ xs, int32_t run,
+                                     int32_t k, uint32_t iter, double *lchunk, int32_t *lx) {
     const int lane = threadIdx.x & 63;
     const int32_t S = a.S, R = a.R;
     const int32_t K = (R + 63) >> 6;
@@ -103,7 +140,7 @@ __device__ inline void wave_walker(const SimArgs &a, int32_t *__restrict__ xs, i
     // chunk sums from scratch
     double csum = 0.0;
     for (int c = 0; c < K; ++c) {
-        const double tot = chunk_total(a, lx, c, lane);
+        const double tot = chunk_total(tab, R, lx, c, lane);
         if (lane == c) csum = tot;
     }
     lchunk[lane] = csum;
@@ -114,16 +151,23 @@ __device__ inline void wave_walker(const SimArgs &a, int32_t *__restrict__ xs, i
     double t = 0.0;
     uint32_t e = 0, fired = 0;
     bool bad = false;
+    // random numbers of 64 events at a time, one event per lane: lane l holds
+    // -log(1 - u1) and u2 of event (e & ~63) + l
+    double rexp = 0.0, ru2 = 0.0;
 
     for (;;) {
         const double P = scan_incl(csum);
         const double a0 = lane_value(P, 63);
         if (!(a0 > 0.0)) break;
-        const U4 rnd = philox4x32_10(e, (uint32_t)k, iter, 0u, k0, k1);
+        if ((e & 63u) == 0u) {
+            const U4 rnd = philox4x32_10(e + (uint32_t)lane, (uint32_t)k, iter, 0u, k0, k1);
+            rexp = -log(1.0 - uniform53(rnd.x, rnd.y));
+            ru2 = uniform53(rnd.z, rnd.w);
+        }
+        const double ex = lane_value(rexp, (int)(e & 63u));
+        const double u2 = lane_value(ru2, (int)(e & 63u));
         e += 1;
-        const double u1 = uniform53(rnd.x, rnd.y);
-        const double u2 = uniform53(rnd.z, rnd.w);
-        const double dt = -log(1.0 - u1) / a0;
+        const double dt = ex / a0;
         if (t + dt > tau) break;
         t = t + dt;
         const double target = u2 * a0;
@@ -138,7 +182,7 @@ __device__ inline void wave_walker(const SimArgs &a, int32_t *__restrict__ xs, i
         // reaction inside the chunk
         const int rsel = cs * 64 + lane;
         double v = 0.0;
-        if (rsel < R) v = prop_lds(a.desc[rsel], lx);
+        if (rsel < R) v = prop_lds(tab.desc(rsel), lx);
         const double Q = scan_incl(v);
         const unsigned long long m2 = __ballot(Q > target2);
         const int ls = m2 ? (__ffsll((long long)m2) - 1) : last_set(__ballot(v > 0.0));
@@ -149,7 +193,7 @@ __device__ inline void wave_walker(const SimArgs &a, int32_t *__restrict__ xs, i
         const int j = __builtin_amdgcn_readfirstlane(cs * 64 + ls);
 
         // header of j; its dependents (with descriptors) and changes
-        const RxnInfo info = a.rinfo[j];
+        const RxnInfo info = tab.info(j);
         const int32_t nd = info.dep_count;
         const int nround = (nd + 63) >> 6;
         int32_t pc = 0;
@@ -165,7 +209,7 @@ __device__ inline void wave_walker(const SimArgs &a, int32_t *__restrict__ xs, i
                 if (q < nround) {
                     const int idx = q * 64 + lane;
                     if (idx < nd) {
-                        de[q] = a.deps[info.dep_begin + idx];
+                        de[q] = tab.dep(info.dep_begin + idx);
                         rr[q] = de[q].r;
                         old[q] = prop_lds(de[q], lx);
                     }
@@ -201,7 +245,7 @@ __device__ inline void wave_walker(const SimArgs &a, int32_t *__restrict__ xs, i
             // very long dependency list: rebuild every chunk sum
             csum = 0.0;
             for (int c = 0; c < K; ++c) {
-                const double tot = chunk_total(a, lx, c, lane);
+                const double tot = chunk_total(tab, R, lx, c, lane);
                 if (lane == c) csum = tot;
             }
             lchunk[lane] = csum;
@@ -211,4 +255,13 @@ __device__ inline void wave_walker(const SimArgs &a, int32_t *__restrict__ xs, i
     __builtin_amdgcn_wave_barrier();
     for (int s = lane; s < S; s += 64) xw[s] = lx[s];
     if (lane == 0) a.ev_walker[(size_t)run * a.cap + k] = fired;
+}
+
+__device__ inline void wave_walker(const SimArgs &a, int32_t *__restrict__ xs, int32_t run, int32_t k,
+                                   uint32_t iter, double *lchunk, int32_t *lx) {
+    GlobalTables tab;
+    tab.d = a.desc;
+    tab.h = a.rinfo;
+    tab.e = a.deps;
+    wave_walker_t(a, tab, xs, run, k, iter, lchunk, lx);
 }

@@ -76,6 +76,9 @@ struct SimArgs {
     int32_t recycle;
     double tgt_thr;
     const double *__restrict__ tgt_coef; // [S]
+    const int32_t *__restrict__ bin_nz;  // species with a nonzero bin_coef, ascending
+    const int32_t *__restrict__ tgt_nz;  // species with a nonzero tgt_coef, ascending
+    int32_t n_bin_nz, n_tgt_nz;
     const int32_t *__restrict__ x_rec;   // [S]
     // ensemble (current and next buffers are passed per launch)
     int32_t *n_walk;                     // [n_runs]
@@ -100,9 +103,9 @@ struct SimArgs {
     int32_t joint_species[5];
     int32_t *err;
     uint32_t *iter_dev;                  // current WE iteration (advanced on the device)
-    // work queue of the lane kernel: segments of up to m_targ consecutive
-    // walkers, ordered by the mean events per walker of their bin
-    int32_t lane_pool;                   // 1: resampling gathers the per-bin event statistics
+    // work queue of the propagation kernels: segments of up to m_targ
+    // consecutive walkers, ordered by the mean events per walker of their bin
+    int32_t queue_stats;                 // 1: resampling gathers the per-bin event statistics
     float *ev_bin;                       // [n_bins] events of the walkers that ended in each bin
     int32_t *n_bin;                      // [n_bins] walkers that ended in each bin
     int32_t seg_rep;                     // counters per bin (spread over replicas, picked by run,
@@ -141,21 +144,23 @@ __device__ __forceinline__ double uniform53(uint32_t a, uint32_t b) {
 }
 
 // ---------------------------------------------------------------- propensity
-// C(x, nu) for nu in {0,1,2,3} as an exact 64-bit integer (x <= 2^17).
-__device__ __forceinline__ uint64_t binom_small(uint32_t x, uint32_t nu) {
-    if (nu == 0) return 1u;
-    if (x < nu) return 0u;
-    if (nu == 1) return x;
-    const uint64_t pair = ((uint64_t)x * (uint64_t)(x - 1u)) >> 1;   // C(x,2)
-    if (nu == 2) return pair;
-    return (pair * (uint64_t)(x - 2u)) / 3u;                          // C(x,3)
+// C(x, nu) for nu in {0,1,2,3}, exactly, as a double (x <= 2^17): x(x-1) and
+// x(x-1)(x-2) are integers below 2^53, so every product is exact; C(x,3) is
+// x(x-1)(x-2)/2 times the double nearest 1/3, rounded to the nearest integer,
+// which is exact because the error is below 2^-3.  No 64-bit integer
+// multiply or divide (quarter-rate on CDNA) is needed.
+__device__ __forceinline__ double binom_f64(double xd, uint32_t nu) {
+    const double p2 = xd * fmax(xd - 1.0, 0.0);
+    const double c3 = rint(((p2 * fmax(xd - 2.0, 0.0)) * 0.5) * (1.0 / 3.0));
+    const double c2 = p2 * 0.5;
+    return nu == 0 ? 1.0 : nu == 1 ? xd : nu == 2 ? c2 : c3;
 }
 
-// a_j = c_j * h_j(x), h_j exact in int64 and converted once.
+// a_j = c_j * h_j(x): h_j is an exact integer (order <= 3 keeps it below
+// 2^53), so the only rounding is the final product, as with an int64 h.
 template <class D>
 __device__ __forceinline__ double propensity_from(const D &d, uint32_t x1, uint32_t x2) {
-    const uint64_t h = binom_small(x1, d.nu1) * binom_small(x2, d.nu2);
-    return d.c * (double)h;
+    return d.c * (binom_f64((double)x1, d.nu1) * binom_f64((double)x2, d.nu2));
 }
 
 // ---------------------------------------------------------------- bins

@@ -94,7 +94,7 @@ struct we_sim {
 extern "C" void we_batch_destroy(we_batch *b);
 we_status we_sim_bookkeeping(we_sim *s, hipStream_t st, hipEvent_t *ev);
 hipError_t launch_ssa_lane(const SimArgs &a, int32_t *xs, hipStream_t st);
-hipError_t launch_lane_schedule(const SimArgs &a, hipStream_t st);
+hipError_t launch_work_queue(const SimArgs &a, hipStream_t st);
 hipError_t launch_ssa_wave(const SimArgs &a, int32_t *xs, hipStream_t st);
 bool lane_kernel_fits(int32_t S, int32_t R, int32_t max_delta);
 bool wave_kernel_fits(int32_t S, int32_t R);

@@ -39,10 +39,16 @@
 
 #define RESAMPLE_LDS_CAP 8192
 
-__device__ __forceinline__ double coord_of(const double *__restrict__ coef,
-                                           const int32_t *__restrict__ xr, int32_t S) {
+// sum_s coef_s x_s in ascending species order over the nonzero
+// coefficients only: a zero coefficient adds +0 or -0, which leaves a sum
+// that started at +0 unchanged, so the result is the full sum bit for bit.
+__device__ __forceinline__ double coord_of(const double *__restrict__ coef, const int32_t *__restrict__ nz,
+                                           int32_t n_nz, const int32_t *__restrict__ xr) {
     double q = 0.0;
-    for (int32_t s = 0; s < S; ++s) q = q + coef[s] * (double)xr[s];
+    for (int32_t i = 0; i < n_nz; ++i) {
+        const int32_t s = nz[i];
+        q = q + coef[s] * (double)xr[s];
+    }
     return q;
 }
 
@@ -56,12 +62,12 @@ __device__ __forceinline__ void recycle_bin_one(const SimArgs &a, int32_t *__res
     const size_t idx = (size_t)run * a.cap + k;
     int32_t *row = x_cur + idx * S;
     int32_t rec = 0;
-    if (a.recycle && coord_of(a.tgt_coef, row, S) >= a.tgt_thr) {
+    if (a.recycle && coord_of(a.tgt_coef, a.tgt_nz, a.n_tgt_nz, row) >= a.tgt_thr) {
         rec = 1;
         for (int32_t s = 0; s < S; ++s) row[s] = a.x_rec[s];
     }
     a.s_rec[idx] = rec;
-    if (grid_bins) a.s_bin[idx] = bin_index(a.edges, a.n_bins, coord_of(a.bin_coef, row, S));
+    if (grid_bins) a.s_bin[idx] = bin_index(a.edges, a.n_bins, coord_of(a.bin_coef, a.bin_nz, a.n_bin_nz, row));
 }
 
 __global__ __launch_bounds__(256) void we_recycle_bin_kernel(SimArgs a, int32_t *__restrict__ x_cur,
@@ -422,14 +428,14 @@ __device__ void resample_run_t(const SimArgs &a, const double *__restrict__ w_cu
         const uint32_t ev = a.ev_walker[base + k];
         wk.tag[k] = (uint16_t)(b | (srec[k] ? 0x8000 : 0));
         atomicAdd(&cnt[b], 1);
-        if (a.lane_pool) atomicAdd(&evb[b], (float)ev);
+        if (a.queue_stats) atomicAdd(&evb[b], (float)ev);
         my_ev += ev;
     }
     ev_part[tid] = my_ev;
     __syncthreads();
-    // per-bin event statistics for the lane kernel's work queue (a
+    // per-bin event statistics for the propagation kernels' work queue (a
     // scheduling hint only: no result depends on it)
-    if (a.lane_pool)
+    if (a.queue_stats)
         for (int32_t b = tid; b < NB; b += nthr)
             if (cnt[b] > 0) {
                 atomicAdd(&a.ev_bin[b], evb[b]);

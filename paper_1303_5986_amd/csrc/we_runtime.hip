@@ -23,7 +23,7 @@
 #include "we_internal.h"
 
 hipError_t launch_ssa_lane(const SimArgs &a, int32_t *xs, hipStream_t st);
-hipError_t launch_lane_schedule(const SimArgs &a, hipStream_t st);
+hipError_t launch_work_queue(const SimArgs &a, hipStream_t st);
 bool lane_kernel_fits(int32_t S, int32_t R, int32_t max_delta);
 hipError_t launch_ssa_wave(const SimArgs &a, int32_t *xs, hipStream_t st);
 bool wave_kernel_fits(int32_t S, int32_t R);
@@ -249,7 +249,7 @@ struct Layout {
 // Order of the pieces in the workspace; make_layout and we_init agree on it.
 enum Piece { P_X0, P_X1, P_W0, P_W1, P_BIN, P_ORIG, P_N, P_EVW, P_FLUX, P_EVI, P_SBIN, P_SREC,
              P_SLIST, P_SW, P_SCNT, P_HIST, P_SEEDS, P_BCOEF, P_EDGES, P_TCOEF, P_XREC, P_ERR,
-             P_SEG, P_ITER, P_JHIST, P_SCHED, P_SEGLIST, P_QUEUE, P_COUNT };
+             P_SEG, P_ITER, P_JHIST, P_SCHED, P_SEGLIST, P_QUEUE, P_NZ, P_COUNT };
 
 int32_t seg_rep_for(int32_t NB) { return std::min(32, std::max(1, 4096 / NB)); }
 
@@ -278,6 +278,7 @@ Layout make_layout(int32_t S, int32_t NB, int32_t n_runs, int32_t cap, int32_t m
     L.add(4 * (2 + 3 * (size_t)seg_rep_for(NB)) * (size_t)NB);
     L.add(8 * (size_t)n_runs * NB);
     L.add(8);
+    L.add(4 * 2 * (size_t)S);
     return L;
 }
 
@@ -396,6 +397,8 @@ extern "C" we_status we_init(const we_network *net, const we_grid *g, const we_p
     a.recycle = p->recycle ? 1 : 0;
     a.tgt_thr = p->tgt_thr;
     a.tgt_coef = (const double *)at(P_TCOEF);
+    a.bin_nz = (const int32_t *)at(P_NZ);
+    a.tgt_nz = a.bin_nz + S;
     a.x_rec = (const int32_t *)at(P_XREC);
     a.n_walk = (int32_t *)at(P_N);
     a.bin = (int32_t *)at(P_BIN);
@@ -413,7 +416,7 @@ extern "C" we_status we_init(const we_network *net, const we_grid *g, const we_p
     a.err = (int32_t *)at(P_ERR);
     a.iter_dev = (uint32_t *)at(P_ITER);
     a.jhist = (double *)at(P_JHIST);
-    a.lane_pool = kernel == WE_KERNEL_LANE ? 1 : 0;
+    a.queue_stats = 1;
     a.ev_bin = (float *)at(P_SCHED);
     a.n_bin = (int32_t *)at(P_SCHED) + NB;
     a.seg_rep = seg_rep_for(NB);
@@ -452,6 +455,13 @@ extern "C" we_status we_init(const we_network *net, const we_grid *g, const we_p
     if (e == hipSuccess) e = put(P_BCOEF, g->coef, 8 * (size_t)S);
     if (e == hipSuccess) e = put(P_EDGES, g->edges, 8 * (size_t)(NB + 1));
     if (e == hipSuccess) e = put(P_TCOEF, p->tgt_coef ? p->tgt_coef : zcoef.data(), 8 * (size_t)S);
+    std::vector<int32_t> nz(2 * (size_t)S, 0);
+    a.n_bin_nz = a.n_tgt_nz = 0;
+    for (int32_t sp = 0; sp < S; ++sp) {
+        if (g->coef[sp] != 0.0) nz[a.n_bin_nz++] = sp;
+        if (p->tgt_coef && p->tgt_coef[sp] != 0.0) nz[S + a.n_tgt_nz++] = sp;
+    }
+    if (e == hipSuccess) e = put(P_NZ, nz.data(), 4 * 2 * (size_t)S);
     if (e == hipSuccess) e = put(P_XREC, p->x_rec ? p->x_rec : p->x0, 4 * (size_t)S);
     if (e == hipSuccess) e = hipStreamSynchronize(st_);
     if (e != hipSuccess) {
@@ -547,9 +557,9 @@ we_status launch_iteration(we_sim *s, hipStream_t st, bool profile) {
     SimArgs &a = s->args;
     const int32_t c = s->cur;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
-    if (s->kernel != WE_KERNEL_WAVE) {
-        const hipError_t e = launch_lane_schedule(a, st);
-        if (e != hipSuccess) return hip_fail(e, "lane work-queue launch");
+    {
+        const hipError_t e = launch_work_queue(a, st);
+        if (e != hipSuccess) return hip_fail(e, "work-queue launch");
     }
     if (profile) {
         if (s->ev_used + 4 > 4096) HIP_TRY(drain_profile(s));

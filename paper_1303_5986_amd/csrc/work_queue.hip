@@ -1,0 +1,133 @@
+// work_queue.hip -- the walker work queue of the persistent propagation
+// kernels (gfx950).
+//
+// Before each propagation step three small kernels list the walkers as
+// segments of up to m_targ consecutive slots (one occupied bin after
+// resampling) and order the segments by the mean events per walker seen in
+// their bin during the last interval, busiest first -- longest-processing-
+// time-first scheduling, so the long walkers start early and the short ones
+// fill the tail.  The propagation kernels then take walkers from the front
+// of the queue with one atomic per request.  The order is a scheduling hint
+// only: every result depends on (seed, iteration, slot, event), never on
+// which lane or wave runs a walker.
+#include "we_common.h"
+
+// Segments per bin: one thread per (run, segment).
+__global__ __launch_bounds__(256) void queue_count_kernel(SimArgs a) {
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int32_t run = (int32_t)(gid / a.n_bins), j = (int32_t)(gid - (int64_t)run * a.n_bins);
+    if (run >= a.n_runs) return;
+    const int64_t first = (int64_t)j * a.m_targ;
+    if (first >= a.n_walk[run]) return;
+    const int32_t b = min(max(a.bin[(size_t)run * a.cap + first], 0), a.n_bins - 1);
+    atomicAdd(&a.occ_bin[b * a.seg_rep + run % a.seg_rep], 1);
+}
+
+// Bin order and queue offsets: one block.  Sorts the bins by mean events
+// per walker (descending; ties: higher bin first), lays out their segments
+// in that order, and clears the statistics and the queue.
+#define QUEUE_MAX_BINS 8192
+__global__ __launch_bounds__(1024) void queue_order_kernel(SimArgs a) {
+    __shared__ float key[QUEUE_MAX_BINS];
+    __shared__ int16_t idx[QUEUE_MAX_BINS];
+    __shared__ int32_t part[1024];
+    const int32_t NB = a.n_bins, tid = threadIdx.x, nthr = blockDim.x;
+    int32_t P = 1;
+    while (P < NB) P <<= 1;
+    for (int32_t b = tid; b < P; b += nthr) {
+        float kv = -1.0f;
+        if (b < NB) {
+            const int32_t nw = a.n_bin[b];
+            kv = nw > 0 ? a.ev_bin[b] / (float)nw : 0.0f;
+        }
+        key[b] = kv;
+        idx[b] = (int16_t)b;
+    }
+    __syncthreads();
+    // bitonic sort, descending by (key, bin)
+    for (int32_t size = 2; size <= P; size <<= 1)
+        for (int32_t d = size >> 1; d > 0; d >>= 1) {
+            for (int32_t i = tid; i < P; i += nthr) {
+                const int32_t j = i ^ d;
+                if (j > i) {
+                    const bool desc = (i & size) == 0;
+                    const float ki = key[i], kj = key[j];
+                    const int32_t bi = idx[i], bj = idx[j];
+                    const bool i_first = ki > kj || (ki == kj && bi > bj);
+                    if (i_first != desc) {
+                        key[i] = kj; key[j] = ki;
+                        idx[i] = (int16_t)bj; idx[j] = (int16_t)bi;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    // exclusive prefix of the segment counters in sorted bin order (the
+    // replicas of a bin consecutive): per-thread chunks of that sequence
+    const int32_t rep = a.seg_rep, NC = NB * rep;
+    const int32_t per = (NC + nthr - 1) / nthr;
+    const int32_t lo = min(tid * per, NC), hi = min(lo + per, NC);
+    auto counter = [&](int32_t i) { return (int32_t)idx[i / rep] * rep + i % rep; };
+    int32_t acc = 0;
+    for (int32_t i = lo; i < hi; ++i) acc += a.occ_bin[counter(i)];
+    // block-wide exclusive scan of the chunk sums: within waves, then over
+    // the wave totals
+    const int lane = tid & 63, wv = tid >> 6;
+    int32_t incl = acc;
+    for (int d = 1; d < 64; d <<= 1) {
+        const int32_t y = __shfl_up(incl, d, 64);
+        if (lane >= d) incl += y;
+    }
+    if (lane == 63) part[wv] = incl;
+    __syncthreads();
+    if (tid == 0) {
+        int32_t run = 0;
+        for (int32_t t = 0; t < nthr / 64; ++t) {
+            const int32_t v = part[t];
+            part[t] = run;
+            run += v;
+        }
+        a.queue[0] = 0u;
+        a.queue[1] = (uint32_t)run;
+    }
+    __syncthreads();
+    acc = part[wv] + incl - acc;
+    for (int32_t i = lo; i < hi; ++i) {
+        const int32_t c = counter(i);
+        a.seg_off[c] = acc;
+        acc += a.occ_bin[c];
+    }
+    __syncthreads();
+    for (int32_t c = tid; c < NC; c += nthr) {
+        a.occ_bin[c] = 0;
+        a.seg_cur[c] = 0;
+    }
+    for (int32_t b = tid; b < NB; b += nthr) {
+        a.ev_bin[b] = 0.0f;
+        a.n_bin[b] = 0;
+    }
+}
+
+// Segment list: one thread per (run, segment), same grid as the count.
+__global__ __launch_bounds__(256) void queue_fill_kernel(SimArgs a) {
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int32_t run = (int32_t)(gid / a.n_bins), j = (int32_t)(gid - (int64_t)run * a.n_bins);
+    if (run >= a.n_runs) return;
+    const int32_t n = a.n_walk[run];
+    const int64_t first = (int64_t)j * a.m_targ;
+    if (first >= n) return;
+    const size_t g = (size_t)run * a.cap + first;
+    const int32_t b = min(max(a.bin[g], 0), a.n_bins - 1);
+    const int32_t c = b * a.seg_rep + run % a.seg_rep;
+    const int32_t pos = a.seg_off[c] + atomicAdd(&a.seg_cur[c], 1);
+    a.seg[pos] = make_int2((int32_t)g, (int32_t)min((int64_t)a.m_targ, n - first));
+}
+
+hipError_t launch_work_queue(const SimArgs &a, hipStream_t st) {
+    const int64_t total = (int64_t)a.n_runs * a.n_bins;
+    const unsigned g = (unsigned)((total + 255) / 256);
+    hipLaunchKernelGGL(queue_count_kernel, dim3(g), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(queue_order_kernel, dim3(1), dim3(1024), 0, st, a);
+    hipLaunchKernelGGL(queue_fill_kernel, dim3(g), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
