@@ -326,6 +326,9 @@ def main():
                     help="only run a plain device-to-device copy of MIB MiB five times "
                          "(reference kernel for scaling the HBM byte counters)")
     ap.add_argument("--experiment", default="", choices=["", "toggle_mfpt", "batch"])
+    ap.add_argument("--large-runs", type=int, default=1,
+                    help="independent replicas of the large network (the configuration is 1; "
+                         "more fill the chip and show the wave kernel's throughput ceiling)")
     ap.add_argument("--workload", default="schlogl", choices=["schlogl", "large"],
                     help="schlogl: 2048 Schloegl replicas, lane kernel (default); large: the "
                          "354-species / 3680-reaction network, 4096 walkers, wave kernel")
@@ -368,9 +371,11 @@ def main():
     K, W = args.steps, args.warmup
     if args.workload == "large":
         cfg = wl.large_network_config(n_iters=W + K)
+        if args.large_runs > 1:
+            cfg = cfg.with_seeds(np.arange(2024, 2024 + args.large_runs, dtype=np.uint64))
         kernel, kname = we.WE_KERNEL_WAVE, "ssa_wave_lds_kernel"
         ops_ev = alg_ops_per_event_wave(cfg.net)
-        cfg_desc = {"workload": "large_network_354x3680", "runs": 1, "species": cfg.net.S,
+        cfg_desc = {"workload": "large_network_354x3680", "runs": args.large_runs, "species": cfg.net.S,
                     "reactions": cfg.net.R, "bins": cfg.n_bins, "walkers_per_bin": cfg.m_targ,
                     "tau": cfg.tau, "kernel": "ssa_wave"}
         digest_src = ["paper_1303_5986_amd/csrc/ssa_wave.hip", "paper_1303_5986_amd/csrc/ssa_wave_body.h",
@@ -408,6 +413,8 @@ def main():
     ev_per_launch = events / K
     achieved = ops_ev * ev_per_launch / ssa_avg_s
     traffic = traffic_from_profiles(tag, source_digest(digest_src))
+    if args.workload == "large" and args.large_runs != 1:
+        traffic = None   # the committed counters were taken on the one-run configuration
     cfg_desc["walkers_per_step"] = segments / K
 
     out = {
