@@ -52,22 +52,27 @@ __global__ __launch_bounds__(256) void ssa_wave_kernel(SimArgs a, int32_t *__res
     wave_walker(a, xs, run, k, *a.iter_dev, lchunk, lx);
 }
 
-// LDS-table variant: the block copies the descriptor and header tables (32
-// bytes per reaction, 118 KB at 3680 reactions) into LDS once, and its waves
-// then take walkers from the work queue until it is empty.  Per event the
-// only global-memory round trip left is the fired reaction's dependency
-// ids and changes (16-bit ids: 0.3 MB for the whole 3680-reaction network,
-// which stays in L2).
+// LDS-table variant: the block copies the descriptor table (16 bytes per
+// reaction, 59 KB at 3680 reactions) into LDS once -- and, with HDR, the
+// reaction headers too (another 16 bytes per reaction) -- and its waves then
+// take walkers from the work queue until it is empty.  Without HDR two
+// blocks of 8 walkers fit a CU instead of one, which pays when there are
+// more walkers than one block per CU can hold; with HDR the headers need no
+// global load.  Per event the remaining global traffic is the chosen chunk's
+// 64 headers (without HDR, fetched with the descriptors, in parallel) and the
+// fired reaction's dependency ids and changes (16-bit ids: 0.3 MB for the
+// whole 3680-reaction network, which stays in L2).
 #define WAVE_LDS_MAX_WAVES 8
 #define WAVE_LDS_BYTES (160 * 1024)
 
+template <bool HDR>
 __global__ __launch_bounds__(64 * WAVE_LDS_MAX_WAVES) void ssa_wave_lds_kernel(SimArgs a, int32_t *__restrict__ xs,
                                                                               int32_t s_pad) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int32_t R = a.R;
     RxnDesc *ldesc = reinterpret_cast<RxnDesc *>(smem);
     RxnInfo *linfo = reinterpret_cast<RxnInfo *>(smem + 16 * (size_t)R);
-    unsigned char *wbase = smem + 32 * (size_t)R;
+    unsigned char *wbase = smem + (HDR ? 32 : 16) * (size_t)R;
     const int nw = blockDim.x >> 6, wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     double *lchunk = reinterpret_cast<double *>(wbase) + wv * 64;
     int32_t *lx = reinterpret_cast<int32_t *>(wbase + (size_t)nw * 64 * sizeof(double)) + wv * s_pad;
@@ -77,12 +82,12 @@ __global__ __launch_bounds__(64 * WAVE_LDS_MAX_WAVES) void ssa_wave_lds_kernel(S
     uint4 *sh = reinterpret_cast<uint4 *>(linfo);
     for (int32_t i = threadIdx.x; i < R; i += blockDim.x) {
         sd[i] = gd[i];
-        sh[i] = gh[i];
+        if (HDR) sh[i] = gh[i];
     }
     __syncthreads();
     LdsTables tab;
     tab.d = ldesc;
-    tab.h = linfo;
+    tab.h = HDR ? linfo : a.rinfo;
     tab.ids = a.dep;
     const uint32_t iter = *a.iter_dev;
     const uint32_t M = (uint32_t)a.m_targ, cap = (uint32_t)a.cap;
@@ -109,13 +114,14 @@ __global__ __launch_bounds__(64 * WAVE_LDS_MAX_WAVES) void ssa_wave_lds_kernel(S
 bool wave_kernel_fits(int32_t S, int32_t R) { return R <= 4096 && S <= 8192; }
 
 namespace {
-// Blocks of the LDS variant that stay resident per CU, for a given LDS size.
+// Blocks of an LDS variant that stay resident per CU, for a given LDS size.
+template <bool HDR>
 int lds_blocks_per_cu(int waves, size_t shmem) {
     static size_t last_shmem = 0;
     static int last_waves = 0, last = 1;
     if (shmem != last_shmem || waves != last_waves) {
         int nb = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, ssa_wave_lds_kernel, 64 * waves, shmem) !=
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, ssa_wave_lds_kernel<HDR>, 64 * waves, shmem) !=
                 hipSuccess || nb < 1)
             nb = 1;
         last = nb;
@@ -135,25 +141,38 @@ int device_cus() {
     }
     return n;
 }
+
+template <bool HDR>
+hipError_t launch_lds(const SimArgs &a, int32_t *xs, int32_t s_pad, size_t tables, size_t per_wave, int64_t walkers,
+                      hipStream_t st) {
+    const int nw = (int)std::min<size_t>(WAVE_LDS_MAX_WAVES, (WAVE_LDS_BYTES - tables) / per_wave);
+    const size_t shmem = tables + nw * per_wave;
+    const int64_t resident = (int64_t)lds_blocks_per_cu<HDR>(nw, shmem) * device_cus();
+    const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>(resident, (walkers + nw - 1) / nw));
+    hipLaunchKernelGGL(ssa_wave_lds_kernel<HDR>, dim3(blocks), dim3(64 * nw), shmem, st, a, xs, s_pad);
+    return hipGetLastError();
+}
 }  // namespace
 
-// The LDS variant when its tables and at least two walkers fit in one CU's
-// LDS (it then needs the work queue built by launch_work_queue), else
-// one wave per slot with tables in global memory.
+// The LDS variants when the descriptors and at least two walkers fit in one
+// CU's LDS (they then need the work queue built by launch_work_queue), else
+// one wave per slot with tables in global memory.  Headers go to LDS too
+// when they fit and the run's slots would fill at most two rounds of one
+// such block per CU (WE keeps roughly half its slots live); beyond that the
+// second block per CU is worth more than the header loads it saves.
 hipError_t launch_ssa_wave(const SimArgs &a, int32_t *xs, hipStream_t st) {
     if (!wave_kernel_fits(a.S, a.R)) return hipErrorInvalidValue;
     const int32_t s_pad = (a.S + 3) & ~3;
     const size_t per_wave = 64 * sizeof(double) + sizeof(int32_t) * (size_t)s_pad;
-    const size_t tables = 32 * (size_t)a.R;
     const int64_t walkers = (int64_t)a.n_runs * a.cap;
-    if (tables + 2 * per_wave <= WAVE_LDS_BYTES) {
-        const int nw = (int)std::min<size_t>(WAVE_LDS_MAX_WAVES, (WAVE_LDS_BYTES - tables) / per_wave);
-        const size_t shmem = tables + nw * per_wave;
-        const int64_t resident = (int64_t)lds_blocks_per_cu(nw, shmem) * device_cus();
-        const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>(resident, (walkers + nw - 1) / nw));
-        hipLaunchKernelGGL(ssa_wave_lds_kernel, dim3(blocks), dim3(64 * nw), shmem, st, a, xs, s_pad);
-        return hipGetLastError();
+    const size_t desc_bytes = 16 * (size_t)a.R;
+    if (2 * desc_bytes + 2 * per_wave <= WAVE_LDS_BYTES) {
+        const int nw = (int)std::min<size_t>(WAVE_LDS_MAX_WAVES, (WAVE_LDS_BYTES - 2 * desc_bytes) / per_wave);
+        if (walkers <= 2 * (int64_t)nw * device_cus())
+            return launch_lds<true>(a, xs, s_pad, 2 * desc_bytes, per_wave, walkers, st);
     }
+    if (desc_bytes + 2 * per_wave <= WAVE_LDS_BYTES)
+        return launch_lds<false>(a, xs, s_pad, desc_bytes, per_wave, walkers, st);
     const size_t shmem = WAVE_WALKERS_PER_BLOCK * per_wave;
     const unsigned blocks = (unsigned)((walkers + WAVE_WALKERS_PER_BLOCK - 1) / WAVE_WALKERS_PER_BLOCK);
     hipLaunchKernelGGL(ssa_wave_kernel, dim3(blocks), dim3(64 * WAVE_WALKERS_PER_BLOCK), shmem, st, a,

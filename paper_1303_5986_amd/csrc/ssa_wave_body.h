@@ -93,9 +93,9 @@ __device__ __forceinline__ void add_chunk_deltas(double *lchunk, int rr, double 
 // Where the wave reads the network from.
 //  GlobalTables: descriptors, reaction headers and dependency entries (each
 //    with its reaction's descriptor inline) from global memory;
-//  LdsTables: descriptors and headers from the block's LDS copy; the
-//    dependency lists as 16-bit reaction ids from global memory, their
-//    descriptors from LDS.
+//  LdsTables: descriptors from the block's LDS copy, headers from LDS or
+//    global memory, the dependency lists (16-bit reaction ids) from global
+//    memory and the dependents' descriptors from LDS.
 struct GlobalTables {
     const RxnDesc *__restrict__ d;
     const RxnInfo *__restrict__ h;
@@ -107,7 +107,7 @@ struct GlobalTables {
 
 struct LdsTables {
     const RxnDesc *d;                  // LDS
-    const RxnInfo *h;                  // LDS
+    const RxnInfo *h;                  // LDS or global
     const uint16_t *__restrict__ ids;  // global
     __device__ __forceinline__ RxnDesc desc(int r) const { return d[r]; }
     __device__ __forceinline__ RxnInfo info(int j) const { return h[j]; }
@@ -179,10 +179,15 @@ __device__ inline void wave_walker_t(const SimArgs &a, const T &tab, int32_t *__
         cs = __builtin_amdgcn_readfirstlane(cs);
         const double base = lane_value(P - csum, cs);
         const double target2 = target - base;
-        // reaction inside the chunk
+        // reaction inside the chunk; each lane also fetches its reaction's
+        // header, so the chosen one is a readlane away once j is known
         const int rsel = cs * 64 + lane;
         double v = 0.0;
-        if (rsel < R) v = prop_lds(tab.desc(rsel), lx);
+        RxnInfo hinfo{0, 0, 0, 0};
+        if (rsel < R) {
+            hinfo = tab.info(rsel);
+            v = prop_lds(tab.desc(rsel), lx);
+        }
         const double Q = scan_incl(v);
         const unsigned long long m2 = __ballot(Q > target2);
         const int ls = m2 ? (__ffsll((long long)m2) - 1) : last_set(__ballot(v > 0.0));
@@ -190,10 +195,12 @@ __device__ inline void wave_walker_t(const SimArgs &a, const T &tab, int32_t *__
             if (lane == 0) atomicOr(a.err, WE_DERR_SELECT);
             break;
         }
-        const int j = __builtin_amdgcn_readfirstlane(cs * 64 + ls);
-
         // header of j; its dependents (with descriptors) and changes
-        const RxnInfo info = tab.info(j);
+        RxnInfo info;
+        info.dep_begin = __builtin_amdgcn_readlane(hinfo.dep_begin, ls);
+        info.dep_count = __builtin_amdgcn_readlane(hinfo.dep_count, ls);
+        info.chg_begin = __builtin_amdgcn_readlane(hinfo.chg_begin, ls);
+        info.chg_count = __builtin_amdgcn_readlane(hinfo.chg_count, ls);
         const int32_t nd = info.dep_count;
         const int nround = (nd + 63) >> 6;
         int32_t pc = 0;
