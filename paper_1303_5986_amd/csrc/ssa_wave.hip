@@ -25,10 +25,10 @@
 //    interval.
 //
 // Memory: walker counts (int32) and chunk sums live in LDS (about 2 KB per
-// walker at 354 species).  When they fit, the block also keeps the reaction
-// descriptors and headers in LDS (ssa_wave_lds_kernel); dependency lists and
-// stoichiometry are read from global memory, where they stay resident in
-// the L2 caches.  No per-reaction propensity array is stored.
+// walker at 354 species); the block also keeps the reaction descriptors (and,
+// when they fit, the headers) in LDS; dependency lists and stoichiometry are
+// read from global memory, where they stay resident in the L2 caches.  No
+// per-reaction propensity array is stored.
 //
 // Summation order differs from the sequential order of the oracle (chunked
 // scans), so a0 and the running sums can differ in the last bits; an event
@@ -36,21 +36,6 @@
 #include "ssa_wave_body.h"
 
 #include <algorithm>
-
-__global__ __launch_bounds__(256) void ssa_wave_kernel(SimArgs a, int32_t *__restrict__ xs,
-                                                       int32_t s_pad) {
-    extern __shared__ __align__(16) unsigned char smem[];
-    const int wv = threadIdx.x >> 6;
-    double *lchunk = reinterpret_cast<double *>(smem) + wv * 64;
-    int32_t *lx = reinterpret_cast<int32_t *>(smem + WAVE_WALKERS_PER_BLOCK * 64 * sizeof(double)) +
-                  wv * s_pad;
-    const int64_t gw = (int64_t)blockIdx.x * WAVE_WALKERS_PER_BLOCK + wv;
-    const int32_t run = (int32_t)(gw / a.cap);
-    const int32_t k = (int32_t)(gw - (int64_t)run * a.cap);
-    if (run >= a.n_runs) return;
-    if (k >= a.n_walk[run]) return;
-    wave_walker(a, xs, run, k, *a.iter_dev, lchunk, lx);
-}
 
 // LDS-table variant: the block copies the descriptor table (16 bytes per
 // reaction, 59 KB at 3680 reactions) into LDS once -- and, with HDR, the
@@ -154,12 +139,13 @@ hipError_t launch_lds(const SimArgs &a, int32_t *xs, int32_t s_pad, size_t table
 }
 }  // namespace
 
-// The LDS variants when the descriptors and at least two walkers fit in one
-// CU's LDS (they then need the work queue built by launch_work_queue), else
-// one wave per slot with tables in global memory.  Headers go to LDS too
-// when they fit and the run's slots would fill at most two rounds of one
-// such block per CU (WE keeps roughly half its slots live); beyond that the
-// second block per CU is worth more than the header loads it saves.
+// The LDS variants need the work queue built by launch_work_queue.  The
+// descriptors (16 B per reaction) and two walkers always fit one CU's LDS
+// within wave_kernel_fits (R <= 4096, S <= 8192: at most 64 KB + 2 x 33 KB).
+// Headers go to LDS too when they fit and the run's slots would fill at most
+// two rounds of one such block per CU (WE keeps roughly half its slots live);
+// beyond that the second block per CU is worth more than the header loads it
+// saves.
 hipError_t launch_ssa_wave(const SimArgs &a, int32_t *xs, hipStream_t st) {
     if (!wave_kernel_fits(a.S, a.R)) return hipErrorInvalidValue;
     const int32_t s_pad = (a.S + 3) & ~3;
@@ -171,11 +157,5 @@ hipError_t launch_ssa_wave(const SimArgs &a, int32_t *xs, hipStream_t st) {
         if (walkers <= 2 * (int64_t)nw * device_cus())
             return launch_lds<true>(a, xs, s_pad, 2 * desc_bytes, per_wave, walkers, st);
     }
-    if (desc_bytes + 2 * per_wave <= WAVE_LDS_BYTES)
-        return launch_lds<false>(a, xs, s_pad, desc_bytes, per_wave, walkers, st);
-    const size_t shmem = WAVE_WALKERS_PER_BLOCK * per_wave;
-    const unsigned blocks = (unsigned)((walkers + WAVE_WALKERS_PER_BLOCK - 1) / WAVE_WALKERS_PER_BLOCK);
-    hipLaunchKernelGGL(ssa_wave_kernel, dim3(blocks), dim3(64 * WAVE_WALKERS_PER_BLOCK), shmem, st, a,
-                       xs, s_pad);
-    return hipGetLastError();
+    return launch_lds<false>(a, xs, s_pad, desc_bytes, per_wave, walkers, st);
 }
