@@ -38,6 +38,15 @@
 #include "we_common.h"
 
 #define RESAMPLE_LDS_CAP 8192
+// Threads per run: up to 16 waves, so up to 16 bins are split/merged at
+// once.  With many runs the grid fills the chip anyway and smaller blocks
+// cost less to start, so launches with at least RESAMPLE_MANY_RUNS blocks use
+// 4 waves per run.
+#define RESAMPLE_THREADS 1024
+#define RESAMPLE_MANY_RUNS 512
+__host__ inline unsigned resample_threads(int64_t blocks) {
+    return blocks >= RESAMPLE_MANY_RUNS ? 256u : (unsigned)RESAMPLE_THREADS;
+}
 
 // sum_s coef_s x_s in ascending species order over the nonzero
 // coefficients only: a zero coefficient adds +0 or -0, which leaves a sum
@@ -383,7 +392,7 @@ __device__ void resample_run_t(const SimArgs &a, const double *__restrict__ w_cu
     const int32_t tid = threadIdx.x, nthr = blockDim.x;
     const int lane = tid & 63, wave = tid >> 6, n_waves = nthr >> 6;
     const int32_t NB = a.n_bins, M = a.m_targ, cap = a.cap;
-    __shared__ int64_t ev_part[256];
+    __shared__ int64_t ev_part[RESAMPLE_THREADS];
     int32_t *cnt = reinterpret_cast<int32_t *>(lds);   // [NB]
     int32_t *start = cnt + NB;                          // [NB+1]
     int32_t *ostart = start + NB + 1;                   // [NB+1]
@@ -548,7 +557,7 @@ __device__ __forceinline__ void resample_run(const SimArgs &a, const double *__r
     else resample_run_t<int32_t>(a, w_cur, w_nxt, 0, run, lds);
 }
 
-__global__ __launch_bounds__(256) void we_resample_kernel(SimArgs a, const double *__restrict__ w_cur,
+__global__ __launch_bounds__(RESAMPLE_THREADS) void we_resample_kernel(SimArgs a, const double *__restrict__ w_cur,
                                                           double *__restrict__ w_nxt, int32_t use_lds) {
     extern __shared__ __align__(16) unsigned char lds[];
     resample_run(a, w_cur, w_nxt, use_lds, blockIdx.x, lds);
@@ -622,7 +631,7 @@ __global__ __launch_bounds__(256) void we_batch_recycle_bin_kernel(BatchPtrs b) 
     recycle_bin_one(b.args[i], b.x_cur[i], b.grid_bins[i], (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
-__global__ __launch_bounds__(256) void we_batch_resample_kernel(BatchPtrs b) {
+__global__ __launch_bounds__(RESAMPLE_THREADS) void we_batch_resample_kernel(BatchPtrs b) {
     extern __shared__ __align__(16) unsigned char lds[];
     const int32_t i = blockIdx.y;
     const SimArgs &a = b.args[i];
@@ -651,7 +660,8 @@ hipError_t launch_batch_bookkeeping(const BatchPtrs &b, int32_t n_sims, int64_t 
                                     int64_t max_cells, size_t shmem, bool observe, hipStream_t st) {
     const unsigned gs = (unsigned)((max_slots + 255) / 256);
     hipLaunchKernelGGL(we_batch_recycle_bin_kernel, dim3(gs, n_sims), dim3(256), 0, st, b);
-    hipLaunchKernelGGL(we_batch_resample_kernel, dim3(max_runs, n_sims), dim3(256), shmem, st, b);
+    hipLaunchKernelGGL(we_batch_resample_kernel, dim3(max_runs, n_sims),
+                       dim3(resample_threads((int64_t)max_runs * n_sims)), shmem, st, b);
     hipLaunchKernelGGL(we_batch_gather_kernel, dim3((unsigned)((max_cells + 255) / 256), n_sims), dim3(256), 0, st, b);
     if (observe) hipLaunchKernelGGL(we_batch_observe_kernel, dim3(gs, n_sims), dim3(256), 0, st, b);
     hipLaunchKernelGGL(we_batch_advance_kernel, dim3((n_sims + 63) / 64), dim3(64), 0, st, b, n_sims);
@@ -680,7 +690,7 @@ hipError_t launch_resample(const SimArgs &a, int32_t *x_cur, const double *w_cur
                            double *w_nxt, hipStream_t st) {
     const bool use_lds = resample_uses_lds(a);
     const size_t shmem = resample_lds_bytes(a, use_lds);
-    hipLaunchKernelGGL(we_resample_kernel, dim3(a.n_runs), dim3(256), shmem, st, a, w_cur, w_nxt,
+    hipLaunchKernelGGL(we_resample_kernel, dim3(a.n_runs), dim3(resample_threads(a.n_runs)), shmem, st, a, w_cur, w_nxt,
                        use_lds ? 1 : 0);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
