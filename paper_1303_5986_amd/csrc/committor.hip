@@ -21,9 +21,9 @@
 //     a fixed order per species;
 //  5. model: n_in -> 64 -> 64 -> 1, tanh, tanh, sigmoid, FP32; loss: binary
 //     cross-entropy with the soft label; Adam (beta 0.9/0.999, eps 1e-8).
-//     Forward/backward is one lane per sample; each parameter's gradient is
-//     summed over the minibatch by one lane in sample order, so a training
-//     run is reproducible;
+//     Forward/backward is one wave per sample; each parameter's gradient is
+//     summed over the minibatch by one wave in a fixed order (lane-strided
+//     partial sums, then a butterfly), so a training run is reproducible;
 //  6. bins: n_bins equal-count quantile edges over the dataset, taken on
 //     the logit z = log(q/(1-q)) (quantiles do not change under a monotone
 //     map, and the logit resolves the q ~ 1e-10 values near A that FP32 q
@@ -81,6 +81,13 @@ __device__ float mlp_z(const ParamView &P, const float *feat, const int32_t *xr,
         z3 = fmaf(P.W3[i], tanhf(z), z3);
     }
     return z3;
+}
+
+// Orders the LDS accesses of the lanes of one wave.
+__device__ __forceinline__ void cm_wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // Quantile histogram cell of a logit: 65536 cells over [-Z_SPAN, Z_SPAN].
@@ -266,8 +273,12 @@ struct Scratch {
     float *phi, *h1, *h2, *g1, *g2, *g3, *loss;   // [feature][B] layout
 };
 
-// Forward and backward of one sample per lane; the sample is either drawn
-// from the dataset with Philox (counter (b, step, 1, 2)) or given directly.
+// Forward and backward of one sample per wave, one hidden unit per lane;
+// the sample is either drawn from the dataset with Philox (counter
+// (b, step, 1, 2)) or given directly.  Every dot product runs over its inputs
+// in ascending order, on the lane that owns the output.
+inline size_t cm_fwd_bwd_lds(int32_t n_in) { return 4 * sizeof(float) * ((size_t)n_in + 3 * CM_H); }
+
 __global__ __launch_bounds__(256) void cm_fwd_bwd_kernel(const float *__restrict__ params, const float *__restrict__ feat,
                                                          int32_t n_in, int32_t B, int32_t step,
                                                          uint32_t k0, uint32_t k1, int32_t n_ds,
@@ -276,8 +287,12 @@ __global__ __launch_bounds__(256) void cm_fwd_bwd_kernel(const float *__restrict
                                                          const int32_t *__restrict__ rx,
                                                          const int32_t *__restrict__ direct_x,
                                                          const float *__restrict__ direct_y, Scratch sc) {
-    const int32_t b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= B) return;
+    extern __shared__ float cm_lds[];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int32_t b = (int32_t)blockIdx.x * 4 + wv;
+    if (b >= B) return;   // uniform over the wave
+    float *lphi = cm_lds + (size_t)wv * (n_in + 3 * CM_H);
+    float *lh1 = lphi + n_in, *lh2 = lh1 + CM_H, *lg2 = lh2 + CM_H;
     const ParamView P = cm_view(params, n_in);
     const int32_t *xr;
     float y;
@@ -291,73 +306,70 @@ __global__ __launch_bounds__(256) void cm_fwd_bwd_kernel(const float *__restrict
         xr = rx + ds_idx[pick] * n_in;
         y = ds_y[pick];
     }
-    float h1[CM_H];
-#pragma unroll
-    for (int j = 0; j < CM_H; ++j) h1[j] = P.b1[j];
-    for (int k = 0; k < n_in; ++k) {
+    for (int32_t k = lane; k < n_in; k += 64) {
         const float f = feature(xr[k], feat, k, n_in);
+        lphi[k] = f;
         sc.phi[(size_t)k * B + b] = f;
-#pragma unroll
-        for (int j = 0; j < CM_H; ++j) h1[j] = fmaf(P.W1[j * n_in + k], f, h1[j]);
     }
-#pragma unroll
-    for (int j = 0; j < CM_H; ++j) {
-        h1[j] = tanhf(h1[j]);
-        sc.h1[(size_t)j * B + b] = h1[j];
-    }
+    cm_wave_sync();
+    const int j = lane;   // this lane's hidden unit in both layers
+    float z1 = P.b1[j];
+    for (int32_t k = 0; k < n_in; ++k) z1 = fmaf(P.W1[j * n_in + k], lphi[k], z1);
+    const float h1 = tanhf(z1);
+    lh1[j] = h1;
+    sc.h1[(size_t)j * B + b] = h1;
+    cm_wave_sync();
+    float z2 = P.b2[j];
+    for (int i = 0; i < CM_H; ++i) z2 = fmaf(P.W2[j * CM_H + i], lh1[i], z2);
+    const float h2 = tanhf(z2);
+    lh2[j] = h2;
+    sc.h2[(size_t)j * B + b] = h2;
+    cm_wave_sync();
     float z3 = P.b3[0];
-    for (int i = 0; i < CM_H; ++i) {
-        float z = P.b2[i];
-#pragma unroll
-        for (int j = 0; j < CM_H; ++j) z = fmaf(P.W2[i * CM_H + j], h1[j], z);
-        const float h2 = tanhf(z);
-        sc.h2[(size_t)i * B + b] = h2;
-        z3 = fmaf(P.W3[i], h2, z3);
-    }
+    for (int i = 0; i < CM_H; ++i) z3 = fmaf(P.W3[i], lh2[i], z3);
     const float q = 1.0f / (1.0f + expf(-z3));
-    // binary cross-entropy with a soft label, in the stable form
-    sc.loss[b] = fmaxf(z3, 0.0f) - z3 * y + log1pf(expf(-fabsf(z3)));
     const float g3 = (q - y) / (float)B;
-    sc.g3[b] = g3;
-    float acc[CM_H];
-#pragma unroll
-    for (int j = 0; j < CM_H; ++j) acc[j] = 0.0f;
-    for (int i = 0; i < CM_H; ++i) {
-        const float h2 = sc.h2[(size_t)i * B + b];
-        const float g2 = g3 * P.W3[i] * (1.0f - h2 * h2);
-        sc.g2[(size_t)i * B + b] = g2;
-#pragma unroll
-        for (int j = 0; j < CM_H; ++j) acc[j] = fmaf(P.W2[i * CM_H + j], g2, acc[j]);
+    if (lane == 0) {
+        // binary cross-entropy with a soft label, in the stable form
+        sc.loss[b] = fmaxf(z3, 0.0f) - z3 * y + log1pf(expf(-fabsf(z3)));
+        sc.g3[b] = g3;
     }
-#pragma unroll
-    for (int j = 0; j < CM_H; ++j) sc.g1[(size_t)j * B + b] = acc[j] * (1.0f - h1[j] * h1[j]);
+    const float g2 = g3 * P.W3[j] * (1.0f - h2 * h2);
+    lg2[j] = g2;
+    sc.g2[(size_t)j * B + b] = g2;
+    cm_wave_sync();
+    float acc = 0.0f;
+    for (int i = 0; i < CM_H; ++i) acc = fmaf(P.W2[i * CM_H + j], lg2[i], acc);
+    sc.g1[(size_t)j * B + b] = acc * (1.0f - h1 * h1);
 }
 
-// One lane per parameter: its gradient summed over the minibatch in sample order.
+// One wave per parameter (and one for the mean loss): lane l sums samples
+// l, l+64, l+128, ... in that order, then a fixed butterfly adds the 64 lane
+// sums -- coalesced loads, and the same order on every run.
 __global__ __launch_bounds__(256) void cm_grad_kernel(int32_t n_in, int32_t B, Scratch sc, float *__restrict__ grad,
                                                       float *__restrict__ loss_out) {
-    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int32_t i = (int32_t)blockIdx.x * 4 + (int32_t)(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
     const int32_t np = cm_n_params(n_in);
-    if (i == np && loss_out) {
-        float l = 0.0f;
-        for (int32_t b = 0; b < B; ++b) l += sc.loss[b];
-        *loss_out = l / (float)B;
-        return;
-    }
-    if (i >= np) return;
+    if (i > np || (i == np && !loss_out)) return;   // uniform over the wave
     const int32_t nW1 = CM_H * n_in, nW2 = CM_H * CM_H;
     const int32_t b1 = nW1, w2 = b1 + CM_H, b2 = w2 + nW2, w3 = b2 + CM_H, b3 = w3 + CM_H;
     const float *u, *v = nullptr;
-    if (i < b1) { u = sc.g1 + (size_t)(i / n_in) * B; v = sc.phi + (size_t)(i % n_in) * B; }
+    if (i == np) { u = sc.loss; }
+    else if (i < b1) { u = sc.g1 + (size_t)(i / n_in) * B; v = sc.phi + (size_t)(i % n_in) * B; }
     else if (i < w2) { u = sc.g1 + (size_t)(i - b1) * B; }
     else if (i < b2) { const int32_t r = i - w2; u = sc.g2 + (size_t)(r / CM_H) * B; v = sc.h1 + (size_t)(r % CM_H) * B; }
     else if (i < w3) { u = sc.g2 + (size_t)(i - b2) * B; }
     else if (i < b3) { u = sc.g3; v = sc.h2 + (size_t)(i - w3) * B; }
     else { u = sc.g3; }
     float acc = 0.0f;
-    if (v) for (int32_t b = 0; b < B; ++b) acc = fmaf(u[b], v[b], acc);
-    else for (int32_t b = 0; b < B; ++b) acc += u[b];
-    grad[i] = acc;
+    if (v) for (int32_t b = lane; b < B; b += 64) acc = fmaf(u[b], v[b], acc);
+    else for (int32_t b = lane; b < B; b += 64) acc += u[b];
+    for (int d = 32; d > 0; d >>= 1) acc += __shfl_xor(acc, d, 64);
+    if (lane == 0) {
+        if (i == np) *loss_out = acc / (float)B;
+        else grad[i] = acc;
+    }
 }
 
 __global__ void cm_adam_kernel(int32_t np, float *__restrict__ p, float *__restrict__ m, float *__restrict__ v,
@@ -427,24 +439,69 @@ __global__ void cm_edges_kernel(const uint32_t *__restrict__ qhist, int32_t n, i
     edges[nb] = edges[nb - 1] + (double)Z_SPAN;
 }
 
+// W1 and W2 transposed, so the lanes of a wave (one hidden unit each) read
+// consecutive words: wt[k*64 + j] = W1[j][k], wt[64*n_in + i*64 + j] = W2[j][i].
+__global__ void cm_transpose_kernel(const float *__restrict__ params, int32_t n_in, float *__restrict__ wt) {
+    const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int32_t n1 = CM_H * n_in;
+    const ParamView P = cm_view(params, n_in);
+    if (t < n1) {
+        const int32_t k = t / CM_H, j = t % CM_H;
+        wt[t] = P.W1[j * n_in + k];
+    } else if (t < n1 + CM_H * CM_H) {
+        const int32_t u = t - n1, i = u / CM_H, j = u % CM_H;
+        wt[t] = P.W2[j * CM_H + i];
+    }
+}
+
+// The same z as mlp_z (every dot product over the same terms in the same
+// order, on the lane that owns its output), one walker per wave, one hidden
+// unit per lane; wt is cm_transpose_kernel's output; lphi/lh1/lh2 are the
+// wave's LDS slices (n_in, 64, 64 floats).
+__device__ float mlp_z_wave(const ParamView &P, const float *__restrict__ wt, const float *feat, const int32_t *xr,
+                            int32_t n_in, float *lphi, float *lh1, float *lh2) {
+    const int lane = threadIdx.x & 63;
+    const float *W1t = wt, *W2t = wt + CM_H * n_in;
+    for (int32_t k = lane; k < n_in; k += 64) lphi[k] = feature(xr[k], feat, k, n_in);
+    cm_wave_sync();
+    float z1 = P.b1[lane];
+    for (int32_t k = 0; k < n_in; ++k) z1 = fmaf(W1t[k * CM_H + lane], lphi[k], z1);
+    lh1[lane] = tanhf(z1);
+    cm_wave_sync();
+    float z2 = P.b2[lane];
+    for (int j = 0; j < CM_H; ++j) z2 = fmaf(W2t[j * CM_H + lane], lh1[j], z2);
+    lh2[lane] = tanhf(z2);
+    cm_wave_sync();
+    float z3 = P.b3[0];
+    for (int i = 0; i < CM_H; ++i) z3 = fmaf(P.W3[i], lh2[i], z3);
+    cm_wave_sync();
+    return z3;
+}
+
+// Learned bins after recycling: one wave per walker slot.
 __global__ __launch_bounds__(256) void cm_bin_kernel(SimArgs a, const int32_t *__restrict__ x_cur,
-                                                     const float *__restrict__ params, const float *__restrict__ feat,
+                                                     const float *__restrict__ params, const float *__restrict__ wt,
+                                                     const float *__restrict__ feat,
                                                      const double *__restrict__ qedges) {
-    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    extern __shared__ float cm_lds[];
+    const int wv = threadIdx.x >> 6;
+    const int64_t gid = (int64_t)blockIdx.x * 4 + wv;
     const int32_t run = (int32_t)(gid / a.cap);
     const int32_t k = (int32_t)(gid - (int64_t)run * a.cap);
-    if (run >= a.n_runs) return;
+    if (run >= a.n_runs) return;          // uniform over the wave
     if (k >= a.n_walk[run]) return;
     const size_t idx = (size_t)run * a.cap + k;
+    float *lphi = cm_lds + (size_t)wv * (a.S + 2 * CM_H);
     const ParamView P = cm_view(params, a.S);
-    const float z = mlp_z(P, feat, x_cur + idx * a.S, a.S);
-    a.s_bin[idx] = bin_index(qedges, a.n_bins, (double)z);
+    const float z = mlp_z_wave(P, wt, feat, x_cur + idx * a.S, a.S, lphi, lphi + a.S, lphi + a.S + CM_H);
+    if ((threadIdx.x & 63) == 0) a.s_bin[idx] = bin_index(qedges, a.n_bins, (double)z);
 }
 
 hipError_t committor_bin(we_sim *s, int32_t *x_cur, hipStream_t st) {
     const int64_t total = (int64_t)s->n_runs * s->cap;
-    hipLaunchKernelGGL(cm_bin_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, s->args, x_cur,
-                       s->cm.d_params, s->cm.d_feat, s->cm.d_qedges);
+    const size_t lds = 4 * sizeof(float) * ((size_t)s->S + 2 * CM_H);
+    hipLaunchKernelGGL(cm_bin_kernel, dim3((unsigned)((total + 3) / 4)), dim3(256), lds, st, s->args, x_cur,
+                       s->cm.d_params, s->cm.d_wt, s->cm.d_feat, s->cm.d_qedges);
     return hipGetLastError();
 }
 
@@ -456,6 +513,7 @@ void committor_free(we_sim *s) {
     (void)hipFree(c.d_grad);
     (void)hipFree(c.d_feat);
     (void)hipFree(c.d_qedges);
+    (void)hipFree(c.d_wt);
     c = Committor();
 }
 
@@ -585,6 +643,7 @@ extern "C" we_status we_train_committor(we_sim *s, const we_train_params *tp, fl
     HIP_TRY(hipMalloc(&C.d_grad, pb));
     HIP_TRY(hipMalloc(&C.d_feat, 8ull * n_in));
     HIP_TRY(hipMalloc(&C.d_qedges, 8ull * (C.n_qbins + 1)));
+    HIP_TRY(hipMalloc(&C.d_wt, 4ull * (CM_H * n_in + CM_H * CM_H)));
     HIP_TRY(hipMemsetAsync(C.d_adam_m, 0, pb, s->stream));
     HIP_TRY(hipMemsetAsync(C.d_adam_v, 0, pb, s->stream));
     const uint32_t k0 = (uint32_t)tp->seed, k1 = (uint32_t)(tp->seed >> 32);
@@ -601,17 +660,22 @@ extern "C" we_status we_train_committor(we_sim *s, const we_train_params *tp, fl
     DevBuf dloss;
     HIP_TRY(dloss.alloc(4ull * std::max(tp->steps, 1)));
     for (int32_t step = 0; step < tp->steps; ++step) {
-        hipLaunchKernelGGL(cm_fwd_bwd_kernel, dim3(B / 256), dim3(256), 0, s->stream, C.d_params, C.d_feat, n_in, B,
+        hipLaunchKernelGGL(cm_fwd_bwd_kernel, dim3((B + 3) / 4), dim3(256), cm_fwd_bwd_lds(n_in), s->stream,
+                           C.d_params, C.d_feat, n_in, B,
                            step, k0, k1, n_ds, ds_idx.as<int64_t>(), ds_y.as<float>(), R.d_x,
                            (const int32_t *)nullptr, (const float *)nullptr, sb.view());
         HIP_TRY(hipGetLastError());
-        hipLaunchKernelGGL(cm_grad_kernel, dim3((C.n_params + 1 + 255) / 256), dim3(256), 0, s->stream, n_in, B,
+        hipLaunchKernelGGL(cm_grad_kernel, dim3((C.n_params + 1 + 3) / 4), dim3(256), 0, s->stream, n_in, B,
                            sb.view(), C.d_grad, dloss.as<float>() + step);
         HIP_TRY(hipGetLastError());
         hipLaunchKernelGGL(cm_adam_kernel, dim3((C.n_params + 255) / 256), dim3(256), 0, s->stream, C.n_params,
                            C.d_params, C.d_adam_m, C.d_adam_v, C.d_grad, tp->lr, step + 1);
         HIP_TRY(hipGetLastError());
     }
+
+    const int32_t nt = CM_H * n_in + CM_H * CM_H;
+    hipLaunchKernelGGL(cm_transpose_kernel, dim3((nt + 255) / 256), dim3(256), 0, s->stream, C.d_params, n_in, C.d_wt);
+    HIP_TRY(hipGetLastError());
 
     // equal-count quantile edges of q over the dataset
     DevBuf qhist;
@@ -683,11 +747,11 @@ extern "C" we_status we_mlp_loss_grad(int32_t n_in, const float *params, const f
     HIP_TRY(hipMemcpy(dy.p, y, 4ull * batch, hipMemcpyHostToDevice));
     ScratchBufs sb;
     HIP_TRY(sb.alloc(n_in, batch));
-    hipLaunchKernelGGL(cm_fwd_bwd_kernel, dim3((batch + 255) / 256), dim3(256), 0, nullptr, dp.as<float>(),
+    hipLaunchKernelGGL(cm_fwd_bwd_kernel, dim3((batch + 3) / 4), dim3(256), cm_fwd_bwd_lds(n_in), nullptr, dp.as<float>(),
                        df.as<float>(), n_in, batch, 0, 0u, 0u, 0, (const int64_t *)nullptr, (const float *)nullptr,
                        (const int32_t *)nullptr, dx.as<int32_t>(), dy.as<float>(), sb.view());
     HIP_TRY(hipGetLastError());
-    hipLaunchKernelGGL(cm_grad_kernel, dim3((np + 1 + 255) / 256), dim3(256), 0, nullptr, n_in, batch, sb.view(),
+    hipLaunchKernelGGL(cm_grad_kernel, dim3((np + 1 + 3) / 4), dim3(256), 0, nullptr, n_in, batch, sb.view(),
                        dg.as<float>(), dl.as<float>());
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipDeviceSynchronize());

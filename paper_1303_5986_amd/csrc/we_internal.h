@@ -45,6 +45,7 @@ struct Committor {
     float *d_adam_m = nullptr, *d_adam_v = nullptr, *d_grad = nullptr;
     float *d_feat = nullptr;        // [2*n_in] mean, 1/std of log1p(x)
     double *d_qedges = nullptr;     // [n_qbins+1]
+    float *d_wt = nullptr;          // W1 and W2 transposed ([n_in][64], [64][64]) for inference
     int32_t n_qbins = 0;
 };
 
