@@ -117,6 +117,7 @@ hipError_t launch_batch_bookkeeping(const BatchPtrs &b, int32_t n_sims, int64_t 
                                     int64_t max_cells, size_t shmem, bool observe, hipStream_t st);
 bool resample_uses_lds(const SimArgs &a);
 size_t resample_lds_bytes(const SimArgs &a, bool use_lds);
+int32_t resample_place_rows(const SimArgs &a, int64_t blocks);
 
 struct we_batch {
     hipStream_t stream = nullptr;
@@ -328,9 +329,13 @@ extern "C" we_status we_batch_create(int32_t n, const we_network *const *nets, c
     std::vector<int32_t *> xp0, xp1;
     std::vector<double *> wp0, wp1;
     std::vector<int32_t> use_lds, grid_bins;
+    int32_t runs_hi = 0;
+    for (we_sim *s : b->sims) runs_hi = std::max(runs_hi, s->n_runs);
     for (we_sim *s : b->sims) {
         args.push_back(s->args);
         args.back().queue_stats = 0;   // the batched kernels keep their own work queue
+        // cursor rows for the batched launch's block size
+        args.back().place_rows = resample_place_rows(s->args, (int64_t)runs_hi * (int64_t)b->sims.size());
         xp0.push_back(s->x[0]);
         xp1.push_back(s->x[1]);
         wp0.push_back(s->w[0]);
@@ -338,7 +343,7 @@ extern "C" we_status we_batch_create(int32_t n, const we_network *const *nets, c
         const bool ul = resample_uses_lds(s->args);
         use_lds.push_back(ul ? 1 : 0);
         grid_bins.push_back(1);
-        b->resample_shmem = std::max(b->resample_shmem, resample_lds_bytes(s->args, ul));
+        b->resample_shmem = std::max(b->resample_shmem, resample_lds_bytes(args.back(), ul));
         b->max_slots = std::max<int64_t>(b->max_slots, (int64_t)s->n_runs * s->cap);
         b->max_cells = std::max<int64_t>(b->max_cells, (int64_t)s->n_runs * s->cap * s->S);
         b->max_runs = std::max(b->max_runs, s->n_runs);

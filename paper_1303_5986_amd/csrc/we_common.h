@@ -106,6 +106,8 @@ struct SimArgs {
     // work queue of the propagation kernels: segments of up to m_targ
     // consecutive walkers, ordered by the mean events per walker of their bin
     int32_t queue_stats;                 // 1: resampling gathers the per-bin event statistics
+    int32_t place_rows;                  // resampling: rows of per-bin cursors in LDS, one per
+                                         //   wave that places walkers (at least 1)
     float *ev_bin;                       // [n_bins] events of the walkers that ended in each bin
     int32_t *n_bin;                      // [n_bins] walkers that ended in each bin
     int32_t seg_rep;                     // counters per bin (spread over replicas, picked by run,

@@ -10,6 +10,8 @@
 //      bin of every walker on the progress coordinate (or, with learned
 //      bins, the bin is written afterwards by the committor kernel);
 //   resample (one workgroup per run)
+//      stable placement of the walkers by bin: per-wave cursor rows let
+//      several waves place their own runs of slots at once;
 //      the run's recycled weight (summed in slot order) and reactions fired;
 //      per-bin split/merge (Sec. II.B), one wave per bin:
 //        n == M: unchanged;
@@ -20,12 +22,14 @@
 //                wave finds the largest share with DPP max steps;
 //        n >  M: merge the two lowest-weight walkers (ties: lowest slot): the
 //                first survives with probability w_i/(w_i+w_j), else the
-//                second, and the survivor carries w_i + w_j; repeat.  The
-//                bin is sorted once by (weight, slot); merged walkers queue up
-//                in the order they are made, which is also non-decreasing in
-//                weight, so each merge only compares the heads of the two
-//                queues (ties of equal sums ordered by a small heap): the same
-//                pairs as a full search, in O(n log n) instead of O(n^2);
+//                second, and the survivor carries w_i + w_j; repeat.
+//        Up to 64 walkers a bin is held one walker per lane in registers and
+//        each merge takes two DPP wave minima.  Larger bins are sorted once
+//        by (weight, slot); merged walkers queue up in the order they are
+//        made, which is also non-decreasing in weight, so each merge only
+//        compares the heads of the two queues (ties of equal sums ordered by
+//        a small heap): the same pairs as a full search, in O(n log n)
+//        instead of O(n^2);
 //      output order: bins ascending, parents by ascending slot, copies of a
 //      parent consecutive -- neighbouring lanes then hold walkers of similar
 //      state for the next SSA step;
@@ -37,7 +41,13 @@
 // bit for bit.
 #include "we_common.h"
 
+#include <algorithm>
+
 #define RESAMPLE_LDS_CAP 8192
+#define RESAMPLE_LDS_MAX (150 * 1024)
+// Cursor rows for placing walkers in parallel: one row of n_bins per wave, as
+// long as the rows hold at most this many counters.
+#define RESAMPLE_PLACE_INTS 4096
 // Threads per run: up to 16 waves, so up to 16 bins are split/merged at
 // once.  With many runs the grid fills the chip anyway and smaller blocks
 // cost less to start, so launches with at least RESAMPLE_MANY_RUNS blocks use
@@ -129,6 +139,15 @@ __device__ __forceinline__ double wave_max(double v) {
     return fmax(fmax(rs_readlane(v, 0), rs_readlane(v, 16)), fmax(rs_readlane(v, 32), rs_readlane(v, 48)));
 }
 
+// Smallest value over the 64 lanes, by the same steps as wave_max.
+__device__ __forceinline__ double wave_min(double v) {
+    v = fmin(v, rs_dpp<0xB1>(v));
+    v = fmin(v, rs_dpp<0x4E>(v));
+    v = fmin(v, rs_dpp<0x141>(v));
+    v = fmin(v, rs_dpp<0x140>(v));
+    return fmin(fmin(rs_readlane(v, 0), rs_readlane(v, 16)), fmin(rs_readlane(v, 32), rs_readlane(v, 48)));
+}
+
 __device__ __forceinline__ int32_t wave_excl_scan(int32_t v, int lane, int32_t *total) {
     int32_t x = v;
     for (int d = 1; d < 64; d <<= 1) {
@@ -195,6 +214,37 @@ __device__ void split_bin(const RunWork<Idx> &wk, int32_t p0, int32_t nb, int32_
         const double share = w[q] / (double)cc;
         const int32_t k = wk.list[p0 + q];
         for (int32_t r = 0; r < cc; ++r) {
+            out.orig[o] = k;
+            out.wn[o] = share;
+            out.obin[o] = b;
+            ++o;
+        }
+    }
+}
+
+// n < M with at most 64 parents: parent q lives in lane q, its weight, copy
+// count and per-copy share in registers; the same hand-out as split_bin.
+template <class Idx>
+__device__ void split_bin_lanes(const RunWork<Idx> &wk, int32_t p0, int32_t nb, int32_t M, int32_t b, int32_t o0,
+                                const BinOut &out, int lane) {
+    const bool own = lane < nb;
+    const double wq = own ? wk.w[p0 + lane] : 0.0;
+    int32_t c = 1;
+    double bs = own ? wq / 1.0 : -1.0;
+    for (int32_t e = nb; e < M; ++e) {
+        const double mx = wave_max(bs);
+        const int wl = __ffsll((long long)__ballot(bs == mx)) - 1;
+        if (lane == wl) {
+            c += 1;
+            bs = wq / (double)c;
+        }
+    }
+    int32_t tot;
+    int32_t o = o0 + wave_excl_scan(own ? c : 0, lane, &tot);
+    if (own) {
+        const double share = wq / (double)c;
+        const int32_t k = wk.list[p0 + lane];
+        for (int32_t r = 0; r < c; ++r) {
             out.orig[o] = k;
             out.wn[o] = share;
             out.obin[o] = b;
@@ -293,6 +343,44 @@ struct MergeQueues {
         }
     }
 };
+
+// n > M with at most 64 walkers: walker q lives in lane q.  Each merge finds
+// the lightest live walker by a wave minimum (ties: the lowest lane, which is
+// the lowest slot), then the lightest of the rest; the merged-away walker's
+// lane holds +inf from then on.  The same pairs, draws and sums as merge_bin.
+template <class Idx>
+__device__ void merge_bin_lanes(const RunWork<Idx> &wk, int32_t p0, int32_t nb, int32_t M, int32_t b, int32_t o0,
+                                const BinOut &out, uint32_t iter, uint32_t k0, uint32_t k1, int lane) {
+    const double inf = __builtin_huge_val();
+    double wv = lane < nb ? wk.w[p0 + lane] : inf;
+    double ul = 0.0;
+    for (int32_t m = 0; m < nb - M; ++m) {
+        if ((m & 63) == 0) {   // the next 64 merge draws, one per lane
+            const U4 rr = philox4x32_10((uint32_t)(m + lane), (uint32_t)b, iter, 1u, k0, k1);
+            ul = uniform53(rr.x, rr.y);
+        }
+        const double wi = wave_min(wv);
+        const int qi = __ffsll((long long)__ballot(wv == wi)) - 1;
+        const double wrest = lane == qi ? inf : wv;
+        const double wj = wave_min(wrest);
+        const int qj = __ffsll((long long)__ballot(wrest == wj)) - 1;
+        const double u = rs_readlane(ul, m & 63);
+        const double sum = wi + wj;
+        const double p_i = wi / sum;
+        const int keep = (u < p_i) ? qi : qj;
+        const int drop = (keep == qi) ? qj : qi;
+        if (lane == keep) wv = sum;
+        if (lane == drop) wv = inf;
+    }
+    const bool live = lane < nb && wv != inf;
+    int32_t tot;
+    const int32_t o = o0 + wave_excl_scan(live ? 1 : 0, lane, &tot);
+    if (live) {
+        out.orig[o] = wk.list[p0 + lane];
+        out.wn[o] = wv;
+        out.obin[o] = b;
+    }
+}
 
 // n > M: merge the two lightest walkers (ties: lowest slot) until M remain.
 template <class Idx>
@@ -396,8 +484,12 @@ __device__ void resample_run_t(const SimArgs &a, const double *__restrict__ w_cu
     int32_t *cnt = reinterpret_cast<int32_t *>(lds);   // [NB]
     int32_t *start = cnt + NB;                          // [NB+1]
     int32_t *ostart = start + NB + 1;                   // [NB+1]
-    int32_t *cursor = ostart + NB + 1;                  // [NB]
-    float *evb = reinterpret_cast<float *>(cursor + NB); // [NB] events of the walkers in each bin
+    // walkers are placed by P waves at once, wave r over its own contiguous
+    // run of 64-slot chunks; row r of the cursor table first counts, per bin,
+    // the walkers of those chunks, then holds where the next one goes
+    const int32_t P = max(1, min(n_waves, a.place_rows));
+    int32_t *cursor = ostart + NB + 1;                  // [a.place_rows][NB]
+    float *evb = reinterpret_cast<float *>(cursor + (size_t)max(1, a.place_rows) * NB); // [NB] events per bin
     unsigned char *tail = reinterpret_cast<unsigned char *>(evb + NB);
     tail += (16 - ((uintptr_t)tail & 15)) & 15;
 
@@ -426,10 +518,13 @@ __device__ void resample_run_t(const SimArgs &a, const double *__restrict__ w_cu
         wk.aux = reinterpret_cast<Idx *>(a.s_cnt + base);
     }
 
+    const int32_t n_chunks = (n + 63) >> 6;
+    const int32_t per_row = max(1, (n_chunks + P - 1) / P) * 64;   // slots per row
     for (int32_t b = tid; b < NB; b += nthr) {
         cnt[b] = 0;
         evb[b] = 0.0f;
     }
+    for (int32_t i = tid; i < P * NB; i += nthr) cursor[i] = 0;
     __syncthreads();
     int64_t my_ev = 0;
     for (int32_t k = tid; k < n; k += nthr) {
@@ -437,6 +532,7 @@ __device__ void resample_run_t(const SimArgs &a, const double *__restrict__ w_cu
         const uint32_t ev = a.ev_walker[base + k];
         wk.tag[k] = (uint16_t)(b | (srec[k] ? 0x8000 : 0));
         atomicAdd(&cnt[b], 1);
+        atomicAdd(&cursor[(k / per_row) * NB + b], 1);
         if (a.queue_stats) atomicAdd(&evb[b], (float)ev);
         my_ev += ev;
     }
@@ -451,13 +547,8 @@ __device__ void resample_run_t(const SimArgs &a, const double *__restrict__ w_cu
                 atomicAdd(&a.n_bin[b], cnt[b]);
             }
 
-    // wave 0: reactions fired, bin offsets, stable placement and the
-    // recycled weight in slot order
+    // wave 0: bin offsets (walkers ordered by bin, then slot)
     if (wave == 0) {
-        int64_t ev = 0;
-        for (int32_t t = lane; t < nthr; t += 64) ev += ev_part[t];
-        for (int d = 32; d > 0; d >>= 1) ev += __shfl_xor(ev, d, 64);
-
         const int32_t kb = (NB + 63) >> 6;
         const int32_t b_lo = min(lane * kb, NB), b_hi = min(b_lo + kb, NB);
         int32_t acc = 0, oacc = 0;
@@ -470,7 +561,6 @@ __device__ void resample_run_t(const SimArgs &a, const double *__restrict__ w_cu
         oacc = wave_excl_scan(oacc, lane, &otot);
         for (int32_t b = b_lo; b < b_hi; ++b) {
             start[b] = acc;
-            cursor[b] = acc;
             ostart[b] = oacc;
             acc += cnt[b];
             oacc += cnt[b] > 0 ? M : 0;
@@ -479,25 +569,29 @@ __device__ void resample_run_t(const SimArgs &a, const double *__restrict__ w_cu
             start[NB] = tot;
             ostart[NB] = otot;
         }
-        wave_sync();
+    }
+    __syncthreads();
+    // row r's count of bin b becomes the position of its first walker of b
+    for (int32_t b = tid; b < NB; b += nthr) {
+        int32_t c = start[b];
+        for (int32_t r = 0; r < P; ++r) {
+            const int32_t t = cursor[r * NB + b];
+            cursor[r * NB + b] = c;
+            c += t;
+        }
+    }
+    __syncthreads();
 
-        // lanes with the same bin are ranked by a ballot; the bin's cursor
-        // advances by the group size
-        double f = 0.0;
-        for (int32_t c0 = 0; c0 < n; c0 += 64) {
+    // stable placement: waves r < P, each over its chunks in slot order;
+    // lanes with the same bin are ranked by a ballot and the bin's cursor
+    // advances by the group size
+    if (wave < P) {
+        int32_t *cur = cursor + wave * NB;
+        const int32_t k_hi = min(n, (wave + 1) * per_row);
+        for (int32_t c0 = wave * per_row; c0 < k_hi; c0 += 64) {
             const int32_t k = c0 + lane;
-            const bool valid = k < n;
-            const int32_t tg = valid ? (int32_t)wk.tag[k] : 0;
-            const int32_t b = valid ? (tg & 0x7FFF) : -1;
-            unsigned long long rm = __ballot(valid && (tg & 0x8000));
-            if (rm) {
-                const double wv = (valid && (tg & 0x8000)) ? wr[k] : 0.0;
-                while (rm) {
-                    const int l = __ffsll((long long)rm) - 1;
-                    f = f + rs_readlane(wv, l);
-                    rm &= rm - 1ull;
-                }
-            }
+            const bool valid = k < k_hi;
+            const int32_t b = valid ? (int32_t)(wk.tag[k] & 0x7FFF) : -1;
             unsigned long long todo = __ballot(valid);
             while (todo) {
                 const int leader = __ffsll((long long)todo) - 1;
@@ -505,12 +599,33 @@ __device__ void resample_run_t(const SimArgs &a, const double *__restrict__ w_cu
                 const unsigned long long grp = __ballot(valid && b == lb);
                 if (valid && b == lb) {
                     const unsigned long long below = lane ? (grp & ((1ull << lane) - 1ull)) : 0ull;
-                    wk.list[cursor[lb] + __popcll(below)] = k;
+                    wk.list[cur[lb] + __popcll(below)] = k;
                 }
                 wave_sync();
-                if (lane == leader) cursor[lb] += __popcll(grp);
+                if (lane == leader) cur[lb] += __popcll(grp);
                 wave_sync();
                 todo &= ~grp;
+            }
+        }
+    }
+    // the last wave: reactions fired and the recycled weight, summed in slot
+    // order
+    if (wave == n_waves - 1) {
+        int64_t ev = 0;
+        for (int32_t t = lane; t < nthr; t += 64) ev += ev_part[t];
+        for (int d = 32; d > 0; d >>= 1) ev += __shfl_xor(ev, d, 64);
+        double f = 0.0;
+        for (int32_t c0 = 0; c0 < n; c0 += 64) {
+            const int32_t k = c0 + lane;
+            const bool rec = k < n && (wk.tag[k] & 0x8000);
+            unsigned long long rm = __ballot(rec);
+            if (rm) {
+                const double wv = rec ? wr[k] : 0.0;
+                while (rm) {
+                    const int l = __ffsll((long long)rm) - 1;
+                    f = f + rs_readlane(wv, l);
+                    rm &= rm - 1ull;
+                }
             }
         }
         if (lane == 0 && rec_slot < a.max_iters) {
@@ -541,9 +656,11 @@ __device__ void resample_run_t(const SimArgs &a, const double *__restrict__ w_cu
                 out.obin[o0 + q] = b;
             }
         } else if (nb < M) {
-            split_bin(wk, p0, nb, M, b, o0, out, lane);
+            if (nb <= 64) split_bin_lanes(wk, p0, nb, M, b, o0, out, lane);
+            else split_bin(wk, p0, nb, M, b, o0, out, lane);
         } else {
-            merge_bin(wk, p0, nb, M, b, o0, out, iter, k0, k1, lane);
+            if (nb <= 64) merge_bin_lanes(wk, p0, nb, M, b, o0, out, iter, k0, k1, lane);
+            else merge_bin(wk, p0, nb, M, b, o0, out, iter, k0, k1, lane);
         }
     }
     __syncthreads();
@@ -676,14 +793,27 @@ hipError_t launch_recycle_bin(const SimArgs &a, int32_t *x_cur, bool grid_bins, 
 }
 
 bool resample_uses_lds(const SimArgs &a);
-size_t resample_lds_bytes(const SimArgs &a, bool use_lds) {
-    size_t b = sizeof(int32_t) * (5 * (size_t)a.n_bins + 2) + 16;
+static size_t lds_bytes_rows(const SimArgs &a, bool use_lds, int32_t rows) {
+    size_t b = sizeof(int32_t) * ((4 + (size_t)rows) * a.n_bins + 2) + 16;
     if (use_lds) b += (size_t)a.cap * (sizeof(double) + sizeof(int32_t) + 2 * sizeof(uint16_t));
     return b;
 }
 
+size_t resample_lds_bytes(const SimArgs &a, bool use_lds) {
+    return lds_bytes_rows(a, use_lds, a.place_rows > 0 ? a.place_rows : 1);
+}
+
+// The per-walker arrays go to LDS when they fit beside a single cursor row.
 bool resample_uses_lds(const SimArgs &a) {
-    return a.cap <= RESAMPLE_LDS_CAP && resample_lds_bytes(a, true) <= 150 * 1024;
+    return a.cap <= RESAMPLE_LDS_CAP && lds_bytes_rows(a, true, 1) <= RESAMPLE_LDS_MAX;
+}
+
+int32_t resample_place_rows(const SimArgs &a, int64_t blocks) {
+    const bool ul = resample_uses_lds(a);
+    int32_t rows = (int32_t)(resample_threads(blocks) / 64);
+    rows = std::min<int32_t>(rows, std::max<int32_t>(1, RESAMPLE_PLACE_INTS / std::max(1, a.n_bins)));
+    while (rows > 1 && lds_bytes_rows(a, ul, rows) > RESAMPLE_LDS_MAX) --rows;
+    return rows;
 }
 
 hipError_t launch_resample(const SimArgs &a, int32_t *x_cur, const double *w_cur, int32_t *x_nxt,

@@ -28,6 +28,7 @@ bool lane_kernel_fits(int32_t S, int32_t R, int32_t max_delta);
 hipError_t launch_ssa_wave(const SimArgs &a, int32_t *xs, hipStream_t st);
 bool wave_kernel_fits(int32_t S, int32_t R);
 hipError_t launch_recycle_bin(const SimArgs &a, int32_t *x_cur, bool grid_bins, hipStream_t st);
+int32_t resample_place_rows(const SimArgs &a, int64_t blocks);
 hipError_t launch_resample(const SimArgs &a, int32_t *x_cur, const double *w_cur, int32_t *x_nxt,
                            double *w_nxt, hipStream_t st);
 hipError_t launch_advance(const SimArgs &a, hipStream_t st);
@@ -417,6 +418,7 @@ extern "C" we_status we_init(const we_network *net, const we_grid *g, const we_p
     a.iter_dev = (uint32_t *)at(P_ITER);
     a.jhist = (double *)at(P_JHIST);
     a.queue_stats = 1;
+    a.place_rows = resample_place_rows(a, n_runs);
     a.ev_bin = (float *)at(P_SCHED);
     a.n_bin = (int32_t *)at(P_SCHED) + NB;
     a.seg_rep = seg_rep_for(NB);

@@ -4,8 +4,9 @@ A network whose only reaction has rate zero never fires, so one WE
 iteration is resampling alone: the ensembles below are built to stress the
 split/merge code -- bins far above M with many equal weights (the merge
 order hinges on the slot tie-break), bins far below M with equal shares
-(the split order hinges on the same tie-break), zero weights, and sizes on
-both sides of the LDS limit of the per-run working arrays.  Walkers, weights,
+(the split order hinges on the same tie-break), zero weights, bins on both
+sides of 64 walkers (up to 64 a bin is held one walker per lane), and sizes
+on both sides of the LDS limit of the per-run working arrays.  Walkers, weights,
 bins, parents and the recycled-weight record must equal the oracle's
 bit for bit."""
 import numpy as np
@@ -59,6 +60,10 @@ CASES = [
     (8, 16, [[1, 0, 0, 97, 0, 20, 0, 7], [0, 3, 16, 16, 40, 0, 1, 2]], "equal"),
     (8, 16, [[1, 0, 0, 97, 0, 20, 0, 7], [0, 3, 16, 16, 40, 0, 1, 2]], "dyadic"),
     (8, 16, [[5, 30, 0, 1, 0, 64, 0, 3], [12, 12, 12, 12, 12, 12, 12, 11]], "zeros"),
+    # bins on both sides of 64 walkers (one walker per lane up to 64)
+    (64, 4, [[64, 65, 63, 1, 33, 2], [4, 5, 64, 3, 0, 60]], "equal"),
+    (64, 4, [[64, 65, 63, 1, 33, 2], [4, 5, 64, 3, 0, 60]], "dyadic"),
+    (4, 100, [[1, 64, 65, 99], [63, 2, 100, 101]], "dyadic"),
     (4, 3000, [[1, 9000, 2500, 499], [0, 3000, 5999, 3001]], "equal"),
     (4, 3000, [[1, 9000, 2500, 499], [700, 0, 11000, 300]], "uniform"),
 ]
