@@ -49,7 +49,7 @@ def lib():
         L.or_we_iterate.argtypes = [C.c_void_p, C.c_void_p, C.c_uint32, P(C.c_int32),
                                     P(C.c_int32), P(C.c_double), P(C.c_int32),
                                     P(C.c_int32), C.c_int32, P(C.c_double), P(C.c_int64),
-                                    P(C.c_int32)]
+                                    P(C.c_int32), P(C.c_int32)]
         L.or_we_iterate.restype = C.c_int32
         L.or_resample_bin.argtypes = [C.c_int32, P(C.c_int32), P(C.c_double), C.c_int32,
                                       C.c_uint64, C.c_uint32, C.c_uint32,
@@ -159,7 +159,7 @@ class OracleWE:
     outputs.  The initial ensemble is m_targ walkers at x0 with weight
     1/m_targ each, unless init_x/init_w are given."""
 
-    def __init__(self, cfg, seed: int, init_x=None, init_w=None):
+    def __init__(self, cfg, seed: int, init_x=None, init_w=None, rw_period: int = 0):
         self.cfg = cfg
         self.onet = OracleNet(cfg.net)
         st = self.onet.validate()
@@ -200,6 +200,12 @@ class OracleWE:
         self.flux: List[float] = []
         self.events: List[int] = []
         self.segments: List[int] = []
+        # steady-state reweighting (reweight.py): every rw_period iterations
+        self.rw_period = int(rw_period)
+        self.end_bin = np.zeros(cap, np.int32)
+        self.rw_F = np.zeros((cfg.n_bins, cfg.n_bins), np.float64)
+        self.rw_applied = 0
+        self.rw_skipped = 0
 
     def step(self, n_iters: int = 1):
         L = lib()
@@ -208,15 +214,28 @@ class OracleWE:
         ev = C.c_int64(0)
         for _ in range(n_iters):
             n.value = self.n
+            n_in = self.n
             self.segments.append(self.n)
+            if self.rw_period > 0:
+                start_bin = self.bin[:n_in].copy()
+                start_w = self.w[:n_in].copy()
             st = L.or_we_iterate(self.onet.ptr, self.cptr, self.iter, C.byref(n),
                                  _p(self.x, C.c_int32), _p(self.w, C.c_double),
                                  _p(self.bin, C.c_int32), _p(self.origin, C.c_int32),
                                  self.cfg.cap, C.byref(flux), C.byref(ev),
-                                 _p(self.recycled, C.c_int32))
+                                 _p(self.recycled, C.c_int32), _p(self.end_bin, C.c_int32))
             if st != 0:
                 raise RuntimeError(f"oracle WE iteration {self.iter} failed: status {st}")
             self.n = n.value
+            if self.rw_period > 0:
+                from . import reweight as rw
+                if self.iter >= 1:
+                    rw.accumulate_flux(self.rw_F, start_bin, self.end_bin[:n_in], start_w)
+                if (self.iter + 1) % self.rw_period == 0:
+                    if rw.reweight(self.rw_F, self.bin[:self.n], self.w[: self.n], self.cfg.n_bins):
+                        self.rw_applied += 1
+                    else:
+                        self.rw_skipped += 1
             self.iter += 1
             self.flux.append(flux.value)
             self.events.append(ev.value)

@@ -1,0 +1,150 @@
+"""Steady-state reweighting, written from the paper (test infrastructure only).
+
+Only the test suite, the smoke check and the benchmark's CPU-baseline leg may
+import this module.  It is the plain, slow statement of the reweighting step
+of Sec. II.B.2 ("Reweighting", Eq. ss) that the GPU path is checked against.
+
+What the paper fixes:
+  * w_i is the weight in bin i (the sum of its walkers' weights);
+  * f_ij is the flux of weight into bin i from bin j, and f_ij = k_ij w_j
+    holds whether or not the ensemble is in steady state, so measured fluxes
+    and bin weights give the inter-bin rates k_ij;
+  * the steady-state bin weights solve Eq. ss,
+        sum_j (k_ij w_j - k_ji w_i) = 0   for every bin i,
+    and the walkers of each bin are then rescaled to them.
+
+Readings taken where the paper is silent (each listed in the design notes):
+  RW1  f_ij is accumulated from the start of the run: every interval adds,
+       slot by slot in ascending slot order, the weight each walker carried
+       through the interval to F[i, j], j its bin at the start of the interval
+       and i its bin at the end (after recycling, so a walker recycled from B
+       counts as moving into the bin of A).  The rates are constants of the
+       dynamics, so all intervals estimate the same k_ij.  The walkers of the
+       very first interval have no bin yet (they are binned by the first
+       resampling), so accumulation starts with the second interval.
+  RW2  W_j = sum_i F[i, j] (ascending i): the weight that started intervals in
+       bin j; k_ij = F[i, j] / W_j for i != j.
+  RW3  A reweighting event happens after the resampling of every iteration t
+       with (t + 1) % period == 0.  Candidates are the bins that are occupied
+       now and have W_j > 0.  Eq. ss has a unique positive solution only on a
+       strongly connected set of bins (edge j -> i when F[i, j] > 0, i != j),
+       and near the edge of the explored region transitions are often seen
+       in one direction only.  So the event reweights the strongly connected
+       component, within the candidates, of the candidate holding the most
+       weight now (ties: the lowest bin), and nothing if that component is a
+       single bin.
+  RW4  pi solves Eq. ss on that component with sum(pi) = 1.  The component
+       keeps its total weight W_A = sum_a w_a (ascending a): bin a's target is
+       pi_a / Z * W_A (Z = sum of pi, ascending), and each of its walkers is
+       multiplied by target / w_a.  All other bins are left as they are, so
+       the total weight is conserved.
+
+The solve here is the textbook one (generator matrix, one balance equation
+replaced by the normalisation, LU via numpy); strong connectivity comes from
+scipy's graph routine.  Neither shares code with the device.
+"""
+from __future__ import annotations
+
+from typing import Optional
+
+import numpy as np
+
+
+def accumulate_flux(F: np.ndarray, start_bin, end_bin, w) -> None:
+    """RW1: F[end, start] += weight, walker by walker in slot order."""
+    for k in range(len(w)):
+        i, j = int(end_bin[k]), int(start_bin[k])
+        F[i, j] = F[i, j] + float(w[k])
+
+
+def start_weights(F: np.ndarray) -> np.ndarray:
+    """RW2: W_j = sum_i F[i, j], i ascending."""
+    nb = F.shape[0]
+    W = np.zeros(nb, np.float64)
+    for j in range(nb):
+        acc = 0.0
+        for i in range(nb):
+            acc = acc + float(F[i, j])
+        W[j] = acc
+    return W
+
+
+def bin_weights(bins, w, n_bins: int) -> np.ndarray:
+    """w_i: the weights of bin i's walkers summed in slot order."""
+    out = np.zeros(n_bins, np.float64)
+    for k in range(len(w)):
+        b = int(bins[k])
+        out[b] = out[b] + float(w[k])
+    return out
+
+
+def component_of(F: np.ndarray, cand, pivot: int) -> list:
+    """RW3: the bins of `cand` in the strongly connected component of
+    `pivot` in the graph j -> i (F[i, j] > 0, i != j) restricted to `cand`,
+    ascending."""
+    from scipy.sparse import csr_matrix
+    from scipy.sparse.csgraph import connected_components
+    cand = list(cand)
+    sub = np.asarray(F)[np.ix_(cand, cand)] > 0.0
+    np.fill_diagonal(sub, False)
+    # csgraph edge (r, c) means r -> c: the transpose of F's (into, from)
+    _, label = connected_components(csr_matrix(sub.T.astype(np.int8)), directed=True,
+                                    connection="strong")
+    lp = label[cand.index(pivot)]
+    return [b for b, l in zip(cand, label) if l == lp]
+
+
+def steady_state(F: np.ndarray, active) -> Optional[np.ndarray]:
+    """RW2, RW4: the solution of Eq. ss on a strongly connected set of bins
+    (ascending) with sum 1; None for fewer than two bins."""
+    active = list(active)
+    na = len(active)
+    if na < 2:
+        return None
+    W = start_weights(F)
+    Q = np.zeros((na, na), np.float64)
+    for a, i in enumerate(active):
+        for b, j in enumerate(active):
+            if a != b:
+                Q[a, b] = F[i, j] / W[j]          # k_ij: rate from j into i
+    for b in range(na):
+        Q[b, b] = -sum(Q[a, b] for a in range(na) if a != b)
+    A = Q.copy()
+    A[na - 1, :] = 1.0
+    rhs = np.zeros(na)
+    rhs[na - 1] = 1.0
+    return np.linalg.solve(A, rhs)
+
+
+def reweight(F: np.ndarray, bins, w: np.ndarray, n_bins: int) -> bool:
+    """One reweighting event (RW3, RW4) on the current ensemble (bins, w in
+    slot order); w is rescaled in place.  Returns True if the event applied."""
+    wb = bin_weights(bins, w, n_bins)
+    occupied = np.zeros(n_bins, bool)
+    occupied[np.asarray(bins, np.int64)] = True
+    W = start_weights(F)
+    cand = [i for i in range(n_bins) if occupied[i] and W[i] > 0.0]
+    if len(cand) < 2:
+        return False
+    pivot = cand[0]
+    for i in cand:
+        if wb[i] > wb[pivot]:
+            pivot = i
+    active = component_of(F, cand, pivot)
+    pi = steady_state(F, active)
+    if pi is None:
+        return False
+    Z = 0.0
+    for v in pi:
+        Z = Z + float(v)
+    WA = 0.0
+    for i in active:
+        WA = WA + float(wb[i])
+    factor = {}
+    for a, i in enumerate(active):
+        factor[i] = (float(pi[a]) / Z * WA) / float(wb[i])
+    for k in range(len(w)):
+        b = int(bins[k])
+        if b in factor:
+            w[k] = w[k] * factor[b]
+    return True

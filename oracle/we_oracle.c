@@ -335,7 +335,8 @@ int32_t or_resample_bin(int32_t nb, const int32_t *slot, const double *w,
 int32_t or_we_iterate(const or_net *net, const or_we_cfg *cfg, uint32_t iter,
                       int32_t *n, int32_t *x, double *w, int32_t *bin,
                       int32_t *origin, int32_t cap,
-                      double *flux_out, int64_t *events_out, int32_t *recycled_out)
+                      double *flux_out, int64_t *events_out, int32_t *recycled_out,
+                      int32_t *end_bin_out)
 {
     const int32_t S = net->S, N = *n, M = cfg->m_targ, NB = cfg->n_bins;
     if (N > cap || M * NB > cap) return OR_EINVAL;
@@ -367,6 +368,7 @@ int32_t or_we_iterate(const or_net *net, const or_we_cfg *cfg, uint32_t iter,
     /* 3. bin assignment */
     for (int32_t k = 0; k < N; ++k)
         bin[k] = or_bin_of(NB, cfg->edges, or_coord(S, cfg->bin_coef, x + (size_t)k * S));
+    if (end_bin_out) memcpy(end_bin_out, bin, sizeof(int32_t) * (size_t)N);
 
     /* 4. resample bin by bin into a fresh ensemble */
     int32_t *nx = (int32_t *)malloc(sizeof(int32_t) * (size_t)cap * (size_t)S);

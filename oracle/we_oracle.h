@@ -107,12 +107,16 @@ int32_t or_bin_of(int32_t n_bins, const double *edges, double q);
  * consecutive).  Arrays must hold cap = m_targ*n_bins walkers (and at least
  * the incoming *n).  flux_out gets the weight recycled this iteration;
  * events_out the reactions fired; recycled_out (may be NULL, size cap)
- * gets 1 for every incoming slot whose walker reached B and was recycled.
+ * gets 1 for every incoming slot whose walker reached B and was recycled;
+ * end_bin_out (may be NULL, size cap) gets the bin of every incoming slot at
+ * the end of the interval, after recycling (the end bins of the inter-bin
+ * fluxes used by steady-state reweighting).
  * Returns a status. */
 int32_t or_we_iterate(const or_net *net, const or_we_cfg *cfg, uint32_t iter,
                       int32_t *n, int32_t *x, double *w, int32_t *bin,
                       int32_t *origin, int32_t cap,
-                      double *flux_out, int64_t *events_out, int32_t *recycled_out);
+                      double *flux_out, int64_t *events_out, int32_t *recycled_out,
+                      int32_t *end_bin_out);
 
 /* The resampling step alone, for one bin: nb walkers (parent slots, weights)
  * in ascending slot order.  Writes the surviving/replicated walkers as
