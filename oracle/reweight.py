@@ -26,7 +26,8 @@ Readings taken where the paper is silent (each listed in the design notes):
        bin j; k_ij = F[i, j] / W_j for i != j.
   RW3  A reweighting event happens after the resampling of every iteration t
        with (t + 1) % period == 0.  Candidates are the bins that are occupied
-       now and have W_j > 0.  Eq. ss has a unique positive solution only on a
+       now, weigh more than zero (a bin of zero weight cannot be scaled to a
+       positive target) and have W_j > 0.  Eq. ss has a unique positive solution only on a
        strongly connected set of bins (edge j -> i when F[i, j] > 0, i != j),
        and near the edge of the explored region transitions are often seen
        in one direction only.  So the event reweights the strongly connected
@@ -39,12 +40,22 @@ Readings taken where the paper is silent (each listed in the design notes):
        multiplied by target / w_a.  All other bins are left as they are, so
        the total weight is conserved.
 
-The solve here is the textbook one (generator matrix, one balance equation
-replaced by the normalisation, LU via numpy); strong connectivity comes from
-scipy's graph routine.  Neither shares code with the device.
+The solve here is the textbook one, done exactly: the balance equations
+with one of them replaced by the normalisation, solved by Gaussian
+elimination on the exact values of the measured doubles, and one rounding
+of each pi_a at the end.  (Floating-point LU would do, but its error is
+normwise: bins many decades below the heaviest would come out with few
+correct digits.)  Written for q_b = pi_b / W_b, every coefficient is a
+double or an exact sum of doubles,
+    sum_b F[a, b] q_b - q_a sum_b F[b, a] = 0,   sum_b W_b q_b = 1   (b != a),
+so one power-of-two scale makes the system integer, and fraction-free
+(Bareiss) elimination solves it in Python integers.  Strong connectivity
+comes from scipy's graph routine.  Neither shares code with the device.
 """
 from __future__ import annotations
 
+import math
+from fractions import Fraction
 from typing import Optional
 
 import numpy as np
@@ -102,18 +113,38 @@ def steady_state(F: np.ndarray, active) -> Optional[np.ndarray]:
     if na < 2:
         return None
     W = start_weights(F)
-    Q = np.zeros((na, na), np.float64)
-    for a, i in enumerate(active):
-        for b, j in enumerate(active):
-            if a != b:
-                Q[a, b] = F[i, j] / W[j]          # k_ij: rate from j into i
-    for b in range(na):
-        Q[b, b] = -sum(Q[a, b] for a in range(na) if a != b)
-    A = Q.copy()
-    A[na - 1, :] = 1.0
-    rhs = np.zeros(na)
-    rhs[na - 1] = 1.0
-    return np.linalg.solve(A, rhs)
+    vals = [float(F[i, j]) for i in active for j in active] + [float(W[j]) for j in active]
+    e_min = min(math.frexp(v)[1] for v in vals if v != 0.0) - 53
+    def z(v):                                    # the double v times 2^-e_min, exactly
+        if v == 0.0:
+            return 0
+        m, e = math.frexp(v)
+        return int(m * (1 << 53)) << (e - 53 - e_min)
+    Fz = [[z(float(F[i, j])) for j in active] for i in active]
+    A = []
+    for a in range(na - 1):
+        row = [Fz[a][b] if b != a else 0 for b in range(na)]
+        row[a] = -sum(Fz[b][a] for b in range(na) if b != a)
+        A.append(row + [0])
+    A.append([z(float(W[j])) for j in active] + [1 << (-e_min) if e_min <= 0 else 0])
+    if e_min > 0:                                # right-hand side 1 scaled by 2^-e_min
+        A[-1] = [v << e_min for v in A[-1][:na]] + [1]
+    # Bareiss: every division below is exact
+    prev = 1
+    for k in range(na):
+        if A[k][k] == 0:
+            r = next(r for r in range(k + 1, na) if A[r][k] != 0)
+            A[k], A[r] = A[r], A[k]
+        for i in range(k + 1, na):
+            for j in range(k + 1, na + 1):
+                A[i][j] = (A[i][j] * A[k][k] - A[i][k] * A[k][j]) // prev
+            A[i][k] = 0
+        prev = A[k][k]
+    q = [Fraction(0)] * na
+    for a in range(na - 1, -1, -1):
+        acc = Fraction(A[a][na]) - sum((A[a][b] * q[b] for b in range(a + 1, na)), Fraction(0))
+        q[a] = acc / A[a][a]
+    return np.array([float(q[a] * Fraction(float(W[j]))) for a, j in enumerate(active)])
 
 
 def reweight(F: np.ndarray, bins, w: np.ndarray, n_bins: int) -> bool:
@@ -123,7 +154,7 @@ def reweight(F: np.ndarray, bins, w: np.ndarray, n_bins: int) -> bool:
     occupied = np.zeros(n_bins, bool)
     occupied[np.asarray(bins, np.int64)] = True
     W = start_weights(F)
-    cand = [i for i in range(n_bins) if occupied[i] and W[i] > 0.0]
+    cand = [i for i in range(n_bins) if occupied[i] and wb[i] > 0.0 and W[i] > 0.0]
     if len(cand) < 2:
         return False
     pivot = cand[0]

@@ -1,12 +1,15 @@
 """Pins of the oracle's steady-state reweighting (Sec. II.B.2, Eq. ss)
-against things outside itself: detailed balance of birth-death chains, the
-closed form of a one-way cycle, exact rational arithmetic on a small dense
-chain, hand-computed flux matrices, invariants of the rescaling, and the
-relaxation speed-up the paper reports.  CPU only."""
+against things outside itself: detailed balance of birth-death chains (also
+over 40 decades), the closed form of a one-way cycle, the Markov chain tree
+theorem by brute force on small dense chains, hand-computed flux matrices,
+invariants of the rescaling, and the relaxation speed-up the paper reports.
+CPU only."""
+import itertools
 import math
 from fractions import Fraction
 
 import numpy as np
+import pytest
 
 import closed_form as cf
 from oracle import oracle as orc, reweight as rw
@@ -59,8 +62,7 @@ def test_birth_death_chain_detailed_balance():
     F = _flux_from_rates(K, rng.uniform(0.5, 2.0, n))
     pi = rw.steady_state(F, list(range(n)))
     want = cf.chain_stationary(np.append(lam[:-1], 1.0), np.append(0.0, mu[1:]))
-    # pi spans 3.5 decades here: LU's error grows with that spread (1e-12 seen)
-    assert np.allclose(pi, want, rtol=1e-10, atol=0)
+    assert np.allclose(pi, want, rtol=1e-12, atol=0)
 
 
 def test_one_way_cycle_closed_form():
@@ -75,36 +77,62 @@ def test_one_way_cycle_closed_form():
     assert np.allclose(pi, want / want.sum(), rtol=1e-13, atol=0)
 
 
-def _exact_stationary(Kf):
-    """Gaussian elimination in rationals: sum_j (k_ij p_j - k_ji p_i) = 0 with
-    the last equation replaced by sum p = 1."""
-    n = len(Kf)
-    A = [[Fraction(0)] * (n + 1) for _ in range(n)]
-    for i in range(n):
-        for j in range(n):
-            if i != j:
-                A[i][j] += Kf[i][j]
-                A[i][i] -= Kf[j][i]
-    A[n - 1] = [Fraction(1)] * n + [Fraction(1)]
-    for col in range(n):
-        piv = next(r for r in range(col, n) if A[r][col] != 0)
-        A[col], A[piv] = A[piv], A[col]
-        for r in range(n):
-            if r != col and A[r][col] != 0:
-                f = A[r][col] / A[col][col]
-                A[r] = [x - f * y for x, y in zip(A[r], A[col])]
-    return [A[i][n] / A[i][i] for i in range(n)]
+def _tree_theorem(K):
+    """Markov chain tree theorem, by brute force: pi_r is proportional to the
+    sum, over all spanning trees directed towards r, of the product of their
+    rates (K[i][j]: rate from j into i)."""
+    n = len(K)
+    weight = []
+    for root in range(n):
+        others = [v for v in range(n) if v != root]
+        total = Fraction(0)
+        for succ in itertools.product(range(n), repeat=n - 1):
+            nxt = dict(zip(others, succ))
+            if any(nxt[v] == v for v in others):
+                continue
+            ok = True
+            for v in others:
+                u, steps = v, 0
+                while u != root and steps < n:
+                    u, steps = nxt[u], steps + 1
+                ok = ok and u == root
+            if ok:
+                prod = Fraction(1)
+                for v in others:
+                    prod *= K[nxt[v]][v]
+                total += prod
+        weight.append(total)
+    z = sum(weight)
+    return [wt / z for wt in weight]
 
 
-def test_small_dense_chain_exact_rational():
-    rng = np.random.default_rng(7)
-    n = 5
+@pytest.mark.parametrize("n,seed", [(4, 7), (5, 8)])
+def test_small_dense_chain_tree_theorem(n, seed):
+    rng = np.random.default_rng(seed)
     F = rng.integers(1, 9, size=(n, n)).astype(np.float64) / 16.0
+    F[rng.integers(0, n), rng.integers(0, n)] = 0.0        # one missing edge (or a diagonal)
     W = rw.start_weights(F)
-    Kf = [[Fraction(F[i, j]) / Fraction(W[j]) for j in range(n)] for i in range(n)]
-    want = np.array([float(v) for v in _exact_stationary(Kf)])
+    K = [[Fraction(F[i, j]) / Fraction(W[j]) for j in range(n)] for i in range(n)]
+    want = np.array([float(v) for v in _tree_theorem(K)])
     pi = rw.steady_state(F, list(range(n)))
-    assert np.allclose(pi, want, rtol=1e-13, atol=0)
+    assert np.array_equal(pi, want)              # both exact, rounded once
+
+
+def test_tiny_components_keep_their_digits():
+    """A birth-death chain whose stationary law spans 40 decades: every
+    component comes out to a few ulps of the closed form."""
+    n = 30
+    lam = np.full(n, 0.01)
+    mu = np.full(n, 0.25)
+    K = np.zeros((n, n))
+    for i in range(n - 1):
+        K[i + 1, i] = lam[i]
+        K[i, i + 1] = mu[i + 1]
+    F = _flux_from_rates(K, np.ones(n))
+    pi = rw.steady_state(F, list(range(n)))
+    want = cf.chain_stationary(lam, np.append(0.0, mu[1:]))
+    assert pi[-1] < 1e-40
+    assert np.allclose(pi, want, rtol=1e-12, atol=0)
 
 
 def test_component_selection_and_invariants():
