@@ -121,6 +121,10 @@ typedef struct {
     int32_t joint_width;       /*   joint_bins - 1), first species fastest          */
     int32_t record_iters;      /* keep the resampled ensemble of this many          */
                                /*   iterations on the device (committor training)   */
+    int32_t rw_period;         /* steady-state reweighting (Sec. II.B.2, Eq. ss)    */
+                               /*   after every rw_period-th iteration; 0: none.    */
+                               /*   Needs n_bins <= 512 and grid bins (no learned   */
+                               /*   committor bins, no batches)                     */
 } we_params;
 
 /* Device bytes a sim needs (walker buffers, series, scratch). */
@@ -206,6 +210,28 @@ WE_API we_status we_counters(we_sim *s, int64_t *events, int64_t *segments,
 /* Per-iteration reactions fired, summed over runs, for iterations
  * [first, first+count).  Synchronous. */
 WE_API we_status we_events_series(we_sim *s, int32_t first, int32_t count, int64_t *out);
+
+/* ---------------------------------------------------------------- reweighting
+ * Steady-state reweighting (Sec. II.B.2, Eq. ss), on when rw_period > 0.
+ * Flux matrix: F[i][j] adds, every interval after the first and walker by
+ * walker in slot order, the weight of each walker that started the interval
+ * in bin j and ended it in bin i (after recycling).  W_j = sum_i F[i][j];
+ * the rates are k_ij = F[i][j] / W_j.  After the resampling of iteration t
+ * with (t + 1) % rw_period == 0, the bins that are occupied and have
+ * W_j > 0 are candidates; the strongly connected component (edges j -> i
+ * where F[i][j] > 0) of the candidate holding the most weight (ties: the
+ * lowest bin) gets the solution pi of Eq. ss on it: its walkers are
+ * rescaled so that bin a holds pi_a / sum(pi) of the component's weight.
+ * The component keeps its total weight; other bins are unchanged; a
+ * one-bin component changes nothing (the event counts as skipped). */
+
+/* Run `run`'s flux matrix so far: out[i * n_bins + j] = F[i][j] (n_bins^2
+ * doubles).  WE_EINVAL without reweighting.  Synchronous. */
+WE_API we_status we_rw_flux_matrix(we_sim *s, int32_t run, double *out);
+
+/* Reweighting events of run `run` so far that rescaled weights (applied)
+ * and that changed nothing (skipped).  Synchronous. */
+WE_API we_status we_rw_counts(we_sim *s, int32_t run, int32_t *applied, int32_t *skipped);
 
 /* ---------------------------------------------------------------- learned bins
  * A committor q(x) ~ P(reach B before A | x), learned from the sim's own

@@ -19,7 +19,7 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libwe.so")
 
-SOURCES = ["we_runtime.hip", "work_queue.hip", "ssa_lane.hip", "ssa_wave.hip", "we_resample.hip",
+SOURCES = ["we_runtime.hip", "work_queue.hip", "ssa_lane.hip", "ssa_wave.hip", "we_resample.hip", "reweight.hip",
            "committor.hip", "batch.hip"]
 
 

@@ -698,6 +698,8 @@ extern "C" we_status we_train_committor(we_sim *s, const we_train_params *tp, fl
 extern "C" we_status we_use_committor_bins(we_sim *s, int32_t enable) {
     if (!s) return we_fail(WE_EINVAL, "NULL sim");
     if (enable && !s->cm.trained) return we_fail(WE_ESTATE, "no trained committor");
+    if (enable && s->args.rw_period > 0)
+        return we_fail(WE_EINVAL, "reweighting needs fixed grid bins, not learned ones");
     if (s->graph_exec) return we_fail(WE_ESTATE, "recapture the graph after switching bins");
     s->cm.active = enable != 0;
     return WE_OK;

@@ -108,6 +108,11 @@ struct SimArgs {
     int32_t queue_stats;                 // 1: resampling gathers the per-bin event statistics
     int32_t place_rows;                  // resampling: rows of per-bin cursors in LDS, one per
                                          //   wave that places walkers (at least 1)
+    // steady-state reweighting (off when rw_period == 0)
+    int32_t rw_period;
+    double *rw_F;                        // [n_runs][n_bins][n_bins] flux matrix F[i][j]
+    double *rw_R;                        // [n_runs][n_bins][n_bins] solve scratch (null: in LDS)
+    int32_t *rw_stat;                    // [n_runs][2] events applied, skipped
     float *ev_bin;                       // [n_bins] events of the walkers that ended in each bin
     int32_t *n_bin;                      // [n_bins] walkers that ended in each bin
     int32_t seg_rep;                     // counters per bin (spread over replicas, picked by run,

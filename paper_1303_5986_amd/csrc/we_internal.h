@@ -99,6 +99,10 @@ hipError_t launch_work_queue(const SimArgs &a, hipStream_t st);
 hipError_t launch_ssa_wave(const SimArgs &a, int32_t *xs, hipStream_t st);
 bool lane_kernel_fits(int32_t S, int32_t R, int32_t max_delta);
 bool wave_kernel_fits(int32_t S, int32_t R);
+// reweight.hip
+#define WE_RW_MAX_BINS 512
+bool rw_solve_in_lds(int32_t n_bins);
+hipError_t launch_reweight(const SimArgs &a, double *w_nxt, hipStream_t st);
 
 // committor.hip
 hipError_t committor_record(we_sim *s, hipStream_t st);

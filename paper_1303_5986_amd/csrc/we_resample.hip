@@ -148,6 +148,11 @@ __device__ __forceinline__ double wave_min(double v) {
     return fmin(fmin(rs_readlane(v, 0), rs_readlane(v, 16)), fmin(rs_readlane(v, 32), rs_readlane(v, 48)));
 }
 
+__device__ __forceinline__ int32_t wave_min_i32(int32_t v) {
+    for (int d = 32; d > 0; d >>= 1) v = min(v, __shfl_xor(v, d, 64));
+    return v;
+}
+
 __device__ __forceinline__ int32_t wave_excl_scan(int32_t v, int lane, int32_t *total) {
     int32_t x = v;
     for (int d = 1; d < 64; d <<= 1) {
@@ -219,6 +224,40 @@ __device__ void split_bin(const RunWork<Idx> &wk, int32_t p0, int32_t nb, int32_
             out.obin[o] = b;
             ++o;
         }
+    }
+}
+
+// Steady-state reweighting's flux matrix (Sec. II.B.2): row `Frow` (end bin
+// b) gains, walker by walker in slot order, the weight of each of the bin's
+// walkers in the column of its start bin (held in aux).  One start bin at a
+// time, ascending; each column is read, added to in slot order and written
+// back by this wave alone.
+template <class Idx>
+__device__ void rw_flux_bin(double *__restrict__ Frow, const RunWork<Idx> &wk, int32_t p0, int32_t nb,
+                            int lane) {
+    int32_t jprev = -1;
+    for (;;) {
+        int32_t jm = INT32_MAX;
+        for (int32_t q = lane; q < nb; q += 64) {
+            const int32_t j = (int32_t)wk.aux[p0 + q];
+            if (j > jprev) jm = min(jm, j);
+        }
+        jm = wave_min_i32(jm);
+        if (jm == INT32_MAX) break;
+        double acc = Frow[jm];
+        for (int32_t c0 = 0; c0 < nb; c0 += 64) {
+            const int32_t q = c0 + lane;
+            const bool m = q < nb && (int32_t)wk.aux[p0 + q] == jm;
+            const double wv = m ? wk.w[p0 + q] : 0.0;
+            unsigned long long mk = __ballot(m);
+            while (mk) {
+                const int l = __ffsll((long long)mk) - 1;
+                acc = acc + rs_readlane(wv, l);
+                mk &= mk - 1ull;
+            }
+        }
+        if (lane == 0) Frow[jm] = acc;
+        jprev = jm;
     }
 }
 
@@ -635,7 +674,15 @@ __device__ void resample_run_t(const SimArgs &a, const double *__restrict__ w_cu
         }
     }
     __syncthreads();
-    for (int32_t p = tid; p < n; p += nthr) wk.w[p] = wr[wk.list[p]];
+    // flux matrix of reweighting: from the second interval on (the first
+    // one's walkers carry no bin yet); the start bins go to aux, which only
+    // the split/merge of the same bin uses afterwards
+    const bool rw_acc = a.rw_F != nullptr && iter >= 1u;
+    for (int32_t p = tid; p < n; p += nthr) {
+        const int32_t k = wk.list[p];
+        wk.w[p] = wr[k];
+        if (rw_acc) wk.aux[p] = (Idx)a.bin[base + k];
+    }
     __syncthreads();
 
     // split / merge: one wave per bin
@@ -649,6 +696,7 @@ __device__ void resample_run_t(const SimArgs &a, const double *__restrict__ w_cu
         const int32_t nb = uni(cnt[b]);
         if (nb == 0) continue;
         const int32_t p0 = uni(start[b]), o0 = uni(ostart[b]);
+        if (rw_acc) rw_flux_bin(a.rw_F + ((size_t)run * NB + b) * NB, wk, p0, nb, lane);
         if (nb == M) {
             for (int32_t q = lane; q < nb; q += 64) {
                 out.orig[o0 + q] = wk.list[p0 + q];

@@ -250,12 +250,13 @@ struct Layout {
 // Order of the pieces in the workspace; make_layout and we_init agree on it.
 enum Piece { P_X0, P_X1, P_W0, P_W1, P_BIN, P_ORIG, P_N, P_EVW, P_FLUX, P_EVI, P_SBIN, P_SREC,
              P_SLIST, P_SW, P_SCNT, P_HIST, P_SEEDS, P_BCOEF, P_EDGES, P_TCOEF, P_XREC, P_ERR,
-             P_SEG, P_ITER, P_JHIST, P_SCHED, P_SEGLIST, P_QUEUE, P_NZ, P_COUNT };
+             P_SEG, P_ITER, P_JHIST, P_SCHED, P_SEGLIST, P_QUEUE, P_NZ, P_RWF, P_RWR, P_RWS,
+             P_COUNT };
 
 int32_t seg_rep_for(int32_t NB) { return std::min(32, std::max(1, 4096 / NB)); }
 
 Layout make_layout(int32_t S, int32_t NB, int32_t n_runs, int32_t cap, int32_t max_iters,
-                   int32_t nh, int64_t jcells) {
+                   int32_t nh, int64_t jcells, bool rw) {
     Layout L;
     const size_t W = (size_t)n_runs * cap;
     L.add(4 * W * S); L.add(4 * W * S);
@@ -280,6 +281,10 @@ Layout make_layout(int32_t S, int32_t NB, int32_t n_runs, int32_t cap, int32_t m
     L.add(8 * (size_t)n_runs * NB);
     L.add(8);
     L.add(4 * 2 * (size_t)S);
+    const size_t nb2 = (size_t)NB * NB;
+    L.add(rw ? 8 * (size_t)n_runs * nb2 : 0);
+    L.add(rw && !rw_solve_in_lds(NB) ? 8 * (size_t)n_runs * nb2 : 0);
+    L.add(rw ? 4 * 2 * (size_t)n_runs : 0);
     return L;
 }
 
@@ -311,6 +316,11 @@ we_status check_params(const we_network *net, const we_grid *g, const we_params 
         return fail(WE_EINVAL, "unknown kernel");
     if (p->n_joint < 0 || p->n_joint > 5) return fail(WE_EINVAL, "n_joint must be in [0, 5]");
     if (p->record_iters < 0) return fail(WE_EINVAL, "record_iters must be >= 0");
+    if (p->rw_period < 0) return fail(WE_EINVAL, "rw_period must be >= 0");
+    if (p->rw_period > 0 && g->n_bins > WE_RW_MAX_BINS)
+        return fail(WE_EINVAL, "reweighting needs n_bins <= 512");
+    if (p->rw_period > 0 && (int64_t)p->n_runs * g->n_bins * g->n_bins > ((int64_t)1 << 31))
+        return fail(WE_EINVAL, "reweighting: n_runs * n_bins^2 too large");
     if (p->n_joint > 0) {
         if (!p->joint_species || p->joint_bins < 1 || p->joint_width < 1)
             return fail(WE_EINVAL, "joint histogram needs species, bins >= 1, width >= 1");
@@ -340,7 +350,7 @@ extern "C" we_status we_workspace_size(const we_network *net, const we_grid *g, 
     if (!bytes) return fail(WE_EINVAL, "bytes is NULL");
     const int32_t nh = p->hist_hi >= p->hist_lo ? p->hist_hi - p->hist_lo + 1 : 0;
     *bytes = make_layout(net->S, g->n_bins, p->n_runs, p->m_targ * g->n_bins,
-                         std::max(p->max_iters, 1), nh, joint_cells(p)).total;
+                         std::max(p->max_iters, 1), nh, joint_cells(p), p->rw_period > 0).total;
     return WE_OK;
 }
 
@@ -363,7 +373,7 @@ extern "C" we_status we_init(const we_network *net, const we_grid *g, const we_p
         return fail(WE_EINVAL, "network too large for the wave-per-walker kernel");
 
     const int64_t jcells = joint_cells(p);
-    Layout L = make_layout(S, NB, n_runs, cap, max_iters, nh, jcells);
+    Layout L = make_layout(S, NB, n_runs, cap, max_iters, nh, jcells, p->rw_period > 0);
     we_sim *s = new we_sim();
     s->net = net;
     s->stream = (hipStream_t)hip_stream;
@@ -419,6 +429,10 @@ extern "C" we_status we_init(const we_network *net, const we_grid *g, const we_p
     a.jhist = (double *)at(P_JHIST);
     a.queue_stats = 1;
     a.place_rows = resample_place_rows(a, n_runs);
+    a.rw_period = p->rw_period;
+    a.rw_F = p->rw_period > 0 ? (double *)at(P_RWF) : nullptr;
+    a.rw_R = p->rw_period > 0 && !rw_solve_in_lds(NB) ? (double *)at(P_RWR) : nullptr;
+    a.rw_stat = p->rw_period > 0 ? (int32_t *)at(P_RWS) : nullptr;
     a.ev_bin = (float *)at(P_SCHED);
     a.n_bin = (int32_t *)at(P_SCHED) + NB;
     a.seg_rep = seg_rep_for(NB);
@@ -536,6 +550,10 @@ we_status we_sim_bookkeeping(we_sim *s, hipStream_t st, hipEvent_t *ev) {
     }
     e = launch_resample(a, s->x[c], s->w[c], s->x[nx], s->w[nx], st);
     if (e != hipSuccess) return hip_fail(e, "resample launch");
+    if (a.rw_period > 0) {
+        e = launch_reweight(a, s->w[nx], st);
+        if (e != hipSuccess) return hip_fail(e, "reweight launch");
+    }
     if (ev) HIP_TRY(hipEventRecord(ev[1], st));
     if (a.nh > 0 || a.n_joint > 0) {
         e = launch_observe(a, s->x[nx], s->w[nx], st);
@@ -739,6 +757,30 @@ extern "C" we_status we_events_series(we_sim *s, int32_t first, int32_t count, i
         for (int32_t r = 0; r < s->n_runs; ++r) acc += buf[(size_t)r * s->max_iters + first + i];
         out[i] = acc;
     }
+    return WE_OK;
+}
+
+extern "C" we_status we_rw_flux_matrix(we_sim *s, int32_t run, double *out) {
+    if (!s || !out) return fail(WE_EINVAL, "NULL argument");
+    if (!s->args.rw_F) return fail(WE_EINVAL, "reweighting is off");
+    if (run < 0 || run >= s->n_runs) return fail(WE_EINVAL, "run out of range");
+    we_status st = read_err(s);
+    if (st != WE_OK) return st;
+    const size_t nb2 = (size_t)s->NB * s->NB;
+    HIP_TRY(hipMemcpy(out, s->args.rw_F + (size_t)run * nb2, 8 * nb2, hipMemcpyDeviceToHost));
+    return WE_OK;
+}
+
+extern "C" we_status we_rw_counts(we_sim *s, int32_t run, int32_t *applied, int32_t *skipped) {
+    if (!s) return fail(WE_EINVAL, "NULL sim");
+    if (!s->args.rw_stat) return fail(WE_EINVAL, "reweighting is off");
+    if (run < 0 || run >= s->n_runs) return fail(WE_EINVAL, "run out of range");
+    we_status st = read_err(s);
+    if (st != WE_OK) return st;
+    int32_t c[2] = {0, 0};
+    HIP_TRY(hipMemcpy(c, s->args.rw_stat + 2 * (size_t)run, 8, hipMemcpyDeviceToHost));
+    if (applied) *applied = c[0];
+    if (skipped) *skipped = c[1];
     return WE_OK;
 }
 

@@ -27,7 +27,8 @@ EXPORTED = [
     "we_create_network", "we_destroy_network", "we_workspace_size", "we_init", "we_set_ensemble",
     "we_step_intervals", "we_graph_capture", "we_graph_replay", "we_synchronize", "we_get_walkers",
     "we_histogram", "we_histogram_accum", "we_joint_histogram", "we_flux", "we_mfpt",
-    "we_counters", "we_events_series", "we_profile", "we_profile_read",
+    "we_counters", "we_events_series", "we_rw_flux_matrix", "we_rw_counts", "we_profile",
+    "we_profile_read",
     "we_train_committor", "we_use_committor_bins", "we_committor_eval", "we_committor_state",
     "we_record_labels", "we_get_record", "we_mlp_loss_grad", "we_adam_step",
     "we_batch_create", "we_batch_step", "we_batch_graph_capture", "we_batch_graph_replay",
@@ -60,7 +61,7 @@ class _Params(C.Structure):
                 ("tgt_thr", C.c_double), ("x_rec", C.c_void_p), ("hist_species", C.c_int32),
                 ("hist_lo", C.c_int32), ("hist_hi", C.c_int32), ("n_joint", C.c_int32),
                 ("joint_species", C.c_void_p), ("joint_bins", C.c_int32), ("joint_width", C.c_int32),
-                ("record_iters", C.c_int32)]
+                ("record_iters", C.c_int32), ("rw_period", C.c_int32)]
 
 
 class _TrainParams(C.Structure):
@@ -105,6 +106,8 @@ def load_library(path: str = LIB_PATH):
     L.we_mfpt.argtypes = [vp, i32, P(f64), P(f64), P(f64)]
     L.we_counters.argtypes = [vp, P(i64), P(i64), P(i32)]
     L.we_events_series.argtypes = [vp, i32, i32, vp]
+    L.we_rw_flux_matrix.argtypes = [vp, i32, vp]
+    L.we_rw_counts.argtypes = [vp, i32, P(i32), P(i32)]
     L.we_profile.argtypes = [vp, i32]
     L.we_profile_read.argtypes = [vp, P(f64), P(f64), P(f64), P(i64)]
     L.we_train_committor.argtypes = [vp, vp, vp, P(i32)]
@@ -183,7 +186,7 @@ class Sim:
                  recycle: bool = False, tgt_coef=None, tgt_thr: float = 0.0, x_rec=None,
                  hist_species: int = 0, hist_lo: int = 0, hist_hi: int = -1,
                  joint_species: Sequence[int] = (), joint_bins: int = 16, joint_width: int = 64,
-                 record_iters: int = 0, device=None):
+                 record_iters: int = 0, rw_period: int = 0, device=None):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("no HIP device: libwe.so runs on MI355X only")
@@ -214,7 +217,7 @@ class Sim:
                               _ptr(k["tgt"]), float(tgt_thr), _ptr(k["xrec"]),
                               int(hist_species), int(hist_lo), int(hist_hi),
                               len(joint_species), k["joint"].ctypes.data, int(joint_bins),
-                              int(joint_width), int(record_iters))
+                              int(joint_width), int(record_iters), int(rw_period))
         self.n_joint = len(joint_species)
         self.joint_cells = int(joint_bins) ** self.n_joint if self.n_joint else 0
         self.nh = hist_hi - hist_lo + 1 if hist_hi >= hist_lo else 0
@@ -292,6 +295,19 @@ class Sim:
         m, f, e = C.c_double(), C.c_double(), C.c_double()
         _check(load_library().we_mfpt(self.handle, discard, C.byref(m), C.byref(f), C.byref(e)))
         return m.value, f.value, e.value
+
+    def rw_flux_matrix(self, run: int) -> np.ndarray:
+        """Reweighting's flux matrix of run `run`: F[i, j], weight moved
+        from bin j into bin i."""
+        out = np.zeros(self.n_bins * self.n_bins, np.float64)
+        _check(load_library().we_rw_flux_matrix(self.handle, run, _ptr(out)))
+        return out.reshape(self.n_bins, self.n_bins)
+
+    def rw_counts(self, run: int):
+        """(applied, skipped) reweighting events of run `run`."""
+        ap, sk = C.c_int32(), C.c_int32()
+        _check(load_library().we_rw_counts(self.handle, run, C.byref(ap), C.byref(sk)))
+        return ap.value, sk.value
 
     def counters(self):
         ev, sg, it = C.c_int64(), C.c_int64(), C.c_int32()
@@ -383,7 +399,7 @@ class Sim:
 
 def sim_from_config(cfg, *, kernel: int = WE_KERNEL_AUTO, max_iters: Optional[int] = None,
                     network: Optional[Network] = None, joint: bool = False,
-                    record_iters: int = 0) -> Sim:
+                    record_iters: int = 0, rw_period: int = 0) -> Sim:
     """Build a Sim from a workloads.WEConfig."""
     net = network if network is not None else Network(cfg.net)
     return Sim(net, cfg.bin_coef, cfg.edges, tau=cfg.tau, m_targ=cfg.m_targ, seeds=cfg.seeds,
@@ -392,7 +408,7 @@ def sim_from_config(cfg, *, kernel: int = WE_KERNEL_AUTO, max_iters: Optional[in
                x_rec=cfg.x_rec, hist_species=cfg.hist_species, hist_lo=cfg.hist_lo,
                hist_hi=cfg.hist_hi,
                joint_species=getattr(cfg, "joint_species", ()) if joint else (),
-               record_iters=record_iters)
+               record_iters=record_iters, rw_period=rw_period)
 
 
 def mlp_loss_grad(n_in: int, params, feat, x, y):
