@@ -260,6 +260,106 @@ def experiment_toggle_mfpt(args):
     print(json.dumps(out), flush=True)
 
 
+def schlogl_mfpt_exact(a: int = 82, b: int = 563, top: int = 1500) -> float:
+    """Mean first passage time a -> b of the Schloegl birth-death chain
+    (combinatorial mass action, constants of Sec. III.B): with the chain's
+    stationary law pi, T = sum_{k=a}^{b-1} P(X <= k) / (lambda_k pi_k)."""
+    from paper_1303_5986_amd import workloads as wl
+    p = wl.SCHLOGL_K
+    x = np.arange(top + 1, dtype=np.float64)
+    lam = p["k1"] * p["A"] * x * (x - 1) / 2.0 + p["k3"] * p["B"]
+    mu = p["k2"] * x * (x - 1) * (x - 2) / 6.0 + p["k4"] * x
+    logpi = np.zeros(top + 1)
+    for k in range(1, top + 1):
+        logpi[k] = logpi[k - 1] + np.log(lam[k - 1]) - np.log(mu[k])
+    pi = np.exp(logpi - logpi.max())
+    pi /= pi.sum()
+    cum = np.cumsum(pi)
+    return float(sum(cum[k] / (lam[k] * pi[k]) for k in range(a, b)))
+
+
+def _half_window_err(flux, tau, ref):
+    """RMS relative error over runs of the MFPT estimate tau / mean(flux) with
+    the mean over iterations [t // 2, t], for every t."""
+    f = np.asarray(flux, np.float64)
+    csum = np.concatenate([np.zeros((f.shape[0], 1)), np.cumsum(f, axis=1)], axis=1)
+    t = np.arange(1, f.shape[1] + 1)
+    lo = t // 2
+    mean = (csum[:, t] - csum[:, lo]) / (t - lo)
+    with np.errstate(divide="ignore"):
+        mfpt = np.where(mean > 0, tau / mean, np.inf)
+    return np.sqrt(np.mean((mfpt / ref - 1.0) ** 2, axis=0))
+
+
+def _pooled_err(flux, tau, ref):
+    """Relative error of the MFPT estimate from all runs together: tau / the
+    mean recycled weight over runs and iterations [t // 2, t], for every t."""
+    f = np.asarray(flux, np.float64).mean(axis=0, keepdims=True)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        return np.abs(_half_window_err(f, tau, ref))
+
+
+def experiment_schlogl_rw(args):
+    """The Schloegl flux experiment of Sec. III.B at its published size (80
+    bins of width 10, 32 walkers per bin, tau = 0.1, recycling X >= 563 ->
+    X = 82), with steady-state reweighting every 100, 5 or 2 iterations or
+    none: GPU-seconds (and iterations) until the replicas' MFPT estimates stay
+    within a relative error of the exact MFPT."""
+    import dataclasses
+
+    import torch
+    from paper_1303_5986_amd import we, workloads as wl
+
+    total, chunk = args.exp_iters, 10
+    runs = args.rw_runs
+    base = dataclasses.replace(wl.schlogl_config(n_runs=runs, seed0=301, n_iters=total),
+                               edges=wl.uniform_edges(0.0, 800.0, 80), m_targ=32, tau=0.1)
+    exact = schlogl_mfpt_exact()
+    out = {"metric": "GPU-seconds to MFPT rel-err 5%, steady-state reweighting periods",
+           "workload": f"Schloegl, 80 bins x 32 walkers, tau 0.1, {runs} replicas, X>=563 -> X=82",
+           "exact_mfpt": exact, "estimator": "tau / mean recycled weight over iterations [t/2, t], "
+           "RMS relative error over replicas", "variants": []}
+    for period, reset in ((0, False), (100, False), (5, False), (2, False), (100, True), (5, True),
+                          (2, True)):
+        sim = we.sim_from_config(base, kernel=we.WE_KERNEL_LANE, max_iters=total, rw_period=period,
+                                 rw_reset=reset)
+        sim.graph_capture(chunk)
+        torch.cuda.synchronize()
+        gpu, done, times = 0.0, 0, []
+        while done + chunk <= total:
+            t0 = time.perf_counter()
+            sim.graph_replay(1)
+            sim.synchronize()
+            gpu += time.perf_counter() - t0
+            done += chunk
+            times.append(gpu)
+        flux = np.stack([sim.flux(r, 0, done) for r in range(runs)])
+        at = np.arange(chunk, done + 1, chunk) - 1
+        res = {"rw_period": period, "rw_reset": reset, "iterations": done, "gpu_s_total": gpu,
+               "events": sim.counters()[0]}
+        if period:
+            ap = [sim.rw_counts(r) for r in range(runs)]
+            res["events_applied"] = int(sum(a for a, _ in ap))
+            res["events_skipped"] = int(sum(b for _, b in ap))
+        for name, err in (("pooled", _pooled_err(flux, base.tau, exact)),
+                          ("per_replica_rms", _half_window_err(flux, base.tau, exact))):
+            r = {"final_rel_err": float(err[-1]),
+                 "rel_err_at": {str(i + 1): round(float(err[i]), 4)
+                                for i in (29, 49, 99, 199, 499, done - 1) if i < done}}
+            for thr in (0.05, 0.1, 0.2):
+                r[f"gpu_s_to_{int(thr * 100)}pct"] = _time_to(err[at], np.array(times), thr)
+                ok = err <= thr
+                r[f"iters_to_{int(thr * 100)}pct"] = (None if not ok[-1] else
+                                                     int(np.flatnonzero(~ok)[-1] + 2 if (~ok).any() else 1))
+            res[name] = r
+        out["variants"].append(res)
+        print(json.dumps({"rw_period": period, "rw_reset": reset,
+                          "pooled_iters_to_5pct": res["pooled"]["iters_to_5pct"],
+                          "pooled_gpu_s_to_5pct": res["pooled"]["gpu_s_to_5pct"]}),
+              file=sys.stderr, flush=True)
+    print(json.dumps(out), flush=True)
+
+
 def experiment_batch(args):
     """64 independent WE runs on seeded networks of 8..3680 reactions and
     256..8192 walker slots: one batch (persistent propagation launches,
@@ -325,7 +425,9 @@ def main():
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB five times "
                          "(reference kernel for scaling the HBM byte counters)")
-    ap.add_argument("--experiment", default="", choices=["", "toggle_mfpt", "batch"])
+    ap.add_argument("--experiment", default="", choices=["", "toggle_mfpt", "batch", "schlogl_rw"])
+    ap.add_argument("--rw-runs", type=int, default=32,
+                    help="replicas in the reweighting experiment")
     ap.add_argument("--large-runs", type=int, default=1,
                     help="independent replicas of the large network (the configuration is 1; "
                          "more fill the chip and show the wave kernel's throughput ceiling)")
@@ -348,6 +450,9 @@ def main():
         return
     if args.experiment == "batch":
         experiment_batch(args)
+        return
+    if args.experiment == "schlogl_rw":
+        experiment_schlogl_rw(args)
         return
     if args.calibrate_copy:
         import torch

@@ -125,6 +125,9 @@ typedef struct {
                                /*   after every rw_period-th iteration; 0: none.    */
                                /*   Needs n_bins <= 512 and grid bins (no learned   */
                                /*   committor bins, no batches)                     */
+    int32_t rw_reset;          /* 1: the flux matrix restarts after every event, so */
+                               /*   each event uses only the intervals since the    */
+                               /*   last one; 0: it accumulates from the start      */
 } we_params;
 
 /* Device bytes a sim needs (walker buffers, series, scratch). */
@@ -223,7 +226,8 @@ WE_API we_status we_events_series(we_sim *s, int32_t first, int32_t count, int64
  * lowest bin) gets the solution pi of Eq. ss on it: its walkers are
  * rescaled so that bin a holds pi_a / sum(pi) of the component's weight.
  * The component keeps its total weight; other bins are unchanged; a
- * one-bin component changes nothing (the event counts as skipped). */
+ * one-bin component changes nothing (the event counts as skipped).  With
+ * rw_reset, F is cleared after every event (applied or skipped). */
 
 /* Run `run`'s flux matrix so far: out[i * n_bins + j] = F[i][j] (n_bins^2
  * doubles).  WE_EINVAL without reweighting.  Synchronous. */

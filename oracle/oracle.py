@@ -159,7 +159,8 @@ class OracleWE:
     outputs.  The initial ensemble is m_targ walkers at x0 with weight
     1/m_targ each, unless init_x/init_w are given."""
 
-    def __init__(self, cfg, seed: int, init_x=None, init_w=None, rw_period: int = 0):
+    def __init__(self, cfg, seed: int, init_x=None, init_w=None, rw_period: int = 0,
+                 rw_reset: bool = False):
         self.cfg = cfg
         self.onet = OracleNet(cfg.net)
         st = self.onet.validate()
@@ -202,6 +203,7 @@ class OracleWE:
         self.segments: List[int] = []
         # steady-state reweighting (reweight.py): every rw_period iterations
         self.rw_period = int(rw_period)
+        self.rw_reset = bool(rw_reset)
         self.end_bin = np.zeros(cap, np.int32)
         self.rw_F = np.zeros((cfg.n_bins, cfg.n_bins), np.float64)
         self.rw_applied = 0
@@ -236,6 +238,8 @@ class OracleWE:
                         self.rw_applied += 1
                     else:
                         self.rw_skipped += 1
+                    if self.rw_reset:
+                        self.rw_F[:] = 0.0
             self.iter += 1
             self.flux.append(flux.value)
             self.events.append(ev.value)

@@ -22,6 +22,10 @@ Readings taken where the paper is silent (each listed in the design notes):
        dynamics, so all intervals estimate the same k_ij.  The walkers of the
        very first interval have no bin yet (they are binned by the first
        resampling), so accumulation starts with the second interval.
+       Optionally (rw_reset) F starts over after every event, so that each
+       event uses only the intervals since the previous one: the rates then
+       come from an ensemble that earlier events have already brought closer
+       to steady state, which is how repeated application converges.
   RW2  W_j = sum_i F[i, j] (ascending i): the weight that started intervals in
        bin j; k_ij = F[i, j] / W_j for i != j.
   RW3  A reweighting event happens after the resampling of every iteration t

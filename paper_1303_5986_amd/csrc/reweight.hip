@@ -23,7 +23,8 @@
 //      set every s_m and pi_m is positive.
 //   5. Bin a's walkers are scaled by (pi_a / Z * W_A) / w_a, Z = sum pi,
 //      W_A the component's current weight, which it keeps; every other bin
-//      is scaled by 1 (exactly unchanged).
+//      is scaled by 1 (exactly unchanged).  Optionally F is cleared, so that
+//      the next event sees only the intervals after this one.
 // The rate matrix lives in LDS when it fits, else in a per-run global
 // scratch.  Sums over lanes use fixed shuffle trees, so the result is
 // deterministic (graph replays equal eager runs bit for bit).
@@ -281,9 +282,14 @@ __global__ __launch_bounds__(RW_THREADS) void we_reweight_kernel(SimArgs a, doub
         }
     }
 
-    // 5. rescale
+    // 5. rescale; with rw_reset the flux matrix starts over (every read of
+    // it lies before the last barrier)
     if (ok)
         for (int32_t k = tid; k < n; k += nthr) w[k] = w[k] * fac[bins[k]];
+    if (a.rw_reset) {
+        double *Fw = a.rw_F + (size_t)run * NB * NB;
+        for (size_t t = tid; t < (size_t)NB * NB; t += nthr) Fw[t] = 0.0;
+    }
     if (tid == 0) a.rw_stat[2 * (size_t)run + (ok ? 0 : 1)] += 1;
 }
 

@@ -110,6 +110,7 @@ struct SimArgs {
                                          //   wave that places walkers (at least 1)
     // steady-state reweighting (off when rw_period == 0)
     int32_t rw_period;
+    int32_t rw_reset;                    // 1: F restarts after every event
     double *rw_F;                        // [n_runs][n_bins][n_bins] flux matrix F[i][j]
     double *rw_R;                        // [n_runs][n_bins][n_bins] solve scratch (null: in LDS)
     int32_t *rw_stat;                    // [n_runs][2] events applied, skipped

@@ -430,6 +430,7 @@ extern "C" we_status we_init(const we_network *net, const we_grid *g, const we_p
     a.queue_stats = 1;
     a.place_rows = resample_place_rows(a, n_runs);
     a.rw_period = p->rw_period;
+    a.rw_reset = p->rw_reset ? 1 : 0;
     a.rw_F = p->rw_period > 0 ? (double *)at(P_RWF) : nullptr;
     a.rw_R = p->rw_period > 0 && !rw_solve_in_lds(NB) ? (double *)at(P_RWR) : nullptr;
     a.rw_stat = p->rw_period > 0 ? (int32_t *)at(P_RWS) : nullptr;

@@ -61,7 +61,7 @@ class _Params(C.Structure):
                 ("tgt_thr", C.c_double), ("x_rec", C.c_void_p), ("hist_species", C.c_int32),
                 ("hist_lo", C.c_int32), ("hist_hi", C.c_int32), ("n_joint", C.c_int32),
                 ("joint_species", C.c_void_p), ("joint_bins", C.c_int32), ("joint_width", C.c_int32),
-                ("record_iters", C.c_int32), ("rw_period", C.c_int32)]
+                ("record_iters", C.c_int32), ("rw_period", C.c_int32), ("rw_reset", C.c_int32)]
 
 
 class _TrainParams(C.Structure):
@@ -186,7 +186,7 @@ class Sim:
                  recycle: bool = False, tgt_coef=None, tgt_thr: float = 0.0, x_rec=None,
                  hist_species: int = 0, hist_lo: int = 0, hist_hi: int = -1,
                  joint_species: Sequence[int] = (), joint_bins: int = 16, joint_width: int = 64,
-                 record_iters: int = 0, rw_period: int = 0, device=None):
+                 record_iters: int = 0, rw_period: int = 0, rw_reset: bool = False, device=None):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("no HIP device: libwe.so runs on MI355X only")
@@ -217,7 +217,7 @@ class Sim:
                               _ptr(k["tgt"]), float(tgt_thr), _ptr(k["xrec"]),
                               int(hist_species), int(hist_lo), int(hist_hi),
                               len(joint_species), k["joint"].ctypes.data, int(joint_bins),
-                              int(joint_width), int(record_iters), int(rw_period))
+                              int(joint_width), int(record_iters), int(rw_period), int(bool(rw_reset)))
         self.n_joint = len(joint_species)
         self.joint_cells = int(joint_bins) ** self.n_joint if self.n_joint else 0
         self.nh = hist_hi - hist_lo + 1 if hist_hi >= hist_lo else 0
@@ -399,7 +399,7 @@ class Sim:
 
 def sim_from_config(cfg, *, kernel: int = WE_KERNEL_AUTO, max_iters: Optional[int] = None,
                     network: Optional[Network] = None, joint: bool = False,
-                    record_iters: int = 0, rw_period: int = 0) -> Sim:
+                    record_iters: int = 0, rw_period: int = 0, rw_reset: bool = False) -> Sim:
     """Build a Sim from a workloads.WEConfig."""
     net = network if network is not None else Network(cfg.net)
     return Sim(net, cfg.bin_coef, cfg.edges, tau=cfg.tau, m_targ=cfg.m_targ, seeds=cfg.seeds,
@@ -408,7 +408,7 @@ def sim_from_config(cfg, *, kernel: int = WE_KERNEL_AUTO, max_iters: Optional[in
                x_rec=cfg.x_rec, hist_species=cfg.hist_species, hist_lo=cfg.hist_lo,
                hist_hi=cfg.hist_hi,
                joint_species=getattr(cfg, "joint_species", ()) if joint else (),
-               record_iters=record_iters, rw_period=rw_period)
+               record_iters=record_iters, rw_period=rw_period, rw_reset=rw_reset)
 
 
 def mlp_loss_grad(n_in: int, params, feat, x, y):

@@ -53,10 +53,11 @@ def _compare(it, r, g, o, exact):
         np.testing.assert_allclose(gw, ow, rtol=RTOL, atol=0, err_msg=f"iter {it} run {r}")
 
 
-def _run(cfg, period, n_iters):
+def _run(cfg, period, n_iters, reset=False):
     we = _we()
-    sim = we.sim_from_config(cfg, kernel=we.WE_KERNEL_LANE, max_iters=n_iters, rw_period=period)
-    ors = [orc.OracleWE(cfg, int(s), rw_period=period) for s in cfg.seeds]
+    sim = we.sim_from_config(cfg, kernel=we.WE_KERNEL_LANE, max_iters=n_iters, rw_period=period,
+                             rw_reset=reset)
+    ors = [orc.OracleWE(cfg, int(s), rw_period=period, rw_reset=reset) for s in cfg.seeds]
     for it in range(n_iters):
         sim.step(1)
         exact = it + 1 < period          # no event has happened yet
@@ -73,12 +74,14 @@ def _run(cfg, period, n_iters):
     return sim, ors
 
 
-@pytest.mark.parametrize("n_bins", [100, 200])
-def test_birth_death_reweighting_matches_oracle(n_bins):
+@pytest.mark.parametrize("n_bins,reset", [(100, False), (200, False), (100, True)])
+def test_birth_death_reweighting_matches_oracle(n_bins, reset):
     """Unit bins from X = 10 (far from the stationary Poisson(40)); 100 bins
-    keep the rate matrix in LDS, 200 bins put it in global memory."""
-    _say(f"case: reweighting, birth-death {n_bins} unit bins, M=4, period 5, 3 runs x 30 iterations")
-    sim, ors = _run(_bd_unit(n_bins, [3, 4, 5]), period=5, n_iters=30)
+    keep the rate matrix in LDS, 200 bins put it in global memory; with
+    reset, each event sees only the intervals since the previous one."""
+    _say(f"case: reweighting, birth-death {n_bins} unit bins, M=4, period 5, reset {reset}, "
+         "3 runs x 30 iterations")
+    sim, ors = _run(_bd_unit(n_bins, [3, 4, 5]), period=5, n_iters=30, reset=reset)
     for r, o in enumerate(ors):
         assert o.rw_applied == 6 and o.rw_skipped == 0
         _, w, _, _ = sim.walkers(r)
