@@ -68,11 +68,13 @@ class _NetStruct(C.Structure):
                 ("reac_ptr", C.c_void_p), ("reac_species", C.c_void_p),
                 ("reac_mult", C.c_void_p), ("chg_ptr", C.c_void_p),
                 ("chg_species", C.c_void_p), ("chg_delta", C.c_void_p),
-                ("rate", C.c_void_p)]
+                ("rate", C.c_void_p), ("hill_species", C.c_void_p), ("hill_n", C.c_void_p),
+                ("hill_K", C.c_void_p)]
 
 
 class _CfgStruct(C.Structure):
     _fields_ = [("n_bins", C.c_int32), ("bin_coef", C.c_void_p), ("edges", C.c_void_p),
+                ("n_bins2", C.c_int32), ("bin_coef2", C.c_void_p), ("edges2", C.c_void_p),
                 ("m_targ", C.c_int32), ("tau", C.c_double), ("seed", C.c_uint64),
                 ("recycle", C.c_int32), ("tgt_coef", C.c_void_p), ("tgt_thr", C.c_double),
                 ("x_rec", C.c_void_p)]
@@ -88,7 +90,14 @@ class OracleNet:
             (net.chg_ptr, np.int32), (net.chg_species, np.int32), (net.chg_delta, np.int32),
             (net.rate, np.float64))]
         k = self._keep
-        self.s = _NetStruct(net.S, net.R, *[a.ctypes.data for a in k])
+        hill = []
+        if getattr(net, "hill_species", None) is not None:
+            hill = [np.ascontiguousarray(net.hill_species, np.int32),
+                    np.ascontiguousarray(net.hill_n, np.int32),
+                    np.ascontiguousarray(net.hill_K, np.float64)]
+            self._keep += hill
+        self.s = _NetStruct(net.S, net.R, *[a.ctypes.data for a in k[:7]],
+                            *([a.ctypes.data for a in hill] if hill else [None, None, None]))
         self.ptr = C.cast(C.pointer(self.s), C.c_void_p)
 
     def validate(self) -> int:
@@ -175,8 +184,16 @@ class OracleWE:
                                           else np.zeros(S), np.float64),
             x_rec=np.ascontiguousarray(cfg.x_rec if cfg.x_rec is not None else cfg.x0, np.int32),
         )
+        two_d = getattr(cfg, "edges2", None) is not None
+        if two_d:
+            self._arrs["bin_coef2"] = np.ascontiguousarray(cfg.bin_coef2, np.float64)
+            self._arrs["edges2"] = np.ascontiguousarray(cfg.edges2, np.float64)
         a = self._arrs
-        self.cs = _CfgStruct(cfg.n_bins, a["bin_coef"].ctypes.data, a["edges"].ctypes.data,
+        n1 = len(cfg.edges) - 1
+        self.cs = _CfgStruct(n1, a["bin_coef"].ctypes.data, a["edges"].ctypes.data,
+                             len(cfg.edges2) - 1 if two_d else 0,
+                             a["bin_coef2"].ctypes.data if two_d else None,
+                             a["edges2"].ctypes.data if two_d else None,
                              cfg.m_targ, cfg.tau, self.seed, int(bool(cfg.recycle)),
                              a["tgt_coef"].ctypes.data, float(cfg.tgt_thr), a["x_rec"].ctypes.data)
         self.cptr = C.cast(C.pointer(self.cs), C.c_void_p)

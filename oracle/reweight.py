@@ -53,8 +53,13 @@ correct digits.)  Written for q_b = pi_b / W_b, every coefficient is a
 double or an exact sum of doubles,
     sum_b F[a, b] q_b - q_a sum_b F[b, a] = 0,   sum_b W_b q_b = 1   (b != a),
 so one power-of-two scale makes the system integer, and fraction-free
-(Bareiss) elimination solves it in Python integers.  Strong connectivity
-comes from scipy's graph routine.  Neither shares code with the device.
+(Bareiss) elimination solves it in Python integers.  That costs O(n^3)
+operations on integers of O(n) words, too slow past ~64 bins; larger sets
+(the two-dimensional grids of Sec. III.C) are solved instead by state
+reduction in FP64 (Grassmann, Taksar and Heyman 1985), whose error is
+entrywise relative (no subtractions), and which the tests pin against the
+exact solver.  Strong connectivity comes from scipy's graph routine.
+Neither shares code with the device.
 """
 from __future__ import annotations
 
@@ -109,13 +114,43 @@ def component_of(F: np.ndarray, cand, pivot: int) -> list:
     return [b for b, l in zip(cand, label) if l == lp]
 
 
+EXACT_MAX = 64
+
+
+def steady_state_gth(F: np.ndarray, active) -> np.ndarray:
+    """Eq. ss on a strongly connected set by state reduction: with
+    P[i, j] = k_ji (rate from i into j), remove the last state m each step,
+    P[i, j] += P[i, m] P[m, j] / s_m with s_m = sum_{j<m} P[m, j]; then
+    pi_0 = 1, pi_m = sum_{i<m} pi_i P[i, m] / s_m; normalised to sum 1."""
+    active = list(active)
+    na = len(active)
+    W = start_weights(F)
+    P = np.zeros((na, na))
+    for a, i in enumerate(active):
+        for b, j in enumerate(active):
+            if a != b:
+                P[b, a] = F[i, j] / W[j]          # rate from j (index b) into i (index a)
+    s = np.zeros(na)
+    for m in range(na - 1, 0, -1):
+        s[m] = P[m, :m].sum()
+        P[:m, :m] += np.outer(P[:m, m], P[m, :m] / s[m])
+    pi = np.zeros(na)
+    pi[0] = 1.0
+    for m in range(1, na):
+        pi[m] = float(pi[:m] @ P[:m, m]) / s[m]
+    return pi / pi.sum()
+
+
 def steady_state(F: np.ndarray, active) -> Optional[np.ndarray]:
     """RW2, RW4: the solution of Eq. ss on a strongly connected set of bins
-    (ascending) with sum 1; None for fewer than two bins."""
+    (ascending) with sum 1; None for fewer than two bins.  Exact (one
+    rounding per component) up to EXACT_MAX bins, state reduction beyond."""
     active = list(active)
     na = len(active)
     if na < 2:
         return None
+    if na > EXACT_MAX:
+        return steady_state_gth(F, active)
     W = start_weights(F)
     vals = [float(F[i, j]) for i in active for j in active] + [float(W[j]) for j in active]
     e_min = min(math.frexp(v)[1] for v in vals if v != 0.0) - 53

@@ -12,6 +12,11 @@
  *  - propensity: a_j = c_j * prod_s C(x_s, nu_js)  -- the combinatorial
  *    mass-action convention; it is the one under which the Schloegl model of
  *    Sec. III.B has its wells at 82 and 563 and its barrier at 256.
+ *  - Hill-type rates (Sec. III.C): a reaction with a repressor r divides
+ *    that by 1 + (x_r / K)^n, evaluated as t = x_r / K, p = t * t * ... * t
+ *    (n factors, left to right), d = 1 + p, a_j = (c_j * h_j) / d.
+ *  - two-dimensional grids (Sec. III.C): bin = b1 + n_bins * b2, each axis
+ *    binned like a one-dimensional grid.
  *  - interval boundary: a reaction fires iff t + dt <= tau; the state is then
  *    held to tau (memorylessness of the exponential waiting time).
  *  - split (Sec. II.B): a bin with 0 < n < M_targ walkers is filled by
@@ -95,7 +100,14 @@ int64_t or_h(const or_net *net, const int32_t *x, int32_t j)
 
 double or_propensity(const or_net *net, const int32_t *x, int32_t j)
 {
-    return net->rate[j] * (double)or_h(net, x, j);
+    double a = net->rate[j] * (double)or_h(net, x, j);
+    if (net->hill_species && net->hill_species[j] >= 0) {
+        const double t = (double)x[net->hill_species[j]] / net->hill_K[j];
+        double p = t;
+        for (int32_t i = 1; i < net->hill_n[j]; ++i) p = p * t;
+        a = a / (1.0 + p);
+    }
+    return a;
 }
 
 int32_t or_validate(const or_net *net)
@@ -112,6 +124,11 @@ int32_t or_validate(const or_net *net)
             order += nu;
         }
         if (order > 3) return OR_EINVAL;
+        if (net->hill_species && net->hill_species[j] >= 0) {
+            if (net->hill_species[j] >= net->S || net->hill_n[j] < 1 || net->hill_n[j] > 8 ||
+                !(net->hill_K[j] > 0.0) || isinf(net->hill_K[j]))
+                return OR_EINVAL;
+        }
         for (int32_t p = net->chg_ptr[j]; p < net->chg_ptr[j + 1]; ++p) {
             int32_t s = net->chg_species[p], d = net->chg_delta[p];
             if (s < 0 || s >= net->S || d == 0) return OR_EINVAL;
@@ -338,7 +355,8 @@ int32_t or_we_iterate(const or_net *net, const or_we_cfg *cfg, uint32_t iter,
                       double *flux_out, int64_t *events_out, int32_t *recycled_out,
                       int32_t *end_bin_out)
 {
-    const int32_t S = net->S, N = *n, M = cfg->m_targ, NB = cfg->n_bins;
+    const int32_t S = net->S, N = *n, M = cfg->m_targ;
+    const int32_t NB1 = cfg->n_bins, NB2 = cfg->n_bins2 > 1 ? cfg->n_bins2 : 1, NB = NB1 * NB2;
     if (N > cap || M * NB > cap) return OR_EINVAL;
     int32_t status = OR_OK;
 
@@ -366,8 +384,11 @@ int32_t or_we_iterate(const or_net *net, const or_we_cfg *cfg, uint32_t iter,
     }
 
     /* 3. bin assignment */
-    for (int32_t k = 0; k < N; ++k)
-        bin[k] = or_bin_of(NB, cfg->edges, or_coord(S, cfg->bin_coef, x + (size_t)k * S));
+    for (int32_t k = 0; k < N; ++k) {
+        bin[k] = or_bin_of(NB1, cfg->edges, or_coord(S, cfg->bin_coef, x + (size_t)k * S));
+        if (NB2 > 1)
+            bin[k] += NB1 * or_bin_of(NB2, cfg->edges2, or_coord(S, cfg->bin_coef2, x + (size_t)k * S));
+    }
     if (end_bin_out) memcpy(end_bin_out, bin, sizeof(int32_t) * (size_t)N);
 
     /* 4. resample bin by bin into a fresh ensemble */

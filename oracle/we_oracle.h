@@ -38,12 +38,17 @@ enum { OR_OK = 0, OR_EINVAL = -1, OR_EOVERFLOW = -5 };
  *   reactants of reaction j: reac_species[reac_ptr[j] .. reac_ptr[j+1]) with
  *   multiplicities reac_mult (1..3, distinct species per reaction);
  *   net change of reaction j: chg_species/chg_delta over chg_ptr;
- *   rate[j]: stochastic rate constant c_j (constant reservoir species folded in). */
+ *   rate[j]: stochastic rate constant c_j (constant reservoir species folded in);
+ *   hill_species (may be NULL): reaction j's propensity is divided by the
+ *   repressive Hill factor 1 + (x_r / hill_K[j])^hill_n[j], r = hill_species[j]
+ *   (-1: none), the Hill-type rates of the switch of Sec. III.C. */
 typedef struct {
     int32_t S, R;
     const int32_t *reac_ptr, *reac_species, *reac_mult;
     const int32_t *chg_ptr, *chg_species, *chg_delta;
     const double *rate;
+    const int32_t *hill_species, *hill_n;
+    const double *hill_K;
 } or_net;
 
 /* WE configuration (the arguments of the WE procedure in Sec. II.B plus the
@@ -52,6 +57,9 @@ typedef struct {
     int32_t n_bins;
     const double *bin_coef;   /* [S]  progress coordinate q(x) = sum_s coef_s x_s  */
     const double *edges;      /* [n_bins+1] strictly increasing; out-of-range clamps */
+    int32_t n_bins2;          /* second grid axis (0 or 1: none); bin = b1 + n_bins*b2 */
+    const double *bin_coef2;  /* [S]                                               */
+    const double *edges2;     /* [n_bins2+1]                                       */
     int32_t m_targ;           /* target walkers per occupied bin                  */
     double tau;               /* WE interval                                       */
     uint64_t seed;            /* Philox key                                        */

@@ -12,6 +12,10 @@ Models:
     and folded into the rate constants.
   * futile cycle (Sec. III.A, Eq. futile): E1 + S1 <-> B1 -> E1 + S2,
     E2 + S2 <-> B2 -> E2 + S1, k_f = 1.0, k_s = 0.1.
+  * the epigenetic switch (Sec. III.C): two genes repressing each other,
+    births at Hill-type rates a1 / (1 + (g2/K2)^n), a2 / (1 + (g1/K1)^m),
+    a1 = 156, a2 = 30, n = 3, m = 1, K1 = K2 = 1, deaths at 1/tau = 1 per
+    copy, on the paper's 15 x 31 two-dimensional bin grid;
   * a synthetic two-gene toggle (8 species, 16 mass-action reactions), and
     synthetic large mass-action networks shaped like the 354-species /
     3680-reaction model of Sec. III.D, both generated from a seed.
@@ -27,12 +31,14 @@ import numpy as np
 
 @dataclasses.dataclass
 class Network:
-    """A mass-action reaction network in CSR form.
+    """A reaction network in CSR form.
 
     reactants of reaction j: reac_species[reac_ptr[j]:reac_ptr[j+1]] with
     multiplicities reac_mult (1..3); net change of reaction j:
     chg_species/chg_delta over chg_ptr; rate[j] is the stochastic rate
-    constant c_j, with constant reservoir species folded in.
+    constant c_j, with constant reservoir species folded in.  Optionally a
+    reaction's mass-action propensity is divided by a repressive Hill factor
+    1 + (x_r / K)^n: hill_species[j] = r (-1: none), hill_n[j], hill_K[j].
     """
 
     S: int
@@ -45,16 +51,28 @@ class Network:
     chg_delta: np.ndarray
     rate: np.ndarray
     names: List[str]
+    hill_species: Optional[np.ndarray] = None
+    hill_n: Optional[np.ndarray] = None
+    hill_K: Optional[np.ndarray] = None
+
+    @property
+    def has_hill(self) -> bool:
+        return self.hill_species is not None and bool((self.hill_species >= 0).any())
 
     @staticmethod
-    def from_reactions(names: Sequence[str],
-                       reactions: Sequence[Tuple[Dict[str, int], Dict[str, int], float]]
-                       ) -> "Network":
-        """Build from (reactants, products, c_j) triples; reactants and
+    def from_reactions(names: Sequence[str], reactions: Sequence[tuple]) -> "Network":
+        """Build from (reactants, products, c_j) triples, or quadruples whose
+        last entry is a Hill factor (species name, n, K); reactants and
         products map species name -> stoichiometric count."""
         idx = {n: i for i, n in enumerate(names)}
         rp, rs, rm, cp, cs, cd, rate = [0], [], [], [0], [], [], []
-        for reac, prod, c in reactions:
+        hs, hn, hk = [], [], []
+        for rx in reactions:
+            reac, prod, c = rx[0], rx[1], rx[2]
+            hill = rx[3] if len(rx) > 3 else None
+            hs.append(idx[hill[0]] if hill else -1)
+            hn.append(int(hill[1]) if hill else 0)
+            hk.append(float(hill[2]) if hill else 0.0)
             for sp in sorted(reac, key=lambda n: idx[n]):
                 rs.append(idx[sp])
                 rm.append(int(reac[sp]))
@@ -71,11 +89,15 @@ class Network:
             cp.append(len(cs))
             rate.append(float(c))
         i32 = lambda a: np.ascontiguousarray(np.asarray(a, dtype=np.int32))
+        any_hill = any(v >= 0 for v in hs)
         return Network(S=len(names), R=len(reactions),
                        reac_ptr=i32(rp), reac_species=i32(rs), reac_mult=i32(rm),
                        chg_ptr=i32(cp), chg_species=i32(cs), chg_delta=i32(cd),
                        rate=np.ascontiguousarray(np.asarray(rate, dtype=np.float64)),
-                       names=list(names))
+                       names=list(names),
+                       hill_species=i32(hs) if any_hill else None,
+                       hill_n=i32(hn) if any_hill else None,
+                       hill_K=np.ascontiguousarray(np.asarray(hk, np.float64)) if any_hill else None)
 
     def order(self, j: int) -> int:
         return int(self.reac_mult[self.reac_ptr[j]:self.reac_ptr[j + 1]].sum())
@@ -84,8 +106,9 @@ class Network:
 @dataclasses.dataclass
 class WEConfig:
     """Everything the WE procedure needs besides the network: the bin grid on
-    a linear progress coordinate, walkers per bin, the interval, the initial
-    state, the recycling target and the seeds of independent runs."""
+    a linear progress coordinate (or on two, bin = b1 + n1 * b2), walkers per
+    bin, the interval, the initial state, the recycling target and the seeds
+    of independent runs."""
 
     name: str
     net: Network
@@ -103,10 +126,20 @@ class WEConfig:
     hist_species: int = 0
     hist_lo: int = 0
     hist_hi: int = 0
+    bin_coef2: Optional[np.ndarray] = None   # second grid axis (None: 1-D)
+    edges2: Optional[np.ndarray] = None
+
+    @property
+    def n_bins1(self) -> int:
+        return len(self.edges) - 1
+
+    @property
+    def n_bins2(self) -> int:
+        return 1 if self.edges2 is None else len(self.edges2) - 1
 
     @property
     def n_bins(self) -> int:
-        return len(self.edges) - 1
+        return self.n_bins1 * self.n_bins2
 
     @property
     def cap(self) -> int:
@@ -343,6 +376,42 @@ def large_network_config(seed: int = 2024, n_walkers: int = 4096, n_bins: int = 
 # Synthetic two-gene mutual-repression toggle (8 species, 16 reactions).
 # --------------------------------------------------------------------------
 TOGGLE_SPECIES = ["G1", "G1r", "G2", "G2r", "P1", "P2", "D1", "D2"]
+
+
+# --------------------------------------------------------------------------
+# Epigenetic switch, Sec. III.C.
+# --------------------------------------------------------------------------
+SWITCH_P = dict(a1=156.0, a2=30.0, n=3, m=1, K1=1.0, K2=1.0, k0=1.0)
+
+
+def switch() -> Network:
+    """0 -> g1 at a1 / (1 + (g2/K2)^n), g1 -> 0 at k0 g1, 0 -> g2 at
+    a2 / (1 + (g1/K1)^m), g2 -> 0 at k0 g2 (Sec. III.C)."""
+    p = SWITCH_P
+    return Network.from_reactions(["g1", "g2"], [
+        ({}, {"g1": 1}, p["a1"], ("g2", p["n"], p["K2"])),
+        ({"g1": 1}, {}, p["k0"]),
+        ({}, {"g2": 1}, p["a2"], ("g1", p["m"], p["K1"])),
+        ({"g2": 1}, {}, p["k0"]),
+    ])
+
+
+def switch_config(n_runs: int = 6, seed0: int = 1, n_iters: int = 500, m_targ: int = 16) -> WEConfig:
+    """The WE setup of Sec. III.C: 15 bins on g1 (unit width on [0, 10],
+    width 10 on [10, 50], then [50, inf)) times 31 on g2 (unit width on
+    [0, 30], then [30, inf)); 16 walkers per bin; tau = 0.1.  States (never
+    defined in the paper): A = (g1, g2) = (0, 30), the g2-high state, and
+    B = {g1 >= 50}; walkers reaching B restart from A."""
+    top = 1e9
+    e1 = np.array(list(range(0, 11)) + [20, 30, 40, 50, top], np.float64)
+    e2 = np.array(list(range(0, 31)) + [top], np.float64)
+    return WEConfig(
+        name="switch", net=switch(), x0=np.array([0, 30], np.int32),
+        bin_coef=np.array([1.0, 0.0]), edges=e1, m_targ=m_targ, tau=0.1, n_iters=n_iters,
+        seeds=np.arange(seed0, seed0 + n_runs, dtype=np.uint64),
+        recycle=True, tgt_coef=np.array([1.0, 0.0]), tgt_thr=50.0,
+        x_rec=np.array([0, 30], np.int32),
+        bin_coef2=np.array([0.0, 1.0]), edges2=e2)
 
 
 def toggle_rates(seed: int) -> Dict[str, float]:

@@ -166,3 +166,68 @@ def chi2_pvalue(counts: np.ndarray, probs: np.ndarray, min_expected: float = 5.0
     chi2 = float(((obs_p - exp_p) ** 2 / exp_p).sum())
     dof = max(len(obs_p) - 1, 1)
     return float(stats.chi2.sf(chi2, dof))
+
+
+# ---------------------------------------------------------------- epigenetic switch
+SWITCH = dict(a1=156.0, a2=30.0, n=3, m=1, K1=1.0, K2=1.0, k0=1.0)
+
+
+def switch_rates(g1: int, g2: int):
+    """Birth and death rates of the switch of Sec. III.C at (g1, g2):
+    g1 born at a1 / (1 + (g2/K2)^n), g2 at a2 / (1 + (g1/K1)^m), each copy
+    dies at k0."""
+    p = SWITCH
+    b1 = p["a1"] / (1.0 + (g2 / p["K2"]) ** p["n"])
+    b2 = p["a2"] / (1.0 + (g1 / p["K1"]) ** p["m"])
+    return b1, p["k0"] * g1, b2, p["k0"] * g2
+
+
+def _switch_generator(G1: int, G2: int, absorb_g1: int = None):
+    """Sparse generator (column = from) of the switch on [0, G1] x [0, G2],
+    no births out of the box; with absorb_g1, states g1 >= absorb_g1 are
+    cut off (their inflow is lost: first-passage form)."""
+    import scipy.sparse as sp
+    top1 = G1 if absorb_g1 is None else absorb_g1 - 1
+    n1, n2 = top1 + 1, G2 + 1
+    idx = lambda a, b: a * n2 + b
+    rows, cols, vals = [], [], []
+    diag = np.zeros(n1 * n2)
+    for a in range(n1):
+        for b in range(n2):
+            i = idx(a, b)
+            b1, d1, b2, d2 = switch_rates(a, b)
+            if a < G1:                      # birth of g1 (lost if it lands in the cut-off set)
+                diag[i] -= b1
+                if a + 1 <= top1:
+                    rows.append(idx(a + 1, b)); cols.append(i); vals.append(b1)
+            if a > 0:
+                diag[i] -= d1
+                rows.append(idx(a - 1, b)); cols.append(i); vals.append(d1)
+            if b < G2:
+                diag[i] -= b2
+                rows.append(idx(a, b + 1)); cols.append(i); vals.append(b2)
+            if b > 0:
+                diag[i] -= d2
+                rows.append(idx(a, b - 1)); cols.append(i); vals.append(d2)
+    rows += list(range(n1 * n2)); cols += list(range(n1 * n2)); vals += list(diag)
+    Q = sp.csc_matrix((vals, (rows, cols)), shape=(n1 * n2, n1 * n2))
+    return Q, n1, n2
+
+
+def switch_mfpt(a=(0, 30), b_g1: int = 50, G2: int = 120) -> float:
+    """Mean first passage time from state a into {g1 >= b_g1}: solve
+    Q_T^T m = -1 over the states below b_g1 (the backward equation)."""
+    import scipy.sparse.linalg as spla
+    Q, n1, n2 = _switch_generator(b_g1, G2, absorb_g1=b_g1)
+    m = spla.spsolve(Q.T.tocsc(), -np.ones(n1 * n2))
+    return float(m[a[0] * n2 + a[1]])
+
+
+def switch_transient(x0=(0, 30), t: float = 0.5, G1: int = 60, G2: int = 80) -> np.ndarray:
+    """P(g1, g2, t) from x0 on [0, G1] x [0, G2] (no births out of the box);
+    array [G1 + 1, G2 + 1]."""
+    import scipy.sparse.linalg as spla
+    Q, n1, n2 = _switch_generator(G1, G2)
+    p0 = np.zeros(n1 * n2)
+    p0[x0[0] * n2 + x0[1]] = 1.0
+    return spla.expm_multiply(Q * t, p0).reshape(n1, n2)

@@ -225,3 +225,29 @@ def test_reweighting_speeds_up_relaxation():
     assert min(tv[0]) > 0.6
     assert max(tv[5]) < 0.4
     assert np.mean(tv[5]) < 0.3
+
+
+@pytest.mark.parametrize("n,seed", [(20, 1), (64, 2)])
+def test_state_reduction_matches_the_exact_solve(n, seed):
+    """The FP64 state reduction used past EXACT_MAX bins against the exact
+    solver, on sparse random chains whose rates span six decades."""
+    rng = np.random.default_rng(seed)
+    F = np.zeros((n, n))
+    for j in range(n):
+        for i in rng.choice(n, size=4, replace=False):
+            F[i, j] = 10.0 ** rng.uniform(-6, 0)
+        F[(j + 1) % n, j] = 10.0 ** rng.uniform(-6, 0)      # a cycle keeps it irreducible
+    exact = rw.steady_state(F, list(range(n)))
+    gth = rw.steady_state_gth(F, list(range(n)))
+    assert np.allclose(gth, exact, rtol=1e-11, atol=0)
+
+
+def test_state_reduction_keeps_tiny_components():
+    n = 30
+    K = np.zeros((n, n))
+    for i in range(n - 1):
+        K[i + 1, i] = 0.01
+        K[i, i + 1] = 0.25
+    F = _flux_from_rates(K, np.ones(n))
+    want = cf.chain_stationary(np.full(n, 0.01), np.append(0.0, np.full(n - 1, 0.25)))
+    assert np.allclose(rw.steady_state_gth(F, list(range(n))), want, rtol=1e-12, atol=0)
