@@ -360,6 +360,55 @@ def experiment_schlogl_rw(args):
     print(json.dumps(out), flush=True)
 
 
+def experiment_switch_mfpt(args):
+    """The epigenetic switch of Sec. III.C at the paper's WE settings (15 x 31
+    bins, 16 walkers per bin, tau = 0.1, 500 iterations, reweighting every
+    100, first 100 iterations discarded): the combined MFPT of the replicas
+    against the exact value, the paper's six-run estimate, and E_50% (the MFPT
+    over the brute-force-equivalent dynamics, segments x tau, propagated
+    until a replica's running estimate first comes within 50%)."""
+    import torch
+    from paper_1303_5986_amd import we, workloads as wl
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    import closed_form as cf
+
+    runs, total, chunk = args.switch_runs, 500, 50
+    cfg = wl.switch_config(n_runs=runs, n_iters=total)
+    exact = cf.switch_mfpt()
+    sim = we.sim_from_config(cfg, kernel=we.WE_KERNEL_LANE, max_iters=total, rw_period=100)
+    sim.graph_capture(chunk)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.graph_replay(total // chunk)
+    sim.synchronize()
+    gpu = time.perf_counter() - t0
+    flux = np.stack([sim.flux(r, 0, total) for r in range(runs)])
+    per_run = flux[:, 100:].mean(axis=1) / cfg.tau
+    mfpt = 1.0 / per_run.mean()
+    sem_rel = per_run.std(ddof=1) / np.sqrt(runs) / per_run.mean()
+    six = per_run[:6]
+    e50 = []
+    for r in range(runs):
+        run_mean = np.cumsum(flux[r]) / np.arange(1, total + 1) / cfg.tau
+        with np.errstate(divide="ignore"):
+            est = np.where(run_mean > 0, 1.0 / run_mean, np.inf)
+        ok = np.flatnonzero(np.abs(est / exact - 1.0) <= 0.5)
+        e50.append(int(ok[0]) + 1 if ok.size else None)
+    ev, seg_total, _ = sim.counters()
+    out = {"metric": "MFPT of the epigenetic switch, WE with reweighting every 100 iterations",
+           "workload": f"switch (Sec. III.C), 15x31 bins x 16 walkers, tau 0.1, {runs} replicas x {total} iterations",
+           "exact_mfpt": exact, "mfpt": mfpt, "rel_err": mfpt / exact - 1.0, "sem_rel": sem_rel,
+           "replica_rel_sd": float(per_run.std(ddof=1) / per_run.mean()),
+           "first_six": {"mfpt": float(1.0 / six.mean()),
+                         "sem": float(six.std(ddof=1) / np.sqrt(6) / six.mean() / six.mean())},
+           "iterations_to_50pct": e50[:6], "median_iterations_to_50pct": float(np.median([v for v in e50 if v])),
+           "segments_per_replica": seg_total / runs,
+           "e50_approx": exact / (float(np.median([v for v in e50 if v])) * seg_total / runs / total * cfg.tau),
+           "events": ev, "gpu_s": gpu,
+           "ms_per_iteration": gpu * 1e3 / total}
+    print(json.dumps(out), flush=True)
+
+
 def experiment_batch(args):
     """64 independent WE runs on seeded networks of 8..3680 reactions and
     256..8192 walker slots: one batch (persistent propagation launches,
@@ -425,7 +474,8 @@ def main():
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB five times "
                          "(reference kernel for scaling the HBM byte counters)")
-    ap.add_argument("--experiment", default="", choices=["", "toggle_mfpt", "batch", "schlogl_rw"])
+    ap.add_argument("--experiment", default="", choices=["", "toggle_mfpt", "batch", "schlogl_rw", "switch_mfpt"])
+    ap.add_argument("--switch-runs", type=int, default=64, help="replicas in the switch experiment")
     ap.add_argument("--rw-runs", type=int, default=32,
                     help="replicas in the reweighting experiment")
     ap.add_argument("--large-runs", type=int, default=1,
@@ -453,6 +503,9 @@ def main():
         return
     if args.experiment == "schlogl_rw":
         experiment_schlogl_rw(args)
+        return
+    if args.experiment == "switch_mfpt":
+        experiment_switch_mfpt(args)
         return
     if args.calibrate_copy:
         import torch

@@ -82,16 +82,33 @@ WE_API we_status we_create_network(int32_t n_species, int32_t n_reactions,
                                    const double *rate_c, we_network **out);
 WE_API void we_destroy_network(we_network *net);
 
+/* Hill-type rate (Sec. III.C): reaction `reaction`'s propensity becomes
+ * c_j h_j(x) / (1 + (x_r / K)^n), r = `species`, evaluated in FP64 as
+ * t = x_r / K, p = t * t * ... (n factors), a = (c_j h_j) / (1 + p).
+ * 1 <= n <= 8, K > 0 finite.  Call before we_init; networks with Hill-type
+ * rates run on the lane kernel only (at most 8 species and 16 reactions)
+ * and not inside batches.  Errors: WE_EINVAL. */
+WE_API we_status we_set_hill(we_network *net, int32_t reaction, int32_t species, int32_t n,
+                             double K);
+
 /* ---------------------------------------------------------------- bins
  * Static grid on a linear progress coordinate q(x) = sum_s coef[s] * x_s
  * (summed in species order in FP64).  Bin b is [edges[b], edges[b+1]);
  * q below edges[0] goes to bin 0 and q at or above edges[n_bins] to bin
  * n_bins-1 (the paper's grids are regular and the open-ended bin of
- * Sec. III.C is the precedent).  edges must be strictly increasing. */
+ * Sec. III.C is the precedent).  edges must be strictly increasing.
+ * Optionally a second axis (the two-dimensional grid of Sec. III.C):
+ * n_bins2 > 1 bins on q2(x) = sum_s coef2[s] x_s with edges2, binned the
+ * same way; the bin is b1 + n_bins * b2, and there are n_bins * n_bins2
+ * bins in all (at most 8192).  n_bins2 = 0 or 1: one axis (coef2 and
+ * edges2 unused). */
 typedef struct {
     int32_t n_bins;
     const double *coef;    /* [n_species] */
     const double *edges;   /* [n_bins + 1] */
+    int32_t n_bins2;
+    const double *coef2;   /* [n_species] */
+    const double *edges2;  /* [n_bins2 + 1] */
 } we_grid;
 
 /* ---------------------------------------------------------------- run setup

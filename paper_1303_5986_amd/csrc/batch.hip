@@ -292,6 +292,10 @@ extern "C" we_status we_batch_create(int32_t n, const we_network *const *nets, c
             we_batch_destroy(b);
             return we_fail(WE_EINVAL, "reweighting is not supported inside a batch");
         }
+        if (!nets[i]->hill.empty()) {
+            we_batch_destroy(b);
+            return we_fail(WE_EINVAL, "Hill-type rates are not supported inside a batch");
+        }
         const int32_t S = nets[i]->S, R = nets[i]->R;
         if (p.kernel == WE_KERNEL_AUTO) {
             if (!(lane_kernel_fits(S, R, nets[i]->max_delta) && R <= 32)) {

@@ -2,7 +2,8 @@
 //
 // Each lane carries one walker through one WE interval tau (Sec. II.A, the
 // propagation step of the WE procedure in Sec. II.B):
-//   1. all propensities a_j = c_j * prod_s C(x_s, nu_js) and their total a0,
+//   1. all propensities a_j = c_j * prod_s C(x_s, nu_js) (divided by
+//      1 + (x_r / K)^n for a Hill-type rate, Sec. III.C) and their total a0,
 //      summed in reaction order;
 //   2. waiting time dt = -log(1 - u1) / a0; stop when t + dt > tau (the
 //      exponential is memoryless, so the overshoot is simply discarded);
@@ -33,14 +34,11 @@
 // grows steeply along the progress coordinate), so a fixed walker-per-lane
 // assignment would leave most lanes of a wave idle while its slowest walker
 // finishes.
-template <int SMAX, int RMAX>
-__global__ __launch_bounds__(256) void ssa_lane_pool_kernel(SimArgs a, int32_t *__restrict__ xs) {
+template <int SMAX, int RMAX, bool HILL>
+__device__ __forceinline__ void lane_pool(const SimArgs &a, int32_t *__restrict__ xs, int32_t *wrows) {
     constexpr bool REG = RMAX <= LANE_REG_RMAX;
-    constexpr int ROWS = REG ? 1 : RMAX * LaneRow<SMAX>::W;
-    __shared__ int32_t rows[4 * ROWS];
-    int32_t *wrows = rows + (threadIdx.x >> 6) * ROWS;
     if constexpr (!REG) lane_stage_rows<SMAX>(a, wrows);
-    LaneNet<SMAX, RMAX> net;
+    LaneNet<SMAX, RMAX, HILL> net;
     net.load(a, wrows);
     const int lane = threadIdx.x & 63;
     const uint32_t iter = *a.iter_dev;
@@ -89,6 +87,21 @@ __global__ __launch_bounds__(256) void ssa_lane_pool_kernel(SimArgs a, int32_t *
     }
 }
 
+template <int SMAX, int RMAX>
+__global__ __launch_bounds__(256) void ssa_lane_pool_kernel(SimArgs a, int32_t *__restrict__ xs) {
+    constexpr int ROWS = RMAX <= LANE_REG_RMAX ? 1 : RMAX * LaneRow<SMAX>::W;
+    __shared__ int32_t rows[4 * ROWS];
+    lane_pool<SMAX, RMAX, false>(a, xs, rows + (threadIdx.x >> 6) * ROWS);
+}
+
+// The same for networks with Hill-type rates (Sec. III.C).
+template <int SMAX, int RMAX>
+__global__ __launch_bounds__(256) void ssa_lane_hill_kernel(SimArgs a, int32_t *__restrict__ xs) {
+    constexpr int ROWS = RMAX <= LANE_REG_RMAX ? 1 : RMAX * LaneRow<SMAX>::W;
+    __shared__ int32_t rows[4 * ROWS];
+    lane_pool<SMAX, RMAX, true>(a, xs, rows + (threadIdx.x >> 6) * ROWS);
+}
+
 // Fixed assignment, one walker per lane: used for the two largest variants,
 // whose register footprint leaves no room for the queue state.
 template <int SMAX, int RMAX>
@@ -109,15 +122,17 @@ __global__ __launch_bounds__(256) void ssa_lane_kernel(SimArgs a, int32_t *__res
 
 namespace {
 // Persistent grid: as many blocks as stay resident on the device.
-template <int SMAX, int RMAX>
+template <int SMAX, int RMAX, bool HILL>
 unsigned pool_blocks(const SimArgs &a) {
-    static int per_cu = -1, n_cu = 0;
+    static int per_cu = -1, n_cu = 0;   // one cache per kernel
+    void (*kernel)(SimArgs, int32_t *);
+    if constexpr (HILL) kernel = ssa_lane_hill_kernel<SMAX, RMAX>;
+    else kernel = ssa_lane_pool_kernel<SMAX, RMAX>;
     if (per_cu < 0) {
         int dev = 0;
         if (hipGetDevice(&dev) != hipSuccess ||
             hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, ssa_lane_pool_kernel<SMAX, RMAX>, 256, 0) !=
-                hipSuccess || per_cu < 1) {
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 256, 0) != hipSuccess || per_cu < 1) {
             per_cu = 1;
             n_cu = std::max(n_cu, 1);
         }
@@ -136,8 +151,15 @@ hipError_t launch_fixed(const SimArgs &a, int32_t *xs, hipStream_t st) {
 
 template <int SMAX, int RMAX>
 hipError_t launch_pool(const SimArgs &a, int32_t *xs, hipStream_t st) {
-    hipLaunchKernelGGL((ssa_lane_pool_kernel<SMAX, RMAX>), dim3(pool_blocks<SMAX, RMAX>(a)), dim3(256), 0, st, a,
-                       xs);
+    hipLaunchKernelGGL((ssa_lane_pool_kernel<SMAX, RMAX>), dim3(pool_blocks<SMAX, RMAX, false>(a)),
+                       dim3(256), 0, st, a, xs);
+    return hipGetLastError();
+}
+
+template <int SMAX, int RMAX>
+hipError_t launch_hill(const SimArgs &a, int32_t *xs, hipStream_t st) {
+    hipLaunchKernelGGL((ssa_lane_hill_kernel<SMAX, RMAX>), dim3(pool_blocks<SMAX, RMAX, true>(a)),
+                       dim3(256), 0, st, a, xs);
     return hipGetLastError();
 }
 }  // namespace
@@ -145,6 +167,11 @@ hipError_t launch_pool(const SimArgs &a, int32_t *xs, hipStream_t st) {
 // Launch helper: picks the smallest register footprint that holds the
 // network.  The queue variants need the queue built by launch_work_queue.
 hipError_t launch_ssa_lane(const SimArgs &a, int32_t *xs, hipStream_t st) {
+    if (a.hill) {
+        if (a.S <= 2 && a.R <= 8) return launch_hill<2, 8>(a, xs, st);
+        if (a.S <= 8 && a.R <= 16) return launch_hill<8, 16>(a, xs, st);
+        return hipErrorInvalidValue;
+    }
     if (a.S <= 1 && a.R <= 4) return launch_pool<1, 4>(a, xs, st);
     if (a.S <= 2 && a.R <= 8) return launch_pool<2, 8>(a, xs, st);
     if (a.S <= 8 && a.R <= 16) return launch_pool<8, 16>(a, xs, st);

@@ -44,6 +44,31 @@ __device__ __forceinline__ double lane_propensity(const LaneRxn &d, const int32_
     return d.c * (h1 * h2);
 }
 
+struct LaneHill {
+    double K;
+    uint32_t s, n;
+};
+
+__device__ __forceinline__ LaneHill lane_hill(const HillDesc *__restrict__ hill, int j) {
+    const uint4 r = reinterpret_cast<const uint4 *>(hill)[j];
+    LaneHill o;
+    o.K = __hiloint2double((int)r.y, (int)r.x);
+    o.s = r.z;
+    o.n = r.w;
+    return o;
+}
+
+// Hill-type repression (Sec. III.C): a / (1 + t^n), t = x_s / K, the power
+// by repeated multiplication, each step one rounding.
+template <int SMAX>
+__device__ __forceinline__ double lane_repress(double a, const LaneHill &h, const int32_t (&x)[SMAX]) {
+    if (h.n == 0) return a;
+    const double t = (double)x[SMAX == 1 ? 0 : h.s] / h.K;
+    double p = t;
+    for (uint32_t i = 1; i < h.n; ++i) p = p * t;
+    return a / (1.0 + p);
+}
+
 }  // namespace
 
 // Words of the delta row a variant reads (4 species per word).
@@ -64,14 +89,17 @@ __device__ __forceinline__ void lane_stage_rows(const SimArgs &a, int32_t *rows)
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// The network's uniform tables as one lane kernel sees them.
-template <int SMAX, int RMAX>
+// The network's uniform tables as one lane kernel sees them.  HILL: some
+// reactions carry a Hill-type repression (read with the descriptors).
+template <int SMAX, int RMAX, bool HILL = false>
 struct LaneNet {
     static constexpr int W = LaneRow<SMAX>::W;
     static constexpr bool REG = RMAX <= LANE_REG_RMAX;
     LaneRxn rx[REG ? RMAX : 1];
     uint32_t drow[REG ? RMAX : 1][W];
+    LaneHill hl[HILL && REG ? RMAX : 1];
     const RxnDesc *desc;
+    const HillDesc *hill;
     const int32_t *dpack;
     const int32_t *rows;   // this wave's staged delta rows (unused when REG)
     int32_t R;
@@ -80,6 +108,7 @@ struct LaneNet {
     // in bounds; small networks keep them in registers for the whole launch
     __device__ __forceinline__ void load(const SimArgs &a, const int32_t *rows_) {
         desc = a.desc;
+        hill = a.hill;
         dpack = a.dpack;
         rows = rows_;
         R = a.R;
@@ -89,6 +118,7 @@ struct LaneNet {
                 rx[j] = lane_rxn(a.desc, j);
 #pragma unroll
                 for (int w = 0; w < W; ++w) drow[j][w] = (uint32_t)a.dpack[j * WE_DPACK_WORDS + w];
+                if constexpr (HILL) hl[j] = lane_hill(a.hill, j);
             }
         }
     }
@@ -120,11 +150,11 @@ struct LaneWalker {
 // One event of the direct method (Sec. II.A); false once the walker's
 // interval is over (next event beyond tau, no reaction possible, or a count
 // out of range -- then w.bad is set).
-template <int SMAX, int RMAX>
-__device__ __forceinline__ bool lane_event(const LaneNet<SMAX, RMAX> &net, LaneWalker &w, int32_t (&x)[SMAX],
-                                           uint32_t iter, double tau) {
+template <int SMAX, int RMAX, bool HILL>
+__device__ __forceinline__ bool lane_event(const LaneNet<SMAX, RMAX, HILL> &net, LaneWalker &w,
+                                           int32_t (&x)[SMAX], uint32_t iter, double tau) {
     constexpr int W = LaneRow<SMAX>::W;
-    constexpr bool REG = LaneNet<SMAX, RMAX>::REG;
+    constexpr bool REG = LaneNet<SMAX, RMAX, HILL>::REG;
     double prop[RMAX];
     double a0 = 0.0;
 #pragma unroll
@@ -133,6 +163,7 @@ __device__ __forceinline__ bool lane_event(const LaneNet<SMAX, RMAX> &net, LaneW
         prop[j] = 0.0;
         if (j < net.R) {
             prop[j] = lane_propensity<SMAX>(d, x);
+            if constexpr (HILL) prop[j] = lane_repress<SMAX>(prop[j], REG ? net.hl[REG ? j : 0] : lane_hill(net.hill, j), x);
             a0 = a0 + prop[j];
         }
     }

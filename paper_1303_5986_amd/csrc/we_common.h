@@ -32,6 +32,14 @@ struct __align__(16) RxnDesc {
     uint8_t order;   // nu1 + nu2
 };
 
+// A reaction's Hill-type repression (Sec. III.C): its propensity is divided
+// by 1 + (x_species / K)^n; n = 0: none.
+struct __align__(16) HillDesc {
+    double K;
+    int32_t species;
+    int32_t n;
+};
+
 // Where a reaction's dependency entries and changes start, in one load.
 struct __align__(16) RxnInfo {
     int32_t dep_begin, dep_count, chg_begin, chg_count;
@@ -65,6 +73,7 @@ struct SimArgs {
     const uint16_t *__restrict__ dep;    //       (sorted, unique)
     const RxnInfo *__restrict__ rinfo;   // [R]
     const DepEntry *__restrict__ deps;   // dependency entries with descriptors
+    const HillDesc *__restrict__ hill;   // [R padded] Hill-type rates (null: none)
     int32_t S, R;
     // runs
     int32_t n_runs, cap, n_bins, m_targ, max_iters;
@@ -77,6 +86,11 @@ struct SimArgs {
     double tgt_thr;
     const double *__restrict__ tgt_coef; // [S]
     const int32_t *__restrict__ bin_nz;  // species with a nonzero bin_coef, ascending
+    // second grid axis (n_bins2 > 1): bin = b1 + n_bins1 * b2, n_bins = n_bins1 * n_bins2
+    int32_t n_bins1, n_bins2, n_bin_nz2;
+    const double *__restrict__ bin_coef2;
+    const double *__restrict__ edges2;
+    const int32_t *__restrict__ bin_nz2;
     const int32_t *__restrict__ tgt_nz;  // species with a nonzero tgt_coef, ascending
     int32_t n_bin_nz, n_tgt_nz;
     const int32_t *__restrict__ x_rec;   // [S]

@@ -33,6 +33,8 @@ struct we_network {
     RxnInfo *d_rinfo = nullptr;
     DepEntry *d_deps = nullptr;
     int32_t *d_dpack = nullptr;     // [R][WE_DPACK_WORDS] int8 deltas (species < 32)
+    std::vector<HillDesc> hill;     // empty: no Hill-type rates
+    HillDesc *d_hill = nullptr;     // [R padded to 64]
 };
 
 // The learned committor attached to a sim (see committor.hip).

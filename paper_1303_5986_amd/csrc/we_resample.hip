@@ -7,8 +7,9 @@
 //      B = { x : sum_s coef_s x_s >= thr } is flagged and restarts from the
 //      state A, keeping its weight; checked once, at the end of the interval
 //      (the paper checks walkers only every tau);
-//      bin of every walker on the progress coordinate (or, with learned
-//      bins, the bin is written afterwards by the committor kernel);
+//      bin of every walker on the progress coordinate, or on a grid over two
+//      coordinates, bin = b1 + n1 * b2 (or, with learned bins, the bin is
+//      written afterwards by the committor kernel);
 //   resample (one workgroup per run)
 //      stable placement of the walkers by bin: per-wave cursor rows let
 //      several waves place their own runs of slots at once;
@@ -86,7 +87,12 @@ __device__ __forceinline__ void recycle_bin_one(const SimArgs &a, int32_t *__res
         for (int32_t s = 0; s < S; ++s) row[s] = a.x_rec[s];
     }
     a.s_rec[idx] = rec;
-    if (grid_bins) a.s_bin[idx] = bin_index(a.edges, a.n_bins, coord_of(a.bin_coef, a.bin_nz, a.n_bin_nz, row));
+    if (grid_bins) {
+        int32_t b = bin_index(a.edges, a.n_bins1, coord_of(a.bin_coef, a.bin_nz, a.n_bin_nz, row));
+        if (a.n_bins2 > 1)
+            b += a.n_bins1 * bin_index(a.edges2, a.n_bins2, coord_of(a.bin_coef2, a.bin_nz2, a.n_bin_nz2, row));
+        a.s_bin[idx] = b;
+    }
 }
 
 __global__ __launch_bounds__(256) void we_recycle_bin_kernel(SimArgs a, int32_t *__restrict__ x_cur,

@@ -220,8 +220,31 @@ extern "C" we_status we_create_network(int32_t S, int32_t R, const int32_t *reac
     return WE_OK;
 }
 
+extern "C" we_status we_set_hill(we_network *net, int32_t reaction, int32_t species, int32_t n,
+                                 double K) {
+    if (!net) return fail(WE_EINVAL, "NULL network");
+    if (reaction < 0 || reaction >= net->R || species < 0 || species >= net->S)
+        return fail(WE_EINVAL, "reaction or species out of range");
+    if (n < 1 || n > 8 || !(K > 0.0) || std::isinf(K)) return fail(WE_EINVAL, "need 1 <= n <= 8 and K > 0");
+    const int32_t R_pad = (net->R + 63) / 64 * 64;
+    if (net->hill.empty()) {
+        HillDesc none{};
+        none.K = 1.0;
+        none.species = -1;
+        none.n = 0;
+        net->hill.assign(R_pad, none);
+        HIP_TRY(hipMalloc(&net->d_hill, sizeof(HillDesc) * R_pad));
+    }
+    net->hill[reaction].K = K;
+    net->hill[reaction].species = species;
+    net->hill[reaction].n = n;
+    HIP_TRY(hipMemcpy(net->d_hill, net->hill.data(), sizeof(HillDesc) * R_pad, hipMemcpyHostToDevice));
+    return WE_OK;
+}
+
 extern "C" void we_destroy_network(we_network *net) {
     if (!net) return;
+    (void)hipFree(net->d_hill);
     (void)hipFree(net->d_desc);
     (void)hipFree(net->d_chg_ptr);
     (void)hipFree(net->d_chg);
@@ -255,7 +278,7 @@ enum Piece { P_X0, P_X1, P_W0, P_W1, P_BIN, P_ORIG, P_N, P_EVW, P_FLUX, P_EVI, P
 
 int32_t seg_rep_for(int32_t NB) { return std::min(32, std::max(1, 4096 / NB)); }
 
-Layout make_layout(int32_t S, int32_t NB, int32_t n_runs, int32_t cap, int32_t max_iters,
+Layout make_layout(int32_t S, int32_t NB, int32_t n_bins2, int32_t n_runs, int32_t cap, int32_t max_iters,
                    int32_t nh, int64_t jcells, bool rw) {
     Layout L;
     const size_t W = (size_t)n_runs * cap;
@@ -269,8 +292,8 @@ Layout make_layout(int32_t S, int32_t NB, int32_t n_runs, int32_t cap, int32_t m
     L.add(4 * W); L.add(4 * W); L.add(4 * W); L.add(8 * W); L.add(4 * W);
     L.add(8 * (size_t)n_runs * std::max(nh, 1));
     L.add(8 * (size_t)n_runs);
-    L.add(8 * (size_t)S);
-    L.add(8 * (size_t)(NB + 1));
+    L.add(8 * 2 * (size_t)S);
+    L.add(8 * (size_t)(NB + 1 + n_bins2 + 1));
     L.add(8 * (size_t)S);
     L.add(4 * (size_t)S);
     L.add(4);
@@ -280,7 +303,7 @@ Layout make_layout(int32_t S, int32_t NB, int32_t n_runs, int32_t cap, int32_t m
     L.add(4 * (2 + 3 * (size_t)seg_rep_for(NB)) * (size_t)NB);
     L.add(8 * (size_t)n_runs * NB);
     L.add(8);
-    L.add(4 * 2 * (size_t)S);
+    L.add(4 * 3 * (size_t)S);
     const size_t nb2 = (size_t)NB * NB;
     L.add(rw ? 8 * (size_t)n_runs * nb2 : 0);
     L.add(rw && !rw_solve_in_lds(NB) ? 8 * (size_t)n_runs * nb2 : 0);
@@ -288,16 +311,26 @@ Layout make_layout(int32_t S, int32_t NB, int32_t n_runs, int32_t cap, int32_t m
     return L;
 }
 
+int32_t grid_bins(const we_grid *g) { return g->n_bins * (g->n_bins2 > 1 ? g->n_bins2 : 1); }
+int32_t grid_bins2(const we_grid *g) { return g->n_bins2 > 1 ? g->n_bins2 : 1; }
+
 we_status check_params(const we_network *net, const we_grid *g, const we_params *p) {
     if (!net || !g || !p) return fail(WE_EINVAL, "NULL argument");
     if (g->n_bins < 1 || !g->coef || !g->edges) return fail(WE_EINVAL, "bad grid");
     for (int32_t b = 0; b < g->n_bins; ++b)
         if (!(g->edges[b] < g->edges[b + 1])) return fail(WE_EINVAL, "edges must increase strictly");
+    if (g->n_bins2 < 0) return fail(WE_EINVAL, "n_bins2 must be >= 0");
+    if (g->n_bins2 > 1) {
+        if (!g->coef2 || !g->edges2) return fail(WE_EINVAL, "the second grid axis needs coef2 and edges2");
+        for (int32_t b = 0; b < g->n_bins2; ++b)
+            if (!(g->edges2[b] < g->edges2[b + 1])) return fail(WE_EINVAL, "edges2 must increase strictly");
+        if ((int64_t)g->n_bins * g->n_bins2 > 8192) return fail(WE_EINVAL, "at most 8192 bins");
+    }
     if (!(p->tau > 0.0) || std::isinf(p->tau)) return fail(WE_EINVAL, "tau must be > 0");
     if (p->m_targ < 1 || p->n_runs < 1 || p->max_iters < 0)
         return fail(WE_EINVAL, "m_targ, n_runs must be >= 1");
     if (!p->seeds || !p->x0) return fail(WE_EINVAL, "seeds and x0 are required");
-    const int64_t cap = (int64_t)p->m_targ * g->n_bins;
+    const int64_t cap = (int64_t)p->m_targ * grid_bins(g);
     if (g->n_bins > 8192) return fail(WE_EINVAL, "at most 8192 bins");
     if (cap > (1 << 22) || cap * p->n_runs > (int64_t)1 << 30)
         return fail(WE_EINVAL, "too many walker slots");
@@ -317,9 +350,9 @@ we_status check_params(const we_network *net, const we_grid *g, const we_params 
     if (p->n_joint < 0 || p->n_joint > 5) return fail(WE_EINVAL, "n_joint must be in [0, 5]");
     if (p->record_iters < 0) return fail(WE_EINVAL, "record_iters must be >= 0");
     if (p->rw_period < 0) return fail(WE_EINVAL, "rw_period must be >= 0");
-    if (p->rw_period > 0 && g->n_bins > WE_RW_MAX_BINS)
-        return fail(WE_EINVAL, "reweighting needs n_bins <= 512");
-    if (p->rw_period > 0 && (int64_t)p->n_runs * g->n_bins * g->n_bins > ((int64_t)1 << 31))
+    if (p->rw_period > 0 && grid_bins(g) > WE_RW_MAX_BINS)
+        return fail(WE_EINVAL, "reweighting needs at most 512 bins");
+    if (p->rw_period > 0 && (int64_t)p->n_runs * grid_bins(g) * grid_bins(g) > ((int64_t)1 << 31))
         return fail(WE_EINVAL, "reweighting: n_runs * n_bins^2 too large");
     if (p->n_joint > 0) {
         if (!p->joint_species || p->joint_bins < 1 || p->joint_width < 1)
@@ -349,7 +382,7 @@ extern "C" we_status we_workspace_size(const we_network *net, const we_grid *g, 
     if (st != WE_OK) return st;
     if (!bytes) return fail(WE_EINVAL, "bytes is NULL");
     const int32_t nh = p->hist_hi >= p->hist_lo ? p->hist_hi - p->hist_lo + 1 : 0;
-    *bytes = make_layout(net->S, g->n_bins, p->n_runs, p->m_targ * g->n_bins,
+    *bytes = make_layout(net->S, grid_bins(g), grid_bins2(g), p->n_runs, p->m_targ * grid_bins(g),
                          std::max(p->max_iters, 1), nh, joint_cells(p), p->rw_period > 0).total;
     return WE_OK;
 }
@@ -361,19 +394,24 @@ extern "C" we_status we_init(const we_network *net, const we_grid *g, const we_p
     *out = nullptr;
     we_status st = check_params(net, g, p);
     if (st != WE_OK) return st;
-    const int32_t S = net->S, NB = g->n_bins, M = p->m_targ, n_runs = p->n_runs;
+    const int32_t S = net->S, NB = grid_bins(g), NB1 = g->n_bins, NB2 = grid_bins2(g);
+    const int32_t M = p->m_targ, n_runs = p->n_runs;
     const int32_t cap = M * NB, max_iters = std::max(p->max_iters, 1);
     const int32_t nh = p->hist_hi >= p->hist_lo ? p->hist_hi - p->hist_lo + 1 : 0;
     int32_t kernel = p->kernel;
+    const bool hill = !net->hill.empty();
+    if (hill && (kernel == WE_KERNEL_WAVE || S > 8 || net->R > 16 || net->max_delta > 127))
+        return fail(WE_EINVAL, "Hill-type rates run on the lane kernel only (S <= 8, R <= 16)");
     if (kernel == WE_KERNEL_AUTO)
-        kernel = lane_kernel_fits(S, net->R, net->max_delta) && net->R <= 32 ? WE_KERNEL_LANE : WE_KERNEL_WAVE;
+        kernel = hill || (lane_kernel_fits(S, net->R, net->max_delta) && net->R <= 32) ? WE_KERNEL_LANE
+                                                                                       : WE_KERNEL_WAVE;
     if (kernel == WE_KERNEL_LANE && !lane_kernel_fits(S, net->R, net->max_delta))
         return fail(WE_EINVAL, "network does not fit the lane-per-walker kernel (S <= 32, R <= 64, |change| <= 127)");
     if (kernel == WE_KERNEL_WAVE && (!wave_kernel_fits(S, net->R) || net->max_chg > 64))
         return fail(WE_EINVAL, "network too large for the wave-per-walker kernel");
 
     const int64_t jcells = joint_cells(p);
-    Layout L = make_layout(S, NB, n_runs, cap, max_iters, nh, jcells, p->rw_period > 0);
+    Layout L = make_layout(S, NB, NB2, n_runs, cap, max_iters, nh, jcells, p->rw_period > 0);
     we_sim *s = new we_sim();
     s->net = net;
     s->stream = (hipStream_t)hip_stream;
@@ -399,17 +437,23 @@ extern "C" we_status we_init(const we_network *net, const we_grid *g, const we_p
     a.desc = net->d_desc; a.chg_ptr = net->d_chg_ptr; a.chg = net->d_chg; a.dpack = net->d_dpack;
     a.dep_ptr = net->d_dep_ptr; a.dep = net->d_dep;
     a.rinfo = net->d_rinfo; a.deps = net->d_deps;
+    a.hill = hill ? net->d_hill : nullptr;
     a.S = S; a.R = net->R;
     a.n_runs = n_runs; a.cap = cap; a.n_bins = NB; a.m_targ = M; a.max_iters = max_iters;
     a.tau = p->tau;
     a.seeds = (const uint64_t *)at(P_SEEDS);
     a.bin_coef = (const double *)at(P_BCOEF);
     a.edges = (const double *)at(P_EDGES);
+    a.n_bins1 = NB1;
+    a.n_bins2 = NB2;
+    a.bin_coef2 = a.bin_coef + S;
+    a.edges2 = a.edges + NB1 + 1;
     a.recycle = p->recycle ? 1 : 0;
     a.tgt_thr = p->tgt_thr;
     a.tgt_coef = (const double *)at(P_TCOEF);
     a.bin_nz = (const int32_t *)at(P_NZ);
     a.tgt_nz = a.bin_nz + S;
+    a.bin_nz2 = a.bin_nz + 2 * S;
     a.x_rec = (const int32_t *)at(P_XREC);
     a.n_walk = (int32_t *)at(P_N);
     a.bin = (int32_t *)at(P_BIN);
@@ -469,16 +513,24 @@ extern "C" we_status we_init(const we_network *net, const we_grid *g, const we_p
     if (e == hipSuccess) e = put(P_N, hn.data(), 4 * (size_t)n_runs);
     if (e == hipSuccess) e = put(P_ORIG, horig.data(), 4 * W);
     if (e == hipSuccess) e = put(P_SEEDS, p->seeds, 8 * (size_t)n_runs);
-    if (e == hipSuccess) e = put(P_BCOEF, g->coef, 8 * (size_t)S);
-    if (e == hipSuccess) e = put(P_EDGES, g->edges, 8 * (size_t)(NB + 1));
+    std::vector<double> coefs(2 * (size_t)S, 0.0), edges_all((size_t)NB1 + 1 + NB2 + 1, 0.0);
+    for (int32_t sp = 0; sp < S; ++sp) {
+        coefs[sp] = g->coef[sp];
+        if (NB2 > 1) coefs[S + sp] = g->coef2[sp];
+    }
+    for (int32_t b = 0; b <= NB1; ++b) edges_all[b] = g->edges[b];
+    for (int32_t b = 0; b <= NB2; ++b) edges_all[NB1 + 1 + b] = NB2 > 1 ? g->edges2[b] : (double)b;
+    if (e == hipSuccess) e = put(P_BCOEF, coefs.data(), 8 * coefs.size());
+    if (e == hipSuccess) e = put(P_EDGES, edges_all.data(), 8 * edges_all.size());
     if (e == hipSuccess) e = put(P_TCOEF, p->tgt_coef ? p->tgt_coef : zcoef.data(), 8 * (size_t)S);
-    std::vector<int32_t> nz(2 * (size_t)S, 0);
-    a.n_bin_nz = a.n_tgt_nz = 0;
+    std::vector<int32_t> nz(3 * (size_t)S, 0);
+    a.n_bin_nz = a.n_tgt_nz = a.n_bin_nz2 = 0;
     for (int32_t sp = 0; sp < S; ++sp) {
         if (g->coef[sp] != 0.0) nz[a.n_bin_nz++] = sp;
         if (p->tgt_coef && p->tgt_coef[sp] != 0.0) nz[S + a.n_tgt_nz++] = sp;
+        if (NB2 > 1 && g->coef2[sp] != 0.0) nz[2 * S + a.n_bin_nz2++] = sp;
     }
-    if (e == hipSuccess) e = put(P_NZ, nz.data(), 4 * 2 * (size_t)S);
+    if (e == hipSuccess) e = put(P_NZ, nz.data(), 4 * nz.size());
     if (e == hipSuccess) e = put(P_XREC, p->x_rec ? p->x_rec : p->x0, 4 * (size_t)S);
     if (e == hipSuccess) e = hipStreamSynchronize(st_);
     if (e != hipSuccess) {

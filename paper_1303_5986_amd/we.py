@@ -24,7 +24,8 @@ _STATUS = {WE_EINVAL: "EINVAL", WE_ENOMEM: "ENOMEM", WE_EDEVICE: "EDEVICE",
            WE_ECAPACITY: "ECAPACITY", WE_EOVERFLOW: "EOVERFLOW", WE_ESTATE: "ESTATE"}
 
 EXPORTED = [
-    "we_create_network", "we_destroy_network", "we_workspace_size", "we_init", "we_set_ensemble",
+    "we_create_network", "we_destroy_network", "we_set_hill", "we_workspace_size", "we_init",
+    "we_set_ensemble",
     "we_step_intervals", "we_graph_capture", "we_graph_replay", "we_synchronize", "we_get_walkers",
     "we_histogram", "we_histogram_accum", "we_joint_histogram", "we_flux", "we_mfpt",
     "we_counters", "we_events_series", "we_rw_flux_matrix", "we_rw_counts", "we_profile",
@@ -51,7 +52,8 @@ class WEError(RuntimeError):
 
 
 class _Grid(C.Structure):
-    _fields_ = [("n_bins", C.c_int32), ("coef", C.c_void_p), ("edges", C.c_void_p)]
+    _fields_ = [("n_bins", C.c_int32), ("coef", C.c_void_p), ("edges", C.c_void_p),
+                ("n_bins2", C.c_int32), ("coef2", C.c_void_p), ("edges2", C.c_void_p)]
 
 
 class _Params(C.Structure):
@@ -89,6 +91,7 @@ def load_library(path: str = LIB_PATH):
     L = C.CDLL(path)
     P, vp, i32, i64, f64 = C.POINTER, C.c_void_p, C.c_int32, C.c_int64, C.c_double
     L.we_create_network.argtypes = [i32, i32] + [vp] * 7 + [P(vp)]
+    L.we_set_hill.argtypes = [vp, i32, i32, i32, f64]
     L.we_destroy_network.argtypes = [vp]
     L.we_destroy_network.restype = None
     L.we_workspace_size.argtypes = [vp, vp, vp, P(C.c_size_t)]
@@ -162,6 +165,11 @@ class Network:
         _check(L.we_create_network(self.S, self.R, *[_ptr(a) for a in arrs], _ptr(rate),
                                    C.byref(h)))
         self.handle = h
+        if getattr(net, "hill_species", None) is not None:
+            for j in range(self.R):
+                if int(net.hill_species[j]) >= 0:
+                    _check(L.we_set_hill(self.handle, j, int(net.hill_species[j]), int(net.hill_n[j]),
+                                         float(net.hill_K[j])))
 
     def close(self):
         if getattr(self, "handle", None):
@@ -186,7 +194,8 @@ class Sim:
                  recycle: bool = False, tgt_coef=None, tgt_thr: float = 0.0, x_rec=None,
                  hist_species: int = 0, hist_lo: int = 0, hist_hi: int = -1,
                  joint_species: Sequence[int] = (), joint_bins: int = 16, joint_width: int = 64,
-                 record_iters: int = 0, rw_period: int = 0, rw_reset: bool = False, device=None):
+                 record_iters: int = 0, rw_period: int = 0, rw_reset: bool = False,
+                 bin_coef2=None, edges2=None, device=None):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("no HIP device: libwe.so runs on MI355X only")
@@ -201,17 +210,21 @@ class Sim:
             tgt=None if tgt_coef is None else np.ascontiguousarray(tgt_coef, np.float64),
             xrec=None if x_rec is None else np.ascontiguousarray(x_rec, np.int32),
             joint=np.ascontiguousarray(list(joint_species) or [0], np.int32),
+            coef2=None if bin_coef2 is None else np.ascontiguousarray(bin_coef2, np.float64),
+            edges2=None if edges2 is None else np.ascontiguousarray(edges2, np.float64),
         )
         k = self._keep
         if k["coef"].shape != (S,) or k["x0"].shape != (S,):
             raise ValueError("bin_coef and x0 need one entry per species")
-        self.n_bins = len(k["edges"]) - 1
+        n2 = 0 if k["edges2"] is None else len(k["edges2"]) - 1
+        self.n_bins = (len(k["edges"]) - 1) * max(n2, 1)
         self.n_runs = len(k["seeds"])
         self.m_targ = int(m_targ)
         self.cap = self.m_targ * self.n_bins
         self.S = S
         self.tau = float(tau)
-        self.grid = _Grid(self.n_bins, k["coef"].ctypes.data, k["edges"].ctypes.data)
+        self.grid = _Grid(len(k["edges"]) - 1, k["coef"].ctypes.data, k["edges"].ctypes.data,
+                          n2, _ptr(k["coef2"]), _ptr(k["edges2"]))
         self.params = _Params(float(tau), int(m_targ), self.n_runs, int(max_iters), int(kernel),
                               k["seeds"].ctypes.data, k["x0"].ctypes.data, int(bool(recycle)),
                               _ptr(k["tgt"]), float(tgt_thr), _ptr(k["xrec"]),
@@ -408,7 +421,8 @@ def sim_from_config(cfg, *, kernel: int = WE_KERNEL_AUTO, max_iters: Optional[in
                x_rec=cfg.x_rec, hist_species=cfg.hist_species, hist_lo=cfg.hist_lo,
                hist_hi=cfg.hist_hi,
                joint_species=getattr(cfg, "joint_species", ()) if joint else (),
-               record_iters=record_iters, rw_period=rw_period, rw_reset=rw_reset)
+               record_iters=record_iters, rw_period=rw_period, rw_reset=rw_reset,
+               bin_coef2=getattr(cfg, "bin_coef2", None), edges2=getattr(cfg, "edges2", None))
 
 
 def mlp_loss_grad(n_in: int, params, feat, x, y):
@@ -481,7 +495,12 @@ class Batch:
                      xrec=None if c.x_rec is None else np.ascontiguousarray(c.x_rec, np.int32),
                      joint=np.zeros(1, np.int32))
             self._keep.append(k)
-            grids[i] = _Grid(len(k["edges"]) - 1, k["coef"].ctypes.data, k["edges"].ctypes.data)
+            e2 = getattr(c, "edges2", None)
+            if e2 is not None:
+                k["coef2"] = np.ascontiguousarray(c.bin_coef2, np.float64)
+                k["edges2"] = np.ascontiguousarray(e2, np.float64)
+            grids[i] = _Grid(len(k["edges"]) - 1, k["coef"].ctypes.data, k["edges"].ctypes.data,
+                             0 if e2 is None else len(e2) - 1, _ptr(k.get("coef2")), _ptr(k.get("edges2")))
             kern = WE_KERNEL_AUTO if kernels is None else int(kernels[i])
             params[i] = _Params(float(c.tau), int(c.m_targ), len(k["seeds"]), int(max_iters), kern,
                                 k["seeds"].ctypes.data, k["x0"].ctypes.data, int(bool(c.recycle)),
