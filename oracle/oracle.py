@@ -38,6 +38,9 @@ def lib():
         L.or_ssa_interval.argtypes = [C.c_void_p, P(C.c_int32), C.c_double, C.c_uint64,
                                       C.c_uint32, C.c_uint32]
         L.or_ssa_interval.restype = C.c_int64
+        L.or_tauleap_interval.argtypes = [C.c_void_p, P(C.c_int32), C.c_double, C.c_double, C.c_uint64,
+                                          C.c_uint32, C.c_uint32]
+        L.or_tauleap_interval.restype = C.c_int64
         L.or_ssa_first_passage.argtypes = [C.c_void_p, P(C.c_int32), C.c_double,
                                            P(C.c_double), C.c_double, C.c_uint64,
                                            C.c_uint32, P(C.c_int64)]
@@ -77,7 +80,7 @@ class _CfgStruct(C.Structure):
                 ("n_bins2", C.c_int32), ("bin_coef2", C.c_void_p), ("edges2", C.c_void_p),
                 ("m_targ", C.c_int32), ("tau", C.c_double), ("seed", C.c_uint64),
                 ("recycle", C.c_int32), ("tgt_coef", C.c_void_p), ("tgt_thr", C.c_double),
-                ("x_rec", C.c_void_p)]
+                ("x_rec", C.c_void_p), ("engine", C.c_int32), ("leap_eps", C.c_double)]
 
 
 class OracleNet:
@@ -129,6 +132,14 @@ def propensity(onet: OracleNet, x, j: int) -> float:
 def ssa_interval(onet: OracleNet, x, tau: float, seed: int, slot: int, it: int):
     xa = np.array(x, dtype=np.int32, copy=True)
     ev = lib().or_ssa_interval(onet.ptr, _p(xa, C.c_int32), tau, seed, slot, it)
+    return xa, int(ev)
+
+
+def tauleap_interval(onet: OracleNet, x, tau: float, eps: float, seed: int, slot: int, it: int):
+    xa = np.array(x, dtype=np.int32, copy=True)
+    ev = lib().or_tauleap_interval(onet.ptr, _p(xa, C.c_int32), tau, eps, seed, slot, it)
+    if ev < 0:
+        raise RuntimeError(f"oracle tau-leap failed: status {ev}")
     return xa, int(ev)
 
 
@@ -195,7 +206,9 @@ class OracleWE:
                              a["bin_coef2"].ctypes.data if two_d else None,
                              a["edges2"].ctypes.data if two_d else None,
                              cfg.m_targ, cfg.tau, self.seed, int(bool(cfg.recycle)),
-                             a["tgt_coef"].ctypes.data, float(cfg.tgt_thr), a["x_rec"].ctypes.data)
+                             a["tgt_coef"].ctypes.data, float(cfg.tgt_thr), a["x_rec"].ctypes.data,
+                             1 if getattr(cfg, "engine", "ssa") == "tauleap" else 0,
+                             float(getattr(cfg, "leap_eps", 0.03)))
         self.cptr = C.cast(C.pointer(self.cs), C.c_void_p)
         self.x = np.zeros(cap * S, np.int32)
         self.w = np.zeros(cap, np.float64)

@@ -213,6 +213,167 @@ int64_t or_ssa_interval(const or_net *net, int32_t *x, double tau,
     return fired;
 }
 
+/* ---- tau-leaping */
+typedef struct {
+    uint32_t key[2], slot, iter, n, buf[4];
+    int32_t idx;
+} leap_rng;
+
+static double leap_u(leap_rng *g)
+{
+    if (g->idx == 4) {
+        uint32_t ctr[4] = {g->n, g->slot, g->iter, 4u};
+        or_philox4x32_10(ctr, g->key, g->buf);
+        g->n += 1;
+        g->idx = 0;
+    }
+    return ((double)g->buf[g->idx++] + 0.5) * (1.0 / 4294967296.0);
+}
+
+/* Poisson(lam): inversion (sequential search) below 20; above, the PTRS
+ * transformed rejection of W. Hoermann, "The transformed rejection method
+ * for generating Poisson random variables", Insurance: Mathematics and
+ * Economics 12 (1993). */
+static int64_t leap_poisson(leap_rng *g, double lam)
+{
+    if (!(lam > 0.0)) return 0;
+    if (lam < 20.0) {
+        const double u = leap_u(g);
+        double p = exp(-lam), F = p;
+        int64_t k = 0;
+        while (u > F && k < 1000) {
+            k += 1;
+            p = p * lam / (double)k;
+            F = F + p;
+        }
+        return k;
+    }
+    const double slam = sqrt(lam), loglam = log(lam);
+    const double b = 0.931 + 2.53 * slam, a = -0.059 + 0.02483 * b;
+    const double invalpha = 1.1239 + 1.1328 / (b - 3.4), vr = 0.9277 - 3.6224 / (b - 2.0);
+    for (;;) {
+        const double U = leap_u(g) - 0.5, V = leap_u(g);
+        const double us = 0.5 - fabs(U);
+        const int64_t k = (int64_t)floor((2.0 * a / us + b) * U + lam + 0.43);
+        if (us >= 0.07 && V <= vr) return k;
+        if (k < 0 || (us < 0.013 && V > us)) continue;
+        if (log(V) + log(invalpha) - log(a / (us * us) + b) <= -lam + (double)k * loglam - lgamma((double)k + 1.0))
+            return k;
+    }
+}
+
+/* g_i of CGP 2006 (Eq. 27) for a species consumed with highest order hor
+ * and, in those reactions, multiplicity nu, at count x. */
+static double leap_g(int32_t hor, int32_t nu, double x)
+{
+    if (hor <= 1) return 1.0;
+    if (hor == 2) return nu == 1 ? 2.0 : 2.0 + 1.0 / (x - 1.0);
+    if (nu == 1) return 3.0;
+    if (nu == 2) return 1.5 * (2.0 + 1.0 / (x - 1.0));
+    return 3.0 + 1.0 / (x - 1.0) + 2.0 / (x - 2.0);
+}
+
+int64_t or_tauleap_interval(const or_net *net, int32_t *x, double tau, double eps,
+                            uint64_t seed, uint32_t slot, uint32_t iter)
+{
+    const int32_t R = net->R, S = net->S;
+    double *a = (double *)malloc(sizeof(double) * (size_t)R);
+    int64_t *K = (int64_t *)malloc(sizeof(int64_t) * (size_t)R);
+    int64_t *xn = (int64_t *)malloc(sizeof(int64_t) * (size_t)S);
+    int32_t *hor = (int32_t *)calloc((size_t)S, sizeof(int32_t));
+    int32_t *hnu = (int32_t *)calloc((size_t)S, sizeof(int32_t));
+    /* highest order of the reactions consuming each species, and its
+     * multiplicity there (the largest, if several) */
+    for (int32_t j = 0; j < R; ++j) {
+        int32_t order = 0;
+        for (int32_t p = net->reac_ptr[j]; p < net->reac_ptr[j + 1]; ++p) order += net->reac_mult[p];
+        for (int32_t p = net->reac_ptr[j]; p < net->reac_ptr[j + 1]; ++p) {
+            const int32_t sp = net->reac_species[p], nu = net->reac_mult[p];
+            if (order > hor[sp] || (order == hor[sp] && nu > hnu[sp])) {
+                hor[sp] = order;
+                hnu[sp] = nu;
+            }
+        }
+    }
+    uint32_t key[2];
+    seed_key(seed, key);
+    leap_rng g;
+    g.key[0] = key[0];
+    g.key[1] = key[1];
+    g.slot = slot;
+    g.iter = iter;
+    g.n = 0;
+    g.idx = 4;
+    double t = 0.0;
+    int64_t fired = 0;
+    uint32_t e = 0;
+    int32_t status = OR_OK;
+    for (;;) {
+        double a0 = 0.0;
+        for (int32_t j = 0; j < R; ++j) {
+            a[j] = or_propensity(net, x, j);
+            a0 = a0 + a[j];
+        }
+        if (!(a0 > 0.0)) break;
+        double tp = INFINITY;
+        for (int32_t i = 0; i < S; ++i) {
+            if (hor[i] == 0) continue;
+            double mu = 0.0, sig = 0.0;
+            for (int32_t j = 0; j < R; ++j) {
+                int32_t d = 0;
+                for (int32_t p = net->chg_ptr[j]; p < net->chg_ptr[j + 1]; ++p)
+                    if (net->chg_species[p] == i) d = net->chg_delta[p];
+                mu = mu + (double)d * a[j];
+                sig = sig + (double)d * (double)d * a[j];
+            }
+            const double bi = fmax(eps * (double)x[i] / leap_g(hor[i], hnu[i], (double)x[i]), 1.0);
+            if (mu != 0.0) tp = fmin(tp, bi / fabs(mu));
+            if (sig != 0.0) tp = fmin(tp, bi * bi / sig);
+        }
+        if (tp < 10.0 / a0) {
+            /* one exact event */
+            uint32_t ctr[4] = {e, slot, iter, 0u}, r[4];
+            or_philox4x32_10(ctr, key, r);
+            e += 1;
+            const double u1 = or_u53(r[0], r[1]), u2 = or_u53(r[2], r[3]);
+            const double dt = -log(1.0 - u1) / a0;
+            if (t + dt > tau) break;
+            t = t + dt;
+            fired += 1;
+            if (fire(net, x, select_reaction(a, R, u2 * a0)) != OR_OK) { status = OR_EOVERFLOW; break; }
+            continue;
+        }
+        for (;;) {
+            const double rest = tau - t;
+            const int last = !(tp < rest);
+            const double dt = last ? rest : tp;
+            for (int32_t i = 0; i < S; ++i) xn[i] = x[i];
+            for (int32_t j = 0; j < R; ++j) {
+                K[j] = leap_poisson(&g, a[j] * dt);
+                for (int32_t p = net->chg_ptr[j]; p < net->chg_ptr[j + 1]; ++p)
+                    xn[net->chg_species[p]] += K[j] * (int64_t)net->chg_delta[p];
+            }
+            int neg = 0, big = 0;
+            for (int32_t i = 0; i < S; ++i) {
+                neg |= xn[i] < 0;
+                big |= xn[i] > OR_COUNT_MAX;
+            }
+            if (neg) {
+                tp = tp * 0.5;
+                continue;
+            }
+            if (big) { status = OR_EOVERFLOW; break; }
+            for (int32_t i = 0; i < S; ++i) x[i] = (int32_t)xn[i];
+            for (int32_t j = 0; j < R; ++j) fired += K[j];
+            t = last ? tau : t + dt;
+            break;
+        }
+        if (status != OR_OK || !(t < tau)) break;
+    }
+    free(a); free(K); free(xn); free(hor); free(hnu);
+    return status != OR_OK ? status : fired;
+}
+
 double or_ssa_first_passage(const or_net *net, int32_t *x, double T,
                             const double *coef, double thr,
                             uint64_t seed, uint32_t traj, int64_t *events)
@@ -363,8 +524,10 @@ int32_t or_we_iterate(const or_net *net, const or_we_cfg *cfg, uint32_t iter,
     /* 1. propagate every walker through one interval */
     int64_t events = 0;
     for (int32_t k = 0; k < N; ++k) {
-        int64_t f = or_ssa_interval(net, x + (size_t)k * S, cfg->tau, cfg->seed,
-                                    (uint32_t)k, iter);
+        int64_t f = cfg->engine == 1
+                        ? or_tauleap_interval(net, x + (size_t)k * S, cfg->tau, cfg->leap_eps, cfg->seed,
+                                              (uint32_t)k, iter)
+                        : or_ssa_interval(net, x + (size_t)k * S, cfg->tau, cfg->seed, (uint32_t)k, iter);
         if (f < 0) { status = (int32_t)f; f = 0; }
         events += f;
     }

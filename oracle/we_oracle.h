@@ -67,6 +67,8 @@ typedef struct {
     const double *tgt_coef;   /* [S]  B = { x : sum_s tgt_coef_s x_s >= tgt_thr }   */
     double tgt_thr;
     const int32_t *x_rec;     /* [S]  recycling state A                            */
+    int32_t engine;           /* 0: exact SSA; 1: tau-leaping (or_tauleap_interval) */
+    double leap_eps;          /* tau-leaping error control epsilon                  */
 } or_we_cfg;
 
 /* Philox4x32-10: ten rounds of the Philox S-box with key schedule, per
@@ -93,6 +95,29 @@ int32_t or_validate(const or_net *net);
  * Returns the number of reactions fired, or a negative status. */
 int64_t or_ssa_interval(const or_net *net, int32_t *x, double tau,
                         uint64_t seed, uint32_t slot, uint32_t iter);
+
+/* Explicit tau-leaping over one interval (Sec. IV proposes combining WE with
+ * tau-leaping; the method is Gillespie's, J. Chem. Phys. 115, 1716 (2001),
+ * with the step-size bound of Cao, Gillespie and Petzold, J. Chem. Phys.
+ * 124, 044109 (2006)).  From t = 0, repeatedly:
+ *   1. propensities a_j and a0 as in or_ssa_interval; stop if a0 = 0;
+ *   2. tau' = min over reactant species i of
+ *        min(b_i / |mu_i|, b_i^2 / sigma_i^2),  b_i = max(eps x_i / g_i, 1),
+ *      mu_i = sum_j nu_ij a_j, sigma_i^2 = sum_j nu_ij^2 a_j (j ascending),
+ *      g_i from the highest order of the reactions that consume i (CGP 2006,
+ *      Eq. 27); zero denominators count as +infinity;
+ *   3. if tau' < 10 / a0: one exact direct-method event, with the SSA stream
+ *      (counter (e, slot, iter, 0)) and the same stopping rule at tau;
+ *   4. else leap dt = min(tau', tau - t): K_j ~ Poisson(a_j dt) for j
+ *      ascending; if some count would go negative, halve tau' and draw again;
+ *      otherwise x += sum_j K_j nu_j and t += dt (the leap that reaches tau
+ *      ends the interval).
+ * Poisson draws: inversion below a mean of 20, Hoermann's PTRS transformed
+ * rejection (1993) above; uniforms (r + 0.5) 2^-32 from the words of
+ * Philox(ctr = (n, slot, iter, 4), key = seed), n = 0, 1, ..., four per block.
+ * Returns the number of reactions fired, or a negative status. */
+int64_t or_tauleap_interval(const or_net *net, int32_t *x, double tau, double eps,
+                            uint64_t seed, uint32_t slot, uint32_t iter);
 
 /* Brute-force SSA first passage: from x (in place) run the direct method
  * for at most time T; stop at the first event after which

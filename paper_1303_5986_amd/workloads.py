@@ -128,6 +128,8 @@ class WEConfig:
     hist_hi: int = 0
     bin_coef2: Optional[np.ndarray] = None   # second grid axis (None: 1-D)
     edges2: Optional[np.ndarray] = None
+    engine: str = "ssa"                      # "ssa" (exact) or "tauleap"
+    leap_eps: float = 0.03                   # tau-leaping error control
 
     @property
     def n_bins1(self) -> int:
