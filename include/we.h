@@ -145,6 +145,15 @@ typedef struct {
     int32_t rw_reset;          /* 1: the flux matrix restarts after every event, so */
                                /*   each event uses only the intervals since the    */
                                /*   last one; 0: it accumulates from the start      */
+    int32_t engine;            /* propagation: 0 exact direct-method SSA; 1 explicit */
+                               /*   tau-leaping (Sec. IV proposes it; Gillespie     */
+                               /*   2001 with the step bound of Cao, Gillespie and  */
+                               /*   Petzold 2006, an exact event instead of a leap  */
+                               /*   where the bound is below 10/a0, leaps halved    */
+                               /*   when a count would go negative; leap uniforms   */
+                               /*   from Philox(n, slot, iter, 4)).  Lane kernel,   */
+                               /*   mass action, S <= 8, R <= 16, no batches        */
+    double leap_eps;           /* tau-leaping error control epsilon, in (0, 1)      */
 } we_params;
 
 /* Device bytes a sim needs (walker buffers, series, scratch). */

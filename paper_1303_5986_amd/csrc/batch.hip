@@ -292,6 +292,10 @@ extern "C" we_status we_batch_create(int32_t n, const we_network *const *nets, c
             we_batch_destroy(b);
             return we_fail(WE_EINVAL, "reweighting is not supported inside a batch");
         }
+        if (p.engine != 0) {
+            we_batch_destroy(b);
+            return we_fail(WE_EINVAL, "tau-leaping is not supported inside a batch");
+        }
         if (!nets[i]->hill.empty()) {
             we_batch_destroy(b);
             return we_fail(WE_EINVAL, "Hill-type rates are not supported inside a batch");

@@ -34,12 +34,16 @@
 // grows steeply along the progress coordinate), so a fixed walker-per-lane
 // assignment would leave most lanes of a wave idle while its slowest walker
 // finishes.
-template <int SMAX, int RMAX, bool HILL>
+template <int SMAX, int RMAX, bool HILL, bool LEAP>
 __device__ __forceinline__ void lane_pool(const SimArgs &a, int32_t *__restrict__ xs, int32_t *wrows) {
     constexpr bool REG = RMAX <= LANE_REG_RMAX;
     if constexpr (!REG) lane_stage_rows<SMAX>(a, wrows);
     LaneNet<SMAX, RMAX, HILL> net;
     net.load(a, wrows);
+    uint32_t hor[LEAP ? SMAX : 1], hnu[LEAP ? SMAX : 1];
+    if constexpr (LEAP) leap_orders(net, hor, hnu);
+    LeapRng lr;
+    lr.reset();
     const int lane = threadIdx.x & 63;
     const uint32_t iter = *a.iter_dev;
     const double tau = a.tau;
@@ -74,13 +78,19 @@ __device__ __forceinline__ void lane_pool(const SimArgs &a, int32_t *__restrict_
                         gslot = g;
                         xr = xs + gslot * a.S;
                         w.begin(x, xr, a.S, k, a.seeds[run]);
+                        if constexpr (LEAP) lr.reset();
                         active = true;
                     }
                 }
             }
         }
         if (!__ballot(active) && exhausted) break;
-        if (active && !lane_event(net, w, x, iter, tau)) {
+        bool more = false;
+        if (active) {
+            if constexpr (LEAP) more = lane_leap_step(net, w, lr, x, hor, hnu, iter, tau, a.leap_eps);
+            else more = lane_event(net, w, x, iter, tau);
+        }
+        if (active && !more) {
             lane_finish(a, w, x, xr, gslot);
             active = false;
         }
@@ -91,7 +101,7 @@ template <int SMAX, int RMAX>
 __global__ __launch_bounds__(256) void ssa_lane_pool_kernel(SimArgs a, int32_t *__restrict__ xs) {
     constexpr int ROWS = RMAX <= LANE_REG_RMAX ? 1 : RMAX * LaneRow<SMAX>::W;
     __shared__ int32_t rows[4 * ROWS];
-    lane_pool<SMAX, RMAX, false>(a, xs, rows + (threadIdx.x >> 6) * ROWS);
+    lane_pool<SMAX, RMAX, false, false>(a, xs, rows + (threadIdx.x >> 6) * ROWS);
 }
 
 // The same for networks with Hill-type rates (Sec. III.C).
@@ -99,7 +109,15 @@ template <int SMAX, int RMAX>
 __global__ __launch_bounds__(256) void ssa_lane_hill_kernel(SimArgs a, int32_t *__restrict__ xs) {
     constexpr int ROWS = RMAX <= LANE_REG_RMAX ? 1 : RMAX * LaneRow<SMAX>::W;
     __shared__ int32_t rows[4 * ROWS];
-    lane_pool<SMAX, RMAX, true>(a, xs, rows + (threadIdx.x >> 6) * ROWS);
+    lane_pool<SMAX, RMAX, true, false>(a, xs, rows + (threadIdx.x >> 6) * ROWS);
+}
+
+// The same with tau-leaping instead of the exact direct method.
+template <int SMAX, int RMAX>
+__global__ __launch_bounds__(256) void ssa_lane_leap_kernel(SimArgs a, int32_t *__restrict__ xs) {
+    constexpr int ROWS = RMAX <= LANE_REG_RMAX ? 1 : RMAX * LaneRow<SMAX>::W;
+    __shared__ int32_t rows[4 * ROWS];
+    lane_pool<SMAX, RMAX, false, true>(a, xs, rows + (threadIdx.x >> 6) * ROWS);
 }
 
 // Fixed assignment, one walker per lane: used for the two largest variants,
@@ -122,11 +140,12 @@ __global__ __launch_bounds__(256) void ssa_lane_kernel(SimArgs a, int32_t *__res
 
 namespace {
 // Persistent grid: as many blocks as stay resident on the device.
-template <int SMAX, int RMAX, bool HILL>
+template <int SMAX, int RMAX, int VARIANT>   // 0: exact, 1: Hill-type rates, 2: tau-leaping
 unsigned pool_blocks(const SimArgs &a) {
     static int per_cu = -1, n_cu = 0;   // one cache per kernel
     void (*kernel)(SimArgs, int32_t *);
-    if constexpr (HILL) kernel = ssa_lane_hill_kernel<SMAX, RMAX>;
+    if constexpr (VARIANT == 1) kernel = ssa_lane_hill_kernel<SMAX, RMAX>;
+    else if constexpr (VARIANT == 2) kernel = ssa_lane_leap_kernel<SMAX, RMAX>;
     else kernel = ssa_lane_pool_kernel<SMAX, RMAX>;
     if (per_cu < 0) {
         int dev = 0;
@@ -151,14 +170,20 @@ hipError_t launch_fixed(const SimArgs &a, int32_t *xs, hipStream_t st) {
 
 template <int SMAX, int RMAX>
 hipError_t launch_pool(const SimArgs &a, int32_t *xs, hipStream_t st) {
-    hipLaunchKernelGGL((ssa_lane_pool_kernel<SMAX, RMAX>), dim3(pool_blocks<SMAX, RMAX, false>(a)),
+    hipLaunchKernelGGL((ssa_lane_pool_kernel<SMAX, RMAX>), dim3(pool_blocks<SMAX, RMAX, 0>(a)),
                        dim3(256), 0, st, a, xs);
     return hipGetLastError();
 }
 
 template <int SMAX, int RMAX>
 hipError_t launch_hill(const SimArgs &a, int32_t *xs, hipStream_t st) {
-    hipLaunchKernelGGL((ssa_lane_hill_kernel<SMAX, RMAX>), dim3(pool_blocks<SMAX, RMAX, true>(a)),
+    hipLaunchKernelGGL((ssa_lane_hill_kernel<SMAX, RMAX>), dim3(pool_blocks<SMAX, RMAX, 1>(a)),
+                       dim3(256), 0, st, a, xs);
+    return hipGetLastError();
+}
+template <int SMAX, int RMAX>
+hipError_t launch_leap(const SimArgs &a, int32_t *xs, hipStream_t st) {
+    hipLaunchKernelGGL((ssa_lane_leap_kernel<SMAX, RMAX>), dim3(pool_blocks<SMAX, RMAX, 2>(a)),
                        dim3(256), 0, st, a, xs);
     return hipGetLastError();
 }
@@ -167,6 +192,13 @@ hipError_t launch_hill(const SimArgs &a, int32_t *xs, hipStream_t st) {
 // Launch helper: picks the smallest register footprint that holds the
 // network.  The queue variants need the queue built by launch_work_queue.
 hipError_t launch_ssa_lane(const SimArgs &a, int32_t *xs, hipStream_t st) {
+    if (a.engine == 1) {
+        if (a.hill) return hipErrorInvalidValue;
+        if (a.S <= 1 && a.R <= 4) return launch_leap<1, 4>(a, xs, st);
+        if (a.S <= 2 && a.R <= 8) return launch_leap<2, 8>(a, xs, st);
+        if (a.S <= 8 && a.R <= 16) return launch_leap<8, 16>(a, xs, st);
+        return hipErrorInvalidValue;
+    }
     if (a.hill) {
         if (a.S <= 2 && a.R <= 8) return launch_hill<2, 8>(a, xs, st);
         if (a.S <= 8 && a.R <= 16) return launch_hill<8, 16>(a, xs, st);

@@ -220,6 +220,243 @@ __device__ __forceinline__ bool lane_event(const LaneNet<SMAX, RMAX, HILL> &net,
     return true;
 }
 
+// ---------------------------------------------------------------- tau-leaping
+// An engine for the propagation step that WE leaves open (Sec. IV suggests
+// tau-leaping): explicit leaps (Gillespie 2001) with the step bound of Cao,
+// Gillespie and Petzold (2006), one exact event instead of a leap where the
+// bound is below 10 / a0, and the leap halved when a count would go negative.
+
+// The walker's leap stream: the four words of Philox(n, slot, iter, 4), in
+// turn, as uniforms (r + 0.5) 2^-32.
+struct LeapRng {
+    uint32_t n, idx, b0, b1, b2, b3;
+    __device__ __forceinline__ void reset() {
+        n = 0;
+        idx = 4;
+    }
+    __device__ __forceinline__ double u(uint32_t slot, uint32_t iter, uint32_t k0, uint32_t k1) {
+        if (idx == 4) {
+            const U4 r = philox4x32_10(n, slot, iter, 4u, k0, k1);
+            b0 = r.x;
+            b1 = r.y;
+            b2 = r.z;
+            b3 = r.w;
+            n += 1;
+            idx = 0;
+        }
+        const uint32_t v = idx == 0 ? b0 : idx == 1 ? b1 : idx == 2 ? b2 : b3;
+        idx += 1;
+        return ((double)v + 0.5) * (1.0 / 4294967296.0);
+    }
+};
+
+// Poisson(lam): inversion by sequential search below 20; above, Hoermann's
+// PTRS transformed rejection (1993).
+__device__ __forceinline__ int64_t leap_poisson(LeapRng &g, double lam, uint32_t slot, uint32_t iter, uint32_t k0,
+                                                uint32_t k1) {
+    if (!(lam > 0.0)) return 0;
+    if (lam < 20.0) {
+        const double u = g.u(slot, iter, k0, k1);
+        double p = exp(-lam), F = p;
+        int64_t k = 0;
+        while (u > F && k < 1000) {
+            k += 1;
+            p = p * lam / (double)k;
+            F = F + p;
+        }
+        return k;
+    }
+    const double slam = sqrt(lam), loglam = log(lam);
+    const double b = 0.931 + 2.53 * slam, a = -0.059 + 0.02483 * b;
+    const double invalpha = 1.1239 + 1.1328 / (b - 3.4), vr = 0.9277 - 3.6224 / (b - 2.0);
+    for (;;) {
+        const double U = g.u(slot, iter, k0, k1) - 0.5, V = g.u(slot, iter, k0, k1);
+        const double us = 0.5 - fabs(U);
+        const int64_t k = (int64_t)floor((2.0 * a / us + b) * U + lam + 0.43);
+        if (us >= 0.07 && V <= vr) return k;
+        if (k < 0 || (us < 0.013 && V > us)) continue;
+        if (log(V) + log(invalpha) - log(a / (us * us) + b) <= -lam + (double)k * loglam - lgamma((double)k + 1.0))
+            return k;
+    }
+}
+
+// g_i of the step bound for a species consumed with highest order hor and
+// multiplicity nu there, at count x (Cao, Gillespie, Petzold 2006, Eq. 27).
+__device__ __forceinline__ double leap_g(uint32_t hor, uint32_t nu, double x) {
+    if (hor <= 1) return 1.0;
+    if (hor == 2) return nu == 1 ? 2.0 : 2.0 + 1.0 / (x - 1.0);
+    if (nu == 1) return 3.0;
+    if (nu == 2) return 1.5 * (2.0 + 1.0 / (x - 1.0));
+    return 3.0 + 1.0 / (x - 1.0) + 2.0 / (x - 2.0);
+}
+
+// The change of species s by reaction j, from the int8 delta rows.
+template <int SMAX, int RMAX, bool HILL>
+__device__ __forceinline__ int32_t lane_delta(const LaneNet<SMAX, RMAX, HILL> &net, int j, int s) {
+    constexpr int W = LaneRow<SMAX>::W;
+    const uint32_t word = LaneNet<SMAX, RMAX, HILL>::REG ? net.drow[LaneNet<SMAX, RMAX, HILL>::REG ? j : 0][s >> 2]
+                                                        : (uint32_t)net.rows[j * W + (s >> 2)];
+    return (int32_t)(word << (24 - 8 * (s & 3))) >> 24;
+}
+
+// Highest order of the reactions consuming each species, and the species'
+// multiplicity there (the largest, if several), from the descriptors.
+template <int SMAX, int RMAX, bool HILL>
+__device__ __forceinline__ void leap_orders(const LaneNet<SMAX, RMAX, HILL> &net, uint32_t (&hor)[SMAX],
+                                            uint32_t (&hnu)[SMAX]) {
+    constexpr bool REG = LaneNet<SMAX, RMAX, HILL>::REG;
+#pragma unroll
+    for (int s = 0; s < SMAX; ++s) {
+        hor[s] = 0;
+        hnu[s] = 0;
+    }
+#pragma unroll
+    for (int j = 0; j < RMAX; ++j) {
+        if (j < net.R) {
+            const LaneRxn d = REG ? net.rx[REG ? j : 0] : lane_rxn(net.desc, j);
+            const uint32_t order = d.nu1 + d.nu2;
+#pragma unroll
+            for (int s = 0; s < SMAX; ++s) {
+                const uint32_t nu = (d.nu1 && d.s1 == (uint32_t)s) ? d.nu1 : (d.nu2 && d.s2 == (uint32_t)s) ? d.nu2 : 0u;
+                if (nu && (order > hor[s] || (order == hor[s] && nu > hnu[s]))) {
+                    hor[s] = order;
+                    hnu[s] = nu;
+                }
+            }
+        }
+    }
+}
+
+// One tau-leaping step (a leap or an exact event); false once the walker's
+// interval is over.
+template <int SMAX, int RMAX, bool HILL>
+__device__ __forceinline__ bool lane_leap_step(const LaneNet<SMAX, RMAX, HILL> &net, LaneWalker &w, LeapRng &g,
+                                               int32_t (&x)[SMAX], const uint32_t (&hor)[SMAX],
+                                               const uint32_t (&hnu)[SMAX], uint32_t iter, double tau, double eps) {
+    constexpr bool REG = LaneNet<SMAX, RMAX, HILL>::REG;
+    double prop[RMAX];
+    double a0 = 0.0;
+#pragma unroll
+    for (int j = 0; j < RMAX; ++j) {
+        const LaneRxn d = REG ? net.rx[REG ? j : 0] : lane_rxn(net.desc, j);
+        prop[j] = 0.0;
+        if (j < net.R) {
+            prop[j] = lane_propensity<SMAX>(d, x);
+            a0 = a0 + prop[j];
+        }
+    }
+    if (!(a0 > 0.0)) return false;
+    double tp = __builtin_huge_val();
+#pragma unroll
+    for (int s = 0; s < SMAX; ++s) {
+        if (hor[s] != 0) {
+            double mu = 0.0, sig = 0.0;
+#pragma unroll
+            for (int j = 0; j < RMAX; ++j) {
+                if (j < net.R) {
+                    const double dd = (double)lane_delta(net, j, s);
+                    mu = mu + dd * prop[j];
+                    sig = sig + dd * dd * prop[j];
+                }
+            }
+            const double bi = fmax(eps * (double)x[s] / leap_g(hor[s], hnu[s], (double)x[s]), 1.0);
+            if (mu != 0.0) tp = fmin(tp, bi / fabs(mu));
+            if (sig != 0.0) tp = fmin(tp, bi * bi / sig);
+        }
+    }
+    if (tp < 10.0 / a0) {
+        // one exact event, as in lane_event
+        const U4 r = philox4x32_10(w.e, w.slot, iter, 0u, w.k0, w.k1);
+        w.e += 1;
+        const double u1 = uniform53(r.x, r.y);
+        const double u2 = uniform53(r.z, r.w);
+        const double dt = -log(1.0 - u1) / a0;
+        if (w.t + dt > tau) return false;
+        w.t = w.t + dt;
+        const double target = u2 * a0;
+        double cum = 0.0;
+        int32_t jsel = -1, last_pos = -1;
+#pragma unroll
+        for (int j = 0; j < RMAX; ++j) {
+            if (j < net.R) {
+                cum = cum + prop[j];
+                if (prop[j] > 0.0) last_pos = j;
+                if (jsel < 0 && cum > target) jsel = j;
+            }
+        }
+        if (jsel < 0) jsel = last_pos;
+        w.fired += 1;
+        int32_t any = 0;
+#pragma unroll
+        for (int s = 0; s < SMAX; ++s) {
+            int32_t dv = 0;
+#pragma unroll
+            for (int j = 0; j < RMAX; ++j)
+                if (j == jsel) dv = lane_delta(net, j, s);
+            x[s] += dv;
+            any |= x[s];
+        }
+        if (any & ~WE_COUNT_MAX_DEV) {
+            w.bad = true;
+            return false;
+        }
+        return true;
+    }
+    for (;;) {
+        const double rest = tau - w.t;
+        const bool last = !(tp < rest);
+        const double dt = last ? rest : tp;
+        int64_t xn[SMAX];
+#pragma unroll
+        for (int s = 0; s < SMAX; ++s) xn[s] = x[s];
+        uint32_t kf = 0;
+        // one reaction at a time (a single copy of the sampler); its
+        // propensity and delta row are picked by register selects
+#pragma unroll 1
+        for (int j = 0; j < net.R; ++j) {
+            double pj = 0.0;
+#pragma unroll
+            for (int jj = 0; jj < RMAX; ++jj) pj = (jj == j) ? prop[jj] : pj;
+            const int64_t K = leap_poisson(g, pj * dt, w.slot, iter, w.k0, w.k1);
+            kf += (uint32_t)K;
+#pragma unroll
+            for (int s = 0; s < SMAX; ++s) {
+                int32_t d = 0;
+                if constexpr (REG) {
+#pragma unroll
+                    for (int jj = 0; jj < RMAX; ++jj) d = (jj == j) ? lane_delta(net, jj, s) : d;
+                } else {
+                    d = lane_delta(net, j, s);
+                }
+                xn[s] += K * (int64_t)d;
+            }
+        }
+        bool neg = false, big = false;
+#pragma unroll
+        for (int s = 0; s < SMAX; ++s) {
+            neg = neg || xn[s] < 0;
+            big = big || xn[s] > WE_COUNT_MAX_DEV;
+        }
+        if (neg) {
+            tp = tp * 0.5;
+            continue;
+        }
+        if (big) {
+            w.bad = true;
+            return false;
+        }
+#pragma unroll
+        for (int s = 0; s < SMAX; ++s) x[s] = (int32_t)xn[s];
+        w.fired += kf;
+        if (last) {
+            w.t = tau;
+            return false;
+        }
+        w.t = w.t + dt;
+        return w.t < tau;
+    }
+}
+
 template <int SMAX>
 __device__ __forceinline__ void lane_finish(const SimArgs &a, const LaneWalker &w, const int32_t (&x)[SMAX],
                                             int32_t *__restrict__ xr, size_t gslot) {

@@ -75,6 +75,8 @@ struct SimArgs {
     const DepEntry *__restrict__ deps;   // dependency entries with descriptors
     const HillDesc *__restrict__ hill;   // [R padded] Hill-type rates (null: none)
     int32_t S, R;
+    int32_t engine;                      // 0: exact SSA, 1: tau-leaping (lane kernel)
+    double leap_eps;                     // tau-leaping error control
     // runs
     int32_t n_runs, cap, n_bins, m_targ, max_iters;
     double tau;

@@ -350,6 +350,9 @@ we_status check_params(const we_network *net, const we_grid *g, const we_params 
     if (p->n_joint < 0 || p->n_joint > 5) return fail(WE_EINVAL, "n_joint must be in [0, 5]");
     if (p->record_iters < 0) return fail(WE_EINVAL, "record_iters must be >= 0");
     if (p->rw_period < 0) return fail(WE_EINVAL, "rw_period must be >= 0");
+    if (p->engine != 0 && p->engine != 1) return fail(WE_EINVAL, "engine must be 0 (SSA) or 1 (tau-leaping)");
+    if (p->engine == 1 && !(p->leap_eps > 0.0 && p->leap_eps < 1.0))
+        return fail(WE_EINVAL, "leap_eps must lie in (0, 1)");
     if (p->rw_period > 0 && grid_bins(g) > WE_RW_MAX_BINS)
         return fail(WE_EINVAL, "reweighting needs at most 512 bins");
     if (p->rw_period > 0 && (int64_t)p->n_runs * grid_bins(g) * grid_bins(g) > ((int64_t)1 << 31))
@@ -400,6 +403,8 @@ extern "C" we_status we_init(const we_network *net, const we_grid *g, const we_p
     const int32_t nh = p->hist_hi >= p->hist_lo ? p->hist_hi - p->hist_lo + 1 : 0;
     int32_t kernel = p->kernel;
     const bool hill = !net->hill.empty();
+    if (p->engine == 1 && (hill || kernel == WE_KERNEL_WAVE || S > 8 || net->R > 16 || net->max_delta > 127))
+        return fail(WE_EINVAL, "tau-leaping runs on the lane kernel only (mass action, S <= 8, R <= 16)");
     if (hill && (kernel == WE_KERNEL_WAVE || S > 8 || net->R > 16 || net->max_delta > 127))
         return fail(WE_EINVAL, "Hill-type rates run on the lane kernel only (S <= 8, R <= 16)");
     if (kernel == WE_KERNEL_AUTO)
@@ -438,6 +443,8 @@ extern "C" we_status we_init(const we_network *net, const we_grid *g, const we_p
     a.dep_ptr = net->d_dep_ptr; a.dep = net->d_dep;
     a.rinfo = net->d_rinfo; a.deps = net->d_deps;
     a.hill = hill ? net->d_hill : nullptr;
+    a.engine = p->engine;
+    a.leap_eps = p->engine == 1 ? p->leap_eps : 0.0;
     a.S = S; a.R = net->R;
     a.n_runs = n_runs; a.cap = cap; a.n_bins = NB; a.m_targ = M; a.max_iters = max_iters;
     a.tau = p->tau;

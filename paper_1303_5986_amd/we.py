@@ -63,7 +63,8 @@ class _Params(C.Structure):
                 ("tgt_thr", C.c_double), ("x_rec", C.c_void_p), ("hist_species", C.c_int32),
                 ("hist_lo", C.c_int32), ("hist_hi", C.c_int32), ("n_joint", C.c_int32),
                 ("joint_species", C.c_void_p), ("joint_bins", C.c_int32), ("joint_width", C.c_int32),
-                ("record_iters", C.c_int32), ("rw_period", C.c_int32), ("rw_reset", C.c_int32)]
+                ("record_iters", C.c_int32), ("rw_period", C.c_int32), ("rw_reset", C.c_int32),
+                ("engine", C.c_int32), ("leap_eps", C.c_double)]
 
 
 class _TrainParams(C.Structure):
@@ -195,7 +196,7 @@ class Sim:
                  hist_species: int = 0, hist_lo: int = 0, hist_hi: int = -1,
                  joint_species: Sequence[int] = (), joint_bins: int = 16, joint_width: int = 64,
                  record_iters: int = 0, rw_period: int = 0, rw_reset: bool = False,
-                 bin_coef2=None, edges2=None, device=None):
+                 bin_coef2=None, edges2=None, engine: str = "ssa", leap_eps: float = 0.03, device=None):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("no HIP device: libwe.so runs on MI355X only")
@@ -230,7 +231,8 @@ class Sim:
                               _ptr(k["tgt"]), float(tgt_thr), _ptr(k["xrec"]),
                               int(hist_species), int(hist_lo), int(hist_hi),
                               len(joint_species), k["joint"].ctypes.data, int(joint_bins),
-                              int(joint_width), int(record_iters), int(rw_period), int(bool(rw_reset)))
+                              int(joint_width), int(record_iters), int(rw_period), int(bool(rw_reset)),
+                              {"ssa": 0, "tauleap": 1}[engine], float(leap_eps))
         self.n_joint = len(joint_species)
         self.joint_cells = int(joint_bins) ** self.n_joint if self.n_joint else 0
         self.nh = hist_hi - hist_lo + 1 if hist_hi >= hist_lo else 0
@@ -422,7 +424,8 @@ def sim_from_config(cfg, *, kernel: int = WE_KERNEL_AUTO, max_iters: Optional[in
                hist_hi=cfg.hist_hi,
                joint_species=getattr(cfg, "joint_species", ()) if joint else (),
                record_iters=record_iters, rw_period=rw_period, rw_reset=rw_reset,
-               bin_coef2=getattr(cfg, "bin_coef2", None), edges2=getattr(cfg, "edges2", None))
+               bin_coef2=getattr(cfg, "bin_coef2", None), edges2=getattr(cfg, "edges2", None),
+               engine=getattr(cfg, "engine", "ssa"), leap_eps=getattr(cfg, "leap_eps", 0.03))
 
 
 def mlp_loss_grad(n_in: int, params, feat, x, y):
@@ -506,7 +509,9 @@ class Batch:
                                 k["seeds"].ctypes.data, k["x0"].ctypes.data, int(bool(c.recycle)),
                                 _ptr(k["tgt"]), float(c.tgt_thr), _ptr(k["xrec"]),
                                 int(c.hist_species), int(c.hist_lo), int(c.hist_hi),
-                                0, k["joint"].ctypes.data, 1, 1, 0)
+                                0, k["joint"].ctypes.data, 1, 1, 0, 0, 0,
+                                {"ssa": 0, "tauleap": 1}[getattr(c, "engine", "ssa")],
+                                float(getattr(c, "leap_eps", 0.03)))
         nets = (C.c_void_p * n)(*[net.handle.value for net in self.networks])
         self.stream = torch.cuda.current_stream()
         h = C.c_void_p()
