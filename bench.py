@@ -409,6 +409,63 @@ def experiment_switch_mfpt(args):
     print(json.dumps(out), flush=True)
 
 
+def experiment_tauleap(args):
+    """The tau-leaping engine (Sec. IV proposes combining WE with it) against
+    the exact direct method on two workloads: the default Schloegl benchmark
+    (2048 replicas; leaps only pay in the upper well) and a high-copy
+    birth-death chain (k = 1e4, gamma = 1, stationary law Poisson(1e4), 40
+    bins of width 10 around the mean, 16 walkers per bin, tau = 0.1, 256
+    replicas).  Time per WE iteration, reactions fired per second, and the
+    accuracy of the weighted ensemble's mean and variance (birth-death) or of
+    the flux (Schloegl)."""
+    import dataclasses
+
+    import torch
+    from paper_1303_5986_amd import we, workloads as wl
+
+    W, K = args.warmup, args.steps
+    out = {"metric": "tau-leaping vs exact SSA, WE iteration time and accuracy", "leap_eps": 0.03,
+           "workloads": {}}
+    bd_net = wl.birth_death(k=1e4, gamma=1.0)
+    bd = wl.WEConfig(name="birth_death_1e4", net=bd_net, x0=np.array([10000], np.int32),
+                     bin_coef=np.array([1.0]), edges=wl.uniform_edges(9800.0, 10200.0, 40), m_targ=16,
+                     tau=0.1, n_iters=W + K, seeds=np.arange(1, 257, dtype=np.uint64))
+    sch = wl.schlogl_config(n_runs=args.runs, seed0=1, n_iters=W + K)
+    for name, base in (("birth_death_1e4", bd), ("schlogl", sch)):
+        res = {}
+        for engine in ("ssa", "tauleap"):
+            cfg = dataclasses.replace(base, engine=engine, leap_eps=0.03)
+            sim = we.sim_from_config(cfg, kernel=we.WE_KERNEL_LANE, max_iters=W + K)
+            sim.step(W)
+            sim.synchronize()
+            ev0 = sim.counters()[0]
+            sim.graph_capture(2)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sim.graph_replay(K // 2)
+            sim.synchronize()
+            dt = time.perf_counter() - t0
+            ev = sim.counters()[0] - ev0
+            r = {"ms_per_iteration": dt * 1e3 / K, "reactions_per_s": ev / dt, "reactions_per_iteration": ev / K}
+            if name == "birth_death_1e4":
+                m1 = m2 = 0.0
+                for run in range(len(cfg.seeds)):
+                    x, w, _, _ = sim.walkers(run)
+                    m1 += float(np.dot(w, x[:, 0]))
+                    m2 += float(np.dot(w, x[:, 0].astype(np.float64) ** 2))
+                m1 /= len(cfg.seeds)
+                m2 /= len(cfg.seeds)
+                r.update(mean=m1, var=m2 - m1 * m1, mean_exact=1e4, var_exact=1e4)
+            else:
+                flux = np.stack([sim.flux(run, W, K) for run in range(len(cfg.seeds))])
+                r["mean_flux_per_s"] = float(flux.mean() / cfg.tau)
+            res[engine] = r
+        res["speedup"] = res["ssa"]["ms_per_iteration"] / res["tauleap"]["ms_per_iteration"]
+        out["workloads"][name] = res
+        print(json.dumps({name: {"speedup": res["speedup"]}}), file=sys.stderr, flush=True)
+    print(json.dumps(out), flush=True)
+
+
 def experiment_batch(args):
     """64 independent WE runs on seeded networks of 8..3680 reactions and
     256..8192 walker slots: one batch (persistent propagation launches,
@@ -474,7 +531,8 @@ def main():
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB five times "
                          "(reference kernel for scaling the HBM byte counters)")
-    ap.add_argument("--experiment", default="", choices=["", "toggle_mfpt", "batch", "schlogl_rw", "switch_mfpt"])
+    ap.add_argument("--experiment", default="",
+                    choices=["", "toggle_mfpt", "batch", "schlogl_rw", "switch_mfpt", "tauleap"])
     ap.add_argument("--switch-runs", type=int, default=64, help="replicas in the switch experiment")
     ap.add_argument("--rw-runs", type=int, default=32,
                     help="replicas in the reweighting experiment")
@@ -506,6 +564,9 @@ def main():
         return
     if args.experiment == "switch_mfpt":
         experiment_switch_mfpt(args)
+        return
+    if args.experiment == "tauleap":
+        experiment_tauleap(args)
         return
     if args.calibrate_copy:
         import torch
