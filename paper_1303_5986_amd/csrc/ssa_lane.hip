@@ -85,14 +85,16 @@ __device__ __forceinline__ void lane_pool(const SimArgs &a, int32_t *__restrict_
             }
         }
         if (!__ballot(active) && exhausted) break;
-        bool more = false;
-        if (active) {
-            if constexpr (LEAP) more = lane_leap_step(net, w, lr, x, hor, hnu, iter, tau, a.leap_eps);
-            else more = lane_event(net, w, x, iter, tau);
-        }
-        if (active && !more) {
-            lane_finish(a, w, x, xr, gslot);
-            active = false;
+        if constexpr (LEAP) {
+            if (active && !lane_leap_step(net, w, lr, x, hor, hnu, iter, tau, a.leap_eps)) {
+                lane_finish(a, w, x, xr, gslot);
+                active = false;
+            }
+        } else {
+            if (active && !lane_event(net, w, x, iter, tau)) {
+                lane_finish(a, w, x, xr, gslot);
+                active = false;
+            }
         }
     }
 }
