@@ -24,7 +24,7 @@
 
 // Idle lanes refill once at least this many of the wave's lanes are idle.
 #ifndef LANE_REFILL_MIN
-#define LANE_REFILL_MIN 4
+#define LANE_REFILL_MIN 8
 #endif
 
 // Persistent lane kernel: every lane runs walkers from the work queue (see
