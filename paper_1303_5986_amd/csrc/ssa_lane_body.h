@@ -172,7 +172,7 @@ __device__ __forceinline__ bool lane_event(const LaneNet<SMAX, RMAX, HILL> &net,
     w.e += 1;
     const double u1 = uniform53(r.x, r.y);
     const double u2 = uniform53(r.z, r.w);
-    const double dt = -log(1.0 - u1) / a0;
+    const double dt = neg_log1m(u1) * recip(a0);
     if (w.t + dt > tau) return false;
     w.t = w.t + dt;
     const double target = u2 * a0;
@@ -370,7 +370,7 @@ __device__ __forceinline__ bool lane_leap_step(const LaneNet<SMAX, RMAX, HILL> &
         w.e += 1;
         const double u1 = uniform53(r.x, r.y);
         const double u2 = uniform53(r.z, r.w);
-        const double dt = -log(1.0 - u1) / a0;
+        const double dt = neg_log1m(u1) * recip(a0);
         if (w.t + dt > tau) return false;
         w.t = w.t + dt;
         const double target = u2 * a0;

@@ -161,7 +161,7 @@ __device__ inline void wave_walker_t(const SimArgs &a, const T &tab, int32_t *__
         if (!(a0 > 0.0)) break;
         if ((e & 63u) == 0u) {
             const U4 rnd = philox4x32_10(e + (uint32_t)lane, (uint32_t)k, iter, 0u, k0, k1);
-            rexp = -log(1.0 - uniform53(rnd.x, rnd.y));
+            rexp = neg_log1m(uniform53(rnd.x, rnd.y));
             ru2 = uniform53(rnd.z, rnd.w);
         }
         const double ex = lane_value(rexp, (int)(e & 63u));

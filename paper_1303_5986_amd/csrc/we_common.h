@@ -167,6 +167,54 @@ __device__ __forceinline__ double uniform53(uint32_t a, uint32_t b) {
     return (double)m * 0x1.0p-53;
 }
 
+// 1/d for a positive normal double: the hardware reciprocal estimate and two
+// Newton steps r <- r + r (1 - d r); within an ulp or so of the quotient.
+__device__ __forceinline__ double recip(double d) {
+    double r = __builtin_amdgcn_rcp(d);
+    r = fma(r, fma(-d, r, 1.0), r);
+    r = fma(r, fma(-d, r, 1.0), r);
+    return r;
+}
+
+// -log(1 - u) for u in [0, 1) a 53-bit uniform, in FP64, within about one
+// ulp: the exponential waiting-time variate of the direct method (Sec. II.A).
+// With y = 1 - u (exact) = 2^k m, m in [sqrt(1/2), sqrt(2)):
+//   log m = 2 atanh(s), s = f / (2 + f), f = m - 1 (exact),
+//         = f - (f^2/2 - s (f^2/2 + R)),  R = sum_{i=1..10} 2 s^(2i) / (2i + 1)
+// (the atanh series; |s| <= 0.1716, so the first omitted term is below
+// 1e-18 relative), and k ln 2 is added as k ln2_hi (exact: ln2_hi has 42
+// significant bits) plus k ln2_lo.  This is the argument reduction of the
+// classical fdlibm logarithm with Taylor coefficients; about 40 instructions
+// against twice that for the general-purpose log, whose extra precision the
+// waiting time does not need.
+__device__ __forceinline__ double neg_log1m(double u) {
+    constexpr double LN2_HI = 0x1.62e42fefa38p-1, LN2_LO = 0x1.ef35793c7673p-45;
+    int k;
+    double m = frexp(1.0 - u, &k);                 // 1 - u in (2^-53, 1], m in [0.5, 1)
+    if (m < 0x1.6a09e667f3bcdp-1) {                // below sqrt(1/2)
+        m = m + m;
+        k -= 1;
+    }
+    const double f = m - 1.0;
+    const double s = f * recip(2.0 + f);
+    const double z = s * s;
+    double R = 2.0 / 21.0;
+    R = fma(z, R, 2.0 / 19.0);
+    R = fma(z, R, 2.0 / 17.0);
+    R = fma(z, R, 2.0 / 15.0);
+    R = fma(z, R, 2.0 / 13.0);
+    R = fma(z, R, 2.0 / 11.0);
+    R = fma(z, R, 2.0 / 9.0);
+    R = fma(z, R, 2.0 / 7.0);
+    R = fma(z, R, 2.0 / 5.0);
+    R = fma(z, R, 2.0 / 3.0);
+    R = R * z;
+    const double hfsq = 0.5 * f * f;
+    const double dk = (double)k;
+    // -log y = -k ln2_hi - (f - (hfsq - (s (hfsq + R) + k ln2_lo)))
+    return -dk * LN2_HI - (f - (hfsq - fma(s, hfsq + R, dk * LN2_LO)));
+}
+
 // ---------------------------------------------------------------- propensity
 // C(x, nu) for nu in {0,1,2,3}, exactly, as a double (x <= 2^17): x(x-1) and
 // x(x-1)(x-2) are integers below 2^53, so every product is exact; C(x,3) is
