@@ -18,6 +18,7 @@ bounded sample of the same workload.
 """
 import argparse
 import hashlib
+import re
 import json
 import os
 import sys
@@ -94,11 +95,19 @@ def alg_ops_per_event_wave(net) -> float:
     return 117 + K + 1 + 64 * (5 + fbar) + 63 + 1 + dbar * (2 * (4 + fbar) + 2) + nchg + 2
 
 
+def _code_only(text: str) -> str:
+    """C++ source without comments and blank space, so that the digest tracks
+    the code a kernel is compiled from, not its commentary."""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
 def source_digest(paths):
     h = hashlib.sha256()
     for p in paths:
-        with open(os.path.join(ROOT, p), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, p), encoding="utf-8") as f:
+            h.update(_code_only(f.read()).encode())
     return h.hexdigest()[:16]
 
 

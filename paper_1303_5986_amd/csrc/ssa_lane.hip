@@ -81,7 +81,7 @@ __device__ __forceinline__ void lane_pool(const SimArgs &a, int32_t *__restrict_
                         const uint32_t k = g - run * (uint32_t)a.cap;
                         gslot = g;
                         xr = xs + gslot * a.S;
-                        w.begin(x, xr, a.S, k, a.seeds[run]);
+                        w.begin(x, xr, a.S, k, a.seeds[run], iter);
                         if constexpr (LEAP) lr.reset();
                         active = true;
                     }
@@ -162,9 +162,9 @@ unsigned pool_blocks(const SimArgs &a) {
             per_cu = 1;
             n_cu = std::max(n_cu, 1);
         }
-        // Fewer resident blocks than the occupancy limit (7 for <1,4>) run
-        // faster: on Schloegl at 2048 x 60 x 8 walkers a launch took 1.190 ms
-        // at 5 per CU against 1.215 at 4, 1.268 at 3 and 1.230 at 7.
+        // More resident blocks are not faster: on Schloegl at 2048 x 60 x 8
+        // walkers, when <1,4> could hold 7 per CU, a launch took 1.188 ms at 5
+        // per CU against 1.215 at 4, 1.268 at 3, 1.243 at 6 and 1.230 at 7.
         if (per_cu > LANE_POOL_PER_CU) per_cu = LANE_POOL_PER_CU;
     }
     const int64_t need = ((int64_t)a.n_runs * a.cap + 255) / 256;

@@ -126,15 +126,75 @@ struct LaneNet {
 
 // One walker's progress through the current interval (its counts live in a
 // separate register array, which keeps this struct out of LDS).
+// The walker's SSA stream, Philox4x32-10 at counter (e, slot, iter, 0) under
+// key (k0, k1), with everything that does not depend on the event number e
+// worked out once per walker.  Round 0 multiplies only c0 = e (c2 = iter is
+// the same for every event), so its output word c0 = hi(M1 iter) ^ slot ^ k0
+// is fixed; round 1 then multiplies that fixed word, so its M0 product is
+// fixed as well and is folded, with the round keys, into a1, b1 and b2.  The
+// remaining round keys k + r W are kept rather than recomputed per event.
+// draw(e) returns exactly philox4x32_10(e, slot, iter, 0, k0, k1).
+struct SsaStream {
+    uint32_t k1;        // round 0 key word 1
+    uint32_t a1, b1;    // round 1: lo(M1 iter) ^ (k0 + W0); hi(M0 c0') ^ (k1 + W1)
+    uint32_t b2;        // round 2: lo(M0 c0') ^ (k1 + 2 W1)
+    uint32_t kk0[8];    // k0 + r W0, r = 2..9
+    uint32_t kk1[7];    // k1 + r W1, r = 3..9
+
+    __device__ __forceinline__ void init(uint32_t slot, uint32_t iter, uint32_t k0_, uint32_t k1_) {
+        const uint64_t p = (uint64_t)PHILOX_M1 * iter;
+        const uint32_t c0 = (uint32_t)(p >> 32) ^ slot ^ k0_;   // round 0 output word c0
+        const uint64_t q = (uint64_t)PHILOX_M0 * c0;
+        k1 = k1_;
+        a1 = (uint32_t)p ^ (k0_ + PHILOX_W0);
+        b1 = (uint32_t)(q >> 32) ^ (k1_ + PHILOX_W1);
+        b2 = (uint32_t)q ^ (k1_ + 2u * PHILOX_W1);
+#pragma unroll
+        for (int r = 2; r < 10; ++r) kk0[r - 2] = k0_ + (uint32_t)r * PHILOX_W0;
+#pragma unroll
+        for (int r = 3; r < 10; ++r) kk1[r - 3] = k1_ + (uint32_t)r * PHILOX_W1;
+    }
+
+    __device__ __forceinline__ U4 draw(uint32_t e) const {
+        // round 0: (e, slot, iter, 0) -> (fixed, lo(M1 iter), hi(M0 e) ^ k1, lo(M0 e))
+        uint64_t p0 = (uint64_t)PHILOX_M0 * e;
+        uint32_t c2 = (uint32_t)(p0 >> 32) ^ k1;
+        uint32_t c3 = (uint32_t)p0;
+        // round 1: the M0 product of the fixed word is in b1 (and in b2 for round 2)
+        uint64_t p1 = (uint64_t)PHILOX_M1 * c2;
+        uint32_t c0 = (uint32_t)(p1 >> 32) ^ a1;
+        uint32_t c1 = (uint32_t)p1;
+        c2 = b1 ^ c3;
+        // round 2: its c3 is the fixed lo(M0 c0'), already in b2
+        p0 = (uint64_t)PHILOX_M0 * c0;
+        p1 = (uint64_t)PHILOX_M1 * c2;
+        c0 = (uint32_t)(p1 >> 32) ^ c1 ^ kk0[0];
+        c1 = (uint32_t)p1;
+        c2 = (uint32_t)(p0 >> 32) ^ b2;
+        c3 = (uint32_t)p0;
+#pragma unroll
+        for (int r = 3; r < 10; ++r) {
+            p0 = (uint64_t)PHILOX_M0 * c0;
+            p1 = (uint64_t)PHILOX_M1 * c2;
+            c0 = (uint32_t)(p1 >> 32) ^ c1 ^ kk0[r - 2];
+            c1 = (uint32_t)p1;
+            c2 = (uint32_t)(p0 >> 32) ^ c3 ^ kk1[r - 3];
+            c3 = (uint32_t)p0;
+        }
+        return U4{c0, c1, c2, c3};
+    }
+};
+
 struct LaneWalker {
     double t;
     uint32_t e, fired;
     uint32_t slot, k0, k1;
     bool bad;
+    SsaStream rs;
 
     template <int SMAX>
     __device__ __forceinline__ void begin(int32_t (&x)[SMAX], const int32_t *__restrict__ xr, int32_t S, uint32_t k,
-                                          uint64_t seed) {
+                                          uint64_t seed, uint32_t iter) {
 #pragma unroll
         for (int s = 0; s < SMAX; ++s) x[s] = (s < S) ? xr[s] : 0;
         t = 0.0;
@@ -144,6 +204,7 @@ struct LaneWalker {
         k0 = (uint32_t)seed;
         k1 = (uint32_t)(seed >> 32);
         bad = false;
+        rs.init(k, iter, k0, k1);
     }
 };
 
@@ -168,7 +229,7 @@ __device__ __forceinline__ bool lane_event(const LaneNet<SMAX, RMAX, HILL> &net,
         }
     }
     if (!(a0 > 0.0)) return false;
-    const U4 r = philox4x32_10(w.e, w.slot, iter, 0u, w.k0, w.k1);
+    const U4 r = w.rs.draw(w.e);
     w.e += 1;
     const double u1 = uniform53(r.x, r.y);
     const double u2 = uniform53(r.z, r.w);
@@ -477,7 +538,7 @@ __device__ __forceinline__ void lane_walker(const SimArgs &a, int32_t *__restric
     int32_t *xr = xs + gslot * a.S;
     LaneWalker w;
     int32_t x[SMAX];
-    w.begin(x, xr, a.S, (uint32_t)k, a.seeds[run]);
+    w.begin(x, xr, a.S, (uint32_t)k, a.seeds[run], iter);
     while (lane_event(net, w, x, iter, a.tau)) {
     }
     lane_finish(a, w, x, xr, gslot);

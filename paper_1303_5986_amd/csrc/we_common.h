@@ -144,10 +144,14 @@ struct SimArgs {
 // ---------------------------------------------------------------- Philox
 struct U4 { uint32_t x, y, z, w; };
 
+// Round multipliers and Weyl key increments of Philox4x32.
+constexpr uint32_t PHILOX_M0 = 0xD2511F53u, PHILOX_M1 = 0xCD9E8D57u;
+constexpr uint32_t PHILOX_W0 = 0x9E3779B9u, PHILOX_W1 = 0xBB67AE85u;
+
 __device__ __forceinline__ U4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                              uint32_t k0, uint32_t k1) {
-    const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
-    const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+    const uint32_t M0 = PHILOX_M0, M1 = PHILOX_M1;
+    const uint32_t W0 = PHILOX_W0, W1 = PHILOX_W1;
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
         const uint64_t p0 = (uint64_t)M0 * c0, p1 = (uint64_t)M1 * c2;   // one 32x32->64 multiply each
