@@ -130,10 +130,10 @@ struct SimArgs {
     double *rw_F;                        // [n_runs][n_bins][n_bins] flux matrix F[i][j]
     double *rw_R;                        // [n_runs][n_bins][n_bins] solve scratch (null: in LDS)
     int32_t *rw_stat;                    // [n_runs][2] events applied, skipped
-    float *ev_bin;                       // [n_bins] events of the walkers that ended in each bin
-    int32_t *n_bin;                      // [n_bins] walkers that ended in each bin
+    float *ev_bin;                       // [n_bins][seg_rep] events of the walkers that ended in each bin
+    int32_t *n_bin;                      // [n_bins][seg_rep] walkers that ended in each bin
     int32_t seg_rep;                     // counters per bin (spread over replicas, picked by run,
-                                         //   against atomic contention): min(32, max(1, 4096/n_bins))
+                                         //   against atomic contention): min(128, max(1, 16384/n_bins))
     int32_t *occ_bin;                    // [n_bins][seg_rep] queue segments per counter
     int32_t *seg_off;                    // [n_bins][seg_rep] first queue segment of each counter
     int32_t *seg_cur;                    // [n_bins][seg_rep]

@@ -588,8 +588,9 @@ __device__ void resample_run_t(const SimArgs &a, const double *__restrict__ w_cu
     if (a.queue_stats)
         for (int32_t b = tid; b < NB; b += nthr)
             if (cnt[b] > 0) {
-                atomicAdd(&a.ev_bin[b], evb[b]);
-                atomicAdd(&a.n_bin[b], cnt[b]);
+                const int32_t c = b * a.seg_rep + run % a.seg_rep;
+                atomicAdd(&a.ev_bin[c], evb[b]);
+                atomicAdd(&a.n_bin[c], cnt[b]);
             }
 
     // wave 0: bin offsets (walkers ordered by bin, then slot)
@@ -884,7 +885,59 @@ hipError_t launch_resample(const SimArgs &a, int32_t *x_cur, const double *w_cur
     return hipGetLastError();
 }
 
-hipError_t launch_observe(const SimArgs &a, const int32_t *xs, const double *ws, hipStream_t st) {
+// The same with the one-species histogram summed per block in LDS first:
+// block (run, i) takes walkers i*OBS_WALKERS ... of one run, adds their
+// weights into an LDS copy of the run's histogram row, then adds the nonzero
+// entries to the row in device memory (one atomic per distinct count per
+// block instead of one per walker, and none on a shared address within a
+// run).  The joint histogram keeps one atomic per walker.  Thread 0 of
+// block (0, 0) also advances the iteration counter, which no step of this
+// kernel reads, in place of the separate advance launch.
+#define OBS_WALKERS 1024
+#define OBS_LDS_BINS 6144
+__global__ __launch_bounds__(256) void we_observe_lds_kernel(SimArgs a, const int32_t *__restrict__ xs,
+                                                             const double *__restrict__ ws) {
+    extern __shared__ __align__(16) unsigned char obs_lds[];
+    double *h = reinterpret_cast<double *>(obs_lds);
+    const int32_t run = blockIdx.x, tid = threadIdx.x;
+    if (run == 0 && blockIdx.y == 0 && tid == 0) *a.iter_dev += 1u;
+    const int32_t n = a.n_walk[run];
+    const int32_t k0 = (int32_t)blockIdx.y * OBS_WALKERS, k1 = min(n, k0 + OBS_WALKERS);
+    if (k0 >= n) return;   // uniform over the block
+    for (int32_t v = tid; v < a.nh; v += blockDim.x) h[v] = 0.0;
+    __syncthreads();
+    const size_t base = (size_t)run * a.cap;
+    for (int32_t k = k0 + tid; k < k1; k += blockDim.x) {
+        const size_t idx = base + k;
+        const double wv = ws[idx];
+        const int32_t v = xs[idx * a.S + a.hist_species] - a.hist_lo;
+        if (v >= 0 && v < a.nh) atomicAdd(&h[v], wv);
+        if (a.n_joint > 0) {
+            int32_t cell = 0, mul = 1;
+            for (int d = 0; d < a.n_joint; ++d) {
+                const int32_t c = min(xs[idx * a.S + a.joint_species[d]] / a.joint_width, a.joint_bins - 1);
+                cell += c * mul;
+                mul *= a.joint_bins;
+            }
+            atomicAdd(&a.jhist[(size_t)run * a.jcells + cell], wv);
+        }
+    }
+    __syncthreads();
+    double *row = a.hist + (size_t)run * a.nh;
+    for (int32_t v = tid; v < a.nh; v += blockDim.x)
+        if (h[v] != 0.0) atomicAdd(&row[v], h[v]);
+}
+
+// Histograms and the end of the iteration; returns whether the iteration
+// counter was advanced (else the caller launches the advance kernel).
+hipError_t launch_observe(const SimArgs &a, const int32_t *xs, const double *ws, hipStream_t st, bool *advanced) {
+    *advanced = false;
+    if (a.nh > 0 && a.nh <= OBS_LDS_BINS) {
+        const dim3 grid((unsigned)a.n_runs, (unsigned)((a.cap + OBS_WALKERS - 1) / OBS_WALKERS));
+        hipLaunchKernelGGL(we_observe_lds_kernel, grid, dim3(256), (size_t)a.nh * sizeof(double), st, a, xs, ws);
+        *advanced = true;
+        return hipGetLastError();
+    }
     const int64_t total = (int64_t)a.n_runs * a.cap;
     hipLaunchKernelGGL(we_observe_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st,
                        a, xs, ws);

@@ -32,7 +32,8 @@ int32_t resample_place_rows(const SimArgs &a, int64_t blocks);
 hipError_t launch_resample(const SimArgs &a, int32_t *x_cur, const double *w_cur, int32_t *x_nxt,
                            double *w_nxt, hipStream_t st);
 hipError_t launch_advance(const SimArgs &a, hipStream_t st);
-hipError_t launch_observe(const SimArgs &a, const int32_t *xs, const double *ws, hipStream_t st);
+hipError_t launch_observe(const SimArgs &a, const int32_t *xs, const double *ws, hipStream_t st,
+                          bool *advanced);
 
 namespace {
 thread_local std::string g_err;
@@ -276,7 +277,7 @@ enum Piece { P_X0, P_X1, P_W0, P_W1, P_BIN, P_ORIG, P_N, P_EVW, P_FLUX, P_EVI, P
              P_SEG, P_ITER, P_JHIST, P_SCHED, P_SEGLIST, P_QUEUE, P_NZ, P_RWF, P_RWR, P_RWS,
              P_COUNT };
 
-int32_t seg_rep_for(int32_t NB) { return std::min(32, std::max(1, 4096 / NB)); }
+int32_t seg_rep_for(int32_t NB) { return std::min(128, std::max(1, 16384 / NB)); }
 
 Layout make_layout(int32_t S, int32_t NB, int32_t n_bins2, int32_t n_runs, int32_t cap, int32_t max_iters,
                    int32_t nh, int64_t jcells, bool rw) {
@@ -300,7 +301,7 @@ Layout make_layout(int32_t S, int32_t NB, int32_t n_bins2, int32_t n_runs, int32
     L.add(4 * (size_t)n_runs * max_iters);
     L.add(4);
     L.add(8 * (size_t)n_runs * (size_t)jcells);
-    L.add(4 * (2 + 3 * (size_t)seg_rep_for(NB)) * (size_t)NB);
+    L.add(4 * 5 * (size_t)seg_rep_for(NB) * (size_t)NB);
     L.add(8 * (size_t)n_runs * NB);
     L.add(8);
     L.add(4 * 3 * (size_t)S);
@@ -485,10 +486,10 @@ extern "C" we_status we_init(const we_network *net, const we_grid *g, const we_p
     a.rw_F = p->rw_period > 0 ? (double *)at(P_RWF) : nullptr;
     a.rw_R = p->rw_period > 0 && !rw_solve_in_lds(NB) ? (double *)at(P_RWR) : nullptr;
     a.rw_stat = p->rw_period > 0 ? (int32_t *)at(P_RWS) : nullptr;
-    a.ev_bin = (float *)at(P_SCHED);
-    a.n_bin = (int32_t *)at(P_SCHED) + NB;
     a.seg_rep = seg_rep_for(NB);
-    a.occ_bin = (int32_t *)at(P_SCHED) + 2 * NB;
+    a.ev_bin = (float *)at(P_SCHED);
+    a.n_bin = (int32_t *)at(P_SCHED) + a.seg_rep * NB;
+    a.occ_bin = a.n_bin + a.seg_rep * NB;
     a.seg_off = a.occ_bin + a.seg_rep * NB;
     a.seg_cur = a.seg_off + a.seg_rep * NB;
     a.seg = (int2 *)at(P_SEGLIST);
@@ -615,12 +616,15 @@ we_status we_sim_bookkeeping(we_sim *s, hipStream_t st, hipEvent_t *ev) {
         if (e != hipSuccess) return hip_fail(e, "reweight launch");
     }
     if (ev) HIP_TRY(hipEventRecord(ev[1], st));
+    bool advanced = false;
     if (a.nh > 0 || a.n_joint > 0) {
-        e = launch_observe(a, s->x[nx], s->w[nx], st);
+        e = launch_observe(a, s->x[nx], s->w[nx], st, &advanced);
         if (e != hipSuccess) return hip_fail(e, "observe launch");
     }
-    e = launch_advance(a, st);
-    if (e != hipSuccess) return hip_fail(e, "advance launch");
+    if (!advanced) {
+        e = launch_advance(a, st);
+        if (e != hipSuccess) return hip_fail(e, "advance launch");
+    }
     if (ev) HIP_TRY(hipEventRecord(ev[2], st));
     s->cur = nx;
     if (!s->capturing) {

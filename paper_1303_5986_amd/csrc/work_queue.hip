@@ -27,6 +27,7 @@ __global__ __launch_bounds__(256) void queue_count_kernel(SimArgs a) {
 // per walker (descending; ties: higher bin first), lays out their segments
 // in that order, and clears the statistics and the queue.
 #define QUEUE_MAX_BINS 8192
+#define QUEUE_CHUNK 16   // counters per thread: NB * seg_rep <= 16384 over 1024 threads
 __global__ __launch_bounds__(1024) void queue_order_kernel(SimArgs a) {
     __shared__ float key[QUEUE_MAX_BINS];
     __shared__ int16_t idx[QUEUE_MAX_BINS];
@@ -34,14 +35,40 @@ __global__ __launch_bounds__(1024) void queue_order_kernel(SimArgs a) {
     const int32_t NB = a.n_bins, tid = threadIdx.x, nthr = blockDim.x;
     int32_t P = 1;
     while (P < NB) P <<= 1;
-    for (int32_t b = tid; b < P; b += nthr) {
-        float kv = -1.0f;
-        if (b < NB) {
-            const int32_t nw = a.n_bin[b];
-            kv = nw > 0 ? a.ev_bin[b] / (float)nw : 0.0f;
+    const int32_t rep = a.seg_rep, NC = NB * rep;
+    const int lane = tid & 63, wv = tid >> 6, nwv = nthr >> 6;
+    // key of each bin: its replicas' event and walker counts summed by one
+    // wave (rep <= 128: two entries per lane at most); four bins per wave at
+    // a time, so that their loads are in flight together
+    for (int32_t b0 = wv; b0 < P; b0 += 4 * nwv) {
+        float ev[4];
+        int32_t nw[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int32_t b = b0 + u * nwv;
+            ev[u] = 0.0f;
+            nw[u] = 0;
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const int32_t r = lane + 64 * q;
+                if (b < NB && r < rep) {
+                    ev[u] += a.ev_bin[b * rep + r];
+                    nw[u] += a.n_bin[b * rep + r];
+                }
+            }
         }
-        key[b] = kv;
-        idx[b] = (int16_t)b;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            for (int d = 32; d > 0; d >>= 1) {
+                ev[u] += __shfl_xor(ev[u], d, 64);
+                nw[u] += __shfl_xor(nw[u], d, 64);
+            }
+            const int32_t b = b0 + u * nwv;
+            if (lane == 0 && b < P) {
+                key[b] = b < NB ? (nw[u] > 0 ? ev[u] / (float)nw[u] : 0.0f) : -1.0f;
+                idx[b] = (int16_t)b;
+            }
+        }
     }
     __syncthreads();
     // bitonic sort, descending by (key, bin)
@@ -63,16 +90,20 @@ __global__ __launch_bounds__(1024) void queue_order_kernel(SimArgs a) {
             __syncthreads();
         }
     // exclusive prefix of the segment counters in sorted bin order (the
-    // replicas of a bin consecutive): per-thread chunks of that sequence
-    const int32_t rep = a.seg_rep, NC = NB * rep;
+    // replicas of a bin consecutive): per-thread chunks of that sequence,
+    // at most QUEUE_CHUNK long (NB * rep <= 16384), held in registers
     const int32_t per = (NC + nthr - 1) / nthr;
     const int32_t lo = min(tid * per, NC), hi = min(lo + per, NC);
     auto counter = [&](int32_t i) { return (int32_t)idx[i / rep] * rep + i % rep; };
+    int32_t cnt[QUEUE_CHUNK];
     int32_t acc = 0;
-    for (int32_t i = lo; i < hi; ++i) acc += a.occ_bin[counter(i)];
+#pragma unroll
+    for (int q = 0; q < QUEUE_CHUNK; ++q) {
+        cnt[q] = lo + q < hi ? a.occ_bin[counter(lo + q)] : 0;
+        acc += cnt[q];
+    }
     // block-wide exclusive scan of the chunk sums: within waves, then over
     // the wave totals
-    const int lane = tid & 63, wv = tid >> 6;
     int32_t incl = acc;
     for (int d = 1; d < 64; d <<= 1) {
         const int32_t y = __shfl_up(incl, d, 64);
@@ -92,19 +123,18 @@ __global__ __launch_bounds__(1024) void queue_order_kernel(SimArgs a) {
     }
     __syncthreads();
     acc = part[wv] + incl - acc;
-    for (int32_t i = lo; i < hi; ++i) {
-        const int32_t c = counter(i);
-        a.seg_off[c] = acc;
-        acc += a.occ_bin[c];
-    }
+#pragma unroll
+    for (int q = 0; q < QUEUE_CHUNK; ++q)
+        if (lo + q < hi) {
+            a.seg_off[counter(lo + q)] = acc;
+            acc += cnt[q];
+        }
     __syncthreads();
     for (int32_t c = tid; c < NC; c += nthr) {
         a.occ_bin[c] = 0;
         a.seg_cur[c] = 0;
-    }
-    for (int32_t b = tid; b < NB; b += nthr) {
-        a.ev_bin[b] = 0.0f;
-        a.n_bin[b] = 0;
+        a.ev_bin[c] = 0.0f;
+        a.n_bin[c] = 0;
     }
 }
 
