@@ -50,9 +50,13 @@
 #define WAVE_LDS_MAX_WAVES 8
 #define WAVE_LDS_BYTES (160 * 1024)
 
+// At least 4 waves per SIMD (two blocks per CU), so at most 128 VGPRs: one
+// more register and the <false> variant drops to one block per CU (measured:
+// 132 VGPRs took 8 replicas of the 3680-reaction network from 1.41 to 2.14 ms
+// per launch).
 template <bool HDR>
-__global__ __launch_bounds__(64 * WAVE_LDS_MAX_WAVES) void ssa_wave_lds_kernel(SimArgs a, int32_t *__restrict__ xs,
-                                                                              int32_t s_pad) {
+__global__ __launch_bounds__(64 * WAVE_LDS_MAX_WAVES, 4) void ssa_wave_lds_kernel(SimArgs a, int32_t *__restrict__ xs,
+                                                                                 int32_t s_pad) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int32_t R = a.R;
     RxnDesc *ldesc = reinterpret_cast<RxnDesc *>(smem);
