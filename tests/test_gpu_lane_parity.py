@@ -4,10 +4,11 @@ The lane kernel computes the same FP64 operations in the same order as the
 oracle and draws the same Philox blocks, so the integer trajectories, bins,
 parent slots and weights must be IDENTICAL after every WE iteration; the
 recycled-weight series too (summed in slot order on both sides).  The only
-possible source of a difference is the device log() versus the host's, which
-could flip an event only when t + dt lands within an ulp or so of tau; no
-such case is expected at these sizes and any occurrence fails the test with
-the iteration and slot named.
+possible source of a difference is the waiting time (the kernel's own FP64
+logarithm and Newton reciprocal against the host's log and division, an ulp
+or two apart), which could flip an event only when t + dt lands within a few
+ulps of tau; no such case is expected at these sizes and any occurrence fails
+the test with the iteration and slot named.
 """
 import dataclasses
 
