@@ -237,29 +237,69 @@ __device__ __forceinline__ bool lane_event(const LaneNet<SMAX, RMAX, HILL> &net,
     if (w.t + dt > tau) return false;
     w.t = w.t + dt;
     const double target = u2 * a0;
-    double cum = 0.0;
-    int32_t jsel = -1, last_pos = -1;
+    // The chosen reaction is the first j whose running sum (in reaction order)
+    // exceeds the target; if rounding leaves the target above the whole sum,
+    // the last reaction with a positive propensity.
+    int32_t jsel = -1;
     uint32_t dsel[W];
 #pragma unroll
     for (int q = 0; q < W; ++q) dsel[q] = 0u;
+    if constexpr (RMAX <= 8) {
+        // Small networks: all running sums first, then one pass from the last
+        // reaction to the first that takes every hit and so ends on the first
+        // (the sums never decrease, every term being >= 0; padding rows repeat
+        // the last sum and never come before a real hit).  A select per
+        // reaction and no first-hit bookkeeping: 1.067 -> 0.994 ms per launch
+        // on Schloegl, measured A/B.  Larger networks keep the forward pass:
+        // the stored sums would cost them occupancy.
+        double cum[RMAX];
+        double c = 0.0;
 #pragma unroll
-    for (int j = 0; j < RMAX; ++j) {
-        if (j < net.R) {
-            cum = cum + prop[j];
-            if (prop[j] > 0.0) last_pos = j;
-            const bool hit = (jsel < 0) && (cum > target);
-            if (hit) jsel = j;
+        for (int j = 0; j < RMAX; ++j) {
+            if (j < net.R) c = c + prop[j];
+            cum[j] = c;
+        }
+#pragma unroll
+        for (int j = RMAX - 1; j >= 0; --j) {
+            const bool hit = cum[j] > target;
             if constexpr (REG) {
 #pragma unroll
                 for (int q = 0; q < W; ++q) dsel[q] = hit ? net.drow[REG ? j : 0][q] : dsel[q];
+            } else {
+                jsel = hit ? j : jsel;
             }
         }
-    }
-    if (jsel < 0) {   // rounding left the target above the running sum
-        jsel = last_pos;
-        if constexpr (REG) {
+        if (!(c > target)) {
 #pragma unroll
-            for (int q = 0; q < W; ++q) dsel[q] = (uint32_t)net.dpack[jsel * WE_DPACK_WORDS + q];
+            for (int j = 0; j < RMAX; ++j)
+                if (j < net.R && prop[j] > 0.0) jsel = j;
+            if constexpr (REG) {
+#pragma unroll
+                for (int q = 0; q < W; ++q) dsel[q] = (uint32_t)net.dpack[jsel * WE_DPACK_WORDS + q];
+            }
+        }
+    } else {
+        double cum = 0.0;
+        int32_t last_pos = -1;
+#pragma unroll
+        for (int j = 0; j < RMAX; ++j) {
+            if (j < net.R) {
+                cum = cum + prop[j];
+                if (prop[j] > 0.0) last_pos = j;
+                const bool hit = (jsel < 0) && (cum > target);
+                if (hit) jsel = j;
+                if constexpr (REG) {
+#pragma unroll
+                    for (int q = 0; q < W; ++q) dsel[q] = hit ? net.drow[REG ? j : 0][q] : dsel[q];
+                }
+            }
+        }
+        if (jsel < 0) {
+            jsel = last_pos;
+            if constexpr (REG) {
+#pragma unroll
+                for (int q = 0; q < W; ++q) dsel[q] = (uint32_t)net.dpack[jsel * WE_DPACK_WORDS + q];
+            }
         }
     }
     if constexpr (!REG) {
