@@ -222,7 +222,9 @@ __device__ __forceinline__ bool lane_event(const LaneNet<SMAX, RMAX, HILL> &net,
     for (int j = 0; j < RMAX; ++j) {
         const LaneRxn d = REG ? net.rx[REG ? j : 0] : lane_rxn(net.desc, j);
         prop[j] = 0.0;
-        if (j < net.R) {
+        // register-held tables: rows past R are zero-rate padding, whose
+        // propensity is +0 and leaves every sum unchanged, so no row test
+        if (REG || j < net.R) {
             prop[j] = lane_propensity<SMAX>(d, x);
             if constexpr (HILL) prop[j] = lane_repress<SMAX>(prop[j], REG ? net.hl[REG ? j : 0] : lane_hill(net.hill, j), x);
             a0 = a0 + prop[j];
@@ -256,7 +258,7 @@ __device__ __forceinline__ bool lane_event(const LaneNet<SMAX, RMAX, HILL> &net,
         double c = 0.0;
 #pragma unroll
         for (int j = 0; j < RMAX; ++j) {
-            if (j < net.R) c = c + prop[j];
+            if (REG || j < net.R) c = c + prop[j];
             cum[j] = c;
         }
 #pragma unroll
@@ -272,7 +274,7 @@ __device__ __forceinline__ bool lane_event(const LaneNet<SMAX, RMAX, HILL> &net,
         if (!(c > target)) {
 #pragma unroll
             for (int j = 0; j < RMAX; ++j)
-                if (j < net.R && prop[j] > 0.0) jsel = j;
+                if ((REG || j < net.R) && prop[j] > 0.0) jsel = j;
             if constexpr (REG) {
 #pragma unroll
                 for (int q = 0; q < W; ++q) dsel[q] = (uint32_t)net.dpack[jsel * WE_DPACK_WORDS + q];
