@@ -28,7 +28,7 @@
 #endif
 // Idle lanes refill once at least this many of the wave's lanes are idle.
 #ifndef LANE_REFILL_MIN
-#define LANE_REFILL_MIN 8
+#define LANE_REFILL_MIN 12
 #endif
 
 // Persistent lane kernel: every lane runs walkers from the work queue (see
