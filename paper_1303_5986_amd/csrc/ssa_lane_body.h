@@ -124,8 +124,6 @@ struct LaneNet {
     }
 };
 
-// One walker's progress through the current interval (its counts live in a
-// separate register array, which keeps this struct out of LDS).
 // The walker's SSA stream, Philox4x32-10 at counter (e, slot, iter, 0) under
 // key (k0, k1), with everything that does not depend on the event number e
 // worked out once per walker.  Round 0 multiplies only c0 = e (c2 = iter is
@@ -185,6 +183,8 @@ struct SsaStream {
     }
 };
 
+// One walker's progress through the current interval (its counts live in a
+// separate register array, which keeps this struct out of LDS).
 struct LaneWalker {
     double t;
     uint32_t e, fired;

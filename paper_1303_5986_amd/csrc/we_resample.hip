@@ -928,7 +928,7 @@ __global__ __launch_bounds__(256) void we_observe_lds_kernel(SimArgs a, const in
         if (h[v] != 0.0) atomicAdd(&row[v], h[v]);
 }
 
-// Histograms and the end of the iteration; returns whether the iteration
+// Histograms and the end of the iteration; *advanced tells whether the iteration
 // counter was advanced (else the caller launches the advance kernel).
 hipError_t launch_observe(const SimArgs &a, const int32_t *xs, const double *ws, hipStream_t st, bool *advanced) {
     *advanced = false;

@@ -277,7 +277,11 @@ enum Piece { P_X0, P_X1, P_W0, P_W1, P_BIN, P_ORIG, P_N, P_EVW, P_FLUX, P_EVI, P
              P_SEG, P_ITER, P_JHIST, P_SCHED, P_SEGLIST, P_QUEUE, P_NZ, P_RWF, P_RWR, P_RWS,
              P_COUNT };
 
-int32_t seg_rep_for(int32_t NB) { return std::min(128, std::max(1, 16384 / NB)); }
+// Counter replicas per bin of the work-queue statistics: enough to spread the
+// runs' atomics, never more than there are runs (replica run % rep).
+int32_t seg_rep_for(int32_t NB, int32_t n_runs) {
+    return std::max(1, std::min(std::min(128, 16384 / NB), n_runs));
+}
 
 Layout make_layout(int32_t S, int32_t NB, int32_t n_bins2, int32_t n_runs, int32_t cap, int32_t max_iters,
                    int32_t nh, int64_t jcells, bool rw) {
@@ -301,7 +305,7 @@ Layout make_layout(int32_t S, int32_t NB, int32_t n_bins2, int32_t n_runs, int32
     L.add(4 * (size_t)n_runs * max_iters);
     L.add(4);
     L.add(8 * (size_t)n_runs * (size_t)jcells);
-    L.add(4 * 5 * (size_t)seg_rep_for(NB) * (size_t)NB);
+    L.add(4 * 5 * (size_t)seg_rep_for(NB, n_runs) * (size_t)NB);
     L.add(8 * (size_t)n_runs * NB);
     L.add(8);
     L.add(4 * 3 * (size_t)S);
@@ -486,7 +490,7 @@ extern "C" we_status we_init(const we_network *net, const we_grid *g, const we_p
     a.rw_F = p->rw_period > 0 ? (double *)at(P_RWF) : nullptr;
     a.rw_R = p->rw_period > 0 && !rw_solve_in_lds(NB) ? (double *)at(P_RWR) : nullptr;
     a.rw_stat = p->rw_period > 0 ? (int32_t *)at(P_RWS) : nullptr;
-    a.seg_rep = seg_rep_for(NB);
+    a.seg_rep = seg_rep_for(NB, n_runs);
     a.ev_bin = (float *)at(P_SCHED);
     a.n_bin = (int32_t *)at(P_SCHED) + a.seg_rep * NB;
     a.occ_bin = a.n_bin + a.seg_rep * NB;
