@@ -308,6 +308,7 @@ int64_t or_tauleap_interval(const or_net *net, int32_t *x, double tau, double ep
     int64_t fired = 0;
     uint32_t e = 0;
     int32_t status = OR_OK;
+    int32_t ssa_left = 0;   /* exact events still to take before the bound is evaluated again */
     for (;;) {
         double a0 = 0.0;
         for (int32_t j = 0; j < R; ++j) {
@@ -316,21 +317,34 @@ int64_t or_tauleap_interval(const or_net *net, int32_t *x, double tau, double ep
         }
         if (!(a0 > 0.0)) break;
         double tp = INFINITY;
-        for (int32_t i = 0; i < S; ++i) {
-            if (hor[i] == 0) continue;
-            double mu = 0.0, sig = 0.0;
-            for (int32_t j = 0; j < R; ++j) {
-                int32_t d = 0;
-                for (int32_t p = net->chg_ptr[j]; p < net->chg_ptr[j + 1]; ++p)
-                    if (net->chg_species[p] == i) d = net->chg_delta[p];
-                mu = mu + (double)d * a[j];
-                sig = sig + (double)d * (double)d * a[j];
+        int exact = 0;
+        if (ssa_left > 0) {
+            ssa_left -= 1;
+            exact = 1;
+        } else {
+            for (int32_t i = 0; i < S; ++i) {
+                if (hor[i] == 0) continue;
+                double mu = 0.0, sig = 0.0;
+                for (int32_t j = 0; j < R; ++j) {
+                    int32_t d = 0;
+                    for (int32_t p = net->chg_ptr[j]; p < net->chg_ptr[j + 1]; ++p)
+                        if (net->chg_species[p] == i) d = net->chg_delta[p];
+                    mu = mu + (double)d * a[j];
+                    sig = sig + (double)d * (double)d * a[j];
+                }
+                const double bi = fmax(eps * (double)x[i] / leap_g(hor[i], hnu[i], (double)x[i]), 1.0);
+                if (mu != 0.0) tp = fmin(tp, bi / fabs(mu));
+                if (sig != 0.0) tp = fmin(tp, bi * bi / sig);
             }
-            const double bi = fmax(eps * (double)x[i] / leap_g(hor[i], hnu[i], (double)x[i]), 1.0);
-            if (mu != 0.0) tp = fmin(tp, bi / fabs(mu));
-            if (sig != 0.0) tp = fmin(tp, bi * bi / sig);
         }
-        if (tp < 10.0 / a0) {
+        if (!exact && tp < 10.0 / a0) {
+            /* leaping does not pay here: this and the next OR_LEAP_SSA_RUN - 1
+             * steps are exact events (Cao, Gillespie and Petzold recommend a
+             * run of about 100 before the bound is tried again) */
+            exact = 1;
+            ssa_left = OR_LEAP_SSA_RUN - 1;
+        }
+        if (exact) {
             /* one exact event */
             uint32_t ctr[4] = {e, slot, iter, 0u}, r[4];
             or_philox4x32_10(ctr, key, r);

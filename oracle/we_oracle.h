@@ -31,6 +31,8 @@ extern "C" {
 /* Largest copy number a species may hold: keeps every combinatorial factor
  * h_j(x) (reaction order <= 3) below 2^53, so it is exact in FP64. */
 #define OR_COUNT_MAX 131071
+/* tau-leaping: exact events taken in a row once the step bound is below 10 / a0 */
+#define OR_LEAP_SSA_RUN 100
 
 enum { OR_OK = 0, OR_EINVAL = -1, OR_EOVERFLOW = -5 };
 
@@ -106,8 +108,11 @@ int64_t or_ssa_interval(const or_net *net, int32_t *x, double tau,
  *      mu_i = sum_j nu_ij a_j, sigma_i^2 = sum_j nu_ij^2 a_j (j ascending),
  *      g_i from the highest order of the reactions that consume i (CGP 2006,
  *      Eq. 27); zero denominators count as +infinity;
- *   3. if tau' < 10 / a0: one exact direct-method event, with the SSA stream
- *      (counter (e, slot, iter, 0)) and the same stopping rule at tau;
+ *   3. if tau' < 10 / a0: OR_LEAP_SSA_RUN (100) steps of exact direct-method
+ *      events, this one included, without evaluating tau' (the run of about
+ *      100 SSA steps that Cao, Gillespie and Petzold recommend), with the SSA
+ *      stream (counter (e, slot, iter, 0)) and the same stopping rule at tau;
+ *      the run ends early with the interval;
  *   4. else leap dt = min(tau', tau - t): K_j ~ Poisson(a_j dt) for j
  *      ascending; if some count would go negative, halve tau' and draw again;
  *      otherwise x += sum_j K_j nu_j and t += dt (the leap that reaches tau

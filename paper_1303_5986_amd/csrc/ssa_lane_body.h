@@ -326,16 +326,22 @@ __device__ __forceinline__ bool lane_event(const LaneNet<SMAX, RMAX, HILL> &net,
 // ---------------------------------------------------------------- tau-leaping
 // An engine for the propagation step that WE leaves open (Sec. IV suggests
 // tau-leaping): explicit leaps (Gillespie 2001) with the step bound of Cao,
-// Gillespie and Petzold (2006), one exact event instead of a leap where the
-// bound is below 10 / a0, and the leap halved when a count would go negative.
+// Gillespie and Petzold (2006), a run of 100 exact events instead of a leap
+// where the bound is below 10 / a0, and the leap halved when a count would go
+// negative.
+
+// Exact events taken in a row once the step bound is below 10 / a0.
+#define LEAP_SSA_RUN 100
 
 // The walker's leap stream: the four words of Philox(n, slot, iter, 4), in
 // turn, as uniforms (r + 0.5) 2^-32.
 struct LeapRng {
     uint32_t n, idx, b0, b1, b2, b3;
+    uint32_t ssa_left;   // exact events still to take before the step bound is tried again
     __device__ __forceinline__ void reset() {
         n = 0;
         idx = 4;
+        ssa_left = 0;
     }
     __device__ __forceinline__ double u(uint32_t slot, uint32_t iter, uint32_t k0, uint32_t k1) {
         if (idx == 4) {
@@ -450,9 +456,11 @@ __device__ __forceinline__ bool lane_leap_step(const LaneNet<SMAX, RMAX, HILL> &
     }
     if (!(a0 > 0.0)) return false;
     double tp = __builtin_huge_val();
+    bool exact = g.ssa_left > 0;
+    if (exact) g.ssa_left -= 1;
 #pragma unroll
     for (int s = 0; s < SMAX; ++s) {
-        if (hor[s] != 0) {
+        if (!exact && hor[s] != 0) {
             double mu = 0.0, sig = 0.0;
 #pragma unroll
             for (int j = 0; j < RMAX; ++j) {
@@ -467,7 +475,14 @@ __device__ __forceinline__ bool lane_leap_step(const LaneNet<SMAX, RMAX, HILL> &
             if (sig != 0.0) tp = fmin(tp, bi * bi / sig);
         }
     }
-    if (tp < 10.0 / a0) {
+    if (!exact && tp < 10.0 / a0) {
+        // leaping does not pay here: this and the next LEAP_SSA_RUN - 1 steps
+        // are exact events (a run of about 100, as Cao, Gillespie and Petzold
+        // recommend, before the bound is tried again)
+        exact = true;
+        g.ssa_left = LEAP_SSA_RUN - 1;
+    }
+    if (exact) {
         // one exact event, as in lane_event
         const U4 r = philox4x32_10(w.e, w.slot, iter, 0u, w.k0, w.k1);
         w.e += 1;
