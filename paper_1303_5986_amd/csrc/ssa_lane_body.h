@@ -449,7 +449,7 @@ __device__ __forceinline__ bool lane_leap_step(const LaneNet<SMAX, RMAX, HILL> &
     for (int j = 0; j < RMAX; ++j) {
         const LaneRxn d = REG ? net.rx[REG ? j : 0] : lane_rxn(net.desc, j);
         prop[j] = 0.0;
-        if (j < net.R) {
+        if (REG || j < net.R) {   // zero-rate padding adds +0, as in lane_event
             prop[j] = lane_propensity<SMAX>(d, x);
             a0 = a0 + prop[j];
         }
@@ -492,17 +492,24 @@ __device__ __forceinline__ bool lane_leap_step(const LaneNet<SMAX, RMAX, HILL> &
         if (w.t + dt > tau) return false;
         w.t = w.t + dt;
         const double target = u2 * a0;
-        double cum = 0.0;
-        int32_t jsel = -1, last_pos = -1;
+        // the first j whose running sum exceeds the target (one pass from the
+        // last reaction to the first, as in lane_event), else the last
+        // reaction with a positive propensity
+        double cum[RMAX];
+        double c = 0.0;
 #pragma unroll
         for (int j = 0; j < RMAX; ++j) {
-            if (j < net.R) {
-                cum = cum + prop[j];
-                if (prop[j] > 0.0) last_pos = j;
-                if (jsel < 0 && cum > target) jsel = j;
-            }
+            if (REG || j < net.R) c = c + prop[j];
+            cum[j] = c;
         }
-        if (jsel < 0) jsel = last_pos;
+        int32_t jsel = -1;
+#pragma unroll
+        for (int j = RMAX - 1; j >= 0; --j) jsel = cum[j] > target ? j : jsel;
+        if (!(c > target)) {
+#pragma unroll
+            for (int j = 0; j < RMAX; ++j)
+                if ((REG || j < net.R) && prop[j] > 0.0) jsel = j;
+        }
         w.fired += 1;
         int32_t any = 0;
 #pragma unroll
