@@ -133,7 +133,7 @@ struct SimArgs {
     float *ev_bin;                       // [n_bins][seg_rep] events of the walkers that ended in each bin
     int32_t *n_bin;                      // [n_bins][seg_rep] walkers that ended in each bin
     int32_t seg_rep;                     // counters per bin (spread over replicas, picked by run,
-                                         //   against atomic contention): min(128, 16384/n_bins, n_runs), >= 1
+                                         //   against atomic contention): min(128, 16384/n_bins, n_runs/16), >= 1
     int32_t *occ_bin;                    // [n_bins][seg_rep] queue segments per counter
     int32_t *seg_off;                    // [n_bins][seg_rep] first queue segment of each counter
     int32_t *seg_cur;                    // [n_bins][seg_rep]

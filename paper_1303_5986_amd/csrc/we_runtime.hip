@@ -277,10 +277,11 @@ enum Piece { P_X0, P_X1, P_W0, P_W1, P_BIN, P_ORIG, P_N, P_EVW, P_FLUX, P_EVI, P
              P_SEG, P_ITER, P_JHIST, P_SCHED, P_SEGLIST, P_QUEUE, P_NZ, P_RWF, P_RWR, P_RWS,
              P_COUNT };
 
-// Counter replicas per bin of the work-queue statistics: enough to spread the
-// runs' atomics, never more than there are runs (replica run % rep).
+// Counter replicas per bin of the work-queue statistics: about 16 runs per
+// replica (replica run % rep), enough to spread the runs' atomics without a
+// long scan of nearly empty replicas when there are few runs.
 int32_t seg_rep_for(int32_t NB, int32_t n_runs) {
-    return std::max(1, std::min(std::min(128, 16384 / NB), n_runs));
+    return std::max(1, std::min(std::min(128, 16384 / NB), n_runs / 16));
 }
 
 Layout make_layout(int32_t S, int32_t NB, int32_t n_bins2, int32_t n_runs, int32_t cap, int32_t max_iters,
