@@ -811,9 +811,16 @@ __global__ __launch_bounds__(RESAMPLE_THREADS) void we_batch_resample_kernel(Bat
     resample_run(a, b.w_cur[i], b.w_nxt[i], b.use_lds[i], blockIdx.x, lds);
 }
 
+// Grid-strided over each member's own cells: a grid sized for the largest
+// member would spend most of its workgroups on members that have no cells
+// left for them.
 __global__ __launch_bounds__(256) void we_batch_gather_kernel(BatchPtrs b) {
     const int32_t i = blockIdx.y;
-    gather_one(b.args[i], b.x_cur[i], b.x_nxt[i], (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+    const SimArgs &a = b.args[i];
+    const int64_t cells = (int64_t)a.n_runs * a.cap * a.S;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; gid < cells; gid += stride)
+        gather_one(a, b.x_cur[i], b.x_nxt[i], gid);
 }
 
 __global__ __launch_bounds__(256) void we_batch_observe_kernel(BatchPtrs b) {
@@ -828,13 +835,18 @@ __global__ void we_batch_advance_kernel(BatchPtrs b, int32_t n) {
     if (i < n) *b.args[i].iter_dev += 1u;
 }
 
+// Workgroups per member in the batched gather (each strides over its member's
+// cells): 64 members then give 32768 workgroups, 128 per CU.
+#define BATCH_GATHER_BLOCKS 512
+
 hipError_t launch_batch_bookkeeping(const BatchPtrs &b, int32_t n_sims, int64_t max_slots, int32_t max_runs,
                                     int64_t max_cells, size_t shmem, bool observe, hipStream_t st) {
     const unsigned gs = (unsigned)((max_slots + 255) / 256);
     hipLaunchKernelGGL(we_batch_recycle_bin_kernel, dim3(gs, n_sims), dim3(256), 0, st, b);
     hipLaunchKernelGGL(we_batch_resample_kernel, dim3(max_runs, n_sims),
                        dim3(resample_threads((int64_t)max_runs * n_sims)), shmem, st, b);
-    hipLaunchKernelGGL(we_batch_gather_kernel, dim3((unsigned)((max_cells + 255) / 256), n_sims), dim3(256), 0, st, b);
+    const unsigned gg = (unsigned)std::max<int64_t>(1, std::min<int64_t>((max_cells + 255) / 256, BATCH_GATHER_BLOCKS));
+    hipLaunchKernelGGL(we_batch_gather_kernel, dim3(gg, n_sims), dim3(256), 0, st, b);
     if (observe) hipLaunchKernelGGL(we_batch_observe_kernel, dim3(gs, n_sims), dim3(256), 0, st, b);
     hipLaunchKernelGGL(we_batch_advance_kernel, dim3((n_sims + 63) / 64), dim3(64), 0, st, b, n_sims);
     return hipGetLastError();
