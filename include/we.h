@@ -154,6 +154,18 @@ typedef struct {
                                /*   from Philox(n, slot, iter, 4)).  Lane kernel,   */
                                /*   mass action, S <= 8, R <= 16, no batches        */
     double leap_eps;           /* tau-leaping error control epsilon, in (0, 1)      */
+    int32_t resample_rule;     /* per-bin split/merge (Sec. II.B):                  */
+                               /*   0: count-only, as the procedure is printed:     */
+                               /*      n < m_targ: replicate, n > m_targ: merge the */
+                               /*      two lowest weights until m_targ remain;      */
+                               /*   1: weight-equalizing (the paper resamples       */
+                               /*      "according to the weight" of each segment):  */
+                               /*      with W the bin's weight summed in slot order */
+                               /*      and w* = W / m_targ, merge the two lowest    */
+                               /*      while their sum is <= w* or                  */
+                               /*      sum_k max(1, ceil(w_k / (2 w*))) > m_targ,   */
+                               /*      then replicate up to m_targ.  A bin of zero  */
+                               /*      weight falls back to rule 0.                 */
 } we_params;
 
 /* Device bytes a sim needs (walker buffers, series, scratch). */

@@ -54,7 +54,7 @@ def lib():
                                     P(C.c_int32), C.c_int32, P(C.c_double), P(C.c_int64),
                                     P(C.c_int32), P(C.c_int32)]
         L.or_we_iterate.restype = C.c_int32
-        L.or_resample_bin.argtypes = [C.c_int32, P(C.c_int32), P(C.c_double), C.c_int32,
+        L.or_resample_bin.argtypes = [C.c_int32, P(C.c_int32), P(C.c_double), C.c_int32, C.c_int32,
                                       C.c_uint64, C.c_uint32, C.c_uint32,
                                       P(C.c_int32), P(C.c_double)]
         L.or_resample_bin.restype = C.c_int32
@@ -80,7 +80,8 @@ class _CfgStruct(C.Structure):
                 ("n_bins2", C.c_int32), ("bin_coef2", C.c_void_p), ("edges2", C.c_void_p),
                 ("m_targ", C.c_int32), ("tau", C.c_double), ("seed", C.c_uint64),
                 ("recycle", C.c_int32), ("tgt_coef", C.c_void_p), ("tgt_thr", C.c_double),
-                ("x_rec", C.c_void_p), ("engine", C.c_int32), ("leap_eps", C.c_double)]
+                ("x_rec", C.c_void_p), ("engine", C.c_int32), ("leap_eps", C.c_double),
+                ("resample_rule", C.c_int32)]
 
 
 class OracleNet:
@@ -163,13 +164,13 @@ def bin_of(edges, q: float) -> int:
     return lib().or_bin_of(len(e) - 1, _p(e, C.c_double), q)
 
 
-def resample_bin(slots, weights, m_targ: int, seed: int, b: int, it: int):
+def resample_bin(slots, weights, m_targ: int, seed: int, b: int, it: int, rule: int = 0):
     s = np.ascontiguousarray(slots, dtype=np.int32)
     w = np.ascontiguousarray(weights, dtype=np.float64)
     n_out = max(m_targ, len(s), 1)
     os_ = np.zeros(n_out, np.int32)
     ow = np.zeros(n_out, np.float64)
-    n = lib().or_resample_bin(len(s), _p(s, C.c_int32), _p(w, C.c_double), m_targ, seed,
+    n = lib().or_resample_bin(len(s), _p(s, C.c_int32), _p(w, C.c_double), m_targ, rule, seed,
                               b, it, _p(os_, C.c_int32), _p(ow, C.c_double))
     return os_[:n].copy(), ow[:n].copy()
 
@@ -208,7 +209,8 @@ class OracleWE:
                              cfg.m_targ, cfg.tau, self.seed, int(bool(cfg.recycle)),
                              a["tgt_coef"].ctypes.data, float(cfg.tgt_thr), a["x_rec"].ctypes.data,
                              1 if getattr(cfg, "engine", "ssa") == "tauleap" else 0,
-                             float(getattr(cfg, "leap_eps", 0.03)))
+                             float(getattr(cfg, "leap_eps", 0.03)),
+                             int(getattr(cfg, "resample_rule", 0)))
         self.cptr = C.cast(C.pointer(self.cs), C.c_void_p)
         self.x = np.zeros(cap * S, np.int32)
         self.w = np.zeros(cap, np.float64)

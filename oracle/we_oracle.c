@@ -26,6 +26,14 @@
  *  - merge (Sec. II.B): while n > M_targ, take the two lowest-weight walkers
  *    (ties: lowest slot); keep the first with probability w_i / (w_i + w_j),
  *    else the second; the survivor carries w_i + w_j.
+ *  - weight-equalizing resampling (rule 1; the paper resamples "according to
+ *    the weight" of each segment and ran implementations that keep the
+ *    weights in a bin near W/M_targ): with W the bin's weight (summed in slot
+ *    order) and w* = W / M_targ, the two lowest-weight walkers are merged as
+ *    above while their sum is at most w*, or while the bin has no room to
+ *    split its heavy walkers: sum_k max(1, ceil(w_k / (2 w*))) > M_targ (this
+ *    also covers n > M_targ); the survivors are then split as above up to
+ *    M_targ.  Rule 0 is the count-only procedure as printed.
  *  - recycling (Sec. II.B.2): checked once at the end of each interval,
  *    before binning; a walker in B adds its weight to the flux and restarts
  *    from A with its weight.
@@ -447,83 +455,105 @@ int32_t or_bin_of(int32_t n_bins, const double *edges, double q)
 /* ------------------------------------------------------------------ */
 /* Resampling of one bin (split / merge).                             */
 /* ------------------------------------------------------------------ */
+/* The paper's split for a bin whose survivors number n_alive < m_targ:
+ * every survivor starts with one copy; the remaining copies go one at a time
+ * to the survivor with the largest per-copy weight (ties: lowest slot);
+ * copies carry w_k / c_k.  Writes the copies in slot order. */
+static int32_t split_survivors(int32_t nb, const int32_t *slot, const double *cw, const int32_t *alive,
+                               int32_t n_alive, int32_t m_targ, int32_t *out_slot, double *out_w)
+{
+    int32_t *c = (int32_t *)malloc(sizeof(int32_t) * (size_t)nb);
+    for (int32_t k = 0; k < nb; ++k) c[k] = alive[k] ? 1 : 0;
+    for (int32_t extra = n_alive; extra < m_targ; ++extra) {
+        int32_t best = -1;
+        double best_share = 0.0;
+        for (int32_t k = 0; k < nb; ++k) {
+            if (!alive[k]) continue;
+            double share = cw[k] / (double)c[k];
+            if (best < 0 || share > best_share) { best = k; best_share = share; }
+        }
+        c[best] += 1;
+    }
+    int32_t o = 0;
+    for (int32_t k = 0; k < nb; ++k) {
+        if (!alive[k]) continue;
+        double share = cw[k] / (double)c[k];
+        for (int32_t copy = 0; copy < c[k]; ++copy) {
+            out_slot[o] = slot[k];
+            out_w[o] = share;
+            ++o;
+        }
+    }
+    free(c);
+    return o;
+}
+
+/* Copies a walker of weight v needs so that none carries more than twice the
+ * bin's ideal weight (at least one: every walker holds a place). */
+static int32_t need_copies(double v, double two_ideal)
+{
+    double q = ceil(v / two_ideal);
+    return q < 1.0 ? 1 : (int32_t)q;
+}
+
 int32_t or_resample_bin(int32_t nb, const int32_t *slot, const double *w,
-                        int32_t m_targ, uint64_t seed, uint32_t bin, uint32_t iter,
+                        int32_t m_targ, int32_t rule, uint64_t seed, uint32_t bin, uint32_t iter,
                         int32_t *out_slot, double *out_w)
 {
-    if (nb == 0) return 0;
-    if (nb == m_targ) {
-        for (int32_t k = 0; k < nb; ++k) { out_slot[k] = slot[k]; out_w[k] = w[k]; }
-        return nb;
-    }
-    if (nb < m_targ) {
-        /* split: copies c_k, start at one each, hand out the rest greedily */
-        int32_t *c = (int32_t *)malloc(sizeof(int32_t) * (size_t)nb);
-        for (int32_t k = 0; k < nb; ++k) c[k] = 1;
-        for (int32_t extra = nb; extra < m_targ; ++extra) {
-            int32_t best = 0;
-            double best_share = w[0] / (double)c[0];
-            for (int32_t k = 1; k < nb; ++k) {
-                double share = w[k] / (double)c[k];
-                if (share > best_share) { best = k; best_share = share; }
-            }
-            c[best] += 1;
-        }
-        int32_t o = 0;
-        for (int32_t k = 0; k < nb; ++k) {
-            double share = w[k] / (double)c[k];
-            for (int32_t copy = 0; copy < c[k]; ++copy) {
-                out_slot[o] = slot[k];
-                out_w[o] = share;
-                ++o;
-            }
-        }
-        free(c);
-        return o;
-    }
-    /* merge: alive[k] marks survivors; cw[k] is the current weight */
-    uint32_t key[2];
-    seed_key(seed, key);
+    if (nb <= 0) return 0;
+    /* the bin's weight and ideal per-walker weight (weight-equalizing rule) */
+    double W = 0.0;
+    for (int32_t k = 0; k < nb; ++k) W = W + w[k];
+    const int equalize = (rule == 1) && (W > 0.0);
+    const double ideal = W / (double)m_targ;
+    const double two_ideal = ideal + ideal;
+
     int32_t *alive = (int32_t *)malloc(sizeof(int32_t) * (size_t)nb);
     double *cw = (double *)malloc(sizeof(double) * (size_t)nb);
-    for (int32_t k = 0; k < nb; ++k) { alive[k] = 1; cw[k] = w[k]; }
+    int32_t need = 0;
+    for (int32_t k = 0; k < nb; ++k) {
+        alive[k] = 1;
+        cw[k] = w[k];
+        if (equalize) need += need_copies(w[k], two_ideal);
+    }
     int32_t n_alive = nb;
+
+    /* merge: the two lowest by (weight, slot); slots ascend with k */
+    uint32_t key[2];
+    seed_key(seed, key);
     uint32_t m = 0;
-    while (n_alive > m_targ) {
-        /* the two lowest by (weight, slot); slots ascend with k */
+    while (n_alive > 1) {
         int32_t i = -1, j = -1;
         for (int32_t k = 0; k < nb; ++k) {
             if (!alive[k]) continue;
             if (i < 0 || cw[k] < cw[i]) { j = i; i = k; }
             else if (j < 0 || cw[k] < cw[j]) { j = k; }
         }
+        double sum = cw[i] + cw[j];
+        int go = equalize ? (sum <= ideal || need > m_targ) : (n_alive > m_targ);
+        if (!go) break;
         uint32_t ctr[4] = {m, bin, iter, 1u}, r[4];
         or_philox4x32_10(ctr, key, r);
         m += 1;
         double u = or_u53(r[0], r[1]);
-        double sum = cw[i] + cw[j];
         double p_i = cw[i] / sum;
         int32_t keep = (u < p_i) ? i : j;
         int32_t drop = (keep == i) ? j : i;
+        if (equalize)
+            need = need - need_copies(cw[i], two_ideal) - need_copies(cw[j], two_ideal)
+                   + need_copies(sum, two_ideal);
         cw[keep] = sum;
         alive[drop] = 0;
         n_alive -= 1;
     }
-    int32_t o = 0;
-    for (int32_t k = 0; k < nb; ++k) {
-        if (!alive[k]) continue;
-        out_slot[o] = slot[k];
-        out_w[o] = cw[k];
-        ++o;
-    }
+
+    /* split: the survivors up to m_targ copies (nothing to do at m_targ) */
+    int32_t o = split_survivors(nb, slot, cw, alive, n_alive, m_targ, out_slot, out_w);
     free(alive);
     free(cw);
     return o;
 }
 
-/* ------------------------------------------------------------------ */
-/* One WE iteration.                                                  */
-/* ------------------------------------------------------------------ */
 int32_t or_we_iterate(const or_net *net, const or_we_cfg *cfg, uint32_t iter,
                       int32_t *n, int32_t *x, double *w, int32_t *bin,
                       int32_t *origin, int32_t cap,
@@ -582,8 +612,8 @@ int32_t or_we_iterate(const or_net *net, const or_we_cfg *cfg, uint32_t iter,
         int32_t nb = 0;
         for (int32_t k = 0; k < N; ++k)
             if (bin[k] == b) { bslot[nb] = k; bw[nb] = w[k]; ++nb; }
-        int32_t no = or_resample_bin(nb, bslot, bw, M, cfg->seed, (uint32_t)b, iter,
-                                     oslot, ow);
+        int32_t no = or_resample_bin(nb, bslot, bw, M, cfg->resample_rule, cfg->seed, (uint32_t)b,
+                                     iter, oslot, ow);
         for (int32_t o = 0; o < no; ++o) {
             memcpy(nx + (size_t)out * S, x + (size_t)oslot[o] * S, sizeof(int32_t) * (size_t)S);
             nw[out] = ow[o];

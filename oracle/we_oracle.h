@@ -71,6 +71,8 @@ typedef struct {
     const int32_t *x_rec;     /* [S]  recycling state A                            */
     int32_t engine;           /* 0: exact SSA; 1: tau-leaping (or_tauleap_interval) */
     double leap_eps;          /* tau-leaping error control epsilon                  */
+    int32_t resample_rule;    /* 0: count-only split/merge as printed (Sec. II.B);
+                                 1: weight-equalizing (or_resample_bin)             */
 } or_we_cfg;
 
 /* Philox4x32-10: ten rounds of the Philox S-box with key schedule, per
@@ -159,9 +161,16 @@ int32_t or_we_iterate(const or_net *net, const or_we_cfg *cfg, uint32_t iter,
 /* The resampling step alone, for one bin: nb walkers (parent slots, weights)
  * in ascending slot order.  Writes the surviving/replicated walkers as
  * (parent slot, weight) into out_slot/out_w in canonical order and returns
- * their number (m_targ if nb > 0, else 0). */
+ * their number (m_targ if nb > 0, else 0).
+ *   rule 0 (Sec. II.B as printed): n < M_targ: split; n > M_targ: merge the
+ *     two lowest-weight walkers until M_targ remain; n = M_targ: unchanged.
+ *   rule 1 (weight-equalizing): with W = sum of the bin's weights (slot
+ *     order) and w* = W / M_targ, merge the two lowest-weight walkers while
+ *     their sum is <= w* or sum_k max(1, ceil(w_k / (2 w*))) > M_targ; then
+ *     split the survivors up to M_targ.  A bin of zero weight uses rule 0.
+ * Merge draw m of (bin, iter) is Philox(ctr = (m, bin, iter, 1), key = seed). */
 int32_t or_resample_bin(int32_t nb, const int32_t *slot, const double *w,
-                        int32_t m_targ, uint64_t seed, uint32_t bin, uint32_t iter,
+                        int32_t m_targ, int32_t rule, uint64_t seed, uint32_t bin, uint32_t iter,
                         int32_t *out_slot, double *out_w);
 
 #ifdef __cplusplus

@@ -79,6 +79,7 @@ struct SimArgs {
     double leap_eps;                     // tau-leaping error control
     // runs
     int32_t n_runs, cap, n_bins, m_targ, max_iters;
+    int32_t rs_rule;                     // split/merge: 0 count-only, 1 weight-equalizing
     double tau;
     const uint64_t *__restrict__ seeds;  // [n_runs]
     // bins and target

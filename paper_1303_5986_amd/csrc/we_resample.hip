@@ -24,6 +24,11 @@
 //        n >  M: merge the two lowest-weight walkers (ties: lowest slot): the
 //                first survives with probability w_i/(w_i+w_j), else the
 //                second, and the survivor carries w_i + w_j; repeat.
+//        With the weight-equalizing rule (rs_rule 1), whatever n: W is the
+//        bin's weight summed in slot order and w* = W/M; the two lowest are
+//        merged as above while their sum is <= w* or the bin has no room to
+//        split its heavy walkers (sum_k max(1, ceil(w_k/(2w*))) > M, which
+//        includes n > M); the survivors are then replicated up to M as above.
 //        Up to 64 walkers a bin is held one walker per lane in registers and
 //        each merge takes two DPP wave minima.  Larger bins are sorted once
 //        by (weight, slot); merged walkers queue up in the order they are
@@ -177,6 +182,18 @@ __device__ __forceinline__ void wave_sync() {
 }
 
 __device__ __forceinline__ int32_t uni(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
+__device__ __forceinline__ int32_t wave_sum_i32(int32_t v) {
+    for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d, 64);
+    return v;
+}
+
+// Copies a walker of weight v needs so that none carries more than twice the
+// bin's ideal weight (at least one: every walker holds a place).
+__device__ __forceinline__ int32_t need_copies(double v, double two_ideal) {
+    const double q = ceil(v / two_ideal);
+    return q < 1.0 ? 1 : (int32_t)q;
+}
 
 struct BinOut {
     int32_t *orig;
@@ -427,12 +444,147 @@ __device__ void merge_bin_lanes(const RunWork<Idx> &wk, int32_t p0, int32_t nb, 
     }
 }
 
-// n > M: merge the two lightest walkers (ties: lowest slot) until M remain.
+// After merging with the weight-equalizing rule: the n_live survivors of a
+// bin (positions whose weight is >= 0; merged-away ones hold -1) replicated
+// up to M copies as in split_bin, the counts in aux.
 template <class Idx>
+__device__ void split_survivors(const RunWork<Idx> &wk, int32_t p0, int32_t nb, int32_t n_live, int32_t M,
+                                int32_t b, int32_t o0, const BinOut &out, int lane) {
+    const int32_t kq = (nb + 63) >> 6;
+    const int32_t q_lo = min(lane * kq, nb), q_hi = min(q_lo + kq, nb);
+    const double *w = wk.w + p0;
+    Idx *c = wk.aux + p0;
+    double bs = -1.0;
+    int32_t bq = -1;
+    for (int32_t q = q_lo; q < q_hi; ++q) {
+        const bool live = w[q] >= 0.0;
+        c[q] = (Idx)(live ? 1 : 0);
+        if (live) {
+            const double sh = w[q] / 1.0;
+            if (sh > bs) { bs = sh; bq = q; }
+        }
+    }
+    for (int32_t e = n_live; e < M; ++e) {
+        const double mx = wave_max(bs);
+        const int wl = __ffsll((long long)__ballot(bs == mx)) - 1;
+        if (lane == wl) {
+            c[bq] = (Idx)(c[bq] + 1);
+            bs = -1.0;
+            bq = -1;
+            for (int32_t q = q_lo; q < q_hi; ++q) {
+                if (!(w[q] >= 0.0)) continue;
+                const double sh = w[q] / (double)c[q];
+                if (sh > bs) { bs = sh; bq = q; }
+            }
+        }
+    }
+    int32_t cl = 0;
+    for (int32_t q = q_lo; q < q_hi; ++q) cl += (int32_t)c[q];
+    int32_t tot;
+    int32_t o = o0 + wave_excl_scan(cl, lane, &tot);
+    for (int32_t q = q_lo; q < q_hi; ++q) {
+        const int32_t cc = (int32_t)c[q];
+        if (cc == 0) continue;
+        const double share = w[q] / (double)cc;
+        const int32_t k = wk.list[p0 + q];
+        for (int32_t r = 0; r < cc; ++r) {
+            out.orig[o] = k;
+            out.wn[o] = share;
+            out.obin[o] = b;
+            ++o;
+        }
+    }
+}
+
+// Weight-equalizing rule with at most 64 walkers: walker q lives in lane q.
+// The merges are merge_bin_lanes' (same pairs, draws and sums) under the
+// rule's condition; the survivors are then replicated as in split_bin_lanes
+// (merged-away lanes hold +inf and get no copy).
+template <class Idx>
+__device__ void equalize_bin_lanes(const RunWork<Idx> &wk, int32_t p0, int32_t nb, int32_t M, int32_t b,
+                                   int32_t o0, const BinOut &out, uint32_t iter, uint32_t k0, uint32_t k1,
+                                   int lane) {
+    const double inf = __builtin_huge_val();
+    const bool own = lane < nb;
+    double wv = own ? wk.w[p0 + lane] : inf;
+    double Wb = 0.0;                      // the bin's weight, in slot order
+    for (int32_t q = 0; q < nb; ++q) Wb = Wb + wk.w[p0 + q];
+    const bool eq = Wb > 0.0;
+    const double ideal = Wb / (double)M;
+    const double two_ideal = ideal + ideal;
+    int32_t need = eq ? wave_sum_i32(own ? need_copies(wv, two_ideal) : 0) : 0;
+    int32_t n = nb;
+    double ul = 0.0;
+    for (int32_t m = 0; n > 1; ++m) {
+        const double wi = wave_min(wv);
+        const int qi = __ffsll((long long)__ballot(wv == wi)) - 1;
+        const double wrest = lane == qi ? inf : wv;
+        const double wj = wave_min(wrest);
+        const int qj = __ffsll((long long)__ballot(wrest == wj)) - 1;
+        const double sum = wi + wj;
+        const bool go = eq ? (sum <= ideal || need > M) : (n > M);
+        if (!go) break;
+        if ((m & 63) == 0) {   // the next 64 merge draws, one per lane
+            const U4 rr = philox4x32_10((uint32_t)(m + lane), (uint32_t)b, iter, 1u, k0, k1);
+            ul = uniform53(rr.x, rr.y);
+        }
+        const double u = rs_readlane(ul, m & 63);
+        const double p_i = wi / sum;
+        const int keep = (u < p_i) ? qi : qj;
+        const int drop = (keep == qi) ? qj : qi;
+        if (eq) need = need - need_copies(wi, two_ideal) - need_copies(wj, two_ideal) + need_copies(sum, two_ideal);
+        if (lane == keep) wv = sum;
+        if (lane == drop) wv = inf;
+        n -= 1;
+    }
+    const bool live = own && wv != inf;
+    int32_t c = live ? 1 : 0;
+    double bs = live ? wv / 1.0 : -1.0;
+    for (int32_t e = n; e < M; ++e) {
+        const double mx = wave_max(bs);
+        const int wl = __ffsll((long long)__ballot(bs == mx)) - 1;
+        if (lane == wl) {
+            c += 1;
+            bs = wv / (double)c;
+        }
+    }
+    int32_t tot;
+    int32_t o = o0 + wave_excl_scan(c, lane, &tot);
+    if (live) {
+        const double share = wv / (double)c;
+        const int32_t k = wk.list[p0 + lane];
+        for (int32_t r = 0; r < c; ++r) {
+            out.orig[o] = k;
+            out.wn[o] = share;
+            out.obin[o] = b;
+            ++o;
+        }
+    }
+}
+
+// n > M: merge the two lightest walkers (ties: lowest slot) until M remain.
+// EQ: the weight-equalizing rule's merges, then the survivors' split.
+template <class Idx, bool EQ>
 __device__ void merge_bin(const RunWork<Idx> &wk, int32_t p0, int32_t nb, int32_t M, int32_t b, int32_t o0,
                           const BinOut &out, uint32_t iter, uint32_t k0, uint32_t k1, int lane) {
     double *W = wk.w + p0;
     Idx *perm = wk.aux + p0;
+    bool eq = false;
+    double ideal = 0.0, two_ideal = 0.0;
+    int32_t need = 0;
+    if (EQ) {
+        double Wb = 0.0;                  // the bin's weight, in slot order
+        for (int32_t q = 0; q < nb; ++q) Wb = Wb + W[q];
+        eq = Wb > 0.0;
+        ideal = Wb / (double)M;
+        two_ideal = ideal + ideal;
+        if (eq) {
+            int32_t nl = 0;
+            for (int32_t q = lane; q < nb; q += 64) nl += need_copies(W[q], two_ideal);
+            need = wave_sum_i32(nl);
+        }
+        wave_sync();
+    }
     // sort order of the bin by (weight, slot): bitonic network whose first
     // step of every merge compares mirrored pairs, so positions past nb act as
     // +inf and never move
@@ -478,17 +630,26 @@ __device__ void merge_bin(const RunWork<Idx> &wk, int32_t p0, int32_t nb, int32_
     Q.hw = 0.0;
     Q.lane = lane;
     double ul = 0.0;
-    for (int32_t m = 0; m < nb - M; ++m) {
+    int32_t n = nb;
+    for (int32_t m = 0; EQ ? (n > 1) : (m < nb - M); ++m) {
         double wi, wj;
         int32_t qi, qj;
         Q.pop(&wi, &qi);
         Q.pop(&wj, &qj);
+        const double sum = wi + wj;
+        if (EQ) {
+            // the two just taken stay live (their weights are untouched)
+            const bool go = eq ? (sum <= ideal || need > M) : (n > M);
+            if (!go) break;
+            if (eq)
+                need = need - need_copies(wi, two_ideal) - need_copies(wj, two_ideal) +
+                       need_copies(sum, two_ideal);
+        }
         if ((m & 63) == 0) {   // the next 64 merge draws, one per lane
             const U4 rr = philox4x32_10((uint32_t)(m + lane), (uint32_t)b, iter, 1u, k0, k1);
             ul = uniform53(rr.x, rr.y);
         }
         const double u = rs_readlane(ul, m & 63);
-        const double sum = wi + wj;
         const double p_i = wi / sum;
         const int32_t keep = (u < p_i) ? qi : qj;
         const int32_t drop = (keep == qi) ? qj : qi;
@@ -498,8 +659,13 @@ __device__ void merge_bin(const RunWork<Idx> &wk, int32_t p0, int32_t nb, int32_
         }
         wave_sync();
         Q.push(sum, keep);
+        n -= 1;
     }
     wave_sync();
+    if (EQ) {
+        split_survivors(wk, p0, nb, n, M, b, o0, out, lane);
+        return;
+    }
 
     const int32_t kq = (nb + 63) >> 6;
     const int32_t q_lo = min(lane * kq, nb), q_hi = min(q_lo + kq, nb);
@@ -704,7 +870,10 @@ __device__ void resample_run_t(const SimArgs &a, const double *__restrict__ w_cu
         if (nb == 0) continue;
         const int32_t p0 = uni(start[b]), o0 = uni(ostart[b]);
         if (rw_acc) rw_flux_bin(a.rw_F + ((size_t)run * NB + b) * NB, wk, p0, nb, lane);
-        if (nb == M) {
+        if (a.rs_rule == 1) {
+            if (nb <= 64) equalize_bin_lanes(wk, p0, nb, M, b, o0, out, iter, k0, k1, lane);
+            else merge_bin<Idx, true>(wk, p0, nb, M, b, o0, out, iter, k0, k1, lane);
+        } else if (nb == M) {
             for (int32_t q = lane; q < nb; q += 64) {
                 out.orig[o0 + q] = wk.list[p0 + q];
                 out.wn[o0 + q] = wk.w[p0 + q];
@@ -715,7 +884,7 @@ __device__ void resample_run_t(const SimArgs &a, const double *__restrict__ w_cu
             else split_bin(wk, p0, nb, M, b, o0, out, lane);
         } else {
             if (nb <= 64) merge_bin_lanes(wk, p0, nb, M, b, o0, out, iter, k0, k1, lane);
-            else merge_bin(wk, p0, nb, M, b, o0, out, iter, k0, k1, lane);
+            else merge_bin<Idx, false>(wk, p0, nb, M, b, o0, out, iter, k0, k1, lane);
         }
     }
     __syncthreads();

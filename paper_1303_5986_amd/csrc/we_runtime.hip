@@ -359,6 +359,8 @@ we_status check_params(const we_network *net, const we_grid *g, const we_params 
     if (p->engine != 0 && p->engine != 1) return fail(WE_EINVAL, "engine must be 0 (SSA) or 1 (tau-leaping)");
     if (p->engine == 1 && !(p->leap_eps > 0.0 && p->leap_eps < 1.0))
         return fail(WE_EINVAL, "leap_eps must lie in (0, 1)");
+    if (p->resample_rule != 0 && p->resample_rule != 1)
+        return fail(WE_EINVAL, "resample_rule must be 0 (count-only) or 1 (weight-equalizing)");
     if (p->rw_period > 0 && grid_bins(g) > WE_RW_MAX_BINS)
         return fail(WE_EINVAL, "reweighting needs at most 512 bins");
     if (p->rw_period > 0 && (int64_t)p->n_runs * grid_bins(g) * grid_bins(g) > ((int64_t)1 << 31))
@@ -453,6 +455,7 @@ extern "C" we_status we_init(const we_network *net, const we_grid *g, const we_p
     a.leap_eps = p->engine == 1 ? p->leap_eps : 0.0;
     a.S = S; a.R = net->R;
     a.n_runs = n_runs; a.cap = cap; a.n_bins = NB; a.m_targ = M; a.max_iters = max_iters;
+    a.rs_rule = p->resample_rule;
     a.tau = p->tau;
     a.seeds = (const uint64_t *)at(P_SEEDS);
     a.bin_coef = (const double *)at(P_BCOEF);

@@ -64,7 +64,7 @@ class _Params(C.Structure):
                 ("hist_lo", C.c_int32), ("hist_hi", C.c_int32), ("n_joint", C.c_int32),
                 ("joint_species", C.c_void_p), ("joint_bins", C.c_int32), ("joint_width", C.c_int32),
                 ("record_iters", C.c_int32), ("rw_period", C.c_int32), ("rw_reset", C.c_int32),
-                ("engine", C.c_int32), ("leap_eps", C.c_double)]
+                ("engine", C.c_int32), ("leap_eps", C.c_double), ("resample_rule", C.c_int32)]
 
 
 class _TrainParams(C.Structure):
@@ -196,7 +196,8 @@ class Sim:
                  hist_species: int = 0, hist_lo: int = 0, hist_hi: int = -1,
                  joint_species: Sequence[int] = (), joint_bins: int = 16, joint_width: int = 64,
                  record_iters: int = 0, rw_period: int = 0, rw_reset: bool = False,
-                 bin_coef2=None, edges2=None, engine: str = "ssa", leap_eps: float = 0.03, device=None):
+                 bin_coef2=None, edges2=None, engine: str = "ssa", leap_eps: float = 0.03,
+                 resample_rule: int = 0, device=None):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("no HIP device: libwe.so runs on MI355X only")
@@ -232,7 +233,7 @@ class Sim:
                               int(hist_species), int(hist_lo), int(hist_hi),
                               len(joint_species), k["joint"].ctypes.data, int(joint_bins),
                               int(joint_width), int(record_iters), int(rw_period), int(bool(rw_reset)),
-                              {"ssa": 0, "tauleap": 1}[engine], float(leap_eps))
+                              {"ssa": 0, "tauleap": 1}[engine], float(leap_eps), int(resample_rule))
         self.n_joint = len(joint_species)
         self.joint_cells = int(joint_bins) ** self.n_joint if self.n_joint else 0
         self.nh = hist_hi - hist_lo + 1 if hist_hi >= hist_lo else 0
@@ -425,7 +426,8 @@ def sim_from_config(cfg, *, kernel: int = WE_KERNEL_AUTO, max_iters: Optional[in
                joint_species=getattr(cfg, "joint_species", ()) if joint else (),
                record_iters=record_iters, rw_period=rw_period, rw_reset=rw_reset,
                bin_coef2=getattr(cfg, "bin_coef2", None), edges2=getattr(cfg, "edges2", None),
-               engine=getattr(cfg, "engine", "ssa"), leap_eps=getattr(cfg, "leap_eps", 0.03))
+               engine=getattr(cfg, "engine", "ssa"), leap_eps=getattr(cfg, "leap_eps", 0.03),
+               resample_rule=getattr(cfg, "resample_rule", 0))
 
 
 def mlp_loss_grad(n_in: int, params, feat, x, y):
@@ -511,7 +513,8 @@ class Batch:
                                 int(c.hist_species), int(c.hist_lo), int(c.hist_hi),
                                 0, k["joint"].ctypes.data, 1, 1, 0, 0, 0,
                                 {"ssa": 0, "tauleap": 1}[getattr(c, "engine", "ssa")],
-                                float(getattr(c, "leap_eps", 0.03)))
+                                float(getattr(c, "leap_eps", 0.03)),
+                                int(getattr(c, "resample_rule", 0)))
         nets = (C.c_void_p * n)(*[net.handle.value for net in self.networks])
         self.stream = torch.cuda.current_stream()
         h = C.c_void_p()

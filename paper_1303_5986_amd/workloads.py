@@ -130,6 +130,9 @@ class WEConfig:
     edges2: Optional[np.ndarray] = None
     engine: str = "ssa"                      # "ssa" (exact) or "tauleap"
     leap_eps: float = 0.03                   # tau-leaping error control
+    resample_rule: int = 0                   # 0: count-only split/merge as printed;
+                                             # 1: weight-equalizing (keeps a bin's weights
+                                             #    near its weight / m_targ)
 
     @property
     def n_bins1(self) -> int:

@@ -100,6 +100,24 @@ def test_futile_cycle_six_species_bit_identical():
     _run_parity(cfg, 40, [0, 1])
 
 
+def test_weight_equalizing_rule_bit_identical():
+    """The weight-equalizing split/merge (rule 1) on the paper's futile-cycle
+    grid (101 unit bins on S1, 100 walkers per bin, bins above 64 walkers
+    take the sorted-queue path) and on Schloegl with recycling (8 walkers per
+    bin, one walker per lane): states, weights, bins, parents and flux equal
+    the oracle's after every iteration."""
+    _say("case: rule 1, futile cycle 2 runs x 30 iterations (M = 100)")
+    cfg = wl.WEConfig(name="futile", net=wl.futile_cycle(),
+                      x0=np.array([50, 50, 1, 1, 0, 0], np.int32),
+                      bin_coef=np.array([1.0, 0, 0, 0, 0, 0]),
+                      edges=np.arange(0.0, 102.0), m_targ=100, tau=1.0, n_iters=30,
+                      seeds=np.array([601, 602], np.uint64), resample_rule=1)
+    _run_parity(cfg, 30, [0, 1])
+    _say("case: rule 1, Schloegl with recycling, 3 runs x 120 iterations")
+    cfg = dataclasses.replace(wl.schlogl_config(n_runs=3, seed0=7, n_iters=120), resample_rule=1)
+    _run_parity(cfg, 120, [0, 1, 2])
+
+
 @pytest.mark.parametrize("S,R,seed", [(12, 30, 5), (24, 60, 6)])
 def test_random_small_networks_bit_identical(S, R, seed):
     """Random mass-action networks that select the 16x32 and 32x64 register

@@ -7,15 +7,15 @@ prints and that the closed-form references reproduce.
   Paper: WE 1.143e-9 +- 4.7e-11, CME 1.148e-9.
 * Futile cycle (Sec. III.A): P(S1 > 90, t = 100 s) from S1 = S2 = 50,
   101 unit bins on S1, 100 walkers per bin, tau = 1, 100 intervals.
-  Paper: WE 2.47e-18 +- 3.4e-19 from ten replicas, CME 2.72e-18.  Here the
-  per-replica estimates are strongly skewed (median about 1e-21, the mean
-  carried by a few replicas), far more than the paper's ten replicas
-  suggest, so 100 replicas are run -- one launch of about a million
-  walkers -- and the check is looser.
+  Paper: WE 2.47e-18 +- 3.4e-19 from ten replicas (a 14% standard error),
+  CME 2.72e-18.  Run with the weight-equalizing split/merge, the reading
+  under which the oracle reproduces that estimate and spread (the
+  count-only procedure as printed leaves the tail bins' weight on a few
+  heavy walkers, with a median replicate ~1e3 below the exact value); 100
+  replicas in one launch of about a million walkers.
 
 The checks: the replicas' mean lies within 3 standard errors (over
-replicas) of the exact value; Schloegl within 25% of it, the futile cycle
-within a factor of 3.
+replicas) of the exact value, and within 25% of it.
 """
 import json
 import os
@@ -65,12 +65,12 @@ def test_schlogl_transient_tail_at_paper_scale():
 
 
 def test_futile_cycle_tail_at_paper_scale():
-    print("case: futile cycle P(S1>90, t=100), 101 bins x 100 walkers x 100 replicas", flush=True)
+    print("case: futile cycle P(S1>90, t=100), 101 bins x 100 walkers x 100 replicas, rule 1", flush=True)
     x0 = np.array([50, 50, 1, 1, 0, 0], np.int32)      # S1 S2 E1 E2 B1 B2
     cfg = wl.WEConfig(name="futile_t100", net=wl.futile_cycle(), x0=x0,
                       bin_coef=np.array([1.0, 0, 0, 0, 0, 0]), edges=np.arange(0.0, 102.0),
                       m_targ=100, tau=1.0, n_iters=100,
-                      seeds=np.arange(601, 701, dtype=np.uint64))
+                      seeds=np.arange(601, 701, dtype=np.uint64), resample_rule=1)
     est = _tail_estimates(cfg, 0, 91, 100)
     states, p = cf.futile_transient(100.0)
     exact = sum(pk for s, pk in zip(states, p) if s[0] > 90)
@@ -78,4 +78,5 @@ def test_futile_cycle_tail_at_paper_scale():
     print(f"   WE {mean:.4e} +- {sem:.1e} (100 replicas, median {np.median(est):.2e}); "
           f"exact {exact:.4e}; paper CME {PAPER['futile_tail_t100']['value']:.3e}", flush=True)
     assert abs(mean - exact) < 3 * sem
-    assert exact / 3 < mean < 3 * exact
+    assert abs(mean / exact - 1) < 0.25
+    assert np.median(est) > 0.3 * exact

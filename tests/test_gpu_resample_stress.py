@@ -8,7 +8,9 @@ order hinges on the slot tie-break), bins far below M with equal shares
 sides of 64 walkers (up to 64 a bin is held one walker per lane), and sizes
 on both sides of the LDS limit of the per-run working arrays.  Walkers, weights,
 bins, parents and the recycled-weight record must equal the oracle's
-bit for bit."""
+bit for bit.  Every case runs under both split/merge rules: count-only as
+printed (rule 0) and weight-equalizing (rule 1), whose merges also run in
+bins at or below M and whose split then follows the merges."""
 import numpy as np
 import pytest
 
@@ -22,12 +24,13 @@ def _say(msg):
     print(msg, flush=True)
 
 
-def _frozen_config(n_bins, m_targ, n_runs):
+def _frozen_config(n_bins, m_targ, n_runs, rule):
     net = wl.Network.from_reactions(["X", "Y"], [({"X": 1}, {"X": 1, "Y": 1}, 0.0)])
     return wl.WEConfig(name="frozen", net=net, x0=np.array([0, 0], np.int32),
                        bin_coef=np.array([1.0, 0.0]),
                        edges=wl.uniform_edges(0.0, float(n_bins), n_bins), m_targ=m_targ,
-                       tau=1.0, n_iters=4, seeds=np.arange(11, 11 + n_runs, dtype=np.uint64))
+                       tau=1.0, n_iters=4, seeds=np.arange(11, 11 + n_runs, dtype=np.uint64),
+                       resample_rule=rule)
 
 
 def _ensemble(rng, counts, weight_kind):
@@ -69,13 +72,14 @@ CASES = [
 ]
 
 
+@pytest.mark.parametrize("rule", [0, 1])
 @pytest.mark.parametrize("case", range(len(CASES)))
-def test_resample_matches_oracle_on_stress_ensembles(case):
+def test_resample_matches_oracle_on_stress_ensembles(case, rule):
     we = __import__("paper_1303_5986_amd.we", fromlist=["we"])
     n_bins, m_targ, counts, kind = CASES[case]
-    _say(f"case: resample stress {case}: bins={n_bins} M={m_targ} counts={counts} weights={kind}")
+    _say(f"case: resample stress {case} rule {rule}: bins={n_bins} M={m_targ} counts={counts} weights={kind}")
     rng = np.random.default_rng(100 + case)
-    cfg = _frozen_config(n_bins, m_targ, len(counts))
+    cfg = _frozen_config(n_bins, m_targ, len(counts), rule)
     sim = we.sim_from_config(cfg, kernel=we.WE_KERNEL_LANE, max_iters=4)
     ors = []
     for r, cnt in enumerate(counts):

@@ -277,12 +277,21 @@ def test_split_single_walker_is_w_over_m():
 
 
 def test_split_greedy_shares():
+    """(0.5, 0.2, 0.1) filled to 8: the extra copies go, one at a time, to the
+    largest per-copy weight: 0.5, 0.25, 0.2, 1/6, 0.125 -> copies (5, 2, 1)."""
     s, w = orc.resample_bin([1, 4, 9], [0.5, 0.2, 0.1], 8, 1, 0, 0)
-    assert len(s) == 8
-    # 0.5 is split most; shares stay within a factor of the largest share
-    assert list(s).count(1) >= list(s).count(4) >= list(s).count(9) >= 1
+    assert list(s) == [1] * 5 + [4] * 2 + [9]
+    assert list(w) == [0.5 / 5] * 5 + [0.2 / 2] * 2 + [0.1]
     assert math.isclose(sum(w), 0.8, rel_tol=1e-15)
-    assert list(s) == sorted(s)
+
+
+def test_split_tie_goes_to_lowest_slot():
+    """Equal per-copy weights: the extra copy goes to the lowest slot."""
+    s, w = orc.resample_bin([3, 6], [0.2, 0.2], 3, 1, 0, 0)
+    assert list(s) == [3, 3, 6] and list(w) == [0.1, 0.1, 0.2]
+    s, w = orc.resample_bin([2, 5, 8], [0.3, 0.1, 0.2], 5, 1, 0, 0)
+    # shares 0.3 -> (0.15, 0.1, 0.2) -> 0.2 wins -> (0.15, 0.1, 0.1)
+    assert list(s) == [2, 2, 5, 8, 8] and list(w) == [0.15, 0.15, 0.1, 0.1, 0.1]
 
 
 def test_resample_keeps_exact_population():
@@ -335,6 +344,104 @@ def test_merge_takes_two_lowest():
     assert set(s) in ({0, 1, 3}, {1, 2, 3})
     merged = [v for k, v in zip(s, w) if k in (0, 2)]
     assert merged == [0.2 + 0.1] or merged == [0.1 + 0.2]
+
+
+# ------------------------------------------------ weight-equalizing split/merge
+def test_equalize_merges_light_pair_then_splits_heaviest():
+    """Rule 1 by hand: W = 1, w* = 0.25.  0.05 + 0.05 <= w* is merged; the
+    next pair 0.1 + 0.4 exceeds w* and every walker fits (sum of
+    max(1, ceil(w / 0.5)) = 3 <= 4), so merging stops; the survivors
+    (0.1, 0.5, 0.4) are split to 4 copies: 0.5 gets the extra one."""
+    for it in range(8):
+        s, w = orc.resample_bin([0, 1, 2, 3], [0.05, 0.05, 0.5, 0.4], 4, 3, 0, it, rule=1)
+        assert list(s[1:]) == [2, 2, 3] and s[0] in (0, 1)
+        assert list(w) == [0.05 + 0.05, 0.25, 0.25, 0.4]
+    # rule 0 leaves a bin of exactly M walkers untouched
+    s, w = orc.resample_bin([0, 1, 2, 3], [0.05, 0.05, 0.5, 0.4], 4, 3, 0, 0, rule=0)
+    assert list(s) == [0, 1, 2, 3] and list(w) == [0.05, 0.05, 0.5, 0.4]
+
+
+def test_equalize_makes_room_for_a_heavy_walker():
+    """One walker of 0.3 among nine of 0.7/9 with M = 10 (w* = 0.1): no pair
+    sums to <= w*, but the heavy walker needs ceil(0.3 / 0.2) = 2 places, so
+    one pair of light walkers is merged and the heavy walker split in two."""
+    w0 = [0.7 / 9] * 4 + [0.3] + [0.7 / 9] * 5
+    s, w = orc.resample_bin(list(range(10)), w0, 10, 5, 0, 0, rule=1)
+    assert len(s) == 10
+    assert list(s).count(4) == 2 and list(w[list(s).index(4):][:2]) == [0.15, 0.15]
+    assert max(w) <= 2 * 0.1
+    assert len(set(s)) == 9           # one light walker merged away
+    assert math.isclose(w.sum(), 1.0, rel_tol=1e-15)
+
+
+def test_equalize_bounds_every_share_and_conserves_weight():
+    """On random bins spanning many decades of weight, rule 1 returns M
+    walkers in canonical order, conserves the bin's weight, and no walker
+    carries more than twice W / M."""
+    rng = np.random.default_rng(17)
+    for trial in range(300):
+        n = int(rng.integers(1, 60))
+        M = int(rng.integers(1, 40))
+        w = rng.random(n) * 10.0 ** rng.integers(-12, 0, n)
+        s, ow = orc.resample_bin(list(range(n)), w, M, trial + 1, 2, trial, rule=1)
+        W = sum(w)
+        assert len(s) == M and list(s) == sorted(s)
+        assert abs(ow.sum() - W) <= 1e-14 * W
+        assert ow.max() <= 2.0 * (W / M) * (1 + 1e-12)
+
+
+def test_equalize_is_unbiased_in_expectation():
+    """E[w'_k] = w_k under rule 1 (merges keep a walker with probability
+    proportional to its weight; splits are deterministic).  Here w* = 0.2:
+    0.01 + 0.02, then 0.03 + 0.03, then 0.04 + 0.06 are merged and 0.9 is
+    split four ways."""
+    w = np.array([0.01, 0.02, 0.03, 0.04, 0.9])
+    acc = np.zeros(5)
+    n_draw = 20000
+    for it in range(n_draw):
+        s, ow = orc.resample_bin(list(range(5)), w, 5, 5, 1, it, rule=1)
+        assert len(s) == 5 and list(s).count(4) == 4
+        for k, v in zip(s, ow):
+            acc[k] += v
+    mean = acc / n_draw
+    assert np.all(np.abs(mean - w) < 5 * np.sqrt(w * 0.1 / n_draw) + 1e-15)
+
+
+def _futile_tail_replicas(rule, seeds):
+    x0 = np.array([50, 50, 1, 1, 0, 0], np.int32)
+    cfg = wl.WEConfig(name="futile_t100", net=wl.futile_cycle(), x0=x0,
+                      bin_coef=np.array([1.0, 0, 0, 0, 0, 0]), edges=np.arange(0.0, 102.0),
+                      m_targ=100, tau=1.0, n_iters=100, seeds=np.asarray(seeds, np.uint64),
+                      resample_rule=rule)
+    est = []
+    for sd in seeds:
+        o = orc.OracleWE(cfg, int(sd))
+        o.step(100)
+        x, w, _, _ = o.walkers()
+        est.append(w[x[:, 0] > 90].sum())
+    return np.array(est)
+
+
+def test_futile_cycle_tail_reproduces_the_paper_only_with_weight_equalizing():
+    """Sec. III.A: P(S1 > 90, t = 100) from ten replicates of 101 unit bins on
+    S1 x 100 walkers, tau = 1, 100 iterations; paper 2.47e-18 +- 3.4e-19
+    (14% s.e.), exact CME 2.72e-18.  With the weight-equalizing rule the
+    oracle's ten replicates agree with both; with the count-only rule as
+    printed, heavy walkers in full bins are never split, a few walkers carry
+    each tail bin's weight, and a typical replicate falls short by a factor
+    of ~1e3 (median), so that reading cannot give the paper's spread."""
+    states, p = cf.futile_transient(100.0)
+    exact = sum(pk for st, pk in zip(states, p) if st[0] > 90)
+    assert abs(exact / PAPER["futile_tail_t100"]["value"] - 1) < 0.01
+    seeds = range(601, 611)
+    eq = _futile_tail_replicas(1, seeds)
+    mean, sem = eq.mean(), eq.std(ddof=1) / np.sqrt(len(eq))
+    assert abs(mean - exact) < 3 * sem
+    assert abs(mean / exact - 1) < 0.25
+    assert np.median(eq) > 0.3 * exact
+    assert sem / mean < 0.35                      # the paper: 0.14 over ten replicates
+    cnt = _futile_tail_replicas(0, seeds)
+    assert np.median(cnt) < 1e-2 * exact
 
 
 # ------------------------------------------------------------ whole WE iterations
