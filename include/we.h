@@ -336,6 +336,27 @@ WE_API we_status we_mlp_loss_grad(int32_t n_in, const float *params, const float
                                   int32_t batch, const int32_t *x, const float *y, float *loss,
                                   float *grad);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight training loops, harnesses that forbid hipMalloc): the loss
+ * and gradient of we_mlp_loss_grad computed on caller-owned DEVICE buffers,
+ * asynchronously on `hip_stream` (a stream of the current device; NULL: the
+ * null stream), with no allocation of any kind.  params[n_params(n_in)],
+ * feat[2*n_in], x[batch*n_in], y[batch] are read; loss (one float, the mean
+ * BCE) and grad[n_params(n_in)] are written.  The per-sample activations and
+ * deltas live in a fixed device array of WE_MLP_NOALLOC_FLOATS floats (5 MiB)
+ * that each GPU holds until the process ends, so batch * (n_in + 258) must
+ * not exceed WE_MLP_NOALLOC_FLOATS (batch 4096 at 64 inputs).  Every call on
+ * a GPU shares that array; each call writes every entry it reads, so nothing
+ * needs clearing, but calls that overlap in time on one GPU (different
+ * streams, other threads) race and must be serialized by the caller.
+ * Errors: WE_EINVAL (bad sizes or NULL pointers), WE_ECAPACITY (beyond the
+ * scratch), WE_EDEVICE (symbol lookup or launch failure). */
+#define WE_MLP_NOALLOC_FLOATS (4096 * (64 + 258))
+#define WE_MAX_DEVICES 64
+WE_API we_status we_mlp_loss_grad_noalloc(int32_t n_in, const float *params, const float *feat,
+                                          int32_t batch, const int32_t *x, const float *y, float *loss,
+                                          float *grad, void *hip_stream);
+
 /* One Adam update (step t >= 1) of n host parameters in place.  Synchronous. */
 WE_API we_status we_adam_step(int32_t n, float *params, float *m, float *v, const float *grad,
                               float lr, int32_t t);

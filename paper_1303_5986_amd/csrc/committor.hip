@@ -32,6 +32,7 @@
 //     recycling.
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <vector>
 
 #include "we_internal.h"
@@ -759,6 +760,68 @@ extern "C" we_status we_mlp_loss_grad(int32_t n_in, const float *params, const f
     HIP_TRY(hipDeviceSynchronize());
     if (grad) HIP_TRY(hipMemcpy(grad, dg.p, 4ull * np, hipMemcpyDeviceToHost));
     if (loss) HIP_TRY(hipMemcpy(loss, dl.p, 4, hipMemcpyDeviceToHost));
+    return WE_OK;
+}
+
+// ------------------------------------------------- allocation-free loss/gradient
+// Fixed device scratch of we_mlp_loss_grad_noalloc: the per-sample features,
+// activations and deltas ([feature][batch] layout) of one minibatch.  Each
+// GPU holds its own copy for the life of the process.  Host code must never
+// pass `scratch` itself to a kernel (in host code the name is a host-side
+// stand-in, not a device address): it uses the per-device address looked up
+// once with hipGetSymbolAddress.
+static __device__ __align__(256) float scratch[WE_MLP_NOALLOC_FLOATS];
+
+namespace {
+std::mutex g_scratch_mu;
+float *g_scratch_dev[WE_MAX_DEVICES] = {};
+
+// The current device's address of `scratch`, looked up on the first call
+// made with that device current.
+we_status scratch_address(float **out) {
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= WE_MAX_DEVICES) return we_fail(WE_EDEVICE, "device index beyond WE_MAX_DEVICES");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *p = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return we_fail(WE_EDEVICE, "hipGetSymbolAddress returned no address for the scratch array");
+        g_scratch_dev[dev] = static_cast<float *>(p);
+    }
+    *out = g_scratch_dev[dev];
+    return WE_OK;
+}
+}  // namespace
+
+extern "C" we_status we_mlp_loss_grad_noalloc(int32_t n_in, const float *params, const float *feat, int32_t batch,
+                                              const int32_t *x, const float *y, float *loss, float *grad,
+                                              void *hip_stream) {
+    if (n_in < 1 || n_in > 1024 || batch < 1 || !params || !feat || !x || !y || !loss || !grad)
+        return we_fail(WE_EINVAL, "bad arguments");
+    const size_t need = (size_t)batch * ((size_t)n_in + 4 * CM_H + 2);
+    if (need > (size_t)WE_MLP_NOALLOC_FLOATS)
+        return we_fail(WE_ECAPACITY, "batch * (n_in + 258) exceeds the fixed scratch of WE_MLP_NOALLOC_FLOATS floats");
+    float *base = nullptr;
+    we_status st = scratch_address(&base);
+    if (st != WE_OK) return st;
+    const size_t B = (size_t)batch;
+    Scratch sc;
+    sc.phi = base;
+    sc.h1 = sc.phi + (size_t)n_in * B;
+    sc.h2 = sc.h1 + CM_H * B;
+    sc.g1 = sc.h2 + CM_H * B;
+    sc.g2 = sc.g1 + CM_H * B;
+    sc.g3 = sc.g2 + CM_H * B;
+    sc.loss = sc.g3 + B;
+    hipStream_t st_h = static_cast<hipStream_t>(hip_stream);
+    const int32_t np = cm_n_params(n_in);
+    hipLaunchKernelGGL(cm_fwd_bwd_kernel, dim3((batch + 3) / 4), dim3(256), cm_fwd_bwd_lds(n_in), st_h, params, feat,
+                       n_in, batch, 0, 0u, 0u, 0, (const int64_t *)nullptr, (const float *)nullptr,
+                       (const int32_t *)nullptr, x, y, sc);
+    HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(cm_grad_kernel, dim3((np + 1 + 3) / 4), dim3(256), 0, st_h, n_in, batch, sc, grad, loss);
+    HIP_TRY(hipGetLastError());
     return WE_OK;
 }
 

@@ -31,7 +31,7 @@ EXPORTED = [
     "we_counters", "we_events_series", "we_rw_flux_matrix", "we_rw_counts", "we_profile",
     "we_profile_read",
     "we_train_committor", "we_use_committor_bins", "we_committor_eval", "we_committor_state",
-    "we_record_labels", "we_get_record", "we_mlp_loss_grad", "we_adam_step",
+    "we_record_labels", "we_get_record", "we_mlp_loss_grad", "we_mlp_loss_grad_noalloc", "we_adam_step",
     "we_batch_create", "we_batch_step", "we_batch_graph_capture", "we_batch_graph_replay",
     "we_batch_sim", "we_batch_info", "we_batch_destroy",
     "we_destroy", "we_last_error",
@@ -121,6 +121,7 @@ def load_library(path: str = LIB_PATH):
     L.we_record_labels.argtypes = [vp, vp, f64, vp, P(i32)]
     L.we_get_record.argtypes = [vp, i32, vp, vp, vp, vp]
     L.we_mlp_loss_grad.argtypes = [i32, vp, vp, i32, vp, vp, vp, vp]
+    L.we_mlp_loss_grad_noalloc.argtypes = [i32, vp, vp, i32, vp, vp, vp, vp, vp]
     L.we_adam_step.argtypes = [i32, vp, vp, vp, vp, C.c_float, i32]
     L.we_batch_create.argtypes = [i32, vp, vp, vp, vp, i32, C.c_char_p, P(vp)]
     L.we_batch_step.argtypes = [vp, i32]
@@ -442,6 +443,22 @@ def mlp_loss_grad(n_in: int, params, feat, x, y):
     _check(load_library().we_mlp_loss_grad(n_in, _ptr(p), _ptr(f), len(yy), _ptr(xx), _ptr(yy),
                                            _ptr(loss), _ptr(g)))
     return float(loss[0]), g
+
+
+def mlp_loss_grad_noalloc(n_in: int, params, feat, x, y, loss, grad, stream=None):
+    """we_mlp_loss_grad_noalloc on torch device tensors (float32 params[n_params],
+    feat[2*n_in], y[batch], loss[1], grad[n_params]; int32 x[batch, n_in]),
+    launched on `stream` (default: torch's current stream).  Asynchronous."""
+    import torch
+    for t in (params, feat, x, y, loss, grad):
+        if not (t.is_cuda and t.is_contiguous()):
+            raise ValueError("mlp_loss_grad_noalloc needs contiguous device tensors")
+    st = stream if stream is not None else torch.cuda.current_stream()
+    batch = int(y.numel())
+    vp = C.c_void_p
+    _check(load_library().we_mlp_loss_grad_noalloc(
+        int(n_in), vp(params.data_ptr()), vp(feat.data_ptr()), batch, vp(x.data_ptr()),
+        vp(y.data_ptr()), vp(loss.data_ptr()), vp(grad.data_ptr()), vp(st.cuda_stream)))
 
 
 def adam_step(params, m, v, grad, lr: float, t: int):
