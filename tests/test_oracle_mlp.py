@@ -54,6 +54,36 @@ def test_adam_first_step_closed_form():
     assert np.allclose(q, p - 1e-3 * g / (np.abs(g) + 1e-8), rtol=0, atol=1e-15)
 
 
+def test_adam_two_steps_hand_computed():
+    """A scalar parameter, gradients g1 = 1 then g2 = -2 (beta 0.9 / 0.999):
+    m1 = 0.1, v1 = 0.001, so m1/(1-0.9) = 1, v1/(1-0.999) = 1 and the first
+    step is lr/(1+eps); m2 = 0.09 - 0.2 = -0.11, v2 = 0.000999 + 0.004 =
+    0.004999, bias-corrected -0.11/0.19 and 0.004999/0.001999, so the second
+    step is lr * 0.5789474 / 1.5813763 = 0.3661035 lr upwards.  A slip in the
+    bias correction (beta instead of beta^t) moves step 2 by ~11%."""
+    lr = 1e-2
+    p0 = np.array([0.5])
+    p1, m1, v1 = mlp.adam(p0, np.zeros(1), np.zeros(1), np.array([1.0]), lr, 1)
+    assert abs(m1[0] - 0.1) < 1e-15 and abs(v1[0] - 0.001) < 1e-16
+    assert abs(p1[0] - (0.5 - lr / (1 + 1e-8))) < 1e-15
+    p2, m2, v2 = mlp.adam(p1, m1, v1, np.array([-2.0]), lr, 2)
+    assert abs(m2[0] + 0.11) < 1e-15 and abs(v2[0] - 0.004999) < 1e-16
+    step = (0.11 / 0.19) / (np.sqrt(0.004999 / 0.001999) + 1e-8)
+    assert abs(step - 0.3661035) < 1e-6
+    assert abs(p2[0] - (p1[0] + lr * step)) < 1e-14
+
+
+def test_adam_constant_gradient_takes_equal_steps():
+    """With a constant gradient the bias-corrected moments are exactly g and
+    g^2 at every t, so every step is lr g / (|g| + eps) (t = 1..6)."""
+    g = np.array([0.3, -2.0, 1e-3])
+    p, m, v = np.zeros(3), np.zeros(3), np.zeros(3)
+    for t in range(1, 7):
+        q, m, v = mlp.adam(p, m, v, g, 1e-3, t)
+        assert np.allclose(p - q, 1e-3 * g / (np.abs(g) + 1e-8), rtol=1e-12, atol=0)
+        p = q
+
+
 def test_lineage_labels_hand_worked():
     """Two iterations, one run, three slots.  Iteration 1 (children):
     slot 0 from parent 0, flagged recycled (B); slot 1 from parent 0, in A;
