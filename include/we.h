@@ -182,6 +182,62 @@ WE_API we_status we_init(const we_network *net, const we_grid *grid, const we_pa
                          void *hip_stream, void *workspace, size_t workspace_bytes,
                          we_sim **out);
 
+/* Switch a sim's bins (Sec. II.B bins the state space; Sec. IV calls the
+ * choice of bins open).  kind WE_BINS_GRID: grid NULL returns to the sim's
+ * grid bins (after learned ones); a non-NULL grid replaces the coordinates
+ * and edges, keeping the number of bins on each axis (the slot reservation
+ * m_targ * n_bins depends on it).  kind WE_BINS_LEARNED: bin on the trained
+ * committor (we_train_committor), grid must be NULL.  Takes effect from the
+ * next iteration.  Synchronous.  Errors: WE_EINVAL (bin counts differ, edges
+ * not increasing), WE_ESTATE (a captured graph exists: recapture after
+ * switching; learned bins without a trained committor). */
+typedef enum { WE_BINS_GRID = 0, WE_BINS_LEARNED = 1 } we_bins_kind;
+typedef struct {
+    int32_t kind;              /* we_bins_kind                                      */
+    const we_grid *grid;       /* WE_BINS_GRID: new grid, or NULL                   */
+} we_bins;
+WE_API we_status we_set_bins(we_sim *s, const we_bins *bins);
+
+/* ---------------------------------------------------------------- checkpoints
+ * The WE procedure saves every trajectory's coordinates and weight after
+ * each iteration (Sec. II.B).  A checkpoint holds the whole state of a sim at
+ * an iteration boundary: every run's walkers (states, weights, bins, parent
+ * slots), the iteration, the seeds, the flux, event and segment series, the
+ * histogram accumulators, the reweighting flux matrix, the grid and
+ * parameters the sim was built with, and a trained committor (model, Adam
+ * moments, feature scaling, bin edges, whether bins are learned).  Random
+ * numbers are keyed by (seed, slot, event, iteration), so no generator state
+ * is needed: a sim loaded from a checkpoint continues exactly as the saved
+ * one would have.  Not saved: committor training records and captured
+ * graphs.  Format: a 64-byte header ("WESIMCKP", version, sizes, a
+ * fingerprint of the network) followed by sections in a fixed order, host
+ * byte order.
+ *
+ * we_save: synchronous; first reports a device fault latched by earlier
+ * steps (as we_histogram does).  Errors: WE_EINVAL (NULL), WE_EDEVICE (file
+ * cannot be written; device fault). */
+WE_API we_status we_save(we_sim *s, const char *path);
+
+/* Sizes recorded in a checkpoint (host-only: reads the header). */
+typedef struct {
+    int32_t version;
+    int32_t n_species, n_reactions, n_runs, n_bins, m_targ, max_iters, iteration;
+    int32_t hist_lo, hist_hi, n_joint, joint_bins, kernel;
+    double tau;
+    uint64_t workspace_bytes;  /* device bytes the loaded sim needs              */
+} we_checkpoint_info;
+WE_API we_status we_checkpoint_inspect(const char *path, we_checkpoint_info *info);
+
+/* Build a sim from a checkpoint on network `net`, which must be the network
+ * it was saved with (same species, reactions, rates, stoichiometry and Hill
+ * factors; checked by fingerprint).  hip_stream, workspace and
+ * workspace_bytes as for we_init (workspace_bytes >= the checkpoint's
+ * workspace_bytes).  Synchronous.  Errors: WE_EINVAL (unreadable file, bad
+ * magic or version, network mismatch, workspace too small), WE_ENOMEM,
+ * WE_EDEVICE. */
+WE_API we_status we_load(const we_network *net, const char *path, void *hip_stream, void *workspace,
+                         size_t workspace_bytes, we_sim **out);
+
 /* Replace run `run`'s ensemble before the first step: n walkers, states
  * x[n*S] (walker-major), weights w[n].  Errors: WE_ESTATE after stepping,
  * WE_ECAPACITY if n > cap, WE_EINVAL for counts out of range. */

@@ -276,6 +276,31 @@ class OracleWE:
             self.flux.append(flux.value)
             self.events.append(ev.value)
 
+    # checkpoints: the ensemble after an iteration plus the series; the
+    # random numbers are keyed by (seed, slot, event, iteration), so nothing
+    # else is needed to continue
+    _STATE = ("x", "w", "bin", "origin", "recycled", "end_bin", "rw_F")
+
+    def save(self, path: str):
+        np.savez(path, n=self.n, iter=self.iter, seed=self.seed, flux=np.array(self.flux, np.float64),
+                 events=np.array(self.events, np.int64), segments=np.array(self.segments, np.int64),
+                 rw=np.array([self.rw_applied, self.rw_skipped], np.int64),
+                 **{k: getattr(self, k) for k in self._STATE})
+
+    @classmethod
+    def load(cls, cfg, path: str, rw_period: int = 0, rw_reset: bool = False) -> "OracleWE":
+        z = np.load(path, allow_pickle=False)
+        o = cls(cfg, int(z["seed"]), rw_period=rw_period, rw_reset=rw_reset)
+        for k in cls._STATE:
+            getattr(o, k)[...] = z[k]
+        o.n = int(z["n"])
+        o.iter = int(z["iter"])
+        o.flux = [float(v) for v in z["flux"]]
+        o.events = [int(v) for v in z["events"]]
+        o.segments = [int(v) for v in z["segments"]]
+        o.rw_applied, o.rw_skipped = (int(v) for v in z["rw"])
+        return o
+
     # views of the current ensemble
     def walkers(self) -> Tuple[np.ndarray, np.ndarray, np.ndarray, np.ndarray]:
         S = self.cfg.net.S

@@ -518,6 +518,64 @@ void committor_free(we_sim *s) {
     c = Committor();
 }
 
+// The trained model as host arrays, and back (checkpoints).
+we_status committor_export(we_sim *s, CommittorHost &h) {
+    const Committor &C = s->cm;
+    h = CommittorHost();
+    h.trained = C.trained;
+    h.active = C.active;
+    if (!C.trained) return WE_OK;
+    h.n_in = C.n_in;
+    h.n_qbins = C.n_qbins;
+    const size_t np = (size_t)C.n_params, nwt = (size_t)CM_H * C.n_in + (size_t)CM_H * CM_H;
+    h.params.resize(np);
+    h.adam_m.resize(np);
+    h.adam_v.resize(np);
+    h.feat.resize(2 * (size_t)C.n_in);
+    h.qedges.resize((size_t)C.n_qbins + 1);
+    h.wt.resize(nwt);
+    HIP_TRY(hipMemcpyAsync(h.params.data(), C.d_params, 4 * np, hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipMemcpyAsync(h.adam_m.data(), C.d_adam_m, 4 * np, hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipMemcpyAsync(h.adam_v.data(), C.d_adam_v, 4 * np, hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipMemcpyAsync(h.feat.data(), C.d_feat, 8 * (size_t)C.n_in, hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipMemcpyAsync(h.qedges.data(), C.d_qedges, 8 * h.qedges.size(), hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipMemcpyAsync(h.wt.data(), C.d_wt, 4 * nwt, hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    return WE_OK;
+}
+
+we_status committor_import(we_sim *s, const CommittorHost &h) {
+    committor_free(s);
+    if (!h.trained) return WE_OK;
+    if (h.n_in != s->S || h.n_qbins != s->NB) return we_fail(WE_EINVAL, "checkpoint committor does not fit the sim");
+    Committor &C = s->cm;
+    C.n_in = h.n_in;
+    C.n_params = cm_n_params(h.n_in);
+    C.n_qbins = h.n_qbins;
+    const size_t np = (size_t)C.n_params, nwt = (size_t)CM_H * C.n_in + (size_t)CM_H * CM_H;
+    if (h.params.size() != np || h.adam_m.size() != np || h.adam_v.size() != np ||
+        h.feat.size() != 2 * (size_t)C.n_in || h.qedges.size() != (size_t)C.n_qbins + 1 || h.wt.size() != nwt)
+        return we_fail(WE_EINVAL, "checkpoint committor arrays have the wrong sizes");
+    HIP_TRY(hipMalloc(&C.d_params, 4 * np));
+    HIP_TRY(hipMalloc(&C.d_adam_m, 4 * np));
+    HIP_TRY(hipMalloc(&C.d_adam_v, 4 * np));
+    HIP_TRY(hipMalloc(&C.d_grad, 4 * np));
+    HIP_TRY(hipMalloc(&C.d_feat, 8 * (size_t)C.n_in));
+    HIP_TRY(hipMalloc(&C.d_qedges, 8 * h.qedges.size()));
+    HIP_TRY(hipMalloc(&C.d_wt, 4 * nwt));
+    HIP_TRY(hipMemcpyAsync(C.d_params, h.params.data(), 4 * np, hipMemcpyHostToDevice, s->stream));
+    HIP_TRY(hipMemcpyAsync(C.d_adam_m, h.adam_m.data(), 4 * np, hipMemcpyHostToDevice, s->stream));
+    HIP_TRY(hipMemcpyAsync(C.d_adam_v, h.adam_v.data(), 4 * np, hipMemcpyHostToDevice, s->stream));
+    HIP_TRY(hipMemsetAsync(C.d_grad, 0, 4 * np, s->stream));
+    HIP_TRY(hipMemcpyAsync(C.d_feat, h.feat.data(), 8 * (size_t)C.n_in, hipMemcpyHostToDevice, s->stream));
+    HIP_TRY(hipMemcpyAsync(C.d_qedges, h.qedges.data(), 8 * h.qedges.size(), hipMemcpyHostToDevice, s->stream));
+    HIP_TRY(hipMemcpyAsync(C.d_wt, h.wt.data(), 4 * nwt, hipMemcpyHostToDevice, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    C.trained = true;
+    C.active = h.active;
+    return WE_OK;
+}
+
 // ------------------------------------------------------------------ C ABI
 namespace {
 

@@ -61,6 +61,17 @@ struct Records {
     int32_t *d_n = nullptr;         // [cap_iters][n_runs]
 };
 
+// Host copy of a sim's grid and parameters (the arrays the we_grid and
+// we_params pointers referred to at init).
+struct SimConfig {
+    we_params p{};
+    int32_t n_bins = 0, n_bins2 = 0;
+    std::vector<double> coef, edges, coef2, edges2, tgt_coef;
+    std::vector<uint64_t> seeds;
+    std::vector<int32_t> x0, x_rec, joint;
+    size_t ws_bytes = 0;
+};
+
 struct we_sim {
     const we_network *net = nullptr;
     hipStream_t stream = nullptr;
@@ -91,10 +102,13 @@ struct we_sim {
     Records rec;
     Committor cm;
     double *d_bin_edges_grid = nullptr;
+    // the configuration the sim was built from (checkpoints, we_set_bins)
+    SimConfig cfg;
 };
 
 // we_runtime.hip
 extern "C" void we_batch_destroy(we_batch *b);
+we_status we_read_err(we_sim *s);
 we_status we_sim_bookkeeping(we_sim *s, hipStream_t st, hipEvent_t *ev);
 hipError_t launch_ssa_lane(const SimArgs &a, int32_t *xs, hipStream_t st);
 hipError_t launch_work_queue(const SimArgs &a, hipStream_t st);
@@ -107,6 +121,14 @@ bool rw_solve_in_lds(int32_t n_bins);
 hipError_t launch_reweight(const SimArgs &a, double *w_nxt, hipStream_t st);
 
 // committor.hip
+struct CommittorHost {
+    bool trained = false, active = false;
+    int32_t n_in = 0, n_qbins = 0;
+    std::vector<float> params, adam_m, adam_v, feat, wt;
+    std::vector<double> qedges;
+};
+we_status committor_export(we_sim *s, CommittorHost &h);
+we_status committor_import(we_sim *s, const CommittorHost &h);
 hipError_t committor_record(we_sim *s, hipStream_t st);
 hipError_t committor_bin(we_sim *s, int32_t *x_cur, hipStream_t st);
 void committor_free(we_sim *s);

@@ -398,6 +398,39 @@ extern "C" we_status we_workspace_size(const we_network *net, const we_grid *g, 
     return WE_OK;
 }
 
+// Bin coefficients, edges and the lists of species with nonzero bin and
+// target coefficients, from the sim's configuration, on the sim's stream
+// (synchronous).
+hipError_t upload_grid(we_sim *s) {
+    SimArgs &a = s->args;
+    const SimConfig &cf = s->cfg;
+    const int32_t S = s->S, NB1 = cf.n_bins, NB2 = cf.n_bins2 > 1 ? cf.n_bins2 : 1;
+    std::vector<double> coefs, edges_all;
+    std::vector<int32_t> nz;
+    coefs.assign(2 * (size_t)S, 0.0);
+    edges_all.assign((size_t)NB1 + 1 + NB2 + 1, 0.0);
+    for (int32_t sp = 0; sp < S; ++sp) {
+        coefs[sp] = cf.coef[sp];
+        if (NB2 > 1) coefs[S + sp] = cf.coef2[sp];
+    }
+    for (int32_t b = 0; b <= NB1; ++b) edges_all[b] = cf.edges[b];
+    for (int32_t b = 0; b <= NB2; ++b) edges_all[NB1 + 1 + b] = NB2 > 1 ? cf.edges2[b] : (double)b;
+    nz.assign(3 * (size_t)S, 0);
+    a.n_bin_nz = a.n_tgt_nz = a.n_bin_nz2 = 0;
+    for (int32_t sp = 0; sp < S; ++sp) {
+        if (cf.coef[sp] != 0.0) nz[a.n_bin_nz++] = sp;
+        if (cf.tgt_coef[sp] != 0.0) nz[S + a.n_tgt_nz++] = sp;
+        if (NB2 > 1 && cf.coef2[sp] != 0.0) nz[2 * S + a.n_bin_nz2++] = sp;
+    }
+    hipError_t e = hipMemcpyAsync((void *)a.bin_coef, coefs.data(), 8 * coefs.size(), hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync((void *)a.edges, edges_all.data(), 8 * edges_all.size(), hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync((void *)a.bin_nz, nz.data(), 4 * nz.size(), hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    return e;
+}
+
 extern "C" we_status we_init(const we_network *net, const we_grid *g, const we_params *p,
                              void *hip_stream, void *workspace, size_t workspace_bytes,
                              we_sim **out) {
@@ -518,7 +551,6 @@ extern "C" we_status we_init(const we_network *net, const we_grid *g, const we_p
             for (int32_t q = 0; q < S; ++q) hx[((size_t)r * cap + k) * S + q] = p->x0[q];
             hw[(size_t)r * cap + k] = 1.0 / (double)M;
         }
-    std::vector<double> zcoef(S, 0.0);
     const hipStream_t st_ = s->stream;
     auto put = [&](int piece, const void *src, size_t bytes) -> hipError_t {
         return hipMemcpyAsync(at(piece), src, bytes, hipMemcpyHostToDevice, st_);
@@ -529,24 +561,30 @@ extern "C" we_status we_init(const we_network *net, const we_grid *g, const we_p
     if (e == hipSuccess) e = put(P_N, hn.data(), 4 * (size_t)n_runs);
     if (e == hipSuccess) e = put(P_ORIG, horig.data(), 4 * W);
     if (e == hipSuccess) e = put(P_SEEDS, p->seeds, 8 * (size_t)n_runs);
-    std::vector<double> coefs(2 * (size_t)S, 0.0), edges_all((size_t)NB1 + 1 + NB2 + 1, 0.0);
-    for (int32_t sp = 0; sp < S; ++sp) {
-        coefs[sp] = g->coef[sp];
-        if (NB2 > 1) coefs[S + sp] = g->coef2[sp];
+    // the configuration, kept for checkpoints and we_set_bins
+    SimConfig &cf = s->cfg;
+    cf.p = *p;
+    cf.p.kernel = kernel;
+    cf.n_bins = NB1;
+    cf.n_bins2 = g->n_bins2;
+    cf.coef.assign(g->coef, g->coef + S);
+    cf.edges.assign(g->edges, g->edges + NB1 + 1);
+    if (NB2 > 1) {
+        cf.coef2.assign(g->coef2, g->coef2 + S);
+        cf.edges2.assign(g->edges2, g->edges2 + NB2 + 1);
     }
-    for (int32_t b = 0; b <= NB1; ++b) edges_all[b] = g->edges[b];
-    for (int32_t b = 0; b <= NB2; ++b) edges_all[NB1 + 1 + b] = NB2 > 1 ? g->edges2[b] : (double)b;
-    if (e == hipSuccess) e = put(P_BCOEF, coefs.data(), 8 * coefs.size());
-    if (e == hipSuccess) e = put(P_EDGES, edges_all.data(), 8 * edges_all.size());
-    if (e == hipSuccess) e = put(P_TCOEF, p->tgt_coef ? p->tgt_coef : zcoef.data(), 8 * (size_t)S);
-    std::vector<int32_t> nz(3 * (size_t)S, 0);
-    a.n_bin_nz = a.n_tgt_nz = a.n_bin_nz2 = 0;
-    for (int32_t sp = 0; sp < S; ++sp) {
-        if (g->coef[sp] != 0.0) nz[a.n_bin_nz++] = sp;
-        if (p->tgt_coef && p->tgt_coef[sp] != 0.0) nz[S + a.n_tgt_nz++] = sp;
-        if (NB2 > 1 && g->coef2[sp] != 0.0) nz[2 * S + a.n_bin_nz2++] = sp;
-    }
-    if (e == hipSuccess) e = put(P_NZ, nz.data(), 4 * nz.size());
+    cf.tgt_coef.assign(S, 0.0);
+    if (p->tgt_coef) cf.tgt_coef.assign(p->tgt_coef, p->tgt_coef + S);
+    cf.seeds.assign(p->seeds, p->seeds + n_runs);
+    cf.x0.assign(p->x0, p->x0 + S);
+    cf.x_rec.assign(p->x_rec ? p->x_rec : p->x0, (p->x_rec ? p->x_rec : p->x0) + S);
+    cf.joint.assign(p->joint_species ? p->joint_species : p->x0,
+                    (p->joint_species ? p->joint_species : p->x0) + (p->n_joint > 0 ? p->n_joint : 0));
+    cf.ws_bytes = L.total;
+    cf.p.seeds = nullptr; cf.p.x0 = nullptr; cf.p.tgt_coef = nullptr; cf.p.x_rec = nullptr;
+    cf.p.joint_species = nullptr;
+    if (e == hipSuccess) e = put(P_TCOEF, cf.tgt_coef.data(), 8 * (size_t)S);
+    if (e == hipSuccess) e = upload_grid(s);
     if (e == hipSuccess) e = put(P_XREC, p->x_rec ? p->x_rec : p->x0, 4 * (size_t)S);
     if (e == hipSuccess) e = hipStreamSynchronize(st_);
     if (e != hipSuccess) {
@@ -603,6 +641,8 @@ we_status read_err(we_sim *s) {
     return WE_OK;
 }
 }  // namespace
+
+we_status we_read_err(we_sim *s) { return read_err(s); }
 
 // Everything after propagation: recycle and bin, resample and gather,
 // observables, the device iteration counter, records; flips the buffers.
@@ -894,6 +934,38 @@ extern "C" we_status we_profile_read(we_sim *s, double *ms_propagate, double *ms
     if (ms_resample) *ms_resample = s->prof_ms[1];
     if (ms_observe) *ms_observe = s->prof_ms[2];
     if (iterations) *iterations = s->prof_iters;
+    return WE_OK;
+}
+
+extern "C" we_status we_set_bins(we_sim *s, const we_bins *b) {
+    if (!s || !b) return fail(WE_EINVAL, "NULL argument");
+    if (b->kind == WE_BINS_LEARNED) {
+        if (b->grid) return fail(WE_EINVAL, "learned bins take no grid");
+        return we_use_committor_bins(s, 1);
+    }
+    if (b->kind != WE_BINS_GRID) return fail(WE_EINVAL, "unknown bin kind");
+    if (s->graph_exec) return fail(WE_ESTATE, "recapture the graph after switching bins");
+    if (b->grid) {
+        const we_grid *g = b->grid;
+        SimConfig &cf = s->cfg;
+        if (g->n_bins != cf.n_bins || (g->n_bins2 > 1 ? g->n_bins2 : 1) != (cf.n_bins2 > 1 ? cf.n_bins2 : 1))
+            return fail(WE_EINVAL, "a new grid must keep the number of bins on each axis");
+        if (!g->coef || !g->edges || (g->n_bins2 > 1 && (!g->coef2 || !g->edges2)))
+            return fail(WE_EINVAL, "bad grid");
+        for (int32_t k = 0; k < g->n_bins; ++k)
+            if (!(g->edges[k] < g->edges[k + 1])) return fail(WE_EINVAL, "edges must increase strictly");
+        for (int32_t k = 0; g->n_bins2 > 1 && k < g->n_bins2; ++k)
+            if (!(g->edges2[k] < g->edges2[k + 1])) return fail(WE_EINVAL, "edges2 must increase strictly");
+        HIP_TRY(hipStreamSynchronize(s->stream));
+        cf.coef.assign(g->coef, g->coef + s->S);
+        cf.edges.assign(g->edges, g->edges + g->n_bins + 1);
+        if (g->n_bins2 > 1) {
+            cf.coef2.assign(g->coef2, g->coef2 + s->S);
+            cf.edges2.assign(g->edges2, g->edges2 + g->n_bins2 + 1);
+        }
+        HIP_TRY(upload_grid(s));
+    }
+    s->cm.active = false;
     return WE_OK;
 }
 

@@ -34,6 +34,7 @@ EXPORTED = [
     "we_record_labels", "we_get_record", "we_mlp_loss_grad", "we_mlp_loss_grad_noalloc", "we_adam_step",
     "we_batch_create", "we_batch_step", "we_batch_graph_capture", "we_batch_graph_replay",
     "we_batch_sim", "we_batch_info", "we_batch_destroy",
+    "we_set_bins", "we_save", "we_checkpoint_inspect", "we_load",
     "we_destroy", "we_last_error",
 ]
 
@@ -65,6 +66,21 @@ class _Params(C.Structure):
                 ("joint_species", C.c_void_p), ("joint_bins", C.c_int32), ("joint_width", C.c_int32),
                 ("record_iters", C.c_int32), ("rw_period", C.c_int32), ("rw_reset", C.c_int32),
                 ("engine", C.c_int32), ("leap_eps", C.c_double), ("resample_rule", C.c_int32)]
+
+
+class _Bins(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("grid", C.c_void_p)]
+
+
+class _CheckpointInfo(C.Structure):
+    _fields_ = [("version", C.c_int32), ("n_species", C.c_int32), ("n_reactions", C.c_int32),
+                ("n_runs", C.c_int32), ("n_bins", C.c_int32), ("m_targ", C.c_int32),
+                ("max_iters", C.c_int32), ("iteration", C.c_int32), ("hist_lo", C.c_int32),
+                ("hist_hi", C.c_int32), ("n_joint", C.c_int32), ("joint_bins", C.c_int32),
+                ("kernel", C.c_int32), ("tau", C.c_double), ("workspace_bytes", C.c_uint64)]
+
+
+WE_BINS_GRID, WE_BINS_LEARNED = 0, 1
 
 
 class _TrainParams(C.Structure):
@@ -132,6 +148,10 @@ def load_library(path: str = LIB_PATH):
     L.we_batch_info.argtypes = [vp, P(i32), vp]
     L.we_batch_destroy.argtypes = [vp]
     L.we_batch_destroy.restype = None
+    L.we_set_bins.argtypes = [vp, vp]
+    L.we_save.argtypes = [vp, C.c_char_p]
+    L.we_checkpoint_inspect.argtypes = [C.c_char_p, vp]
+    L.we_load.argtypes = [vp, C.c_char_p, vp, vp, C.c_size_t, P(vp)]
     L.we_destroy.argtypes = [vp]
     L.we_destroy.restype = None
     L.we_last_error.restype = C.c_char_p
@@ -253,6 +273,61 @@ class Sim:
                          C.c_void_p(self.stream.cuda_stream), C.c_void_p(aligned),
                          C.c_size_t(int(nbytes.value)), C.byref(h)))
         self.handle = h
+
+    # ------------------------------------------------------------ checkpoints, bins
+    def save(self, path: str):
+        """Write a checkpoint of every run at the current iteration."""
+        _check(load_library().we_save(self.handle, os.fspath(path).encode()))
+
+    @classmethod
+    def load(cls, network: "Network", path: str, device=None) -> "Sim":
+        """A sim rebuilt from a checkpoint saved on `network`."""
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device: libwe.so runs on MI355X only")
+        L = load_library()
+        info = checkpoint_info(path)
+        self = cls.__new__(cls)
+        self.network = network
+        self.S = info.n_species
+        self.n_bins = info.n_bins
+        self.n_runs = info.n_runs
+        self.m_targ = info.m_targ
+        self.cap = self.m_targ * self.n_bins
+        self.tau = info.tau
+        self.n_joint = info.n_joint
+        self.joint_cells = int(info.joint_bins) ** self.n_joint if self.n_joint else 0
+        self.nh = info.hist_hi - info.hist_lo + 1 if info.hist_hi >= info.hist_lo else 0
+        self._keep = {}
+        dev = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        self.device = dev
+        nbytes = int(info.workspace_bytes)
+        with torch.cuda.device(dev):
+            self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+            self.stream = torch.cuda.current_stream(dev)
+        aligned = (self.workspace.data_ptr() + 255) & ~255
+        h = C.c_void_p()
+        _check(L.we_load(network.handle, os.fspath(path).encode(), C.c_void_p(self.stream.cuda_stream),
+                         C.c_void_p(aligned), C.c_size_t(nbytes), C.byref(h)))
+        self.handle = h
+        return self
+
+    def set_grid_bins(self, bin_coef=None, edges=None, bin_coef2=None, edges2=None):
+        """Bin on a new grid with the same number of bins per axis, or (no
+        arguments) on the sim's grid again after learned bins."""
+        if edges is None:
+            _check(load_library().we_set_bins(self.handle, C.byref(_Bins(WE_BINS_GRID, None))))
+            return
+        k = dict(coef=np.ascontiguousarray(bin_coef, np.float64), edges=np.ascontiguousarray(edges, np.float64),
+                 coef2=None if bin_coef2 is None else np.ascontiguousarray(bin_coef2, np.float64),
+                 edges2=None if edges2 is None else np.ascontiguousarray(edges2, np.float64))
+        n2 = 0 if k["edges2"] is None else len(k["edges2"]) - 1
+        g = _Grid(len(k["edges"]) - 1, k["coef"].ctypes.data, k["edges"].ctypes.data, n2,
+                  _ptr(k["coef2"]), _ptr(k["edges2"]))
+        _check(load_library().we_set_bins(self.handle, C.byref(_Bins(WE_BINS_GRID, C.addressof(g)))))
+
+    def set_learned_bins(self):
+        _check(load_library().we_set_bins(self.handle, C.byref(_Bins(WE_BINS_LEARNED, None))))
 
     # ------------------------------------------------------------ stepping
     def set_ensemble(self, run: int, x, w):
@@ -459,6 +534,13 @@ def mlp_loss_grad_noalloc(n_in: int, params, feat, x, y, loss, grad, stream=None
     _check(load_library().we_mlp_loss_grad_noalloc(
         int(n_in), vp(params.data_ptr()), vp(feat.data_ptr()), batch, vp(x.data_ptr()),
         vp(y.data_ptr()), vp(loss.data_ptr()), vp(grad.data_ptr()), vp(st.cuda_stream)))
+
+
+def checkpoint_info(path: str) -> _CheckpointInfo:
+    """Sizes recorded in a checkpoint file (reads its header only)."""
+    info = _CheckpointInfo()
+    _check(load_library().we_checkpoint_inspect(os.fspath(path).encode(), C.byref(info)))
+    return info
 
 
 def adam_step(params, m, v, grad, lr: float, t: int):
