@@ -5,16 +5,22 @@ One step = one full WE iteration over every run of the workload: propagate
 every walker through tau (Gillespie direct method), recycle walkers that
 reached the target, bin, split/merge per bin, accumulate the histogram.
 
-Default workload: the Schloegl model (Sec. III.B) in steady state with
-recycling X >= 563 -> 82, 60 bins of width 40/3 on [0, 800], 8 walkers per
-bin, tau = 0.05 -- 2048 independent replicas in one launch.  Inputs are
-synthetic (the model is fully specified by its rate constants); the ensemble
-is resident in HBM for the whole timed region.
+Headline workload: the seeded stand-in for the 354-species / 3680-reaction
+model of Sec. III.D -- 50 bins of width 20 on its binned species, 81 walkers
+per bin (4050 slots), tau = 0.1, with the 5-species joint histogram -- on the
+wave-per-walker kernels.  It starts from x0 and is burnt in (untimed) until
+live walkers and events per step have settled; the `burn_in` key says how
+many steps that took.  Then K steps are run with HIP events around every
+kernel (per-kernel times, the roofline) and K more without them, timed as a
+whole: `value` is SSA events/s over that second window.  Inputs are
+synthetic; the ensemble is resident in HBM for the whole timed region.
 
-Prints one JSON line.  `value` is SSA events/s over the K timed steps.
-`roofline` covers the propagation kernel (the dominant one), timed with HIP
-events on the sim's stream; `cpu_baseline` is the sequential CPU oracle on a
-bounded sample of the same workload.
+Extra keys: `schlogl_lane`, the same measurement for 2048 Schloegl replicas
+(Sec. III.B, recycling X >= 563 -> 82) on the lane-per-walker kernel;
+`toggle_mfpt`, GPU-seconds until 16 replicas' MFPT estimates of the toggle
+stay within 5% of the brute-force reference, plain species-difference bins
+against learned-committor bins.  `cpu_baseline` is the CPU oracle on every
+host core (at most 16) on a bounded sample of the headline workload.
 """
 import argparse
 import hashlib
@@ -35,6 +41,8 @@ METRIC = "SSA events/s; GPU-seconds to MFPT rel-err 5%, learned vs plain bins"
 # (FP64 FMA at this rate gives the published 78.6 TFLOP/s).
 PEAK_LANE_OPS = 256 * 64 * 2.4e9
 PEAK_HBM = 8.0e12
+# LDS: 128 bytes per clock per CU
+PEAK_LDS = 256 * 128 * 2.4e9
 
 
 def alg_ops_per_event(net) -> float:
@@ -121,18 +129,6 @@ def traffic_from_profiles(kernel_tag: str, digest: str):
     if rec.get("source_digest") != digest:
         return None
     return rec.get("bytes_per_launch")
-
-
-def cpu_baseline(cfg, n_runs: int, n_iters: int):
-    from oracle import oracle as orc
-    ev = 0
-    t0 = time.perf_counter()
-    for r in range(n_runs):
-        o = orc.OracleWE(cfg, int(cfg.seeds[r]))
-        o.step(n_iters)
-        ev += sum(o.events)
-    dt = time.perf_counter() - t0
-    return ev / dt, dt, ev
 
 
 def _rel_err_curve(flux, tau, burn, ref):
@@ -258,7 +254,7 @@ def experiment_toggle_mfpt(args):
         em, ri, ts = (int(v) for v in spec.split(":"))
         variants.append(run(True, em, ri, ts))
     learned = variants[0]
-    out = {"metric": "GPU-seconds to MFPT rel-err 5%, learned vs plain bins",
+    return {"metric": "GPU-seconds to MFPT rel-err 5%, learned vs plain bins",
            "workload": "toggle (seed 101), 16 replicas x 64 bins x 16 walkers, tau 0.7",
            "plain_coordinate": args.plain_coord,
            "reference": {"mfpt": ref_mfpt, "sem_rel": ref_sem / ref_flux, "kind":
@@ -266,7 +262,6 @@ def experiment_toggle_mfpt(args):
                          "iterations": ref_iters, "gpu_s": t_ref, "events": ev_ref},
            "burn_in_iterations": burn, "plain": plain, "learned": learned,
            "learned_variants": variants[1:]}
-    print(json.dumps(out), flush=True)
 
 
 def schlogl_mfpt_exact(a: int = 82, b: int = 563, top: int = 1500) -> float:
@@ -528,15 +523,133 @@ def experiment_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def _burn_in(sim, warmup: int, chunk: int = 25, min_iters: int = 100, cap: int = 1000) -> int:
+    """Untimed steps until the workload is in its steady window: at least
+    max(warmup, min_iters) steps, then until two successive chunks of `chunk`
+    steps agree on live walkers per step within 2% and on events per step
+    within 5% (or `cap` steps).  Returns the steps taken."""
+    done, prev = 0, None
+    while True:
+        ev0, seg0, _ = sim.counters()
+        sim.step(chunk)
+        sim.synchronize()
+        ev1, seg1, _ = sim.counters()
+        done += chunk
+        cur = ((seg1 - seg0) / chunk, (ev1 - ev0) / chunk)
+        if prev is not None and done >= max(warmup, min_iters):
+            if abs(cur[0] - prev[0]) <= 0.02 * prev[0] and abs(cur[1] - prev[1]) <= 0.05 * max(prev[1], 1.0):
+                return done
+        if done >= cap:
+            return done
+        prev = cur
+
+
+def _measure(sim, K: int, W: int):
+    """Steady-window measurement of one sim: burn in, then K steps with HIP
+    events around every kernel (per-kernel times), then K more steps with no
+    events recorded, timed as a whole (the headline rate)."""
+    import torch
+    burn = _burn_in(sim, W)
+    ev0, seg0, _ = sim.counters()
+    sim.profile(True)
+    sim.step(K)
+    sim.synchronize()
+    ms_ssa, ms_res, ms_obs, _ = sim.profile_read()
+    sim.profile(False)
+    ev1, seg1, _ = sim.counters()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(K)
+    sim.synchronize()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ev2, seg2, _ = sim.counters()
+    return {"burn_in": burn, "events_profiled": ev1 - ev0, "segments_profiled": seg1 - seg0,
+            "ms_ssa": ms_ssa / K, "ms_res": ms_res / K, "ms_obs": ms_obs / K,
+            "events": ev2 - ev1, "segments": seg2 - seg1, "elapsed": t1 - t0}
+
+
+def lds_bytes_per_event_fact(net) -> float:
+    """LDS bytes one event of the factored-table wave kernel moves, as built:
+      the chosen chunk: 64 x (16 B descriptor + 8 B header + 2 x 4 B counts);
+      the changed species: old count and incidence word (8 B), the store (4 B);
+      each dependent (mean list length d, repeats included): 2 B id, 16 B
+        descriptor, 2 x 4 B counts before and 2 x 4 B after the firing;
+      the mailbox: one 8 B post per dependent segment (at most d), then the
+        64 chunk lanes read and clear 4 slots each (2 x 2 KB)."""
+    users = [0] * net.S
+    for j in range(net.R):
+        for p in range(net.reac_ptr[j], net.reac_ptr[j + 1]):
+            users[int(net.reac_species[p])] += 1
+    dl = [sum(users[int(net.chg_species[p])] for p in range(net.chg_ptr[j], net.chg_ptr[j + 1]))
+          for j in range(net.R)]
+    d = float(np.mean(dl))
+    nchg = float(np.diff(net.chg_ptr).mean())
+    return 64 * (16 + 8 + 8) + nchg * 12 + d * (2 + 16 + 8 + 8) + d * 8 + 2 * 2048
+
+
+def _cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _cpu_worker(job):
+    """A bounded sample of the workload on the oracle, timed inside the
+    worker: for the large network, `n` direct-method intervals of length tau
+    from its initial state; for Schloegl, one WE run of `n` iterations."""
+    kind, seed, tau, n = job
+    from oracle import oracle as orc
+    from paper_1303_5986_amd import workloads as wl
+    t0 = time.perf_counter()
+    ev = 0
+    if kind == "large":
+        cfg = wl.large_network_config()
+        onet = orc.OracleNet(cfg.net)
+        for k in range(n):
+            _, e = orc.ssa_interval(onet, cfg.x0, tau, seed, k, 0)
+            ev += e
+    else:
+        cfg = wl.schlogl_config(n_runs=1, seed0=seed, n_iters=n)
+        o = orc.OracleWE(cfg, seed)
+        o.step(n)
+        ev = sum(o.events)
+    return ev, time.perf_counter() - t0
+
+
+def cpu_baseline_all_cores(kind: str, tau: float, n: int):
+    """The oracle on every host core the process may use (at most 16, the
+    box's share per GPU), one worker per core with its own seed; the value is
+    all workers' events over the wall time."""
+    import multiprocessing as mp
+    cores = min(16, len(os.sched_getaffinity(0)))
+    jobs = [(kind, 1000 + i, tau, n) for i in range(cores)]
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(cores) as pool:
+        res = pool.map(_cpu_worker, jobs)
+    wall = time.perf_counter() - t0
+    ev = sum(e for e, _ in res)
+    per_core = float(np.mean([e / t for e, t in res]))
+    what = (f"{n} direct-method interval(s) of tau={tau:g} from the workload's initial state"
+            if kind == "large" else f"one WE run of {n} iterations from the workload's initial ensemble")
+    return {"value": ev / wall, "unit": "events/s", "cores": cores, "kind": "oracle",
+            "cpu_model": _cpu_model(), "single_core_value": per_core,
+            "sample": f"{cores} workers x {what}, each with its own seed ({ev} events, {wall:.1f} s wall)"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=300)
+    ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=150)
-    ap.add_argument("--runs", type=int, default=2048)
+    ap.add_argument("--runs", type=int, default=2048, help="Schloegl replicas in the lane-kernel line")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-runs", type=int, default=6)
-    ap.add_argument("--cpu-iters", type=int, default=800)
+    ap.add_argument("--no-extras", action="store_true",
+                    help="headline only: skip the Schloegl lane-kernel line and the toggle experiment")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB five times "
                          "(reference kernel for scaling the HBM byte counters)")
@@ -547,10 +660,11 @@ def main():
                     help="replicas in the reweighting experiment")
     ap.add_argument("--large-runs", type=int, default=1,
                     help="independent replicas of the large network (the configuration is 1; "
-                         "more fill the chip and show the wave kernel's throughput ceiling)")
-    ap.add_argument("--workload", default="schlogl", choices=["schlogl", "large"],
-                    help="schlogl: 2048 Schloegl replicas, lane kernel (default); large: the "
-                         "354-species / 3680-reaction network, 4096 walkers, wave kernel")
+                         "more fill the chip and show the wave kernels' throughput ceiling)")
+    ap.add_argument("--workload", default="large", choices=["schlogl", "large"],
+                    help="headline workload. large (default): the 354-species / 3680-reaction "
+                         "network, 50 bins x 81 walkers, tau 0.1, with its 5-species joint "
+                         "histogram, wave kernel; schlogl: 2048 Schloegl replicas, lane kernel")
     ap.add_argument("--batch-runs", type=int, default=64)
     ap.add_argument("--autotune-iters", type=int, default=3)
     ap.add_argument("--tune-cache", action="store_true")
@@ -563,7 +677,7 @@ def main():
                          "the first is the reported one")
     args = ap.parse_args()
     if args.experiment == "toggle_mfpt":
-        experiment_toggle_mfpt(args)
+        print(json.dumps(experiment_toggle_mfpt(args)), flush=True)
         return
     if args.experiment == "batch":
         experiment_batch(args)
@@ -593,102 +707,107 @@ def main():
               "so N GPUs would each run this same line on their own replicas.", file=sys.stderr)
         sys.exit(2)
 
-    import torch
     from paper_1303_5986_amd import we, workloads as wl
 
     K, W = args.steps, args.warmup
-    if args.workload == "large":
-        cfg = wl.large_network_config(n_iters=W + K)
+    max_iters = 1000 + 2 * K + 50
+
+    def line_large():
+        cfg = wl.large_network_config(n_iters=max_iters)
         if args.large_runs > 1:
             cfg = cfg.with_seeds(np.arange(2024, 2024 + args.large_runs, dtype=np.uint64))
-        kernel, kname = we.WE_KERNEL_WAVE, "ssa_wave_lds_kernel"
+        sim = we.sim_from_config(cfg, kernel=we.WE_KERNEL_WAVE, max_iters=max_iters, joint=True)
+        m = _measure(sim, K, W)
         ops_ev = alg_ops_per_event_wave(cfg.net)
-        cfg_desc = {"workload": "large_network_354x3680", "runs": args.large_runs, "species": cfg.net.S,
-                    "reactions": cfg.net.R, "bins": cfg.n_bins, "walkers_per_bin": cfg.m_targ,
-                    "tau": cfg.tau, "kernel": "ssa_wave"}
-        digest_src = ["paper_1303_5986_amd/csrc/ssa_wave.hip", "paper_1303_5986_amd/csrc/ssa_wave_body.h",
-                      "paper_1303_5986_amd/csrc/we_common.h"]
-        tag = "ssa_wave_large"
-    else:
-        cfg = wl.schlogl_config(n_runs=args.runs, seed0=1, n_iters=W + K)
-        kernel, kname = we.WE_KERNEL_LANE, "ssa_lane_pool_kernel<1,4>"
+        lds_ev = lds_bytes_per_event_fact(cfg.net)
+        kname = sim.propagation_kernel()
+        ev_launch = m["events_profiled"] / K
+        ssa_s = m["ms_ssa"] / 1e3
+        achieved = ops_ev * ev_launch / ssa_s
+        traffic = traffic_from_profiles(
+            "ssa_wave_large", source_digest(["paper_1303_5986_amd/csrc/ssa_wave.hip",
+                                             "paper_1303_5986_amd/csrc/ssa_wave_body.h",
+                                             "paper_1303_5986_amd/csrc/ssa_wave_fact.h",
+                                             "paper_1303_5986_amd/csrc/we_common.h"]))
+        if args.large_runs != 1:
+            traffic = None   # the committed counters were taken on the one-run configuration
+        roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12, "unit": "Tops/s",
+                "frac": achieved / PEAK_LANE_OPS, "traffic": traffic, "ops_per_event": ops_ev,
+                "kernel": kname, "avg_launch_ms": m["ms_ssa"], "events_per_launch": ev_launch}
+        if kname == "ssa_wave_fact_kernel":
+            lds = lds_ev * ev_launch / ssa_s
+            roof["lds"] = {"achieved": lds / 1e12, "peak": PEAK_LDS / 1e12, "unit": "TB/s",
+                           "frac": lds / PEAK_LDS, "bytes_per_event": lds_ev}
+        desc = {"workload": "large_network_354x3680", "runs": args.large_runs, "species": cfg.net.S,
+                "reactions": cfg.net.R, "bins": cfg.n_bins, "walkers_per_bin": cfg.m_targ, "tau": cfg.tau,
+                "joint_histogram_species": len(cfg.joint_species), "kernel": "ssa_wave",
+                "walkers_per_step": m["segments"] / K}
+        return m, roof, desc
+
+    def line_schlogl(runs):
+        cfg = wl.schlogl_config(n_runs=runs, seed0=1, n_iters=max_iters)
+        sim = we.sim_from_config(cfg, kernel=we.WE_KERNEL_LANE, max_iters=max_iters)
+        m = _measure(sim, K, W)
         ops_ev = alg_ops_per_event(cfg.net)
-        cfg_desc = {"workload": "schlogl_steady_state_recycling", "runs": args.runs,
-                    "bins": cfg.n_bins, "walkers_per_bin": cfg.m_targ, "tau": cfg.tau,
-                    "target": "X>=563 -> X=82", "kernel": "ssa_lane"}
-        digest_src = ["paper_1303_5986_amd/csrc/ssa_lane.hip", "paper_1303_5986_amd/csrc/ssa_lane_body.h",
-                      "paper_1303_5986_amd/csrc/we_common.h"]
-        tag = "ssa_lane_schlogl"
-    sim = we.sim_from_config(cfg, kernel=kernel, max_iters=W + K)
-    sim.step(W)
-    sim.synchronize()
-    ev0, seg0, _ = sim.counters()
-    sim.profile(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    sim.step(K)
-    sim.synchronize()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms_ssa, ms_res, ms_obs, n_prof = sim.profile_read()
-    ev1, seg1, _ = sim.counters()
-    elapsed = t1 - t0
-    events = ev1 - ev0
-    segments = seg1 - seg0
-    value = events / elapsed
+        ev_launch = m["events_profiled"] / K
+        ssa_s = m["ms_ssa"] / 1e3
+        achieved = ops_ev * ev_launch / ssa_s
+        traffic = traffic_from_profiles(
+            "ssa_lane_schlogl", source_digest(["paper_1303_5986_amd/csrc/ssa_lane.hip",
+                                               "paper_1303_5986_amd/csrc/ssa_lane_body.h",
+                                               "paper_1303_5986_amd/csrc/we_common.h"]))
+        roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12, "unit": "Tops/s",
+                "frac": achieved / PEAK_LANE_OPS, "traffic": traffic, "ops_per_event": ops_ev,
+                "kernel": sim.propagation_kernel(), "avg_launch_ms": m["ms_ssa"], "events_per_launch": ev_launch}
+        desc = {"workload": "schlogl_steady_state_recycling", "runs": runs, "bins": cfg.n_bins,
+                "walkers_per_bin": cfg.m_targ, "tau": cfg.tau, "target": "X>=563 -> X=82",
+                "kernel": "ssa_lane", "walkers_per_step": m["segments"] / K}
+        return m, roof, desc
 
-    ssa_avg_s = ms_ssa / 1e3 / K
-    ev_per_launch = events / K
-    achieved = ops_ev * ev_per_launch / ssa_avg_s
-    traffic = traffic_from_profiles(tag, source_digest(digest_src))
-    if args.workload == "large" and args.large_runs != 1:
-        traffic = None   # the committed counters were taken on the one-run configuration
-    cfg_desc["walkers_per_step"] = segments / K
-
+    if args.workload == "large":
+        m, roof, desc = line_large()
+    else:
+        m, roof, desc = line_schlogl(args.runs)
     out = {
         "metric": METRIC,
-        "value": value,
+        "value": m["events"] / m["elapsed"],
         "unit": "events/s",
         "n_gpus": 1,
         "steps": K,
         "warmup": W,
-        "ms_per_step": elapsed * 1e3 / K,
+        "burn_in": m["burn_in"],
+        "ms_per_step": m["elapsed"] * 1e3 / K,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": cfg_desc,
-        "we_iters_per_s": K / elapsed,
-        "events_per_segment": events / max(segments, 1),
-        "kernel_ms_per_step": {"ssa": ms_ssa / K, "resample": ms_res / K, "observe": ms_obs / K},
-        "roofline": {
-            "bound": "alu",
-            "achieved": achieved / 1e12,
-            "peak": PEAK_LANE_OPS / 1e12,
-            "unit": "Tops/s",
-            "frac": achieved / PEAK_LANE_OPS,
-            "traffic": traffic,
-            "ops_per_event": ops_ev,
-            "kernel": kname,
-            "avg_launch_ms": ms_ssa / K,
-            "events_per_launch": ev_per_launch,
-        },
+        "config": desc,
+        "we_iters_per_s": K / m["elapsed"],
+        "events_per_segment": m["events"] / max(m["segments"], 1),
+        "kernel_ms_per_step": {"ssa": m["ms_ssa"], "resample": m["ms_res"], "observe": m["ms_obs"]},
+        "roofline": roof,
     }
     if not args.no_cpu:
         if args.workload == "large":
-            import dataclasses
-            cpu_cfg = dataclasses.replace(wl.large_network_config(n_iters=args.cpu_iters),
-                                          m_targ=2)
-            rate, secs, cev = cpu_baseline(cpu_cfg, 1, 4)
-            args.cpu_runs, args.cpu_iters = 1, 4
+            out["cpu_baseline"] = cpu_baseline_all_cores("large", 0.1, 6)
         else:
-            cpu_cfg = wl.schlogl_config(n_runs=args.cpu_runs, seed0=1, n_iters=args.cpu_iters)
-            rate, secs, cev = cpu_baseline(cpu_cfg, args.cpu_runs, args.cpu_iters)
-        out["cpu_baseline"] = {"value": rate, "unit": "events/s", "cores": 1, "kind": "oracle",
-                               "sample": f"{args.cpu_runs} runs x {args.cpu_iters} WE iterations "
-                                         f"of the same workload from its initial ensemble "
-                                         f"({cev} events, {secs:.1f} s, single thread)"}
+            out["cpu_baseline"] = cpu_baseline_all_cores("schlogl", 0.05, 2000)
+    if not args.no_extras:
+        if args.workload == "large":
+            ms, rs, ds = line_schlogl(args.runs)
+            out["schlogl_lane"] = {"config": ds, "events_per_s": ms["events"] / ms["elapsed"],
+                                   "ms_per_step": ms["elapsed"] * 1e3 / K, "burn_in": ms["burn_in"],
+                                   "roofline": rs}
+        tg = experiment_toggle_mfpt(args)
+        out["toggle_mfpt"] = {
+            "metric": "GPU-seconds to MFPT rel-err 5% (16 replicas, RMS over replicas)",
+            "workload": tg["workload"], "reference_mfpt": tg["reference"]["mfpt"],
+            "plain_delta_bins_gpu_s": tg["plain"]["gpu_s_to_5pct"],
+            "learned_bins_gpu_s": tg["learned"]["gpu_s_to_5pct"],
+            "plain_final_rel_err": tg["plain"]["final_rel_err"],
+            "learned_final_rel_err": tg["learned"]["final_rel_err"],
+            "learned_includes": "plain-bin record phase and training"}
     print(json.dumps(out), flush=True)
 
 

@@ -182,6 +182,11 @@ WE_API we_status we_init(const we_network *net, const we_grid *grid, const we_pa
                          void *hip_stream, void *workspace, size_t workspace_bytes,
                          we_sim **out);
 
+/* Name of the propagation kernel the sim's steps launch (the variant is
+ * chosen from the network and the launch shape); "" for NULL.  The string is
+ * static. */
+WE_API const char *we_propagation_kernel(const we_sim *s);
+
 /* Switch a sim's bins (Sec. II.B bins the state space; Sec. IV calls the
  * choice of bins open).  kind WE_BINS_GRID: grid NULL returns to the sim's
  * grid bins (after learned ones); a non-NULL grid replaces the coordinates

@@ -223,6 +223,19 @@ hipError_t launch_ssa_lane(const SimArgs &a, int32_t *xs, hipStream_t st) {
     return hipErrorInvalidValue;
 }
 
+// The name of the kernel launch_ssa_lane runs for these arguments.
+const char *ssa_lane_name(const SimArgs &a) {
+    if (a.engine == 1)
+        return a.S <= 1 && a.R <= 4 ? "ssa_lane_leap_kernel<1,4>"
+               : a.S <= 2 && a.R <= 8 ? "ssa_lane_leap_kernel<2,8>" : "ssa_lane_leap_kernel<8,16>";
+    if (a.hill) return a.S <= 2 && a.R <= 8 ? "ssa_lane_hill_kernel<2,8>" : "ssa_lane_hill_kernel<8,16>";
+    if (a.S <= 1 && a.R <= 4) return "ssa_lane_pool_kernel<1,4>";
+    if (a.S <= 2 && a.R <= 8) return "ssa_lane_pool_kernel<2,8>";
+    if (a.S <= 8 && a.R <= 16) return "ssa_lane_pool_kernel<8,16>";
+    if (a.S <= 16 && a.R <= 32) return "ssa_lane_kernel<16,32>";
+    return "ssa_lane_kernel<32,64>";
+}
+
 // Deltas travel as int8, so every change must lie in [-128, 127].
 bool lane_kernel_fits(int32_t S, int32_t R, int32_t max_delta) {
     return S <= 32 && R <= 64 && max_delta <= 127;

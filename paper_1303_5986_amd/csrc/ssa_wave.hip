@@ -25,15 +25,22 @@
 //    interval.
 //
 // Memory: walker counts (int32) and chunk sums live in LDS (about 2 KB per
-// walker at 354 species); the block also keeps the reaction descriptors (and,
-// when they fit, the headers) in LDS; dependency lists and stoichiometry are
-// read from global memory, where they stay resident in the L2 caches.  No
-// per-reaction propensity array is stored.
+// walker at 354 species).  Two kernels share that scheme:
+//  * ssa_wave_fact_kernel keeps every table in LDS: descriptors, an 8-byte
+//    change header per reaction and the factored dependency graph (per
+//    species, the reactions taking it as a reactant); nothing in its event
+//    loop reads global memory;
+//  * ssa_wave_lds_kernel keeps the descriptors (and, when they fit, 16-byte
+//    reaction headers) in LDS and reads each fired reaction's sorted
+//    dependency list and changes from global memory, where they stay in L2;
+//    its smaller tables leave room for two blocks per CU.
+// No per-reaction propensity array is stored.
 //
 // Summation order differs from the sequential order of the oracle (chunked
 // scans), so a0 and the running sums can differ in the last bits; an event
 // changes only if u2*a0 or t+dt falls within a few ulps of a boundary.
 #include "ssa_wave_body.h"
+#include "ssa_wave_fact.h"
 
 #include <algorithm>
 
@@ -100,6 +107,58 @@ __global__ __launch_bounds__(64 * WAVE_LDS_MAX_WAVES, 4) void ssa_wave_lds_kerne
     }
 }
 
+// Factored-table variant: the block copies the descriptors (16 bytes per
+// reaction), the change headers (8 bytes), the per-species incidence words
+// (4 bytes) and the incidence lists (2 bytes per entry) into LDS -- 98 KB at
+// 354 species / 3680 reactions -- and each wave keeps its walker's counts and
+// a 2 KB mailbox of chunk-sum changes beside them (16 walkers per CU at that
+// size); waves take walkers from the work queue until it is empty.  Nothing
+// in the event loop reads global memory.
+#define WAVE_FACT_MAX_WAVES 16
+
+__global__ __launch_bounds__(64 * WAVE_FACT_MAX_WAVES) void ssa_wave_fact_kernel(SimArgs a, int32_t *__restrict__ xs,
+                                                                                int32_t s_pad) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int32_t R = a.R, S = a.S;
+    uint4 *ld = reinterpret_cast<uint4 *>(smem);
+    uint2 *lh = reinterpret_cast<uint2 *>(smem + fact_off_hdr(R));
+    uint32_t *ltab = reinterpret_cast<uint32_t *>(smem + fact_off_tab(R));
+    uint16_t *linc = reinterpret_cast<uint16_t *>(smem + fact_off_inc(R, S));
+    unsigned char *wbase = smem + fact_tables_bytes(R, S, a.n_inc);
+    const int nw = blockDim.x >> 6, wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    double *lmail = reinterpret_cast<double *>(wbase) + wv * 256;
+    int32_t *lx = reinterpret_cast<int32_t *>(wbase + (size_t)nw * 256 * sizeof(double)) + wv * s_pad;
+    const uint4 *gd = reinterpret_cast<const uint4 *>(a.desc);
+    for (int32_t i = threadIdx.x; i < R; i += blockDim.x) {
+        ld[i] = gd[i];
+        lh[i] = a.fhdr[i];
+    }
+    for (int32_t i = threadIdx.x; i < S; i += blockDim.x) ltab[i] = a.inc_tab[i];
+    for (int32_t i = threadIdx.x; i < a.n_inc; i += blockDim.x) linc[i] = a.inc[i];
+    __syncthreads();
+    FactTables tab;
+    tab.d = ld;
+    tab.h = lh;
+    tab.tab = ltab;
+    tab.inc = linc;
+    const uint32_t iter = *a.iter_dev;
+    const uint32_t M = (uint32_t)a.m_targ, cap = (uint32_t)a.cap;
+    const uint32_t total = a.queue[1] * M;
+    // whole-wave queue atomic: see ssa_wave_lds_kernel
+    for (;;) {
+        const uint32_t got = atomicAdd(&a.queue[0], lane == 0 ? 1u : 0u);
+        const uint32_t q = (uint32_t)__shfl((int)got, 0, 64);
+        if (q >= total) break;
+        const uint32_t sg = q / M, o = q - sg * M;
+        const int2 seg = a.seg[sg];
+        if ((int32_t)o < seg.y) {
+            const uint32_t g = (uint32_t)seg.x + o;
+            const uint32_t run = g / cap;
+            wave_walker_fact(a, tab, xs, (int32_t)run, (int32_t)(g - run * cap), iter, lmail, lx);
+        }
+    }
+}
+
 bool wave_kernel_fits(int32_t S, int32_t R) { return R <= 4096 && S <= 8192; }
 
 namespace {
@@ -150,16 +209,91 @@ hipError_t launch_lds(const SimArgs &a, int32_t *xs, int32_t s_pad, size_t table
 // two rounds of one such block per CU (WE keeps roughly half its slots live);
 // beyond that the second block per CU is worth more than the header loads it
 // saves.
+// The factored-table kernel when the network has its tables and they fit
+// beside one wave's slice.
+bool wave_fact_fits(const SimArgs &a, size_t *tables, size_t *per_wave) {
+    if (!a.fhdr || !a.inc || !a.inc_tab) return false;
+    *tables = fact_tables_bytes(a.R, a.S, a.n_inc);
+    *per_wave = 256 * sizeof(double) + sizeof(int32_t) * (size_t)((a.S + 3) & ~3);
+    return *tables + *per_wave <= WAVE_LDS_BYTES;
+}
+
+namespace {
+int fact_blocks_per_cu(int waves, size_t shmem) {
+    static size_t last_shmem = 0;
+    static int last_waves = 0, last = 1;
+    if (shmem != last_shmem || waves != last_waves) {
+        int nb = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, ssa_wave_fact_kernel, 64 * waves, shmem) != hipSuccess ||
+            nb < 1)
+            nb = 1;
+        last = nb;
+        last_shmem = shmem;
+        last_waves = waves;
+    }
+    return last;
+}
+}  // namespace
+
+// Which variant: the factored-table kernel when every live walker gets a wave
+// at once (WE keeps roughly half its slots live), i.e. when each walker's
+// event chain is the bound; otherwise the descriptor-table kernel, which
+// issues fewer instructions per event (236 against 306 vector instructions
+// at 354/3680) and holds up to 16 walkers per CU in two blocks.  Measured
+// on the 354/3680 network: one run (2465 live walkers) 0.417-0.430 ms per
+// launch against 0.458 ms; eight runs (19,600 live walkers) 1.59 ms against
+// 1.41 ms.
+namespace {
+// Waves per block of the factored-table kernel when it is the one to run
+// (0: the descriptor-table kernel), with its LDS bytes.
+int fact_choice(const SimArgs &a, size_t *shmem_out) {
+    size_t tables = 0, per_wave = 0;
+    if (!wave_fact_fits(a, &tables, &per_wave)) return 0;
+    const int nw = (int)std::min<size_t>(WAVE_FACT_MAX_WAVES, (WAVE_LDS_BYTES - tables) / per_wave);
+    const size_t shmem = tables + nw * per_wave;
+    const int64_t live = ((int64_t)a.n_runs * a.cap + 1) / 2;
+    if (nw < 1 || live > (int64_t)fact_blocks_per_cu(nw, shmem) * nw * device_cus()) return 0;
+    *shmem_out = shmem;
+    return nw;
+}
+
+bool lds_headers(const SimArgs &a, int32_t s_pad, size_t per_wave) {
+    const int64_t walkers = (int64_t)a.n_runs * a.cap;
+    const size_t desc_bytes = 16 * (size_t)a.R;
+    if (2 * desc_bytes + 2 * per_wave > WAVE_LDS_BYTES) return false;
+    const int nw = (int)std::min<size_t>(WAVE_LDS_MAX_WAVES, (WAVE_LDS_BYTES - 2 * desc_bytes) / per_wave);
+    return walkers <= 2 * (int64_t)nw * device_cus();
+}
+}  // namespace
+
+const char *ssa_wave_name(const SimArgs &a) {
+    size_t shmem = 0;
+    if (fact_choice(a, &shmem) > 0) return "ssa_wave_fact_kernel";
+    const int32_t s_pad = (a.S + 3) & ~3;
+    const size_t per_wave = 64 * sizeof(double) + sizeof(int32_t) * (size_t)s_pad;
+    return lds_headers(a, s_pad, per_wave) ? "ssa_wave_lds_kernel<true>" : "ssa_wave_lds_kernel<false>";
+}
+
 hipError_t launch_ssa_wave(const SimArgs &a, int32_t *xs, hipStream_t st) {
     if (!wave_kernel_fits(a.S, a.R)) return hipErrorInvalidValue;
+    {
+        size_t shmem = 0;
+        const int nw = fact_choice(a, &shmem);
+        if (nw > 0) {
+            const int64_t walkers = (int64_t)a.n_runs * a.cap;
+            const int64_t resident = (int64_t)fact_blocks_per_cu(nw, shmem) * device_cus();
+            const unsigned blocks =
+                (unsigned)std::max<int64_t>(1, std::min<int64_t>(resident, (walkers + nw - 1) / nw));
+            const int32_t s_pad = (a.S + 3) & ~3;
+            hipLaunchKernelGGL(ssa_wave_fact_kernel, dim3(blocks), dim3(64 * nw), shmem, st, a, xs, s_pad);
+            return hipGetLastError();
+        }
+    }
     const int32_t s_pad = (a.S + 3) & ~3;
     const size_t per_wave = 64 * sizeof(double) + sizeof(int32_t) * (size_t)s_pad;
     const int64_t walkers = (int64_t)a.n_runs * a.cap;
     const size_t desc_bytes = 16 * (size_t)a.R;
-    if (2 * desc_bytes + 2 * per_wave <= WAVE_LDS_BYTES) {
-        const int nw = (int)std::min<size_t>(WAVE_LDS_MAX_WAVES, (WAVE_LDS_BYTES - 2 * desc_bytes) / per_wave);
-        if (walkers <= 2 * (int64_t)nw * device_cus())
-            return launch_lds<true>(a, xs, s_pad, 2 * desc_bytes, per_wave, walkers, st);
-    }
+    if (lds_headers(a, s_pad, per_wave))
+        return launch_lds<true>(a, xs, s_pad, 2 * desc_bytes, per_wave, walkers, st);
     return launch_lds<false>(a, xs, s_pad, desc_bytes, per_wave, walkers, st);
 }

@@ -61,6 +61,36 @@ __host__ __device__ inline int32_t pack_change(int32_t s, int32_t d) {
 __host__ __device__ inline int32_t change_species(int32_t p) { return (int32_t)((uint32_t)p >> 16); }
 __host__ __device__ inline int32_t change_delta(int32_t p) { return (int32_t)(int16_t)(p & 0xffff); }
 
+// Factored dependency graph of the LDS-resident wave kernel.  Per reaction
+// an 8-byte change header: up to 4 changed species, one 16-bit code each
+// (bits 0-8 species < 512, bits 9-12 delta + 8, delta in [-8, 7]), code k at
+// bits 16k.  Per species one 32-bit word: where the ids of the reactions
+// taking it as a reactant start in the incidence list (bits 0-15) and how
+// many there are (bits 16-31); each species' ids ascend.  The reactions whose
+// propensity a firing changes are the union of its changed species' lists.
+#define FACT_MAX_SPECIES 512
+#define FACT_MAX_INC 65535
+#define FACT_MAX_CHANGES 4
+__host__ __device__ inline uint32_t fact_code(int32_t s, int32_t delta) {
+    return (uint32_t)s | ((uint32_t)(delta + 8) << 9);
+}
+__host__ __device__ inline int32_t fact_species(uint32_t code) { return (int32_t)(code & 0x1FFu); }
+__host__ __device__ inline int32_t fact_delta(uint32_t code) { return (int32_t)((code >> 9) & 0xFu) - 8; }
+__host__ __device__ inline uint32_t fact_inc_word(int32_t begin, int32_t count) {
+    return (uint32_t)begin | ((uint32_t)count << 16);
+}
+// LDS byte offsets of the tables: descriptors, headers, per-species words,
+// incidence ids, then the waves' slices; 16-byte aligned pieces.
+__host__ __device__ inline size_t fact_align16(size_t v) { return (v + 15) & ~(size_t)15; }
+__host__ __device__ inline size_t fact_off_hdr(int32_t R) { return 16 * (size_t)R; }
+__host__ __device__ inline size_t fact_off_tab(int32_t R) { return fact_align16(24 * (size_t)R); }
+__host__ __device__ inline size_t fact_off_inc(int32_t R, int32_t S) {
+    return fact_align16(fact_off_tab(R) + 4 * (size_t)S);
+}
+__host__ __device__ inline size_t fact_tables_bytes(int32_t R, int32_t S, int32_t n_inc) {
+    return fact_align16(fact_off_inc(R, S) + 2 * (size_t)n_inc);
+}
+
 // Everything a WE kernel needs, passed by value.
 struct SimArgs {
     // network
@@ -74,6 +104,10 @@ struct SimArgs {
     const RxnInfo *__restrict__ rinfo;   // [R]
     const DepEntry *__restrict__ deps;   // dependency entries with descriptors
     const HillDesc *__restrict__ hill;   // [R padded] Hill-type rates (null: none)
+    const uint2 *__restrict__ fhdr;      // [R] factored change headers (null: network too large)
+    const uint32_t *__restrict__ inc_tab;// [S] incidence start | count << 16
+    const uint16_t *__restrict__ inc;    // [n_inc] species -> reactions taking it as a reactant
+    int32_t n_inc;
     int32_t S, R;
     int32_t engine;                      // 0: exact SSA, 1: tau-leaping (lane kernel)
     double leap_eps;                     // tau-leaping error control

@@ -33,6 +33,12 @@ struct we_network {
     RxnInfo *d_rinfo = nullptr;
     DepEntry *d_deps = nullptr;
     int32_t *d_dpack = nullptr;     // [R][WE_DPACK_WORDS] int8 deltas (species < 32)
+    std::vector<uint2> fhdr;        // factored change headers (empty: do not fit)
+    std::vector<uint32_t> inc_tab;  // per species: incidence start | count << 16
+    std::vector<uint16_t> inc;      // incidence lists, species by species
+    uint2 *d_fhdr = nullptr;
+    uint32_t *d_inc_tab = nullptr;
+    uint16_t *d_inc = nullptr;
     std::vector<HillDesc> hill;     // empty: no Hill-type rates
     HillDesc *d_hill = nullptr;     // [R padded to 64]
 };
@@ -115,6 +121,8 @@ hipError_t launch_work_queue(const SimArgs &a, hipStream_t st);
 hipError_t launch_ssa_wave(const SimArgs &a, int32_t *xs, hipStream_t st);
 bool lane_kernel_fits(int32_t S, int32_t R, int32_t max_delta);
 bool wave_kernel_fits(int32_t S, int32_t R);
+const char *ssa_lane_name(const SimArgs &a);
+const char *ssa_wave_name(const SimArgs &a);
 // reweight.hip
 #define WE_RW_MAX_BINS 512
 bool rw_solve_in_lds(int32_t n_bins);

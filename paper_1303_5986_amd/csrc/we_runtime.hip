@@ -170,6 +170,34 @@ extern "C" we_status we_create_network(int32_t S, int32_t R, const int32_t *reac
         for (int32_t r : tmp) net->dep.push_back((uint16_t)r);
         net->dep_ptr.push_back((int32_t)net->dep.size());
     }
+    // factored form (change headers + incidence lists) for the LDS-resident
+    // wave kernel, when the network fits its packed fields
+    {
+        bool fits = S <= FACT_MAX_SPECIES;
+        size_t n_inc = 0;
+        for (int32_t sp = 0; sp < S; ++sp) n_inc += users[sp].size();
+        fits = fits && n_inc <= FACT_MAX_INC;
+        for (int32_t j = 0; j < R && fits; ++j) {
+            fits = chg_ptr[j + 1] - chg_ptr[j] <= FACT_MAX_CHANGES;
+            for (int32_t p = chg_ptr[j]; p < chg_ptr[j + 1] && fits; ++p)
+                fits = chg_delta[p] >= -8 && chg_delta[p] <= 7;
+        }
+        if (fits) {
+            net->inc_tab.assign(S, 0u);
+            for (int32_t sp = 0; sp < S; ++sp) {
+                net->inc_tab[sp] = fact_inc_word((int32_t)net->inc.size(), (int32_t)users[sp].size());
+                for (int32_t r : users[sp]) net->inc.push_back((uint16_t)r);   // ascending r
+            }
+            net->fhdr.assign(R, uint2{0u, 0u});
+            for (int32_t j = 0; j < R; ++j) {
+                uint64_t h = 0;
+                for (int32_t p = chg_ptr[j]; p < chg_ptr[j + 1]; ++p)
+                    h |= (uint64_t)fact_code(chg_species[p], chg_delta[p]) << (16 * (p - chg_ptr[j]));
+                net->fhdr[j] = uint2{(uint32_t)h, (uint32_t)(h >> 32)};
+            }
+            if (net->inc.empty()) net->inc.push_back(0);
+        }
+    }
     std::vector<RxnInfo> rinfo(R);
     std::vector<DepEntry> deps;
     for (int32_t j = 0; j < R; ++j) {
@@ -213,6 +241,11 @@ extern "C" we_status we_create_network(int32_t S, int32_t R, const int32_t *reac
     if (e == hipSuccess) e = up((void **)&net->d_rinfo, rinfo.data(), sizeof(RxnInfo) * R);
     if (e == hipSuccess) e = up((void **)&net->d_deps, deps.data(), sizeof(DepEntry) * deps.size());
     if (e == hipSuccess) e = up((void **)&net->d_dpack, dpack.data(), 4 * dpack.size());
+    if (e == hipSuccess && !net->fhdr.empty()) {
+        e = up((void **)&net->d_fhdr, net->fhdr.data(), sizeof(uint2) * net->fhdr.size());
+        if (e == hipSuccess) e = up((void **)&net->d_inc_tab, net->inc_tab.data(), 4 * net->inc_tab.size());
+        if (e == hipSuccess) e = up((void **)&net->d_inc, net->inc.data(), 2 * net->inc.size());
+    }
     if (e != hipSuccess) {
         we_destroy_network(net);
         return hip_fail(e, "network upload");
@@ -245,6 +278,9 @@ extern "C" we_status we_set_hill(we_network *net, int32_t reaction, int32_t spec
 
 extern "C" void we_destroy_network(we_network *net) {
     if (!net) return;
+    (void)hipFree(net->d_fhdr);
+    (void)hipFree(net->d_inc_tab);
+    (void)hipFree(net->d_inc);
     (void)hipFree(net->d_hill);
     (void)hipFree(net->d_desc);
     (void)hipFree(net->d_chg_ptr);
@@ -484,6 +520,10 @@ extern "C" we_status we_init(const we_network *net, const we_grid *g, const we_p
     a.dep_ptr = net->d_dep_ptr; a.dep = net->d_dep;
     a.rinfo = net->d_rinfo; a.deps = net->d_deps;
     a.hill = hill ? net->d_hill : nullptr;
+    a.fhdr = net->d_fhdr;
+    a.inc_tab = net->d_inc_tab;
+    a.inc = net->d_inc;
+    a.n_inc = (int32_t)net->inc.size();
     a.engine = p->engine;
     a.leap_eps = p->engine == 1 ? p->leap_eps : 0.0;
     a.S = S; a.R = net->R;
@@ -935,6 +975,11 @@ extern "C" we_status we_profile_read(we_sim *s, double *ms_propagate, double *ms
     if (ms_observe) *ms_observe = s->prof_ms[2];
     if (iterations) *iterations = s->prof_iters;
     return WE_OK;
+}
+
+extern "C" const char *we_propagation_kernel(const we_sim *s) {
+    if (!s) return "";
+    return s->kernel == WE_KERNEL_LANE ? ssa_lane_name(s->args) : ssa_wave_name(s->args);
 }
 
 extern "C" we_status we_set_bins(we_sim *s, const we_bins *b) {

@@ -34,7 +34,7 @@ EXPORTED = [
     "we_record_labels", "we_get_record", "we_mlp_loss_grad", "we_mlp_loss_grad_noalloc", "we_adam_step",
     "we_batch_create", "we_batch_step", "we_batch_graph_capture", "we_batch_graph_replay",
     "we_batch_sim", "we_batch_info", "we_batch_destroy",
-    "we_set_bins", "we_save", "we_checkpoint_inspect", "we_load",
+    "we_set_bins", "we_save", "we_checkpoint_inspect", "we_load", "we_propagation_kernel",
     "we_destroy", "we_last_error",
 ]
 
@@ -149,6 +149,8 @@ def load_library(path: str = LIB_PATH):
     L.we_batch_destroy.argtypes = [vp]
     L.we_batch_destroy.restype = None
     L.we_set_bins.argtypes = [vp, vp]
+    L.we_propagation_kernel.argtypes = [vp]
+    L.we_propagation_kernel.restype = C.c_char_p
     L.we_save.argtypes = [vp, C.c_char_p]
     L.we_checkpoint_inspect.argtypes = [C.c_char_p, vp]
     L.we_load.argtypes = [vp, C.c_char_p, vp, vp, C.c_size_t, P(vp)]
@@ -158,7 +160,7 @@ def load_library(path: str = LIB_PATH):
     for name in EXPORTED:
         fn = getattr(L, name)
         if name not in ("we_destroy", "we_destroy_network", "we_last_error", "we_batch_sim",
-                        "we_batch_destroy"):
+                        "we_batch_destroy", "we_propagation_kernel"):
             fn.restype = C.c_int
     _LIB = L
     return L
@@ -273,6 +275,10 @@ class Sim:
                          C.c_void_p(self.stream.cuda_stream), C.c_void_p(aligned),
                          C.c_size_t(int(nbytes.value)), C.byref(h)))
         self.handle = h
+
+    def propagation_kernel(self) -> str:
+        """Name of the propagation kernel this sim's steps launch."""
+        return load_library().we_propagation_kernel(self.handle).decode()
 
     # ------------------------------------------------------------ checkpoints, bins
     def save(self, path: str):

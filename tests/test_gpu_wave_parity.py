@@ -1,5 +1,10 @@
 """GPU parity of the wave-per-walker path against the CPU oracle.
 
+Three kernels implement the path: the factored-table kernel (every table in
+LDS) runs when all live walkers get a wave at once, the descriptor-table
+kernel otherwise, and the latter's header-table variant when a network does
+not fit the factored format; each is driven below.
+
 The wave kernel draws the same Philox blocks as the oracle but sums
 propensities in chunks (two wave-level prefix scans, incremental chunk sums)
 instead of sequentially, so a0 and the running sums may differ in the last
@@ -168,3 +173,83 @@ def test_wave_single_bin_matches_brute_force_distribution():
     p = stats.chi2_contingency(tab)[1] if tab.shape[1] > 1 else 1.0
     _say(f"   two-sample chi-square p = {p:.3f}")
     assert p > 0.01
+
+
+def test_descriptor_table_kernel_many_walkers():
+    """More walkers than the factored kernel holds at once (8 runs x 1536
+    slots of a 100 x 700 network), which takes the descriptor-table kernel
+    with descriptors alone in LDS and the dependency lists from global
+    memory (two blocks per CU)."""
+    _say("case: wave kernel, 8 runs x 1536 slots, random 100x700 network (descriptor-table kernel)")
+    net = wl.random_network(13, 100, 700, rate_lo=1e-3, rate_hi=1.0)
+    rng = np.random.default_rng(13)
+    x0 = rng.integers(0, 20, size=100).astype(np.int32)
+    coef = np.zeros(100)
+    coef[1] = 1.0
+    cfg = wl.WEConfig(name="rnd_many", net=net, x0=x0, bin_coef=coef,
+                      edges=np.array([0, 2, 4, 8, 16, 32, 64.]), m_targ=256, tau=0.05, n_iters=8,
+                      seeds=np.arange(31, 39, dtype=np.uint64))
+    assert cfg.cap * len(cfg.seeds) // 2 > 16 * 256
+    _compare(cfg, 8, [0, 5], _we().WE_KERNEL_WAVE)
+
+
+def test_header_table_kernel_for_networks_outside_the_factored_format():
+    """A reaction changing five species does not fit the factored format
+    (at most four changes per reaction), so this network runs on the
+    descriptor-table kernel with the reaction headers in LDS."""
+    _say("case: wave kernel, five-change reaction (header-table kernel)")
+    names = ["A", "B", "C", "D", "E", "F"]
+    rx = [({}, {"A": 1}, 3.0), ({"A": 1}, {"B": 1, "C": 1, "D": 1, "E": 1, "F": 1}, 0.5)]
+    for n in names[1:]:
+        rx.append(({n: 1}, {}, 0.4))
+        rx.append(({n: 2}, {"A": 1}, 0.02))
+    net = wl.Network.from_reactions(names, rx)
+    coef = np.zeros(6)
+    coef[2] = 1.0
+    cfg = wl.WEConfig(name="five", net=net, x0=np.array([5, 3, 3, 3, 3, 3], np.int32), bin_coef=coef,
+                      edges=np.arange(0.0, 21.0, 2.0), m_targ=6, tau=0.2, n_iters=20,
+                      seeds=np.array([4, 5], np.uint64))
+    _compare(cfg, 20, [0, 1], _we().WE_KERNEL_WAVE)
+
+
+def test_wave_large_network_from_its_own_initial_state():
+    """The large workload itself at its own start: x0 log-uniform on [0, 1000]
+    (a0 about 2e7 per unit time), on a reduced budget (tau = 5e-6, four
+    intervals, about 100 events per walker per interval).  Walker by walker
+    the wave kernel follows the oracle (the same random numbers), and its
+    histogram of the binned species over 1024 independent trajectories (one
+    bin) matches an oracle brute-force ensemble on other seeds (two-sample
+    chi-square p > 0.01) for two species."""
+    _say("case: wave kernel, 354/3680 network from its own x0, tau 5e-6")
+    we = _we()
+    base = wl.large_network_config()
+    cfg = wl.WEConfig(name="large_x0", net=base.net, x0=base.x0, bin_coef=base.bin_coef,
+                      edges=np.array([-1e9, 1e9]), m_targ=32, tau=5e-6, n_iters=4,
+                      seeds=np.array([321], np.uint64))
+    _compare(cfg, 4, [0], _we().WE_KERNEL_WAVE, max_frac=0.05)
+    big = wl.WEConfig(name="large_x0_bf", net=base.net, x0=base.x0, bin_coef=base.bin_coef,
+                      edges=np.array([-1e9, 1e9]), m_targ=1024, tau=5e-6, n_iters=4,
+                      seeds=np.array([654], np.uint64))
+    sim = we.sim_from_config(big, kernel=we.WE_KERNEL_WAVE, max_iters=4)
+    sim.step(4)
+    x, _, _, _ = sim.walkers(0)
+    onet = orc.OracleNet(base.net)
+    cpu = []
+    for k in range(200):
+        y = base.x0.copy()
+        for it in range(4):
+            y, _ = orc.ssa_interval(onet, y, 5e-6, 777, k, it)
+        cpu.append(y)
+    cpu = np.array(cpu)
+    sp = int(np.argmax(base.bin_coef))
+    busiest = int(np.argmax(np.abs(x - base.x0).mean(axis=0)))   # the species that moved most
+    for s in (sp, busiest):
+        g, c = x[:, s], cpu[:, s]
+        edges = np.arange(min(g.min(), c.min()), max(g.max(), c.max()) + 2)
+        hg, hc = np.histogram(g, edges)[0], np.histogram(c, edges)[0]
+        keep = (hg + hc) >= 5
+        tab = np.vstack([np.append(hg[keep], hg[~keep].sum()), np.append(hc[keep], hc[~keep].sum())])
+        tab = tab[:, tab.sum(axis=0) > 0]
+        p = stats.chi2_contingency(tab)[1] if tab.shape[1] > 1 else 1.0
+        _say(f"   species {s}: two-sample chi-square p = {p:.3f} over {tab.shape[1]} cells")
+        assert p > 0.01
