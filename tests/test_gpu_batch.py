@@ -98,8 +98,10 @@ def test_batch_autotune_writes_and_reuses_cache():
 
 def test_uneven_batch_runs():
     """A 16-run slice of the uneven batch workload (8 to 3680 reactions,
-    256 to 8192 walker slots) steps through a captured graph; every member's
-    weights still sum to one."""
+    256 to 8192 walker slots) steps through a captured graph.  Every member's
+    weights still sum to one, and every member the autotuner put on the lane
+    kernel equals the oracle's run of the same configuration and seed, bit
+    for bit (states, weights, bins, parents, flux)."""
     print("case: uneven batch, 16 runs", flush=True)
     we = _we()
     cfgs = wl.batch_configs(n_runs=16, n_iters=20)
@@ -107,7 +109,68 @@ def test_uneven_batch_runs():
     b.graph_capture(10)
     b.graph_replay(2)
     b.synchronize()
-    for m in b.members:
-        x, w, _, _ = m.walkers(0)
+    kernels = list(b.kernels())
+    n_lane = 0
+    for c, m, k in zip(cfgs, b.members, kernels):
+        x, w, bb, oo = m.walkers(0)
         assert abs(w.sum() - 1.0) < 1e-12
         assert (x >= 0).all()
+        if k != we.WE_KERNEL_LANE:
+            continue
+        n_lane += 1
+        o = orc.OracleWE(c, int(c.seeds[0]))
+        o.step(20)
+        ox, ow, ob, oo_ = o.walkers()
+        print(f"   {c.name}: S={c.net.S} R={c.net.R}, {len(w)} walkers vs oracle", flush=True)
+        assert len(w) == len(ow)
+        assert np.array_equal(x, ox) and np.array_equal(w, ow)
+        assert np.array_equal(bb, ob) and np.array_equal(oo, oo_)
+        assert np.array_equal(m.flux(0), np.array(o.flux))
+    assert n_lane >= 2
+
+
+def test_batch_learned_bins_equal_standalone_runs():
+    """Records and learned bins inside a batch.  Two toggle members (lane and
+    wave kernel) record 30 eager iterations; their recorded ensembles equal
+    a standalone run's.  Each member then trains its committor and switches
+    to learned bins, and its checkpoint is loaded into a standalone sim.  The
+    batch continues 10 eager iterations and 20 through a captured graph (the
+    batched committor-bin launch), the standalone sims the same 30 on their
+    own: states, weights, bins, parents and flux are equal bit for bit."""
+    print("case: batch with records and learned bins (toggle lane + wave members)", flush=True)
+    we = _we()
+    base = wl.toggle_config(n_runs=2, n_bins=16, m_targ=4, n_iters=80)
+    cfgs = [base, wl.toggle_config(seed0=100, n_runs=1, n_bins=16, m_targ=6, n_iters=80)]
+    cfgs[1].seeds = np.array([77], np.uint64)
+    kernels = [we.WE_KERNEL_LANE, we.WE_KERNEL_WAVE]
+    b = we.Batch(cfgs, max_iters=80, kernels=kernels, record_iters=30)
+    b.step(30)
+    b.synchronize()
+    s0 = we.sim_from_config(cfgs[0], kernel=kernels[0], max_iters=80, record_iters=30)
+    s0.step(30)
+    for it in (0, 17, 29):
+        gn, gx, go, grc = b.members[0].record(it)
+        sn, sx, so, src = s0.record(it)
+        assert np.array_equal(gn, sn) and np.array_equal(gx, sx)
+        assert np.array_equal(go, so) and np.array_equal(grc, src)
+    tmp = tempfile.mkdtemp(prefix="we_bcm_")
+    solo = []
+    for i, (c, m) in enumerate(zip(cfgs, b.members)):
+        loss, n = m.train_committor(c.bin_coef, c.a_thr, steps=120, batch=512, lr=2e-3, seed=4 + i,
+                                    edge_mode=1)
+        assert n > 0
+        m.use_committor_bins(True)
+        path = os.path.join(tmp, f"m{i}.ckpt")
+        m.save(path)
+        solo.append(we.Sim.load(b.networks[i], path))
+    b.step(10)
+    b.graph_capture(10)
+    b.graph_replay(2)
+    b.synchronize()
+    for i, s in enumerate(solo):
+        s.step(30)
+        s.synchronize()
+        _same(b.members[i], s)
+        x, w, bb, _ = b.members[i].walkers(0)
+        assert abs(w.sum() - 1.0) < 1e-12
+    print(f"   members equal their standalone learned-bin runs after 30 iterations", flush=True)

@@ -179,3 +179,64 @@ def test_learned_bins_gain_over_a_product_count_coordinate():
     ep, el = rel_err(plain), rel_err(learned)
     _say(f"   reference MFPT {ref:.0f}; RMS relative error plain {ep:.3f}, learned {el:.3f}")
     assert el * 1.5 < ep
+
+
+@pytest.mark.parametrize("edge_mode", [0, 1])
+def test_inference_and_learned_bins_match_oracle_forward(edge_mode):
+    """Device inference against the FP64 forward pass on the trained
+    parameters: q(x) of the live walkers and of seeded states spanning the
+    count range to 2e-5 absolute (the logit to 1e-3 where |z| < 8), and the
+    learned bin of every live walker after a step on committor bins equal to
+    the oracle's bin of the FP64 logit on the same edges -- except within
+    1e-3 of an edge, where the FP32 and FP64 logits may fall either side and
+    either neighbouring bin is accepted.  Equal-count edges are quantiles of
+    the training states' own FP32 logits, so walkers sitting in those states
+    lie on an edge by construction; equal-width edges are not data points,
+    and there such walkers must be rare.  Walkers in the same state always
+    share a bin."""
+    _say(f"case: committor inference + learned bins vs oracle forward, edge_mode={edge_mode}")
+    we = _we()
+    cfg = wl.toggle_config(n_runs=4, n_iters=80)
+    sim = we.sim_from_config(cfg, kernel=we.WE_KERNEL_LANE, max_iters=80, record_iters=60)
+    sim.step(60)
+    sim.train_committor(cfg.bin_coef, cfg.a_thr, steps=300, batch=1024, lr=2e-3, seed=3,
+                        edge_mode=edge_mode)
+    sim.use_committor_bins(True)
+    sim.step(2)
+    sim.synchronize()
+    p, feat, edges = sim.committor_state()
+    S = cfg.net.S
+    assert len(edges) == cfg.n_bins + 1 and np.all(np.diff(edges[1:-1]) > 0)
+    xs, bs = [], []
+    for r in range(len(cfg.seeds)):
+        x, w, b, _ = sim.walkers(r)
+        xs.append(x)
+        bs.append(b)
+    X = np.concatenate(xs)
+    B = np.concatenate(bs)
+    rng = np.random.default_rng(11)
+    extra = np.floor(np.exp(rng.uniform(0, np.log(1001), size=(512, S))) - 1).astype(np.int32)
+    allx = np.concatenate([X, extra])
+    q_dev = sim.committor(allx).astype(np.float64)
+    _, _, _, z = mlp.forward(p.astype(np.float64), feat.astype(np.float64), allx, S)
+    q_ref = 1.0 / (1.0 + np.exp(-z))
+    err_q = np.abs(q_dev - q_ref)
+    _say(f"   {len(X)} walkers + {len(extra)} seeded states; max |q - q_ref| {err_q.max():.2e}; "
+         f"z range [{z.min():.1f}, {z.max():.1f}]")
+    assert err_q.max() <= 2e-5
+    mid = np.abs(z) < 8
+    z_dev = np.log(q_dev[mid] / (1.0 - q_dev[mid]))
+    assert np.abs(z_dev - z[mid]).max() <= 1e-3
+    zw = z[:len(X)]
+    ref_bins = np.array([orc.bin_of(edges, float(v)) for v in zw])
+    inner = edges[1:-1]
+    near = np.min(np.abs(zw[:, None] - inner[None, :]), axis=1) <= 1e-3
+    assert np.array_equal(B[~near], ref_bins[~near])
+    assert np.all(np.abs(B[near] - ref_bins[near]) <= 1)
+    _say(f"   bins equal on {np.sum(~near)} walkers; {np.sum(near)} within 1e-3 of an edge")
+    if edge_mode == 1:
+        assert np.sum(near) <= max(2, len(X) // 100)
+    _, inv = np.unique(X, axis=0, return_inverse=True)
+    inv = inv.ravel()
+    for g in np.unique(inv[near]):
+        assert np.unique(B[inv == g]).size == 1
