@@ -57,7 +57,9 @@ typedef enum {
 typedef enum {
     WE_KERNEL_AUTO = 0, /* lane-per-walker for small networks, else wave      */
     WE_KERNEL_LANE = 1, /* one lane per walker, full propensity recompute     */
-    WE_KERNEL_WAVE = 2  /* one 64-wide wavefront per walker                   */
+    WE_KERNEL_WAVE = 2, /* one 64-wide wavefront per walker                   */
+    WE_KERNEL_GROUP = 3 /* 64 / walkers_per_wave lanes per walker, full       */
+                        /*   propensity recompute split over the group       */
 } we_kernel;
 
 /* ---------------------------------------------------------------- network
@@ -166,6 +168,9 @@ typedef struct {
                                /*      sum_k max(1, ceil(w_k / (2 w*))) > m_targ,   */
                                /*      then replicate up to m_targ.  A bin of zero  */
                                /*      weight falls back to rule 0.                 */
+    int32_t walkers_per_wave;  /* group kernel: walkers sharing one wave, one of    */
+                               /*   2, 4, 8, 16, 32 (64 / that many lanes each,     */
+                               /*   (64 / L) * S <= 4096); other kernels: ignored   */
 } we_params;
 
 /* Device bytes a sim needs (walker buffers, series, scratch). */
@@ -422,18 +427,44 @@ WE_API we_status we_mlp_loss_grad_noalloc(int32_t n_in, const float *params, con
 WE_API we_status we_adam_step(int32_t n, float *params, float *m, float *v, const float *grad,
                               float lr, int32_t t);
 
+/* ---------------------------------------------------------------- peaks
+ * Microbenchmarks of the ceilings the kernels' rooflines are priced against,
+ * measured on the current device (not part of the method): HBM bandwidth of
+ * a 1 GiB device-to-device copy (read + write bytes), LDS read bandwidth
+ * (conflict-free 16-byte reads), FP64 FMA rate (2 flops each) and 32-bit
+ * integer lane-operation rate; each the median of five timed launches.
+ * Allocates 2 GiB of device memory for the duration of the call.
+ * Synchronous on hip_stream (NULL: the default stream). */
+typedef struct {
+    double hbm_gbs;            /* GB/s */
+    double lds_tbs;            /* TB/s */
+    double fp64_tflops;        /* TFLOP/s */
+    double int32_tops;         /* 10^12 lane operations/s */
+    int32_t compute_units;
+} we_peaks;
+WE_API we_status we_measure_peaks(void *hip_stream, we_peaks *out);
+
 /* ---------------------------------------------------------------- batches
  * Many independent WE runs of DIFFERENT networks stepped together on one
  * stream (the paper runs independent replicas, Sec. IV).  Member i is an
  * ordinary sim built from nets[i], grids[i], params[i] (library-allocated
- * workspace, records not supported); the propagation of all members is one
- * persistent launch per kernel variant whose waves pull (run, walker-tile)
- * work items from a device counter, so uneven runs balance across the chip.
- * autotune_iters > 0: a network that fits both kernels (params.kernel
- * AUTO) is timed for that many iterations with each and the faster is kept;
- * choices are cached in the JSON file cache_path (NULL: no cache).
+ * workspace; no reweighting, tau-leaping or Hill rates); the propagation of
+ * all members is one persistent launch per kernel variant whose waves pull
+ * (run, walker-tile) work items from a device counter, so uneven runs
+ * balance across the chip.
+ * autotune_iters > 0: for a member with params.kernel AUTO, every kernel
+ * its network fits -- lane (64 walkers per wave), group (32, 16, 8, 4 or 2
+ * walkers per wave), wave (1) -- is timed for that many iterations and the
+ * fastest is kept; choices are cached in the JSON file cache_path (NULL: no
+ * cache).  autotune_iters = 0: lane for networks of up to 32 reactions that
+ * fit it, else wave.
  * Members are owned by the batch: read them with the sim getters via
- * we_batch_sim, never step or destroy them directly. */
+ * we_batch_sim, never step or destroy them directly.  The committor calls
+ * apply to members too: a member with params.record_iters > 0 records its
+ * ensembles during eager we_batch_step calls, we_train_committor trains its
+ * model, and after we_use_committor_bins(member, 1) the batch bins that
+ * member on its learned committor from the next iteration on (one batched
+ * launch for all such members). */
 typedef struct we_batch we_batch;
 WE_API we_status we_batch_create(int32_t n, const we_network *const *nets, const we_grid *grids,
                                  const we_params *params, void *hip_stream,
@@ -441,12 +472,17 @@ WE_API we_status we_batch_create(int32_t n, const we_network *const *nets, const
 /* n iterations of every member (asynchronous).  Errors: WE_ECAPACITY past
  * the smallest member max_iters. */
 WE_API we_status we_batch_step(we_batch *b, int32_t n);
-/* Capture n (even) batched iterations as one HIP graph / replay it. */
+/* Capture n (even) batched iterations as one HIP graph / replay it.
+ * Errors: WE_ESTATE while a member is still recording (capture), or when a
+ * member's bins were switched or its model retrained into new buffers
+ * since the capture (replay: capture again). */
 WE_API we_status we_batch_graph_capture(we_batch *b, int32_t n);
 WE_API we_status we_batch_graph_replay(we_batch *b, int32_t times);
-/* Member i (NULL if out of range); kernels[i] gets each member's kernel. */
+/* Member i (NULL if out of range); kernels[i] gets each member's kernel and
+ * walkers_per_wave[i] its walkers per wave (lane 64, group 2..32, wave 1);
+ * either array may be NULL. */
 WE_API we_sim *we_batch_sim(we_batch *b, int32_t i);
-WE_API we_status we_batch_info(we_batch *b, int32_t *n_sims, int32_t *kernels);
+WE_API we_status we_batch_info(we_batch *b, int32_t *n_sims, int32_t *kernels, int32_t *walkers_per_wave);
 WE_API void we_batch_destroy(we_batch *b);
 
 /* Per-kernel timing with HIP events recorded on the sim's stream around

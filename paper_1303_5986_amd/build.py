@@ -20,7 +20,7 @@ ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libwe.so")
 
 SOURCES = ["we_runtime.hip", "work_queue.hip", "ssa_lane.hip", "ssa_wave.hip", "we_resample.hip", "reweight.hip",
-           "committor.hip", "batch.hip", "checkpoint.hip"]
+           "committor.hip", "batch.hip", "checkpoint.hip", "ssa_group.hip", "peaks.hip"]
 
 
 def hipcc() -> str:

@@ -8,6 +8,7 @@
 // every kernel variant gets ONE persistent launch whose waves pull work
 // items (run, tile) from a device counter until the list is exhausted:
 //   lane variants: a tile is 64 consecutive walker slots, one per lane;
+//   group variants: a tile is 64 / L consecutive slots, L lanes each;
 //   wave variant:  a tile is one walker slot, one wave.
 // Items of cheap and expensive runs mix freely, so uneven runs balance
 // across the chip.  The bookkeeping is batched the same way: recycle/bin,
@@ -15,12 +16,15 @@
 // iteration counters are one launch each, with the member index on grid y;
 // a member's arguments and buffers are read from device tables.  The whole
 // iteration can be captured as a HIP graph (the work counters are cleared
-// by a kernel, not a memset, so replays are safe).  A batch bins on grids
-// only (no learned bins, no records).
+// by a kernel, not a memset, so replays are safe).  Members may record their
+// ensembles (eager steps only) and, once a member's committor is trained and
+// switched on, bin on it: one batched launch evaluates every such member's
+// model after the batched recycle/bin.
 //
-// Autotuning: for a network that fits both kernels, a short pilot of each
-// (timed with HIP events) picks the faster; the choice is cached in a JSON
-// file keyed by (species, reactions, walker slots, runs).
+// Autotuning: every kernel a network fits -- lane (64 walkers per wave),
+// group with 32, 16, 8, 4 or 2 walkers per wave, wave (one) -- runs a short
+// pilot (timed with HIP events) and the fastest is kept; the choice is cached
+// in a JSON file keyed by (species, reactions, walker slots, runs, tau).
 #include <algorithm>
 #include <cstdio>
 #include <fstream>
@@ -29,13 +33,31 @@
 #include <string>
 #include <vector>
 
+#include "ssa_group_body.h"
 #include "ssa_lane_body.h"
 #include "ssa_wave_body.h"
 #include "we_internal.h"
 
 namespace {
 
-enum Variant { V_LANE_1_4 = 0, V_LANE_2_8, V_LANE_8_16, V_LANE_16_32, V_WAVE, V_COUNT };
+enum Variant {
+    V_LANE_1_4 = 0, V_LANE_2_8, V_LANE_8_16, V_LANE_16_32,
+    V_GROUP_2, V_GROUP_4, V_GROUP_8, V_GROUP_16, V_GROUP_32,
+    V_WAVE, V_COUNT
+};
+
+// Walker slots per work item of a variant.
+int32_t tile_of(int v) {
+    switch (v) {
+    case V_GROUP_2: return 32;
+    case V_GROUP_4: return 16;
+    case V_GROUP_8: return 8;
+    case V_GROUP_16: return 4;
+    case V_GROUP_32: return 2;
+    case V_WAVE: return 1;
+    default: return 64;
+    }
+}
 
 struct Item {
     int32_t sim, run, slot;
@@ -44,6 +66,14 @@ struct Item {
 Variant variant_of(const we_sim *s) {
     const int32_t S = s->S, R = s->net->R;
     if (s->kernel == WE_KERNEL_WAVE) return V_WAVE;
+    if (s->kernel == WE_KERNEL_GROUP)
+        switch (s->group_lanes) {
+        case 2: return V_GROUP_2;
+        case 4: return V_GROUP_4;
+        case 8: return V_GROUP_8;
+        case 16: return V_GROUP_16;
+        default: return V_GROUP_32;
+        }
     if (S <= 1 && R <= 4) return V_LANE_1_4;
     if (S <= 2 && R <= 8) return V_LANE_2_8;
     if (S <= 8 && R <= 16) return V_LANE_8_16;
@@ -99,6 +129,32 @@ __global__ __launch_bounds__(256) void batch_wave_kernel(const SimArgs *__restri
     }
 }
 
+// Group variant: a work item is 64 / L consecutive slots of one run, one
+// group of L lanes per slot; lx slices are s_max ints (the largest species
+// count among the members on this variant).
+template <int L>
+__global__ __launch_bounds__(256) void batch_group_kernel(const SimArgs *__restrict__ args,
+                                                          int32_t *const *__restrict__ xptr,
+                                                          const Item *__restrict__ items, int32_t n_items,
+                                                          uint32_t *__restrict__ counter, int32_t s_max) {
+    extern __shared__ int32_t bglds[];
+    constexpr int G = 64 / L;
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int grp = lane / L;
+    int32_t *lx = bglds + ((size_t)wv * G + grp) * s_max;
+    for (;;) {
+        // every lane executes the atomic (lane 0 adds one): see batch_lane_kernel
+        const uint32_t got = atomicAdd(counter, lane == 0 ? 1u : 0u);
+        const uint32_t idx = (uint32_t)__shfl((int)got, 0, 64);
+        if (idx >= (uint32_t)n_items) break;
+        const Item it = items[idx];
+        const SimArgs &a = args[it.sim];
+        const int32_t k = it.slot + grp;
+        const bool live = k < a.cap && k < a.n_walk[it.run];
+        group_walker<L>(a, xptr[it.sim], it.run, k, live, *a.iter_dev, lx);
+    }
+}
+
 __global__ void batch_reset_kernel(uint32_t *counters, int32_t n) {
     const int32_t i = threadIdx.x;
     if (i < n) counters[i] = 0u;
@@ -114,7 +170,8 @@ struct BatchPtrs {
     const int32_t *grid_bins;
 };
 hipError_t launch_batch_bookkeeping(const BatchPtrs &b, int32_t n_sims, int64_t max_slots, int32_t max_runs,
-                                    int64_t max_cells, size_t shmem, bool observe, hipStream_t st);
+                                    int64_t max_cells, size_t shmem, bool observe, const CmBatchModel *models,
+                                    int32_t s_max_cm, hipStream_t st);
 bool resample_uses_lds(const SimArgs &a);
 size_t resample_lds_bytes(const SimArgs &a, bool use_lds);
 int32_t resample_place_rows(const SimArgs &a, int64_t blocks);
@@ -135,20 +192,28 @@ struct we_batch {
     size_t resample_shmem = 0;
     bool observe = false;
     int32_t s_pad = 4;
+    int32_t s_group = 1;              // largest species count among group-kernel members
     int32_t iter = 0, max_iters = 0;
     hipGraphExec_t graph_exec = nullptr;
     hipStream_t capture_stream = nullptr;
     int32_t graph_iters = 0;
     bool capturing = false;
+    // learned bins: each member's active model as the device tables hold it
+    std::vector<CmBatchModel> cm_host, cm_graph;
+    std::vector<int32_t> grid_bins_host;
+    CmBatchModel *d_models = nullptr;
+    int32_t s_max_cm = 0;
+    bool any_cm = false;
 };
 
 namespace {
 
 // Pilot timing of one kernel choice: a throw-away sim, `iters` iterations.
-we_status pilot_ms(const we_network *net, const we_grid *g, const we_params *p, int32_t kernel, int32_t iters,
-                   hipStream_t st, double *ms) {
+we_status pilot_ms(const we_network *net, const we_grid *g, const we_params *p, int32_t kernel,
+                   int32_t walkers_per_wave, int32_t iters, hipStream_t st, double *ms) {
     we_params q = *p;
     q.kernel = kernel;
+    q.walkers_per_wave = walkers_per_wave;
     q.max_iters = iters;
     q.record_iters = 0;
     q.n_joint = 0;
@@ -213,7 +278,7 @@ we_status build_items(we_batch *b) {
     for (size_t i = 0; i < b->sims.size(); ++i) {
         we_sim *s = b->sims[i];
         const Variant v = b->var[i];
-        const int32_t step = (v == V_WAVE) ? 1 : 64;
+        const int32_t step = tile_of(v);
         for (int32_t r = 0; r < s->n_runs; ++r)
             for (int32_t k = 0; k < s->cap; k += step) b->items[v].push_back(Item{(int32_t)i, r, k});
     }
@@ -227,9 +292,47 @@ we_status build_items(we_batch *b) {
     return WE_OK;
 }
 
-we_status launch_batch_iteration(we_batch *b, hipStream_t st) {
-    for (we_sim *s : b->sims)
-        if (s->cm.active) return we_fail(WE_ESTATE, "learned bins are not supported inside a batch");
+bool same_models(const std::vector<CmBatchModel> &x, const std::vector<CmBatchModel> &y) {
+    if (x.size() != y.size()) return false;
+    for (size_t i = 0; i < x.size(); ++i)
+        if (x[i].params != y[i].params || x[i].wt != y[i].wt || x[i].feat != y[i].feat || x[i].qedges != y[i].qedges)
+            return false;
+    return true;
+}
+
+std::vector<CmBatchModel> current_models(const we_batch *b) {
+    std::vector<CmBatchModel> m;
+    for (const we_sim *s : b->sims) m.push_back(committor_batch_model(s));
+    return m;
+}
+
+// Bring the device tables of learned bins up to date with the members'
+// committors (trained and switched on since the last iteration, or off).
+we_status refresh_models(we_batch *b) {
+    std::vector<CmBatchModel> m = current_models(b);
+    if (same_models(m, b->cm_host)) return WE_OK;
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    b->any_cm = false;
+    b->s_max_cm = 0;
+    for (size_t i = 0; i < m.size(); ++i) {
+        const bool on = m[i].params != nullptr;
+        b->grid_bins_host[i] = on ? 0 : 1;
+        if (on) {
+            b->any_cm = true;
+            b->s_max_cm = std::max(b->s_max_cm, b->sims[i]->S);
+        }
+    }
+    HIP_TRY(hipMemcpy(b->d_models, m.data(), sizeof(CmBatchModel) * m.size(), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(b->d_grid_bins, b->grid_bins_host.data(), sizeof(int32_t) * m.size(), hipMemcpyHostToDevice));
+    b->cm_host = m;
+    return WE_OK;
+}
+
+we_status launch_batch_iteration(we_batch *b, hipStream_t st, bool capture) {
+    if (!capture) {
+        we_status r = refresh_models(b);
+        if (r != WE_OK) return r;
+    }
     const int32_t parity = b->sims[0]->cur;
     hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(64), 0, st, b->d_counters, (int32_t)V_COUNT);
     HIP_TRY(hipGetLastError());
@@ -252,6 +355,25 @@ we_status launch_batch_iteration(we_batch *b, hipStream_t st) {
         case V_LANE_16_32:
             hipLaunchKernelGGL((batch_lane_kernel<16, 32>), dim3(blocks), dim3(256), 0, st, b->d_args, xp, b->d_items[v], n, cnt);
             break;
+        case V_GROUP_2:
+        case V_GROUP_4:
+        case V_GROUP_8:
+        case V_GROUP_16:
+        case V_GROUP_32: {
+            const int32_t G = tile_of(v);
+            const size_t shmem = sizeof(int32_t) * 4 * (size_t)G * b->s_group;
+            if (v == V_GROUP_2)
+                hipLaunchKernelGGL((batch_group_kernel<2>), dim3(blocks), dim3(256), shmem, st, b->d_args, xp, b->d_items[v], n, cnt, b->s_group);
+            else if (v == V_GROUP_4)
+                hipLaunchKernelGGL((batch_group_kernel<4>), dim3(blocks), dim3(256), shmem, st, b->d_args, xp, b->d_items[v], n, cnt, b->s_group);
+            else if (v == V_GROUP_8)
+                hipLaunchKernelGGL((batch_group_kernel<8>), dim3(blocks), dim3(256), shmem, st, b->d_args, xp, b->d_items[v], n, cnt, b->s_group);
+            else if (v == V_GROUP_16)
+                hipLaunchKernelGGL((batch_group_kernel<16>), dim3(blocks), dim3(256), shmem, st, b->d_args, xp, b->d_items[v], n, cnt, b->s_group);
+            else
+                hipLaunchKernelGGL((batch_group_kernel<32>), dim3(blocks), dim3(256), shmem, st, b->d_args, xp, b->d_items[v], n, cnt, b->s_group);
+            break;
+        }
         default: {
             const size_t shmem = WAVE_WALKERS_PER_BLOCK * (64 * sizeof(double) + sizeof(int32_t) * (size_t)b->s_pad);
             hipLaunchKernelGGL(batch_wave_kernel, dim3(blocks), dim3(256), shmem, st, b->d_args, xp, b->d_items[v],
@@ -266,9 +388,18 @@ we_status launch_batch_iteration(we_batch *b, hipStream_t st) {
                  (const double *const *)b->d_wptr[parity], b->d_wptr[1 - parity], b->d_use_lds,
                  b->d_grid_bins};
     HIP_TRY(launch_batch_bookkeeping(bp, (int32_t)b->sims.size(), b->max_slots, b->max_runs, b->max_cells,
-                                     b->resample_shmem, b->observe, st));
+                                     b->resample_shmem, b->observe, b->any_cm ? b->d_models : nullptr,
+                                     b->s_max_cm, st));
     for (we_sim *s : b->sims) s->cur = 1 - s->cur;
+    if (!capture)
+        for (we_sim *s : b->sims) HIP_TRY(committor_record(s, st));
     return WE_OK;
+}
+
+bool recording(const we_batch *b) {
+    for (const we_sim *s : b->sims)
+        if (s->rec.cap_iters > 0 && s->rec.n_iters < s->rec.cap_iters) return true;
+    return false;
 }
 
 }  // namespace
@@ -284,10 +415,6 @@ extern "C" we_status we_batch_create(int32_t n, const we_network *const *nets, c
     bool cache_dirty = false;
     for (int32_t i = 0; i < n; ++i) {
         we_params p = params[i];
-        if (p.record_iters > 0) {
-            we_batch_destroy(b);
-            return we_fail(WE_EINVAL, "records are not supported inside a batch");
-        }
         if (p.rw_period > 0) {
             we_batch_destroy(b);
             return we_fail(WE_EINVAL, "reweighting is not supported inside a batch");
@@ -302,26 +429,39 @@ extern "C" we_status we_batch_create(int32_t n, const we_network *const *nets, c
         }
         const int32_t S = nets[i]->S, R = nets[i]->R;
         if (p.kernel == WE_KERNEL_AUTO) {
-            if (!(lane_kernel_fits(S, R, nets[i]->max_delta) && R <= 32)) {
-                p.kernel = WE_KERNEL_WAVE;
-            } else if (autotune_iters > 0) {
+            const bool lane_ok = lane_kernel_fits(S, R, nets[i]->max_delta);
+            if (autotune_iters > 0) {
                 char key[128];
                 std::snprintf(key, sizeof key, "S%d_R%d_cap%d_runs%d_tau%g", S, R, p.m_targ * grids[i].n_bins,
                               p.n_runs, p.tau);
                 auto it = cache.find(key);
                 if (it != cache.end()) {
-                    p.kernel = it->second;
+                    // value: kernel + 16 * walkers per wave (group kernel)
+                    p.kernel = it->second % 16;
+                    p.walkers_per_wave = it->second / 16;
                 } else {
-                    double t_lane = 0.0, t_wave = 0.0;
-                    we_status r = pilot_ms(nets[i], &grids[i], &p, WE_KERNEL_LANE, autotune_iters, b->stream, &t_lane);
-                    if (r == WE_OK) r = pilot_ms(nets[i], &grids[i], &p, WE_KERNEL_WAVE, autotune_iters, b->stream, &t_wave);
-                    if (r != WE_OK) { we_batch_destroy(b); return r; }
-                    p.kernel = (t_wave < t_lane) ? WE_KERNEL_WAVE : WE_KERNEL_LANE;
-                    cache[key] = p.kernel;
+                    std::vector<std::pair<int32_t, int32_t>> cand;
+                    if (lane_ok) cand.push_back({WE_KERNEL_LANE, 0});
+                    for (int32_t wpw : {32, 16, 8, 4, 2})
+                        if (group_kernel_fits(S, R, 64 / wpw)) cand.push_back({WE_KERNEL_GROUP, wpw});
+                    if (wave_kernel_fits(S, R) && nets[i]->max_chg <= 64) cand.push_back({WE_KERNEL_WAVE, 0});
+                    double best = 0.0;
+                    for (size_t c = 0; c < cand.size(); ++c) {
+                        double t = 0.0;
+                        we_status r = pilot_ms(nets[i], &grids[i], &p, cand[c].first, cand[c].second, autotune_iters,
+                                               b->stream, &t);
+                        if (r != WE_OK) { we_batch_destroy(b); return r; }
+                        if (c == 0 || t < best) {
+                            best = t;
+                            p.kernel = cand[c].first;
+                            p.walkers_per_wave = cand[c].second;
+                        }
+                    }
+                    cache[key] = p.kernel + 16 * p.walkers_per_wave;
                     cache_dirty = true;
                 }
             } else {
-                p.kernel = WE_KERNEL_LANE;
+                p.kernel = (lane_ok && R <= 32) ? WE_KERNEL_LANE : WE_KERNEL_WAVE;
             }
         }
         we_sim *s = nullptr;
@@ -330,6 +470,7 @@ extern "C" we_status we_batch_create(int32_t n, const we_network *const *nets, c
         b->sims.push_back(s);
         b->var.push_back(variant_of(s));
         b->s_pad = std::max(b->s_pad, (S + 3) & ~3);
+        if (s->kernel == WE_KERNEL_GROUP) b->s_group = std::max(b->s_group, S);
         b->max_iters = (i == 0) ? s->max_iters : std::min(b->max_iters, s->max_iters);
     }
     if (cache_dirty) write_cache(cache_path, cache);
@@ -365,6 +506,10 @@ extern "C" we_status we_batch_create(int32_t n, const we_network *const *nets, c
     HIP_TRY(hipMalloc(&b->d_wptr[1], sizeof(double *) * n));
     HIP_TRY(hipMemcpy(b->d_wptr[0], wp0.data(), sizeof(double *) * n, hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(b->d_wptr[1], wp1.data(), sizeof(double *) * n, hipMemcpyHostToDevice));
+    HIP_TRY(hipMalloc(&b->d_models, sizeof(CmBatchModel) * n));
+    b->cm_host.assign(n, CmBatchModel{});
+    b->grid_bins_host.assign(n, 1);
+    HIP_TRY(hipMemcpy(b->d_models, b->cm_host.data(), sizeof(CmBatchModel) * n, hipMemcpyHostToDevice));
     HIP_TRY(hipMalloc(&b->d_use_lds, sizeof(int32_t) * n));
     HIP_TRY(hipMalloc(&b->d_grid_bins, sizeof(int32_t) * n));
     HIP_TRY(hipMemcpy(b->d_use_lds, use_lds.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice));
@@ -386,7 +531,7 @@ extern "C" we_status we_batch_step(we_batch *b, int32_t n) {
     if (!b) return we_fail(WE_EINVAL, "NULL batch");
     if (n < 0 || (int64_t)b->iter + n > b->max_iters) return we_fail(WE_ECAPACITY, "max_iters exceeded");
     for (int32_t i = 0; i < n; ++i) {
-        we_status r = launch_batch_iteration(b, b->stream);
+        we_status r = launch_batch_iteration(b, b->stream, false);
         if (r != WE_OK) return r;
         b->iter += 1;
         for (we_sim *s : b->sims) {
@@ -403,11 +548,16 @@ extern "C" we_status we_batch_graph_capture(we_batch *b, int32_t n) {
     if (b->graph_exec) { (void)hipGraphExecDestroy(b->graph_exec); b->graph_exec = nullptr; }
     if (!b->capture_stream) HIP_TRY(hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking));
     HIP_TRY(hipStreamSynchronize(b->stream));
+    if (recording(b)) return we_fail(WE_ESTATE, "a member is recording: step eagerly until its record buffer is full");
+    {
+        we_status r = refresh_models(b);
+        if (r != WE_OK) return r;
+    }
     std::vector<int32_t> cur0;
     for (we_sim *s : b->sims) { cur0.push_back(s->cur); s->capturing = true; }
     HIP_TRY(hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal));
     we_status r = WE_OK;
-    for (int32_t i = 0; i < n && r == WE_OK; ++i) r = launch_batch_iteration(b, b->capture_stream);
+    for (int32_t i = 0; i < n && r == WE_OK; ++i) r = launch_batch_iteration(b, b->capture_stream, true);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(b->capture_stream, &g);
     for (size_t i = 0; i < b->sims.size(); ++i) { b->sims[i]->cur = cur0[i]; b->sims[i]->capturing = false; }
@@ -417,6 +567,7 @@ extern "C" we_status we_batch_graph_capture(we_batch *b, int32_t n) {
     (void)hipGraphDestroy(g);
     if (e != hipSuccess) return we_hip_fail(e, "hipGraphInstantiate");
     b->graph_iters = n;
+    b->cm_graph = b->cm_host;
     return WE_OK;
 }
 
@@ -425,6 +576,8 @@ extern "C" we_status we_batch_graph_replay(we_batch *b, int32_t times) {
     if (!b->graph_exec) return we_fail(WE_ESTATE, "no captured graph");
     if (times < 0 || (int64_t)b->iter + (int64_t)times * b->graph_iters > b->max_iters)
         return we_fail(WE_ECAPACITY, "max_iters exceeded");
+    if (!same_models(current_models(b), b->cm_graph))
+        return we_fail(WE_ESTATE, "a member's bins changed since the capture: capture again");
     for (int32_t t = 0; t < times; ++t) {
         HIP_TRY(hipGraphLaunch(b->graph_exec, b->stream));
         b->iter += b->graph_iters;
@@ -441,11 +594,16 @@ extern "C" we_sim *we_batch_sim(we_batch *b, int32_t i) {
     return b->sims[i];
 }
 
-extern "C" we_status we_batch_info(we_batch *b, int32_t *n_sims, int32_t *kernels) {
+extern "C" we_status we_batch_info(we_batch *b, int32_t *n_sims, int32_t *kernels, int32_t *walkers_per_wave) {
     if (!b) return we_fail(WE_EINVAL, "NULL batch");
     if (n_sims) *n_sims = (int32_t)b->sims.size();
-    if (kernels)
-        for (size_t i = 0; i < b->sims.size(); ++i) kernels[i] = b->sims[i]->kernel;
+    for (size_t i = 0; i < b->sims.size(); ++i) {
+        const we_sim *s = b->sims[i];
+        if (kernels) kernels[i] = s->kernel;
+        if (walkers_per_wave)
+            walkers_per_wave[i] = s->kernel == WE_KERNEL_GROUP ? 64 / s->group_lanes
+                                  : s->kernel == WE_KERNEL_WAVE ? 1 : 64;
+    }
     return WE_OK;
 }
 
@@ -462,6 +620,7 @@ extern "C" void we_batch_destroy(we_batch *b) {
     (void)hipFree(b->d_wptr[1]);
     (void)hipFree(b->d_use_lds);
     (void)hipFree(b->d_grid_bins);
+    (void)hipFree(b->d_models);
     if (b->graph_exec) (void)hipGraphExecDestroy(b->graph_exec);
     if (b->capture_stream) (void)hipStreamDestroy(b->capture_stream);
     delete b;

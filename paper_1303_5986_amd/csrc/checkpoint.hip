@@ -50,7 +50,7 @@ struct ParamsRec {
     int32_t m_targ, n_runs, max_iters, kernel, recycle;
     int32_t hist_species, hist_lo, hist_hi, n_joint, joint_bins, joint_width;
     int32_t record_iters, rw_period, rw_reset, engine, resample_rule;
-    int32_t n_bins, n_bins2, hist_iters, pad;
+    int32_t n_bins, n_bins2, hist_iters, walkers_per_wave;   // 0: not the group kernel
 };
 
 enum : uint32_t {
@@ -183,6 +183,7 @@ extern "C" we_status we_save(we_sim *s, const char *path) {
     pr.hist_hi = cf.p.hist_hi; pr.n_joint = cf.p.n_joint; pr.joint_bins = cf.p.joint_bins;
     pr.joint_width = cf.p.joint_width; pr.record_iters = cf.p.record_iters; pr.rw_period = cf.p.rw_period;
     pr.rw_reset = cf.p.rw_reset; pr.engine = cf.p.engine; pr.resample_rule = cf.p.resample_rule;
+    pr.walkers_per_wave = s->kernel == WE_KERNEL_GROUP ? 64 / s->group_lanes : 0;
     pr.n_bins = cf.n_bins; pr.n_bins2 = cf.n_bins2; pr.hist_iters = s->hist_iters;
 
     Writer w;
@@ -325,6 +326,7 @@ extern "C" we_status we_load(const we_network *net, const char *path, void *hip_
     p.joint_bins = pr.joint_bins; p.joint_width = pr.joint_width; p.record_iters = pr.record_iters;
     p.rw_period = pr.rw_period; p.rw_reset = pr.rw_reset; p.engine = pr.engine; p.leap_eps = pr.leap_eps;
     p.resample_rule = pr.resample_rule;
+    p.walkers_per_wave = pr.walkers_per_wave;
     if (workspace && workspace_bytes < h.ws_bytes) return we_fail(WE_EINVAL, "checkpoint: workspace too small");
 
     we_sim *s = nullptr;

@@ -506,6 +506,57 @@ hipError_t committor_bin(we_sim *s, int32_t *x_cur, hipStream_t st) {
     return hipGetLastError();
 }
 
+// Learned bins of every batch member whose committor is active, after the
+// batched recycle/bin: grid (CM_BATCH_BLOCKS, members), one wave per walker
+// slot as in cm_bin_kernel, each wave striding over its member's slots (a
+// grid sized for the largest member would spend most of its workgroups on
+// members with no slots left for them); members without a model (params
+// NULL) return at once.
+#define CM_BATCH_BLOCKS 256
+__global__ __launch_bounds__(256) void cm_batch_bin_kernel(const SimArgs *__restrict__ args,
+                                                           int32_t *const *__restrict__ x_cur,
+                                                           const CmBatchModel *__restrict__ models,
+                                                           int32_t s_lds) {
+    extern __shared__ float cm_lds[];
+    const int32_t i = blockIdx.y;
+    const CmBatchModel m = models[i];
+    if (!m.params) return;
+    const SimArgs &a = args[i];
+    const int wv = threadIdx.x >> 6;
+    float *lphi = cm_lds + (size_t)wv * (s_lds + 2 * CM_H);
+    const ParamView P = cm_view(m.params, a.S);
+    const int64_t slots = (int64_t)a.n_runs * a.cap;
+    for (int64_t gid = (int64_t)blockIdx.x * 4 + wv; gid < slots; gid += (int64_t)gridDim.x * 4) {
+        const int32_t run = (int32_t)(gid / a.cap);   // uniform over the wave
+        const int32_t k = (int32_t)(gid - (int64_t)run * a.cap);
+        if (k >= a.n_walk[run]) continue;
+        const size_t idx = (size_t)run * a.cap + k;
+        const float z =
+            mlp_z_wave(P, m.wt, m.feat, x_cur[i] + idx * a.S, a.S, lphi, lphi + s_lds, lphi + s_lds + CM_H);
+        if ((threadIdx.x & 63) == 0) a.s_bin[idx] = bin_index(m.qedges, a.n_bins, (double)z);
+    }
+}
+
+CmBatchModel committor_batch_model(const we_sim *s) {
+    CmBatchModel m{};
+    if (s->cm.active) {
+        m.params = s->cm.d_params;
+        m.wt = s->cm.d_wt;
+        m.feat = s->cm.d_feat;
+        m.qedges = s->cm.d_qedges;
+    }
+    return m;
+}
+
+hipError_t committor_bin_batch(const SimArgs *d_args, int32_t *const *d_x, const CmBatchModel *d_models,
+                               int32_t n_sims, int64_t max_slots, int32_t s_max, hipStream_t st) {
+    const size_t lds = 4 * sizeof(float) * ((size_t)s_max + 2 * CM_H);
+    const unsigned gx = (unsigned)std::max<int64_t>(1, std::min<int64_t>((max_slots + 3) / 4, CM_BATCH_BLOCKS));
+    hipLaunchKernelGGL(cm_batch_bin_kernel, dim3(gx, (unsigned)n_sims), dim3(256), lds, st, d_args, d_x, d_models,
+                       s_max);
+    return hipGetLastError();
+}
+
 void committor_free(we_sim *s) {
     Committor &c = s->cm;
     (void)hipFree(c.d_params);

@@ -83,6 +83,7 @@ struct we_sim {
     hipStream_t stream = nullptr;
     SimArgs args{};
     int32_t kernel = WE_KERNEL_LANE;
+    int32_t group_lanes = 0;        // lanes per walker of the group kernel
     int32_t S = 0, NB = 0, M = 0, n_runs = 0, cap = 0, max_iters = 0;
     double tau = 0.0;
     int32_t iter = 0;
@@ -123,6 +124,8 @@ bool lane_kernel_fits(int32_t S, int32_t R, int32_t max_delta);
 bool wave_kernel_fits(int32_t S, int32_t R);
 const char *ssa_lane_name(const SimArgs &a);
 const char *ssa_wave_name(const SimArgs &a);
+hipError_t launch_ssa_group(const SimArgs &a, int32_t *xs, int32_t lanes, hipStream_t st);
+const char *ssa_group_name(int32_t lanes);
 // reweight.hip
 #define WE_RW_MAX_BINS 512
 bool rw_solve_in_lds(int32_t n_bins);
@@ -139,4 +142,14 @@ we_status committor_export(we_sim *s, CommittorHost &h);
 we_status committor_import(we_sim *s, const CommittorHost &h);
 hipError_t committor_record(we_sim *s, hipStream_t st);
 hipError_t committor_bin(we_sim *s, int32_t *x_cur, hipStream_t st);
+// A batch member's active model as device pointers (all NULL: grid bins).
+struct CmBatchModel {
+    const float *params, *wt, *feat;
+    const double *qedges;
+};
+CmBatchModel committor_batch_model(const we_sim *s);
+// Learned bins of all members with a model: d_models[n_sims] on the device,
+// s_max >= every such member's species count.
+hipError_t committor_bin_batch(const SimArgs *d_args, int32_t *const *d_x, const CmBatchModel *d_models,
+                               int32_t n_sims, int64_t max_slots, int32_t s_max, hipStream_t st);
 void committor_free(we_sim *s);

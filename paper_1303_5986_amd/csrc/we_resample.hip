@@ -46,6 +46,7 @@
 // All weight arithmetic is sequential per bin, so weights are reproducible
 // bit for bit.
 #include "we_common.h"
+#include "we_internal.h"
 
 #include <algorithm>
 
@@ -1009,9 +1010,14 @@ __global__ void we_batch_advance_kernel(BatchPtrs b, int32_t n) {
 #define BATCH_GATHER_BLOCKS 512
 
 hipError_t launch_batch_bookkeeping(const BatchPtrs &b, int32_t n_sims, int64_t max_slots, int32_t max_runs,
-                                    int64_t max_cells, size_t shmem, bool observe, hipStream_t st) {
+                                    int64_t max_cells, size_t shmem, bool observe, const CmBatchModel *models,
+                                    int32_t s_max_cm, hipStream_t st) {
     const unsigned gs = (unsigned)((max_slots + 255) / 256);
     hipLaunchKernelGGL(we_batch_recycle_bin_kernel, dim3(gs, n_sims), dim3(256), 0, st, b);
+    if (models) {
+        const hipError_t e = committor_bin_batch(b.args, b.x_cur, models, n_sims, max_slots, s_max_cm, st);
+        if (e != hipSuccess) return e;
+    }
     hipLaunchKernelGGL(we_batch_resample_kernel, dim3(max_runs, n_sims),
                        dim3(resample_threads((int64_t)max_runs * n_sims)), shmem, st, b);
     const unsigned gg = (unsigned)std::max<int64_t>(1, std::min<int64_t>((max_cells + 255) / 256, BATCH_GATHER_BLOCKS));

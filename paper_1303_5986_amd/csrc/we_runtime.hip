@@ -20,6 +20,7 @@
 #include <string>
 #include <vector>
 
+#include "ssa_group_body.h"
 #include "we_internal.h"
 
 hipError_t launch_ssa_lane(const SimArgs &a, int32_t *xs, hipStream_t st);
@@ -387,7 +388,7 @@ we_status check_params(const we_network *net, const we_grid *g, const we_params 
     }
     if (p->hist_hi >= p->hist_lo && (p->hist_species < 0 || p->hist_species >= net->S))
         return fail(WE_EINVAL, "hist_species out of range");
-    if (p->kernel < WE_KERNEL_AUTO || p->kernel > WE_KERNEL_WAVE)
+    if (p->kernel < WE_KERNEL_AUTO || p->kernel > WE_KERNEL_GROUP)
         return fail(WE_EINVAL, "unknown kernel");
     if (p->n_joint < 0 || p->n_joint > 5) return fail(WE_EINVAL, "n_joint must be in [0, 5]");
     if (p->record_iters < 0) return fail(WE_EINVAL, "record_iters must be >= 0");
@@ -480,10 +481,20 @@ extern "C" we_status we_init(const we_network *net, const we_grid *g, const we_p
     const int32_t nh = p->hist_hi >= p->hist_lo ? p->hist_hi - p->hist_lo + 1 : 0;
     int32_t kernel = p->kernel;
     const bool hill = !net->hill.empty();
-    if (p->engine == 1 && (hill || kernel == WE_KERNEL_WAVE || S > 8 || net->R > 16 || net->max_delta > 127))
+    const bool other = kernel == WE_KERNEL_WAVE || kernel == WE_KERNEL_GROUP;
+    if (p->engine == 1 && (hill || other || S > 8 || net->R > 16 || net->max_delta > 127))
         return fail(WE_EINVAL, "tau-leaping runs on the lane kernel only (mass action, S <= 8, R <= 16)");
-    if (hill && (kernel == WE_KERNEL_WAVE || S > 8 || net->R > 16 || net->max_delta > 127))
+    if (hill && (other || S > 8 || net->R > 16 || net->max_delta > 127))
         return fail(WE_EINVAL, "Hill-type rates run on the lane kernel only (S <= 8, R <= 16)");
+    int32_t group_lanes = 0;
+    if (kernel == WE_KERNEL_GROUP) {
+        const int32_t wpw = p->walkers_per_wave;
+        if (!(wpw == 2 || wpw == 4 || wpw == 8 || wpw == 16 || wpw == 32))
+            return fail(WE_EINVAL, "the group kernel takes 2, 4, 8, 16 or 32 walkers per wave");
+        group_lanes = 64 / wpw;
+        if (!group_kernel_fits(S, net->R, group_lanes))
+            return fail(WE_EINVAL, "network does not fit the group kernel ((64 / L) * S <= 4096, R <= 65535)");
+    }
     if (kernel == WE_KERNEL_AUTO)
         kernel = hill || (lane_kernel_fits(S, net->R, net->max_delta) && net->R <= 32) ? WE_KERNEL_LANE
                                                                                        : WE_KERNEL_WAVE;
@@ -498,6 +509,7 @@ extern "C" we_status we_init(const we_network *net, const we_grid *g, const we_p
     s->net = net;
     s->stream = (hipStream_t)hip_stream;
     s->kernel = kernel;
+    s->group_lanes = group_lanes;
     s->S = S; s->NB = NB; s->M = M; s->n_runs = n_runs; s->cap = cap; s->max_iters = max_iters;
     s->tau = p->tau;
     if (workspace) {
@@ -738,8 +750,9 @@ we_status launch_iteration(we_sim *s, hipStream_t st, bool profile) {
         for (int k = 0; k < 4; ++k) HIP_TRY(next_event(s, &ev[k]));
         HIP_TRY(hipEventRecord(ev[0], st));
     }
-    hipError_t e = (s->kernel == WE_KERNEL_WAVE) ? launch_ssa_wave(a, s->x[c], st)
-                                                 : launch_ssa_lane(a, s->x[c], st);
+    hipError_t e = (s->kernel == WE_KERNEL_WAVE)    ? launch_ssa_wave(a, s->x[c], st)
+                   : (s->kernel == WE_KERNEL_GROUP) ? launch_ssa_group(a, s->x[c], s->group_lanes, st)
+                                                    : launch_ssa_lane(a, s->x[c], st);
     if (e != hipSuccess) return hip_fail(e, "SSA launch");
     if (profile) HIP_TRY(hipEventRecord(ev[1], st));
     return we_sim_bookkeeping(s, st, profile ? ev + 1 : nullptr);
@@ -979,6 +992,7 @@ extern "C" we_status we_profile_read(we_sim *s, double *ms_propagate, double *ms
 
 extern "C" const char *we_propagation_kernel(const we_sim *s) {
     if (!s) return "";
+    if (s->kernel == WE_KERNEL_GROUP) return ssa_group_name(s->group_lanes);
     return s->kernel == WE_KERNEL_LANE ? ssa_lane_name(s->args) : ssa_wave_name(s->args);
 }
 

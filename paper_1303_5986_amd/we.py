@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libwe.so")
 
 WE_OK, WE_EINVAL, WE_ENOMEM, WE_EDEVICE, WE_ECAPACITY, WE_EOVERFLOW, WE_ESTATE = 0, -1, -2, -3, -4, -5, -6
-WE_KERNEL_AUTO, WE_KERNEL_LANE, WE_KERNEL_WAVE = 0, 1, 2
+WE_KERNEL_AUTO, WE_KERNEL_LANE, WE_KERNEL_WAVE, WE_KERNEL_GROUP = 0, 1, 2, 3
 WE_COUNT_MAX = 131071
 
 _STATUS = {WE_EINVAL: "EINVAL", WE_ENOMEM: "ENOMEM", WE_EDEVICE: "EDEVICE",
@@ -33,7 +33,7 @@ EXPORTED = [
     "we_train_committor", "we_use_committor_bins", "we_committor_eval", "we_committor_state",
     "we_record_labels", "we_get_record", "we_mlp_loss_grad", "we_mlp_loss_grad_noalloc", "we_adam_step",
     "we_batch_create", "we_batch_step", "we_batch_graph_capture", "we_batch_graph_replay",
-    "we_batch_sim", "we_batch_info", "we_batch_destroy",
+    "we_batch_sim", "we_batch_info", "we_batch_destroy", "we_measure_peaks",
     "we_set_bins", "we_save", "we_checkpoint_inspect", "we_load", "we_propagation_kernel",
     "we_destroy", "we_last_error",
 ]
@@ -65,7 +65,13 @@ class _Params(C.Structure):
                 ("hist_lo", C.c_int32), ("hist_hi", C.c_int32), ("n_joint", C.c_int32),
                 ("joint_species", C.c_void_p), ("joint_bins", C.c_int32), ("joint_width", C.c_int32),
                 ("record_iters", C.c_int32), ("rw_period", C.c_int32), ("rw_reset", C.c_int32),
-                ("engine", C.c_int32), ("leap_eps", C.c_double), ("resample_rule", C.c_int32)]
+                ("engine", C.c_int32), ("leap_eps", C.c_double), ("resample_rule", C.c_int32),
+                ("walkers_per_wave", C.c_int32)]
+
+
+class _Peaks(C.Structure):
+    _fields_ = [("hbm_gbs", C.c_double), ("lds_tbs", C.c_double), ("fp64_tflops", C.c_double),
+                ("int32_tops", C.c_double), ("compute_units", C.c_int32)]
 
 
 class _Bins(C.Structure):
@@ -145,7 +151,8 @@ def load_library(path: str = LIB_PATH):
     L.we_batch_graph_replay.argtypes = [vp, i32]
     L.we_batch_sim.argtypes = [vp, i32]
     L.we_batch_sim.restype = vp
-    L.we_batch_info.argtypes = [vp, P(i32), vp]
+    L.we_batch_info.argtypes = [vp, P(i32), vp, vp]
+    L.we_measure_peaks.argtypes = [vp, vp]
     L.we_batch_destroy.argtypes = [vp]
     L.we_batch_destroy.restype = None
     L.we_set_bins.argtypes = [vp, vp]
@@ -220,7 +227,7 @@ class Sim:
                  joint_species: Sequence[int] = (), joint_bins: int = 16, joint_width: int = 64,
                  record_iters: int = 0, rw_period: int = 0, rw_reset: bool = False,
                  bin_coef2=None, edges2=None, engine: str = "ssa", leap_eps: float = 0.03,
-                 resample_rule: int = 0, device=None):
+                 resample_rule: int = 0, walkers_per_wave: int = 0, device=None):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("no HIP device: libwe.so runs on MI355X only")
@@ -256,7 +263,8 @@ class Sim:
                               int(hist_species), int(hist_lo), int(hist_hi),
                               len(joint_species), k["joint"].ctypes.data, int(joint_bins),
                               int(joint_width), int(record_iters), int(rw_period), int(bool(rw_reset)),
-                              {"ssa": 0, "tauleap": 1}[engine], float(leap_eps), int(resample_rule))
+                              {"ssa": 0, "tauleap": 1}[engine], float(leap_eps), int(resample_rule),
+                              int(walkers_per_wave))
         self.n_joint = len(joint_species)
         self.joint_cells = int(joint_bins) ** self.n_joint if self.n_joint else 0
         self.nh = hist_hi - hist_lo + 1 if hist_hi >= hist_lo else 0
@@ -497,7 +505,8 @@ class Sim:
 
 def sim_from_config(cfg, *, kernel: int = WE_KERNEL_AUTO, max_iters: Optional[int] = None,
                     network: Optional[Network] = None, joint: bool = False,
-                    record_iters: int = 0, rw_period: int = 0, rw_reset: bool = False) -> Sim:
+                    record_iters: int = 0, rw_period: int = 0, rw_reset: bool = False,
+                    walkers_per_wave: int = 0) -> Sim:
     """Build a Sim from a workloads.WEConfig."""
     net = network if network is not None else Network(cfg.net)
     return Sim(net, cfg.bin_coef, cfg.edges, tau=cfg.tau, m_targ=cfg.m_targ, seeds=cfg.seeds,
@@ -509,7 +518,7 @@ def sim_from_config(cfg, *, kernel: int = WE_KERNEL_AUTO, max_iters: Optional[in
                record_iters=record_iters, rw_period=rw_period, rw_reset=rw_reset,
                bin_coef2=getattr(cfg, "bin_coef2", None), edges2=getattr(cfg, "edges2", None),
                engine=getattr(cfg, "engine", "ssa"), leap_eps=getattr(cfg, "leap_eps", 0.03),
-               resample_rule=getattr(cfg, "resample_rule", 0))
+               resample_rule=getattr(cfg, "resample_rule", 0), walkers_per_wave=walkers_per_wave)
 
 
 def mlp_loss_grad(n_in: int, params, feat, x, y):
@@ -585,7 +594,7 @@ class Batch:
     persistent propagation launch per kernel variant (we_batch_create)."""
 
     def __init__(self, cfgs, *, max_iters: int, autotune_iters: int = 0,
-                 cache_path: Optional[str] = None, kernels=None):
+                 cache_path: Optional[str] = None, kernels=None, record_iters: int = 0):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("no HIP device: libwe.so runs on MI355X only")
@@ -611,15 +620,16 @@ class Batch:
                 k["edges2"] = np.ascontiguousarray(e2, np.float64)
             grids[i] = _Grid(len(k["edges"]) - 1, k["coef"].ctypes.data, k["edges"].ctypes.data,
                              0 if e2 is None else len(e2) - 1, _ptr(k.get("coef2")), _ptr(k.get("edges2")))
-            kern = WE_KERNEL_AUTO if kernels is None else int(kernels[i])
+            kern = WE_KERNEL_AUTO if kernels is None else kernels[i]
+            kern, wpw = (int(kern[0]), int(kern[1])) if isinstance(kern, tuple) else (int(kern), 0)
             params[i] = _Params(float(c.tau), int(c.m_targ), len(k["seeds"]), int(max_iters), kern,
                                 k["seeds"].ctypes.data, k["x0"].ctypes.data, int(bool(c.recycle)),
                                 _ptr(k["tgt"]), float(c.tgt_thr), _ptr(k["xrec"]),
                                 int(c.hist_species), int(c.hist_lo), int(c.hist_hi),
-                                0, k["joint"].ctypes.data, 1, 1, 0, 0, 0,
+                                0, k["joint"].ctypes.data, 1, 1, int(record_iters), 0, 0,
                                 {"ssa": 0, "tauleap": 1}[getattr(c, "engine", "ssa")],
                                 float(getattr(c, "leap_eps", 0.03)),
-                                int(getattr(c, "resample_rule", 0)))
+                                int(getattr(c, "resample_rule", 0)), wpw)
         nets = (C.c_void_p * n)(*[net.handle.value for net in self.networks])
         self.stream = torch.cuda.current_stream()
         h = C.c_void_p()
@@ -641,8 +651,15 @@ class Batch:
     def kernels(self):
         k = np.zeros(len(self.cfgs), np.int32)
         n = C.c_int32()
-        _check(load_library().we_batch_info(self.handle, C.byref(n), _ptr(k)))
+        _check(load_library().we_batch_info(self.handle, C.byref(n), _ptr(k), None))
         return k
+
+    def walkers_per_wave(self):
+        """Walkers per wave of every member's kernel: 64 lane, 2..32 group, 1 wave."""
+        w = np.zeros(len(self.cfgs), np.int32)
+        n = C.c_int32()
+        _check(load_library().we_batch_info(self.handle, C.byref(n), None, _ptr(w)))
+        return w
 
     def synchronize(self):
         for m in self.members:
@@ -658,3 +675,13 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def measure_peaks() -> dict:
+    """we_measure_peaks on torch's current stream: measured HBM (GB/s), LDS
+    (TB/s), FP64 (TFLOP/s) and int32 lane-operation (10^12/s) ceilings."""
+    import torch
+    pk = _Peaks()
+    _check(load_library().we_measure_peaks(C.c_void_p(torch.cuda.current_stream().cuda_stream), C.byref(pk)))
+    return {"hbm_gbs": pk.hbm_gbs, "lds_tbs": pk.lds_tbs, "fp64_tflops": pk.fp64_tflops,
+            "int32_tops": pk.int32_tops, "compute_units": pk.compute_units}

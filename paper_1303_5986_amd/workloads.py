@@ -539,3 +539,53 @@ def batch_configs(n_runs: int = 64, seed: int = 7, r_max: int = 3680, w_min: int
                             n_iters=n_iters, seeds=np.array([seed * 1000 + k], np.uint64),
                             hist_species=bs, hist_lo=0, hist_hi=-1))
     return out
+
+
+# --------------------------------------------------------------------------
+# The batched rare-event workload: the uneven batch above, each run given a
+# recycling target from pilot runs of its own.
+# --------------------------------------------------------------------------
+def batch_tau(events_per_walker: float, tau0: float = 0.01, target: float = 10.0,
+              lo: float = 0.01, hi: float = 5.0) -> float:
+    """Interval giving about `target` events per walker: tau0 scaled by
+    target / (events per walker-interval measured over a pilot at tau0),
+    clipped to [lo, hi] (the toggle's tau is likewise ~10 / a0)."""
+    return float(np.clip(tau0 * target / max(float(events_per_walker), 1e-3), lo, hi))
+
+
+def rare_target(x: np.ndarray, w: np.ndarray, tail: float = 1e-4):
+    """Recycling target from a relaxed pilot ensemble (states x[n, S],
+    weights w[n] summing to one): the coordinate species is the one with the
+    largest weighted mean count (ties: lowest id); the recycling state A is
+    the heaviest walker's state (ties: lowest slot); the threshold is the
+    smallest integer t >= c_A + 2 with pilot weight P(c >= t) <= tail.
+    Returns (species, x_A, threshold)."""
+    x = np.asarray(x, np.int64)
+    w = np.asarray(w, np.float64)
+    mean = (w[:, None] * x).sum(axis=0)
+    sp = int(np.flatnonzero(mean == mean.max())[0])
+    xa = x[int(np.argmax(w))].astype(np.int32)
+    c = x[:, sp]
+    t = int(xa[sp]) + 2
+    top = int(c.max()) + 1
+    while t < top and w[c >= t].sum() > tail:
+        t += 1
+    return sp, xa, t
+
+
+def rare_batch_config(base: WEConfig, tau: float, species: int, x_a: np.ndarray, thr: int,
+                      n_bins: int = 16) -> WEConfig:
+    """A run of the uneven batch turned into a first-passage problem: start
+    and recycle at x_A, target {x_species >= thr}, n_bins equal bins on the
+    species count between c_A and thr."""
+    S = base.net.S
+    coef = np.zeros(S, np.float64)
+    coef[species] = 1.0
+    ca = float(x_a[species])
+    out = WEConfig(name=base.name + "_rare", net=base.net, x0=np.asarray(x_a, np.int32).copy(), bin_coef=coef,
+                   edges=uniform_edges(ca, float(thr), n_bins), m_targ=base.m_targ, tau=float(tau),
+                   n_iters=base.n_iters, seeds=base.seeds.copy(), recycle=True, tgt_coef=coef.copy(),
+                   tgt_thr=float(thr), x_rec=np.asarray(x_a, np.int32).copy(), hist_species=species, hist_lo=0,
+                   hist_hi=-1)
+    out.a_thr = ca            # A region for committor labels: bin_coef . x <= c_A
+    return out

@@ -53,3 +53,32 @@ def test_more_than_one_gpu_is_refused():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
                        capture_output=True, text=True, timeout=120)
     assert "one GPU only" in r.stdout + r.stderr
+
+
+def test_rare_target_by_hand():
+    """The recycling target of the batched rare-event workload from a
+    pilot ensemble: species 0 has the larger weighted mean (0.2*9 + 0.3*2 =
+    2.4 against species 1's 0.2*3 + 0.5*1 + 0.3*2 = 1.7); A is the heaviest
+    walker (slot 1); the threshold is the smallest t >= c_A + 2 with
+    P(c >= t) <= tail."""
+    import numpy as np
+    x = np.array([[9, 3], [0, 1], [2, 2]])
+    w = np.array([0.2, 0.5, 0.3])
+    sp, xa, thr = wl.rare_target(x, w, tail=0.25)
+    assert sp == 0
+    assert list(xa) == [0, 1]
+    # c_A = 0: t = 2 has P(c >= 2) = 0.5 > 0.25; t = 3 has 0.2 <= 0.25
+    assert thr == 3
+    sp, xa, thr = wl.rare_target(x, w, tail=0.1)
+    assert thr == 10            # nothing is left at or above 10 (max count 9, P(c >= 10) = 0)
+    cfg = wl.rare_batch_config(wl.batch_configs(n_runs=2, n_iters=10)[1], 0.5, 0, np.array([4, 1] + [0] * 6, np.int32), 12)
+    assert cfg.recycle and cfg.tgt_thr == 12.0 and cfg.a_thr == 4.0
+    assert cfg.edges[0] == 4.0 and cfg.edges[-1] == 12.0 and len(cfg.edges) == 17
+    assert cfg.bin_coef[0] == 1.0 and cfg.bin_coef.sum() == 1.0
+
+
+def test_batch_tau_scales_to_ten_events():
+    assert wl.batch_tau(1.0) == 0.1
+    assert wl.batch_tau(100.0) == 0.01          # clipped below
+    assert wl.batch_tau(0.0) == 5.0             # clipped above
+    assert abs(wl.batch_tau(2.0, tau0=0.3) - 1.5) < 1e-15

@@ -91,7 +91,8 @@ def test_batch_autotune_writes_and_reuses_cache():
     assert "S1_R4" in text and "S6_R6" in text
     b2 = we.Batch(cfgs, max_iters=10, autotune_iters=3, cache_path=path)
     assert list(b2.kernels()) == list(k1)
-    assert all(k in (we.WE_KERNEL_LANE, we.WE_KERNEL_WAVE) for k in k1)
+    assert list(b2.walkers_per_wave()) == list(b1.walkers_per_wave())
+    assert all(k in (we.WE_KERNEL_LANE, we.WE_KERNEL_GROUP, we.WE_KERNEL_WAVE) for k in k1)
     b2.step(4)
     b2.synchronize()
 
@@ -151,8 +152,11 @@ def test_batch_learned_bins_equal_standalone_runs():
     for it in (0, 17, 29):
         gn, gx, go, grc = b.members[0].record(it)
         sn, sx, so, src = s0.record(it)
-        assert np.array_equal(gn, sn) and np.array_equal(gx, sx)
-        assert np.array_equal(go, so) and np.array_equal(grc, src)
+        assert np.array_equal(gn, sn)
+        for r in range(len(gn)):
+            k = gn[r]
+            assert np.array_equal(gx[r, :k], sx[r, :k]) and np.array_equal(go[r, :k], so[r, :k])
+            assert np.array_equal(grc[r, :k], src[r, :k])
     tmp = tempfile.mkdtemp(prefix="we_bcm_")
     solo = []
     for i, (c, m) in enumerate(zip(cfgs, b.members)):
