@@ -808,6 +808,63 @@ def experiment_paper_tails(args):
     print(json.dumps(out), flush=True)
 
 
+def experiment_walkers_per_wave(args):
+    """Events/s of every propagation kernel a network fits, across network
+    sizes: the lane kernel (64 walkers per wave, up to 64 reactions), the
+    group kernel with 32, 16, 8, 4 and 2 walkers per wave, and the wave
+    kernel (one).  Seeded random networks of R reactions (S = max(8,
+    R * 354 / 3680) species, counts log-uniform on [0, 20]), 32 runs x 16 bins
+    x 16 walkers, tau chosen for about ten events per walker; 20 untimed
+    intervals, then 40 timed with HIP events around the propagation launch
+    (the kernel's own time, the work the autotuner's choice is about)."""
+    import dataclasses
+    import torch
+    from paper_1303_5986_amd import we, workloads as wl
+    rows = []
+    for R in (16, 40, 100, 300, 1000, 3000):
+        S = max(8, int(round(R * 354 / 3680)))
+        net = wl.random_network(4000 + R, S, R)
+        x0 = wl.log_uniform_counts(np.random.default_rng(4001 + R), S, hi=20)
+        sp = int(np.argmax(x0))
+        coef = np.zeros(S)
+        coef[sp] = 1.0
+        cfg = wl.WEConfig(name=f"wpw{R}", net=net, x0=x0, bin_coef=coef, edges=wl.uniform_edges(0.0, 32.0, 16),
+                          m_targ=16, tau=0.01, n_iters=80, seeds=np.arange(1, 33, dtype=np.uint64))
+        # calibrate tau to about ten events per walker on the wave kernel
+        sim = we.sim_from_config(cfg, kernel=we.WE_KERNEL_WAVE, max_iters=20)
+        sim.step(10)
+        sim.synchronize()
+        ev, sg, _ = sim.counters()
+        cfg = dataclasses.replace(cfg, tau=wl.batch_tau(ev / max(sg, 1)))
+        cands = []
+        if S <= 32 and R <= 64:
+            cands.append(("lane", we.WE_KERNEL_LANE, 0))
+        for wpw in (32, 16, 8, 4, 2):
+            if (wpw * S) <= 4096:
+                cands.append((f"group{wpw}", we.WE_KERNEL_GROUP, wpw))
+        cands.append(("wave", we.WE_KERNEL_WAVE, 0))
+        row = {"reactions": R, "species": S, "tau": cfg.tau}
+        for name, k, wpw in cands:
+            sim = we.sim_from_config(cfg, kernel=k, walkers_per_wave=wpw, max_iters=80)
+            sim.step(20)
+            sim.synchronize()
+            e0, _, _ = sim.counters()
+            sim.profile(True)
+            sim.step(40)
+            sim.synchronize()
+            ms_ssa, _, _, _ = sim.profile_read()
+            e1, _, _ = sim.counters()
+            row[name] = {"events_per_s": (e1 - e0) / (ms_ssa * 1e-3), "ms_per_launch": ms_ssa / 40,
+                         "kernel": sim.propagation_kernel()}
+        best = max((n for n, _, _ in cands), key=lambda n: row[n]["events_per_s"])
+        row["fastest"] = best
+        rows.append(row)
+        print(f"R={R}: " + ", ".join(f"{n} {row[n]['events_per_s']:.2e}" for n, _, _ in cands) + f" -> {best}",
+              file=sys.stderr, flush=True)
+    print(json.dumps({"metric": "propagation events/s by walkers per wave", "runs": 32, "bins": 16,
+                      "walkers_per_bin": 16, "rows": rows}), flush=True)
+
+
 def _burn_in(sim, warmup: int, chunk: int = 25, min_iters: int = 100, cap: int = 1000) -> int:
     """Untimed steps until the workload is in its steady window: at least
     max(warmup, min_iters) steps, then until two successive chunks of `chunk`
@@ -940,7 +997,7 @@ def main():
                          "(reference kernel for scaling the HBM byte counters)")
     ap.add_argument("--experiment", default="",
                     choices=["", "toggle_mfpt", "batch", "schlogl_rw", "switch_mfpt", "tauleap", "rare_batch",
-                             "paper_tails"])
+                             "paper_tails", "walkers_per_wave"])
     ap.add_argument("--switch-runs", type=int, default=64, help="replicas in the switch experiment")
     ap.add_argument("--rw-runs", type=int, default=32,
                     help="replicas in the reweighting experiment")
@@ -981,6 +1038,9 @@ def main():
         return
     if args.experiment == "paper_tails":
         experiment_paper_tails(args)
+        return
+    if args.experiment == "walkers_per_wave":
+        experiment_walkers_per_wave(args)
         return
     if args.experiment == "schlogl_rw":
         experiment_schlogl_rw(args)

@@ -84,6 +84,7 @@ struct we_sim {
     SimArgs args{};
     int32_t kernel = WE_KERNEL_LANE;
     int32_t group_lanes = 0;        // lanes per walker of the group kernel
+    int32_t *rs_binfo = nullptr;    // [n_runs][3][NB] bin-parallel resampling (workspace)
     int32_t S = 0, NB = 0, M = 0, n_runs = 0, cap = 0, max_iters = 0;
     double tau = 0.0;
     int32_t iter = 0;

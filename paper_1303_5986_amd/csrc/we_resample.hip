@@ -55,6 +55,9 @@
 // Cursor rows for placing walkers in parallel: one row of n_bins per wave, as
 // long as the rows hold at most this many counters.
 #define RESAMPLE_PLACE_INTS 4096
+// Bin-parallel resampling: runs fewer than this, bins at least this many.
+#define RESAMPLE_BIN_PARALLEL_RUNS 256
+#define RESAMPLE_BIN_PARALLEL_BINS 32
 // Threads per run: up to 16 waves, so up to 16 bins are split/merged at
 // once.  With many runs the grid fills the chip anyway and smaller blocks
 // cost less to start, so launches with at least RESAMPLE_MANY_RUNS blocks use
@@ -686,9 +689,50 @@ __device__ void merge_bin(const RunWork<Idx> &wk, int32_t p0, int32_t nb, int32_
 
 }  // namespace
 
+// One bin's split/merge (and its row of the reweighting flux matrix) on the
+// calling wave: the walkers at positions [p0, p0 + nb) of wk, the output at
+// slots [o0, o0 + M).
+template <class Idx>
+__device__ void resample_bin(const SimArgs &a, const RunWork<Idx> &wk, const BinOut &out, int32_t run, int32_t b,
+                             int32_t nb, int32_t p0, int32_t o0, uint32_t iter, uint32_t k0, uint32_t k1,
+                             bool rw_acc, int lane) {
+    const int32_t NB = a.n_bins, M = a.m_targ;
+    if (rw_acc) rw_flux_bin(a.rw_F + ((size_t)run * NB + b) * NB, wk, p0, nb, lane);
+    if (a.rs_rule == 1) {
+        if (nb <= 64) equalize_bin_lanes(wk, p0, nb, M, b, o0, out, iter, k0, k1, lane);
+        else merge_bin<Idx, true>(wk, p0, nb, M, b, o0, out, iter, k0, k1, lane);
+    } else if (nb == M) {
+        for (int32_t q = lane; q < nb; q += 64) {
+            out.orig[o0 + q] = wk.list[p0 + q];
+            out.wn[o0 + q] = wk.w[p0 + q];
+            out.obin[o0 + q] = b;
+        }
+    } else if (nb < M) {
+        if (nb <= 64) split_bin_lanes(wk, p0, nb, M, b, o0, out, lane);
+        else split_bin(wk, p0, nb, M, b, o0, out, lane);
+    } else {
+        if (nb <= 64) merge_bin_lanes(wk, p0, nb, M, b, o0, out, iter, k0, k1, lane);
+        else merge_bin<Idx, false>(wk, p0, nb, M, b, o0, out, iter, k0, k1, lane);
+    }
+}
+
+// The run's working arrays in device memory (see resample_run_t).
+__device__ __forceinline__ RunWork<int32_t> global_work(const SimArgs &a, size_t base) {
+    RunWork<int32_t> wk;
+    wk.w = a.s_w + base;
+    wk.list = a.s_list + base;
+    wk.tag = reinterpret_cast<uint16_t *>(a.s_cnt + base);
+    wk.qa = a.s_bin + base;
+    wk.aux = a.s_cnt + base;
+    return wk;
+}
+
+// binfo != NULL (device arrays only, use_lds 0): stop after placement and
+// staging, and leave each bin's count, first position and first output slot
+// in binfo[run][3][n_bins] for we_resample_bins_kernel.
 template <class Idx>
 __device__ void resample_run_t(const SimArgs &a, const double *__restrict__ w_cur, double *__restrict__ w_nxt,
-                               int32_t use_lds, int32_t run, unsigned char *lds) {
+                               int32_t use_lds, int32_t run, unsigned char *lds, int32_t *__restrict__ binfo) {
     const int32_t tid = threadIdx.x, nthr = blockDim.x;
     const int lane = tid & 63, wave = tid >> 6, n_waves = nthr >> 6;
     const int32_t NB = a.n_bins, M = a.m_targ, cap = a.cap;
@@ -723,11 +767,12 @@ __device__ void resample_run_t(const SimArgs &a, const double *__restrict__ w_cu
         // global: the tag array in the first half of the s_cnt rows, the
         // queue over s_bin (read only before the first barrier), the aux
         // array over s_cnt once placement is done
-        wk.w = a.s_w + base;
-        wk.list = a.s_list + base;
-        wk.tag = reinterpret_cast<uint16_t *>(a.s_cnt + base);
-        wk.qa = reinterpret_cast<Idx *>(a.s_bin + base);
-        wk.aux = reinterpret_cast<Idx *>(a.s_cnt + base);
+        const RunWork<int32_t> g = global_work(a, base);
+        wk.w = g.w;
+        wk.list = g.list;
+        wk.tag = g.tag;
+        wk.qa = reinterpret_cast<Idx *>(g.qa);
+        wk.aux = reinterpret_cast<Idx *>(g.aux);
     }
 
     const int32_t n_chunks = (n + 63) >> 6;
@@ -859,6 +904,18 @@ __device__ void resample_run_t(const SimArgs &a, const double *__restrict__ w_cu
     }
     __syncthreads();
 
+    if (binfo) {
+        // bin-parallel mode: leave the bins to we_resample_bins_kernel
+        int32_t *bi = binfo + (size_t)run * 3 * NB;
+        for (int32_t b = tid; b < NB; b += nthr) {
+            bi[b] = cnt[b];
+            bi[NB + b] = start[b];
+            bi[2 * NB + b] = ostart[b];
+        }
+        if (tid == 0) a.n_walk[run] = ostart[NB];
+        return;
+    }
+
     // split / merge: one wave per bin
     const uint64_t seed = a.seeds[run];
     const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
@@ -869,24 +926,7 @@ __device__ void resample_run_t(const SimArgs &a, const double *__restrict__ w_cu
     for (int32_t b = wave; b < NB; b += n_waves) {
         const int32_t nb = uni(cnt[b]);
         if (nb == 0) continue;
-        const int32_t p0 = uni(start[b]), o0 = uni(ostart[b]);
-        if (rw_acc) rw_flux_bin(a.rw_F + ((size_t)run * NB + b) * NB, wk, p0, nb, lane);
-        if (a.rs_rule == 1) {
-            if (nb <= 64) equalize_bin_lanes(wk, p0, nb, M, b, o0, out, iter, k0, k1, lane);
-            else merge_bin<Idx, true>(wk, p0, nb, M, b, o0, out, iter, k0, k1, lane);
-        } else if (nb == M) {
-            for (int32_t q = lane; q < nb; q += 64) {
-                out.orig[o0 + q] = wk.list[p0 + q];
-                out.wn[o0 + q] = wk.w[p0 + q];
-                out.obin[o0 + q] = b;
-            }
-        } else if (nb < M) {
-            if (nb <= 64) split_bin_lanes(wk, p0, nb, M, b, o0, out, lane);
-            else split_bin(wk, p0, nb, M, b, o0, out, lane);
-        } else {
-            if (nb <= 64) merge_bin_lanes(wk, p0, nb, M, b, o0, out, iter, k0, k1, lane);
-            else merge_bin<Idx, false>(wk, p0, nb, M, b, o0, out, iter, k0, k1, lane);
-        }
+        resample_bin(a, wk, out, run, b, nb, uni(start[b]), uni(ostart[b]), iter, k0, k1, rw_acc, lane);
     }
     __syncthreads();
     if (tid == 0) a.n_walk[run] = ostart[NB];
@@ -894,15 +934,40 @@ __device__ void resample_run_t(const SimArgs &a, const double *__restrict__ w_cu
 
 __device__ __forceinline__ void resample_run(const SimArgs &a, const double *__restrict__ w_cur,
                                              double *__restrict__ w_nxt, int32_t use_lds, int32_t run,
-                                             unsigned char *lds) {
-    if (use_lds) resample_run_t<uint16_t>(a, w_cur, w_nxt, 1, run, lds);
-    else resample_run_t<int32_t>(a, w_cur, w_nxt, 0, run, lds);
+                                             unsigned char *lds, int32_t *binfo = nullptr) {
+    if (use_lds) resample_run_t<uint16_t>(a, w_cur, w_nxt, 1, run, lds, nullptr);
+    else resample_run_t<int32_t>(a, w_cur, w_nxt, 0, run, lds, binfo);
 }
 
 __global__ __launch_bounds__(RESAMPLE_THREADS) void we_resample_kernel(SimArgs a, const double *__restrict__ w_cur,
-                                                          double *__restrict__ w_nxt, int32_t use_lds) {
+                                                          double *__restrict__ w_nxt, int32_t use_lds,
+                                                          int32_t *__restrict__ binfo) {
     extern __shared__ __align__(16) unsigned char lds[];
-    resample_run(a, w_cur, w_nxt, use_lds, blockIdx.x, lds);
+    resample_run(a, w_cur, w_nxt, use_lds, blockIdx.x, lds, binfo);
+}
+
+// Bin-parallel split/merge after we_resample_kernel's placement: grid
+// (ceil(n_bins / 4), runs), one wave per bin, the same per-bin steps on the
+// run's arrays in device memory; bins of one run write disjoint ranges.
+__global__ __launch_bounds__(256) void we_resample_bins_kernel(SimArgs a, double *__restrict__ w_nxt,
+                                                               const int32_t *__restrict__ binfo) {
+    const int lane = threadIdx.x & 63;
+    const int32_t run = blockIdx.y, NB = a.n_bins;
+    const int32_t b = (int32_t)blockIdx.x * 4 + (int32_t)(threadIdx.x >> 6);
+    if (b >= NB) return;                       // uniform over the wave
+    const int32_t *bi = binfo + (size_t)run * 3 * NB;
+    const int32_t nb = uni(bi[b]);
+    if (nb == 0) return;
+    const size_t base = (size_t)run * a.cap;
+    const RunWork<int32_t> wk = global_work(a, base);
+    BinOut out;
+    out.orig = a.origin + base;
+    out.obin = a.bin + base;
+    out.wn = w_nxt + base;
+    const uint32_t iter = *a.iter_dev;
+    const uint64_t seed = a.seeds[run];
+    resample_bin(a, wk, out, run, b, nb, uni(bi[NB + b]), uni(bi[2 * NB + b]), iter, (uint32_t)seed,
+                 (uint32_t)(seed >> 32), a.rw_F != nullptr && iter >= 1u, lane);
 }
 
 // New state rows from their parents: one lane per copy number.
@@ -1058,14 +1123,32 @@ int32_t resample_place_rows(const SimArgs &a, int64_t blocks) {
     return rows;
 }
 
+// Bin-parallel resampling pays when the runs alone leave most of the chip idle
+// and each of a run's waves would otherwise take four bins or more in turn
+// (measured, one MI355X: 16 toggle runs x 64 bins 0.045 -> 0.033 ms, 64
+// switch runs x 465 bins 0.211 -> 0.202 ms; one run of 50 bins 0.063 ->
+// 0.067 ms, so not there: its staging then goes to device memory).
+bool resample_bins_parallel(const SimArgs &a) {
+    const int64_t waves = resample_threads(a.n_runs) / 64;
+    return a.n_runs < RESAMPLE_BIN_PARALLEL_RUNS && a.n_bins >= RESAMPLE_BIN_PARALLEL_BINS &&
+           a.n_bins >= 4 * waves;
+}
+
 hipError_t launch_resample(const SimArgs &a, int32_t *x_cur, const double *w_cur, int32_t *x_nxt,
-                           double *w_nxt, hipStream_t st) {
-    const bool use_lds = resample_uses_lds(a);
+                           double *w_nxt, int32_t *binfo, hipStream_t st) {
+    const bool split = binfo && resample_bins_parallel(a);
+    const bool use_lds = !split && resample_uses_lds(a);
     const size_t shmem = resample_lds_bytes(a, use_lds);
     hipLaunchKernelGGL(we_resample_kernel, dim3(a.n_runs), dim3(resample_threads(a.n_runs)), shmem, st, a, w_cur, w_nxt,
-                       use_lds ? 1 : 0);
+                       use_lds ? 1 : 0, split ? binfo : nullptr);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    if (split) {
+        hipLaunchKernelGGL(we_resample_bins_kernel, dim3((unsigned)((a.n_bins + 3) / 4), (unsigned)a.n_runs), dim3(256),
+                           0, st, a, w_nxt, binfo);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
     const int64_t total = (int64_t)a.n_runs * a.cap * a.S;
     hipLaunchKernelGGL(we_gather_rows_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st,
                        a, x_cur, x_nxt);

@@ -31,7 +31,7 @@ bool wave_kernel_fits(int32_t S, int32_t R);
 hipError_t launch_recycle_bin(const SimArgs &a, int32_t *x_cur, bool grid_bins, hipStream_t st);
 int32_t resample_place_rows(const SimArgs &a, int64_t blocks);
 hipError_t launch_resample(const SimArgs &a, int32_t *x_cur, const double *w_cur, int32_t *x_nxt,
-                           double *w_nxt, hipStream_t st);
+                           double *w_nxt, int32_t *binfo, hipStream_t st);
 hipError_t launch_advance(const SimArgs &a, hipStream_t st);
 hipError_t launch_observe(const SimArgs &a, const int32_t *xs, const double *ws, hipStream_t st,
                           bool *advanced);
@@ -298,7 +298,7 @@ extern "C" void we_destroy_network(we_network *net) {
 namespace {
 
 struct Layout {
-    size_t off[32];
+    size_t off[48];
     size_t total = 0;
     int n = 0;
     size_t add(size_t bytes) {
@@ -312,7 +312,8 @@ struct Layout {
 enum Piece { P_X0, P_X1, P_W0, P_W1, P_BIN, P_ORIG, P_N, P_EVW, P_FLUX, P_EVI, P_SBIN, P_SREC,
              P_SLIST, P_SW, P_SCNT, P_HIST, P_SEEDS, P_BCOEF, P_EDGES, P_TCOEF, P_XREC, P_ERR,
              P_SEG, P_ITER, P_JHIST, P_SCHED, P_SEGLIST, P_QUEUE, P_NZ, P_RWF, P_RWR, P_RWS,
-             P_COUNT };
+             P_RSB, P_COUNT };
+static_assert(P_COUNT <= 48, "Layout holds at most 48 pieces");
 
 // Counter replicas per bin of the work-queue statistics: about 16 runs per
 // replica (replica run % rep), enough to spread the runs' atomics without a
@@ -351,6 +352,7 @@ Layout make_layout(int32_t S, int32_t NB, int32_t n_bins2, int32_t n_runs, int32
     L.add(rw ? 8 * (size_t)n_runs * nb2 : 0);
     L.add(rw && !rw_solve_in_lds(NB) ? 8 * (size_t)n_runs * nb2 : 0);
     L.add(rw ? 4 * 2 * (size_t)n_runs : 0);
+    L.add(4 * 3 * (size_t)n_runs * NB);          // bin-parallel resampling: count, start, output start
     return L;
 }
 
@@ -587,6 +589,7 @@ extern "C" we_status we_init(const we_network *net, const we_grid *g, const we_p
     a.seg_cur = a.seg_off + a.seg_rep * NB;
     a.seg = (int2 *)at(P_SEGLIST);
     a.queue = (uint32_t *)at(P_QUEUE);
+    s->rs_binfo = (int32_t *)at(P_RSB);
     a.n_joint = p->n_joint;
     a.joint_bins = p->n_joint > 0 ? p->joint_bins : 1;
     a.joint_width = p->n_joint > 0 ? p->joint_width : 1;
@@ -709,7 +712,7 @@ we_status we_sim_bookkeeping(we_sim *s, hipStream_t st, hipEvent_t *ev) {
         e = committor_bin(s, s->x[c], st);
         if (e != hipSuccess) return hip_fail(e, "committor bin launch");
     }
-    e = launch_resample(a, s->x[c], s->w[c], s->x[nx], s->w[nx], st);
+    e = launch_resample(a, s->x[c], s->w[c], s->x[nx], s->w[nx], s->rs_binfo, st);
     if (e != hipSuccess) return hip_fail(e, "resample launch");
     if (a.rw_period > 0) {
         e = launch_reweight(a, s->w[nx], st);
