@@ -182,7 +182,11 @@ def experiment_toggle_mfpt(args):
     ref_iters = args.ref_iters
     bf = dataclasses.replace(base, edges=np.array([-1e9, 1e9]), m_targ=1024,
                              seeds=np.arange(1001, 1065, dtype=np.uint64))
-    simb = we.sim_from_config(bf, kernel=we.WE_KERNEL_LANE, max_iters=ref_iters)
+    # each sim on the kernel the autotuner picks for its shape (the same for
+    # plain and learned bins)
+    kb = we.autotune(bf)
+    kern = we.autotune(base)
+    simb = we.sim_from_config(bf, kernel=kb[0], walkers_per_wave=kb[1], max_iters=ref_iters)
     simb.graph_capture(20)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -196,7 +200,7 @@ def experiment_toggle_mfpt(args):
             group: int = 0):
         cfg = base if group == 0 else dataclasses.replace(
             base, seeds=base.seeds + np.uint64(group * base.seeds.size))
-        sim = we.sim_from_config(cfg, kernel=we.WE_KERNEL_LANE, max_iters=total,
+        sim = we.sim_from_config(cfg, kernel=kern[0], walkers_per_wave=kern[1], max_iters=total,
                                  record_iters=record_iters if learned else 0)
         times, iters = [], []
         gpu = 0.0
@@ -273,6 +277,7 @@ def experiment_toggle_mfpt(args):
     return {"metric": "GPU-seconds to MFPT rel-err 5%, learned vs plain bins",
            "workload": "toggle (seed 101), 16 replicas x 64 bins x 16 walkers, tau 0.7",
            "resample_rule": base.resample_rule, "groups": groups,
+           "kernel": {"we_iterations": list(kern), "reference": list(kb)},
            "plain_coordinate": args.plain_coord,
            "reference": {"mfpt": ref_mfpt, "sem_rel": ref_sem / ref_flux, "kind":
                          "GPU brute force: 64 runs x 1024 walkers in one bin, recycling",
@@ -1181,7 +1186,7 @@ def main():
             "learned_bins_gpu_s": tg["learned"]["gpu_s_to_5pct"],
             "plain_final_rel_err": tg["plain"]["final_rel_err"],
             "learned_final_rel_err": tg["learned"]["final_rel_err"],
-            "groups_of_16": tg["groups"],
+            "groups_of_16": tg["groups"], "kernel": tg["kernel"],
             "learned_includes": "plain-bin record phase and training"}
     print(json.dumps(out), flush=True)
 

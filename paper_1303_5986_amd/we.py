@@ -685,3 +685,18 @@ def measure_peaks() -> dict:
     _check(load_library().we_measure_peaks(C.c_void_p(torch.cuda.current_stream().cuda_stream), C.byref(pk)))
     return {"hbm_gbs": pk.hbm_gbs, "lds_tbs": pk.lds_tbs, "fp64_tflops": pk.fp64_tflops,
             "int32_tops": pk.int32_tops, "compute_units": pk.compute_units}
+
+
+def autotune(cfg, iters: int = 3, cache_path: Optional[str] = None):
+    """(kernel, walkers_per_wave) that the batch autotuner picks for one
+    configuration: every kernel its network fits (lane, group with 32..2
+    walkers per wave, wave) timed on pilot sims of the configuration's shape
+    for `iters` intervals; walkers_per_wave is 0 unless the group kernel
+    wins."""
+    b = Batch([cfg], max_iters=2, autotune_iters=int(iters), cache_path=cache_path)
+    try:
+        k, w = int(b.kernels()[0]), int(b.walkers_per_wave()[0])
+    finally:
+        b.close()
+    return k, (w if k == WE_KERNEL_GROUP else 0)
+
