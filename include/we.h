@@ -318,6 +318,12 @@ WE_API we_status we_counters(we_sim *s, int64_t *events, int64_t *segments,
  * [first, first+count).  Synchronous. */
 WE_API we_status we_events_series(we_sim *s, int32_t first, int32_t count, int64_t *out);
 
+/* Reactions fired by each walker of `run` during the last interval, in the
+ * slot order that interval started with: out[cap] (host), *n = walkers
+ * propagated (entries past it are stale).  Synchronous.  A diagnostic of
+ * load balance: an interval lasts as long as its busiest walker. */
+WE_API we_status we_walker_events(we_sim *s, int32_t run, int32_t *n, uint32_t *out);
+
 /* ---------------------------------------------------------------- reweighting
  * Steady-state reweighting (Sec. II.B.2, Eq. ss), on when rw_period > 0.
  * Flux matrix: F[i][j] adds, every interval after the first and walker by

@@ -928,6 +928,21 @@ extern "C" we_status we_events_series(we_sim *s, int32_t first, int32_t count, i
     return WE_OK;
 }
 
+extern "C" we_status we_walker_events(we_sim *s, int32_t run, int32_t *n, uint32_t *out) {
+    if (!s || !n || !out) return fail(WE_EINVAL, "NULL argument");
+    if (run < 0 || run >= s->n_runs) return fail(WE_EINVAL, "run out of range");
+    if (s->iter < 1) return fail(WE_ESTATE, "no interval propagated yet");
+    we_status st = read_err(s);
+    if (st != WE_OK) return st;
+    const int32_t last = s->iter - 1;
+    int32_t nn = 0;
+    if (last < s->max_iters)
+        HIP_TRY(hipMemcpy(&nn, s->args.seg_iter + (size_t)run * s->max_iters + last, 4, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(out, s->args.ev_walker + (size_t)run * s->cap, 4 * (size_t)s->cap, hipMemcpyDeviceToHost));
+    *n = nn;
+    return WE_OK;
+}
+
 extern "C" we_status we_rw_flux_matrix(we_sim *s, int32_t run, double *out) {
     if (!s || !out) return fail(WE_EINVAL, "NULL argument");
     if (!s->args.rw_F) return fail(WE_EINVAL, "reweighting is off");

@@ -33,7 +33,7 @@ EXPORTED = [
     "we_train_committor", "we_use_committor_bins", "we_committor_eval", "we_committor_state",
     "we_record_labels", "we_get_record", "we_mlp_loss_grad", "we_mlp_loss_grad_noalloc", "we_adam_step",
     "we_batch_create", "we_batch_step", "we_batch_graph_capture", "we_batch_graph_replay",
-    "we_batch_sim", "we_batch_info", "we_batch_destroy", "we_measure_peaks",
+    "we_batch_sim", "we_batch_info", "we_batch_destroy", "we_measure_peaks", "we_walker_events",
     "we_set_bins", "we_save", "we_checkpoint_inspect", "we_load", "we_propagation_kernel",
     "we_destroy", "we_last_error",
 ]
@@ -153,6 +153,7 @@ def load_library(path: str = LIB_PATH):
     L.we_batch_sim.restype = vp
     L.we_batch_info.argtypes = [vp, P(i32), vp, vp]
     L.we_measure_peaks.argtypes = [vp, vp]
+    L.we_walker_events.argtypes = [vp, i32, P(i32), vp]
     L.we_batch_destroy.argtypes = [vp]
     L.we_batch_destroy.restype = None
     L.we_set_bins.argtypes = [vp, vp]
@@ -419,6 +420,13 @@ class Sim:
         ev, sg, it = C.c_int64(), C.c_int64(), C.c_int32()
         _check(load_library().we_counters(self.handle, C.byref(ev), C.byref(sg), C.byref(it)))
         return ev.value, sg.value, it.value
+
+    def walker_events(self, run: int) -> np.ndarray:
+        """Reactions fired by each walker of `run` in the last interval."""
+        out = np.zeros(self.cap, np.uint32)
+        n = C.c_int32(0)
+        _check(load_library().we_walker_events(self.handle, int(run), C.byref(n), _ptr(out)))
+        return out[: n.value]
 
     def events_series(self, first: int = 0, count: Optional[int] = None) -> np.ndarray:
         if count is None:
