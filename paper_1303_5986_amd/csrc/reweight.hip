@@ -246,11 +246,16 @@ __global__ __launch_bounds__(RW_THREADS) void we_reweight_kernel(SimArgs a, doub
                 }
                 __syncthreads();
                 if (misc[3]) break;
-                for (size_t t = tid; t < (size_t)m * m; t += nthr) {
-                    const int32_t i = (int32_t)(t / m), j = (int32_t)(t - (size_t)i * m);
+                // one row per wave: rows with r(i -> m) = 0 are skipped whole
+                // (the rates join neighbouring bins only, so most rows are, and
+                // the elimination keeps that band); each entry gets the same
+                // single update as before, so the result is unchanged
+                const int32_t n_waves = nthr >> 6;
+                for (int32_t i = wave; i < m; i += n_waves) {
                     const double rim = R[(size_t)i * na + m];
-                    if (i != j && rim != 0.0)
-                        R[(size_t)i * na + j] = R[(size_t)i * na + j] + rim * R[(size_t)m * na + j];
+                    if (rim == 0.0) continue;
+                    for (int32_t j = lane; j < m; j += 64)
+                        if (j != i) R[(size_t)i * na + j] = R[(size_t)i * na + j] + rim * R[(size_t)m * na + j];
                 }
                 __syncthreads();
             }
