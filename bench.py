@@ -517,9 +517,11 @@ def experiment_batch(args):
     tb = time.perf_counter() - t0
     evb = sum(m.counters()[0] for m in b.members) - ev0
     kernels = b.kernels().tolist()
+    wpw = b.walkers_per_wave().tolist()
 
     # the same runs as independent sims, each launched on its own, in turn
-    sims = [we.sim_from_config(c, kernel=int(k), max_iters=W + 2 * K) for c, k in zip(cfgs, kernels)]
+    sims = [we.sim_from_config(c, kernel=int(k), walkers_per_wave=int(w) if int(k) == we.WE_KERNEL_GROUP else 0,
+                               max_iters=W + 2 * K) for c, k, w in zip(cfgs, kernels, wpw)]
     for s in sims:
         s.step(W)
     for s in sims:
@@ -540,7 +542,8 @@ def experiment_batch(args):
            "batched": {"events_per_s": evb / tb, "we_iters_per_s": K / tb, "ms_per_step": tb * 1e3 / K},
            "sequential": {"events_per_s": evs / ts, "we_iters_per_s": K / ts, "ms_per_step": ts * 1e3 / K},
            "speedup": ts / tb, "events_equal": bool(evb == evs),
-           "kernels": {"lane": kernels.count(1), "wave": kernels.count(2)},
+           "kernels": {"lane": kernels.count(1), "group": kernels.count(3), "wave": kernels.count(2)},
+           "walkers_per_wave": wpw,
            "autotune_s": tune_s}
     print(json.dumps(out), flush=True)
 
