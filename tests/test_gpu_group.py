@@ -151,3 +151,40 @@ def test_autotuner_times_group_variants():
     b.synchronize()
     b2 = we.Batch(cfgs, max_iters=10, autotune_iters=2, cache_path=path)
     assert int(b2.kernels()[0]) == k and int(b2.walkers_per_wave()[0]) == w
+
+
+def test_autotune_helper_and_walker_events():
+    """we.autotune returns a kernel the configuration runs on; the per-walker
+    event counts of an interval sum to the interval's events (run 0) and
+    cover every walker propagated."""
+    we = _we()
+    cfg = wl.toggle_config(n_runs=2, n_bins=16, m_targ=8, n_iters=10)
+    k, w = we.autotune(cfg, iters=2)
+    assert k in (we.WE_KERNEL_LANE, we.WE_KERNEL_GROUP, we.WE_KERNEL_WAVE)
+    assert (w in (2, 4, 8, 16, 32)) if k == we.WE_KERNEL_GROUP else w == 0
+    sim = we.sim_from_config(cfg, kernel=k, walkers_per_wave=w, max_iters=10)
+    sim.step(3)
+    sim.synchronize()
+    n_prev = len(sim.walkers(0)[1])
+    sim.step(1)
+    sim.synchronize()
+    ev = sim.walker_events(0)
+    assert len(ev) == n_prev
+    per_run = sim.counters()[0]
+    total = sum(int(sim.walker_events(r).sum()) for r in range(2))
+    assert total == int(sim.events_series(3, 1)[0])
+    assert per_run >= total
+
+
+def test_measured_peaks_are_plausible():
+    """The ceilings measured on the device lie within a factor of two of the
+    datasheet figures the rooflines use (HBM 8 TB/s, LDS 78.6 TB/s, FP64
+    78.6 TFLOP/s, int32 lane operations 39.3e12/s at 2.4 GHz)."""
+    we = _we()
+    pk = we.measure_peaks()
+    _say(f"   measured {pk}")
+    assert pk["compute_units"] >= 1
+    assert 1000 < pk["hbm_gbs"] < 16000
+    assert 39 < pk["lds_tbs"] < 160
+    assert 39 < pk["fp64_tflops"] < 160
+    assert 19 < pk["int32_tops"] < 80
