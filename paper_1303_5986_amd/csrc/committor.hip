@@ -404,39 +404,70 @@ __global__ __launch_bounds__(256) void cm_eval_kernel(const float *__restrict__ 
 
 // Equal-count edges in logit space: edge b is the upper end of the cell where
 // the cumulative count first reaches b*n/nb; edges stay strictly increasing.
-__global__ void cm_edges_kernel(const uint32_t *__restrict__ qhist, int32_t n, int32_t nb, double *__restrict__ edges,
-                                int32_t mode) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// One block of 1024 threads: thread t owns cells [64t, 64t+64); a block scan
+// of the threads' totals gives each its starting count, each thread marks
+// the edges (or quantile cells) its cells reach first, and thread 0 writes
+// the edges in order (the nudges of edges sharing a cell are sequential).
+#define CM_EDGE_THREADS 1024
+#define CM_EDGE_MAX_BINS 8192
+__global__ __launch_bounds__(CM_EDGE_THREADS) void cm_edges_kernel(const uint32_t *__restrict__ qhist, int32_t n,
+                                                                  int32_t nb, double *__restrict__ edges,
+                                                                  int32_t mode) {
+    constexpr int32_t PER = Q_HIST / CM_EDGE_THREADS;
+    __shared__ int64_t part[CM_EDGE_THREADS];
+    __shared__ int32_t cellof[CM_EDGE_MAX_BINS];
+    __shared__ int32_t q_lo, q_hi;
+    const int32_t t = threadIdx.x;
+    int64_t own = 0;
+    for (int32_t i = 0; i < PER; ++i) own += qhist[t * PER + i];
+    part[t] = own;
+    if (t == 0) {
+        q_lo = -1;
+        q_hi = -1;
+    }
+    for (int32_t b = t; b < CM_EDGE_MAX_BINS; b += CM_EDGE_THREADS) cellof[b] = -1;   // not reached
+    __syncthreads();
+    for (int32_t d = 1; d < CM_EDGE_THREADS; d <<= 1) {     // inclusive scan of the totals
+        const int64_t v = t >= d ? part[t - d] : 0;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    int64_t cum = part[t] - own;
+    const int64_t N = n > 0 ? (int64_t)n : 1;
+    for (int32_t i = 0; i < PER; ++i) {
+        const int32_t c = t * PER + i;
+        const int64_t prev = cum;
+        cum += qhist[c];
+        if (cum == prev) continue;
+        if (mode == 1) {
+            if (prev * 200 < N && cum * 200 >= N) q_lo = c;
+            if (prev * 200 < N * 199 && cum * 200 >= N * 199) q_hi = c;
+        } else {
+            // edges b with prev*nb < b*n <= cum*nb start in this cell
+            const int64_t b_from = prev * nb / N + 1, b_to = cum * nb / N;
+            for (int64_t b = b_from < 1 ? 1 : b_from; b <= b_to && b < nb; ++b) cellof[b] = c;
+        }
+    }
+    __syncthreads();
+    if (t != 0) return;
     const double cell = 2.0 * (double)Z_SPAN / (double)Q_HIST;
     const double nudge = cell / 64.0;
     edges[0] = -(double)Z_SPAN;
     if (mode == 1) {
         // uniform in the logit between the 0.5% and 99.5% quantiles of the data
-        int64_t cum = 0;
-        double zlo = -(double)Z_SPAN, zhi = (double)Z_SPAN;
-        bool have_lo = false;
-        for (int32_t c = 0; c < Q_HIST; ++c) {
-            cum += qhist[c];
-            if (!have_lo && cum * 200 >= (int64_t)n) { zlo = -(double)Z_SPAN + c * cell; have_lo = true; }
-            if (cum * 200 >= (int64_t)n * 199) { zhi = -(double)Z_SPAN + (c + 1) * cell; break; }
-        }
+        const double zlo = q_lo >= 0 ? -(double)Z_SPAN + q_lo * cell : -(double)Z_SPAN;
+        double zhi = q_hi >= 0 ? -(double)Z_SPAN + (q_hi + 1) * cell : (double)Z_SPAN;
         if (!(zhi > zlo)) zhi = zlo + cell;
         for (int32_t b = 1; b < nb; ++b) edges[b] = zlo + (zhi - zlo) * (double)b / (double)nb;
         edges[nb] = edges[nb - 1] + (double)Z_SPAN;
         return;
     }
-    int64_t cum = 0;
-    int32_t b = 1;
-    for (int32_t c = 0; c < Q_HIST && b < nb; ++c) {
-        cum += qhist[c];
-        while (b < nb && cum * nb >= (int64_t)b * n) {
-            double e = -(double)Z_SPAN + (double)(c + 1) * cell;
-            if (e <= edges[b - 1]) e = edges[b - 1] + nudge;
-            edges[b] = e;
-            ++b;
-        }
+    for (int32_t b = 1; b < nb; ++b) {
+        double e = cellof[b] >= 0 ? -(double)Z_SPAN + (double)(cellof[b] + 1) * cell : edges[b - 1];
+        if (e <= edges[b - 1]) e = edges[b - 1] + nudge;
+        edges[b] = e;
     }
-    for (; b < nb; ++b) edges[b] = edges[b - 1] + nudge;
     edges[nb] = edges[nb - 1] + (double)Z_SPAN;
 }
 
@@ -794,8 +825,9 @@ extern "C" we_status we_train_committor(we_sim *s, const we_train_params *tp, fl
     hipLaunchKernelGGL(cm_eval_kernel, dim3((n_ds + 255) / 256), dim3(256), 0, s->stream, C.d_params, C.d_feat, n_in,
                        n_ds, ds_idx.as<int64_t>(), R.d_x, (float *)nullptr, qhist.as<uint32_t>());
     HIP_TRY(hipGetLastError());
-    hipLaunchKernelGGL(cm_edges_kernel, dim3(1), dim3(64), 0, s->stream, qhist.as<uint32_t>(), n_ds, C.n_qbins,
-                       C.d_qedges, tp->edge_mode);
+    if (C.n_qbins > CM_EDGE_MAX_BINS) return we_fail(WE_EINVAL, "at most 8192 learned bins");
+    hipLaunchKernelGGL(cm_edges_kernel, dim3(1), dim3(CM_EDGE_THREADS), 0, s->stream, qhist.as<uint32_t>(), n_ds,
+                       C.n_qbins, C.d_qedges, tp->edge_mode);
     HIP_TRY(hipGetLastError());
     if (loss_out && tp->steps > 0)
         HIP_TRY(hipMemcpyAsync(loss_out, dloss.p, 4ull * tp->steps, hipMemcpyDeviceToHost, s->stream));
