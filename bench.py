@@ -49,7 +49,8 @@ def alg_ops_per_event(net) -> float:
     """Arithmetic of one direct-method event with full propensity recompute,
     counted per operation of the algorithm (each a single lane operation; a
     log or a divide counts as one):
-      Philox4x32-10: 10 rounds x (2 mul-lo, 2 mul-hi, 4 xor, 2 key adds) = 100
+      Philox4x32-10: 10 rounds x (2 32x32->64 products, 4 xor); the key
+        schedule does not depend on the counter and is not counted       = 60
       two 53-bit uniforms: 2 x (2 shifts, 1 or, 1 convert, 1 scale)      = 10
       waiting time: 1 - u1, log, divide by a0, t + dt, compare to tau     = 5
       selection target u2*a0, time update                                 = 2
@@ -68,13 +69,13 @@ def alg_ops_per_event(net) -> float:
             f += 1
         per_rxn += 5 + f
     nchg = np.diff(net.chg_ptr).mean()
-    return 100 + 10 + 5 + 2 + per_rxn + nchg + 2
+    return 60 + 10 + 5 + 2 + per_rxn + nchg + 2
 
 
 def alg_ops_per_event_wave(net) -> float:
     """Arithmetic of one event of the chunked direct method on one wave, per
     the same operation model as alg_ops_per_event:
-      random numbers, waiting time, target, time update     = 117
+      random numbers, waiting time, target, time update     = 77
       chunk-sum scan over K = ceil(R/64) chunks             = K adds + ballot (1)
       the chosen chunk: 64 propensity evaluations (5 + f each, the mean f
         over reactions) and a 64-lane scan (63 adds) + ballot (1)
@@ -100,7 +101,7 @@ def alg_ops_per_event_wave(net) -> float:
     dbar = float(np.mean(deps))
     K = (net.R + 63) // 64
     nchg = float(np.diff(net.chg_ptr).mean())
-    return 117 + K + 1 + 64 * (5 + fbar) + 63 + 1 + dbar * (2 * (4 + fbar) + 2) + nchg + 2
+    return 77 + K + 1 + 64 * (5 + fbar) + 63 + 1 + dbar * (2 * (4 + fbar) + 2) + nchg + 2
 
 
 def _code_only(text: str) -> str:
@@ -197,7 +198,16 @@ def experiment_toggle_mfpt(args):
     ev_ref = simb.counters()[0]
 
     def run(learned: bool, edge_mode: int = 0, record_iters: int = 150, train_steps: int = 600,
-            group: int = 0):
+            extra: int = 0, group: int = 0):
+        """edge_mode 0/1: the trainer's edges (equal-count quantiles / equal
+        logit widths over the data); 2: equal logit widths from the A state's
+        logit to extra / 2 (a half-unit upper logit); 3: equal logit widths
+        first, then, after `extra` iterations of measuring every learned bin's
+        mean weight, inner edges at equal quantiles of
+        y(z) = int sqrt(rho(z) q(z) (1 - q(z))) dz (rho: weight per unit logit,
+        piecewise constant over the bins), which equalizes the bins' terms
+        w_b * Var_b(q) of the split/merge variance for a discrepancy
+        function proportional to q."""
         cfg = base if group == 0 else dataclasses.replace(
             base, seeds=base.seeds + np.uint64(group * base.seeds.size))
         sim = we.sim_from_config(cfg, kernel=kern[0], walkers_per_wave=kern[1], max_iters=total,
@@ -218,11 +228,41 @@ def experiment_toggle_mfpt(args):
             t0 = time.perf_counter()
             loss, n = sim.train_committor(np.array([0, 0, 0, 0, 1, -1, 2, -2.0]), -base.tgt_thr,
                                           steps=train_steps,
-                                          batch=1024, lr=2e-3, seed=7, edge_mode=edge_mode)
+                                          batch=1024, lr=2e-3, seed=7, edge_mode=min(edge_mode, 1))
             sim.use_committor_bins(True)
+            if edge_mode == 2:
+                qa = float(sim.committor(cfg.x_rec[None, :])[0])
+                za, zhi = float(np.log(qa / (1.0 - qa))), 0.5 * extra
+                e = za + (zhi - za) * np.arange(cfg.n_bins + 1) / cfg.n_bins
+                e[0], e[-1] = za - 50.0, zhi + 50.0
+                sim.set_learned_bins(e)
+            sim.synchronize()
             train_s = time.perf_counter() - t0
             gpu += train_s
             _, _, edges = sim.committor_state()
+            if edge_mode == 3:
+                nb, wsum, cnt = cfg.n_bins, np.zeros(cfg.n_bins), 0
+                for i in range(extra):
+                    t0 = time.perf_counter()
+                    sim.step(1)
+                    sim.synchronize()
+                    gpu += time.perf_counter() - t0
+                    done += 1
+                    for r in range(cfg.seeds.size):
+                        _, w, b, _ = sim.walkers(r)
+                        wsum += np.bincount(b, weights=w, minlength=nb)[:nb]
+                    cnt += cfg.seeds.size
+                    if done % chunk == 0:
+                        times.append(gpu)
+                        iters.append(done)
+                edges = _weighted_logit_edges(edges, wsum / cnt)
+                sim.set_learned_bins(edges)
+                while done % chunk:
+                    t0 = time.perf_counter()
+                    sim.step(1)
+                    sim.synchronize()
+                    gpu += time.perf_counter() - t0
+                    done += 1
         sim.graph_capture(chunk)
         while done + chunk <= total:
             t0 = time.perf_counter()
@@ -244,7 +284,7 @@ def experiment_toggle_mfpt(args):
                "mfpt_runs_rel": [round(float(v), 3) for v in
                                  (tau / flux[:, burn:].mean(axis=1)) / ref_mfpt]}
         if learned:
-            res.update(edge_mode=edge_mode, record_iters=record_iters, train_steps=train_steps,
+            res.update(edge_mode=edge_mode, record_iters=record_iters, train_steps=train_steps, extra=extra,
                        train_states=n, loss_first=float(loss[:10].mean()),
                        loss_last=float(loss[-50:].mean()),
                        edges=[round(float(v), 2) for v in edges[1:-1:8]])
@@ -260,20 +300,28 @@ def experiment_toggle_mfpt(args):
     plain = run(False)
     variants = []
     specs = [tuple(int(v) for v in spec.split(":")) for spec in args.variants.split(",")]
-    for em, ri, ts in specs:
-        variants.append(run(True, em, ri, ts))
+    specs = [sp + (0,) * (4 - len(sp)) for sp in specs]
+    for sp in specs:
+        variants.append(run(True, *sp))
     learned = variants[0]
     # further independent groups of 16 replicas (seeds shifted by 16 per
     # group): the time to 5% of one group is itself a noisy statistic
     groups = {"plain": [plain["gpu_s_to_5pct"]], "learned": [learned["gpu_s_to_5pct"]],
               "plain_final": [plain["final_rel_err"]], "learned_final": [learned["final_rel_err"]]}
+    per_variant = [{"spec": ":".join(str(v) for v in sp), "to_5pct": [r["gpu_s_to_5pct"]],
+                    "final": [r["final_rel_err"]]} for sp, r in zip(specs, variants)]
     for g in range(1, args.toggle_groups):
         pg = run(False, group=g)
-        lg = run(True, *specs[0], group=g)
         groups["plain"].append(pg["gpu_s_to_5pct"])
-        groups["learned"].append(lg["gpu_s_to_5pct"])
         groups["plain_final"].append(pg["final_rel_err"])
-        groups["learned_final"].append(lg["final_rel_err"])
+        for k, sp in enumerate(specs if args.toggle_groups_all else specs[:1]):
+            lg = run(True, *sp, group=g)
+            if k == 0:
+                groups["learned"].append(lg["gpu_s_to_5pct"])
+                groups["learned_final"].append(lg["final_rel_err"])
+            per_variant[k]["to_5pct"].append(lg["gpu_s_to_5pct"])
+            per_variant[k]["final"].append(lg["final_rel_err"])
+    groups["variants"] = per_variant
     return {"metric": "GPU-seconds to MFPT rel-err 5%, learned vs plain bins",
            "workload": "toggle (seed 101), 16 replicas x 64 bins x 16 walkers, tau 0.7",
            "resample_rule": base.resample_rule, "groups": groups,
@@ -284,6 +332,26 @@ def experiment_toggle_mfpt(args):
                          "iterations": ref_iters, "gpu_s": t_ref, "events": ev_ref},
            "burn_in_iterations": burn, "plain": plain, "learned": learned,
            "learned_variants": variants[1:]}
+
+
+def _weighted_logit_edges(edges, wbar, floor=0.02):
+    """Inner logit edges at equal quantiles of y(z) = int sqrt(rho q (1-q)) dz,
+    rho the mean weight per unit logit of each inner bin (wbar[b] / width),
+    q = 1 / (1 + exp(-z)) at the bin's centre; the first and last inner
+    edges stay.  Each inner bin's increment is kept at or above `floor`
+    times the mean, so the edges stay strictly increasing."""
+    e = np.asarray(edges, np.float64)
+    nb = len(e) - 1
+    z = e[1:-1]
+    dz = np.diff(z)
+    zc = 0.5 * (z[:-1] + z[1:])
+    q = 1.0 / (1.0 + np.exp(-zc))
+    dy = np.sqrt(np.maximum(np.asarray(wbar, np.float64)[1:-1], 0.0) * dz * q * (1.0 - q))
+    dy = np.maximum(dy, floor * max(dy.mean(), 1e-300))
+    y = np.concatenate([[0.0], np.cumsum(dy)])
+    out = e.copy()
+    out[1:-1] = np.interp(np.linspace(0.0, y[-1], nb - 1), y, z)
+    return out
 
 
 def schlogl_mfpt_exact(a: int = 82, b: int = 563, top: int = 1500) -> float:
@@ -1032,8 +1100,11 @@ def main():
     ap.add_argument("--toggle-groups", type=int, default=4,
                     help="independent 16-replica groups of the toggle experiment")
     ap.add_argument("--variants", default="1:400:1500",
-                    help="learned-bin runs as edge_mode:record_iters:train_steps, comma separated; "
-                         "the first is the reported one")
+                    help="learned-bin runs as edge_mode:record_iters:train_steps[:extra], comma "
+                         "separated; the first is the reported one (edge modes 2 and 3 and their "
+                         "extra parameter: see experiment_toggle_mfpt)")
+    ap.add_argument("--toggle-groups-all", action="store_true",
+                    help="run every learned variant in every group (default: the first only)")
     args = ap.parse_args()
     if args.experiment == "toggle_mfpt":
         print(json.dumps(experiment_toggle_mfpt(args)), flush=True)

@@ -197,14 +197,19 @@ WE_API const char *we_propagation_kernel(const we_sim *s);
  * grid bins (after learned ones); a non-NULL grid replaces the coordinates
  * and edges, keeping the number of bins on each axis (the slot reservation
  * m_targ * n_bins depends on it).  kind WE_BINS_LEARNED: bin on the trained
- * committor (we_train_committor), grid must be NULL.  Takes effect from the
- * next iteration.  Synchronous.  Errors: WE_EINVAL (bin counts differ, edges
- * not increasing), WE_ESTATE (a captured graph exists: recapture after
- * switching; learned bins without a trained committor). */
+ * committor (we_train_committor), grid must be NULL; qedges NULL keeps the
+ * logit edges computed at training, otherwise n_bins + 1 host doubles
+ * replace them (inner edges strictly increasing; a logit below the second
+ * edge falls in bin 0, one at or above the last inner edge in the last bin).
+ * Takes effect from the next iteration.  Synchronous.  Errors: WE_EINVAL
+ * (bin counts differ, edges not increasing, qedges with grid bins),
+ * WE_ESTATE (a captured graph exists: recapture after switching; learned
+ * bins without a trained committor). */
 typedef enum { WE_BINS_GRID = 0, WE_BINS_LEARNED = 1 } we_bins_kind;
 typedef struct {
     int32_t kind;              /* we_bins_kind                                      */
     const we_grid *grid;       /* WE_BINS_GRID: new grid, or NULL                   */
+    const double *qedges;      /* WE_BINS_LEARNED: [n_bins + 1] logit edges, or NULL */
 } we_bins;
 WE_API we_status we_set_bins(we_sim *s, const we_bins *bins);
 

@@ -847,6 +847,19 @@ extern "C" we_status we_use_committor_bins(we_sim *s, int32_t enable) {
     return WE_OK;
 }
 
+// Caller-given logit edges for the learned bins (we_set_bins).
+we_status committor_set_edges(we_sim *s, const double *edges) {
+    if (!s->cm.trained) return we_fail(WE_ESTATE, "no trained committor");
+    const int32_t nb = s->cm.n_qbins;
+    for (int32_t b = 1; b + 1 < nb; ++b)
+        if (!(edges[b] < edges[b + 1])) return we_fail(WE_EINVAL, "inner logit edges must increase strictly");
+    for (int32_t b = 0; b <= nb; ++b)
+        if (!std::isfinite(edges[b])) return we_fail(WE_EINVAL, "logit edges must be finite");
+    HIP_TRY(hipMemcpyAsync(s->cm.d_qedges, edges, 8ull * (nb + 1), hipMemcpyHostToDevice, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    return WE_OK;
+}
+
 extern "C" we_status we_committor_eval(we_sim *s, int32_t n, const int32_t *x, float *q) {
     if (!s || (n > 0 && (!x || !q))) return we_fail(WE_EINVAL, "NULL argument");
     if (!s->cm.trained) return we_fail(WE_ESTATE, "no trained committor");

@@ -141,6 +141,7 @@ struct CommittorHost {
 };
 we_status committor_export(we_sim *s, CommittorHost &h);
 we_status committor_import(we_sim *s, const CommittorHost &h);
+we_status committor_set_edges(we_sim *s, const double *edges);
 hipError_t committor_record(we_sim *s, hipStream_t st);
 hipError_t committor_bin(we_sim *s, int32_t *x_cur, hipStream_t st);
 // A batch member's active model as device pointers (all NULL: grid bins).

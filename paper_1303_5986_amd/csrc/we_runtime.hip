@@ -1018,9 +1018,13 @@ extern "C" we_status we_set_bins(we_sim *s, const we_bins *b) {
     if (!s || !b) return fail(WE_EINVAL, "NULL argument");
     if (b->kind == WE_BINS_LEARNED) {
         if (b->grid) return fail(WE_EINVAL, "learned bins take no grid");
-        return we_use_committor_bins(s, 1);
+        const bool was = s->cm.active;
+        we_status e = we_use_committor_bins(s, 1);
+        if (e == WE_OK && b->qedges && (e = committor_set_edges(s, b->qedges)) != WE_OK) s->cm.active = was;
+        return e;
     }
     if (b->kind != WE_BINS_GRID) return fail(WE_EINVAL, "unknown bin kind");
+    if (b->qedges) return fail(WE_EINVAL, "logit edges go with learned bins");
     if (s->graph_exec) return fail(WE_ESTATE, "recapture the graph after switching bins");
     if (b->grid) {
         const we_grid *g = b->grid;

@@ -75,7 +75,7 @@ class _Peaks(C.Structure):
 
 
 class _Bins(C.Structure):
-    _fields_ = [("kind", C.c_int32), ("grid", C.c_void_p)]
+    _fields_ = [("kind", C.c_int32), ("grid", C.c_void_p), ("qedges", C.c_void_p)]
 
 
 class _CheckpointInfo(C.Structure):
@@ -331,7 +331,7 @@ class Sim:
         """Bin on a new grid with the same number of bins per axis, or (no
         arguments) on the sim's grid again after learned bins."""
         if edges is None:
-            _check(load_library().we_set_bins(self.handle, C.byref(_Bins(WE_BINS_GRID, None))))
+            _check(load_library().we_set_bins(self.handle, C.byref(_Bins(WE_BINS_GRID, None, None))))
             return
         k = dict(coef=np.ascontiguousarray(bin_coef, np.float64), edges=np.ascontiguousarray(edges, np.float64),
                  coef2=None if bin_coef2 is None else np.ascontiguousarray(bin_coef2, np.float64),
@@ -339,10 +339,15 @@ class Sim:
         n2 = 0 if k["edges2"] is None else len(k["edges2"]) - 1
         g = _Grid(len(k["edges"]) - 1, k["coef"].ctypes.data, k["edges"].ctypes.data, n2,
                   _ptr(k["coef2"]), _ptr(k["edges2"]))
-        _check(load_library().we_set_bins(self.handle, C.byref(_Bins(WE_BINS_GRID, C.addressof(g)))))
+        _check(load_library().we_set_bins(self.handle, C.byref(_Bins(WE_BINS_GRID, C.addressof(g), None))))
 
-    def set_learned_bins(self):
-        _check(load_library().we_set_bins(self.handle, C.byref(_Bins(WE_BINS_LEARNED, None))))
+    def set_learned_bins(self, qedges=None):
+        """Bin on the trained committor; qedges (n_bins + 1 logit edges)
+        replaces the edges computed at training."""
+        q = None if qedges is None else np.ascontiguousarray(qedges, np.float64)
+        if q is not None and len(q) != self.n_bins + 1:
+            raise ValueError(f"need {self.n_bins + 1} logit edges, got {len(q)}")
+        _check(load_library().we_set_bins(self.handle, C.byref(_Bins(WE_BINS_LEARNED, None, _ptr(q)))))
 
     # ------------------------------------------------------------ stepping
     def set_ensemble(self, run: int, x, w):

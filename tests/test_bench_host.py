@@ -17,17 +17,17 @@ from paper_1303_5986_amd import workloads as wl  # noqa: E402
 
 
 def test_ops_per_event_schlogl_by_hand():
-    """Philox 100 + uniforms 10 + waiting time 5 + target/time 2, and per
-    reaction 5 + f_j: A+2X->3X (C(x,2): 3), 3X->A+2X (C(x,3): 6), B->X (0),
+    """Philox 60 (20 products, 40 xors) + uniforms 10 + waiting time 5 +
+    target/time 2, and per reaction 5 + f_j: A+2X->3X (C(x,2): 3), 3X->A+2X (C(x,3): 6), B->X (0),
     X->B (0), so 4 x 5 + 9 = 29; one changed species + 2 bound checks."""
-    assert bench.alg_ops_per_event(wl.schlogl()) == 100 + 10 + 5 + 2 + 29 + 1 + 2 == 149
+    assert bench.alg_ops_per_event(wl.schlogl()) == 60 + 10 + 5 + 2 + 29 + 1 + 2 == 109
 
 
 def test_ops_per_event_two_species_reaction():
     """A + B -> C adds the two-species product (1) to 5; mean changed
     species 3."""
     net = wl.Network.from_reactions(["A", "B", "C"], [({"A": 1, "B": 1}, {"C": 1}, 1.0)])
-    assert bench.alg_ops_per_event(net) == 100 + 10 + 5 + 2 + 6 + 3 + 2
+    assert bench.alg_ops_per_event(net) == 60 + 10 + 5 + 2 + 6 + 3 + 2
 
 
 def test_source_digest_ignores_comments_only(tmp_path):
@@ -82,3 +82,21 @@ def test_batch_tau_scales_to_ten_events():
     assert wl.batch_tau(100.0) == 0.01          # clipped below
     assert wl.batch_tau(0.0) == 5.0             # clipped above
     assert abs(wl.batch_tau(2.0, tau0=0.3) - 1.5) < 1e-15
+
+
+def test_weighted_logit_edges_keep_ends_order_and_symmetry():
+    """Equal weight per unit logit on edges symmetric about z = 0: the new
+    inner edges keep the first and last inner edge, increase strictly, stay
+    symmetric, and crowd towards z = 0, where q (1 - q) is largest."""
+    import numpy as np
+    e = np.linspace(-9.0, 9.0, 65)
+    w = np.diff(e)
+    out = bench._weighted_logit_edges(e, w)
+    assert out[1] == e[1] and out[-2] == e[-2] and out[0] == e[0] and out[-1] == e[-1]
+    assert np.all(np.diff(out[1:-1]) > 0)
+    assert np.allclose(out, -out[::-1], atol=1e-9)
+    assert np.diff(out[31:34]).max() < np.diff(e[31:34]).min()
+    # a bin without weight still gets a positive width
+    w2 = w.copy()
+    w2[10:20] = 0.0
+    assert np.all(np.diff(bench._weighted_logit_edges(e, w2)[1:-1]) > 0)

@@ -240,3 +240,45 @@ def test_inference_and_learned_bins_match_oracle_forward(edge_mode):
     inv = inv.ravel()
     for g in np.unique(inv[near]):
         assert np.unique(B[inv == g]).size == 1
+
+
+def test_caller_logit_edges_replace_the_trained_ones():
+    """we_set_bins with WE_BINS_LEARNED and caller edges: the sim keeps those
+    edges, and after a step every live walker sits in the oracle's bin of
+    its FP64 logit on them (either neighbour within 1e-3 of an edge);
+    non-increasing inner edges, and edges with grid bins, are refused and
+    leave the edges unchanged."""
+    _say("case: caller-given logit edges for learned bins")
+    we = _we()
+    cfg = wl.toggle_config(n_runs=4, n_iters=40)
+    sim = we.sim_from_config(cfg, kernel=we.WE_KERNEL_LANE, max_iters=40, record_iters=30)
+    sim.step(30)
+    sim.train_committor(cfg.bin_coef, cfg.a_thr, steps=200, batch=1024, lr=2e-3, seed=5, edge_mode=1)
+    p, feat, e_trained = sim.committor_state()
+    nb = cfg.n_bins
+    e = np.linspace(-6.0, 3.0, nb + 1)
+    sim.set_learned_bins(e)
+    _, _, got = sim.committor_state()
+    assert np.array_equal(got, e)
+    bad = e.copy()
+    bad[5] = bad[4]
+    with pytest.raises(we.WEError):
+        sim.set_learned_bins(bad)
+    _, _, got = sim.committor_state()
+    assert np.array_equal(got, e)
+    import ctypes
+    st = we.load_library().we_set_bins(sim.handle, ctypes.byref(we._Bins(we.WE_BINS_GRID, None,
+                                                                          e.ctypes.data)))
+    assert st != 0                           # logit edges go with learned bins only
+    sim.step(2)
+    sim.synchronize()
+    S = cfg.net.S
+    for r in range(len(cfg.seeds)):
+        x, w, b, _ = sim.walkers(r)
+        _, _, _, z = mlp.forward(p.astype(np.float64), feat.astype(np.float64), x, S)
+        ref = np.array([orc.bin_of(e, float(v)) for v in z])
+        near = np.min(np.abs(z[:, None] - e[None, 1:-1]), axis=1) <= 1e-3
+        assert np.array_equal(b[~near], ref[~near])
+        assert np.all(np.abs(b[near] - ref[near]) <= 1)
+        assert abs(w.sum() - 1.0) < 1e-12
+    _say(f"   {nb} caller edges on [-6, 3] kept; bins equal the oracle's")
