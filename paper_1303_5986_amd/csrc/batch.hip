@@ -151,7 +151,8 @@ __global__ __launch_bounds__(256) void batch_group_kernel(const SimArgs *__restr
         const SimArgs &a = args[it.sim];
         const int32_t k = it.slot + grp;
         const bool live = k < a.cap && k < a.n_walk[it.run];
-        group_walker<L>(a, xptr[it.sim], it.run, k, live, *a.iter_dev, lx);
+        const GroupTables tb{a.desc, a.chg_ptr, a.chg};
+        group_walker<L>(a, tb, xptr[it.sim], it.run, k, live, *a.iter_dev, lx);
     }
 }
 

@@ -8,7 +8,9 @@
 // events per walker, built by launch_work_queue) with one atomic, runs them
 // through the interval, and takes the next batch until the queue is empty.
 // Counts live in LDS (S ints per walker, 64 / L walkers per wave, four waves
-// per block); descriptors and changes are read through the cache.
+// per block); the descriptors and changes are copied to LDS beside them when
+// they take at most 48 KB (ssa_group_kernel<L, true>), else read through the
+// cache (<L, false>).
 #include "ssa_group_body.h"
 #include "we_internal.h"
 
@@ -16,13 +18,36 @@
 
 #define GROUP_WAVES 4
 
-template <int L>
+// LDS copy of the network tables (descriptors, change offsets, changes),
+// 16-byte aligned, in front of the walkers' counts.
+__host__ __device__ inline size_t group_tables_bytes(int32_t R, int32_t n_chg) {
+    return (16 * (size_t)R + 4 * ((size_t)R + 1 + (size_t)n_chg) + 15) & ~(size_t)15;
+}
+
+template <int L, bool LT>
 __global__ __launch_bounds__(64 * GROUP_WAVES) void ssa_group_kernel(SimArgs a, int32_t *__restrict__ xs) {
-    extern __shared__ int32_t glds[];
+    extern __shared__ __align__(16) unsigned char gsm[];
     constexpr int G = 64 / L;
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int grp = lane / L;
-    int32_t *lx = glds + ((size_t)wv * G + grp) * a.S;
+    GroupTables tb{a.desc, a.chg_ptr, a.chg};
+    size_t off = 0;
+    if constexpr (LT) {
+        const int32_t R = a.R;
+        uint4 *ld = reinterpret_cast<uint4 *>(gsm);
+        int32_t *lcp = reinterpret_cast<int32_t *>(gsm + 16 * (size_t)R);
+        int32_t *lcg = lcp + R + 1;
+        const uint4 *gd = reinterpret_cast<const uint4 *>(a.desc);
+        for (int32_t i = threadIdx.x; i < R; i += blockDim.x) ld[i] = gd[i];
+        for (int32_t i = threadIdx.x; i <= R; i += blockDim.x) lcp[i] = a.chg_ptr[i];
+        for (int32_t i = threadIdx.x; i < a.n_chg; i += blockDim.x) lcg[i] = a.chg[i];
+        __syncthreads();
+        tb.desc = reinterpret_cast<const RxnDesc *>(ld);
+        tb.chg_ptr = lcp;
+        tb.chg = lcg;
+        off = group_tables_bytes(R, a.n_chg);
+    }
+    int32_t *lx = reinterpret_cast<int32_t *>(gsm + off) + ((size_t)wv * G + grp) * a.S;
     const uint32_t iter = *a.iter_dev;
     const uint32_t M = (uint32_t)a.m_targ, cap = (uint32_t)a.cap;
     const uint32_t total = a.queue[1] * M;
@@ -45,7 +70,7 @@ __global__ __launch_bounds__(64 * GROUP_WAVES) void ssa_group_kernel(SimArgs a, 
                 live = true;
             }
         }
-        group_walker<L>(a, xs, run, k, live, iter, lx);
+        group_walker<L>(a, tb, xs, run, k, live, iter, lx);
     }
 }
 
@@ -61,15 +86,23 @@ int group_cus() {
     return n;
 }
 
-template <int L>
+// Tables in LDS when they take at most GROUP_LDS_TABLES bytes (every
+// reaction's descriptor and changes are then one LDS read away instead of a
+// cache round trip in the event chain).
+#define GROUP_LDS_TABLES (48 * 1024)
+
+bool group_tables_in_lds(const SimArgs &a) { return group_tables_bytes(a.R, a.n_chg) <= GROUP_LDS_TABLES; }
+
+template <int L, bool LT>
 hipError_t launch_group(const SimArgs &a, int32_t *xs, hipStream_t st) {
     constexpr int G = 64 / L;
-    const size_t shmem = sizeof(int32_t) * (size_t)GROUP_WAVES * G * a.S;
+    const size_t shmem =
+        (LT ? group_tables_bytes(a.R, a.n_chg) : 0) + sizeof(int32_t) * (size_t)GROUP_WAVES * G * a.S;
     static size_t last_shmem = 0;
     static int per_cu = 0;
     if (per_cu == 0 || shmem != last_shmem) {
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, ssa_group_kernel<L>, 64 * GROUP_WAVES, shmem) !=
-                hipSuccess ||
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, ssa_group_kernel<L, LT>, 64 * GROUP_WAVES,
+                                                         shmem) != hipSuccess ||
             per_cu < 1)
             per_cu = 1;
         last_shmem = shmem;
@@ -77,8 +110,13 @@ hipError_t launch_group(const SimArgs &a, int32_t *xs, hipStream_t st) {
     const int64_t walkers = (int64_t)a.n_runs * a.cap;
     const int64_t need = (walkers + (int64_t)GROUP_WAVES * G - 1) / ((int64_t)GROUP_WAVES * G);
     const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>(need, (int64_t)per_cu * group_cus()));
-    hipLaunchKernelGGL(ssa_group_kernel<L>, dim3(blocks), dim3(64 * GROUP_WAVES), shmem, st, a, xs);
+    hipLaunchKernelGGL((ssa_group_kernel<L, LT>), dim3(blocks), dim3(64 * GROUP_WAVES), shmem, st, a, xs);
     return hipGetLastError();
+}
+
+template <int L>
+hipError_t launch_group(const SimArgs &a, int32_t *xs, hipStream_t st) {
+    return group_tables_in_lds(a) ? launch_group<L, true>(a, xs, st) : launch_group<L, false>(a, xs, st);
 }
 }  // namespace
 
@@ -93,12 +131,13 @@ hipError_t launch_ssa_group(const SimArgs &a, int32_t *xs, int32_t lanes, hipStr
     }
 }
 
-const char *ssa_group_name(int32_t lanes) {
+const char *ssa_group_name(const SimArgs &a, int32_t lanes) {
+    const bool t = group_tables_in_lds(a);
     switch (lanes) {
-    case 2: return "ssa_group_kernel<2>";
-    case 4: return "ssa_group_kernel<4>";
-    case 8: return "ssa_group_kernel<8>";
-    case 16: return "ssa_group_kernel<16>";
-    default: return "ssa_group_kernel<32>";
+    case 2: return t ? "ssa_group_kernel<2, true>" : "ssa_group_kernel<2, false>";
+    case 4: return t ? "ssa_group_kernel<4, true>" : "ssa_group_kernel<4, false>";
+    case 8: return t ? "ssa_group_kernel<8, true>" : "ssa_group_kernel<8, false>";
+    case 16: return t ? "ssa_group_kernel<16, true>" : "ssa_group_kernel<16, false>";
+    default: return t ? "ssa_group_kernel<32, true>" : "ssa_group_kernel<32, false>";
     }
 }

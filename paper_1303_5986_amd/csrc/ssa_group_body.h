@@ -7,7 +7,8 @@
 // g of the group owns the block of reactions [g B, (g + 1) B), B = ceil(R/L).
 // Per event (Sec. II.A):
 //   1. each lane sums its block's propensities, recomputed from the walker's
-//      counts in LDS (descriptors come through the cache);
+//      counts in LDS (descriptors and changes from the network tables: an
+//      LDS copy in ssa_group_kernel when they fit, else through the cache);
 //   2. an inclusive scan over the group's L partial sums (log2 L cross-lane
 //      steps) gives a0 and, with a ballot, the lane whose block holds u2 a0;
 //   3. that lane walks its block again to find j;
@@ -52,12 +53,20 @@ __device__ __forceinline__ double group_scan_incl(double v) {
     return v;
 }
 
+// The network tables a group walker reads: a.desc, a.chg_ptr and a.chg, or
+// a block's LDS copy of them.
+struct GroupTables {
+    const RxnDesc *desc;
+    const int32_t *chg_ptr;
+    const int32_t *chg;
+};
+
 // The walkers in slots k of run `run` for the groups with live set (k may
 // differ per group); lx is this group's slice of S counts in LDS.  Every lane
 // of the wave must call it.
 template <int L>
-__device__ inline void group_walker(const SimArgs &a, int32_t *__restrict__ xs, int32_t run, int32_t k, bool live,
-                                    uint32_t iter, int32_t *lx) {
+__device__ inline void group_walker(const SimArgs &a, const GroupTables &tb, int32_t *__restrict__ xs, int32_t run,
+                                    int32_t k, bool live, uint32_t iter, int32_t *lx) {
     const int lane = threadIdx.x & 63;
     const int gl = lane & (L - 1);
     const int gbase = lane - gl;
@@ -87,7 +96,7 @@ __device__ inline void group_walker(const SimArgs &a, int32_t *__restrict__ xs, 
         double part = 0.0;
         if (go)
             for (int32_t r = r_lo; r < r_hi; ++r) {
-                const RxnDesc d = a.desc[r];
+                const RxnDesc d = tb.desc[r];
                 part += propensity_from(d, (uint32_t)lx[d.s1], (uint32_t)lx[d.s2]);
             }
         // 2. group scan, a0, waiting time
@@ -121,7 +130,7 @@ __device__ inline void group_walker(const SimArgs &a, int32_t *__restrict__ xs, 
             double run_s = 0.0;
             int32_t last = -1;
             for (int32_t r = r_lo; r < r_hi; ++r) {
-                const RxnDesc d = a.desc[r];
+                const RxnDesc d = tb.desc[r];
                 const double ar = propensity_from(d, (uint32_t)lx[d.s1], (uint32_t)lx[d.s2]);
                 if (ar > 0.0) {
                     last = r;
@@ -145,9 +154,9 @@ __device__ inline void group_walker(const SimArgs &a, int32_t *__restrict__ xs, 
         // 4. state update, one change per lane
         bool lbad = false;
         if (go) {
-            const int32_t c0 = a.chg_ptr[j], c1 = a.chg_ptr[j + 1];
+            const int32_t c0 = tb.chg_ptr[j], c1 = tb.chg_ptr[j + 1];
             for (int32_t c = c0 + gl; c < c1; c += L) {
-                const int32_t p = a.chg[c];
+                const int32_t p = tb.chg[c];
                 const int32_t sp = change_species(p);
                 const int32_t nv = lx[sp] + change_delta(p);
                 lx[sp] = nv;

@@ -62,6 +62,23 @@ __device__ __forceinline__ int32_t last_set(unsigned long long m) {
     return m ? 63 - __clzll((long long)m) : -1;
 }
 
+// Issue priority of the calling wave from its walker's expected remaining
+// events in the interval, (tau - t) * a0: longest remaining chain first.  A
+// launch lasts as long as its longest walker chain, and waves sharing a SIMD
+// compete for issue; the wave with more left to do then issues first and the
+// others fill its dependency stalls.  Four levels (s_setprio 0..3), at 16,
+// 48 and 96 remaining events.  Scheduling only: no result depends on it.
+__device__ __forceinline__ void chain_priority(double rem) {
+    if (rem > 96.0)
+        __builtin_amdgcn_s_setprio(3);
+    else if (rem > 48.0)
+        __builtin_amdgcn_s_setprio(2);
+    else if (rem > 16.0)
+        __builtin_amdgcn_s_setprio(1);
+    else
+        __builtin_amdgcn_s_setprio(0);
+}
+
 // Sum of all 64 propensities of chunk c (last lane of the scan).
 template <class T>
 __device__ __forceinline__ double chunk_total(const T &tab, int32_t R, const int32_t *lx, int c, int lane) {
@@ -173,6 +190,7 @@ __device__ inline void wave_walker_t(const SimArgs &a, const T &tab, int32_t *__
         const double dt = ex / a0;
         if (t + dt > tau) break;
         t = t + dt;
+        if ((e & 15u) == 1u) chain_priority((tau - t) * a0);
         const double target = u2 * a0;
 
         // chunk holding the target

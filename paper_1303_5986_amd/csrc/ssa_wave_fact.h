@@ -27,6 +27,8 @@
 //     them without bank conflicts).
 //     Fixed order throughout, so a run is reproducible bit for bit.
 // A reaction whose dependents exceed two rounds rebuilds every chunk sum.
+// Every 16 events the wave's issue priority follows its walker's expected
+// remaining events (chain_priority), so the longest chains issue first.
 #pragma once
 #include "ssa_wave_body.h"
 
@@ -138,6 +140,7 @@ __device__ inline void wave_walker_fact(const SimArgs &a, const FactTables &tab,
         const double dt = ex * recip(a0);
         if (t + dt > tau) break;
         t = t + dt;
+        if ((e & 15u) == 1u) chain_priority((tau - t) * a0);
         const double target = u2 * a0;
 
         // chunk holding the target

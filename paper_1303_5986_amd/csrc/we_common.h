@@ -108,6 +108,7 @@ struct SimArgs {
     const uint32_t *__restrict__ inc_tab;// [S] incidence start | count << 16
     const uint16_t *__restrict__ inc;    // [n_inc] species -> reactions taking it as a reactant
     int32_t n_inc;
+    int32_t n_chg;                       // entries of chg (chg_ptr[R])
     int32_t S, R;
     int32_t engine;                      // 0: exact SSA, 1: tau-leaping (lane kernel)
     double leap_eps;                     // tau-leaping error control

@@ -126,7 +126,7 @@ bool wave_kernel_fits(int32_t S, int32_t R);
 const char *ssa_lane_name(const SimArgs &a);
 const char *ssa_wave_name(const SimArgs &a);
 hipError_t launch_ssa_group(const SimArgs &a, int32_t *xs, int32_t lanes, hipStream_t st);
-const char *ssa_group_name(int32_t lanes);
+const char *ssa_group_name(const SimArgs &a, int32_t lanes);
 // reweight.hip
 #define WE_RW_MAX_BINS 512
 bool rw_solve_in_lds(int32_t n_bins);

@@ -538,6 +538,7 @@ extern "C" we_status we_init(const we_network *net, const we_grid *g, const we_p
     a.inc_tab = net->d_inc_tab;
     a.inc = net->d_inc;
     a.n_inc = (int32_t)net->inc.size();
+    a.n_chg = (int32_t)net->chg.size();
     a.engine = p->engine;
     a.leap_eps = p->engine == 1 ? p->leap_eps : 0.0;
     a.S = S; a.R = net->R;
@@ -1010,7 +1011,7 @@ extern "C" we_status we_profile_read(we_sim *s, double *ms_propagate, double *ms
 
 extern "C" const char *we_propagation_kernel(const we_sim *s) {
     if (!s) return "";
-    if (s->kernel == WE_KERNEL_GROUP) return ssa_group_name(s->group_lanes);
+    if (s->kernel == WE_KERNEL_GROUP) return ssa_group_name(s->args, s->group_lanes);
     return s->kernel == WE_KERNEL_LANE ? ssa_lane_name(s->args) : ssa_wave_name(s->args);
 }
 

@@ -41,10 +41,10 @@ def _random_cfg(S, R, seed, m_targ=4, n_runs=2, tau=0.05, n_iters=20):
                        seeds=np.arange(seed, seed + n_runs, dtype=np.uint64))
 
 
-def _compare(cfg, wpw, n_iters, max_frac=0.01):
+def _compare(cfg, wpw, n_iters, max_frac=0.01, lds_tables=True):
     we = _we()
     sim = we.sim_from_config(cfg, kernel=we.WE_KERNEL_GROUP, walkers_per_wave=wpw, max_iters=n_iters)
-    assert sim.propagation_kernel() == f"ssa_group_kernel<{64 // wpw}>"
+    assert sim.propagation_kernel() == f"ssa_group_kernel<{64 // wpw}, {'true' if lds_tables else 'false'}>"
     sim.step(n_iters)
     sim.synchronize()
     total = same = 0
@@ -69,6 +69,14 @@ def _compare(cfg, wpw, n_iters, max_frac=0.01):
 def test_group_kernel_random_network_matches_oracle(wpw):
     _say(f"case: group kernel, {wpw} walkers per wave, random 30x200 network, 2 runs x 20 iterations")
     _compare(_random_cfg(30, 200, 17), wpw, 20)
+
+
+@pytest.mark.parametrize("wpw", [8, 2])
+def test_group_kernel_tables_through_the_cache_match_oracle(wpw):
+    """A network whose descriptors and changes exceed the 48 KB LDS table
+    budget (3200 reactions): the variant reading them through the cache."""
+    _say(f"case: group kernel, {wpw} walkers per wave, random 300x3200 network (tables in global memory)")
+    _compare(_random_cfg(300, 3200, 23, tau=0.002, n_iters=5), wpw, 5, lds_tables=False)
 
 
 @pytest.mark.parametrize("wpw", [32, 8])
