@@ -9,8 +9,10 @@
 //   1. each lane sums its block's propensities, recomputed from the walker's
 //      counts in LDS (descriptors and changes from the network tables: an
 //      LDS copy in ssa_group_kernel when they fit, else through the cache);
-//   2. an inclusive scan over the group's L partial sums (log2 L cross-lane
+//   2. an inclusive scan over the group's L partial sums (log2 L DPP
 //      steps) gives a0 and, with a ballot, the lane whose block holds u2 a0;
+//      the random numbers of L events are drawn at once, one event per lane
+//      of the group, and read by the event that uses them;
 //   3. that lane walks its block again to find j;
 //   4. the group applies j's changes to the counts, one change per lane.
 // The blocks follow the reactions' own order, so j is the reaction the
@@ -43,13 +45,34 @@ __host__ __device__ inline bool group_kernel_fits(int32_t S, int32_t R, int32_t 
     return group_lanes_valid(lanes) && R >= 1 && R <= 65535 && S >= 1 && (64 / lanes) * S <= GROUP_LDS_INTS_PER_WAVE;
 }
 
+union GroupF64 {
+    double d;
+    int32_t w[2];
+};
+
+// Row-shift DPP move of a double (source outside the 16-lane row: 0).
+template <int CTRL, int ROW_MASK, bool BOUND>
+__device__ __forceinline__ double group_dpp(double v) {
+    GroupF64 in, out;
+    in.d = v;
+    out.w[0] = __builtin_amdgcn_update_dpp(0, in.w[0], CTRL, ROW_MASK, 0xF, BOUND);
+    out.w[1] = __builtin_amdgcn_update_dpp(0, in.w[1], CTRL, ROW_MASK, 0xF, BOUND);
+    return out.d;
+}
+
+// Inclusive scan within groups of L lanes by DPP row shifts (groups of up
+// to 16 lie inside a row); a group of 32 adds the first row's total to its
+// second row by a row broadcast.  A step adds its source only from the same
+// group, so the sums follow a fixed order.
 template <int L>
 __device__ __forceinline__ double group_scan_incl(double v) {
-#pragma unroll
-    for (int d = 1; d < L; d <<= 1) {
-        const double u = __shfl_up(v, d, L);
-        if (((int)threadIdx.x & (L - 1)) >= d) v += u;
-    }
+    const int gl = (int)threadIdx.x & (L - 1);
+    double u;
+    if (L > 1) { u = group_dpp<0x111, 0xF, true>(v); if (gl >= 1) v += u; }    // row_shr:1
+    if (L > 2) { u = group_dpp<0x112, 0xF, true>(v); if (gl >= 2) v += u; }    // row_shr:2
+    if (L > 4) { u = group_dpp<0x114, 0xF, true>(v); if (gl >= 4) v += u; }    // row_shr:4
+    if (L > 8) { u = group_dpp<0x118, 0xF, true>(v); if (gl >= 8) v += u; }    // row_shr:8
+    if (L > 16) { u = group_dpp<0x142, 0xA, false>(v); if (gl >= 16) v += u; } // row_bcast:15, rows 1, 3
     return v;
 }
 
@@ -91,6 +114,9 @@ __device__ inline void group_walker(const SimArgs &a, const GroupTables &tb, int
     double t = 0.0;
     uint32_t e = 0, fired = 0;
     bool go = live, bad = false, nosel = false;
+    // random numbers of L events at a time: lane gl of a group holds
+    // -log(1 - u1) and u2 of the group's event (e & ~(L - 1)) + gl
+    double rexp = 0.0, ru2 = 0.0;
     while (__ballot(go)) {
         // 1. this lane's partial sum over its block
         double part = 0.0;
@@ -99,7 +125,15 @@ __device__ inline void group_walker(const SimArgs &a, const GroupTables &tb, int
                 const RxnDesc d = tb.desc[r];
                 part += propensity_from(d, (uint32_t)lx[d.s1], (uint32_t)lx[d.s2]);
             }
-        // 2. group scan, a0, waiting time
+        // 2. group scan, a0, waiting time (e is the same on a group's lanes)
+        if (go && (e & (L - 1)) == 0u) {
+            const U4 rnd = philox4x32_10(e + (uint32_t)gl, (uint32_t)k, iter, 0u, k0, k1);
+            rexp = -log(1.0 - uniform53(rnd.x, rnd.y));
+            ru2 = uniform53(rnd.z, rnd.w);
+        }
+        const int src = gbase + (int)(e & (L - 1));
+        const double ex = __shfl(rexp, src, 64);
+        const double uu = __shfl(ru2, src, 64);
         const double incl = group_scan_incl<L>(part);
         const double a0 = __shfl(incl, gbase + L - 1, 64);
         double u2 = 0.0;
@@ -107,9 +141,8 @@ __device__ inline void group_walker(const SimArgs &a, const GroupTables &tb, int
             if (!(a0 > 0.0)) {
                 go = false;
             } else {
-                const U4 rnd = philox4x32_10(e, (uint32_t)k, iter, 0u, k0, k1);
-                const double dt = -log(1.0 - uniform53(rnd.x, rnd.y)) / a0;
-                u2 = uniform53(rnd.z, rnd.w);
+                const double dt = ex / a0;
+                u2 = uu;
                 e += 1;
                 if (t + dt > tau) go = false;
                 else t = t + dt;
