@@ -1156,27 +1156,45 @@ hipError_t launch_resample(const SimArgs &a, int32_t *x_cur, const double *w_cur
 }
 
 // The same with the one-species histogram summed per block in LDS first:
-// block (run, i) takes walkers i*OBS_WALKERS ... of one run, adds their
+// block (run, i) takes walkers i*per ... (i+1)*per - 1 of one run, adds their
 // weights into an LDS copy of the run's histogram row, then adds the nonzero
 // entries to the row in device memory (one atomic per distinct count per
 // block instead of one per walker, and none on a shared address within a
-// run).  The joint histogram keeps one atomic per walker.  Thread 0 of
+// run); the joint histogram likewise, per distinct cell.  Thread 0 of
 // block (0, 0) also advances the iteration counter, which no step of this
-// kernel reads, in place of the separate advance launch.
+// kernel reads, in place of the separate advance launch.  per = 1024
+// walkers (four per thread) when the runs alone give enough blocks, else 256
+// (one per thread: few runs, where the blocks' walkers are the whole grid).
 #define OBS_WALKERS 1024
+#define OBS_WALKERS_FEW 256
+#define OBS_FEW_RUNS 64
 #define OBS_LDS_BINS 6144
+#define OBS_JOINT_LOG2 9
+#define OBS_JOINT_SLOTS (1 << OBS_JOINT_LOG2)
+#define OBS_JOINT_PROBES 16
 __global__ __launch_bounds__(256) void we_observe_lds_kernel(SimArgs a, const int32_t *__restrict__ xs,
-                                                             const double *__restrict__ ws) {
+                                                             const double *__restrict__ ws, int32_t per) {
     extern __shared__ __align__(16) unsigned char obs_lds[];
     double *h = reinterpret_cast<double *>(obs_lds);
+    // joint-histogram cells of this block's walkers, summed per distinct cell
+    // in an open-addressing table before one device atomic per cell (walkers
+    // of one bin tend to share a cell, and device atomics on one address
+    // serialize)
+    __shared__ int32_t jkey[OBS_JOINT_SLOTS];
+    __shared__ double jval[OBS_JOINT_SLOTS];
     const int32_t run = blockIdx.x, tid = threadIdx.x;
     if (run == 0 && blockIdx.y == 0 && tid == 0) *a.iter_dev += 1u;
     const int32_t n = a.n_walk[run];
-    const int32_t k0 = (int32_t)blockIdx.y * OBS_WALKERS, k1 = min(n, k0 + OBS_WALKERS);
+    const int32_t k0 = (int32_t)blockIdx.y * per, k1 = min(n, k0 + per);
     if (k0 >= n) return;   // uniform over the block
     for (int32_t v = tid; v < a.nh; v += blockDim.x) h[v] = 0.0;
+    for (int32_t v = tid; v < OBS_JOINT_SLOTS; v += blockDim.x) {
+        jkey[v] = -1;
+        jval[v] = 0.0;
+    }
     __syncthreads();
     const size_t base = (size_t)run * a.cap;
+    double *jrow = a.jhist + (size_t)run * a.jcells;
     for (int32_t k = k0 + tid; k < k1; k += blockDim.x) {
         const size_t idx = base + k;
         const double wv = ws[idx];
@@ -1189,13 +1207,25 @@ __global__ __launch_bounds__(256) void we_observe_lds_kernel(SimArgs a, const in
                 cell += c * mul;
                 mul *= a.joint_bins;
             }
-            atomicAdd(&a.jhist[(size_t)run * a.jcells + cell], wv);
+            const uint32_t h0 = ((uint32_t)cell * 2654435761u) >> (32 - OBS_JOINT_LOG2);
+            bool done = false;
+            for (int32_t p = 0; p < OBS_JOINT_PROBES && !done; ++p) {
+                const int32_t slot = (int32_t)((h0 + (uint32_t)p) & (OBS_JOINT_SLOTS - 1));
+                const int32_t prev = atomicCAS(&jkey[slot], -1, cell);
+                if (prev == -1 || prev == cell) {
+                    atomicAdd(&jval[slot], wv);
+                    done = true;
+                }
+            }
+            if (!done) atomicAdd(&jrow[cell], wv);   // table crowded: straight to the device row
         }
     }
     __syncthreads();
     double *row = a.hist + (size_t)run * a.nh;
     for (int32_t v = tid; v < a.nh; v += blockDim.x)
         if (h[v] != 0.0) atomicAdd(&row[v], h[v]);
+    for (int32_t v = tid; v < OBS_JOINT_SLOTS; v += blockDim.x)
+        if (jkey[v] >= 0) atomicAdd(&jrow[jkey[v]], jval[v]);
 }
 
 // Histograms and the end of the iteration; *advanced tells whether the iteration
@@ -1203,8 +1233,10 @@ __global__ __launch_bounds__(256) void we_observe_lds_kernel(SimArgs a, const in
 hipError_t launch_observe(const SimArgs &a, const int32_t *xs, const double *ws, hipStream_t st, bool *advanced) {
     *advanced = false;
     if (a.nh > 0 && a.nh <= OBS_LDS_BINS) {
-        const dim3 grid((unsigned)a.n_runs, (unsigned)((a.cap + OBS_WALKERS - 1) / OBS_WALKERS));
-        hipLaunchKernelGGL(we_observe_lds_kernel, grid, dim3(256), (size_t)a.nh * sizeof(double), st, a, xs, ws);
+        const int32_t per = a.n_runs < OBS_FEW_RUNS ? OBS_WALKERS_FEW : OBS_WALKERS;
+        const dim3 grid((unsigned)a.n_runs, (unsigned)((a.cap + per - 1) / per));
+        hipLaunchKernelGGL(we_observe_lds_kernel, grid, dim3(256), (size_t)a.nh * sizeof(double), st, a, xs, ws,
+                           per);
         *advanced = true;
         return hipGetLastError();
     }
