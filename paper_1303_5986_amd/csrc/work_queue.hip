@@ -25,18 +25,48 @@ __global__ __launch_bounds__(256) void queue_count_kernel(SimArgs a) {
 
 // Bin order and queue offsets: one block.  Sorts the bins by mean events
 // per walker (descending; ties: higher bin first), lays out their segments
-// in that order, and clears the statistics and the queue.
+// in that order, and clears the statistics and the queue.  SMALL (few runs,
+// queue_small below): the same block first counts the segments into LDS
+// and afterwards lists them itself, so the three steps are one launch.
 #define QUEUE_MAX_BINS 8192
 #define QUEUE_CHUNK 16   // counters per thread: NB * seg_rep <= 16384 over 1024 threads
+#define QUEUE_SMALL_SEGS 4096
+#define QUEUE_SMALL_BINS 1024
+template <bool SMALL>
 __global__ __launch_bounds__(1024) void queue_order_kernel(SimArgs a) {
-    __shared__ float key[QUEUE_MAX_BINS];
-    __shared__ int16_t idx[QUEUE_MAX_BINS];
+    constexpr int32_t KB = SMALL ? QUEUE_SMALL_BINS : QUEUE_MAX_BINS;
+    __shared__ float key[KB];
+    __shared__ int16_t idx[KB];
     __shared__ int32_t part[1024];
+    // SMALL only: per counter, segments / first position / fill cursor, and
+    // each (run, segment)'s bin (-1: no walkers)
+    __shared__ int32_t s_occ[SMALL ? QUEUE_SMALL_BINS : 1];
+    __shared__ int32_t s_off[SMALL ? QUEUE_SMALL_BINS : 1];
+    __shared__ int32_t s_cur[SMALL ? QUEUE_SMALL_BINS : 1];
+    __shared__ int16_t s_bin[SMALL ? QUEUE_SMALL_SEGS : 1];
     const int32_t NB = a.n_bins, tid = threadIdx.x, nthr = blockDim.x;
     int32_t P = 1;
     while (P < NB) P <<= 1;
     const int32_t rep = a.seg_rep, NC = NB * rep;
     const int lane = tid & 63, wv = tid >> 6, nwv = nthr >> 6;
+    const int32_t n_seg = a.n_runs * NB;
+    if constexpr (SMALL) {
+        for (int32_t c = tid; c < NC; c += nthr) {
+            s_occ[c] = 0;
+            s_cur[c] = 0;
+        }
+        __syncthreads();
+        for (int32_t sg = tid; sg < n_seg; sg += nthr) {
+            const int32_t run = sg / NB, j = sg - run * NB;
+            const int64_t first = (int64_t)j * a.m_targ;
+            int32_t b = -1;
+            if (first < a.n_walk[run]) {
+                b = min(max(a.bin[(size_t)run * a.cap + first], 0), NB - 1);
+                atomicAdd(&s_occ[b * rep + run % rep], 1);
+            }
+            s_bin[sg] = (int16_t)b;
+        }
+    }
     // key of each bin: its replicas' event and walker counts summed by one
     // wave (rep <= 128: two entries per lane at most); four bins per wave at
     // a time, so that their loads are in flight together
@@ -99,7 +129,7 @@ __global__ __launch_bounds__(1024) void queue_order_kernel(SimArgs a) {
     int32_t acc = 0;
 #pragma unroll
     for (int q = 0; q < QUEUE_CHUNK; ++q) {
-        cnt[q] = lo + q < hi ? a.occ_bin[counter(lo + q)] : 0;
+        cnt[q] = lo + q < hi ? (SMALL ? s_occ[counter(lo + q)] : a.occ_bin[counter(lo + q)]) : 0;
         acc += cnt[q];
     }
     // block-wide exclusive scan of the chunk sums: within waves, then over
@@ -126,13 +156,31 @@ __global__ __launch_bounds__(1024) void queue_order_kernel(SimArgs a) {
 #pragma unroll
     for (int q = 0; q < QUEUE_CHUNK; ++q)
         if (lo + q < hi) {
-            a.seg_off[counter(lo + q)] = acc;
+            if (SMALL)
+                s_off[counter(lo + q)] = acc;
+            else
+                a.seg_off[counter(lo + q)] = acc;
             acc += cnt[q];
         }
     __syncthreads();
+    if constexpr (SMALL) {
+        // the segment list, as queue_fill_kernel lays it out
+        for (int32_t sg = tid; sg < n_seg; sg += nthr) {
+            const int32_t b = s_bin[sg];
+            if (b < 0) continue;
+            const int32_t run = sg / NB, j = sg - run * NB;
+            const int32_t n = a.n_walk[run];
+            const int64_t first = (int64_t)j * a.m_targ;
+            const int32_t c = b * rep + run % rep;
+            const int32_t pos = s_off[c] + atomicAdd(&s_cur[c], 1);
+            a.seg[pos] = make_int2((int32_t)((size_t)run * a.cap + first), (int32_t)min((int64_t)a.m_targ, n - first));
+        }
+    }
     for (int32_t c = tid; c < NC; c += nthr) {
-        a.occ_bin[c] = 0;
-        a.seg_cur[c] = 0;
+        if (!SMALL) {
+            a.occ_bin[c] = 0;
+            a.seg_cur[c] = 0;
+        }
         a.ev_bin[c] = 0.0f;
         a.n_bin[c] = 0;
     }
@@ -153,11 +201,22 @@ __global__ __launch_bounds__(256) void queue_fill_kernel(SimArgs a) {
     a.seg[pos] = make_int2((int32_t)g, (int32_t)min((int64_t)a.m_targ, n - first));
 }
 
+// Few runs (at most QUEUE_SMALL_SEGS segments, QUEUE_SMALL_BINS counters):
+// one block does all three steps; else three launches.
+bool queue_small(const SimArgs &a) {
+    return (int64_t)a.n_runs * a.n_bins <= QUEUE_SMALL_SEGS && a.n_bins <= QUEUE_SMALL_BINS &&
+           (int64_t)a.n_bins * a.seg_rep <= QUEUE_SMALL_BINS;
+}
+
 hipError_t launch_work_queue(const SimArgs &a, hipStream_t st) {
+    if (queue_small(a)) {
+        hipLaunchKernelGGL(queue_order_kernel<true>, dim3(1), dim3(1024), 0, st, a);
+        return hipGetLastError();
+    }
     const int64_t total = (int64_t)a.n_runs * a.n_bins;
     const unsigned g = (unsigned)((total + 255) / 256);
     hipLaunchKernelGGL(queue_count_kernel, dim3(g), dim3(256), 0, st, a);
-    hipLaunchKernelGGL(queue_order_kernel, dim3(1), dim3(1024), 0, st, a);
+    hipLaunchKernelGGL(queue_order_kernel<false>, dim3(1), dim3(1024), 0, st, a);
     hipLaunchKernelGGL(queue_fill_kernel, dim3(g), dim3(256), 0, st, a);
     return hipGetLastError();
 }
