@@ -24,7 +24,7 @@ __host__ __device__ inline size_t group_tables_bytes(int32_t R, int32_t n_chg) {
     return (16 * (size_t)R + 4 * ((size_t)R + 1 + (size_t)n_chg) + 15) & ~(size_t)15;
 }
 
-template <int L, bool LT>
+template <int L, bool LT, int BR>
 __global__ __launch_bounds__(64 * GROUP_WAVES) void ssa_group_kernel(SimArgs a, int32_t *__restrict__ xs) {
     extern __shared__ __align__(16) unsigned char gsm[];
     constexpr int G = 64 / L;
@@ -70,7 +70,7 @@ __global__ __launch_bounds__(64 * GROUP_WAVES) void ssa_group_kernel(SimArgs a, 
                 live = true;
             }
         }
-        group_walker<L>(a, tb, xs, run, k, live, iter, lx);
+        group_walker<L, BR>(a, tb, xs, run, k, live, iter, lx);
     }
 }
 
@@ -93,7 +93,14 @@ int group_cus() {
 
 bool group_tables_in_lds(const SimArgs &a) { return group_tables_bytes(a.R, a.n_chg) <= GROUP_LDS_TABLES; }
 
-template <int L, bool LT>
+// Blocks of at most GROUP_REG_RXNS reactions per lane (with the tables in
+// LDS) keep their descriptors and propensities in registers.
+#define GROUP_REG_RXNS 4
+bool group_regs(const SimArgs &a, int32_t lanes) {
+    return group_tables_in_lds(a) && (a.R + lanes - 1) / lanes <= GROUP_REG_RXNS;
+}
+
+template <int L, bool LT, int BR>
 hipError_t launch_group(const SimArgs &a, int32_t *xs, hipStream_t st) {
     constexpr int G = 64 / L;
     const size_t shmem =
@@ -101,7 +108,7 @@ hipError_t launch_group(const SimArgs &a, int32_t *xs, hipStream_t st) {
     static size_t last_shmem = 0;
     static int per_cu = 0;
     if (per_cu == 0 || shmem != last_shmem) {
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, ssa_group_kernel<L, LT>, 64 * GROUP_WAVES,
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, ssa_group_kernel<L, LT, BR>, 64 * GROUP_WAVES,
                                                          shmem) != hipSuccess ||
             per_cu < 1)
             per_cu = 1;
@@ -110,13 +117,14 @@ hipError_t launch_group(const SimArgs &a, int32_t *xs, hipStream_t st) {
     const int64_t walkers = (int64_t)a.n_runs * a.cap;
     const int64_t need = (walkers + (int64_t)GROUP_WAVES * G - 1) / ((int64_t)GROUP_WAVES * G);
     const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>(need, (int64_t)per_cu * group_cus()));
-    hipLaunchKernelGGL((ssa_group_kernel<L, LT>), dim3(blocks), dim3(64 * GROUP_WAVES), shmem, st, a, xs);
+    hipLaunchKernelGGL((ssa_group_kernel<L, LT, BR>), dim3(blocks), dim3(64 * GROUP_WAVES), shmem, st, a, xs);
     return hipGetLastError();
 }
 
 template <int L>
 hipError_t launch_group(const SimArgs &a, int32_t *xs, hipStream_t st) {
-    return group_tables_in_lds(a) ? launch_group<L, true>(a, xs, st) : launch_group<L, false>(a, xs, st);
+    if (group_regs(a, L)) return launch_group<L, true, GROUP_REG_RXNS>(a, xs, st);
+    return group_tables_in_lds(a) ? launch_group<L, true, 0>(a, xs, st) : launch_group<L, false, 0>(a, xs, st);
 }
 }  // namespace
 
@@ -132,12 +140,14 @@ hipError_t launch_ssa_group(const SimArgs &a, int32_t *xs, int32_t lanes, hipStr
 }
 
 const char *ssa_group_name(const SimArgs &a, int32_t lanes) {
-    const bool t = group_tables_in_lds(a);
-    switch (lanes) {
-    case 2: return t ? "ssa_group_kernel<2, true>" : "ssa_group_kernel<2, false>";
-    case 4: return t ? "ssa_group_kernel<4, true>" : "ssa_group_kernel<4, false>";
-    case 8: return t ? "ssa_group_kernel<8, true>" : "ssa_group_kernel<8, false>";
-    case 16: return t ? "ssa_group_kernel<16, true>" : "ssa_group_kernel<16, false>";
-    default: return t ? "ssa_group_kernel<32, true>" : "ssa_group_kernel<32, false>";
-    }
+    // 5 lane counts x (registers, tables in LDS, tables through the cache)
+    static const char *const names[5][3] = {
+        {"ssa_group_kernel<2, true, 4>", "ssa_group_kernel<2, true, 0>", "ssa_group_kernel<2, false, 0>"},
+        {"ssa_group_kernel<4, true, 4>", "ssa_group_kernel<4, true, 0>", "ssa_group_kernel<4, false, 0>"},
+        {"ssa_group_kernel<8, true, 4>", "ssa_group_kernel<8, true, 0>", "ssa_group_kernel<8, false, 0>"},
+        {"ssa_group_kernel<16, true, 4>", "ssa_group_kernel<16, true, 0>", "ssa_group_kernel<16, false, 0>"},
+        {"ssa_group_kernel<32, true, 4>", "ssa_group_kernel<32, true, 0>", "ssa_group_kernel<32, false, 0>"}};
+    const int li = lanes == 2 ? 0 : lanes == 4 ? 1 : lanes == 8 ? 2 : lanes == 16 ? 3 : 4;
+    const int vi = group_regs(a, lanes) ? 0 : group_tables_in_lds(a) ? 1 : 2;
+    return names[li][vi];
 }

@@ -86,8 +86,11 @@ struct GroupTables {
 
 // The walkers in slots k of run `run` for the groups with live set (k may
 // differ per group); lx is this group's slice of S counts in LDS.  Every lane
-// of the wave must call it.
-template <int L>
+// of the wave must call it.  BR > 0 (blocks of at most BR reactions): each
+// lane keeps its block's descriptors in registers for the whole interval and
+// its block's propensities from step 1 for step 3, instead of reading the
+// descriptors again every event.
+template <int L, int BR = 0>
 __device__ inline void group_walker(const SimArgs &a, const GroupTables &tb, int32_t *__restrict__ xs, int32_t run,
                                     int32_t k, bool live, uint32_t iter, int32_t *lx) {
     const int lane = threadIdx.x & 63;
@@ -117,14 +120,34 @@ __device__ inline void group_walker(const SimArgs &a, const GroupTables &tb, int
     // random numbers of L events at a time: lane gl of a group holds
     // -log(1 - u1) and u2 of the group's event (e & ~(L - 1)) + gl
     double rexp = 0.0, ru2 = 0.0;
+    constexpr int NR = BR > 0 ? BR : 1;
+    RxnDesc dr[NR];
+    double pr[NR];
+    if constexpr (BR > 0) {
+#pragma unroll
+        for (int b = 0; b < NR; ++b) {
+            dr[b] = RxnDesc{};
+            pr[b] = 0.0;
+            if (r_lo + b < r_hi) dr[b] = tb.desc[r_lo + b];
+        }
+    }
     while (__ballot(go)) {
         // 1. this lane's partial sum over its block
         double part = 0.0;
-        if (go)
+        if constexpr (BR > 0) {
+            if (go)
+#pragma unroll
+                for (int b = 0; b < NR; ++b)
+                    if (r_lo + b < r_hi) {
+                        pr[b] = propensity_from(dr[b], (uint32_t)lx[dr[b].s1], (uint32_t)lx[dr[b].s2]);
+                        part += pr[b];
+                    }
+        } else if (go) {
             for (int32_t r = r_lo; r < r_hi; ++r) {
                 const RxnDesc d = tb.desc[r];
                 part += propensity_from(d, (uint32_t)lx[d.s1], (uint32_t)lx[d.s2]);
             }
+        }
         // 2. group scan, a0, waiting time (e is the same on a group's lanes)
         if (go && (e & (L - 1)) == 0u) {
             const U4 rnd = philox4x32_10(e + (uint32_t)gl, (uint32_t)k, iter, 0u, k0, k1);
@@ -162,15 +185,26 @@ __device__ inline void group_walker(const SimArgs &a, const GroupTables &tb, int
             const double t2 = target - excl;
             double run_s = 0.0;
             int32_t last = -1;
-            for (int32_t r = r_lo; r < r_hi; ++r) {
-                const RxnDesc d = tb.desc[r];
-                const double ar = propensity_from(d, (uint32_t)lx[d.s1], (uint32_t)lx[d.s2]);
-                if (ar > 0.0) {
-                    last = r;
-                    run_s += ar;
-                    if (run_s > t2) {
-                        j = r;
-                        break;
+            if constexpr (BR > 0) {
+                // the propensities of step 1, in the same order
+#pragma unroll
+                for (int b = 0; b < NR; ++b)
+                    if (j < 0 && r_lo + b < r_hi && pr[b] > 0.0) {
+                        last = r_lo + b;
+                        run_s += pr[b];
+                        if (run_s > t2) j = r_lo + b;
+                    }
+            } else {
+                for (int32_t r = r_lo; r < r_hi; ++r) {
+                    const RxnDesc d = tb.desc[r];
+                    const double ar = propensity_from(d, (uint32_t)lx[d.s1], (uint32_t)lx[d.s2]);
+                    if (ar > 0.0) {
+                        last = r;
+                        run_s += ar;
+                        if (run_s > t2) {
+                            j = r;
+                            break;
+                        }
                     }
                 }
             }

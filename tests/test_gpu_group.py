@@ -41,10 +41,14 @@ def _random_cfg(S, R, seed, m_targ=4, n_runs=2, tau=0.05, n_iters=20):
                        seeds=np.arange(seed, seed + n_runs, dtype=np.uint64))
 
 
-def _compare(cfg, wpw, n_iters, max_frac=0.01, lds_tables=True):
+def _compare(cfg, wpw, n_iters, max_frac=0.01, tables="lds"):
+    """tables: 'regs' (descriptors and propensities of blocks of at most four
+    reactions in registers), 'lds' (tables in LDS) or 'cache' (through the
+    cache): the kernel variant the network and walkers per wave select."""
     we = _we()
     sim = we.sim_from_config(cfg, kernel=we.WE_KERNEL_GROUP, walkers_per_wave=wpw, max_iters=n_iters)
-    assert sim.propagation_kernel() == f"ssa_group_kernel<{64 // wpw}, {'true' if lds_tables else 'false'}>"
+    suffix = {"regs": "true, 4", "lds": "true, 0", "cache": "false, 0"}[tables]
+    assert sim.propagation_kernel() == f"ssa_group_kernel<{64 // wpw}, {suffix}>"
     sim.step(n_iters)
     sim.synchronize()
     total = same = 0
@@ -76,7 +80,15 @@ def test_group_kernel_tables_through_the_cache_match_oracle(wpw):
     """A network whose descriptors and changes exceed the 48 KB LDS table
     budget (3200 reactions): the variant reading them through the cache."""
     _say(f"case: group kernel, {wpw} walkers per wave, random 300x3200 network (tables in global memory)")
-    _compare(_random_cfg(300, 3200, 23, tau=0.002, n_iters=5), wpw, 5, lds_tables=False)
+    _compare(_random_cfg(300, 3200, 23, tau=0.002, n_iters=5), wpw, 5, tables="cache")
+
+
+@pytest.mark.parametrize("wpw", [4, 2])
+def test_group_kernel_register_blocks_match_oracle(wpw):
+    """60 reactions on 16 or 32 lanes per walker (blocks of at most four
+    reactions): descriptors and propensities held in registers."""
+    _say(f"case: group kernel, {wpw} walkers per wave, random 12x60 network (register blocks)")
+    _compare(_random_cfg(12, 60, 29), wpw, 20, tables="regs")
 
 
 @pytest.mark.parametrize("wpw", [32, 8])
@@ -86,7 +98,7 @@ def test_group_kernel_schlogl_with_recycling_matches_oracle(wpw):
     a run may differ, where a walker did)."""
     _say(f"case: group kernel, {wpw} walkers per wave, Schloegl with recycling, 3 runs x 40 iterations")
     cfg = wl.schlogl_config(n_runs=3, seed0=5, n_iters=40)
-    sim = _compare(cfg, wpw, 40)
+    sim = _compare(cfg, wpw, 40, tables="regs")
     for r in range(3):
         o = orc.OracleWE(cfg, int(cfg.seeds[r]))
         o.step(40)
