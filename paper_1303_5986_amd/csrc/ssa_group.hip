@@ -93,11 +93,13 @@ int group_cus() {
 
 bool group_tables_in_lds(const SimArgs &a) { return group_tables_bytes(a.R, a.n_chg) <= GROUP_LDS_TABLES; }
 
-// Blocks of at most GROUP_REG_RXNS reactions per lane (with the tables in
-// LDS) keep their descriptors and propensities in registers.
-#define GROUP_REG_RXNS 4
-bool group_regs(const SimArgs &a, int32_t lanes) {
-    return group_tables_in_lds(a) && (a.R + lanes - 1) / lanes <= GROUP_REG_RXNS;
+// Blocks of at most 8 reactions per lane (with the tables in LDS) keep their
+// descriptors and propensities in registers: 4 register slots for blocks of
+// up to 4 (more would cost them occupancy), 8 for blocks of 5 to 8.
+int group_regs(const SimArgs &a, int32_t lanes) {
+    if (!group_tables_in_lds(a)) return 0;
+    const int32_t B = (a.R + lanes - 1) / lanes;
+    return B <= 4 ? 4 : B <= 8 ? 8 : 0;
 }
 
 template <int L, bool LT, int BR>
@@ -123,7 +125,9 @@ hipError_t launch_group(const SimArgs &a, int32_t *xs, hipStream_t st) {
 
 template <int L>
 hipError_t launch_group(const SimArgs &a, int32_t *xs, hipStream_t st) {
-    if (group_regs(a, L)) return launch_group<L, true, GROUP_REG_RXNS>(a, xs, st);
+    const int br = group_regs(a, L);
+    if (br == 4) return launch_group<L, true, 4>(a, xs, st);
+    if (br == 8) return launch_group<L, true, 8>(a, xs, st);
     return group_tables_in_lds(a) ? launch_group<L, true, 0>(a, xs, st) : launch_group<L, false, 0>(a, xs, st);
 }
 }  // namespace
@@ -140,14 +144,20 @@ hipError_t launch_ssa_group(const SimArgs &a, int32_t *xs, int32_t lanes, hipStr
 }
 
 const char *ssa_group_name(const SimArgs &a, int32_t lanes) {
-    // 5 lane counts x (registers, tables in LDS, tables through the cache)
-    static const char *const names[5][3] = {
-        {"ssa_group_kernel<2, true, 4>", "ssa_group_kernel<2, true, 0>", "ssa_group_kernel<2, false, 0>"},
-        {"ssa_group_kernel<4, true, 4>", "ssa_group_kernel<4, true, 0>", "ssa_group_kernel<4, false, 0>"},
-        {"ssa_group_kernel<8, true, 4>", "ssa_group_kernel<8, true, 0>", "ssa_group_kernel<8, false, 0>"},
-        {"ssa_group_kernel<16, true, 4>", "ssa_group_kernel<16, true, 0>", "ssa_group_kernel<16, false, 0>"},
-        {"ssa_group_kernel<32, true, 4>", "ssa_group_kernel<32, true, 0>", "ssa_group_kernel<32, false, 0>"}};
+    // 5 lane counts x (4 or 8 register slots, tables in LDS, through the cache)
+    static const char *const names[5][4] = {
+        {"ssa_group_kernel<2, true, 4>", "ssa_group_kernel<2, true, 8>", "ssa_group_kernel<2, true, 0>",
+         "ssa_group_kernel<2, false, 0>"},
+        {"ssa_group_kernel<4, true, 4>", "ssa_group_kernel<4, true, 8>", "ssa_group_kernel<4, true, 0>",
+         "ssa_group_kernel<4, false, 0>"},
+        {"ssa_group_kernel<8, true, 4>", "ssa_group_kernel<8, true, 8>", "ssa_group_kernel<8, true, 0>",
+         "ssa_group_kernel<8, false, 0>"},
+        {"ssa_group_kernel<16, true, 4>", "ssa_group_kernel<16, true, 8>", "ssa_group_kernel<16, true, 0>",
+         "ssa_group_kernel<16, false, 0>"},
+        {"ssa_group_kernel<32, true, 4>", "ssa_group_kernel<32, true, 8>", "ssa_group_kernel<32, true, 0>",
+         "ssa_group_kernel<32, false, 0>"}};
     const int li = lanes == 2 ? 0 : lanes == 4 ? 1 : lanes == 8 ? 2 : lanes == 16 ? 3 : 4;
-    const int vi = group_regs(a, lanes) ? 0 : group_tables_in_lds(a) ? 1 : 2;
+    const int br = group_regs(a, lanes);
+    const int vi = br == 4 ? 0 : br == 8 ? 1 : group_tables_in_lds(a) ? 2 : 3;
     return names[li][vi];
 }

@@ -47,7 +47,7 @@ def _compare(cfg, wpw, n_iters, max_frac=0.01, tables="lds"):
     cache): the kernel variant the network and walkers per wave select."""
     we = _we()
     sim = we.sim_from_config(cfg, kernel=we.WE_KERNEL_GROUP, walkers_per_wave=wpw, max_iters=n_iters)
-    suffix = {"regs": "true, 4", "lds": "true, 0", "cache": "false, 0"}[tables]
+    suffix = {"regs": "true, 4", "regs8": "true, 8", "lds": "true, 0", "cache": "false, 0"}[tables]
     assert sim.propagation_kernel() == f"ssa_group_kernel<{64 // wpw}, {suffix}>"
     sim.step(n_iters)
     sim.synchronize()
@@ -72,7 +72,7 @@ def _compare(cfg, wpw, n_iters, max_frac=0.01, tables="lds"):
 @pytest.mark.parametrize("wpw", [32, 16, 8, 4, 2])
 def test_group_kernel_random_network_matches_oracle(wpw):
     _say(f"case: group kernel, {wpw} walkers per wave, random 30x200 network, 2 runs x 20 iterations")
-    _compare(_random_cfg(30, 200, 17), wpw, 20)
+    _compare(_random_cfg(30, 200, 17), wpw, 20, tables="regs8" if wpw == 2 else "lds")   # blocks of 7 on 32 lanes
 
 
 @pytest.mark.parametrize("wpw", [8, 2])
@@ -83,12 +83,13 @@ def test_group_kernel_tables_through_the_cache_match_oracle(wpw):
     _compare(_random_cfg(300, 3200, 23, tau=0.002, n_iters=5), wpw, 5, tables="cache")
 
 
-@pytest.mark.parametrize("wpw", [4, 2])
-def test_group_kernel_register_blocks_match_oracle(wpw):
+@pytest.mark.parametrize("wpw,tables", [(4, "regs"), (2, "regs"), (8, "regs8")])
+def test_group_kernel_register_blocks_match_oracle(wpw, tables):
     """60 reactions on 16 or 32 lanes per walker (blocks of at most four
-    reactions): descriptors and propensities held in registers."""
+    reactions) or on 8 (blocks of 8): descriptors and propensities held in
+    registers."""
     _say(f"case: group kernel, {wpw} walkers per wave, random 12x60 network (register blocks)")
-    _compare(_random_cfg(12, 60, 29), wpw, 20, tables="regs")
+    _compare(_random_cfg(12, 60, 29), wpw, 20, tables=tables)
 
 
 @pytest.mark.parametrize("wpw", [32, 8])
