@@ -410,41 +410,70 @@ struct MergeQueues {
     }
 };
 
-// n > M with at most 64 walkers: walker q lives in lane q.  Each merge finds
-// the lightest live walker by a wave minimum (ties: the lowest lane, which is
-// the lowest slot), then the lightest of the rest; the merged-away walker's
-// lane holds +inf from then on.  The same pairs, draws and sums as merge_bin.
-template <class Idx>
+// n > M with at most 64 K walkers: walker q lives in lane q % 64, register
+// q / 64.  Each merge finds the lightest live walker by a wave minimum (ties:
+// the lowest register, then the lowest lane, i.e. the lowest slot), then the
+// lightest of the rest; the merged-away walker holds +inf from then on.  The
+// same pairs, draws and sums as merge_bin, without its sort of the bin.
+template <int K, class Idx>
 __device__ void merge_bin_lanes(const RunWork<Idx> &wk, int32_t p0, int32_t nb, int32_t M, int32_t b, int32_t o0,
                                 const BinOut &out, uint32_t iter, uint32_t k0, uint32_t k1, int lane) {
     const double inf = __builtin_huge_val();
-    double wv = lane < nb ? wk.w[p0 + lane] : inf;
+    double wv[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) wv[k] = 64 * k + lane < nb ? wk.w[p0 + 64 * k + lane] : inf;
+    // the lowest slot among the walkers of weight w, given each register's ballot
+    auto lowest = [&](const double *v, double w) {
+        int32_t q = -1;
+#pragma unroll
+        for (int k = K - 1; k >= 0; --k) {
+            const unsigned long long m = __ballot(v[k] == w);
+            if (m) q = 64 * k + __ffsll((long long)m) - 1;
+        }
+        return q;
+    };
     double ul = 0.0;
     for (int32_t m = 0; m < nb - M; ++m) {
         if ((m & 63) == 0) {   // the next 64 merge draws, one per lane
             const U4 rr = philox4x32_10((uint32_t)(m + lane), (uint32_t)b, iter, 1u, k0, k1);
             ul = uniform53(rr.x, rr.y);
         }
-        const double wi = wave_min(wv);
-        const int qi = __ffsll((long long)__ballot(wv == wi)) - 1;
-        const double wrest = lane == qi ? inf : wv;
-        const double wj = wave_min(wrest);
-        const int qj = __ffsll((long long)__ballot(wrest == wj)) - 1;
+        double lm = wv[0];
+#pragma unroll
+        for (int k = 1; k < K; ++k) lm = fmin(lm, wv[k]);
+        const double wi = wave_min(lm);
+        const int32_t qi = lowest(wv, wi);
+        double wr[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) wr[k] = (64 * k + lane == qi) ? inf : wv[k];
+        double lr = wr[0];
+#pragma unroll
+        for (int k = 1; k < K; ++k) lr = fmin(lr, wr[k]);
+        const double wj = wave_min(lr);
+        const int32_t qj = lowest(wr, wj);
         const double u = rs_readlane(ul, m & 63);
         const double sum = wi + wj;
         const double p_i = wi / sum;
-        const int keep = (u < p_i) ? qi : qj;
-        const int drop = (keep == qi) ? qj : qi;
-        if (lane == keep) wv = sum;
-        if (lane == drop) wv = inf;
+        const int32_t keep = (u < p_i) ? qi : qj;
+        const int32_t drop = (keep == qi) ? qj : qi;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            if (64 * k + lane == keep) wv[k] = sum;
+            if (64 * k + lane == drop) wv[k] = inf;
+        }
     }
-    const bool live = lane < nb && wv != inf;
-    int32_t tot;
-    const int32_t o = o0 + wave_excl_scan(live ? 1 : 0, lane, &tot);
-    if (live) {
-        out.orig[o] = wk.list[p0 + lane];
-        out.wn[o] = wv;
-        out.obin[o] = b;
+    int32_t o = o0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const bool live = 64 * k + lane < nb && wv[k] != inf;
+        int32_t tot;
+        const int32_t ok = o + wave_excl_scan(live ? 1 : 0, lane, &tot);
+        if (live) {
+            out.orig[ok] = wk.list[p0 + 64 * k + lane];
+            out.wn[ok] = wv[k];
+            out.obin[ok] = b;
+        }
+        o += tot;
     }
 }
 
@@ -711,7 +740,9 @@ __device__ void resample_bin(const SimArgs &a, const RunWork<Idx> &wk, const Bin
         if (nb <= 64) split_bin_lanes(wk, p0, nb, M, b, o0, out, lane);
         else split_bin(wk, p0, nb, M, b, o0, out, lane);
     } else {
-        if (nb <= 64) merge_bin_lanes(wk, p0, nb, M, b, o0, out, iter, k0, k1, lane);
+        if (nb <= 64) merge_bin_lanes<1>(wk, p0, nb, M, b, o0, out, iter, k0, k1, lane);
+        else if (nb <= 128) merge_bin_lanes<2>(wk, p0, nb, M, b, o0, out, iter, k0, k1, lane);
+        else if (nb <= 256) merge_bin_lanes<4>(wk, p0, nb, M, b, o0, out, iter, k0, k1, lane);
         else merge_bin<Idx, false>(wk, p0, nb, M, b, o0, out, iter, k0, k1, lane);
     }
 }
