@@ -288,30 +288,58 @@ __device__ void rw_flux_bin(double *__restrict__ Frow, const RunWork<Idx> &wk, i
     }
 }
 
-// n < M with at most 64 parents: parent q lives in lane q, its weight, copy
-// count and per-copy share in registers; the same hand-out as split_bin.
-template <class Idx>
+// n < M with at most 64 K parents: lane L owns the contiguous parents
+// [K L, K L + K) (as split_bin's lanes do), their weights, copy counts and
+// per-copy shares in registers; the same hand-out as split_bin: the lowest
+// lane holding the wave's largest share holds the lowest tied slot, and
+// within a lane the lowest slot wins a tie.
+template <int K, class Idx>
 __device__ void split_bin_lanes(const RunWork<Idx> &wk, int32_t p0, int32_t nb, int32_t M, int32_t b, int32_t o0,
                                 const BinOut &out, int lane) {
-    const bool own = lane < nb;
-    const double wq = own ? wk.w[p0 + lane] : 0.0;
-    int32_t c = 1;
-    double bs = own ? wq / 1.0 : -1.0;
+    double wq[K];
+    int32_t c[K];
+    double bs = -1.0;
+    int32_t bk = -1;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int32_t q = K * lane + k;
+        wq[k] = q < nb ? wk.w[p0 + q] : 0.0;
+        c[k] = 1;
+        if (q < nb) {
+            const double sh = wq[k] / 1.0;
+            if (sh > bs) { bs = sh; bk = k; }
+        }
+    }
     for (int32_t e = nb; e < M; ++e) {
         const double mx = wave_max(bs);
         const int wl = __ffsll((long long)__ballot(bs == mx)) - 1;
         if (lane == wl) {
-            c += 1;
-            bs = wq / (double)c;
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+                if (k == bk) c[k] += 1;
+            bs = -1.0;
+            bk = -1;
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+                if (K * lane + k < nb) {
+                    const double sh = wq[k] / (double)c[k];
+                    if (sh > bs) { bs = sh; bk = k; }
+                }
         }
     }
+    int32_t cl = 0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) cl += K * lane + k < nb ? c[k] : 0;
     int32_t tot;
-    int32_t o = o0 + wave_excl_scan(own ? c : 0, lane, &tot);
-    if (own) {
-        const double share = wq / (double)c;
-        const int32_t k = wk.list[p0 + lane];
-        for (int32_t r = 0; r < c; ++r) {
-            out.orig[o] = k;
+    int32_t o = o0 + wave_excl_scan(cl, lane, &tot);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int32_t q = K * lane + k;
+        if (q >= nb) continue;
+        const double share = wq[k] / (double)c[k];
+        const int32_t kk = wk.list[p0 + q];
+        for (int32_t r = 0; r < c[k]; ++r) {
+            out.orig[o] = kk;
             out.wn[o] = share;
             out.obin[o] = b;
             ++o;
@@ -737,7 +765,8 @@ __device__ void resample_bin(const SimArgs &a, const RunWork<Idx> &wk, const Bin
             out.obin[o0 + q] = b;
         }
     } else if (nb < M) {
-        if (nb <= 64) split_bin_lanes(wk, p0, nb, M, b, o0, out, lane);
+        if (nb <= 64) split_bin_lanes<1>(wk, p0, nb, M, b, o0, out, lane);
+        else if (nb <= 128) split_bin_lanes<2>(wk, p0, nb, M, b, o0, out, lane);
         else split_bin(wk, p0, nb, M, b, o0, out, lane);
     } else {
         if (nb <= 64) merge_bin_lanes<1>(wk, p0, nb, M, b, o0, out, iter, k0, k1, lane);
