@@ -843,15 +843,40 @@ __device__ void resample_run_t(const SimArgs &a, const double *__restrict__ w_cu
     }
     for (int32_t i = tid; i < P * NB; i += nthr) cursor[i] = 0;
     __syncthreads();
+    // counts per bin and per cursor row: each wave takes 64 consecutive slots
+    // (one cursor row: per_row is a multiple of 64) and adds each bin's group
+    // of lanes with one LDS atomic (walkers sit in slot order by their
+    // previous bin, so a chunk holds few bins, and LDS atomics on one address
+    // serialize)
     int64_t my_ev = 0;
-    for (int32_t k = tid; k < n; k += nthr) {
-        const int32_t b = sbin[k];
-        const uint32_t ev = a.ev_walker[base + k];
-        wk.tag[k] = (uint16_t)(b | (srec[k] ? 0x8000 : 0));
-        atomicAdd(&cnt[b], 1);
-        atomicAdd(&cursor[(k / per_row) * NB + b], 1);
-        if (a.queue_stats) atomicAdd(&evb[b], (float)ev);
-        my_ev += ev;
+    for (int32_t c0 = wave * 64; c0 < n; c0 += nthr) {
+        const int32_t k = c0 + lane;
+        const bool valid = k < n;
+        int32_t b = -1;
+        uint32_t ev = 0u;
+        if (valid) {
+            b = sbin[k];
+            ev = a.ev_walker[base + k];
+            wk.tag[k] = (uint16_t)(b | (srec[k] ? 0x8000 : 0));
+            my_ev += ev;
+        }
+        const int32_t row = c0 / per_row;
+        unsigned long long todo = __ballot(valid);
+        while (todo) {
+            const int leader = __ffsll((long long)todo) - 1;
+            const int32_t lb = __shfl(b, leader, 64);
+            const bool mine = valid && b == lb;
+            const unsigned long long grp = __ballot(mine);
+            float gev = mine ? (float)ev : 0.0f;
+            for (int d = 32; d > 0; d >>= 1) gev += __shfl_xor(gev, d, 64);
+            if (lane == leader) {
+                const int32_t g = (int32_t)__popcll(grp);
+                atomicAdd(&cnt[lb], g);
+                atomicAdd(&cursor[row * NB + lb], g);
+                if (a.queue_stats) atomicAdd(&evb[lb], gev);
+            }
+            todo &= ~grp;
+        }
     }
     ev_part[tid] = my_ev;
     __syncthreads();
