@@ -163,6 +163,21 @@ __device__ __forceinline__ double wave_min(double v) {
     return fmin(fmin(rs_readlane(v, 0), rs_readlane(v, 16)), fmin(rs_readlane(v, 32), rs_readlane(v, 48)));
 }
 
+// Sum over the 64 lanes (every lane gets it), by the steps of wave_max.
+template <int CTRL>
+__device__ __forceinline__ float rs_dpp_f32(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float wave_sum_f32(float v) {
+    v += rs_dpp_f32<0xB1>(v);
+    v += rs_dpp_f32<0x4E>(v);
+    v += rs_dpp_f32<0x141>(v);
+    v += rs_dpp_f32<0x140>(v);
+    const int32_t bits = __float_as_int(v);
+    return (__int_as_float(__builtin_amdgcn_readlane(bits, 0)) + __int_as_float(__builtin_amdgcn_readlane(bits, 16))) +
+           (__int_as_float(__builtin_amdgcn_readlane(bits, 32)) + __int_as_float(__builtin_amdgcn_readlane(bits, 48)));
+}
+
 __device__ __forceinline__ int32_t wave_min_i32(int32_t v) {
     for (int d = 32; d > 0; d >>= 1) v = min(v, __shfl_xor(v, d, 64));
     return v;
@@ -797,6 +812,7 @@ __device__ void resample_run_t(const SimArgs &a, const double *__restrict__ w_cu
     const int lane = tid & 63, wave = tid >> 6, n_waves = nthr >> 6;
     const int32_t NB = a.n_bins, M = a.m_targ, cap = a.cap;
     __shared__ int64_t ev_part[RESAMPLE_THREADS];
+    __shared__ int32_t any_rec;   // 1 when some walker was recycled this interval
     int32_t *cnt = reinterpret_cast<int32_t *>(lds);   // [NB]
     int32_t *start = cnt + NB;                          // [NB+1]
     int32_t *ostart = start + NB + 1;                   // [NB+1]
@@ -842,6 +858,7 @@ __device__ void resample_run_t(const SimArgs &a, const double *__restrict__ w_cu
         evb[b] = 0.0f;
     }
     for (int32_t i = tid; i < P * NB; i += nthr) cursor[i] = 0;
+    if (tid == 0) any_rec = 0;
     __syncthreads();
     // counts per bin and per cursor row: each wave takes 64 consecutive slots
     // (one cursor row: per_row is a multiple of 64) and adds each bin's group
@@ -854,12 +871,15 @@ __device__ void resample_run_t(const SimArgs &a, const double *__restrict__ w_cu
         const bool valid = k < n;
         int32_t b = -1;
         uint32_t ev = 0u;
+        bool rc = false;
         if (valid) {
             b = sbin[k];
             ev = a.ev_walker[base + k];
-            wk.tag[k] = (uint16_t)(b | (srec[k] ? 0x8000 : 0));
+            rc = srec[k] != 0;
+            wk.tag[k] = (uint16_t)(b | (rc ? 0x8000 : 0));
             my_ev += ev;
         }
+        if (__ballot(rc) && lane == 0) any_rec = 1;
         const int32_t row = c0 / per_row;
         unsigned long long todo = __ballot(valid);
         while (todo) {
@@ -867,8 +887,7 @@ __device__ void resample_run_t(const SimArgs &a, const double *__restrict__ w_cu
             const int32_t lb = __shfl(b, leader, 64);
             const bool mine = valid && b == lb;
             const unsigned long long grp = __ballot(mine);
-            float gev = mine ? (float)ev : 0.0f;
-            for (int d = 32; d > 0; d >>= 1) gev += __shfl_xor(gev, d, 64);
+            const float gev = a.queue_stats ? wave_sum_f32(mine ? (float)ev : 0.0f) : 0.0f;
             if (lane == leader) {
                 const int32_t g = (int32_t)__popcll(grp);
                 atomicAdd(&cnt[lb], g);
@@ -958,7 +977,7 @@ __device__ void resample_run_t(const SimArgs &a, const double *__restrict__ w_cu
         for (int32_t t = lane; t < nthr; t += 64) ev += ev_part[t];
         for (int d = 32; d > 0; d >>= 1) ev += __shfl_xor(ev, d, 64);
         double f = 0.0;
-        for (int32_t c0 = 0; c0 < n; c0 += 64) {
+        for (int32_t c0 = 0; any_rec && c0 < n; c0 += 64) {   // no recycled walker: f stays 0
             const int32_t k = c0 + lane;
             const bool rec = k < n && (wk.tag[k] & 0x8000);
             unsigned long long rm = __ballot(rec);
