@@ -782,11 +782,14 @@ __device__ void resample_bin(const SimArgs &a, const RunWork<Idx> &wk, const Bin
     } else if (nb < M) {
         if (nb <= 64) split_bin_lanes<1>(wk, p0, nb, M, b, o0, out, lane);
         else if (nb <= 128) split_bin_lanes<2>(wk, p0, nb, M, b, o0, out, lane);
+        else if (nb <= 256) split_bin_lanes<4>(wk, p0, nb, M, b, o0, out, lane);
+        else if (nb <= 512) split_bin_lanes<8>(wk, p0, nb, M, b, o0, out, lane);
         else split_bin(wk, p0, nb, M, b, o0, out, lane);
     } else {
         if (nb <= 64) merge_bin_lanes<1>(wk, p0, nb, M, b, o0, out, iter, k0, k1, lane);
         else if (nb <= 128) merge_bin_lanes<2>(wk, p0, nb, M, b, o0, out, iter, k0, k1, lane);
         else if (nb <= 256) merge_bin_lanes<4>(wk, p0, nb, M, b, o0, out, iter, k0, k1, lane);
+        else if (nb <= 512) merge_bin_lanes<8>(wk, p0, nb, M, b, o0, out, iter, k0, k1, lane);
         else merge_bin<Idx, false>(wk, p0, nb, M, b, o0, out, iter, k0, k1, lane);
     }
 }
