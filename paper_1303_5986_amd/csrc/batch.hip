@@ -40,20 +40,25 @@
 
 namespace {
 
+// V_GROUPR_L: the group kernel with L lanes per walker for members whose
+// lane blocks hold at most BATCH_GROUP_REG reactions (descriptors and
+// propensities in registers, read once per walker and interval).
 enum Variant {
     V_LANE_1_4 = 0, V_LANE_2_8, V_LANE_8_16, V_LANE_16_32,
     V_GROUP_2, V_GROUP_4, V_GROUP_8, V_GROUP_16, V_GROUP_32,
+    V_GROUPR_2, V_GROUPR_4, V_GROUPR_8, V_GROUPR_16, V_GROUPR_32,
     V_WAVE, V_COUNT
 };
+#define BATCH_GROUP_REG 8
 
 // Walker slots per work item of a variant.
 int32_t tile_of(int v) {
     switch (v) {
-    case V_GROUP_2: return 32;
-    case V_GROUP_4: return 16;
-    case V_GROUP_8: return 8;
-    case V_GROUP_16: return 4;
-    case V_GROUP_32: return 2;
+    case V_GROUP_2: case V_GROUPR_2: return 32;
+    case V_GROUP_4: case V_GROUPR_4: return 16;
+    case V_GROUP_8: case V_GROUPR_8: return 8;
+    case V_GROUP_16: case V_GROUPR_16: return 4;
+    case V_GROUP_32: case V_GROUPR_32: return 2;
     case V_WAVE: return 1;
     default: return 64;
     }
@@ -66,14 +71,16 @@ struct Item {
 Variant variant_of(const we_sim *s) {
     const int32_t S = s->S, R = s->net->R;
     if (s->kernel == WE_KERNEL_WAVE) return V_WAVE;
-    if (s->kernel == WE_KERNEL_GROUP)
+    if (s->kernel == WE_KERNEL_GROUP) {
+        const bool reg = (R + s->group_lanes - 1) / s->group_lanes <= BATCH_GROUP_REG;
         switch (s->group_lanes) {
-        case 2: return V_GROUP_2;
-        case 4: return V_GROUP_4;
-        case 8: return V_GROUP_8;
-        case 16: return V_GROUP_16;
-        default: return V_GROUP_32;
+        case 2: return reg ? V_GROUPR_2 : V_GROUP_2;
+        case 4: return reg ? V_GROUPR_4 : V_GROUP_4;
+        case 8: return reg ? V_GROUPR_8 : V_GROUP_8;
+        case 16: return reg ? V_GROUPR_16 : V_GROUP_16;
+        default: return reg ? V_GROUPR_32 : V_GROUP_32;
         }
+    }
     if (S <= 1 && R <= 4) return V_LANE_1_4;
     if (S <= 2 && R <= 8) return V_LANE_2_8;
     if (S <= 8 && R <= 16) return V_LANE_8_16;
@@ -131,8 +138,9 @@ __global__ __launch_bounds__(256) void batch_wave_kernel(const SimArgs *__restri
 
 // Group variant: a work item is 64 / L consecutive slots of one run, one
 // group of L lanes per slot; lx slices are s_max ints (the largest species
-// count among the members on this variant).
-template <int L>
+// count among the members on this variant).  BR > 0: the members' lane
+// blocks hold at most BR reactions, kept in registers (group_walker).
+template <int L, int BR = 0>
 __global__ __launch_bounds__(256) void batch_group_kernel(const SimArgs *__restrict__ args,
                                                           int32_t *const *__restrict__ xptr,
                                                           const Item *__restrict__ items, int32_t n_items,
@@ -152,7 +160,7 @@ __global__ __launch_bounds__(256) void batch_group_kernel(const SimArgs *__restr
         const int32_t k = it.slot + grp;
         const bool live = k < a.cap && k < a.n_walk[it.run];
         const GroupTables tb{a.desc, a.chg_ptr, a.chg};
-        group_walker<L>(a, tb, xptr[it.sim], it.run, k, live, *a.iter_dev, lx);
+        group_walker<L, BR>(a, tb, xptr[it.sim], it.run, k, live, *a.iter_dev, lx);
     }
 }
 
@@ -356,6 +364,25 @@ we_status launch_batch_iteration(we_batch *b, hipStream_t st, bool capture) {
         case V_LANE_16_32:
             hipLaunchKernelGGL((batch_lane_kernel<16, 32>), dim3(blocks), dim3(256), 0, st, b->d_args, xp, b->d_items[v], n, cnt);
             break;
+        case V_GROUPR_2:
+        case V_GROUPR_4:
+        case V_GROUPR_8:
+        case V_GROUPR_16:
+        case V_GROUPR_32: {
+            const int32_t G = tile_of(v);
+            const size_t shmem = sizeof(int32_t) * 4 * (size_t)G * b->s_group;
+            if (v == V_GROUPR_2)
+                hipLaunchKernelGGL((batch_group_kernel<2, BATCH_GROUP_REG>), dim3(blocks), dim3(256), shmem, st, b->d_args, xp, b->d_items[v], n, cnt, b->s_group);
+            else if (v == V_GROUPR_4)
+                hipLaunchKernelGGL((batch_group_kernel<4, BATCH_GROUP_REG>), dim3(blocks), dim3(256), shmem, st, b->d_args, xp, b->d_items[v], n, cnt, b->s_group);
+            else if (v == V_GROUPR_8)
+                hipLaunchKernelGGL((batch_group_kernel<8, BATCH_GROUP_REG>), dim3(blocks), dim3(256), shmem, st, b->d_args, xp, b->d_items[v], n, cnt, b->s_group);
+            else if (v == V_GROUPR_16)
+                hipLaunchKernelGGL((batch_group_kernel<16, BATCH_GROUP_REG>), dim3(blocks), dim3(256), shmem, st, b->d_args, xp, b->d_items[v], n, cnt, b->s_group);
+            else
+                hipLaunchKernelGGL((batch_group_kernel<32, BATCH_GROUP_REG>), dim3(blocks), dim3(256), shmem, st, b->d_args, xp, b->d_items[v], n, cnt, b->s_group);
+            break;
+        }
         case V_GROUP_2:
         case V_GROUP_4:
         case V_GROUP_8:
