@@ -56,6 +56,7 @@
 // long as the rows hold at most this many counters.
 #define RESAMPLE_PLACE_INTS 4096
 // Bin-parallel resampling: runs fewer than this, bins at least this many.
+#define RESAMPLE_GROUP_COUNT_M 32
 #define RESAMPLE_BIN_PARALLEL_RUNS 256
 #define RESAMPLE_BIN_PARALLEL_BINS 32
 // Threads per run: up to 16 waves, so up to 16 bins are split/merged at
@@ -782,14 +783,11 @@ __device__ void resample_bin(const SimArgs &a, const RunWork<Idx> &wk, const Bin
     } else if (nb < M) {
         if (nb <= 64) split_bin_lanes<1>(wk, p0, nb, M, b, o0, out, lane);
         else if (nb <= 128) split_bin_lanes<2>(wk, p0, nb, M, b, o0, out, lane);
-        else if (nb <= 256) split_bin_lanes<4>(wk, p0, nb, M, b, o0, out, lane);
-        else if (nb <= 512) split_bin_lanes<8>(wk, p0, nb, M, b, o0, out, lane);
         else split_bin(wk, p0, nb, M, b, o0, out, lane);
     } else {
         if (nb <= 64) merge_bin_lanes<1>(wk, p0, nb, M, b, o0, out, iter, k0, k1, lane);
         else if (nb <= 128) merge_bin_lanes<2>(wk, p0, nb, M, b, o0, out, iter, k0, k1, lane);
         else if (nb <= 256) merge_bin_lanes<4>(wk, p0, nb, M, b, o0, out, iter, k0, k1, lane);
-        else if (nb <= 512) merge_bin_lanes<8>(wk, p0, nb, M, b, o0, out, iter, k0, k1, lane);
         else merge_bin<Idx, false>(wk, p0, nb, M, b, o0, out, iter, k0, k1, lane);
     }
 }
@@ -864,10 +862,11 @@ __device__ void resample_run_t(const SimArgs &a, const double *__restrict__ w_cu
     if (tid == 0) any_rec = 0;
     __syncthreads();
     // counts per bin and per cursor row: each wave takes 64 consecutive slots
-    // (one cursor row: per_row is a multiple of 64) and adds each bin's group
-    // of lanes with one LDS atomic (walkers sit in slot order by their
-    // previous bin, so a chunk holds few bins, and LDS atomics on one address
-    // serialize)
+    // (one cursor row: per_row is a multiple of 64); with at least
+    // RESAMPLE_GROUP_COUNT_M walkers per bin it adds each bin's group of lanes
+    // with one LDS atomic (walkers sit in slot order by their previous bin, so
+    // a chunk holds few bins, and LDS atomics on one address serialize), with
+    // smaller bins one atomic per walker (many bins per chunk, few collisions)
     int64_t my_ev = 0;
     for (int32_t c0 = wave * 64; c0 < n; c0 += nthr) {
         const int32_t k = c0 + lane;
@@ -884,6 +883,14 @@ __device__ void resample_run_t(const SimArgs &a, const double *__restrict__ w_cu
         }
         if (__ballot(rc) && lane == 0) any_rec = 1;
         const int32_t row = c0 / per_row;
+        if (M < RESAMPLE_GROUP_COUNT_M) {   // small bins: many per chunk, little contention
+            if (valid) {
+                atomicAdd(&cnt[b], 1);
+                atomicAdd(&cursor[row * NB + b], 1);
+                if (a.queue_stats) atomicAdd(&evb[b], (float)ev);
+            }
+            continue;
+        }
         unsigned long long todo = __ballot(valid);
         while (todo) {
             const int leader = __ffsll((long long)todo) - 1;

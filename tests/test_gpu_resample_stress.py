@@ -5,8 +5,8 @@ iteration is resampling alone: the ensembles below are built to stress the
 split/merge code -- bins far above M with many equal weights (the merge
 order hinges on the slot tie-break), bins far below M with equal shares
 (the split order hinges on the same tie-break), zero weights, bins on both
-sides of 64, 128, 256 and 512 walkers (up to 512 a bin is held one to eight
-walkers per lane), and sizes
+sides of 64, 128, 256 and 512 walkers (a merging bin of up to 256 and a
+splitting bin of up to 128 is held one to four walkers per lane), and sizes
 on both sides of the LDS limit of the per-run working arrays.  Walkers, weights,
 bins, parents and the recycled-weight record must equal the oracle's
 bit for bit.  Every case runs under both split/merge rules: count-only as
@@ -68,7 +68,7 @@ CASES = [
     (64, 4, [[64, 65, 63, 1, 33, 2], [4, 5, 64, 3, 0, 60]], "equal"),
     (64, 4, [[64, 65, 63, 1, 33, 2], [4, 5, 64, 3, 0, 60]], "dyadic"),
     (4, 100, [[1, 64, 65, 99], [63, 2, 100, 101]], "dyadic"),
-    # merges and splits of bins held four or eight walkers per lane (129-512), and past them
+    # bins held four walkers per lane (129-256), and past them
     (4, 480, [[300, 511, 512, 513], [257, 0, 700, 401]], "dyadic"),
     (4, 480, [[300, 511, 512, 513], [257, 0, 700, 401]], "equal"),
     (8, 128, [[128, 129, 200, 256, 257, 1, 0, 3], [130, 0, 255, 64, 65, 9, 8, 7]], "equal"),
