@@ -993,8 +993,8 @@ def lds_bytes_per_event_fact(net) -> float:
       the changed species: old count and incidence word (8 B), the store (4 B);
       each dependent (mean list length d, repeats included): 2 B id, 16 B
         descriptor, 2 x 4 B counts before and 2 x 4 B after the firing;
-      the mailbox: one 8 B post per dependent segment (at most d), then the
-        64 chunk lanes read and clear 4 slots each (2 x 2 KB)."""
+      the chunk sums: one LDS atomic add per dependent (8 B read, 8 B
+        written), then the 64 chunk lanes reload their sums (512 B)."""
     users = [0] * net.S
     for j in range(net.R):
         for p in range(net.reac_ptr[j], net.reac_ptr[j + 1]):
@@ -1003,7 +1003,7 @@ def lds_bytes_per_event_fact(net) -> float:
           for j in range(net.R)]
     d = float(np.mean(dl))
     nchg = float(np.diff(net.chg_ptr).mean())
-    return 64 * (16 + 8 + 8) + nchg * 12 + d * (2 + 16 + 8 + 8) + d * 8 + 2 * 2048
+    return 64 * (16 + 8 + 8) + nchg * 12 + d * (2 + 16 + 8 + 8) + d * 16 + 512
 
 
 def _cpu_model() -> str:

@@ -18,8 +18,10 @@
 //  * after firing j, only the reactions whose propensity can change (the
 //    dependency list of j: every reaction taking a changed species as a
 //    reactant, sorted and without repeats) are re-evaluated, one per lane,
-//    and their propensity changes are added to the chunk sums by a
-//    segmented reduction in a fixed order, so results are reproducible;
+//    and their propensity changes are added to the chunk sums, held in
+//    LDS, by LDS atomic adds (one ds_add_f64 per lane; the LDS unit applies
+//    the lanes of one instruction in a fixed order, so results repeat bit
+//    for bit);
 //  * the chunk sums are rebuilt from scratch at the start of every interval,
 //    which bounds the rounding drift of the incremental updates to one
 //    interval.
@@ -111,8 +113,8 @@ __global__ __launch_bounds__(64 * WAVE_LDS_MAX_WAVES, 4) void ssa_wave_lds_kerne
 // reaction), the change headers (8 bytes), the per-species incidence words
 // (4 bytes) and the incidence lists (2 bytes per entry) into LDS -- 98 KB at
 // 354 species / 3680 reactions -- and each wave keeps its walker's counts and
-// a 2 KB mailbox of chunk-sum changes beside them (16 walkers per CU at that
-// size); waves take walkers from the work queue until it is empty.  Nothing
+// its 64 chunk sums beside them (16 walkers per CU at that size); waves take
+// walkers from the work queue until it is empty.  Nothing
 // in the event loop reads global memory.
 #define WAVE_FACT_MAX_WAVES 16
 
@@ -126,8 +128,8 @@ __global__ __launch_bounds__(64 * WAVE_FACT_MAX_WAVES) void ssa_wave_fact_kernel
     uint16_t *linc = reinterpret_cast<uint16_t *>(smem + fact_off_inc(R, S));
     unsigned char *wbase = smem + fact_tables_bytes(R, S, a.n_inc);
     const int nw = blockDim.x >> 6, wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    double *lmail = reinterpret_cast<double *>(wbase) + wv * 256;
-    int32_t *lx = reinterpret_cast<int32_t *>(wbase + (size_t)nw * 256 * sizeof(double)) + wv * s_pad;
+    double *lchunk = reinterpret_cast<double *>(wbase) + wv * 64;
+    int32_t *lx = reinterpret_cast<int32_t *>(wbase + (size_t)nw * 64 * sizeof(double)) + wv * s_pad;
     const uint4 *gd = reinterpret_cast<const uint4 *>(a.desc);
     for (int32_t i = threadIdx.x; i < R; i += blockDim.x) {
         ld[i] = gd[i];
@@ -154,7 +156,7 @@ __global__ __launch_bounds__(64 * WAVE_FACT_MAX_WAVES) void ssa_wave_fact_kernel
         if ((int32_t)o < seg.y) {
             const uint32_t g = (uint32_t)seg.x + o;
             const uint32_t run = g / cap;
-            wave_walker_fact(a, tab, xs, (int32_t)run, (int32_t)(g - run * cap), iter, lmail, lx);
+            wave_walker_fact(a, tab, xs, (int32_t)run, (int32_t)(g - run * cap), iter, lchunk, lx);
         }
     }
 }
@@ -214,7 +216,7 @@ hipError_t launch_lds(const SimArgs &a, int32_t *xs, int32_t s_pad, size_t table
 bool wave_fact_fits(const SimArgs &a, size_t *tables, size_t *per_wave) {
     if (!a.fhdr || !a.inc || !a.inc_tab) return false;
     *tables = fact_tables_bytes(a.R, a.S, a.n_inc);
-    *per_wave = 256 * sizeof(double) + sizeof(int32_t) * (size_t)((a.S + 3) & ~3);
+    *per_wave = 64 * sizeof(double) + sizeof(int32_t) * (size_t)((a.S + 3) & ~3);
     return *tables + *per_wave <= WAVE_LDS_BYTES;
 }
 
@@ -238,11 +240,11 @@ int fact_blocks_per_cu(int waves, size_t shmem) {
 // Which variant: the factored-table kernel when every live walker gets a wave
 // at once (WE keeps roughly half its slots live), i.e. when each walker's
 // event chain is the bound; otherwise the descriptor-table kernel, which
-// issues fewer instructions per event (236 against 306 vector instructions
-// at 354/3680) and holds up to 16 walkers per CU in two blocks.  Measured
-// on the 354/3680 network: one run (2465 live walkers) 0.417-0.430 ms per
-// launch against 0.458 ms; eight runs (19,600 live walkers) 1.59 ms against
-// 1.41 ms.
+// issues fewer instructions per event (the incidence-list walk is the
+// difference) and holds up to 16 walkers per CU in two blocks.  Measured on
+// the 354/3680 network (before the chunk sums took LDS atomic adds): one run
+// (2465 live walkers) 0.417-0.430 ms per launch against 0.458 ms; eight runs
+// (19,600 live walkers) 1.59 ms against 1.41 ms.
 namespace {
 // Waves per block of the factored-table kernel when it is the one to run
 // (0: the descriptor-table kernel), with its LDS bytes.

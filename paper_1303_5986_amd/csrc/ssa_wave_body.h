@@ -7,7 +7,8 @@
 //    row_bcast:31 broadcasts carry row totals across the wave -- six steps
 //    of two 32-bit DPP moves and one add, no LDS round trip;
 //  * broadcasts of one lane: v_readlane;
-//  * neighbour exchange: wave_shr / wave_shl DPP.
+//  * the dependents' propensity changes go into the per-wave chunk sums in
+//    LDS by ds_add_f64, one instruction per round of 64 dependents.
 // Per event the dependent loads from global memory are: the descriptors of
 // the chosen chunk (64 lanes, one 16-byte load each), then one packed
 // header of the chosen reaction, then its dependency entries (each carrying
@@ -88,21 +89,17 @@ __device__ __forceinline__ double chunk_total(const T &tab, int32_t R, const int
     return lane_value(scan_incl(v), 63);
 }
 
-// Add, per chunk, the propensity changes held by the lanes (dependent
-// reaction rr, change dv; rr < 0 for idle lanes).  rr ascends across lanes.
-__device__ __forceinline__ void add_chunk_deltas(double *lchunk, int rr, double dv, int lane) {
-    const int ch = rr >= 0 ? (rr >> 6) : 64;
-    const double D = scan_incl(dv);
-    const int ch_prev = __builtin_amdgcn_update_dpp(-1, ch, 0x138, 0xF, 0xF, false);   // wave_shr:1
-    const int ch_next = __builtin_amdgcn_update_dpp(-1, ch, 0x130, 0xF, 0xF, false);   // wave_shl:1
-    const bool start = (lane == 0) || (ch_prev != ch);
-    const bool end = (lane == 63) || (ch_next != ch);
-    const unsigned long long smask = __ballot(start);
-    const unsigned long long upto = (lane == 63) ? ~0ull : ((2ull << lane) - 1ull);
-    const int sl = last_set(smask & upto);
-    const double before = __shfl(D, sl > 0 ? sl - 1 : 0, 64);
-    const double seg = D - (sl > 0 ? before : 0.0);
-    if (end && ch < 64) lchunk[ch] = lchunk[ch] + seg;
+// Add v to a double in LDS with one ds_add_f64 (no return value).  The LDS
+// unit applies the lanes of one such instruction that hit the same address
+// in a fixed order, so a sum built this way repeats bit for bit.
+__device__ __forceinline__ void lds_add_f64(double *p, double v) {
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Add each lane's propensity change dv of dependent reaction rr (rr < 0 for
+// idle lanes) to its chunk's sum.
+__device__ __forceinline__ void add_chunk_deltas(double *lchunk, int rr, double dv) {
+    if (rr >= 0) lds_add_f64(&lchunk[rr >> 6], dv);
 }
 
 }  // namespace
@@ -264,7 +261,7 @@ __device__ inline void wave_walker_t(const SimArgs &a, const T &tab, int32_t *__
                 if (q < nround) {
                     double dv = 0.0;
                     if (rr[q] >= 0) dv = prop_lds(de[q], lx) - old[q];
-                    add_chunk_deltas(lchunk, rr[q], dv, lane);
+                    add_chunk_deltas(lchunk, rr[q], dv);
                     __builtin_amdgcn_wave_barrier();
                 }
             }

@@ -18,14 +18,11 @@
 //     its reaction's descriptor and counts before the firing and its counts
 //     again after it (the firing is one LDS store per changed species; the
 //     wave's LDS accesses complete in order);
-//  4. the changes are folded into the chunk sums: a segmented prefix scan
-//     over the lanes (segments: equal (list, chunk), contiguous because each
-//     list is sorted by reaction id) leaves each segment's total on its last
-//     lane, which posts it to a per-wave mailbox slot (list, chunk); every
-//     chunk lane then adds its four slots, in list order, and clears them
-//     (slots of one list are consecutive doubles, so the 64 chunk lanes read
-//     them without bank conflicts).
-//     Fixed order throughout, so a run is reproducible bit for bit.
+//  4. each dependent's change of propensity is added to its chunk's sum,
+//     held per wave in LDS, by an LDS atomic (ds_add_f64); the chunk lanes
+//     then reload their sums.  The LDS unit applies the lanes of one atomic
+//     instruction that hit the same address in a fixed order, so a run
+//     still repeats bit for bit.
 // A reaction whose dependents exceed two rounds rebuilds every chunk sum.
 // Every 16 events the wave's issue priority follows its walker's expected
 // remaining events (chain_priority), so the longest chains issue first.
@@ -35,31 +32,6 @@
 #define FACT_DEP_ROUNDS 2
 
 namespace {
-
-template <int CTRL, int ROW_MASK>
-__device__ __forceinline__ int32_t dpp_sid(int32_t v) {
-    return __builtin_amdgcn_update_dpp(-1, v, CTRL, ROW_MASK, 0xF, false);
-}
-
-template <int CTRL, int ROW_MASK>
-__device__ __forceinline__ double seg_step(double v, int32_t sid) {
-    const double u = dpp_f64<CTRL, ROW_MASK, true>(v);
-    const int32_t t = dpp_sid<CTRL, ROW_MASK>(sid);
-    return t == sid ? v + u : v;
-}
-
-// Inclusive prefix sum within segments of equal, contiguous ids (the same
-// row shifts and row broadcasts as scan_incl; a step adds its source only
-// when the source lane carries the same id, hence lies in the same segment).
-__device__ __forceinline__ double seg_scan(double v, int32_t sid) {
-    v = seg_step<0x111, 0xF>(v, sid);
-    v = seg_step<0x112, 0xF>(v, sid);
-    v = seg_step<0x114, 0xF>(v, sid);
-    v = seg_step<0x118, 0xF>(v, sid);
-    v = seg_step<0x142, 0xA>(v, sid);
-    v = seg_step<0x143, 0xC>(v, sid);
-    return v;
-}
 
 union DescBits {
     RxnDesc d;
@@ -85,19 +57,15 @@ struct FactTables {
     const uint16_t *inc;   // LDS [n_inc] incidence lists
 };
 
-// One walker through one interval on the calling wave; lmail (4 x 64
-// doubles, [list][chunk]) and lx (S ints) are this wave's LDS slices.
+// One walker through one interval on the calling wave; lchunk (64 doubles,
+// the chunk sums) and lx (S ints) are this wave's LDS slices.
 __device__ inline void wave_walker_fact(const SimArgs &a, const FactTables &tab, int32_t *__restrict__ xs,
-                                        int32_t run, int32_t k, uint32_t iter, double *lmail, int32_t *lx) {
+                                        int32_t run, int32_t k, uint32_t iter, double *lchunk, int32_t *lx) {
     const int lane = threadIdx.x & 63;
     const int32_t S = a.S, R = a.R;
     const int32_t K = (R + 63) >> 6;
     int32_t *xw = xs + ((size_t)run * a.cap + k) * S;
     for (int s = lane; s < S; s += 64) lx[s] = xw[s];
-    lmail[lane] = 0.0;
-    lmail[64 + lane] = 0.0;
-    lmail[128 + lane] = 0.0;
-    lmail[192 + lane] = 0.0;
     __builtin_amdgcn_wave_barrier();
 
     // chunk sums from scratch
@@ -116,6 +84,7 @@ __device__ inline void wave_walker_fact(const SimArgs &a, const FactTables &tab,
         return cs_;
     };
     double csum = rebuild();
+    lchunk[lane] = csum;
 
     const uint64_t seed = a.seeds[run];
     const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
@@ -198,10 +167,10 @@ __device__ inline void wave_walker_fact(const SimArgs &a, const FactTables &tab,
         // the dependents' descriptors and counts, before the firing
         const bool fits = nd <= 64 * FACT_DEP_ROUNDS;
         uint4 dq[FACT_DEP_ROUNDS];
-        int32_t x1q[FACT_DEP_ROUNDS], x2q[FACT_DEP_ROUNDS], sid[FACT_DEP_ROUNDS], kq[FACT_DEP_ROUNDS];
+        int32_t x1q[FACT_DEP_ROUNDS], x2q[FACT_DEP_ROUNDS], chk[FACT_DEP_ROUNDS], kq[FACT_DEP_ROUNDS];
 #pragma unroll
         for (int q = 0; q < FACT_DEP_ROUNDS; ++q) {
-            sid[q] = -1;
+            chk[q] = -1;
             kq[q] = 0;
             x1q[q] = 0;
             x2q[q] = 0;
@@ -218,7 +187,7 @@ __device__ inline void wave_walker_fact(const SimArgs &a, const FactTables &tab,
                 x1q[q] = lx[d.s1];
                 x2q[q] = lx[d.s2];
                 kq[q] = kk;
-                sid[q] = (kk << 6) | (r >> 6);
+                chk[q] = r >> 6;
             }
         }
         // fire j (the dependents' old counts were read above)
@@ -234,13 +203,13 @@ __device__ inline void wave_walker_fact(const SimArgs &a, const FactTables &tab,
         __builtin_amdgcn_wave_barrier();
         if (!fits) {
             csum = rebuild();
+            lchunk[lane] = csum;
             continue;
         }
 #pragma unroll
         for (int q = 0; q < FACT_DEP_ROUNDS; ++q) {
             if (q * 64 >= nd) break;
-            double dv = 0.0;
-            if (sid[q] >= 0) {
+            if (chk[q] >= 0) {
                 const RxnDesc d = desc_of(dq[q]);
                 // listed under an earlier changed species too: counted there
                 // (its other reactant is one of sp0 .. sp(k-1))
@@ -252,23 +221,12 @@ __device__ inline void wave_walker_fact(const SimArgs &a, const FactTables &tab,
                 if (!dup) {
                     const double before = propensity_from(d, (uint32_t)x1q[q], (uint32_t)x2q[q]);
                     const double after = propensity_from(d, (uint32_t)lx[d.s1], (uint32_t)lx[d.s2]);
-                    dv = after - before;
+                    lds_add_f64(&lchunk[chk[q]], after - before);
                 }
             }
-            const double D = seg_scan(dv, sid[q]);
-            const int32_t nxt = __builtin_amdgcn_update_dpp(-1, sid[q], 0x130, 0xF, 0xF, false);   // wave_shl:1
-            if (sid[q] >= 0 && (lane == 63 || nxt != sid[q]))
-                lmail[64 * (sid[q] >> 6) + (sid[q] & 63)] = D;
-            __builtin_amdgcn_wave_barrier();
-            const double m0 = lmail[lane], mm1 = lmail[64 + lane];
-            const double mm2 = lmail[128 + lane], mm3 = lmail[192 + lane];
-            lmail[lane] = 0.0;
-            lmail[64 + lane] = 0.0;
-            lmail[128 + lane] = 0.0;
-            lmail[192 + lane] = 0.0;
-            csum = (((csum + m0) + mm1) + mm2) + mm3;
-            __builtin_amdgcn_wave_barrier();
         }
+        __builtin_amdgcn_wave_barrier();
+        csum = lchunk[lane];
     }
     if (bad && lane == 0) atomicOr(a.err, WE_DERR_OVERFLOW);
     __builtin_amdgcn_wave_barrier();

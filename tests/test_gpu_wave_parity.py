@@ -253,3 +253,39 @@ def test_wave_large_network_from_its_own_initial_state():
         p = stats.chi2_contingency(tab)[1] if tab.shape[1] > 1 else 1.0
         _say(f"   species {s}: two-sample chi-square p = {p:.3f} over {tab.shape[1]} cells")
         assert p > 0.01
+
+
+def _run_twice(cfg, n_iters, kernel_expected):
+    we = _we()
+    out = []
+    for _ in range(2):
+        sim = we.sim_from_config(cfg, kernel=we.WE_KERNEL_WAVE, max_iters=n_iters)
+        assert sim.propagation_kernel() == kernel_expected
+        sim.step(n_iters)
+        sim.synchronize()
+        out.append(([sim.walkers(r) for r in range(len(cfg.seeds))], sim.counters()))
+    (wa, ca), (wb, cb) = out
+    assert ca == cb
+    for (xa, wta, ba, oa), (xb, wtb, bb, ob) in zip(wa, wb):
+        assert np.array_equal(xa, xb) and np.array_equal(wta, wtb)
+        assert np.array_equal(ba, bb) and np.array_equal(oa, ob)
+
+
+def test_wave_kernels_repeat_bit_for_bit():
+    """The chunk sums take each dependent's propensity change by an LDS
+    atomic add, whose same-address lanes the LDS unit applies in a fixed
+    order: two runs of the same configuration end with identical walkers,
+    weights and counters, on the factored-table kernel (the 354/3680
+    network from its own start) and on the descriptor-table kernel."""
+    _say("case: wave kernels run twice, factored (354/3680, 12 intervals) and descriptor-table")
+    base = wl.large_network_config(n_iters=12)
+    _run_twice(base, 12, "ssa_wave_fact_kernel")
+    net = wl.random_network(13, 100, 700, rate_lo=1e-3, rate_hi=1.0)
+    rng = np.random.default_rng(13)
+    x0 = rng.integers(0, 20, size=100).astype(np.int32)
+    coef = np.zeros(100)
+    coef[1] = 1.0
+    cfg = wl.WEConfig(name="rnd_many", net=net, x0=x0, bin_coef=coef,
+                      edges=np.array([0, 2, 4, 8, 16, 32, 64.]), m_targ=256, tau=0.05, n_iters=8,
+                      seeds=np.arange(31, 39, dtype=np.uint64))
+    _run_twice(cfg, 8, "ssa_wave_lds_kernel<false>")
