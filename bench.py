@@ -1167,6 +1167,7 @@ def main():
             "ssa_wave_large", source_digest(["paper_1303_5986_amd/csrc/ssa_wave.hip",
                                              "paper_1303_5986_amd/csrc/ssa_wave_body.h",
                                              "paper_1303_5986_amd/csrc/ssa_wave_fact.h",
+                                             "paper_1303_5986_amd/csrc/queue_first.h",
                                              "paper_1303_5986_amd/csrc/we_common.h"]))
         if args.large_runs != 1:
             traffic = None   # the committed counters were taken on the one-run configuration

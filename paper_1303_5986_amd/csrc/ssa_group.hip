@@ -51,11 +51,9 @@ __global__ __launch_bounds__(64 * GROUP_WAVES) void ssa_group_kernel(SimArgs a, 
     const uint32_t iter = *a.iter_dev;
     const uint32_t M = (uint32_t)a.m_targ, cap = (uint32_t)a.cap;
     const uint32_t total = a.queue[1] * M;
+    // G positions per wave: the first G at the wave's static first position
+    uint32_t q0 = first_position() * (uint32_t)G;
     for (;;) {
-        // every lane executes the atomic (lane 0 adds G, the others zero) and
-        // lane 0's result is broadcast, so no lane leaves the wave's path
-        const uint32_t got = atomicAdd(&a.queue[0], lane == 0 ? (uint32_t)G : 0u);
-        const uint32_t q0 = (uint32_t)__shfl((int)got, 0, 64);
         if (q0 >= total) break;
         const uint32_t q = q0 + (uint32_t)grp;
         bool live = false;
@@ -71,6 +69,10 @@ __global__ __launch_bounds__(64 * GROUP_WAVES) void ssa_group_kernel(SimArgs a, 
             }
         }
         group_walker<L, BR>(a, tb, xs, run, k, live, iter, lx);
+        // every lane executes the atomic (lane 0 adds G, the others zero) and
+        // lane 0's result is broadcast, so no lane leaves the wave's path
+        const uint32_t got = atomicAdd(&a.queue[0], lane == 0 ? (uint32_t)G : 0u);
+        q0 = gridDim.x * (blockDim.x >> 6) * (uint32_t)G + (uint32_t)__shfl((int)got, 0, 64);
     }
 }
 

@@ -28,6 +28,7 @@
 // idles.  All cross-lane steps are executed by the whole wave.
 #pragma once
 
+#include "queue_first.h"
 #include "we_common.h"
 
 #include <algorithm>

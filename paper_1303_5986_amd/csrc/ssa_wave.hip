@@ -95,9 +95,8 @@ __global__ __launch_bounds__(64 * WAVE_LDS_MAX_WAVES, 4) void ssa_wave_lds_kerne
     // the compiler routed lanes 1-63 around it (their result is always
     // zero) into an inner loop of their own, so they ran the next walker
     // without lane 0 -- and wave_walker_t needs the whole wave.
+    uint32_t q = first_position();
     for (;;) {
-        const uint32_t got = atomicAdd(&a.queue[0], lane == 0 ? 1u : 0u);
-        const uint32_t q = (uint32_t)__shfl((int)got, 0, 64);
         if (q >= total) break;
         const uint32_t sg = q / M, o = q - sg * M;
         const int2 seg = a.seg[sg];
@@ -106,6 +105,8 @@ __global__ __launch_bounds__(64 * WAVE_LDS_MAX_WAVES, 4) void ssa_wave_lds_kerne
             const uint32_t run = g / cap;
             wave_walker_t(a, tab, xs, (int32_t)run, (int32_t)(g - run * cap), iter, lchunk, lx);
         }
+        const uint32_t got = atomicAdd(&a.queue[0], lane == 0 ? 1u : 0u);
+        q = gridDim.x * (uint32_t)nw + (uint32_t)__shfl((int)got, 0, 64);
     }
 }
 
@@ -146,10 +147,10 @@ __global__ __launch_bounds__(64 * WAVE_FACT_MAX_WAVES) void ssa_wave_fact_kernel
     const uint32_t iter = *a.iter_dev;
     const uint32_t M = (uint32_t)a.m_targ, cap = (uint32_t)a.cap;
     const uint32_t total = a.queue[1] * M;
-    // whole-wave queue atomic: see ssa_wave_lds_kernel
+    // static first position, then the whole-wave queue atomic: see
+    // ssa_wave_lds_kernel
+    uint32_t q = first_position();
     for (;;) {
-        const uint32_t got = atomicAdd(&a.queue[0], lane == 0 ? 1u : 0u);
-        const uint32_t q = (uint32_t)__shfl((int)got, 0, 64);
         if (q >= total) break;
         const uint32_t sg = q / M, o = q - sg * M;
         const int2 seg = a.seg[sg];
@@ -158,6 +159,8 @@ __global__ __launch_bounds__(64 * WAVE_FACT_MAX_WAVES) void ssa_wave_fact_kernel
             const uint32_t run = g / cap;
             wave_walker_fact(a, tab, xs, (int32_t)run, (int32_t)(g - run * cap), iter, lchunk, lx);
         }
+        const uint32_t got = atomicAdd(&a.queue[0], lane == 0 ? 1u : 0u);
+        q = gridDim.x * (uint32_t)nw + (uint32_t)__shfl((int)got, 0, 64);
     }
 }
 

@@ -14,6 +14,7 @@
 // header of the chosen reaction, then its dependency entries (each carrying
 // the descriptor of the reaction it names) together with its changes.
 #pragma once
+#include "queue_first.h"
 #include "we_common.h"
 
 #define WAVE_WALKERS_PER_BLOCK 4
