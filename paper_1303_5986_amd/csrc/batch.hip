@@ -100,17 +100,19 @@ __global__ __launch_bounds__(256) void batch_lane_kernel(const SimArgs *__restri
     __shared__ int32_t rows[4 * ROWS];
     int32_t *wrows = rows + (threadIdx.x >> 6) * ROWS;
     const int lane = threadIdx.x & 63;
+    const uint32_t n_static = gridDim.x * (blockDim.x >> 6);
+    uint32_t idx = first_position();
     for (;;) {
-        // every lane executes the atomic (lane 0 adds one): no lane takes a
-        // path of its own around the wave-wide steps of the walker
-        const uint32_t got = atomicAdd(counter, lane == 0 ? 1u : 0u);
-        const uint32_t idx = (uint32_t)__shfl((int)got, 0, 64);
         if (idx >= (uint32_t)n_items) break;
         const Item it = items[idx];
         const SimArgs &a = args[it.sim];
         if constexpr (!REG) lane_stage_rows<SMAX>(a, wrows);
         const int32_t k = it.slot + lane;
         if (k < a.n_walk[it.run]) lane_walker<SMAX, RMAX>(a, xptr[it.sim], it.run, k, *a.iter_dev, wrows);
+        // every lane executes the atomic (lane 0 adds one): no lane takes a
+        // path of its own around the wave-wide steps of the walker
+        const uint32_t got = atomicAdd(counter, lane == 0 ? 1u : 0u);
+        idx = n_static + (uint32_t)__shfl((int)got, 0, 64);
     }
 }
 
@@ -123,16 +125,18 @@ __global__ __launch_bounds__(256) void batch_wave_kernel(const SimArgs *__restri
     const int wv = threadIdx.x >> 6;
     double *lchunk = reinterpret_cast<double *>(smem) + wv * 64;
     int32_t *lx = reinterpret_cast<int32_t *>(smem + WAVE_WALKERS_PER_BLOCK * 64 * sizeof(double)) + wv * s_pad;
+    const uint32_t n_static = gridDim.x * (blockDim.x >> 6);
+    uint32_t idx = first_position();
     for (;;) {
-        // every lane executes the atomic (lane 0 adds one): no lane takes a
-        // path of its own around the wave-wide steps of the walker
-        const uint32_t got = atomicAdd(counter, lane == 0 ? 1u : 0u);
-        const uint32_t idx = (uint32_t)__shfl((int)got, 0, 64);
         if (idx >= (uint32_t)n_items) break;
         const Item it = items[idx];
         const SimArgs &a = args[it.sim];
         if (it.slot < a.n_walk[it.run]) wave_walker(a, xptr[it.sim], it.run, it.slot, *a.iter_dev, lchunk, lx);
         __builtin_amdgcn_wave_barrier();
+        // every lane executes the atomic (lane 0 adds one): no lane takes a
+        // path of its own around the wave-wide steps of the walker
+        const uint32_t got = atomicAdd(counter, lane == 0 ? 1u : 0u);
+        idx = n_static + (uint32_t)__shfl((int)got, 0, 64);
     }
 }
 
@@ -150,10 +154,9 @@ __global__ __launch_bounds__(256) void batch_group_kernel(const SimArgs *__restr
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int grp = lane / L;
     int32_t *lx = bglds + ((size_t)wv * G + grp) * s_max;
+    const uint32_t n_static = gridDim.x * (blockDim.x >> 6);
+    uint32_t idx = first_position();
     for (;;) {
-        // every lane executes the atomic (lane 0 adds one): see batch_lane_kernel
-        const uint32_t got = atomicAdd(counter, lane == 0 ? 1u : 0u);
-        const uint32_t idx = (uint32_t)__shfl((int)got, 0, 64);
         if (idx >= (uint32_t)n_items) break;
         const Item it = items[idx];
         const SimArgs &a = args[it.sim];
@@ -161,6 +164,9 @@ __global__ __launch_bounds__(256) void batch_group_kernel(const SimArgs *__restr
         const bool live = k < a.cap && k < a.n_walk[it.run];
         const GroupTables tb{a.desc, a.chg_ptr, a.chg};
         group_walker<L, BR>(a, tb, xptr[it.sim], it.run, k, live, *a.iter_dev, lx);
+        // every lane executes the atomic (lane 0 adds one): see batch_lane_kernel
+        const uint32_t got = atomicAdd(counter, lane == 0 ? 1u : 0u);
+        idx = n_static + (uint32_t)__shfl((int)got, 0, 64);
     }
 }
 
