@@ -465,9 +465,10 @@ WE_API we_status we_measure_peaks(void *hip_stream, we_peaks *out);
  * balance across the chip.
  * autotune_iters > 0: for a member with params.kernel AUTO, every kernel
  * its network fits -- lane (64 walkers per wave), group (32, 16, 8, 4 or 2
- * walkers per wave), wave (1) -- is timed for that many iterations and the
- * fastest is kept; choices are cached in the JSON file cache_path (NULL: no
- * cache).  autotune_iters = 0: lane for networks of up to 32 reactions that
+ * walkers per wave), wave (1) -- is timed on one interval of a pilot sim of
+ * the member's shape whose every slot holds a walker at x0 (best of
+ * autotune_iters pilots) and the fastest is kept; choices are cached in the
+ * JSON file cache_path (NULL: no cache).  autotune_iters = 0: lane for networks of up to 32 reactions that
  * fit it, else wave.
  * Members are owned by the batch: read them with the sim getters via
  * we_batch_sim, never step or destroy them directly.  The committor calls

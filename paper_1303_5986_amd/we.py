@@ -703,9 +703,9 @@ def measure_peaks() -> dict:
 def autotune(cfg, iters: int = 3, cache_path: Optional[str] = None):
     """(kernel, walkers_per_wave) that the batch autotuner picks for one
     configuration: every kernel its network fits (lane, group with 32..2
-    walkers per wave, wave) timed on pilot sims of the configuration's shape
-    for `iters` intervals; walkers_per_wave is 0 unless the group kernel
-    wins."""
+    walkers per wave, wave) timed on one interval of a pilot sim of the
+    configuration's shape with every slot filled at x0 (best of `iters`
+    pilots); walkers_per_wave is 0 unless the group kernel wins."""
     b = Batch([cfg], max_iters=2, autotune_iters=int(iters), cache_path=cache_path)
     try:
         k, w = int(b.kernels()[0]), int(b.walkers_per_wave()[0])
