@@ -1,12 +1,12 @@
 // work_queue.hip -- the walker work queue of the persistent propagation
 // kernels (gfx950).
 //
-// Before each propagation step three small kernels list the walkers as
-// segments of up to m_targ consecutive slots (one occupied bin after
-// resampling) and order the segments by the mean events per walker seen in
-// their bin during the last interval, busiest first -- longest-processing-
-// time-first scheduling, so the long walkers start early and the short ones
-// fill the tail.  The propagation kernels then take walkers from the front
+// Before each propagation step three small kernels (one, for few runs) list
+// the walkers as segments of up to m_targ consecutive slots (one occupied
+// bin after resampling) and order the segments by the mean events per walker
+// seen in their bin during the last interval, busiest first -- longest-
+// processing-time-first scheduling, so the long walkers start early and the
+// short ones fill the tail.  The propagation kernels then take walkers from the front
 // of the queue with one atomic per request.  The order is a scheduling hint
 // only: every result depends on (seed, iteration, slot, event), never on
 // which lane or wave runs a walker.
@@ -186,6 +186,88 @@ __global__ __launch_bounds__(1024) void queue_order_kernel(SimArgs a) {
     }
 }
 
+// Tiny case (queue_tiny: at most 64 segments and 64 counters, e.g. one run of
+// up to 64 bins): the same three steps in one wave, with no block barrier
+// in the sort -- lane b holds bin b's key, a bitonic sort over the 64 lanes
+// by shuffles (the same comparator as above, padding keys -1 last), then a
+// wave prefix over the counters in sorted order.  Gives the same segment
+// order per counter as queue_order_kernel<true>.
+__global__ __launch_bounds__(64) void queue_order_wave_kernel(SimArgs a) {
+    __shared__ int32_t s_occ[64], s_off[64], s_cur[64];
+    const int lane = threadIdx.x & 63;
+    const int32_t NB = a.n_bins, rep = a.seg_rep, NC = NB * rep, n_seg = a.n_runs * NB;
+    s_occ[lane] = 0;
+    s_cur[lane] = 0;
+    __syncthreads();
+    // each segment's bin (lane = run * NB + segment)
+    int32_t b = -1, run = 0, j = 0;
+    if (lane < n_seg) {
+        run = lane / NB;
+        j = lane - run * NB;
+        if ((int64_t)j * a.m_targ < a.n_walk[run]) {
+            b = min(max(a.bin[(size_t)run * a.cap + (size_t)j * a.m_targ], 0), NB - 1);
+            atomicAdd(&s_occ[b * rep + run % rep], 1);
+        }
+    }
+    // bin keys: mean events per walker over the bin's replica counters
+    float key = -1.0f;
+    int32_t idx = lane;
+    if (lane < NB) {
+        float ev = 0.0f;
+        int32_t nw = 0;
+        for (int32_t r = 0; r < rep; ++r) {
+            ev += a.ev_bin[lane * rep + r];
+            nw += a.n_bin[lane * rep + r];
+        }
+        key = nw > 0 ? ev / (float)nw : 0.0f;
+    }
+    // bitonic sort over the lanes, descending by (key, bin)
+    for (int size = 2; size <= 64; size <<= 1)
+        for (int d = size >> 1; d > 0; d >>= 1) {
+            const float ko = __shfl_xor(key, d, 64);
+            const int32_t io = __shfl_xor(idx, d, 64);
+            const bool lower = (lane & d) == 0;
+            const float ki = lower ? key : ko, kj = lower ? ko : key;
+            const int32_t bi = lower ? idx : io, bj = lower ? io : idx;
+            const bool i_first = ki > kj || (ki == kj && bi > bj);
+            const bool desc = (lane & size) == 0;
+            if (i_first != desc) {
+                key = ko;
+                idx = io;
+            }
+        }
+    __syncthreads();
+    // exclusive prefix of the counters in sorted bin order (replicas of a
+    // bin consecutive): lane i holds counter i of that sequence
+    const int32_t bin_at = __shfl(idx, rep > 0 ? lane / rep : 0, 64);
+    const int32_t c = bin_at * rep + lane % rep;
+    const int32_t cnt = lane < NC ? s_occ[c] : 0;
+    int32_t incl = cnt;
+    for (int d = 1; d < 64; d <<= 1) {
+        const int32_t y = __shfl_up(incl, d, 64);
+        if (lane >= d) incl += y;
+    }
+    if (lane < NC) s_off[c] = incl - cnt;
+    const int32_t total = __shfl(incl, 63, 64);
+    if (lane == 0) {
+        a.queue[0] = 0u;
+        a.queue[1] = (uint32_t)total;
+    }
+    __syncthreads();
+    // the segment list, as queue_fill_kernel lays it out
+    if (b >= 0) {
+        const int32_t n = a.n_walk[run];
+        const int64_t first = (int64_t)j * a.m_targ;
+        const int32_t cc = b * rep + run % rep;
+        const int32_t pos = s_off[cc] + atomicAdd(&s_cur[cc], 1);
+        a.seg[pos] = make_int2((int32_t)((size_t)run * a.cap + first), (int32_t)min((int64_t)a.m_targ, n - first));
+    }
+    if (lane < NC) {
+        a.ev_bin[lane] = 0.0f;
+        a.n_bin[lane] = 0;
+    }
+}
+
 // Segment list: one thread per (run, segment), same grid as the count.
 __global__ __launch_bounds__(256) void queue_fill_kernel(SimArgs a) {
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -208,7 +290,16 @@ bool queue_small(const SimArgs &a) {
            (int64_t)a.n_bins * a.seg_rep <= QUEUE_SMALL_BINS;
 }
 
+// At most 64 segments and 64 counters: one wave does everything.
+bool queue_tiny(const SimArgs &a) {
+    return (int64_t)a.n_runs * a.n_bins <= 64 && a.n_bins <= 64 && (int64_t)a.n_bins * a.seg_rep <= 64;
+}
+
 hipError_t launch_work_queue(const SimArgs &a, hipStream_t st) {
+    if (queue_tiny(a)) {
+        hipLaunchKernelGGL(queue_order_wave_kernel, dim3(1), dim3(64), 0, st, a);
+        return hipGetLastError();
+    }
     if (queue_small(a)) {
         hipLaunchKernelGGL(queue_order_kernel<true>, dim3(1), dim3(1024), 0, st, a);
         return hipGetLastError();
