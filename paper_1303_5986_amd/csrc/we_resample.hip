@@ -1099,9 +1099,29 @@ __device__ __forceinline__ void gather_one(const SimArgs &a, const int32_t *__re
     x_nxt[(base + dst) * a.S + s] = x_cur[(base + src) * a.S + s];
 }
 
+// The same with 32-bit index arithmetic, for sims whose n_runs * cap * S
+// copy numbers stay below 2^31: a 64-bit division by a runtime divisor is a
+// long instruction sequence, a 32-bit one a short one.
+__device__ __forceinline__ void gather_one32(const SimArgs &a, const int32_t *__restrict__ x_cur,
+                                             int32_t *__restrict__ x_nxt, uint32_t gid) {
+    const uint32_t S = (uint32_t)a.S, per_run = (uint32_t)a.cap * S;
+    const uint32_t run = gid / per_run;
+    if (run >= (uint32_t)a.n_runs) return;
+    const uint32_t rem = gid - run * per_run;
+    const uint32_t dst = rem / S;
+    const uint32_t s = rem - dst * S;
+    if ((int32_t)dst >= a.n_walk[run]) return;
+    const uint32_t base = run * (uint32_t)a.cap;
+    const uint32_t src = (uint32_t)a.origin[base + dst];
+    x_nxt[(base + dst) * S + s] = x_cur[(base + src) * S + s];
+}
+
 __global__ __launch_bounds__(256) void we_gather_rows_kernel(SimArgs a, const int32_t *__restrict__ x_cur,
-                                                             int32_t *__restrict__ x_nxt) {
-    gather_one(a, x_cur, x_nxt, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+                                                             int32_t *__restrict__ x_nxt, int32_t narrow) {
+    if (narrow)
+        gather_one32(a, x_cur, x_nxt, blockIdx.x * blockDim.x + threadIdx.x);
+    else
+        gather_one(a, x_cur, x_nxt, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 // P(x_s = k, t) accumulated over iterations: one lane per walker, FP64 atomics.
@@ -1264,8 +1284,9 @@ hipError_t launch_resample(const SimArgs &a, int32_t *x_cur, const double *w_cur
         if (e != hipSuccess) return e;
     }
     const int64_t total = (int64_t)a.n_runs * a.cap * a.S;
+    const int32_t narrow = total + 256 < ((int64_t)1 << 31) ? 1 : 0;
     hipLaunchKernelGGL(we_gather_rows_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st,
-                       a, x_cur, x_nxt);
+                       a, x_cur, x_nxt, narrow);
     return hipGetLastError();
 }
 
