@@ -1258,14 +1258,16 @@ int32_t resample_place_rows(const SimArgs &a, int64_t blocks) {
 }
 
 // Bin-parallel resampling pays when the runs alone leave most of the chip idle
-// and each of a run's waves would otherwise take four bins or more in turn
+// and a run's waves would otherwise take more than one bin each in turn
 // (measured, one MI355X: 16 toggle runs x 64 bins 0.045 -> 0.033 ms, 64
-// switch runs x 465 bins 0.211 -> 0.202 ms; one run of 50 bins 0.063 ->
-// 0.067 ms, so not there: its staging then goes to device memory).
+// switch runs x 465 bins 0.211 -> 0.202 ms; one run of 50 bins on 16 waves
+// 35.1 -> 33.3 us and eight such runs 57.2 -> 56.4 us per step, with the
+// bins of up to 256 walkers merged in registers -- before those, one run
+// of 50 bins went 0.063 -> 0.067 ms, its staging being in device memory).
 bool resample_bins_parallel(const SimArgs &a) {
     const int64_t waves = resample_threads(a.n_runs) / 64;
     return a.n_runs < RESAMPLE_BIN_PARALLEL_RUNS && a.n_bins >= RESAMPLE_BIN_PARALLEL_BINS &&
-           a.n_bins >= 4 * waves;
+           a.n_bins >= waves;
 }
 
 hipError_t launch_resample(const SimArgs &a, int32_t *x_cur, const double *w_cur, int32_t *x_nxt,
