@@ -23,6 +23,26 @@ __global__ __launch_bounds__(256) void queue_count_kernel(SimArgs a) {
     atomicAdd(&a.occ_bin[b * a.seg_rep + run % a.seg_rep], 1);
 }
 
+// Bitonic sort of 64 (key, bin) pairs held one per lane, descending by key
+// and, for equal keys, by bin: the comparator of the block sort below, with
+// shuffles in place of LDS and barriers.
+__device__ __forceinline__ void wave_sort_desc(float &key, int32_t &idx, int lane) {
+    for (int size = 2; size <= 64; size <<= 1)
+        for (int d = size >> 1; d > 0; d >>= 1) {
+            const float ko = __shfl_xor(key, d, 64);
+            const int32_t io = __shfl_xor(idx, d, 64);
+            const bool lower = (lane & d) == 0;
+            const float ki = lower ? key : ko, kj = lower ? ko : key;
+            const int32_t bi = lower ? idx : io, bj = lower ? io : idx;
+            const bool i_first = ki > kj || (ki == kj && bi > bj);
+            const bool desc = (lane & size) == 0;
+            if (i_first != desc) {
+                key = ko;
+                idx = io;
+            }
+        }
+}
+
 // Bin order and queue offsets: one block.  Sorts the bins by mean events
 // per walker (descending; ties: higher bin first), lays out their segments
 // in that order, and clears the statistics and the queue.  SMALL (few runs,
@@ -101,24 +121,39 @@ __global__ __launch_bounds__(1024) void queue_order_kernel(SimArgs a) {
         }
     }
     __syncthreads();
-    // bitonic sort, descending by (key, bin)
-    for (int32_t size = 2; size <= P; size <<= 1)
-        for (int32_t d = size >> 1; d > 0; d >>= 1) {
-            for (int32_t i = tid; i < P; i += nthr) {
-                const int32_t j = i ^ d;
-                if (j > i) {
-                    const bool desc = (i & size) == 0;
-                    const float ki = key[i], kj = key[j];
-                    const int32_t bi = idx[i], bj = idx[j];
-                    const bool i_first = ki > kj || (ki == kj && bi > bj);
-                    if (i_first != desc) {
-                        key[i] = kj; key[j] = ki;
-                        idx[i] = (int16_t)bj; idx[j] = (int16_t)bi;
+    if (P <= 64) {
+        // at most 64 keys: wave 0 sorts them in registers (slots past P hold
+        // a key below every real and padding key, so they sort last)
+        if (wv == 0) {
+            float k = lane < P ? key[lane] : -2.0f;
+            int32_t b = lane < P ? (int32_t)idx[lane] : 64 + lane;
+            wave_sort_desc(k, b, lane);
+            if (lane < P) {
+                key[lane] = k;
+                idx[lane] = (int16_t)b;
+            }
+        }
+        __syncthreads();
+    } else {
+        // bitonic sort, descending by (key, bin)
+        for (int32_t size = 2; size <= P; size <<= 1)
+            for (int32_t d = size >> 1; d > 0; d >>= 1) {
+                for (int32_t i = tid; i < P; i += nthr) {
+                    const int32_t j = i ^ d;
+                    if (j > i) {
+                        const bool desc = (i & size) == 0;
+                        const float ki = key[i], kj = key[j];
+                        const int32_t bi = idx[i], bj = idx[j];
+                        const bool i_first = ki > kj || (ki == kj && bi > bj);
+                        if (i_first != desc) {
+                            key[i] = kj; key[j] = ki;
+                            idx[i] = (int16_t)bj; idx[j] = (int16_t)bi;
+                        }
                     }
                 }
+                __syncthreads();
             }
-            __syncthreads();
-        }
+    }
     // exclusive prefix of the segment counters in sorted bin order (the
     // replicas of a bin consecutive): per-thread chunks of that sequence,
     // at most QUEUE_CHUNK long (NB * rep <= 16384), held in registers
@@ -221,21 +256,7 @@ __global__ __launch_bounds__(64) void queue_order_wave_kernel(SimArgs a) {
         }
         key = nw > 0 ? ev / (float)nw : 0.0f;
     }
-    // bitonic sort over the lanes, descending by (key, bin)
-    for (int size = 2; size <= 64; size <<= 1)
-        for (int d = size >> 1; d > 0; d >>= 1) {
-            const float ko = __shfl_xor(key, d, 64);
-            const int32_t io = __shfl_xor(idx, d, 64);
-            const bool lower = (lane & d) == 0;
-            const float ki = lower ? key : ko, kj = lower ? ko : key;
-            const int32_t bi = lower ? idx : io, bj = lower ? io : idx;
-            const bool i_first = ki > kj || (ki == kj && bi > bj);
-            const bool desc = (lane & size) == 0;
-            if (i_first != desc) {
-                key = ko;
-                idx = io;
-            }
-        }
+    wave_sort_desc(key, idx, lane);
     __syncthreads();
     // exclusive prefix of the counters in sorted bin order (replicas of a
     // bin consecutive): lane i holds counter i of that sequence
